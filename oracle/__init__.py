@@ -1,0 +1,191 @@
+"""CPU oracle for triangle and 4-clique counting -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The GPU library never does, and this package imports
+nothing from it: the two share no code.  The arithmetic lives in
+``eh_oracle.c`` (plain C, OpenMP over outer vertices); this module only
+compiles it with gcc and marshals arrays through ctypes.
+
+Definitions (paper section 2.1 Generic-Join; section 3.3 triangle loop nest;
+section 5.2 pruning each undirected edge once by degree-assigned ids):
+self-loops are dropped and every other pair is an undirected edge; T counts
+3-vertex subsets that are triangles, K counts 4-vertex cliques; the root of
+an instance is its vertex of smallest rank, rank = (degree asc, id asc).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "eh_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+def build(force: bool = True) -> str:
+    """Compile eh_oracle.c into liboracle.so with gcc -O2 -fopenmp."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+                    "-o", tmp, _SRC], check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        vp = ctypes.c_void_p
+        lib.orc_graph_new.restype = vp
+        lib.orc_graph_new.argtypes = [ctypes.c_uint32, ctypes.c_uint64, _u32p, _u32p,
+                                      ctypes.POINTER(ctypes.c_int)]
+        lib.orc_graph_free.argtypes = [vp]
+        lib.orc_num_edges.restype = ctypes.c_uint64
+        lib.orc_num_edges.argtypes = [vp]
+        lib.orc_get_edges.argtypes = [vp, _u32p, _u32p]
+        lib.orc_get_rank.argtypes = [vp, _u32p]
+        lib.orc_get_degree.argtypes = [vp, _u32p]
+        lib.orc_get_oriented.argtypes = [vp, _u64p, _u32p]
+        lib.orc_max_threads.restype = ctypes.c_int
+        for name in ("orc_triangles_range", "orc_4cliques_range"):
+            f = getattr(lib, name)
+            f.restype = ctypes.c_uint64
+            f.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, _u64p, _u64p,
+                          _u64p, _u64p]
+        for name in ("orc_sym_triangle_sum", "orc_sym_4clique_sum", "orc_sym_ordered_triangles",
+                     "orc_sym_ordered_4cliques"):
+            f = getattr(lib, name)
+            f.restype = ctypes.c_uint64
+            f.argtypes = [vp]
+        _lib = lib
+        return lib
+
+
+def _p32(a):
+    return a.ctypes.data_as(_u32p)
+
+
+def _p64(a):
+    return None if a is None else a.ctypes.data_as(_u64p)
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
+
+
+class Graph:
+    """The cleaned, ranked and oriented graph the oracle counts on."""
+
+    def __init__(self, n: int, src, dst):
+        lib = _load()
+        self._lib = lib
+        src = np.ascontiguousarray(src, dtype=np.uint32)
+        dst = np.ascontiguousarray(dst, dtype=np.uint32)
+        if src.shape != dst.shape:
+            raise ValueError("src and dst differ in length")
+        err = ctypes.c_int(0)
+        self._h = lib.orc_graph_new(int(n), int(src.size), _p32(src), _p32(dst), ctypes.byref(err))
+        if not self._h:
+            raise ValueError("vertex id out of range" if err.value == 1 else "oracle out of memory")
+        self.n = int(n)
+        self.m = int(lib.orc_num_edges(self._h))
+
+    @classmethod
+    def from_edgelist(cls, el) -> "Graph":
+        return cls(el.n, el.src, el.dst)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.orc_graph_free(h)
+            self._h = None
+
+    # -- structure ---------------------------------------------------------
+    def edges(self):
+        a = np.empty(self.m, np.uint32)
+        b = np.empty(self.m, np.uint32)
+        self._lib.orc_get_edges(self._h, _p32(a), _p32(b))
+        return a, b
+
+    def rank(self):
+        r = np.empty(self.n, np.uint32)
+        self._lib.orc_get_rank(self._h, _p32(r))
+        return r
+
+    def degree(self):
+        d = np.empty(self.n, np.uint32)
+        self._lib.orc_get_degree(self._h, _p32(d))
+        return d
+
+    def oriented(self):
+        """(off uint64[n+1], nbr uint32[m]) of the rank-space oriented CSR."""
+        off = np.empty(self.n + 1, np.uint64)
+        nbr = np.empty(self.m, np.uint32)
+        self._lib.orc_get_oriented(self._h, _p64(off), _p32(nbr))
+        return off, nbr
+
+    # -- counts --------------------------------------------------------------
+    def _run(self, fn, threads, rooted, per_vertex, x_begin, x_end):
+        root = np.zeros(self.n, np.uint64) if rooted else None
+        cv = np.zeros(self.n, np.uint64) if per_vertex else None
+        b = ctypes.c_uint64(0)
+        e = ctypes.c_uint64(0)
+        xe = self.n if x_end is None else int(x_end)
+        total = fn(self._h, int(x_begin), xe, int(threads), _p64(root), _p64(cv), ctypes.byref(b),
+                   ctypes.byref(e))
+        return {"count": int(total), "root": root, "per_vertex": cv, "bytes": int(b.value),
+                "edges": int(e.value)}
+
+    def triangles(self, threads: int = 0, rooted: bool = False, per_vertex: bool = False,
+                  x_begin: int = 0, x_end: int | None = None) -> dict:
+        """T; optional per-root (by original id) and per-vertex containment counts.
+
+        ``bytes`` is B_merge over the visited oriented edges, ``edges`` their number.
+        """
+        return self._run(self._lib.orc_triangles_range, threads, rooted, per_vertex, x_begin, x_end)
+
+    def cliques4(self, threads: int = 0, rooted: bool = False, per_vertex: bool = False,
+                 x_begin: int = 0, x_end: int | None = None) -> dict:
+        """K; ``bytes`` is B_K4 over the visited oriented edges."""
+        return self._run(self._lib.orc_4cliques_range, threads, rooted, per_vertex, x_begin, x_end)
+
+    def count(self, pattern: int, threads: int = 0) -> int:
+        if pattern == 3:
+            return self.triangles(threads)["count"]
+        if pattern == 4:
+            return self.cliques4(threads)["count"]
+        raise ValueError("pattern must be 3 or 4")
+
+    # -- cross-checks without orientation -------------------------------------
+    def sym_triangle_sum(self) -> int:
+        return int(self._lib.orc_sym_triangle_sum(self._h))
+
+    def sym_4clique_sum(self) -> int:
+        return int(self._lib.orc_sym_4clique_sum(self._h))
+
+    def sym_ordered_triangles(self) -> int:
+        return int(self._lib.orc_sym_ordered_triangles(self._h))
+
+    def sym_ordered_4cliques(self) -> int:
+        return int(self._lib.orc_sym_ordered_4cliques(self._h))
+
+
+def rooted_count(root_by_id: np.ndarray, roots) -> int:
+    """Instances whose root lies in the set of `roots` (duplicates ignored)."""
+    r = np.unique(np.asarray(roots, dtype=np.int64))
+    return int(root_by_id[r].sum(dtype=np.uint64))

@@ -1,0 +1,426 @@
+/*
+ * eh_oracle.c -- plain CPU oracle for triangle and 4-clique counting.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may call this code:
+ * only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * load it.  It shares no source with the GPU library.
+ *
+ * What it computes (all exact, uint64):
+ *   Input: n and raw pairs (src[i], dst[i]).  Pairs with src == dst are
+ *   dropped, every other pair is read as the undirected edge {src, dst}, and
+ *   duplicates collapse, giving a simple undirected graph G = (V, E).
+ *   T = number of 3-vertex subsets of V with all three edges in E.
+ *   K = number of 4-vertex subsets of V with all six edges in E.
+ *   Rooted counts: the root of an instance is its vertex of smallest rank,
+ *   where rank orders vertices by (degree in G ascending, id ascending).
+ *
+ * How (paper section 2.1, Algorithm 1 "Generic-Join", instantiated for the
+ * triangle in section 3.3 "GHD Translation"; pruned input as in section 5.2):
+ * each undirected edge is kept once, directed from lower to higher rank
+ * (symmetric pruning with degree-assigned ids).  With the attribute order
+ * x < y < z (< w) and N+(x) the sorted higher-ranked neighbours of x,
+ *   T = sum_x sum_{y in N+(x)} |N+(x) & N+(y)|
+ *   K = sum_x sum_{y in N+(x)} sum_{z in S} |S & N+(z)|,  S = N+(x) & N+(y)
+ * Every intersection is a two-pointer merge of sorted arrays.
+ *
+ * Independent cross-checks, with no orientation at all:
+ *   sum over {a,b} in E of |N(a) & N(b)|            = 3 T
+ *   sum over {a,b} in E of edges(N(a) & N(b))       = 6 K
+ *   Generic-Join over the symmetric (unpruned) relation counts ordered
+ *   tuples: 3! T and 4! K (appendix A.2, symmetric filtering).
+ *
+ * Byte models (the reads a list-merge implementation performs):
+ *   B_merge = sum over oriented edges (x,y) of 4 (|N+(x)| + |N+(y)|)
+ *   B_K4    = B_merge + sum over triangles x<y<z of 4 (|S_xy| + |N+(z)|)
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct orc_graph {
+  uint32_t n;
+  uint64_t m;          /* unique undirected edges */
+  uint32_t* ea;        /* edge endpoints, ea[i] < eb[i], sorted lexicographically */
+  uint32_t* eb;
+  uint32_t* deg;       /* degree in G, by original id */
+  uint32_t* rank;      /* rank[id] */
+  uint32_t* vert;      /* vert[rank] = id */
+  uint64_t* off;       /* oriented CSR in rank space: off[n+1] */
+  uint32_t* nbr;       /* nbr[m]: higher-ranked neighbours, sorted */
+  uint64_t* soff;      /* symmetric CSR by original id (built on demand) */
+  uint32_t* snbr;
+} orc_graph;
+
+static int cmp_u64(const void* a, const void* b) {
+  uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+static int cmp_u32(const void* a, const void* b) {
+  uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* vertices sorted by (degree ascending, id ascending) */
+static const uint32_t* g_sort_deg;
+static int cmp_deg_id(const void* a, const void* b) {
+  uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
+  uint32_t dx = g_sort_deg[x], dy = g_sort_deg[y];
+  if (dx != dy) return dx < dy ? -1 : 1;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+void orc_graph_free(orc_graph* g) {
+  if (!g) return;
+  free(g->ea); free(g->eb); free(g->deg); free(g->rank); free(g->vert);
+  free(g->off); free(g->nbr); free(g->soff); free(g->snbr);
+  free(g);
+}
+
+/* err: 0 ok, 1 id out of range, 2 out of memory */
+orc_graph* orc_graph_new(uint32_t n, uint64_t m_raw, const uint32_t* src,
+                         const uint32_t* dst, int* err) {
+  *err = 0;
+  for (uint64_t i = 0; i < m_raw; ++i)
+    if (src[i] >= n || dst[i] >= n) { *err = 1; return NULL; }
+  orc_graph* g = (orc_graph*)calloc(1, sizeof(orc_graph));
+  if (!g) { *err = 2; return NULL; }
+  g->n = n;
+  /* 1-3: drop loops, canonical {min,max}, sort, unique */
+  uint64_t* key = (uint64_t*)malloc((m_raw ? m_raw : 1) * sizeof(uint64_t));
+  if (!key) { *err = 2; orc_graph_free(g); return NULL; }
+  uint64_t k = 0;
+  for (uint64_t i = 0; i < m_raw; ++i) {
+    uint32_t a = src[i], b = dst[i];
+    if (a == b) continue;
+    uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+    key[k++] = ((uint64_t)lo << 32) | hi;
+  }
+  qsort(key, k, sizeof(uint64_t), cmp_u64);
+  uint64_t m = 0;
+  for (uint64_t i = 0; i < k; ++i)
+    if (m == 0 || key[i] != key[m - 1]) key[m++] = key[i];
+  g->m = m;
+  g->ea = (uint32_t*)malloc((m ? m : 1) * sizeof(uint32_t));
+  g->eb = (uint32_t*)malloc((m ? m : 1) * sizeof(uint32_t));
+  g->deg = (uint32_t*)calloc(n ? n : 1, sizeof(uint32_t));
+  g->rank = (uint32_t*)malloc((n ? n : 1) * sizeof(uint32_t));
+  g->vert = (uint32_t*)malloc((n ? n : 1) * sizeof(uint32_t));
+  g->off = (uint64_t*)calloc((size_t)n + 1, sizeof(uint64_t));
+  g->nbr = (uint32_t*)malloc((m ? m : 1) * sizeof(uint32_t));
+  if (!g->ea || !g->eb || !g->deg || !g->rank || !g->vert || !g->off || !g->nbr) {
+    free(key); *err = 2; orc_graph_free(g); return NULL;
+  }
+  for (uint64_t i = 0; i < m; ++i) {
+    g->ea[i] = (uint32_t)(key[i] >> 32);
+    g->eb[i] = (uint32_t)(key[i] & 0xffffffffu);
+  }
+  free(key);
+  /* 4: degree in G */
+  for (uint64_t i = 0; i < m; ++i) { g->deg[g->ea[i]]++; g->deg[g->eb[i]]++; }
+  /* 5: rank by (degree asc, id asc) */
+  for (uint32_t v = 0; v < n; ++v) g->vert[v] = v;
+  g_sort_deg = g->deg;
+  qsort(g->vert, n, sizeof(uint32_t), cmp_deg_id);
+  for (uint32_t r = 0; r < n; ++r) g->rank[g->vert[r]] = r;
+  /* 6: oriented adjacency, lower rank -> higher rank, rows sorted */
+  for (uint64_t i = 0; i < m; ++i) {
+    uint32_t ra = g->rank[g->ea[i]], rb = g->rank[g->eb[i]];
+    g->off[(ra < rb ? ra : rb) + 1]++;
+  }
+  for (uint32_t r = 0; r < n; ++r) g->off[r + 1] += g->off[r];
+  uint64_t* fill = (uint64_t*)malloc(((size_t)n + 1) * sizeof(uint64_t));
+  if (!fill) { *err = 2; orc_graph_free(g); return NULL; }
+  memcpy(fill, g->off, ((size_t)n + 1) * sizeof(uint64_t));
+  for (uint64_t i = 0; i < m; ++i) {
+    uint32_t ra = g->rank[g->ea[i]], rb = g->rank[g->eb[i]];
+    uint32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
+    g->nbr[fill[lo]++] = hi;
+  }
+  free(fill);
+  for (uint32_t r = 0; r < n; ++r)
+    qsort(g->nbr + g->off[r], g->off[r + 1] - g->off[r], sizeof(uint32_t), cmp_u32);
+  return g;
+}
+
+uint64_t orc_num_edges(const orc_graph* g) { return g->m; }
+uint32_t orc_num_vertices(const orc_graph* g) { return g->n; }
+
+void orc_get_edges(const orc_graph* g, uint32_t* a, uint32_t* b) {
+  memcpy(a, g->ea, g->m * sizeof(uint32_t));
+  memcpy(b, g->eb, g->m * sizeof(uint32_t));
+}
+void orc_get_rank(const orc_graph* g, uint32_t* rank) { memcpy(rank, g->rank, g->n * sizeof(uint32_t)); }
+void orc_get_degree(const orc_graph* g, uint32_t* deg) { memcpy(deg, g->deg, g->n * sizeof(uint32_t)); }
+void orc_get_oriented(const orc_graph* g, uint64_t* off, uint32_t* nbr) {
+  memcpy(off, g->off, ((size_t)g->n + 1) * sizeof(uint64_t));
+  memcpy(nbr, g->nbr, g->m * sizeof(uint32_t));
+}
+
+/* |A & B| for sorted arrays, two-pointer merge */
+static uint64_t merge_count(const uint32_t* a, uint64_t na, const uint32_t* b, uint64_t nb) {
+  uint64_t i = 0, j = 0, c = 0;
+  while (i < na && j < nb) {
+    if (a[i] < b[j]) ++i;
+    else if (a[i] > b[j]) ++j;
+    else { ++c; ++i; ++j; }
+  }
+  return c;
+}
+
+/* A & B written to out (sorted), returns its size */
+static uint64_t merge_list(const uint32_t* a, uint64_t na, const uint32_t* b, uint64_t nb,
+                           uint32_t* out) {
+  uint64_t i = 0, j = 0, c = 0;
+  while (i < na && j < nb) {
+    if (a[i] < b[j]) ++i;
+    else if (a[i] > b[j]) ++j;
+    else { out[c++] = a[i]; ++i; ++j; }
+  }
+  return c;
+}
+
+static void add_u64(uint64_t* p, uint64_t v) { __atomic_fetch_add(p, v, __ATOMIC_RELAXED); }
+
+static void set_threads(int threads) {
+#ifdef _OPENMP
+  if (threads > 0) omp_set_num_threads(threads);
+#else
+  (void)threads;
+#endif
+}
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/*
+ * Triangles over outer vertices (ranks) x in [x_begin, x_end).
+ *   root_by_id[id]: triangles whose smallest-rank vertex is id (optional)
+ *   c3_by_id[id]:   triangles containing id (optional)
+ *   bytes:          B_merge over the visited edges (optional)
+ *   edges:          oriented edges visited (optional)
+ */
+uint64_t orc_triangles_range(const orc_graph* g, uint32_t x_begin, uint32_t x_end, int threads,
+                             uint64_t* root_by_id, uint64_t* c3_by_id, uint64_t* bytes,
+                             uint64_t* edges) {
+  set_threads(threads);
+  uint64_t total = 0, b = 0, e = 0;
+  if (x_end > g->n) x_end = g->n;
+  const int64_t xb = x_begin, xe = x_end;
+  const int need_list = c3_by_id != NULL;
+#pragma omp parallel reduction(+ : total, b, e)
+  {
+    uint32_t* tmp = NULL;
+    if (need_list) {
+      uint64_t dmax = 0;
+      for (uint32_t r = 0; r < g->n; ++r)
+        if (g->off[r + 1] - g->off[r] > dmax) dmax = g->off[r + 1] - g->off[r];
+      tmp = (uint32_t*)malloc((dmax ? dmax : 1) * sizeof(uint32_t));
+    }
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t x = xb; x < xe; ++x) {
+      const uint32_t* nx = g->nbr + g->off[x];
+      const uint64_t dx = g->off[x + 1] - g->off[x];
+      uint64_t tx = 0;
+      for (uint64_t i = 0; i < dx; ++i) {
+        const uint32_t y = nx[i];
+        const uint32_t* ny = g->nbr + g->off[y];
+        const uint64_t dy = g->off[y + 1] - g->off[y];
+        uint64_t c;
+        if (need_list) {
+          c = merge_list(nx, dx, ny, dy, tmp);
+          for (uint64_t t = 0; t < c; ++t) add_u64(&c3_by_id[g->vert[tmp[t]]], 1);
+          if (c) add_u64(&c3_by_id[g->vert[y]], c);
+        } else {
+          c = merge_count(nx, dx, ny, dy);
+        }
+        tx += c;
+        b += 4 * (dx + dy);
+      }
+      e += dx;
+      total += tx;
+      if (root_by_id) root_by_id[g->vert[x]] += tx;
+      if (c3_by_id && tx) add_u64(&c3_by_id[g->vert[x]], tx);
+    }
+    free(tmp);
+  }
+  if (bytes) *bytes = b;
+  if (edges) *edges = e;
+  return total;
+}
+
+uint64_t orc_triangles(const orc_graph* g, int threads, uint64_t* root_by_id, uint64_t* c3_by_id,
+                       uint64_t* bytes) {
+  return orc_triangles_range(g, 0, g->n, threads, root_by_id, c3_by_id, bytes, NULL);
+}
+
+/* 4-cliques over outer vertices x in [x_begin, x_end); same optional outputs */
+uint64_t orc_4cliques_range(const orc_graph* g, uint32_t x_begin, uint32_t x_end, int threads,
+                            uint64_t* root_by_id, uint64_t* c4_by_id, uint64_t* bytes,
+                            uint64_t* edges) {
+  set_threads(threads);
+  uint64_t total = 0, b = 0, e = 0;
+  if (x_end > g->n) x_end = g->n;
+  const int64_t xb = x_begin, xe = x_end;
+  uint64_t dmax = 0;
+  for (uint32_t r = 0; r < g->n; ++r)
+    if (g->off[r + 1] - g->off[r] > dmax) dmax = g->off[r + 1] - g->off[r];
+#pragma omp parallel reduction(+ : total, b, e)
+  {
+    uint32_t* s = (uint32_t*)malloc((dmax ? dmax : 1) * sizeof(uint32_t));
+    uint32_t* t = (uint32_t*)malloc((dmax ? dmax : 1) * sizeof(uint32_t));
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t x = xb; x < xe; ++x) {
+      const uint32_t* nx = g->nbr + g->off[x];
+      const uint64_t dx = g->off[x + 1] - g->off[x];
+      uint64_t kx = 0;
+      for (uint64_t i = 0; i < dx; ++i) {
+        const uint32_t y = nx[i];
+        const uint32_t* ny = g->nbr + g->off[y];
+        const uint64_t dy = g->off[y + 1] - g->off[y];
+        const uint64_t ns = merge_list(nx, dx, ny, dy, s);   /* S = N+(x) & N+(y) */
+        b += 4 * (dx + dy);
+        uint64_t kxy = 0;
+        for (uint64_t j = 0; j < ns; ++j) {
+          const uint32_t z = s[j];
+          const uint32_t* nz = g->nbr + g->off[z];
+          const uint64_t dz = g->off[z + 1] - g->off[z];
+          b += 4 * (ns + dz);
+          if (c4_by_id) {
+            const uint64_t c = merge_list(s, ns, nz, dz, t);   /* w in S & N+(z) */
+            for (uint64_t q = 0; q < c; ++q) add_u64(&c4_by_id[g->vert[t[q]]], 1);
+            if (c) {
+              add_u64(&c4_by_id[g->vert[z]], c);
+              add_u64(&c4_by_id[g->vert[y]], c);
+              add_u64(&c4_by_id[g->vert[x]], c);
+            }
+            kxy += c;
+          } else {
+            kxy += merge_count(s, ns, nz, dz);
+          }
+        }
+        kx += kxy;
+      }
+      e += dx;
+      total += kx;
+      if (root_by_id) root_by_id[g->vert[x]] += kx;
+    }
+    free(s);
+    free(t);
+  }
+  if (bytes) *bytes = b;
+  if (edges) *edges = e;
+  return total;
+}
+
+uint64_t orc_4cliques(const orc_graph* g, int threads, uint64_t* root_by_id, uint64_t* c4_by_id,
+                      uint64_t* bytes) {
+  return orc_4cliques_range(g, 0, g->n, threads, root_by_id, c4_by_id, bytes, NULL);
+}
+
+/* ---- cross-checks without orientation ---------------------------------- */
+
+static int build_symmetric(orc_graph* g) {
+  if (g->soff) return 0;
+  const uint32_t n = g->n;
+  g->soff = (uint64_t*)calloc((size_t)n + 1, sizeof(uint64_t));
+  g->snbr = (uint32_t*)malloc((g->m > 0 ? 2 * g->m : 1) * sizeof(uint32_t));
+  if (!g->soff || !g->snbr) return -1;
+  for (uint32_t v = 0; v < n; ++v) g->soff[v + 1] = g->soff[v] + g->deg[v];
+  uint64_t* fill = (uint64_t*)malloc(((size_t)n + 1) * sizeof(uint64_t));
+  if (!fill) return -1;
+  memcpy(fill, g->soff, ((size_t)n + 1) * sizeof(uint64_t));
+  for (uint64_t i = 0; i < g->m; ++i) {
+    g->snbr[fill[g->ea[i]]++] = g->eb[i];
+    g->snbr[fill[g->eb[i]]++] = g->ea[i];
+  }
+  free(fill);
+  for (uint32_t v = 0; v < n; ++v)
+    qsort(g->snbr + g->soff[v], g->soff[v + 1] - g->soff[v], sizeof(uint32_t), cmp_u32);
+  return 0;
+}
+
+/* sum over undirected edges {a,b} of |N(a) & N(b)|  (= 3T) */
+uint64_t orc_sym_triangle_sum(orc_graph* g) {
+  if (build_symmetric(g)) return UINT64_MAX;
+  uint64_t s = 0;
+  for (uint64_t i = 0; i < g->m; ++i) {
+    const uint32_t a = g->ea[i], b = g->eb[i];
+    s += merge_count(g->snbr + g->soff[a], g->soff[a + 1] - g->soff[a],
+                     g->snbr + g->soff[b], g->soff[b + 1] - g->soff[b]);
+  }
+  return s;
+}
+
+/* sum over undirected edges {a,b} of the number of edges inside N(a) & N(b)  (= 6K) */
+uint64_t orc_sym_4clique_sum(orc_graph* g) {
+  if (build_symmetric(g)) return UINT64_MAX;
+  uint64_t dmax = 0;
+  for (uint32_t v = 0; v < g->n; ++v) if (g->deg[v] > dmax) dmax = g->deg[v];
+  uint32_t* c = (uint32_t*)malloc((dmax ? dmax : 1) * sizeof(uint32_t));
+  if (!c) return UINT64_MAX;
+  uint64_t s = 0;
+  for (uint64_t i = 0; i < g->m; ++i) {
+    const uint32_t a = g->ea[i], b = g->eb[i];
+    const uint64_t nc = merge_list(g->snbr + g->soff[a], g->soff[a + 1] - g->soff[a],
+                                   g->snbr + g->soff[b], g->soff[b + 1] - g->soff[b], c);
+    /* edges inside C: each counted twice as (p, q) and (q, p) */
+    uint64_t twice = 0;
+    for (uint64_t j = 0; j < nc; ++j) {
+      const uint32_t p = c[j];
+      twice += merge_count(c, nc, g->snbr + g->soff[p], g->soff[p + 1] - g->soff[p]);
+    }
+    s += twice / 2;
+  }
+  free(c);
+  return s;
+}
+
+/* Generic-Join on the unpruned symmetric relation: ordered triangle tuples (= 6T) */
+uint64_t orc_sym_ordered_triangles(orc_graph* g) {
+  if (build_symmetric(g)) return UINT64_MAX;
+  uint64_t s = 0;
+  for (uint32_t x = 0; x < g->n; ++x) {
+    const uint32_t* nx = g->snbr + g->soff[x];
+    const uint64_t dx = g->soff[x + 1] - g->soff[x];
+    for (uint64_t i = 0; i < dx; ++i) {
+      const uint32_t y = nx[i];
+      s += merge_count(nx, dx, g->snbr + g->soff[y], g->soff[y + 1] - g->soff[y]);
+    }
+  }
+  return s;
+}
+
+/* Generic-Join on the unpruned symmetric relation: ordered 4-clique tuples (= 24K) */
+uint64_t orc_sym_ordered_4cliques(orc_graph* g) {
+  if (build_symmetric(g)) return UINT64_MAX;
+  uint64_t dmax = 0;
+  for (uint32_t v = 0; v < g->n; ++v) if (g->deg[v] > dmax) dmax = g->deg[v];
+  uint32_t* s1 = (uint32_t*)malloc((dmax ? dmax : 1) * sizeof(uint32_t));
+  uint32_t* s2 = (uint32_t*)malloc((dmax ? dmax : 1) * sizeof(uint32_t));
+  if (!s1 || !s2) { free(s1); free(s2); return UINT64_MAX; }
+  uint64_t s = 0;
+  for (uint32_t x = 0; x < g->n; ++x) {
+    const uint32_t* nx = g->snbr + g->soff[x];
+    const uint64_t dx = g->soff[x + 1] - g->soff[x];
+    for (uint64_t i = 0; i < dx; ++i) {
+      const uint32_t y = nx[i];
+      const uint64_t n1 = merge_list(nx, dx, g->snbr + g->soff[y], g->soff[y + 1] - g->soff[y], s1);
+      for (uint64_t j = 0; j < n1; ++j) {
+        const uint32_t z = s1[j];
+        const uint64_t n2 = merge_list(s1, n1, g->snbr + g->soff[z], g->soff[z + 1] - g->soff[z], s2);
+        s += n2;
+      }
+    }
+  }
+  free(s1);
+  free(s2);
+  return s;
+}
