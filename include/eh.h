@@ -1,0 +1,239 @@
+/*
+ * eh.h -- C ABI of the MI355X set-intersection engine for triangle and
+ * 4-clique counting (EmptyHeaded, Aberger et al., SIGMOD 2016).
+ *
+ * The engine keeps a graph as a two-level trie (paper section 2.2 "Input
+ * Data"): level one is the vertex set, level two the neighbour sets, stored
+ * as degree-ordered CSR in HBM.  Each neighbour set has the uint layout
+ * (sorted 32-bit ids) and, when the set optimizer of section 4.4 finds it
+ * dense, an additional bitset layout (section 4.1, Figure 3) whose single
+ * block spans the set's range.  Counting runs Generic-Join (section 2.1,
+ * Algorithm 1) for the two patterns of Table 1 that are single-node plans,
+ * Triangle and 4-Clique, with COUNT(*) aggregation, on data pruned to one
+ * direction per undirected edge with degree-assigned ids (section 5.2).  The
+ * work is the set intersections of section 4.2 (uint & uint by merge or
+ * galloping, bitset & bitset by word AND, uint & bitset by probing), done by
+ * hand-written gfx950 kernels.
+ *
+ * Conventions shared by every call:
+ *   - Vertex ids are uint32 in [0, n).  Input pairs may repeat, appear in both
+ *     directions and contain self-loops: loops are dropped and the rest is
+ *     read as a simple undirected graph.  An id >= n is EH_EINVAL.
+ *   - Counts are exact unsigned 64-bit integers.  A triangle is a 3-vertex
+ *     subset with all three edges, a 4-clique a 4-vertex subset with all six.
+ *   - rank(v) orders vertices by (degree ascending, id ascending); the root
+ *     of a triangle or 4-clique is its vertex of smallest rank.
+ *   - Pointers named d_* are device pointers on the context's device; all
+ *     others are host pointers.  Input arrays are only read during the call.
+ *   - Every call returns an eh_status.  No exception or abort crosses the
+ *     ABI.  HIP failures return EH_EHIP with text in eh_last_error().  Host
+ *     outputs are written only when the call returns EH_OK.
+ *   - Blocking calls return after their result is on the host.  *_async
+ *     calls only enqueue work on the context's stream.
+ *   - A context is used by one host thread at a time; eh_submit and eh_poll
+ *     are thread-safe.
+ */
+#ifndef EH_H_
+#define EH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t eh_status;
+enum {
+  EH_OK = 0,
+  EH_PENDING = 1,     /* eh_poll: request not finished yet */
+  EH_EINVAL = -1,     /* bad argument: null pointer, id >= n, bad pattern or range */
+  EH_ENOMEM = -2,     /* allocation failed, or a request exceeds the memory budget */
+  EH_EHIP = -3,       /* a HIP runtime call failed; see eh_last_error */
+  EH_EBUSY = -4,      /* server queue full */
+  EH_ENOTFOUND = -5,  /* unknown or already retired ticket */
+  EH_EOVERFLOW = -6,  /* size beyond the 32-bit offsets of the trie */
+  EH_ESTATE = -7      /* object in the wrong state (e.g. batch call on a single trie) */
+};
+
+enum { EH_TRIANGLE = 3, EH_4CLIQUE = 4 };
+
+/* Set layouts (section 4.3 "Tradeoffs"): uint only at relation level, the
+ * per-set optimizer (section 4.4), or every non-empty set as a bitset. */
+enum { EH_LAYOUT_UINT = 0, EH_LAYOUT_HYBRID = 1, EH_LAYOUT_BITSET_ALL = 2 };
+
+/* Device memory hooks.  alloc returns NULL on failure.  Both may be called
+ * from the thread that calls into the context only. */
+typedef struct eh_allocator {
+  void* (*alloc)(void* self, size_t bytes, void* hip_stream);
+  void (*free)(void* self, void* ptr, void* hip_stream);
+  void* self;
+} eh_allocator;
+
+typedef struct eh_ctx eh_ctx;
+typedef struct eh_trie eh_trie;
+typedef struct eh_server eh_server;
+typedef struct eh_host_trie eh_host_trie;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* device: HIP device ordinal.  hip_stream: a hipStream_t to launch on, or
+ * NULL for a stream the context creates.  alloc: NULL for hipMalloc/hipFree.
+ * The allocator struct is copied; its `self` must outlive the context. */
+eh_status eh_ctx_create(int device, void* hip_stream, const eh_allocator* alloc, eh_ctx** out);
+eh_status eh_ctx_destroy(eh_ctx* ctx);
+const char* eh_last_error(const eh_ctx* ctx);
+const char* eh_status_str(eh_status s);
+/* Version of this ABI (major * 10000 + minor * 100 + patch). */
+int32_t eh_abi_version(void);
+
+/* ---- tuning knobs (performance only; counts never depend on them) ------- */
+
+enum { EH_KERNEL_AUTO = 0, EH_KERNEL_STAGED = 1, EH_KERNEL_PAIRWISE = 2 };
+enum { EH_STAGE_AUTO = 0, EH_STAGE_SOURCE = 1, EH_STAGE_TARGET = 2 };
+enum { EH_ALGO_AUTO = 0, EH_ALGO_MERGE = 1, EH_ALGO_SEARCH = 2 };
+
+typedef struct eh_tuning {
+  uint32_t kernel;       /* EH_KERNEL_*: staged (one set held in LDS) or pairwise */
+  uint32_t staging;      /* staged kernel, triangle totals: which end of an edge is held */
+  uint32_t algo;         /* pairwise uint & uint: EH_ALGO_AUTO applies the gamma rule */
+  float gamma;           /* galloping when the longer list exceeds gamma x the shorter
+                            (section 4.2 uses 32); <= 0 keeps the current value */
+  uint32_t chunk_work;   /* target streamed elements per work item (0: keep) */
+  uint32_t waves_per_cu; /* persistent waves per compute unit (0: keep) */
+  uint32_t group_lanes;  /* pairwise: lanes per pair, 4..64 power of two; 0: by size bins */
+  uint32_t use_bitsets;  /* 1: dense sets are read through their bitset layout */
+  uint32_t dynamic;      /* 1: waves take work items from an atomic cursor; 0: static */
+  uint32_t stage_words;  /* staged kernels: LDS words for a held set (bitset range / 32, or
+                            list length), at most 1024; 0 means 1024 */
+} eh_tuning;
+
+eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t);
+eh_status eh_ctx_get_tuning(const eh_ctx* ctx, eh_tuning* out);
+
+/* ---- tries -------------------------------------------------------------- */
+
+/* Set optimizer of section 4.4: a set S becomes a bitset iff |S| >= s_min and
+ * (max(S) - min(S) + 1) / |S| <= tau.  The paper's rule is one AVX register
+ * (256 bits) per value: tau = 256.  tau <= 0 selects 32; s_min 0 selects 1. */
+typedef struct eh_build_opts {
+  uint32_t layout;  /* EH_LAYOUT_* */
+  float tau;
+  uint32_t s_min;
+} eh_build_opts;
+
+typedef struct eh_trie_info {
+  uint32_t n;               /* vertices (sum over graphs for a batch) */
+  uint32_t n_graphs;        /* 1 for a single graph */
+  uint64_t m_plus;          /* oriented edges = unique undirected edges */
+  uint64_t n_bitset_sets;   /* sets that also carry the bitset layout */
+  uint64_t bitset_words;    /* 32-bit words over all bitsets */
+  uint64_t device_bytes;    /* HBM held by the trie */
+  uint64_t b_merge;         /* sum over oriented edges (u,v) of 4 (d+(u) + d+(v)) */
+  uint32_t max_out_degree;  /* max d+ */
+  uint32_t reserved;
+} eh_trie_info;
+
+/* Builds the trie of one graph on the host (clean, rank, orient, CSR, set
+ * layouts; section 2.2 dictionary encoding, section 5.2 pruning) and uploads
+ * it.  src/dst: n_edges raw pairs.  opts may be NULL (hybrid, tau 32). */
+eh_status eh_build_trie(eh_ctx* ctx, const uint32_t* src, const uint32_t* dst, uint64_t n_edges,
+                        uint32_t n_vertices, const eh_build_opts* opts, eh_trie** out);
+
+/* Many independent graphs in one trie.  Graph g has n_vertices[g] vertices
+ * with local ids and the raw pairs src/dst[edge_off[g] .. edge_off[g+1]). */
+eh_status eh_build_batch(eh_ctx* ctx, uint32_t n_graphs, const uint32_t* n_vertices,
+                         const uint64_t* edge_off, const uint32_t* src, const uint32_t* dst,
+                         const eh_build_opts* opts, eh_trie** out);
+
+eh_status eh_trie_info_get(const eh_trie* trie, eh_trie_info* out);
+/* Frees the trie's device memory.  Destroy every server using it first. */
+eh_status eh_trie_free(eh_trie* trie);
+
+/* ---- counting ----------------------------------------------------------- */
+
+/* Triangle total of a single-graph trie.  d_per_root: NULL, or a device array
+ * of n uint64 that receives, per original vertex id, the triangles rooted at
+ * it (it is overwritten, not accumulated). */
+eh_status eh_count_triangles(eh_ctx* ctx, const eh_trie* trie, uint64_t* total,
+                             uint64_t* d_per_root);
+/* 4-clique total of a single-graph trie (section 5.3, query K4 on pruned data). */
+eh_status eh_count_4cliques(eh_ctx* ctx, const eh_trie* trie, uint64_t* total);
+/* Enqueue-only forms: the total is written to d_total (one uint64, device)
+ * when the stream reaches it.  pattern: EH_TRIANGLE or EH_4CLIQUE. */
+eh_status eh_count_async(eh_ctx* ctx, const eh_trie* trie, int pattern, uint64_t* d_total);
+
+/* Instances whose root is in the set {roots[i]} (original ids; duplicates are
+ * ignored): a selection on the first attribute of the join (appendix B.1). */
+eh_status eh_count_rooted(eh_ctx* ctx, const eh_trie* trie, int pattern, const uint32_t* roots,
+                          uint32_t n_roots, uint64_t* total);
+
+/* Per-graph counts of graphs [first, first+count) of a batch trie, all in one
+ * launch.  out_counts: host array of count uint64. */
+eh_status eh_count_batch(eh_ctx* ctx, const eh_trie* batch, int pattern, uint32_t first,
+                         uint32_t count, uint64_t* out_counts);
+/* Enqueue-only batch form; d_out: device array of count uint64. */
+eh_status eh_count_batch_async(eh_ctx* ctx, const eh_trie* batch, int pattern, uint32_t first,
+                               uint32_t count, uint64_t* d_out);
+
+/* ---- serving ------------------------------------------------------------ */
+
+/* A server keeps `resident` in HBM and answers rooted count requests.  A
+ * progress thread admits queued requests in arrival order while the summed
+ * footprint of active requests stays within hbm_budget_bytes and fewer than
+ * max_active are active, then advances all active requests together in
+ * device steps of at most step_items work items.  Zero fields take defaults. */
+typedef struct eh_server_opts {
+  uint64_t hbm_budget_bytes;
+  uint32_t max_active;
+  uint32_t max_queued;
+  uint32_t step_items;
+  uint32_t reserved;
+} eh_server_opts;
+
+typedef struct eh_req_stats {
+  uint64_t t_submit_ns;   /* CLOCK_MONOTONIC times */
+  uint64_t t_admit_ns;
+  uint64_t t_done_ns;
+  uint64_t items;         /* work items the request was split into */
+} eh_req_stats;
+
+/* The server uses ctx's device and allocator but its own stream; do not use
+ * ctx from another thread while the server lives. */
+eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server_opts* opts,
+                           eh_server** out);
+/* Copies roots; returns a ticket.  EH_EBUSY when max_queued are waiting,
+ * EH_ENOMEM when the request alone exceeds the budget. */
+eh_status eh_submit(eh_server* srv, int pattern, const uint32_t* roots, uint32_t n_roots,
+                    uint64_t* ticket);
+/* EH_OK with *count (and stats) once done; the ticket is then retired.
+ * EH_PENDING while queued or running; EH_ENOTFOUND for unknown tickets. */
+eh_status eh_poll(eh_server* srv, uint64_t ticket, uint64_t* count, eh_req_stats* stats);
+/* Blocks until the ticket is done (or timeout_ms passes: EH_PENDING). */
+eh_status eh_wait(eh_server* srv, uint64_t ticket, uint32_t timeout_ms, uint64_t* count,
+                  eh_req_stats* stats);
+/* Finishes admitted work, cancels queued requests, joins the thread. */
+eh_status eh_server_destroy(eh_server* srv);
+
+/* ---- host-side trie (no device needed) ----------------------------------- */
+
+/* The host half of eh_build_trie, exposed so the build can be checked
+ * without a GPU.  Arrays are owned by the handle. */
+eh_status eh_host_trie_build(const uint32_t* src, const uint32_t* dst, uint64_t n_edges,
+                             uint32_t n_vertices, const eh_build_opts* opts, eh_host_trie** out);
+/* Sizes: n, m_plus, n_bitset_sets, bitset_words, b_merge, max_out_degree. */
+eh_status eh_host_trie_info(const eh_host_trie* h, eh_trie_info* out);
+/* Copies out (any pointer may be NULL): rank[n] (rank of each id),
+ * row[n+1] and col[m_plus] (oriented CSR in rank space),
+ * bs_off[n] (word offset of each rank's bitset, 0xFFFFFFFF if none),
+ * bs_base[n] (first id covered, a multiple of 32), bs_nw[n] (words),
+ * bs_words[bitset_words]. */
+eh_status eh_host_trie_arrays(const eh_host_trie* h, uint32_t* rank, uint32_t* row, uint32_t* col,
+                              uint32_t* bs_off, uint32_t* bs_base, uint32_t* bs_nw,
+                              uint32_t* bs_words);
+eh_status eh_host_trie_free(eh_host_trie* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EH_H_ */

@@ -1,0 +1,436 @@
+// Host-side trie construction and work-item planning.
+//
+// Trie (paper section 2.2): ids are dictionary-encoded to dense 32-bit ranks
+// ordered by (degree ascending, id ascending); every undirected edge is kept
+// once, directed from lower to higher rank (the degree-based pruning of
+// section 5.2), giving a two-level trie stored as CSR.  Each non-empty
+// neighbour set keeps its uint layout and, when the set optimizer of section
+// 4.4 calls it dense, also a bitset layout (section 4.1) with one block
+// spanning [min, max]: base = min rounded down to a multiple of 32, words of
+// 32 bits.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "eh_internal.h"
+
+namespace eh {
+
+BuildOpts resolve_opts(const eh_build_opts* o) {
+  BuildOpts b;
+  if (!o) return b;
+  b.layout = o->layout;
+  b.tau = o->tau > 0.0f ? o->tau : 32.0f;
+  b.s_min = o->s_min ? o->s_min : 1;
+  return b;
+}
+
+namespace {
+
+// LSD radix sort of 64-bit keys on 16-bit digits, skipping constant digits.
+void radix_sort_u64(std::vector<uint64_t>& a) {
+  const size_t n = a.size();
+  if (n < 2) return;
+  std::vector<uint64_t> tmp(n);
+  std::vector<uint64_t> cnt(1 << 16);
+  for (int shift = 0; shift < 64; shift += 16) {
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (size_t i = 0; i < n; ++i) cnt[(a[i] >> shift) & 0xFFFF]++;
+    bool trivial = false;
+    for (uint64_t c : cnt)
+      if (c == n) { trivial = true; break; }
+    if (trivial) continue;
+    uint64_t s = 0;
+    for (auto& c : cnt) { uint64_t t = c; c = s; s += t; }
+    for (size_t i = 0; i < n; ++i) tmp[cnt[(a[i] >> shift) & 0xFFFF]++] = a[i];
+    a.swap(tmp);
+  }
+}
+
+// One graph, local ids; output arrays are local (ranks from 0, rows from 0).
+eh_status build_one(const uint32_t* src, const uint32_t* dst, uint64_t m_raw, uint32_t n,
+                    const BuildOpts& opts, HostTrie& h, std::string& err) {
+  for (uint64_t i = 0; i < m_raw; ++i) {
+    if (src[i] >= n || dst[i] >= n) {
+      err = "vertex id " + std::to_string(std::max(src[i], dst[i])) + " >= n = " +
+            std::to_string(n);
+      return EH_EINVAL;
+    }
+  }
+  // clean: drop loops, canonical {min, max}, sort, unique
+  std::vector<uint64_t> key;
+  key.reserve(m_raw);
+  for (uint64_t i = 0; i < m_raw; ++i) {
+    uint32_t a = src[i], b = dst[i];
+    if (a == b) continue;
+    if (a > b) std::swap(a, b);
+    key.push_back((uint64_t(a) << 32) | b);
+  }
+  radix_sort_u64(key);
+  key.erase(std::unique(key.begin(), key.end()), key.end());
+  const uint64_t m = key.size();
+  if (m > kMaxIndex) {
+    err = "graph has " + std::to_string(m) + " edges; at most 2^31-1 supported";
+    return EH_EOVERFLOW;
+  }
+  h.n = n;
+  h.m = m;
+  // degree in the simple undirected graph
+  std::vector<uint32_t> deg(n, 0);
+  for (uint64_t k : key) { deg[k >> 32]++; deg[k & 0xFFFFFFFFu]++; }
+  // rank by (degree asc, id asc): counting sort on degree, ids visited ascending
+  uint32_t maxd = 0;
+  for (uint32_t d : deg) maxd = std::max(maxd, d);
+  std::vector<uint32_t> start(size_t(maxd) + 2, 0);
+  for (uint32_t d : deg) start[d + 1]++;
+  for (size_t d = 1; d < start.size(); ++d) start[d] += start[d - 1];
+  h.rank.assign(n, 0);
+  h.vert.assign(n, 0);
+  for (uint32_t v = 0; v < n; ++v) {
+    const uint32_t r = start[deg[v]]++;
+    h.rank[v] = r;
+    h.vert[r] = v;
+  }
+  // orient low rank -> high rank; rows sorted by scattering in target order
+  std::vector<uint32_t> eu(m), ev(m);
+  std::vector<uint32_t> by_v(size_t(n) + 1, 0);
+  h.row.assign(size_t(n) + 1, 0);
+  for (uint64_t i = 0; i < m; ++i) {
+    uint32_t ra = h.rank[key[i] >> 32], rb = h.rank[key[i] & 0xFFFFFFFFu];
+    if (ra > rb) std::swap(ra, rb);
+    eu[i] = ra;
+    ev[i] = rb;
+    h.row[ra + 1]++;
+    by_v[rb + 1]++;
+  }
+  std::vector<uint64_t>().swap(key);
+  for (uint32_t r = 0; r < n; ++r) { h.row[r + 1] += h.row[r]; by_v[r + 1] += by_v[r]; }
+  std::vector<uint32_t> order(m);  // edge ids sorted by target rank
+  {
+    std::vector<uint32_t> fill(by_v.begin(), by_v.end() - 1);
+    for (uint64_t i = 0; i < m; ++i) order[fill[ev[i]]++] = uint32_t(i);
+  }
+  h.col.assign(m, 0);
+  {
+    std::vector<uint32_t> fill(h.row.begin(), h.row.end() - 1);
+    for (uint64_t k = 0; k < m; ++k) {
+      const uint32_t i = order[k];
+      h.col[fill[eu[i]]++] = ev[i];
+    }
+  }
+  // statistics
+  h.dmax = 0;
+  h.b_merge = 0;
+  for (uint32_t u = 0; u < n; ++u) {
+    const uint32_t du = h.row[u + 1] - h.row[u];
+    h.dmax = std::max(h.dmax, du);
+    for (uint32_t e = h.row[u]; e < h.row[u + 1]; ++e) {
+      const uint32_t v = h.col[e];
+      h.b_merge += 4ull * (du + (h.row[v + 1] - h.row[v]));
+    }
+  }
+  // set layouts
+  h.bs_off.assign(n, kNoBitset);
+  h.bs_base.assign(n, 0);
+  h.bs_nw.assign(n, 0);
+  h.bs_words.clear();
+  h.n_bs = 0;
+  if (opts.layout != EH_LAYOUT_UINT) {
+    uint64_t words = 0;
+    for (uint32_t u = 0; u < n; ++u) {
+      const uint32_t len = h.row[u + 1] - h.row[u];
+      if (len == 0) continue;
+      const uint32_t lo = h.col[h.row[u]], hi = h.col[h.row[u + 1] - 1];
+      const double range = double(hi) - double(lo) + 1.0;
+      bool dense;
+      if (opts.layout == EH_LAYOUT_BITSET_ALL)
+        dense = true;
+      else
+        dense = len >= opts.s_min && range <= double(opts.tau) * double(len);
+      if (!dense) continue;
+      const uint32_t base = lo & ~31u;
+      const uint32_t nw = ((hi - base) >> 5) + 1;
+      if (words + nw > kMaxIndex) {
+        err = "bitset words exceed 2^31-1";
+        return EH_EOVERFLOW;
+      }
+      h.bs_off[u] = uint32_t(words);
+      h.bs_base[u] = base;
+      h.bs_nw[u] = nw;
+      words += nw;
+      h.n_bs++;
+    }
+    h.bs_words.assign(words, 0);
+    for (uint32_t u = 0; u < n; ++u) {
+      if (h.bs_off[u] == kNoBitset) continue;
+      uint32_t* w = h.bs_words.data() + h.bs_off[u];
+      const uint32_t base = h.bs_base[u];
+      for (uint32_t e = h.row[u]; e < h.row[u + 1]; ++e) {
+        const uint32_t d = h.col[e] - base;
+        w[d >> 5] |= 1u << (d & 31);
+      }
+    }
+  }
+  h.n_graphs = 1;
+  h.g_vbase = {0, n};
+  return EH_OK;
+}
+
+}  // namespace
+
+eh_status host_build(const uint32_t* src, const uint32_t* dst, uint64_t n_edges, uint32_t n,
+                     const BuildOpts& opts, HostTrie& h, std::string& err) {
+  if (n == 0 && n_edges > 0) {
+    err = "edges given for an empty vertex set";
+    return EH_EINVAL;
+  }
+  return build_one(src, dst, n_edges, n, opts, h, err);
+}
+
+eh_status host_build_batch(uint32_t n_graphs, const uint32_t* n_vertices, const uint64_t* edge_off,
+                           const uint32_t* src, const uint32_t* dst, const BuildOpts& opts,
+                           HostTrie& h, std::string& err) {
+  uint64_t total_n = 0;
+  for (uint32_t g = 0; g < n_graphs; ++g) {
+    total_n += n_vertices[g];
+    if (edge_off[g + 1] < edge_off[g]) {
+      err = "edge_off is not monotone at graph " + std::to_string(g);
+      return EH_EINVAL;
+    }
+  }
+  if (total_n > kMaxIndex) {
+    err = "batch has more than 2^31-1 vertices";
+    return EH_EOVERFLOW;
+  }
+  std::vector<HostTrie> parts(n_graphs);
+  std::vector<eh_status> st(n_graphs, EH_OK);
+  std::vector<std::string> errs(n_graphs);
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::atomic<uint32_t> next{0};
+  auto worker = [&]() {
+    for (;;) {
+      const uint32_t g = next.fetch_add(1);
+      if (g >= n_graphs) return;
+      const uint64_t a = edge_off[g], b = edge_off[g + 1];
+      st[g] = build_one(src + a, dst + a, b - a, n_vertices[g], opts, parts[g], errs[g]);
+    }
+  };
+  std::vector<std::thread> th;
+  for (unsigned i = 0; i < nt; ++i) th.emplace_back(worker);
+  for (auto& t : th) t.join();
+  for (uint32_t g = 0; g < n_graphs; ++g) {
+    if (st[g] != EH_OK) {
+      err = "graph " + std::to_string(g) + ": " + errs[g];
+      return st[g];
+    }
+  }
+  // concatenate: graph g's ranks become vbase[g] + local rank
+  uint64_t M = 0, W = 0;
+  h = HostTrie();
+  h.n_graphs = n_graphs;
+  h.g_vbase.assign(size_t(n_graphs) + 1, 0);
+  // each graph's rank range starts at a multiple of 32 so bitset words of
+  // different sets stay aligned to one another; padding ranks are isolated
+  uint64_t padded = 0;
+  for (uint32_t g = 0; g < n_graphs; ++g) padded += (uint64_t(parts[g].n) + 31) & ~uint64_t(31);
+  if (padded > kMaxIndex) {
+    err = "batch has more than 2^31-1 vertices";
+    return EH_EOVERFLOW;
+  }
+  for (uint32_t g = 0; g < n_graphs; ++g) {
+    h.g_vbase[g + 1] = h.g_vbase[g] + ((parts[g].n + 31u) & ~31u);
+    M += parts[g].m;
+    W += parts[g].bs_words.size();
+  }
+  if (M > kMaxIndex || W > kMaxIndex) {
+    err = "batch exceeds 2^31-1 edges or bitset words";
+    return EH_EOVERFLOW;
+  }
+  const uint32_t N = uint32_t(padded);
+  h.n = N;
+  h.m = M;
+  h.rank.resize(N);
+  h.vert.resize(N);
+  h.row.resize(size_t(N) + 1);
+  h.col.resize(M);
+  h.bs_off.resize(N);
+  h.bs_base.resize(N);
+  h.bs_nw.resize(N);
+  h.bs_words.resize(W);
+  std::vector<uint64_t> ebase(n_graphs + 1, 0), wbase(n_graphs + 1, 0);
+  for (uint32_t g = 0; g < n_graphs; ++g) {
+    ebase[g + 1] = ebase[g] + parts[g].m;
+    wbase[g + 1] = wbase[g] + parts[g].bs_words.size();
+  }
+  next = 0;
+  auto copier = [&]() {
+    for (;;) {
+      const uint32_t g = next.fetch_add(1);
+      if (g >= n_graphs) return;
+      const HostTrie& p = parts[g];
+      const uint32_t vb = h.g_vbase[g];
+      const uint32_t eb = uint32_t(ebase[g]);
+      const uint32_t wb = uint32_t(wbase[g]);
+      for (uint32_t v = 0; v < p.n; ++v) {
+        h.rank[vb + v] = vb + p.rank[v];
+        h.vert[vb + v] = vb + p.vert[v];
+        h.row[vb + v] = eb + p.row[v];
+        h.bs_off[vb + v] = p.bs_off[v] == kNoBitset ? kNoBitset : wb + p.bs_off[v];
+        h.bs_base[vb + v] = vb + p.bs_base[v];  // vb is a multiple of 32
+        h.bs_nw[vb + v] = p.bs_nw[v];
+      }
+      for (uint32_t v = vb + p.n; v < h.g_vbase[g + 1]; ++v) {
+        h.rank[v] = v;
+        h.vert[v] = v;
+        h.row[v] = eb + uint32_t(p.m);
+        h.bs_off[v] = kNoBitset;
+        h.bs_base[v] = 0;
+        h.bs_nw[v] = 0;
+      }
+      for (uint64_t e = 0; e < p.m; ++e) h.col[eb + e] = vb + p.col[e];
+      std::copy(p.bs_words.begin(), p.bs_words.end(), h.bs_words.begin() + wb);
+    }
+  };
+  th.clear();
+  for (unsigned i = 0; i < nt; ++i) th.emplace_back(copier);
+  for (auto& t : th) t.join();
+  h.row[N] = uint32_t(M);
+  h.dmax = 0;
+  h.b_merge = 0;
+  h.n_bs = 0;
+  for (uint32_t g = 0; g < n_graphs; ++g) {
+    h.dmax = std::max(h.dmax, parts[g].dmax);
+    h.b_merge += parts[g].b_merge;
+    h.n_bs += parts[g].n_bs;
+  }
+  return EH_OK;
+}
+
+// ---- work items -------------------------------------------------------------
+
+namespace {
+
+inline uint32_t out_deg(const HostTrie& h, uint32_t v) { return h.row[v + 1] - h.row[v]; }
+
+// elements the kernel streams for set v: its words when the bitset is shorter
+inline uint32_t stream_len(const HostTrie& h, uint32_t v, bool use_bitsets) {
+  const uint32_t d = out_deg(h, v);
+  if (use_bitsets && h.bs_off[v] != kNoBitset && h.bs_nw[v] < d) return h.bs_nw[v];
+  return d;
+}
+
+// Split the streamed list idx[lb .. lb+len) of staged vertex s into items of
+// about `chunk` streamed elements each.
+template <class CostFn>
+void split_items(uint32_t s, uint32_t lb, uint32_t len, uint32_t tag, uint32_t chunk,
+                 uint32_t stage_cost, CostFn cost, std::vector<Item>& out) {
+  uint32_t i = 0;
+  while (i < len) {
+    uint64_t acc = stage_cost;
+    uint32_t j = i;
+    while (j < len) {
+      acc += cost(lb + j);
+      ++j;
+      if (acc >= chunk) break;
+    }
+    out.push_back(Item{s, lb + i, j - i, tag});
+    i = j;
+  }
+}
+
+}  // namespace
+
+void make_items_source(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chunk_work,
+                       uint32_t pattern, bool use_bitsets, std::vector<Item>& out) {
+  const uint32_t du = out_deg(h, u);
+  if (du < (pattern == EH_4CLIQUE ? 3u : 2u)) return;
+  const uint32_t lb = h.row[u];
+  if (pattern == EH_TRIANGLE) {
+    split_items(u, lb, du, tag, chunk_work, du,
+                [&](uint32_t e) { return uint64_t(stream_len(h, h.col[e], use_bitsets)) + 2; },
+                out);
+  } else {
+    // level 1 streams N+(v); level 2 streams N+(w) for w in S, |S| <= min(du, dv)
+    split_items(u, lb, du, tag, chunk_work, du,
+                [&](uint32_t e) {
+                  const uint32_t dv = out_deg(h, h.col[e]);
+                  return uint64_t(dv) + 2 + uint64_t(std::min(du, dv)) * 24;
+                },
+                out);
+  }
+}
+
+eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** out) {
+  const Tuning& tu = c->tune;
+  const uint32_t chunk = std::max<uint32_t>(tu.chunk_work, 64);
+  if (pattern == EH_4CLIQUE) staging = EH_STAGE_SOURCE;
+  for (auto& p : t->plans) {
+    if (p->pattern == pattern && p->staging == staging && p->chunk_work == chunk &&
+        p->use_bitsets == tu.use_bitsets) {
+      *out = p.get();
+      return EH_OK;
+    }
+  }
+  const HostTrie& h = t->host;
+  std::vector<Item> items;
+  auto plan = std::make_unique<Plan>();
+  plan->pattern = pattern;
+  plan->staging = staging;
+  plan->chunk_work = chunk;
+  plan->use_bitsets = tu.use_bitsets;
+  plan->g_item_off.assign(size_t(h.n_graphs) + 1, 0);
+  const bool ub = tu.use_bitsets != 0;
+  if (staging == EH_STAGE_TARGET) {
+    if (!t->has_transpose) {
+      // in-neighbour lists, ascending
+      t->trow.assign(size_t(h.n) + 1, 0);
+      for (uint64_t e = 0; e < h.m; ++e) t->trow[h.col[e] + 1]++;
+      for (uint32_t v = 0; v < h.n; ++v) t->trow[v + 1] += t->trow[v];
+      t->tcol.assign(h.m, 0);
+      std::vector<uint32_t> fill(t->trow.begin(), t->trow.end() - 1);
+      for (uint32_t u = 0; u < h.n; ++u)
+        for (uint32_t e = h.row[u]; e < h.row[u + 1]; ++e) t->tcol[fill[h.col[e]]++] = u;
+      eh_status st = dev_alloc(c, t->tcol_d, sizeof(uint32_t) * std::max<uint64_t>(h.m, 1));
+      if (st != EH_OK) return st;
+      if (h.m)
+        if ((st = hip_check(c, hipMemcpy(t->tcol_d.p, t->tcol.data(), sizeof(uint32_t) * h.m,
+                                         hipMemcpyHostToDevice), "upload in-neighbours")) != EH_OK)
+          return st;
+      t->device_bytes += t->tcol_d.bytes;
+      t->has_transpose = true;
+    }
+  }
+  for (uint32_t g = 0; g < h.n_graphs; ++g) {
+    plan->g_item_off[g] = items.size();
+    const uint32_t v0 = h.g_vbase[g], v1 = h.g_vbase[g + 1];
+    const uint32_t tag = h.n_graphs > 1 ? g : 0;
+    if (staging == EH_STAGE_TARGET) {
+      for (uint32_t v = v0; v < v1; ++v) {
+        const uint32_t dv = out_deg(h, v);
+        const uint32_t lb = t->trow[v], len = t->trow[v + 1] - t->trow[v];
+        if (dv == 0 || len == 0) continue;
+        split_items(v, lb, len, tag, chunk, dv,
+                    [&](uint32_t k) { return uint64_t(stream_len(h, t->tcol[k], ub)) + 2; },
+                    items);
+      }
+    } else {
+      for (uint32_t u = v0; u < v1; ++u) make_items_source(h, u, tag, chunk, pattern, ub, items);
+    }
+  }
+  plan->g_item_off[h.n_graphs] = items.size();
+  plan->n_items = items.size();
+  eh_status st = dev_alloc(c, plan->items, sizeof(Item) * std::max<size_t>(items.size(), 1));
+  if (st != EH_OK) return st;
+  if (!items.empty())
+    if ((st = hip_check(c, hipMemcpy(plan->items.p, items.data(), sizeof(Item) * items.size(),
+                                     hipMemcpyHostToDevice), "upload work items")) != EH_OK) {
+      dev_free(c, plan->items);
+      return st;
+    }
+  *out = plan.get();
+  t->plans.push_back(std::move(plan));
+  return EH_OK;
+}
+
+}  // namespace eh

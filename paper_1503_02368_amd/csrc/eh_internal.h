@@ -1,0 +1,193 @@
+// Internal declarations shared by the host and device halves of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/eh.h"
+
+namespace eh {
+
+constexpr uint32_t kNoBitset = 0xFFFFFFFFu;
+constexpr uint32_t kHiBit = 0x80000000u;   // vdesc.y: the set also has a bitset
+constexpr uint32_t kMaxIndex = 0x7FFFFFFFu;  // offsets must stay below 2^31
+
+// One unit of scheduled work: the set N+(s) is held on chip while the sets
+// N+(t) of the streamed vertices t = idx[lbeg .. lbeg+llen) are intersected
+// with it.  tag selects the output accumulator (graph or request slot).
+struct Item {
+  uint32_t s;
+  uint32_t lbeg;
+  uint32_t llen;
+  uint32_t tag;
+};
+static_assert(sizeof(Item) == 16, "Item is one 128-bit load");
+
+// Host half of a trie: rank-space oriented CSR plus set layouts.
+struct HostTrie {
+  uint32_t n = 0;
+  uint64_t m = 0;                    // oriented edges
+  uint32_t dmax = 0;                 // max out-degree
+  uint64_t b_merge = 0;
+  std::vector<uint32_t> rank;        // rank[id]
+  std::vector<uint32_t> vert;        // vert[rank] = id
+  std::vector<uint32_t> row;         // [n+1]
+  std::vector<uint32_t> col;         // [m], rank ids, rows ascending
+  std::vector<uint32_t> bs_off;      // [n] word offset or kNoBitset
+  std::vector<uint32_t> bs_base;     // [n]
+  std::vector<uint32_t> bs_nw;       // [n]
+  std::vector<uint32_t> bs_words;
+  uint64_t n_bs = 0;
+  // batch: graph g owns ranks [g_vbase[g], g_vbase[g+1]) and edges
+  // [row[g_vbase[g]], row[g_vbase[g+1]])
+  std::vector<uint32_t> g_vbase;     // [G+1]
+  uint32_t n_graphs = 1;
+};
+
+struct BuildOpts {
+  uint32_t layout = EH_LAYOUT_HYBRID;
+  float tau = 32.0f;
+  uint32_t s_min = 1;
+};
+BuildOpts resolve_opts(const eh_build_opts* o);
+
+// Builds one graph's trie into h (appending when h already holds graphs:
+// batch construction).  Returns EH_OK / EH_EINVAL / EH_EOVERFLOW.
+eh_status host_build(const uint32_t* src, const uint32_t* dst, uint64_t n_edges, uint32_t n,
+                     const BuildOpts& opts, HostTrie& h, std::string& err);
+eh_status host_build_batch(uint32_t n_graphs, const uint32_t* n_vertices, const uint64_t* edge_off,
+                           const uint32_t* src, const uint32_t* dst, const BuildOpts& opts,
+                           HostTrie& h, std::string& err);
+
+struct Tuning {
+  uint32_t kernel = EH_KERNEL_STAGED;
+  uint32_t staging = EH_STAGE_TARGET;
+  uint32_t algo = EH_ALGO_AUTO;
+  float gamma = 32.0f;
+  uint32_t chunk_work = 4096;
+  uint32_t waves_per_cu = 32;
+  uint32_t group_lanes = 0;
+  uint32_t use_bitsets = 1;
+  uint32_t dynamic = 0;
+  uint32_t stage_words = 0;
+};
+
+struct Ctx;
+
+// Device buffer owned through the context's allocator.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Work-item plan of one (pattern, staging, granularity) on a trie.
+struct Plan {
+  uint32_t pattern = 0;
+  uint32_t staging = 0;
+  uint32_t chunk_work = 0;
+  uint32_t use_bitsets = 0;
+  uint64_t n_items = 0;
+  DevBuf items;
+  std::vector<uint64_t> g_item_off;  // batch: items of graph g are [off[g], off[g+1])
+};
+
+struct Trie {
+  Ctx* ctx = nullptr;
+  HostTrie host;
+  bool has_transpose = false;
+  std::vector<uint32_t> trow, tcol;  // in-neighbours, host copy
+  // device arrays
+  DevBuf vdesc;   // uint2 [n]: {row begin, out-degree | kHiBit if bitset}
+  DevBuf col;     // uint32 [m]
+  DevBuf bsdesc;  // uint4 [n]: {word offset, base, words, 0}
+  DevBuf bsw;     // uint32 bitset words
+  DevBuf vert;    // uint32 [n]: rank -> id
+  DevBuf tcol_d;  // uint32 [m]: in-neighbour lists (target staging)
+  std::vector<std::unique_ptr<Plan>> plans;
+  uint64_t device_bytes = 0;
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  eh_allocator alloc{};
+  bool has_alloc = false;
+  Tuning tune;
+  std::string err;
+  int n_cu = 256;
+  // scratch: accumulators and cursor
+  DevBuf acc;       // uint64 accumulators
+  size_t acc_cap = 0;
+  DevBuf cursor;    // uint32 work cursors
+  uint64_t* pinned = nullptr;  // host staging for results
+  size_t pinned_cap = 0;
+};
+
+// Allocation through the context.
+eh_status dev_alloc(Ctx* c, DevBuf& b, size_t bytes);
+void dev_free(Ctx* c, DevBuf& b);
+eh_status hip_check(Ctx* c, hipError_t e, const char* what);
+eh_status ensure_acc(Ctx* c, size_t n);
+eh_status ensure_pinned(Ctx* c, size_t n);
+
+// Work-item construction (host) and the plan cache.
+eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** out);
+void make_items_source(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chunk_work,
+                       uint32_t pattern, bool use_bitsets, std::vector<Item>& out);
+
+// Device launches (eh_kernels.hip).  All enqueue on `stream`.
+struct LaunchArgs {
+  const Item* items = nullptr;
+  uint64_t n_items = 0;
+  const uint32_t* idx = nullptr;       // streamed vertex list (col or tcol)
+  const uint2* vdesc = nullptr;
+  const uint32_t* col = nullptr;
+  const uint4* bsdesc = nullptr;
+  const uint32_t* bsw = nullptr;
+  unsigned long long* acc = nullptr;   // accumulators indexed by item tag
+  uint32_t tag_base = 0;               // acc index = tag - tag_base
+  unsigned long long* per_root = nullptr;  // optional, source staging only
+  const uint32_t* vert = nullptr;
+  uint32_t* cursor = nullptr;
+  uint32_t use_bitsets = 0;
+  uint32_t dynamic = 0;
+  uint32_t algo = EH_ALGO_AUTO;
+  float gamma = 32.0f;
+  uint32_t group_lanes = 0;
+  uint32_t dmax = 0;
+  uint32_t stage_words = 0;            // 0: kernel maximum
+};
+eh_status launch_fill_u64(Ctx* c, hipStream_t s, unsigned long long* p, uint64_t n,
+                          unsigned long long v);
+eh_status launch_triangles(Ctx* c, hipStream_t s, const LaunchArgs& a, uint32_t kernel,
+                           uint32_t waves_per_cu);
+eh_status launch_4cliques(Ctx* c, hipStream_t s, const LaunchArgs& a, uint32_t kernel,
+                          uint32_t waves_per_cu);
+eh_status launch_scatter_roots(Ctx* c, hipStream_t s, const unsigned long long* by_rank,
+                               const uint32_t* vert, unsigned long long* by_id, uint32_t n);
+// Largest out-degree the staged 4-clique kernel accepts.
+uint32_t k4_staged_max_degree();
+
+}  // namespace eh
+
+struct eh_ctx {
+  eh::Ctx c;
+};
+struct eh_trie {
+  eh::Trie t;
+};
+struct eh_host_trie {
+  eh::HostTrie h;
+};

@@ -1,0 +1,650 @@
+// gfx950 kernels for the set intersections of Generic-Join (paper section 2.1,
+// Algorithm 1) on the degree-pruned trie, with COUNT(*) aggregation.
+//
+// Triangle:  T = sum over oriented edges (u,v) of |N+(u) & N+(v)|
+// 4-clique:  K = sum over (u,v) of sum over w in S of |S & N+(w)|,
+//            S = N+(u) & N+(v)   (the loop nest of section 3.3 extended by
+//            one attribute; one GHD node, section 5.3)
+//
+// Two kernel families consume the same work items {s, idx[lbeg..+llen), tag}:
+//
+// * Staged ("k_*_staged"): one wave per item.  The set N+(s) is written into
+//   the wave's LDS region once, as a bitset over [min, max] when that range
+//   fits (the bitset layout of section 4.1 with one block of the set's range,
+//   as the set optimizer of section 4.4 builds it), else as a sorted list.
+//   The sets N+(t) of all streamed vertices t are concatenated into one flat
+//   index space that the 64 lanes walk with a per-lane segment cursor, so
+//   short and long lists alike keep every lane busy and reads coalesced.
+//   Each streamed element is tested against the staged set: a bit probe
+//   (uint & bitset, section 4.2), or, when t's set is stored as a bitset
+//   with fewer words than elements, a 32-bit word AND + popcount (bitset &
+//   bitset), or a binary search in the staged list (galloping).
+//
+// * Pairwise ("k_tri_pairwise"): a group of G lanes per pair (s, t) reading
+//   both sets from HBM, dispatching per pair on the layouts and sizes as in
+//   section 4.2: bitset & bitset by word AND + popcount over the overlapping
+//   words; uint & bitset by probing each uint value; uint & uint by a
+//   partitioned merge when the sizes are within a factor gamma (32 in the
+//   paper) and by binary search of the shorter list's values in the longer
+//   one otherwise.
+//
+// Counts accumulate per lane in registers and leave a wave through one
+// reduction and one 64-bit atomic per output slot change.
+#include <hip/hip_runtime.h>
+
+#include "eh_internal.h"
+
+namespace eh {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kSeg = 64;  // streamed sets per flat batch
+
+struct DevArgs {
+  const Item* items;
+  uint64_t n_items;
+  const uint32_t* idx;
+  const uint2* vdesc;
+  const uint32_t* col;
+  const uint4* bsdesc;
+  const uint32_t* bsw;
+  unsigned long long* acc;
+  uint32_t tag_base;
+  unsigned long long* per_root;
+  const uint32_t* vert;
+  uint32_t* cursor;
+  uint32_t use_bitsets;
+  uint32_t dynamic;
+  uint32_t algo;
+  float gamma;
+  uint32_t stage_words;  // <= the kernel's region size
+};
+
+DevArgs to_dev(const LaunchArgs& a) {
+  DevArgs d;
+  d.items = a.items;
+  d.n_items = a.n_items;
+  d.idx = a.idx;
+  d.vdesc = a.vdesc;
+  d.col = a.col;
+  d.bsdesc = a.bsdesc;
+  d.bsw = a.bsw;
+  d.acc = a.acc;
+  d.tag_base = a.tag_base;
+  d.per_root = a.per_root;
+  d.vert = a.vert;
+  d.cursor = a.cursor;
+  d.use_bitsets = a.use_bitsets;
+  d.dynamic = a.dynamic;
+  d.algo = a.algo;
+  d.gamma = a.gamma;
+  d.stage_words = a.stage_words;
+  return d;
+}
+
+// Orders the wave's LDS accesses before and after this point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t x) {
+  return __builtin_amdgcn_readfirstlane(x);
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, kWave);
+    if (lane >= uint32_t(o)) v += t;
+  }
+  return v;
+}
+
+// first index in a[0..n) with a[i] >= x
+__device__ __forceinline__ uint32_t lower_bound_lds(const uint32_t* a, uint32_t n, uint32_t x) {
+  uint32_t lo = 0, len = n;
+  while (len > 0) {
+    const uint32_t half = len >> 1;
+    if (a[lo + half] < x) { lo += half + 1; len -= half + 1; }
+    else len = half;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t lower_bound_glb(const uint32_t* __restrict__ a, uint32_t n,
+                                                    uint32_t x) {
+  uint32_t lo = 0, len = n;
+  while (len > 0) {
+    const uint32_t half = len >> 1;
+    if (a[lo + half] < x) { lo += half + 1; len -= half + 1; }
+    else len = half;
+  }
+  return lo;
+}
+
+// Work-item iteration: static interleave or an atomic cursor.
+struct ItemIter {
+  uint64_t i, step;
+  bool dyn;
+  uint32_t* cursor;
+  __device__ ItemIter(const DevArgs& a, uint32_t wpb) {
+    dyn = a.dynamic != 0;
+    cursor = a.cursor;
+    step = uint64_t(gridDim.x) * wpb;
+    if (dyn) i = fetch();
+    else i = uint64_t(blockIdx.x) * wpb + (threadIdx.x >> 6);
+  }
+  __device__ uint64_t fetch() {
+    uint32_t v = 0;
+    if ((threadIdx.x & 63) == 0) v = atomicAdd(cursor, 1u);
+    return uniform(__shfl(v, 0, kWave));
+  }
+  __device__ void next() {
+    if (dyn) i = fetch();
+    else i += step;
+  }
+};
+
+// Adds a wave's per-lane counts to acc[tag - tag_base] (one atomic per wave).
+__device__ __forceinline__ void flush_tag(const DevArgs& a, unsigned long long& acc, uint32_t tag,
+                                          uint32_t lane) {
+  const unsigned long long s = wave_sum(acc);
+  if (lane == 0 && s) atomicAdd(&a.acc[tag - a.tag_base], s);
+  acc = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Staged set: state shared by the triangle and 4-clique kernels
+// ---------------------------------------------------------------------------
+
+enum : uint32_t { kModeBitmap = 0, kModeList = 1, kModeGlobal = 2 };
+
+struct Staged {
+  uint32_t beg, len, lo, hi, lo_al, mode;
+};
+
+// Loads N+(s) into region R (RW words) and returns how it is held.
+template <int RW>
+__device__ __forceinline__ Staged stage_set(const DevArgs& a, uint32_t s, uint32_t* R,
+                                            uint32_t lane) {
+  Staged st;
+  const uint2 sd = a.vdesc[s];
+  st.beg = uniform(sd.x);
+  st.len = uniform(sd.y & kMaxIndex);
+  if (st.len == 0) { st.mode = kModeGlobal; st.lo = st.hi = st.lo_al = 0; return st; }
+  st.lo = uniform(a.col[st.beg]);
+  st.hi = uniform(a.col[st.beg + st.len - 1]);
+  st.lo_al = st.lo & ~31u;
+  const uint32_t cap = (a.stage_words && a.stage_words < uint32_t(RW)) ? a.stage_words : uint32_t(RW);
+  if (st.hi - st.lo_al < cap * 32u) st.mode = kModeBitmap;
+  else if (st.len <= cap) st.mode = kModeList;
+  else st.mode = kModeGlobal;
+  if (st.mode == kModeBitmap) {
+    for (uint32_t k = lane; k < st.len; k += kWave) {
+      const uint32_t d = a.col[st.beg + k] - st.lo_al;
+      atomicOr(&R[d >> 5], 1u << (d & 31));
+    }
+  } else if (st.mode == kModeList) {
+    for (uint32_t k = lane; k < st.len; k += kWave) R[k] = a.col[st.beg + k];
+  }
+  wave_sync();
+  return st;
+}
+
+// Returns region R to all-zero after stage_set.
+template <int RW>
+__device__ __forceinline__ void unstage_set(const DevArgs& a, const Staged& st, uint32_t* R,
+                                            uint32_t lane) {
+  wave_sync();
+  if (st.mode == kModeBitmap) {
+    for (uint32_t k = lane; k < st.len; k += kWave) R[(a.col[st.beg + k] - st.lo_al) >> 5] = 0;
+  } else if (st.mode == kModeList) {
+    for (uint32_t k = lane; k < st.len; k += kWave) R[k] = 0;
+  }
+  wave_sync();
+}
+
+// Membership of x in the staged set (uint & bitset probe, or galloping search).
+template <int RW>
+__device__ __forceinline__ uint32_t staged_has(const DevArgs& a, const Staged& st,
+                                               const uint32_t* R, uint32_t x) {
+  if (st.mode == kModeBitmap) {
+    const uint32_t d = x - st.lo_al;
+    return d < uint32_t(RW) * 32u ? (R[d >> 5] >> (d & 31)) & 1u : 0u;
+  }
+  if (x < st.lo || x > st.hi) return 0u;
+  if (st.mode == kModeList) {
+    const uint32_t p = lower_bound_lds(R, st.len, x);
+    return R[p] == x ? 1u : 0u;
+  }
+  const uint32_t* L = a.col + st.beg;
+  const uint32_t p = lower_bound_glb(L, st.len, x);
+  return L[p] == x ? 1u : 0u;
+}
+
+// Segment table of one flat batch: P = prefix of lengths (kSeg+1),
+// SB = start in col (or kHiBit | start in bsw), SM = word delta for bitsets.
+struct SegTab {
+  uint32_t* P;
+  uint32_t* SB;
+  int32_t* SM;
+};
+
+// Fills the segment table for streamed vertices vs[0..nseg) (one per lane)
+// and returns the flat length.  Bitset words are used only against a staged
+// bitmap, and only when they are fewer than the set's elements.
+__device__ __forceinline__ uint32_t load_segments(const DevArgs& a, const SegTab& T, uint32_t t,
+                                                  bool active, bool bitmap_ok, uint32_t lo_al,
+                                                  uint32_t lane) {
+  uint32_t len = 0, sb = 0;
+  int32_t sm = 0;
+  if (active) {
+    const uint2 td = a.vdesc[t];
+    const uint32_t tl = td.y & kMaxIndex;
+    sb = td.x;
+    len = tl;
+    if (bitmap_ok && (td.y & kHiBit)) {
+      const uint4 bd = a.bsdesc[t];
+      if (bd.z < tl) {
+        sb = bd.x | kHiBit;
+        len = bd.z;
+        sm = int32_t(bd.y >> 5) - int32_t(lo_al >> 5);
+      }
+    }
+  }
+  const uint32_t incl = wave_incl_scan(len, lane);
+  wave_sync();  // previous batch's readers are done
+  T.P[lane + 1] = incl;
+  if (lane == 0) T.P[0] = 0;
+  T.SB[lane] = sb;
+  T.SM[lane] = sm;
+  wave_sync();
+  return uniform(__shfl(incl, kWave - 1, kWave));
+}
+
+// Walks flat indices lane, lane+64, ... < E of the segment table and tests
+// each element against the staged set held in R (bitmap, list or global).
+template <int RW, int U>
+__device__ __forceinline__ uint32_t flat_probe(const DevArgs& a, const SegTab& T, uint32_t E,
+                                               const Staged& st, const uint32_t* R,
+                                               uint32_t lane) {
+  uint32_t cnt = 0;
+  uint32_t j = 0, cur = 0, nxt = T.P[1], jsb = T.SB[0];
+  int32_t jsm = T.SM[0];
+  for (uint32_t f0 = 0; f0 < E; f0 += kWave * U) {
+    uint32_t val[U];
+    uint32_t wix[U];
+    bool ok[U], isbs[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t f = f0 + uint32_t(u) * kWave + lane;
+      ok[u] = f < E;
+      isbs[u] = false;
+      val[u] = 0;
+      wix[u] = 0;
+      if (ok[u]) {
+        while (nxt <= f) {
+          ++j;
+          cur = nxt;
+          nxt = T.P[j + 1];
+          jsb = T.SB[j];
+          jsm = T.SM[j];
+        }
+        const uint32_t off = f - cur;
+        isbs[u] = (jsb & kHiBit) != 0;
+        const uint32_t* src = isbs[u] ? a.bsw : a.col;
+        val[u] = src[(jsb & kMaxIndex) + off];
+        wix[u] = uint32_t(jsm + int32_t(off));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!ok[u]) continue;
+      if (isbs[u]) {
+        // bitset & bitset: one 32-bit word against the staged bitmap
+        if (wix[u] < uint32_t(RW)) cnt += __popc(val[u] & R[wix[u]]);
+      } else {
+        cnt += staged_has<RW>(a, st, R, val[u]);
+      }
+    }
+  }
+  return cnt;
+}
+
+// ---------------------------------------------------------------------------
+// Triangles, staged
+// ---------------------------------------------------------------------------
+
+template <int WPB, int RW, int U>
+__global__ __launch_bounds__(WPB * kWave) void k_tri_staged(DevArgs a) {
+  __shared__ uint32_t s_region[WPB][RW];
+  __shared__ uint32_t s_pre[WPB][kSeg + 1];
+  __shared__ uint32_t s_sb[WPB][kSeg];
+  __shared__ int32_t s_sm[WPB][kSeg];
+  const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
+  uint32_t* R = s_region[wid];
+  const SegTab T{s_pre[wid], s_sb[wid], s_sm[wid]};
+  for (uint32_t k = lane; k < uint32_t(RW); k += kWave) R[k] = 0;
+  wave_sync();
+  unsigned long long acc = 0;
+  uint32_t cur_tag = 0;
+  bool have_tag = false;
+  for (ItemIter it(a, WPB); it.i < a.n_items; it.next()) {
+    const Item item = a.items[it.i];
+    const uint32_t s = uniform(item.s), lbeg = uniform(item.lbeg), llen = uniform(item.llen);
+    const uint32_t tag = uniform(item.tag);
+    if (have_tag && tag != cur_tag) flush_tag(a, acc, cur_tag, lane);
+    cur_tag = tag;
+    have_tag = true;
+    const Staged st = stage_set<RW>(a, s, R, lane);
+    if (st.len == 0) continue;
+    const bool bitmap_ok = a.use_bitsets && st.mode == kModeBitmap;
+    uint32_t cnt = 0;
+    for (uint32_t b0 = 0; b0 < llen; b0 += kSeg) {
+      const uint32_t nseg = min(uint32_t(kSeg), llen - b0);
+      const bool active = lane < nseg;
+      const uint32_t t = active ? a.idx[lbeg + b0 + lane] : 0u;
+      const uint32_t E = load_segments(a, T, t, active, bitmap_ok, st.lo_al, lane);
+      cnt += flat_probe<RW, U>(a, T, E, st, R, lane);
+    }
+    acc += cnt;
+    if (a.per_root) {
+      const unsigned long long tot = wave_sum((unsigned long long)cnt);
+      if (lane == 0 && tot) atomicAdd(&a.per_root[a.vert[s]], tot);
+    }
+    unstage_set<RW>(a, st, R, lane);
+  }
+  if (have_tag) flush_tag(a, acc, cur_tag, lane);
+}
+
+// ---------------------------------------------------------------------------
+// 4-cliques, staged: N+(u) in region A; per v, S = N+(u) & N+(v) is written
+// in order to list S and (bitmap mode) to bitmap B; level 2 streams N+(w)
+// for w in S against B (or searches the list S).
+// ---------------------------------------------------------------------------
+
+template <int WPB, int RW, int SCAP, int U>
+__global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
+  __shared__ uint32_t s_A[WPB][RW];
+  __shared__ uint32_t s_B[WPB][RW];
+  __shared__ uint32_t s_S[WPB][SCAP];
+  __shared__ uint32_t s_pre[WPB][kSeg + 1];
+  __shared__ uint32_t s_sb[WPB][kSeg];
+  __shared__ int32_t s_sm[WPB][kSeg];
+  const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
+  uint32_t* A = s_A[wid];
+  uint32_t* B = s_B[wid];
+  uint32_t* S = s_S[wid];
+  const SegTab T{s_pre[wid], s_sb[wid], s_sm[wid]};
+  for (uint32_t k = lane; k < uint32_t(RW); k += kWave) { A[k] = 0; B[k] = 0; }
+  wave_sync();
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
+  unsigned long long acc = 0;
+  uint32_t cur_tag = 0;
+  bool have_tag = false;
+  for (ItemIter it(a, WPB); it.i < a.n_items; it.next()) {
+    const Item item = a.items[it.i];
+    const uint32_t u = uniform(item.s), lbeg = uniform(item.lbeg), llen = uniform(item.llen);
+    const uint32_t tag = uniform(item.tag);
+    if (have_tag && tag != cur_tag) flush_tag(a, acc, cur_tag, lane);
+    cur_tag = tag;
+    have_tag = true;
+    const Staged su = stage_set<RW>(a, u, A, lane);
+    if (su.len == 0) continue;
+    uint32_t cnt = 0;
+    for (uint32_t q = 0; q < llen; ++q) {
+      const uint32_t v = uniform(a.idx[lbeg + q]);
+      const uint2 vd = a.vdesc[v];
+      const uint32_t vb = uniform(vd.x), vl = uniform(vd.y & kMaxIndex);
+      // level 1: S = N+(u) & N+(v), compacted in ascending order
+      uint32_t ns = 0;
+      for (uint32_t k0 = 0; k0 < vl; k0 += kWave) {
+        const uint32_t k = k0 + lane;
+        uint32_t x = 0, hit = 0;
+        if (k < vl) {
+          x = a.col[vb + k];
+          hit = staged_has<RW>(a, su, A, x);
+        }
+        const unsigned long long m = __ballot(hit);
+        if (hit) {
+          S[ns + __popcll(m & lt_mask)] = x;
+          if (su.mode == kModeBitmap) {
+            const uint32_t d = x - su.lo_al;
+            atomicOr(&B[d >> 5], 1u << (d & 31));
+          }
+        }
+        ns += uint32_t(__popcll(m));
+      }
+      wave_sync();
+      if (ns >= 2) {
+        // level 2: sum over w in S of |S & N+(w)|
+        Staged ss;
+        ss.beg = 0;
+        ss.len = ns;
+        ss.lo = S[0];
+        ss.hi = S[ns - 1];
+        ss.lo_al = su.lo_al;
+        ss.mode = su.mode == kModeBitmap ? kModeBitmap : kModeList;
+        const uint32_t* probe = su.mode == kModeBitmap ? B : S;
+        const bool bitmap_ok = a.use_bitsets && ss.mode == kModeBitmap;
+        for (uint32_t b0 = 0; b0 < ns; b0 += kSeg) {
+          const uint32_t nseg = min(uint32_t(kSeg), ns - b0);
+          const bool active = lane < nseg;
+          const uint32_t w = active ? S[b0 + lane] : 0u;
+          const uint32_t E = load_segments(a, T, w, active, bitmap_ok, ss.lo_al, lane);
+          // bitmap bounds are B's (RW words); the list S is searched by length
+          cnt += flat_probe<RW, U>(a, T, E, ss, probe, lane);
+        }
+      }
+      wave_sync();
+      if (su.mode == kModeBitmap)
+        for (uint32_t i = lane; i < ns; i += kWave) B[(S[i] - su.lo_al) >> 5] = 0;
+      wave_sync();
+    }
+    acc += cnt;
+    if (a.per_root) {
+      const unsigned long long tot = wave_sum((unsigned long long)cnt);
+      if (lane == 0 && tot) atomicAdd(&a.per_root[a.vert[u]], tot);
+    }
+    unstage_set<RW>(a, su, A, lane);
+  }
+  if (have_tag) flush_tag(a, acc, cur_tag, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Triangles, pairwise (both sets from HBM), G lanes per pair
+// ---------------------------------------------------------------------------
+
+template <int G>
+__device__ __forceinline__ uint32_t pair_count(const DevArgs& a, uint32_t s, uint32_t t,
+                                               uint32_t gl) {
+  const uint2 sd = a.vdesc[s], td = a.vdesc[t];
+  uint32_t sl = sd.y & kMaxIndex, tl = td.y & kMaxIndex;
+  if (sl == 0 || tl == 0) return 0;
+  const bool sbs = a.use_bitsets && (sd.y & kHiBit);
+  const bool tbs = a.use_bitsets && (td.y & kHiBit);
+  uint32_t cnt = 0;
+  if (sbs && tbs) {
+    // bitset & bitset: AND the overlapping 32-bit words, popcount
+    const uint4 bs = a.bsdesc[s], bt = a.bsdesc[t];
+    const uint32_t w0 = max(bs.y, bt.y) >> 5;
+    const uint32_t e_s = (bs.y >> 5) + bs.z, e_t = (bt.y >> 5) + bt.z;
+    const uint32_t w1 = min(e_s, e_t);
+    for (uint32_t w = w0 + gl; w < w1; w += G)
+      cnt += __popc(a.bsw[bs.x + (w - (bs.y >> 5))] & a.bsw[bt.x + (w - (bt.y >> 5))]);
+    return cnt;
+  }
+  if (sbs || tbs) {
+    // uint & bitset: probe each uint value in the bitset
+    const uint4 b = a.bsdesc[sbs ? s : t];
+    const uint32_t ub = sbs ? td.x : sd.x, ul = sbs ? tl : sl;
+    for (uint32_t k = gl; k < ul; k += G) {
+      const uint32_t d = a.col[ub + k] - b.y;
+      if (d < b.z * 32u) cnt += (a.bsw[b.x + (d >> 5)] >> (d & 31)) & 1u;
+    }
+    return cnt;
+  }
+  // uint & uint: A shorter, B longer
+  const uint32_t* Ap = a.col + (sl <= tl ? sd.x : td.x);
+  const uint32_t* Bp = a.col + (sl <= tl ? td.x : sd.x);
+  const uint32_t na = min(sl, tl), nb = max(sl, tl);
+  const bool search = a.algo == EH_ALGO_SEARCH ||
+                      (a.algo == EH_ALGO_AUTO && float(nb) > a.gamma * float(na));
+  if (search) {
+    // galloping regime: each value of the shorter list searched in the longer
+    for (uint32_t k = gl; k < na; k += G) {
+      const uint32_t x = Ap[k];
+      const uint32_t p = lower_bound_glb(Bp, nb, x);
+      cnt += (p < nb && Bp[p] == x) ? 1u : 0u;
+    }
+    return cnt;
+  }
+  // partitioned merge: lane gl owns A[a0, a1) and merges it with B from
+  // lower_bound(B, A[a0]); every match is found by exactly one lane
+  const uint32_t chunk = (na + G - 1) / G;
+  const uint32_t a0 = gl * chunk, a1 = min(a0 + chunk, na);
+  if (a0 >= a1) return 0;
+  uint32_t i = a0, j = lower_bound_glb(Bp, nb, Ap[a0]);
+  uint32_t x = Ap[i];
+  uint32_t y = j < nb ? Bp[j] : 0u;
+  while (i < a1 && j < nb) {
+    if (x < y) { if (++i < a1) x = Ap[i]; }
+    else if (x > y) { if (++j < nb) y = Bp[j]; }
+    else {
+      ++cnt;
+      if (++i < a1) x = Ap[i];
+      if (++j < nb) y = Bp[j];
+    }
+  }
+  return cnt;
+}
+
+template <int WPB, int G>
+__global__ __launch_bounds__(WPB * kWave) void k_tri_pairwise(DevArgs a) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t grp = lane / G, gl = lane % G;
+  constexpr uint32_t kGroups = kWave / G;
+  unsigned long long acc = 0;
+  uint32_t cur_tag = 0;
+  bool have_tag = false;
+  for (ItemIter it(a, WPB); it.i < a.n_items; it.next()) {
+    const Item item = a.items[it.i];
+    const uint32_t s = uniform(item.s), lbeg = uniform(item.lbeg), llen = uniform(item.llen);
+    const uint32_t tag = uniform(item.tag);
+    if (have_tag && tag != cur_tag) flush_tag(a, acc, cur_tag, lane);
+    cur_tag = tag;
+    have_tag = true;
+    uint32_t cnt = 0;
+    for (uint32_t q = grp; q < llen; q += kGroups) cnt += pair_count<G>(a, s, a.idx[lbeg + q], gl);
+    acc += cnt;
+    if (a.per_root) {
+      const unsigned long long tot = wave_sum((unsigned long long)cnt);
+      if (lane == 0 && tot) atomicAdd(&a.per_root[a.vert[s]], tot);
+    }
+  }
+  if (have_tag) flush_tag(a, acc, cur_tag, lane);
+}
+
+__global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += uint64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_scatter_roots(const unsigned long long* by_rank, const uint32_t* vert,
+                                unsigned long long* by_id, uint32_t n) {
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+    by_id[vert[r]] = by_rank[r];
+}
+
+constexpr int kTriWPB = 4;
+constexpr int kTriRW = 1024;  // 32768-bit staging range, or 1024-entry list
+constexpr int kTriU = 4;
+constexpr int kK4WPB = 2;
+constexpr int kK4RW = 1024;
+constexpr int kK4U = 2;
+constexpr int kPairWPB = 4;
+
+uint32_t grid_for(Ctx* c, uint64_t n_items, uint32_t wpb, uint32_t waves_per_cu) {
+  uint64_t want = (uint64_t(c->n_cu) * std::max<uint32_t>(waves_per_cu, wpb) + wpb - 1) / wpb;
+  const uint64_t need = (n_items + wpb - 1) / wpb;
+  if (want > need) want = need;
+  if (want < 1) want = 1;
+  return uint32_t(std::min<uint64_t>(want, 1u << 20));
+}
+
+}  // namespace
+
+uint32_t k4_staged_max_degree() { return 2048; }
+
+eh_status launch_fill_u64(Ctx* c, hipStream_t s, unsigned long long* p, uint64_t n,
+                          unsigned long long v) {
+  if (n == 0) return EH_OK;
+  const uint32_t blocks = uint32_t(std::min<uint64_t>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks), dim3(256), 0, s, p, n, v);
+  return hip_check(c, hipGetLastError(), "fill kernel launch");
+}
+
+eh_status launch_scatter_roots(Ctx* c, hipStream_t s, const unsigned long long* by_rank,
+                               const uint32_t* vert, unsigned long long* by_id, uint32_t n) {
+  if (n == 0) return EH_OK;
+  const uint32_t blocks = std::min<uint32_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_scatter_roots, dim3(blocks), dim3(256), 0, s, by_rank, vert, by_id, n);
+  return hip_check(c, hipGetLastError(), "scatter kernel launch");
+}
+
+eh_status launch_triangles(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t kernel,
+                           uint32_t waves_per_cu) {
+  if (la.n_items == 0) return EH_OK;
+  const DevArgs a = to_dev(la);
+  if (kernel == EH_KERNEL_PAIRWISE) {
+    uint32_t g = la.group_lanes;
+    if (g == 0) g = la.dmax >= 256 ? 64 : la.dmax >= 64 ? 16 : 4;
+    const uint32_t grid = grid_for(c, la.n_items, kPairWPB, waves_per_cu);
+    const dim3 blk(kPairWPB * kWave);
+    switch (g) {
+      case 4: hipLaunchKernelGGL((k_tri_pairwise<kPairWPB, 4>), dim3(grid), blk, 0, s, a); break;
+      case 8: hipLaunchKernelGGL((k_tri_pairwise<kPairWPB, 8>), dim3(grid), blk, 0, s, a); break;
+      case 16: hipLaunchKernelGGL((k_tri_pairwise<kPairWPB, 16>), dim3(grid), blk, 0, s, a); break;
+      case 32: hipLaunchKernelGGL((k_tri_pairwise<kPairWPB, 32>), dim3(grid), blk, 0, s, a); break;
+      case 64: hipLaunchKernelGGL((k_tri_pairwise<kPairWPB, 64>), dim3(grid), blk, 0, s, a); break;
+      default:
+        c->err = "group_lanes must be 4, 8, 16, 32 or 64";
+        return EH_EINVAL;
+    }
+    return hip_check(c, hipGetLastError(), "pairwise triangle kernel launch");
+  }
+  const uint32_t grid = grid_for(c, la.n_items, kTriWPB, waves_per_cu);
+  hipLaunchKernelGGL((k_tri_staged<kTriWPB, kTriRW, kTriU>), dim3(grid), dim3(kTriWPB * kWave), 0,
+                     s, a);
+  return hip_check(c, hipGetLastError(), "staged triangle kernel launch");
+}
+
+eh_status launch_4cliques(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t /*kernel*/,
+                          uint32_t waves_per_cu) {
+  if (la.n_items == 0) return EH_OK;
+  const DevArgs a = to_dev(la);
+  const uint32_t grid = grid_for(c, la.n_items, kK4WPB, waves_per_cu);
+  const dim3 blk(kK4WPB * kWave);
+  if (la.dmax <= 512)
+    hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 512, kK4U>), dim3(grid), blk, 0, s, a);
+  else if (la.dmax <= 1024)
+    hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 1024, kK4U>), dim3(grid), blk, 0, s, a);
+  else if (la.dmax <= 2048)
+    hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 2048, kK4U>), dim3(grid), blk, 0, s, a);
+  else {
+    c->err = "4-clique kernel supports out-degrees up to 2048";
+    return EH_EOVERFLOW;
+  }
+  return hip_check(c, hipGetLastError(), "staged 4-clique kernel launch");
+}
+
+}  // namespace eh

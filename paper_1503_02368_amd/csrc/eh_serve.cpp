@@ -1,0 +1,364 @@
+// Serving: rooted triangle / 4-clique count requests against a resident trie.
+//
+// A request asks for the instances whose root (smallest-rank vertex) lies in
+// a given vertex set -- an equality selection on the first attribute of the
+// join, which the trie answers by starting Generic-Join's outer loop only at
+// those vertices (appendix B.1 pushes such selections first).  Its work is
+// the source-staged items of each root.
+//
+// Continuous batching: a progress thread repeatedly (1) admits queued
+// requests in arrival order while the summed device footprint of active
+// requests fits the budget and a slot is free, (2) gathers up to step_items
+// work items from all active requests, oldest first, (3) runs them as one
+// device step (one launch per pattern) that adds into per-slot counters, and
+// (4) retires every request whose items have all completed.  Requests that
+// arrive while a step runs join the next step; their work shares launches with
+// requests admitted earlier.  The step after the one that finishes a request
+// never waits for that request to be polled.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <ctime>
+
+#include "eh_internal.h"
+
+namespace eh {
+namespace {
+
+uint64_t now_ns() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return uint64_t(ts.tv_sec) * 1000000000ull + uint64_t(ts.tv_nsec);
+}
+
+struct Request {
+  uint64_t ticket = 0;
+  int pattern = 0;
+  std::vector<Item> items;  // tag filled at admission
+  uint64_t footprint = 0;
+  uint64_t next_item = 0;   // next item to dispatch
+  uint64_t done_items = 0;  // items whose step completed
+  uint32_t slot = 0;
+  bool zeroed = false;
+  uint64_t count = 0;
+  eh_req_stats stats{};
+  bool finished = false;
+};
+
+}  // namespace
+
+struct Server {
+  Ctx* c = nullptr;
+  Trie* t = nullptr;
+  eh_server_opts o{};
+  hipStream_t stream = nullptr;
+  DevBuf items_d;          // step_items Items
+  DevBuf acc_d;            // max_active uint64
+  Item* items_h = nullptr; // pinned staging
+  uint64_t* acc_h = nullptr;
+  std::mutex mu;
+  std::condition_variable cv_work;   // progress thread waits for work
+  std::condition_variable cv_done;   // eh_wait waits for completions
+  std::deque<std::shared_ptr<Request>> queue;
+  std::vector<std::shared_ptr<Request>> active;  // by admission order
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> by_ticket;
+  std::vector<uint32_t> free_slots;
+  uint64_t footprint = 0;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::string fatal;  // first device error; every later request fails
+  std::thread th;
+
+  void run();
+  bool step();
+};
+
+namespace {
+
+eh_status server_launch(Server* s, const std::vector<Item>& v, uint64_t off, int pattern) {
+  if (v.empty()) return EH_OK;
+  Ctx* c = s->c;
+  Trie& t = *s->t;
+  LaunchArgs a;
+  a.vdesc = static_cast<const uint2*>(t.vdesc.p);
+  a.col = static_cast<const uint32_t*>(t.col.p);
+  a.bsdesc = static_cast<const uint4*>(t.bsdesc.p);
+  a.bsw = static_cast<const uint32_t*>(t.bsw.p);
+  a.vert = static_cast<const uint32_t*>(t.vert.p);
+  a.idx = static_cast<const uint32_t*>(t.col.p);
+  a.items = static_cast<const Item*>(s->items_d.p) + off;
+  a.n_items = v.size();
+  a.acc = static_cast<unsigned long long*>(s->acc_d.p);
+  a.tag_base = 0;
+  a.use_bitsets = c->tune.use_bitsets && t.host.n_bs > 0;
+  a.dynamic = 0;  // items of many requests: static interleave needs no cursor
+  a.algo = c->tune.algo;
+  a.gamma = c->tune.gamma;
+  a.group_lanes = c->tune.group_lanes;
+  a.dmax = t.host.dmax;
+  a.stage_words = c->tune.stage_words;
+  if (pattern == EH_4CLIQUE) return launch_4cliques(c, s->stream, a, c->tune.kernel, c->tune.waves_per_cu);
+  return launch_triangles(c, s->stream, a, c->tune.kernel, c->tune.waves_per_cu);
+}
+
+}  // namespace
+
+// One device step.  Returns false when there is nothing to do.
+bool Server::step() {
+  std::vector<std::shared_ptr<Request>> batch_reqs;
+  std::vector<uint32_t> to_zero;
+  std::vector<Item> tri, k4;
+  std::vector<std::pair<std::shared_ptr<Request>, uint64_t>> dispatched;
+  {
+    std::unique_lock<std::mutex> lk(mu);
+    // admission, arrival order
+    while (!queue.empty() && !free_slots.empty() && !stop) {
+      auto& r = queue.front();
+      if (footprint + r->footprint > o.hbm_budget_bytes && !active.empty()) break;
+      r->slot = free_slots.back();
+      free_slots.pop_back();
+      for (auto& it : r->items) it.tag = r->slot;
+      r->stats.t_admit_ns = now_ns();
+      footprint += r->footprint;
+      active.push_back(r);
+      queue.pop_front();
+    }
+    if (active.empty()) return false;
+    // gather items, oldest request first
+    uint64_t budget = o.step_items;
+    for (auto& r : active) {
+      if (!r->zeroed) {
+        to_zero.push_back(r->slot);
+        r->zeroed = true;
+      }
+      const uint64_t take = std::min<uint64_t>(budget, r->items.size() - r->next_item);
+      auto& dst = r->pattern == EH_4CLIQUE ? k4 : tri;
+      dst.insert(dst.end(), r->items.begin() + r->next_item, r->items.begin() + r->next_item + take);
+      r->next_item += take;
+      budget -= take;
+      dispatched.emplace_back(r, take);
+      if (budget == 0) break;
+    }
+  }
+  // device step: zero new slots, upload items, launch, read counters
+  eh_status st = EH_OK;
+  for (uint32_t slot : to_zero)
+    if (st == EH_OK)
+      st = launch_fill_u64(c, stream, static_cast<unsigned long long*>(acc_d.p) + slot, 1, 0);
+  const uint64_t n_tri = tri.size(), n_k4 = k4.size();
+  if (st == EH_OK && n_tri + n_k4) {
+    std::memcpy(items_h, tri.data(), n_tri * sizeof(Item));
+    std::memcpy(items_h + n_tri, k4.data(), n_k4 * sizeof(Item));
+    st = hip_check(c, hipMemcpyAsync(items_d.p, items_h, (n_tri + n_k4) * sizeof(Item),
+                                     hipMemcpyHostToDevice, stream), "upload step items");
+  }
+  if (st == EH_OK) st = server_launch(this, tri, 0, EH_TRIANGLE);
+  if (st == EH_OK) st = server_launch(this, k4, n_tri, EH_4CLIQUE);
+  if (st == EH_OK)
+    st = hip_check(c, hipMemcpyAsync(acc_h, acc_d.p, o.max_active * sizeof(uint64_t),
+                                     hipMemcpyDeviceToHost, stream), "read counters");
+  if (st == EH_OK) st = hip_check(c, hipStreamSynchronize(stream), "step sync");
+  {
+    std::unique_lock<std::mutex> lk(mu);
+    if (st != EH_OK && fatal.empty()) fatal = c->err.empty() ? "device step failed" : c->err;
+    for (auto& d : dispatched) d.first->done_items += d.second;
+    const uint64_t t_done = now_ns();
+    std::vector<std::shared_ptr<Request>> keep;
+    for (auto& r : active) {
+      if (r->done_items == r->items.size() || !fatal.empty()) {
+        r->count = acc_h[r->slot];
+        r->stats.t_done_ns = t_done;
+        r->finished = true;
+        footprint -= r->footprint;
+        free_slots.push_back(r->slot);
+        std::vector<Item>().swap(r->items);
+      } else {
+        keep.push_back(r);
+      }
+    }
+    active.swap(keep);
+  }
+  cv_done.notify_all();
+  return true;
+}
+
+void Server::run() {
+  (void)hipSetDevice(c->device);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+      if (stop && active.empty()) {
+        // cancel what was never admitted
+        for (auto& r : queue) {
+          r->finished = true;
+          r->count = 0;
+          r->stats.t_done_ns = now_ns();
+          by_ticket.erase(r->ticket);
+        }
+        queue.clear();
+        cv_done.notify_all();
+        return;
+      }
+    }
+    step();
+  }
+}
+
+}  // namespace eh
+
+struct eh_server {
+  eh::Server s;
+};
+
+using namespace eh;
+
+extern "C" {
+
+eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server_opts* opts,
+                           eh_server** out) {
+  if (!ctx || !resident || !out) return EH_EINVAL;
+  *out = nullptr;
+  Ctx* c = &ctx->c;
+  Trie* t = &const_cast<eh_trie*>(resident)->t;
+  if (t->host.n_graphs != 1) {
+    c->err = "a server needs a single-graph trie";
+    return EH_ESTATE;
+  }
+  eh_server* x = new (std::nothrow) eh_server();
+  if (!x) return EH_ENOMEM;
+  Server& s = x->s;
+  s.c = c;
+  s.t = t;
+  if (opts) s.o = *opts;
+  if (!s.o.hbm_budget_bytes) s.o.hbm_budget_bytes = 256ull << 20;
+  if (!s.o.max_active) s.o.max_active = 256;
+  if (!s.o.max_queued) s.o.max_queued = 4096;
+  if (!s.o.step_items) s.o.step_items = 1 << 18;
+  eh_status st = hip_check(c, hipSetDevice(c->device), "hipSetDevice");
+  if (st == EH_OK)
+    st = hip_check(c, hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking), "server stream");
+  if (st == EH_OK) st = dev_alloc(c, s.items_d, sizeof(Item) * s.o.step_items);
+  if (st == EH_OK) st = dev_alloc(c, s.acc_d, sizeof(uint64_t) * s.o.max_active);
+  if (st == EH_OK)
+    st = hip_check(c, hipHostMalloc((void**)&s.items_h, sizeof(Item) * s.o.step_items,
+                                    hipHostMallocDefault), "pinned items");
+  if (st == EH_OK)
+    st = hip_check(c, hipHostMalloc((void**)&s.acc_h, sizeof(uint64_t) * s.o.max_active,
+                                    hipHostMallocDefault), "pinned counters");
+  if (st != EH_OK) {
+    dev_free(c, s.items_d);
+    dev_free(c, s.acc_d);
+    if (s.items_h) (void)hipHostFree(s.items_h);
+    if (s.acc_h) (void)hipHostFree(s.acc_h);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+    delete x;
+    return st;
+  }
+  for (uint32_t i = s.o.max_active; i-- > 0;) s.free_slots.push_back(i);
+  s.th = std::thread([&s] { s.run(); });
+  *out = x;
+  return EH_OK;
+}
+
+eh_status eh_submit(eh_server* srv, int pattern, const uint32_t* roots, uint32_t n_roots,
+                    uint64_t* ticket) {
+  if (!srv || !roots || !ticket || n_roots == 0) return EH_EINVAL;
+  if (pattern != EH_TRIANGLE && pattern != EH_4CLIQUE) return EH_EINVAL;
+  Server& s = srv->s;
+  const HostTrie& h = s.t->host;
+  auto r = std::make_shared<Request>();
+  r->pattern = pattern;
+  r->stats.t_submit_ns = now_ns();
+  std::vector<uint32_t> rk;
+  rk.reserve(n_roots);
+  for (uint32_t i = 0; i < n_roots; ++i) {
+    if (roots[i] >= h.n) return EH_EINVAL;
+    rk.push_back(h.rank[roots[i]]);
+  }
+  std::sort(rk.begin(), rk.end());
+  rk.erase(std::unique(rk.begin(), rk.end()), rk.end());
+  const uint32_t chunk = s.c->tune.chunk_work;
+  const bool ub = s.c->tune.use_bitsets != 0;
+  for (uint32_t u : rk) make_items_source(h, u, 0, chunk, uint32_t(pattern), ub, r->items);
+  r->stats.items = r->items.size();
+  r->footprint = sizeof(Item) * r->items.size() + sizeof(uint64_t);
+  if (r->footprint > s.o.hbm_budget_bytes) return EH_ENOMEM;
+  {
+    std::unique_lock<std::mutex> lk(s.mu);
+    if (s.stop) return EH_ESTATE;
+    if (!s.fatal.empty()) return EH_EHIP;
+    if (s.queue.size() >= s.o.max_queued) return EH_EBUSY;
+    r->ticket = s.next_ticket++;
+    *ticket = r->ticket;
+    s.by_ticket[r->ticket] = r;
+    if (r->items.empty()) {
+      // no instance can be rooted here: done without device work
+      r->finished = true;
+      r->stats.t_admit_ns = r->stats.t_done_ns = now_ns();
+    } else {
+      s.queue.push_back(r);
+    }
+  }
+  s.cv_work.notify_one();
+  s.cv_done.notify_all();
+  return EH_OK;
+}
+
+static eh_status take_result(Server& s, uint64_t ticket, uint64_t* count, eh_req_stats* stats) {
+  auto itr = s.by_ticket.find(ticket);
+  if (itr == s.by_ticket.end()) return EH_ENOTFOUND;
+  auto& r = itr->second;
+  if (!r->finished) return EH_PENDING;
+  if (!s.fatal.empty()) {
+    s.by_ticket.erase(itr);
+    return EH_EHIP;
+  }
+  if (count) *count = r->count;
+  if (stats) *stats = r->stats;
+  s.by_ticket.erase(itr);
+  return EH_OK;
+}
+
+eh_status eh_poll(eh_server* srv, uint64_t ticket, uint64_t* count, eh_req_stats* stats) {
+  if (!srv) return EH_EINVAL;
+  Server& s = srv->s;
+  std::unique_lock<std::mutex> lk(s.mu);
+  return take_result(s, ticket, count, stats);
+}
+
+eh_status eh_wait(eh_server* srv, uint64_t ticket, uint32_t timeout_ms, uint64_t* count,
+                  eh_req_stats* stats) {
+  if (!srv) return EH_EINVAL;
+  Server& s = srv->s;
+  std::unique_lock<std::mutex> lk(s.mu);
+  const auto deadline = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms);
+  for (;;) {
+    const eh_status st = take_result(s, ticket, count, stats);
+    if (st != EH_PENDING) return st;
+    if (s.cv_done.wait_until(lk, deadline) == std::cv_status::timeout) {
+      return take_result(s, ticket, count, stats);
+    }
+  }
+}
+
+eh_status eh_server_destroy(eh_server* srv) {
+  if (!srv) return EH_EINVAL;
+  Server& s = srv->s;
+  {
+    std::unique_lock<std::mutex> lk(s.mu);
+    s.stop = true;
+  }
+  s.cv_work.notify_all();
+  if (s.th.joinable()) s.th.join();
+  (void)hipStreamSynchronize(s.stream);
+  dev_free(s.c, s.items_d);
+  dev_free(s.c, s.acc_d);
+  if (s.items_h) (void)hipHostFree(s.items_h);
+  if (s.acc_h) (void)hipHostFree(s.acc_h);
+  (void)hipStreamDestroy(s.stream);
+  delete srv;
+  return EH_OK;
+}
+
+}  // extern "C"

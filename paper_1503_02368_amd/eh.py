@@ -1,0 +1,414 @@
+"""ctypes binding of the C ABI declared in include/eh.h.
+
+Argument marshalling only: every counting step runs in the HIP library.
+PyTorch supplies device memory (its caching allocator, through the ABI's
+allocator hooks) and the stream work is launched on.  Importing this module
+does not touch the GPU; :func:`load` raises if the library was not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libeh.so")
+
+# status codes and enums (eh.h)
+EH_OK, EH_PENDING = 0, 1
+EH_EINVAL, EH_ENOMEM, EH_EHIP, EH_EBUSY, EH_ENOTFOUND, EH_EOVERFLOW, EH_ESTATE = -1, -2, -3, -4, -5, -6, -7
+TRIANGLE, CLIQUE4 = 3, 4
+LAYOUT_UINT, LAYOUT_HYBRID, LAYOUT_BITSET_ALL = 0, 1, 2
+KERNEL_AUTO, KERNEL_STAGED, KERNEL_PAIRWISE = 0, 1, 2
+STAGE_AUTO, STAGE_SOURCE, STAGE_TARGET = 0, 1, 2
+ALGO_AUTO, ALGO_MERGE, ALGO_SEARCH = 0, 1, 2
+
+# every symbol include/eh.h declares
+SYMBOLS = [
+    "eh_ctx_create", "eh_ctx_destroy", "eh_last_error", "eh_status_str", "eh_abi_version",
+    "eh_ctx_set_tuning", "eh_ctx_get_tuning", "eh_build_trie", "eh_build_batch",
+    "eh_trie_info_get", "eh_trie_free", "eh_count_triangles", "eh_count_4cliques",
+    "eh_count_async", "eh_count_rooted", "eh_count_batch", "eh_count_batch_async",
+    "eh_server_create", "eh_submit", "eh_poll", "eh_wait", "eh_server_destroy",
+    "eh_host_trie_build", "eh_host_trie_info", "eh_host_trie_arrays", "eh_host_trie_free",
+]
+
+
+class EHError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)),
+                ("free", ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)),
+                ("self", ctypes.c_void_p)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_uint32), ("staging", ctypes.c_uint32), ("algo", ctypes.c_uint32),
+                ("gamma", ctypes.c_float), ("chunk_work", ctypes.c_uint32),
+                ("waves_per_cu", ctypes.c_uint32), ("group_lanes", ctypes.c_uint32),
+                ("use_bitsets", ctypes.c_uint32), ("dynamic", ctypes.c_uint32),
+                ("stage_words", ctypes.c_uint32)]
+
+
+class _BuildOpts(ctypes.Structure):
+    _fields_ = [("layout", ctypes.c_uint32), ("tau", ctypes.c_float), ("s_min", ctypes.c_uint32)]
+
+
+class _TrieInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("n_graphs", ctypes.c_uint32), ("m_plus", ctypes.c_uint64),
+                ("n_bitset_sets", ctypes.c_uint64), ("bitset_words", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64), ("b_merge", ctypes.c_uint64),
+                ("max_out_degree", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
+                ("max_queued", ctypes.c_uint32), ("step_items", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class _ReqStats(ctypes.Structure):
+    _fields_ = [("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64), ("items", ctypes.c_uint64)]
+
+
+_lib = None
+_lock = threading.Lock()
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_vp = ctypes.c_void_p
+
+
+def load():
+    """Loads the built library; raises FileNotFoundError if it is missing."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1503_02368_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        S = ctypes.c_int32
+        sig = {
+            "eh_ctx_create": [ctypes.c_int, _vp, ctypes.POINTER(_Allocator), ctypes.POINTER(_vp)],
+            "eh_ctx_destroy": [_vp],
+            "eh_ctx_set_tuning": [_vp, ctypes.POINTER(_Tuning)],
+            "eh_ctx_get_tuning": [_vp, ctypes.POINTER(_Tuning)],
+            "eh_build_trie": [_vp, _u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32,
+                              ctypes.POINTER(_BuildOpts), ctypes.POINTER(_vp)],
+            "eh_build_batch": [_vp, ctypes.c_uint32, _u32p, _u64p, _u32p, _u32p,
+                               ctypes.POINTER(_BuildOpts), ctypes.POINTER(_vp)],
+            "eh_trie_info_get": [_vp, ctypes.POINTER(_TrieInfo)],
+            "eh_trie_free": [_vp],
+            "eh_count_triangles": [_vp, _vp, _u64p, _vp],
+            "eh_count_4cliques": [_vp, _vp, _u64p],
+            "eh_count_async": [_vp, _vp, ctypes.c_int, _vp],
+            "eh_count_rooted": [_vp, _vp, ctypes.c_int, _u32p, ctypes.c_uint32, _u64p],
+            "eh_count_batch": [_vp, _vp, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, _u64p],
+            "eh_count_batch_async": [_vp, _vp, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, _vp],
+            "eh_server_create": [_vp, _vp, ctypes.POINTER(_ServerOpts), ctypes.POINTER(_vp)],
+            "eh_submit": [_vp, ctypes.c_int, _u32p, ctypes.c_uint32, _u64p],
+            "eh_poll": [_vp, ctypes.c_uint64, _u64p, ctypes.POINTER(_ReqStats)],
+            "eh_wait": [_vp, ctypes.c_uint64, ctypes.c_uint32, _u64p, ctypes.POINTER(_ReqStats)],
+            "eh_server_destroy": [_vp],
+            "eh_host_trie_build": [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32,
+                                   ctypes.POINTER(_BuildOpts), ctypes.POINTER(_vp)],
+            "eh_host_trie_info": [_vp, ctypes.POINTER(_TrieInfo)],
+            "eh_host_trie_arrays": [_vp, _u32p, _u32p, _u32p, _u32p, _u32p, _u32p, _u32p],
+            "eh_host_trie_free": [_vp],
+        }
+        for name, args in sig.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = S
+        lib.eh_last_error.argtypes = [_vp]
+        lib.eh_last_error.restype = ctypes.c_char_p
+        lib.eh_status_str.argtypes = [S]
+        lib.eh_status_str.restype = ctypes.c_char_p
+        lib.eh_abi_version.argtypes = []
+        lib.eh_abi_version.restype = S
+        _lib = lib
+        return lib
+
+
+def _p32(a):
+    return a.ctypes.data_as(_u32p)
+
+
+def _p64(a):
+    return a.ctypes.data_as(_u64p)
+
+
+def _u32(a):
+    return np.ascontiguousarray(a, dtype=np.uint32)
+
+
+def _opts(layout, tau, s_min):
+    return _BuildOpts(int(layout), float(tau), int(s_min))
+
+
+def _info_dict(info: _TrieInfo) -> dict:
+    return {k: int(getattr(info, k)) for k, _ in _TrieInfo._fields_ if k != "reserved"}
+
+
+def host_trie(n, src, dst, layout=LAYOUT_HYBRID, tau=32.0, s_min=1) -> dict:
+    """Runs only the host half of the trie build (no GPU) and returns its arrays."""
+    lib = load()
+    src, dst = _u32(src), _u32(dst)
+    h = _vp()
+    o = _opts(layout, tau, s_min)
+    st = lib.eh_host_trie_build(_p32(src), _p32(dst), src.size, int(n), ctypes.byref(o), ctypes.byref(h))
+    if st != EH_OK:
+        raise EHError(st, lib.eh_last_error(None).decode() or lib.eh_status_str(st).decode())
+    try:
+        info = _TrieInfo()
+        lib.eh_host_trie_info(h, ctypes.byref(info))
+        d = _info_dict(info)
+        nn, m, w = d["n"], d["m_plus"], d["bitset_words"]
+        arr = {k: np.zeros(sz, np.uint32) for k, sz in
+               (("rank", nn), ("row", nn + 1), ("col", m), ("bs_off", nn), ("bs_base", nn),
+                ("bs_nw", nn), ("bs_words", w))}
+        lib.eh_host_trie_arrays(h, *(_p32(arr[k]) for k in
+                                     ("rank", "row", "col", "bs_off", "bs_base", "bs_nw", "bs_words")))
+        d.update(arr)
+        return d
+    finally:
+        lib.eh_host_trie_free(h)
+
+
+class Context:
+    """An eh_ctx on one device, launching on torch's current stream by default."""
+
+    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True):
+        import torch
+        self._lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the engine has no CPU path")
+        self.device = device
+        torch.cuda.set_device(device)
+        if stream is None:
+            # a stream of our own (default priority): handle 0 would be read as
+            # "no stream given" by eh_ctx_create
+            stream = torch.cuda.Stream(device)
+        if not stream.cuda_stream:
+            raise ValueError("pass a non-default stream: the ABI reads a null handle as 'none given'")
+        self.stream = stream
+        handle = _vp(stream.cuda_stream)
+        self._alloc = None
+        alloc_p = None
+        if torch_allocator:
+            dev = device
+
+            @ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+            def _a(_self, nbytes, s):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, s or 0)
+                except Exception:
+                    return None
+
+            @ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+            def _f(_self, ptr, _s):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc = _Allocator(_a, _f, None)
+            alloc_p = ctypes.byref(self._alloc)
+        h = _vp()
+        st = self._lib.eh_ctx_create(int(device), handle, alloc_p, ctypes.byref(h))
+        if st != EH_OK:
+            raise EHError(st, "eh_ctx_create: " + self._lib.eh_last_error(None).decode())
+        self._h = h
+        self._tries = []
+
+    def _check(self, st, what):
+        if st != EH_OK:
+            raise EHError(st, f"{what}: {self._lib.eh_last_error(self._h).decode()}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for t in list(self._tries):
+                t.free()
+            self._lib.eh_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- tuning ----------------------------------------------------------
+    def get_tuning(self) -> dict:
+        t = _Tuning()
+        self._check(self._lib.eh_ctx_get_tuning(self._h, ctypes.byref(t)), "get_tuning")
+        return {k: (float(getattr(t, k)) if k == "gamma" else int(getattr(t, k))) for k, _ in _Tuning._fields_}
+
+    def set_tuning(self, **kw) -> dict:
+        cur = self.get_tuning()
+        unknown = set(kw) - set(cur)
+        if unknown:
+            raise KeyError(f"unknown tuning keys {sorted(unknown)}")
+        cur.update(kw)
+        t = _Tuning(**{k: (float(v) if k == "gamma" else int(v)) for k, v in cur.items()})
+        self._check(self._lib.eh_ctx_set_tuning(self._h, ctypes.byref(t)), "set_tuning")
+        return self.get_tuning()
+
+    # -- tries -------------------------------------------------------------
+    def build_trie(self, n, src, dst, layout=LAYOUT_HYBRID, tau=32.0, s_min=1) -> "Trie":
+        src, dst = _u32(src), _u32(dst)
+        if src.shape != dst.shape:
+            raise ValueError("src and dst differ in length")
+        h = _vp()
+        o = _opts(layout, tau, s_min)
+        self._check(self._lib.eh_build_trie(self._h, _p32(src), _p32(dst), src.size, int(n),
+                                            ctypes.byref(o), ctypes.byref(h)), "build_trie")
+        return Trie(self, h)
+
+    def build_edgelist(self, el, **kw) -> "Trie":
+        return self.build_trie(el.n, el.src, el.dst, **kw)
+
+    def build_batch(self, batch, layout=LAYOUT_HYBRID, tau=32.0, s_min=1) -> "Trie":
+        nv = _u32(batch.n_vertices)
+        off = np.ascontiguousarray(batch.edge_off, dtype=np.uint64)
+        src, dst = _u32(batch.src), _u32(batch.dst)
+        h = _vp()
+        o = _opts(layout, tau, s_min)
+        self._check(self._lib.eh_build_batch(self._h, nv.size, _p32(nv), _p64(off), _p32(src), _p32(dst),
+                                             ctypes.byref(o), ctypes.byref(h)), "build_batch")
+        return Trie(self, h)
+
+    # -- counting ----------------------------------------------------------
+    def count_triangles(self, trie, per_root: bool = False):
+        out = ctypes.c_uint64(0)
+        roots = None
+        if per_root:
+            import torch
+            roots = torch.empty(trie.info["n"], dtype=torch.int64, device=f"cuda:{self.device}")
+        self._check(self._lib.eh_count_triangles(self._h, trie._h, ctypes.byref(out),
+                                                 _vp(roots.data_ptr()) if roots is not None else None),
+                    "count_triangles")
+        if per_root:
+            return int(out.value), roots.cpu().numpy().view(np.uint64)
+        return int(out.value)
+
+    def count_4cliques(self, trie) -> int:
+        out = ctypes.c_uint64(0)
+        self._check(self._lib.eh_count_4cliques(self._h, trie._h, ctypes.byref(out)), "count_4cliques")
+        return int(out.value)
+
+    def count(self, trie, pattern: int) -> int:
+        return self.count_triangles(trie) if pattern == TRIANGLE else self.count_4cliques(trie)
+
+    def count_async(self, trie, pattern: int, d_total) -> None:
+        """Enqueues a count whose result lands in d_total (a 1-element int64 CUDA tensor)."""
+        self._check(self._lib.eh_count_async(self._h, trie._h, int(pattern), _vp(d_total.data_ptr())),
+                    "count_async")
+
+    def count_rooted(self, trie, pattern: int, roots) -> int:
+        r = _u32(roots)
+        out = ctypes.c_uint64(0)
+        self._check(self._lib.eh_count_rooted(self._h, trie._h, int(pattern), _p32(r), r.size,
+                                              ctypes.byref(out)), "count_rooted")
+        return int(out.value)
+
+    def count_batch(self, trie, pattern: int, first: int = 0, count: int | None = None) -> np.ndarray:
+        if count is None:
+            count = trie.info["n_graphs"] - first
+        out = np.zeros(count, np.uint64)
+        self._check(self._lib.eh_count_batch(self._h, trie._h, int(pattern), int(first), int(count),
+                                             _p64(out)), "count_batch")
+        return out
+
+    def count_batch_async(self, trie, pattern: int, first: int, count: int, d_out) -> None:
+        self._check(self._lib.eh_count_batch_async(self._h, trie._h, int(pattern), int(first), int(count),
+                                                   _vp(d_out.data_ptr())), "count_batch_async")
+
+    def server(self, trie, hbm_budget_bytes=0, max_active=0, max_queued=0, step_items=0) -> "Server":
+        return Server(self, trie, hbm_budget_bytes, max_active, max_queued, step_items)
+
+
+class Trie:
+    def __init__(self, ctx: Context, h):
+        self.ctx = ctx
+        self._h = h
+        ctx._tries.append(self)
+        info = _TrieInfo()
+        ctx._check(ctx._lib.eh_trie_info_get(h, ctypes.byref(info)), "trie_info")
+        self.info = _info_dict(info)
+
+    def refresh_info(self) -> dict:
+        info = _TrieInfo()
+        self.ctx._check(self.ctx._lib.eh_trie_info_get(self._h, ctypes.byref(info)), "trie_info")
+        self.info = _info_dict(info)
+        return self.info
+
+    def free(self):
+        if self._h:
+            self.ctx._lib.eh_trie_free(self._h)
+            self._h = None
+            if self in self.ctx._tries:
+                self.ctx._tries.remove(self)
+
+
+@dataclass
+class ReqResult:
+    count: int
+    t_submit_ns: int
+    t_admit_ns: int
+    t_done_ns: int
+    items: int
+
+
+class Server:
+    def __init__(self, ctx: Context, trie: Trie, budget, max_active, max_queued, step_items):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        o = _ServerOpts(int(budget), int(max_active), int(max_queued), int(step_items), 0)
+        h = _vp()
+        ctx._check(self._lib.eh_server_create(ctx._h, trie._h, ctypes.byref(o), ctypes.byref(h)),
+                   "server_create")
+        self._h = h
+
+    def submit(self, pattern: int, roots) -> int:
+        r = _u32(roots)
+        t = ctypes.c_uint64(0)
+        st = self._lib.eh_submit(self._h, int(pattern), _p32(r), r.size, ctypes.byref(t))
+        if st != EH_OK:
+            raise EHError(st, "submit: " + self._lib.eh_status_str(st).decode())
+        return int(t.value)
+
+    def _result(self, st, c, s):
+        if st == EH_PENDING:
+            return None
+        if st != EH_OK:
+            raise EHError(st, "poll: " + self._lib.eh_status_str(st).decode())
+        return ReqResult(int(c.value), int(s.t_submit_ns), int(s.t_admit_ns), int(s.t_done_ns), int(s.items))
+
+    def poll(self, ticket: int):
+        c = ctypes.c_uint64(0)
+        s = _ReqStats()
+        return self._result(self._lib.eh_poll(self._h, int(ticket), ctypes.byref(c), ctypes.byref(s)), c, s)
+
+    def wait(self, ticket: int, timeout_ms: int = 60000):
+        c = ctypes.c_uint64(0)
+        s = _ReqStats()
+        return self._result(self._lib.eh_wait(self._h, int(ticket), int(timeout_ms), ctypes.byref(c),
+                                              ctypes.byref(s)), c, s)
+
+    def close(self):
+        if self._h:
+            self._lib.eh_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

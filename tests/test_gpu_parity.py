@@ -1,0 +1,296 @@
+"""GPU parity: every count from the HIP library equals the oracle's, bit for bit.
+
+Counts are exact integers, so the bar is equality.  Layout (uint, hybrid,
+all-bitset), kernel (staged, pairwise), staging side, intersection algorithm
+and schedule are performance choices only (paper section 4); each is forced
+here and must give the same count.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_02368_amd import inputs
+from golden_io import all_fixtures, load
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(eh):
+    c = eh.Context(0)
+    yield c
+    c.close()
+
+
+def zoo():
+    g = [inputs.complete(n) for n in (3, 4, 5, 17, 70)]
+    g += [inputs.cycle(3), inputs.cycle(4), inputs.cycle(50), inputs.grid(6, 7), inputs.star(30),
+          inputs.wheel(4), inputs.wheel(33), inputs.friendship(9), inputs.complete_bipartite(5, 8),
+          inputs.random_tree(200, 1)]
+    for p in all_fixtures():
+        n, s, d, _ = load(p)
+        g.append(inputs.EdgeList(n, s, d, p.rsplit("/", 1)[-1]))
+    g += [inputs.gnp(40, p, s) for p in (0.2, 0.6, 0.95) for s in (1, 2)]
+    g += [inputs.erdos_renyi_gnm(4096, 32768, seed=1)]
+    g += [inputs.rmat(s, 16, seed=100 + s) for s in (8, 10, 12)]
+    g += [inputs.messy(inputs.rmat(9, 16, seed=7), 3), inputs.relabel(inputs.rmat(10, 8, seed=8), 4)]
+    g += [inputs.chung_lu(5000, 32, 2.1, seed=2, graph=1)]
+    g += [inputs.disjoint_union(inputs.complete(30), inputs.rmat(9, 16, seed=9), inputs.wheel(12))]
+    return g
+
+
+ZOO = zoo()
+_ORACLE = {}
+
+
+def truth(el):
+    key = el.name
+    if key not in _ORACLE:
+        g = oracle.Graph.from_edgelist(el)
+        t = g.triangles(rooted=True)
+        k = g.cliques4()
+        _ORACLE[key] = (t["count"], k["count"], t["root"])
+    return _ORACLE[key]
+
+
+TUNINGS = {
+    "staged_target": dict(kernel=1, staging=2, use_bitsets=1, dynamic=0, stage_words=0),
+    "staged_source": dict(kernel=1, staging=1, use_bitsets=1, dynamic=1, stage_words=0),
+    "staged_nobits": dict(kernel=1, staging=2, use_bitsets=0, dynamic=0, stage_words=0),
+    "staged_list": dict(kernel=1, staging=2, use_bitsets=1, dynamic=0, stage_words=8),
+    "staged_global": dict(kernel=1, staging=1, use_bitsets=1, dynamic=1, stage_words=1),
+    "pair_auto": dict(kernel=2, algo=0, use_bitsets=1, group_lanes=0, dynamic=0),
+    "pair_merge4": dict(kernel=2, algo=1, use_bitsets=0, group_lanes=4, dynamic=1),
+    "pair_search16": dict(kernel=2, algo=2, use_bitsets=0, group_lanes=16, dynamic=0),
+    "pair_merge64": dict(kernel=2, algo=1, use_bitsets=1, group_lanes=64, dynamic=0),
+}
+DEFAULT = dict(kernel=1, staging=2, algo=0, gamma=32.0, chunk_work=4096, waves_per_cu=32,
+               group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0)
+
+
+def tune(ctx, **kw):
+    t = dict(DEFAULT)
+    t.update(kw)
+    ctx.set_tuning(**t)
+
+
+LAYOUTS = [("hybrid32", 1, 32.0), ("uint", 0, 32.0), ("bitset_all", 2, 32.0), ("hybrid256", 1, 256.0),
+           ("hybrid2", 1, 2.0)]
+
+
+@pytest.mark.parametrize("lay", LAYOUTS, ids=lambda x: x[0])
+@pytest.mark.parametrize("tname", list(TUNINGS))
+def test_triangles_zoo(ctx, eh, tname, lay):
+    tune(ctx, **TUNINGS[tname])
+    for el in ZOO:
+        T, _, _ = truth(el)
+        trie = ctx.build_edgelist(el, layout=lay[1], tau=lay[2])
+        try:
+            got = ctx.count_triangles(trie)
+        finally:
+            trie.free()
+        assert got == T, (el.name, tname, lay[0])
+
+
+@pytest.mark.parametrize("lay", LAYOUTS[:3], ids=lambda x: x[0])
+@pytest.mark.parametrize("tname", ["staged_source", "staged_nobits", "staged_list", "staged_global"])
+def test_4cliques_zoo(ctx, eh, tname, lay):
+    tune(ctx, **TUNINGS[tname])
+    for el in ZOO:
+        _, K, _ = truth(el)
+        trie = ctx.build_edgelist(el, layout=lay[1], tau=lay[2])
+        try:
+            got = ctx.count_4cliques(trie)
+        finally:
+            trie.free()
+        assert got == K, (el.name, tname, lay[0])
+
+
+@pytest.mark.parametrize("tname", ["staged_source", "pair_auto", "staged_global"])
+def test_per_root(ctx, eh, tname):
+    tune(ctx, **TUNINGS[tname])
+    for el in ZOO[-6:]:
+        T, _, root = truth(el)
+        trie = ctx.build_edgelist(el)
+        try:
+            tot, per = ctx.count_triangles(trie, per_root=True)
+        finally:
+            trie.free()
+        assert tot == T
+        np.testing.assert_array_equal(per, root)
+
+
+@pytest.mark.parametrize("chunk", [64, 700, 100000])
+def test_chunking_and_grid(ctx, eh, chunk):
+    el = inputs.rmat(13, 16, seed=31)
+    T, K, _ = truth(el)
+    for wpc in (4, 32):
+        for staging in (1, 2):
+            tune(ctx, chunk_work=chunk, waves_per_cu=wpc, staging=staging)
+            trie = ctx.build_edgelist(el)
+            try:
+                assert ctx.count_triangles(trie) == T
+                assert ctx.count_4cliques(trie) == K
+            finally:
+                trie.free()
+
+
+def test_async_and_repeat(ctx, eh):
+    import torch
+    tune(ctx)
+    el = inputs.rmat(14, 16, seed=14)
+    T, K, _ = truth(el)
+    trie = ctx.build_edgelist(el)
+    try:
+        out = torch.zeros(4, dtype=torch.int64, device="cuda")
+        ctx.stream.wait_stream(torch.cuda.current_stream())
+        for i in range(3):
+            ctx.count_async(trie, eh.TRIANGLE, out[i:i + 1])
+        ctx.count_async(trie, eh.CLIQUE4, out[3:4])
+        ctx.stream.synchronize()
+        v = out.cpu().numpy().view(np.uint64)
+        assert list(v) == [T, T, T, K]
+    finally:
+        trie.free()
+
+
+def test_rooted(ctx, eh):
+    tune(ctx)
+    el = inputs.rmat(12, 16, seed=12)
+    g = oracle.Graph.from_edgelist(el)
+    rt = g.triangles(rooted=True)["root"]
+    rk = g.cliques4(rooted=True)["root"]
+    trie = ctx.build_edgelist(el)
+    try:
+        key = inputs.stream_key(3, 3)
+        for i, size in enumerate((1, 7, 100, 1000, el.n)):
+            roots = (inputs.rand_u64(key, 10000 * i, size) % np.uint64(el.n)).astype(np.uint32)
+            assert ctx.count_rooted(trie, eh.TRIANGLE, roots) == oracle.rooted_count(rt, roots)
+            assert ctx.count_rooted(trie, eh.CLIQUE4, roots) == oracle.rooted_count(rk, roots)
+        allv = np.arange(el.n, dtype=np.uint32)
+        assert ctx.count_rooted(trie, eh.TRIANGLE, allv) == int(rt.sum())
+        with pytest.raises(eh.EHError):
+            ctx.count_rooted(trie, eh.TRIANGLE, np.array([el.n], np.uint32))
+        with pytest.raises(eh.EHError):
+            ctx.count_rooted(trie, 5, np.array([0], np.uint32))
+    finally:
+        trie.free()
+
+
+def small_batch(num=120, seed=4):
+    return inputs.batch_chung_lu(num, seed=seed, n_hi=2048)
+
+
+@pytest.mark.parametrize("tname", ["staged_target", "staged_source", "pair_auto"])
+def test_batch(ctx, eh, tname):
+    tune(ctx, **TUNINGS[tname])
+    b = small_batch()
+    want_t = np.array([oracle.Graph.from_edgelist(b.graph(i)).triangles()["count"]
+                       for i in range(b.n_graphs)], np.uint64)
+    want_k = np.array([oracle.Graph.from_edgelist(b.graph(i)).cliques4()["count"]
+                       for i in range(b.n_graphs)], np.uint64)
+    trie = ctx.build_batch(b)
+    try:
+        assert trie.info["n_graphs"] == b.n_graphs
+        np.testing.assert_array_equal(ctx.count_batch(trie, eh.TRIANGLE), want_t)
+        np.testing.assert_array_equal(ctx.count_batch(trie, eh.CLIQUE4), want_k)
+        # one launch per instance gives the same vector
+        per = np.array([ctx.count_batch(trie, eh.TRIANGLE, i, 1)[0] for i in range(b.n_graphs)],
+                       np.uint64)
+        np.testing.assert_array_equal(per, want_t)
+        np.testing.assert_array_equal(ctx.count_batch(trie, eh.TRIANGLE, 17, 40), want_t[17:57])
+        with pytest.raises(eh.EHError):
+            ctx.count_batch(trie, eh.TRIANGLE, b.n_graphs - 1, 2)
+    finally:
+        trie.free()
+
+
+def test_batch_order_invariant(ctx, eh):
+    tune(ctx)
+    b = small_batch(60, seed=9)
+    order = np.argsort(inputs.rand_u64(inputs.stream_key(1, 2), 0, b.n_graphs))
+    srcs, dsts, off = [], [], [0]
+    for i in order:
+        g = b.graph(int(i))
+        srcs.append(g.src)
+        dsts.append(g.dst)
+        off.append(off[-1] + g.m_raw)
+    b2 = inputs.BatchEdges(b.n_vertices[order].copy(), np.array(off, np.uint64),
+                           np.concatenate(srcs), np.concatenate(dsts), "perm")
+    t1 = ctx.build_batch(b)
+    t2 = ctx.build_batch(b2)
+    try:
+        a = ctx.count_batch(t1, eh.TRIANGLE)
+        c = ctx.count_batch(t2, eh.TRIANGLE)
+        np.testing.assert_array_equal(a[order], c)
+    finally:
+        t1.free()
+        t2.free()
+
+
+def test_server_alone_equals_mix(ctx, eh):
+    tune(ctx)
+    el = inputs.rmat(13, 16, seed=13)
+    g = oracle.Graph.from_edgelist(el)
+    roots_t = g.triangles(rooted=True)["root"]
+    roots_k = g.cliques4(rooted=True)["root"]
+    trie = ctx.build_edgelist(el)
+    reqs = inputs.request_stream(el.n, rate_qps=1000, duration_s=0.06, seed=5, log2_lo=2, log2_hi=12)
+    assert len(reqs) > 20
+    want = [oracle.rooted_count(roots_t if r.pattern == 3 else roots_k, r.roots) for r in reqs]
+    srv = ctx.server(trie, step_items=512)
+    try:
+        alone = []
+        for r in reqs:
+            t = srv.submit(r.pattern, r.roots)
+            alone.append(srv.wait(t).count)
+        tickets = [srv.submit(r.pattern, r.roots) for r in reqs]
+        mix = [srv.wait(t).count for t in tickets]
+        assert alone == want
+        assert mix == want
+        with pytest.raises(eh.EHError) as e:
+            srv.poll(tickets[0])
+        assert e.value.status == eh.EH_ENOTFOUND
+    finally:
+        srv.close()
+    # back-pressure: a budget that holds one request at a time
+    srv = ctx.server(trie, hbm_budget_bytes=1 << 16, max_active=2, step_items=64)
+    try:
+        small = [r for r in reqs if r.roots.size < 500][:10]
+        tickets = [srv.submit(r.pattern, r.roots) for r in small]
+        got = [srv.wait(t).count for t in tickets]
+        assert got == [oracle.rooted_count(roots_t if r.pattern == 3 else roots_k, r.roots) for r in small]
+        with pytest.raises(eh.EHError) as e:
+            srv.submit(3, np.arange(el.n, dtype=np.uint32))
+        assert e.value.status == eh.EH_ENOMEM
+        with pytest.raises(eh.EHError):
+            srv.submit(3, np.array([el.n + 5], np.uint32))
+    finally:
+        srv.close()
+    trie.free()
+
+
+def test_full_size_rmat20_triangles(ctx, eh):
+    """The measured workload: R-MAT scale 20, edge factor 16, hybrid layout."""
+    tune(ctx)
+    el = inputs.rmat(20, 16, seed=20)
+    say("rmat20 generated")
+    g = oracle.Graph.from_edgelist(el)
+    T = g.triangles()["count"]
+    say("oracle T", T)
+    trie = ctx.build_edgelist(el)
+    try:
+        for tname in ("staged_target", "staged_source", "pair_auto"):
+            tune(ctx, **TUNINGS[tname])
+            got = ctx.count_triangles(trie)
+            say(tname, got)
+            assert got == T, tname
+    finally:
+        trie.free()
