@@ -162,6 +162,10 @@ eh_status eh_count_4cliques(eh_ctx* ctx, const eh_trie* trie, uint64_t* total);
 /* Enqueue-only forms: the total is written to d_total (one uint64, device)
  * when the stream reaches it.  pattern: EH_TRIANGLE or EH_4CLIQUE. */
 eh_status eh_count_async(eh_ctx* ctx, const eh_trie* trie, int pattern, uint64_t* d_total);
+/* As eh_count_async, but adds the count to *d_total instead of overwriting
+ * it, so that with the default static schedule one call is exactly one
+ * kernel launch: k calls on a zeroed d_total leave k times the count. */
+eh_status eh_count_add_async(eh_ctx* ctx, const eh_trie* trie, int pattern, uint64_t* d_total);
 
 /* Instances whose root is in the set {roots[i]} (original ids; duplicates are
  * ignored): a selection on the first attribute of the join (appendix B.1). */

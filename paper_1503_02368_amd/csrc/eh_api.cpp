@@ -174,7 +174,7 @@ uint32_t tri_staging(const Ctx* c, bool per_root) {
 }
 
 eh_status count_single(Ctx* c, Trie& t, int pattern, unsigned long long* d_total,
-                       unsigned long long* d_per_root) {
+                       unsigned long long* d_per_root, bool accumulate = false) {
   if (t.host.n_graphs != 1) {
     c->err = "single-graph count called on a batch trie";
     return EH_ESTATE;
@@ -184,7 +184,7 @@ eh_status count_single(Ctx* c, Trie& t, int pattern, unsigned long long* d_total
                                                   : EH_STAGE_SOURCE;
   eh_status st = get_plan(c, &t, pattern, staging, &p);
   if (st != EH_OK) return st;
-  if ((st = launch_fill_u64(c, c->stream, d_total, 1, 0)) != EH_OK) return st;
+  if (!accumulate && (st = launch_fill_u64(c, c->stream, d_total, 1, 0)) != EH_OK) return st;
   if (d_per_root && (st = launch_fill_u64(c, c->stream, d_per_root, t.host.n, 0)) != EH_OK)
     return st;
   return enqueue_count(c, t, p, 0, p->n_items, d_total, 0, d_per_root);
@@ -454,6 +454,17 @@ eh_status eh_count_async(eh_ctx* ctx, const eh_trie* trie, int pattern, uint64_t
   }
   Trie& t = const_cast<eh_trie*>(trie)->t;
   return count_single(&ctx->c, t, pattern, reinterpret_cast<unsigned long long*>(d_total), nullptr);
+}
+
+eh_status eh_count_add_async(eh_ctx* ctx, const eh_trie* trie, int pattern, uint64_t* d_total) {
+  if (!ctx || !trie || !d_total) return EH_EINVAL;
+  if (pattern != EH_TRIANGLE && pattern != EH_4CLIQUE) {
+    ctx->c.err = "pattern must be EH_TRIANGLE or EH_4CLIQUE";
+    return EH_EINVAL;
+  }
+  Trie& t = const_cast<eh_trie*>(trie)->t;
+  return count_single(&ctx->c, t, pattern, reinterpret_cast<unsigned long long*>(d_total), nullptr,
+                      true);
 }
 
 eh_status eh_count_rooted(eh_ctx* ctx, const eh_trie* trie, int pattern, const uint32_t* roots,

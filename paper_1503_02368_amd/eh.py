@@ -31,7 +31,7 @@ SYMBOLS = [
     "eh_ctx_create", "eh_ctx_destroy", "eh_last_error", "eh_status_str", "eh_abi_version",
     "eh_ctx_set_tuning", "eh_ctx_get_tuning", "eh_build_trie", "eh_build_batch",
     "eh_trie_info_get", "eh_trie_free", "eh_count_triangles", "eh_count_4cliques",
-    "eh_count_async", "eh_count_rooted", "eh_count_batch", "eh_count_batch_async",
+    "eh_count_async", "eh_count_add_async", "eh_count_rooted", "eh_count_batch", "eh_count_batch_async",
     "eh_server_create", "eh_submit", "eh_poll", "eh_wait", "eh_server_destroy",
     "eh_host_trie_build", "eh_host_trie_info", "eh_host_trie_arrays", "eh_host_trie_free",
 ]
@@ -111,6 +111,7 @@ def load():
             "eh_count_triangles": [_vp, _vp, _u64p, _vp],
             "eh_count_4cliques": [_vp, _vp, _u64p],
             "eh_count_async": [_vp, _vp, ctypes.c_int, _vp],
+            "eh_count_add_async": [_vp, _vp, ctypes.c_int, _vp],
             "eh_count_rooted": [_vp, _vp, ctypes.c_int, _u32p, ctypes.c_uint32, _u64p],
             "eh_count_batch": [_vp, _vp, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, _u64p],
             "eh_count_batch_async": [_vp, _vp, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, _vp],
@@ -310,6 +311,11 @@ class Context:
         """Enqueues a count whose result lands in d_total (a 1-element int64 CUDA tensor)."""
         self._check(self._lib.eh_count_async(self._h, trie._h, int(pattern), _vp(d_total.data_ptr())),
                     "count_async")
+
+    def count_add_async(self, trie, pattern: int, d_total) -> None:
+        """Enqueues one counting launch that adds its count into d_total."""
+        self._check(self._lib.eh_count_add_async(self._h, trie._h, int(pattern), _vp(d_total.data_ptr())),
+                    "count_add_async")
 
     def count_rooted(self, trie, pattern: int, roots) -> int:
         r = _u32(roots)
