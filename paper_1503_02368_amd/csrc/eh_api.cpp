@@ -91,7 +91,7 @@ void free_trie_device(Trie& t) {
   dev_free(c, t.bsdesc);
   dev_free(c, t.bsw);
   dev_free(c, t.vert);
-  dev_free(c, t.tcol_d);
+  dev_free(c, t.tin_d);
   t.device_bytes = 0;
 }
 
@@ -146,8 +146,8 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
   LaunchArgs a = base_args(c, t);
   a.items = static_cast<const Item*>(p->items.p) + i0;
   a.n_items = i1 - i0;
-  a.idx = p->staging == EH_STAGE_TARGET ? static_cast<const uint32_t*>(t.tcol_d.p)
-                                        : static_cast<const uint32_t*>(t.col.p);
+  a.idx = static_cast<const uint32_t*>(t.col.p);
+  if (p->staging == EH_STAGE_TARGET) a.tin = static_cast<const uint2*>(t.tin_d.p);
   a.acc = acc;
   a.tag_base = tag_base;
   a.per_root = per_root;

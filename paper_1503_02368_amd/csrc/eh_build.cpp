@@ -320,6 +320,17 @@ inline uint32_t stream_len(const HostTrie& h, uint32_t v, bool use_bitsets) {
   return d;
 }
 
+// elements streamed for the part of N+(u) above v = col[e] (target staging)
+inline uint32_t suffix_len(const HostTrie& h, uint32_t u, uint32_t e, bool use_bitsets) {
+  const uint32_t len = h.row[u + 1] - e - 1;
+  if (use_bitsets && len && h.bs_off[u] != kNoBitset) {
+    const uint32_t w0 = (h.col[e] + 1 - h.bs_base[u]) >> 5;
+    const uint32_t nw = w0 < h.bs_nw[u] ? h.bs_nw[u] - w0 : 0;
+    if (nw < len) return nw;
+  }
+  return len;
+}
+
 // Split the streamed list idx[lb .. lb+len) of staged vertex s into items of
 // about `chunk` streamed elements each.
 template <class CostFn>
@@ -383,21 +394,25 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
   const bool ub = tu.use_bitsets != 0;
   if (staging == EH_STAGE_TARGET) {
     if (!t->has_transpose) {
-      // in-neighbour lists, ascending
+      // in-edges of each v, ascending in u: {u, position of v in N+(u)}
       t->trow.assign(size_t(h.n) + 1, 0);
       for (uint64_t e = 0; e < h.m; ++e) t->trow[h.col[e] + 1]++;
       for (uint32_t v = 0; v < h.n; ++v) t->trow[v + 1] += t->trow[v];
-      t->tcol.assign(h.m, 0);
+      t->tin.assign(2 * h.m, 0);
       std::vector<uint32_t> fill(t->trow.begin(), t->trow.end() - 1);
       for (uint32_t u = 0; u < h.n; ++u)
-        for (uint32_t e = h.row[u]; e < h.row[u + 1]; ++e) t->tcol[fill[h.col[e]]++] = u;
-      eh_status st = dev_alloc(c, t->tcol_d, sizeof(uint32_t) * std::max<uint64_t>(h.m, 1));
+        for (uint32_t e = h.row[u]; e < h.row[u + 1]; ++e) {
+          const uint32_t k = fill[h.col[e]]++;
+          t->tin[2 * k] = u;
+          t->tin[2 * k + 1] = e;
+        }
+      eh_status st = dev_alloc(c, t->tin_d, sizeof(uint32_t) * 2 * std::max<uint64_t>(h.m, 1));
       if (st != EH_OK) return st;
       if (h.m)
-        if ((st = hip_check(c, hipMemcpy(t->tcol_d.p, t->tcol.data(), sizeof(uint32_t) * h.m,
-                                         hipMemcpyHostToDevice), "upload in-neighbours")) != EH_OK)
+        if ((st = hip_check(c, hipMemcpy(t->tin_d.p, t->tin.data(), sizeof(uint32_t) * 2 * h.m,
+                                         hipMemcpyHostToDevice), "upload in-edges")) != EH_OK)
           return st;
-      t->device_bytes += t->tcol_d.bytes;
+      t->device_bytes += t->tin_d.bytes;
       t->has_transpose = true;
     }
   }
@@ -411,7 +426,9 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
         const uint32_t lb = t->trow[v], len = t->trow[v + 1] - t->trow[v];
         if (dv == 0 || len == 0) continue;
         split_items(v, lb, len, tag, chunk, dv,
-                    [&](uint32_t k) { return uint64_t(stream_len(h, t->tcol[k], ub)) + 2; },
+                    [&](uint32_t k) {
+                      return uint64_t(suffix_len(h, t->tin[2 * k], t->tin[2 * k + 1], ub)) + 2;
+                    },
                     items);
       }
     } else {

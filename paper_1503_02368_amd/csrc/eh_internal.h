@@ -106,14 +106,15 @@ struct Trie {
   Ctx* ctx = nullptr;
   HostTrie host;
   bool has_transpose = false;
-  std::vector<uint32_t> trow, tcol;  // in-neighbours, host copy
+  std::vector<uint32_t> trow;        // [n+1] in-edge offsets
+  std::vector<uint32_t> tin;         // [2m] in-edges {u, position of u->v in col}, by v then u
   // device arrays
   DevBuf vdesc;   // uint2 [n]: {row begin, out-degree | kHiBit if bitset}
   DevBuf col;     // uint32 [m]
   DevBuf bsdesc;  // uint4 [n]: {word offset, base, words, 0}
   DevBuf bsw;     // uint32 bitset words
   DevBuf vert;    // uint32 [n]: rank -> id
-  DevBuf tcol_d;  // uint32 [m]: in-neighbour lists (target staging)
+  DevBuf tin_d;   // uint2 [m]: in-edges (target staging)
   std::vector<std::unique_ptr<Plan>> plans;
   uint64_t device_bytes = 0;
 };
@@ -151,7 +152,8 @@ void make_items_source(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chu
 struct LaunchArgs {
   const Item* items = nullptr;
   uint64_t n_items = 0;
-  const uint32_t* idx = nullptr;       // streamed vertex list (col or tcol)
+  const uint32_t* idx = nullptr;       // streamed vertex list (source staging)
+  const uint2* tin = nullptr;          // in-edges (target staging), else null
   const uint2* vdesc = nullptr;
   const uint32_t* col = nullptr;
   const uint4* bsdesc = nullptr;

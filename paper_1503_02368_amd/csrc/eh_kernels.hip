@@ -44,6 +44,7 @@ struct DevArgs {
   const Item* items;
   uint64_t n_items;
   const uint32_t* idx;
+  const uint2* tin;  // target staging: in-edges {u, position of the edge in col}
   const uint2* vdesc;
   const uint32_t* col;
   const uint4* bsdesc;
@@ -65,6 +66,7 @@ DevArgs to_dev(const LaunchArgs& a) {
   d.items = a.items;
   d.n_items = a.n_items;
   d.idx = a.idx;
+  d.tin = a.tin;
   d.vdesc = a.vdesc;
   d.col = a.col;
   d.bsdesc = a.bsdesc;
@@ -238,34 +240,60 @@ struct SegTab {
   int32_t* SM;
 };
 
-// Fills the segment table for streamed vertices vs[0..nseg) (one per lane)
-// and returns the flat length.  Bitset words are used only against a staged
-// bitmap, and only when they are fewer than the set's elements.
-__device__ __forceinline__ uint32_t load_segments(const DevArgs& a, const SegTab& T, uint32_t t,
-                                                  bool active, bool bitmap_ok, uint32_t lo_al,
-                                                  uint32_t lane) {
-  uint32_t len = 0, sb = 0;
-  int32_t sm = 0;
-  if (active) {
-    const uint2 td = a.vdesc[t];
-    const uint32_t tl = td.y & kMaxIndex;
-    sb = td.x;
-    len = tl;
-    if (bitmap_ok && (td.y & kHiBit)) {
-      const uint4 bd = a.bsdesc[t];
-      if (bd.z < tl) {
-        sb = bd.x | kHiBit;
-        len = bd.z;
-        sm = int32_t(bd.y >> 5) - int32_t(lo_al >> 5);
-      }
+// One streamed segment: start (col index, or kHiBit | bsw index), length,
+// and for bitset words the offset of its first word from the staged bitmap's.
+struct Seg {
+  uint32_t sb, len;
+  int32_t sm;
+};
+
+// The whole set N+(t).  Bitset words are used only against a staged bitmap,
+// and only when they are fewer than the set's elements.
+__device__ __forceinline__ Seg seg_full(const DevArgs& a, uint32_t t, bool bitmap_ok,
+                                        uint32_t lo_al) {
+  const uint2 td = a.vdesc[t];
+  const uint32_t tl = td.y & kMaxIndex;
+  Seg g{td.x, tl, 0};
+  if (bitmap_ok && (td.y & kHiBit)) {
+    const uint4 bd = a.bsdesc[t];
+    if (bd.z < tl) {
+      g.sb = bd.x | kHiBit;
+      g.len = bd.z;
+      g.sm = int32_t(bd.y >> 5) - int32_t(lo_al >> 5);
     }
   }
-  const uint32_t incl = wave_incl_scan(len, lane);
+  return g;
+}
+
+// The part of N+(u) above v, where v = col[e] is u's out-neighbour at edge
+// position e: only these elements can lie in N+(v), all of whose members
+// exceed v.  As bitset words: from the word holding v+1 to the last.
+__device__ __forceinline__ Seg seg_suffix(const DevArgs& a, uint32_t u, uint32_t e, uint32_t v,
+                                          bool bitmap_ok, uint32_t lo_al) {
+  const uint2 ud = a.vdesc[u];
+  const uint32_t end = ud.x + (ud.y & kMaxIndex);
+  Seg g{e + 1, end - e - 1, 0};
+  if (bitmap_ok && (ud.y & kHiBit) && g.len) {
+    const uint4 bd = a.bsdesc[u];
+    const uint32_t w0 = (v + 1 - bd.y) >> 5;  // v >= base since v is in the set
+    const uint32_t nw = w0 < bd.z ? bd.z - w0 : 0u;
+    if (nw < g.len) {
+      g.sb = (bd.x + w0) | kHiBit;
+      g.len = nw;
+      g.sm = int32_t((bd.y >> 5) + w0) - int32_t(lo_al >> 5);
+    }
+  }
+  return g;
+}
+
+// Publishes one segment per lane into the table and returns the flat length.
+__device__ __forceinline__ uint32_t publish_segments(const SegTab& T, const Seg& g, uint32_t lane) {
+  const uint32_t incl = wave_incl_scan(g.len, lane);
   wave_sync();  // previous batch's readers are done
   T.P[lane + 1] = incl;
   if (lane == 0) T.P[0] = 0;
-  T.SB[lane] = sb;
-  T.SM[lane] = sm;
+  T.SB[lane] = g.sb;
+  T.SM[lane] = g.sm;
   wave_sync();
   return uniform(__shfl(incl, kWave - 1, kWave));
 }
@@ -350,9 +378,16 @@ __global__ __launch_bounds__(WPB * kWave) void k_tri_staged(DevArgs a) {
     uint32_t cnt = 0;
     for (uint32_t b0 = 0; b0 < llen; b0 += kSeg) {
       const uint32_t nseg = min(uint32_t(kSeg), llen - b0);
-      const bool active = lane < nseg;
-      const uint32_t t = active ? a.idx[lbeg + b0 + lane] : 0u;
-      const uint32_t E = load_segments(a, T, t, active, bitmap_ok, st.lo_al, lane);
+      Seg g{0, 0, 0};
+      if (lane < nseg) {
+        if (a.tin) {
+          const uint2 ie = a.tin[lbeg + b0 + lane];  // in-edge u -> s at position ie.y
+          g = seg_suffix(a, ie.x, ie.y, s, bitmap_ok, st.lo_al);
+        } else {
+          g = seg_full(a, a.idx[lbeg + b0 + lane], bitmap_ok, st.lo_al);
+        }
+      }
+      const uint32_t E = publish_segments(T, g, lane);
       cnt += flat_probe<RW, U>(a, T, E, st, R, lane);
     }
     acc += cnt;
@@ -437,9 +472,9 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
         const bool bitmap_ok = a.use_bitsets && ss.mode == kModeBitmap;
         for (uint32_t b0 = 0; b0 < ns; b0 += kSeg) {
           const uint32_t nseg = min(uint32_t(kSeg), ns - b0);
-          const bool active = lane < nseg;
-          const uint32_t w = active ? S[b0 + lane] : 0u;
-          const uint32_t E = load_segments(a, T, w, active, bitmap_ok, ss.lo_al, lane);
+          Seg g{0, 0, 0};
+          if (lane < nseg) g = seg_full(a, S[b0 + lane], bitmap_ok, ss.lo_al);
+          const uint32_t E = publish_segments(T, g, lane);
           // bitmap bounds are B's (RW words); the list S is searched by length
           cnt += flat_probe<RW, U>(a, T, E, ss, probe, lane);
         }
