@@ -89,36 +89,46 @@ void free_trie_device(Trie& t) {
   dev_free(c, t.vdesc);
   dev_free(c, t.col);
   dev_free(c, t.bsdesc);
-  dev_free(c, t.bsw);
   dev_free(c, t.vert);
   dev_free(c, t.tin_d);
   t.device_bytes = 0;
 }
 
+// One list buffer holds every set: the uint layout (col, m entries) followed
+// by all bitset words, so a kernel reads either through one base pointer.
+// bsdesc.x is the absolute position of a set's first word in that buffer.
 eh_status upload_trie(Ctx* c, Trie& t) {
   const HostTrie& h = t.host;
+  const uint64_t W = h.bs_words.size();
+  if (h.m + W > kMaxIndex) {
+    c->err = "edges plus bitset words exceed 2^31-1";
+    return EH_EOVERFLOW;
+  }
   std::vector<uint2> vd(std::max<uint32_t>(h.n, 1));
   std::vector<uint4> bd(std::max<uint32_t>(h.n, 1));
   for (uint32_t v = 0; v < h.n; ++v) {
     const uint32_t len = h.row[v + 1] - h.row[v];
     const bool bs = h.bs_off[v] != kNoBitset;
     vd[v] = make_uint2(h.row[v], len | (bs ? kHiBit : 0u));
-    bd[v] = make_uint4(bs ? h.bs_off[v] : 0u, h.bs_base[v], h.bs_nw[v], 0u);
+    bd[v] = make_uint4(bs ? uint32_t(h.m) + h.bs_off[v] : 0u, h.bs_base[v], h.bs_nw[v], 0u);
   }
   eh_status st;
   if ((st = upload(c, t.vdesc, vd.data(), sizeof(uint2) * h.n, "upload vertex table")) != EH_OK)
     return st;
-  if ((st = upload(c, t.col, h.col.data(), sizeof(uint32_t) * h.m, "upload columns")) != EH_OK)
+  if ((st = dev_alloc(c, t.col, sizeof(uint32_t) * (h.m + W))) != EH_OK) return st;
+  if (h.m && (st = hip_check(c, hipMemcpy(t.col.p, h.col.data(), sizeof(uint32_t) * h.m,
+                                          hipMemcpyHostToDevice), "upload columns")) != EH_OK)
+    return st;
+  if (W && (st = hip_check(c, hipMemcpy(static_cast<uint32_t*>(t.col.p) + h.m, h.bs_words.data(),
+                                        sizeof(uint32_t) * W, hipMemcpyHostToDevice),
+                           "upload bitset words")) != EH_OK)
     return st;
   if ((st = upload(c, t.bsdesc, bd.data(), sizeof(uint4) * (h.n_bs ? h.n : 0),
                    "upload bitset table")) != EH_OK)
     return st;
-  if ((st = upload(c, t.bsw, h.bs_words.data(), sizeof(uint32_t) * h.bs_words.size(),
-                   "upload bitset words")) != EH_OK)
-    return st;
   if ((st = upload(c, t.vert, h.vert.data(), sizeof(uint32_t) * h.n, "upload ids")) != EH_OK)
     return st;
-  t.device_bytes = t.vdesc.bytes + t.col.bytes + t.bsdesc.bytes + t.bsw.bytes + t.vert.bytes;
+  t.device_bytes = t.vdesc.bytes + t.col.bytes + t.bsdesc.bytes + t.vert.bytes;
   return EH_OK;
 }
 
@@ -127,7 +137,7 @@ LaunchArgs base_args(Ctx* c, const Trie& t) {
   a.vdesc = static_cast<const uint2*>(t.vdesc.p);
   a.col = static_cast<const uint32_t*>(t.col.p);
   a.bsdesc = static_cast<const uint4*>(t.bsdesc.p);
-  a.bsw = static_cast<const uint32_t*>(t.bsw.p);
+  a.bsw = static_cast<const uint32_t*>(t.col.p);  // words live after col
   a.vert = static_cast<const uint32_t*>(t.vert.p);
   a.cursor = static_cast<uint32_t*>(c->cursor.p);
   a.use_bitsets = c->tune.use_bitsets && t.host.n_bs > 0;

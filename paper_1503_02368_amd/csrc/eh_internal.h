@@ -110,9 +110,8 @@ struct Trie {
   std::vector<uint32_t> tin;         // [2m] in-edges {u, position of u->v in col}, by v then u
   // device arrays
   DevBuf vdesc;   // uint2 [n]: {row begin, out-degree | kHiBit if bitset}
-  DevBuf col;     // uint32 [m]
-  DevBuf bsdesc;  // uint4 [n]: {word offset, base, words, 0}
-  DevBuf bsw;     // uint32 bitset words
+  DevBuf col;     // uint32 [m + W]: the uint sets, then every bitset's words
+  DevBuf bsdesc;  // uint4 [n]: {position of first word in col, base, words, 0}
   DevBuf vert;    // uint32 [n]: rank -> id
   DevBuf tin_d;   // uint2 [m]: in-edges (target staging)
   std::vector<std::unique_ptr<Plan>> plans;
@@ -157,7 +156,7 @@ struct LaunchArgs {
   const uint2* vdesc = nullptr;
   const uint32_t* col = nullptr;
   const uint4* bsdesc = nullptr;
-  const uint32_t* bsw = nullptr;
+  const uint32_t* bsw = nullptr;       // base of bsdesc positions (= col)
   unsigned long long* acc = nullptr;   // accumulators indexed by item tag
   uint32_t tag_base = 0;               // acc index = tag - tag_base
   unsigned long long* per_root = nullptr;  // optional, source staging only

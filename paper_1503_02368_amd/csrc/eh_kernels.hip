@@ -233,14 +233,15 @@ __device__ __forceinline__ uint32_t staged_has(const DevArgs& a, const Staged& s
 }
 
 // Segment table of one flat batch: P = prefix of lengths (kSeg+1),
-// SB = start in col (or kHiBit | start in bsw), SM = word delta for bitsets.
+// SB = start in the list buffer (kHiBit: bitset words), SM = word delta.
 struct SegTab {
   uint32_t* P;
   uint32_t* SB;
   int32_t* SM;
 };
 
-// One streamed segment: start (col index, or kHiBit | bsw index), length,
+// One streamed segment: start in the list buffer (col, then bitset words;
+// kHiBit marks words), length,
 // and for bitset words the offset of its first word from the staged bitmap's.
 struct Seg {
   uint32_t sb, len;
@@ -298,51 +299,91 @@ __device__ __forceinline__ uint32_t publish_segments(const SegTab& T, const Seg&
   return uniform(__shfl(incl, kWave - 1, kWave));
 }
 
-// Walks flat indices lane, lane+64, ... < E of the segment table and tests
-// each element against the staged set held in R (bitmap, list or global).
+// Per-lane cursor over the segment table: for a flat index f it yields the
+// element's position in the list buffer (col followed by all bitset words)
+// and, for bitset words, the word's index in the staged bitmap.  Segment
+// bases are kept relative to f so each element costs one add.
+struct SegCursor {
+  uint32_t j, nxt, base, wbase;
+  bool bits;
+  __device__ __forceinline__ explicit SegCursor(const SegTab& T) {
+    j = 0;
+    nxt = T.P[1];
+    const uint32_t sb = T.SB[0];
+    base = sb & kMaxIndex;
+    wbase = uint32_t(T.SM[0]);
+    bits = (sb & kHiBit) != 0;
+  }
+  __device__ __forceinline__ void seek(const SegTab& T, uint32_t f) {
+    while (nxt <= f) {
+      const uint32_t start = nxt;
+      ++j;
+      nxt = T.P[j + 1];
+      const uint32_t sb = T.SB[j];
+      base = (sb & kMaxIndex) - start;
+      wbase = uint32_t(T.SM[j]) - start;
+      bits = (sb & kHiBit) != 0;
+    }
+  }
+};
+
+// Walks flat indices lane, lane+64, ... < E of the segment table and counts
+// the elements found in the staged set.  Against a staged bitmap every
+// element costs the same: a uint value x tests bit x - lo_al, a bitset word
+// is ANDed with the bitmap word it overlaps, both as popc(R[w] & mask).
 template <int RW, int U>
 __device__ __forceinline__ uint32_t flat_probe(const DevArgs& a, const SegTab& T, uint32_t E,
                                                const Staged& st, const uint32_t* R,
                                                uint32_t lane) {
+  const uint32_t* __restrict__ L = a.col;
   uint32_t cnt = 0;
-  uint32_t j = 0, cur = 0, nxt = T.P[1], jsb = T.SB[0];
-  int32_t jsm = T.SM[0];
+  SegCursor c(T);
+  if (st.mode == kModeBitmap) {
+    const uint32_t lo_al = st.lo_al;
+    for (uint32_t f0 = 0; f0 < E; f0 += kWave * U) {
+      uint32_t val[U], key[U];
+      bool ok[U], bits[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t f = f0 + uint32_t(u) * kWave + lane;
+        ok[u] = f < E;
+        val[u] = 0;
+        key[u] = 0;
+        bits[u] = false;
+        if (ok[u]) {
+          c.seek(T, f);
+          val[u] = L[c.base + f];
+          key[u] = c.wbase + f;
+          bits[u] = c.bits;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t d = val[u] - lo_al;
+        const uint32_t w = bits[u] ? key[u] : (d >> 5);
+        const uint32_t m = bits[u] ? val[u] : (1u << (d & 31));
+        if (ok[u] && w < uint32_t(RW)) cnt += __popc(R[w] & m);
+      }
+    }
+    return cnt;
+  }
+  // staged list or global list: uint elements only, searched
   for (uint32_t f0 = 0; f0 < E; f0 += kWave * U) {
     uint32_t val[U];
-    uint32_t wix[U];
-    bool ok[U], isbs[U];
+    bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t f = f0 + uint32_t(u) * kWave + lane;
       ok[u] = f < E;
-      isbs[u] = false;
       val[u] = 0;
-      wix[u] = 0;
       if (ok[u]) {
-        while (nxt <= f) {
-          ++j;
-          cur = nxt;
-          nxt = T.P[j + 1];
-          jsb = T.SB[j];
-          jsm = T.SM[j];
-        }
-        const uint32_t off = f - cur;
-        isbs[u] = (jsb & kHiBit) != 0;
-        const uint32_t* src = isbs[u] ? a.bsw : a.col;
-        val[u] = src[(jsb & kMaxIndex) + off];
-        wix[u] = uint32_t(jsm + int32_t(off));
+        c.seek(T, f);
+        val[u] = L[c.base + f];
       }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (!ok[u]) continue;
-      if (isbs[u]) {
-        // bitset & bitset: one 32-bit word against the staged bitmap
-        if (wix[u] < uint32_t(RW)) cnt += __popc(val[u] & R[wix[u]]);
-      } else {
-        cnt += staged_has<RW>(a, st, R, val[u]);
-      }
-    }
+    for (int u = 0; u < U; ++u)
+      if (ok[u]) cnt += staged_has<RW>(a, st, R, val[u]);
   }
   return cnt;
 }

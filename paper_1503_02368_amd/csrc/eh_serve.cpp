@@ -83,7 +83,7 @@ eh_status server_launch(Server* s, const std::vector<Item>& v, uint64_t off, int
   a.vdesc = static_cast<const uint2*>(t.vdesc.p);
   a.col = static_cast<const uint32_t*>(t.col.p);
   a.bsdesc = static_cast<const uint4*>(t.bsdesc.p);
-  a.bsw = static_cast<const uint32_t*>(t.bsw.p);
+  a.bsw = static_cast<const uint32_t*>(t.col.p);  // words live after col
   a.vert = static_cast<const uint32_t*>(t.vert.p);
   a.idx = static_cast<const uint32_t*>(t.col.p);
   a.items = static_cast<const Item*>(s->items_d.p) + off;
