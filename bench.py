@@ -197,6 +197,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--b-k4", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--rates", default="200,1000,5000", help="served: arrival rates (QPS)")
+    ap.add_argument("--duration", type=float, default=3.0, help="served: seconds per rate")
+    ap.add_argument("--max-requests", type=int, default=3000, help="served: cap per rate")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("this engine runs on one GPU; no multi-GPU path exists (use --gpus 1)", file=sys.stderr)

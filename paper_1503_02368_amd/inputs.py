@@ -20,8 +20,9 @@ not available here; these synthetic families stand in for them):
   choosing one quadrant per level with probabilities (a, b, c, d) quantised to
   1/65536; no noise, no vertex permutation.
 * Erdos-Renyi G(n, M): M distinct unordered pairs drawn uniformly.
-* Chung-Lu power law: weights w_i = (i+1)**(-1/(gamma-1)), round(n*dbar/2)
-  endpoint pairs drawn with probability proportional to w.
+* Chung-Lu power law: round(n*dbar/2) endpoint pairs; each end is floor(x),
+  x drawn by inverse CDF from the density proportional to
+  (x+1)**(-1/(gamma-1)) on [0, n).
 * Batched Chung-Lu: n_i = round(exp U[ln 64, ln 16384]),
   dbar_i = exp U[ln 8, ln 64], gamma = 2.1, one key per graph.
 * Small structured graphs (complete, grid, cycle, wheel, ...) for pins.
@@ -97,13 +98,15 @@ class EdgeList:
 
 
 def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
-         c: float = 0.19, seed: int = 0, chunk: int = 1 << 22) -> EdgeList:
+         c: float = 0.19, seed: int = 0, chunk: int = 1 << 20) -> EdgeList:
     """R-MAT generator (Chakrabarti, Zhan, Faloutsos 2004), no noise.
 
     Each 64-bit draw supplies four 16-bit level choices; quadrant (row, col)
     is (0,0) below a, (0,1) below a+b, (1,0) below a+b+c, else (1,1).  The row
     bit goes to src and the column bit to dst, most significant level first.
     """
+    import concurrent.futures as cf
+    import os
     n = 1 << scale
     m = edge_factor * n
     key = stream_key(seed, 0x52AA7)
@@ -113,7 +116,8 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
     draws_per = (scale + 3) // 4
     src = np.empty(m, dtype=np.uint32)
     dst = np.empty(m, dtype=np.uint32)
-    for s0 in range(0, m, chunk):
+
+    def fill(s0):
         cnt = min(chunk, m - s0)
         r = rand_u64(key, s0 * draws_per, cnt * draws_per).reshape(cnt, draws_per)
         s = np.zeros(cnt, dtype=np.uint64)
@@ -132,6 +136,15 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
                 lvl += 1
         src[s0:s0 + cnt] = s.astype(np.uint32)
         dst[s0:s0 + cnt] = d.astype(np.uint32)
+
+    starts = list(range(0, m, chunk))
+    nt = min(16, os.cpu_count() or 1)
+    if len(starts) <= 1 or nt == 1:
+        for s0 in starts:
+            fill(s0)
+    else:
+        with cf.ThreadPoolExecutor(max_workers=nt) as ex:
+            list(ex.map(fill, starts))
     return EdgeList(n, src, dst, f"rmat{scale}_ef{edge_factor}_s{seed}")
 
 
@@ -187,19 +200,84 @@ def erdos_renyi_gnm(n: int, m: int, seed: int = 0) -> EdgeList:
     return EdgeList(n, i.astype(np.uint32), j.astype(np.uint32), f"er{n}_m{m}_s{seed}")
 
 
+def _powerlaw_ends(n: np.ndarray, u: np.ndarray, gamma: float, gidx=None) -> np.ndarray:
+    """floor(x) for x with density proportional to (x+1)^(-1/(gamma-1)) on [0, n).
+
+    n holds one size per graph and gidx maps each draw u to its graph (None:
+    one graph).  Inverse CDF: x = (1 + u((n+1)^b - 1))^(1/b) - 1, b = 1 - 1/(gamma-1).
+    """
+    beta = 1.0 - 1.0 / (gamma - 1.0)
+    nf = np.asarray(n, dtype=np.float64)
+    sel = (lambda a: a) if gidx is None else (lambda a: a[gidx])
+    if abs(beta) < 1e-12:
+        x = np.expm1(u * sel(np.log1p(nf)))
+    else:
+        top = np.expm1(beta * np.log1p(nf))   # (n+1)^b - 1
+        x = np.expm1(np.log1p(u * sel(top)) * (1.0 / beta))
+    e = np.floor(x).astype(np.int64)
+    np.clip(e, 0, sel(np.asarray(n, dtype=np.int64)) - 1, out=e)
+    return e
+
+
+def _chung_lu_many(ns, ds, gamma, seed, graph_ids, chunk=1 << 22, threads=None):
+    """Endpoint pairs of several Chung-Lu graphs; returns (src, dst, edge_off).
+
+    Graphs are cut into chunks of about `chunk` draws that a thread pool fills
+    (numpy releases the GIL); every draw is addressed by (graph, counter), so
+    the result does not depend on the chunking or the thread count.
+    """
+    import concurrent.futures as cf
+    import os
+    ns = np.asarray(ns, dtype=np.int64)
+    ms = np.rint(ns * np.asarray(ds, dtype=np.float64) / 2.0).astype(np.int64)
+    off = np.zeros(ns.size + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(ms).astype(np.uint64)
+    src = np.empty(int(off[-1]), dtype=np.uint32)
+    dst = np.empty(int(off[-1]), dtype=np.uint32)
+    keys = np.array([stream_key(seed, 0xC1000000 + int(g)) for g in graph_ids], dtype=np.uint64)
+    spans = []
+    g0 = 0
+    while g0 < ns.size:
+        g1, tot = g0, 0
+        while g1 < ns.size and (tot == 0 or tot + 2 * ms[g1] <= chunk):
+            tot += 2 * int(ms[g1])
+            g1 += 1
+        spans.append((g0, g1, tot))
+        g0 = g1
+
+    def fill(span):
+        g0, g1, tot = span
+        if tot == 0:
+            return
+        cnt = 2 * ms[g0:g1]
+        gidx = np.repeat(np.arange(g0, g1), cnt)
+        starts = np.repeat(np.cumsum(cnt) - cnt, cnt)
+        ctr = (np.arange(tot, dtype=np.int64) - starts + 1).astype(np.uint64)
+        with np.errstate(over="ignore"):
+            z = _mix(keys[gidx] + ctr * _GOLDEN)
+        u = (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+        ends = _powerlaw_ends(ns, u, gamma, gidx).astype(np.uint32)
+        a = int(off[g0])
+        src[a:a + tot // 2] = ends[0::2]
+        dst[a:a + tot // 2] = ends[1::2]
+
+    nt = threads or min(16, os.cpu_count() or 1)
+    if len(spans) == 1 or nt == 1:
+        for sp in spans:
+            fill(sp)
+    else:
+        with cf.ThreadPoolExecutor(max_workers=nt) as ex:
+            list(ex.map(fill, spans))
+    return src, dst, off
+
+
 def chung_lu(n: int, avg_degree: float, gamma: float = 2.1, seed: int = 0,
              graph: int = 0) -> EdgeList:
-    """Chung-Lu style power-law graph: round(n*dbar/2) weighted endpoint pairs."""
-    w = (np.arange(1, n + 1, dtype=np.float64)) ** (-1.0 / (gamma - 1.0))
-    cdf = np.cumsum(w)
-    cdf /= cdf[-1]
-    m = int(round(n * avg_degree / 2.0))
-    key = stream_key(seed, 0xC1000000 + graph)
-    u = rand_uniform(key, 0, 2 * m)
-    ends = np.searchsorted(cdf, u, side="right")
-    np.minimum(ends, n - 1, out=ends)
-    ends = ends.astype(np.uint32)
-    return EdgeList(n, ends[0::2].copy(), ends[1::2].copy(), f"cl{n}_d{avg_degree:.2f}_g{gamma}_s{seed}_{graph}")
+    """Chung-Lu style power-law graph: round(n*dbar/2) endpoint pairs, each end
+    floor(x) with x drawn from the density proportional to (x+1)^(-1/(gamma-1))
+    on [0, n) (vertex i's expected degree falls off as i^(-1/(gamma-1)))."""
+    s, d, _ = _chung_lu_many([n], [avg_degree], gamma, seed, [graph])
+    return EdgeList(n, s, d, f"cl{n}_d{avg_degree:.2f}_g{gamma}_s{seed}_{graph}")
 
 
 @dataclass
@@ -233,16 +311,10 @@ def batch_sizes(num_graphs: int, seed: int, n_lo: int = 64, n_hi: int = 16384,
 
 def batch_chung_lu(num_graphs: int, seed: int = 4, gamma: float = 2.1, n_lo: int = 64,
                    n_hi: int = 16384, d_lo: float = 8.0, d_hi: float = 64.0) -> BatchEdges:
+    """Graph g is chung_lu(n_g, dbar_g, gamma, seed, g) with (n_g, dbar_g) from batch_sizes."""
     n, d = batch_sizes(num_graphs, seed, n_lo, n_hi, d_lo, d_hi)
-    srcs, dsts = [], []
-    off = np.zeros(num_graphs + 1, dtype=np.uint64)
-    for g in range(num_graphs):
-        el = chung_lu(int(n[g]), float(d[g]), gamma, seed, g)
-        srcs.append(el.src)
-        dsts.append(el.dst)
-        off[g + 1] = off[g] + np.uint64(el.m_raw)
-    return BatchEdges(n.astype(np.uint32), off, np.concatenate(srcs), np.concatenate(dsts),
-                      f"batch_cl{num_graphs}_s{seed}")
+    src, dst, off = _chung_lu_many(n, d, gamma, seed, np.arange(num_graphs))
+    return BatchEdges(n.astype(np.uint32), off, src, dst, f"batch_cl{num_graphs}_s{seed}")
 
 
 # ---------------------------------------------------------------------------
