@@ -39,16 +39,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1503_02368_amd", "csrc", "eh_kernels.hip"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 TUNING_FILE = os.path.join(ROOT, "paper_1503_02368_amd", "tuning.json")
 
-WORKLOADS = {
-    "rmat20_triangles": dict(kind="graph", pattern=3, gen="rmat", scale=20, edge_factor=16, seed=20,
-                             layout=1, tau=32.0),
-    "rmat18_4cliques": dict(kind="graph", pattern=4, gen="rmat", scale=18, edge_factor=16, seed=18,
-                            layout=1, tau=32.0),
-    "er4096_triangles": dict(kind="graph", pattern=3, gen="er", n=4096, m=32768, seed=1, layout=0,
-                             tau=32.0),
-    "batch_triangles": dict(kind="batch", pattern=3, graphs=20000, seed=4, layout=1, tau=32.0),
-    "served": dict(kind="served", gen="rmat", scale=22, edge_factor=16, seed=22, layout=1, tau=32.0),
-}
+from paper_1503_02368_amd.workloads import WORKLOADS, make_graph  # noqa: E402
 
 
 def log(*a):
@@ -61,6 +52,7 @@ def kernel_sha() -> str:
 
 
 def load_tuning(name: str) -> dict:
+    """The autotuner's choice for this workload: {layout, tau, tuning}, or {}."""
     if os.path.exists(TUNING_FILE):
         with open(TUNING_FILE) as f:
             return json.load(f).get(name, {})
@@ -77,13 +69,6 @@ def measured_traffic(name: str, launches_per_step: int = 1):
     if not d or d.get("kernel_sha") != kernel_sha():
         return None
     return d.get("bytes_per_launch")
-
-
-def make_graph(w: dict):
-    from paper_1503_02368_amd import inputs
-    if w["gen"] == "rmat":
-        return inputs.rmat(w["scale"], w["edge_factor"], seed=w["seed"])
-    return inputs.erdos_renyi_gnm(w["n"], w["m"], seed=w["seed"])
 
 
 def cpu_baseline(el, pattern: int, budget_s: float = 20.0) -> dict:
@@ -107,7 +92,8 @@ def cpu_baseline(el, pattern: int, budget_s: float = 20.0) -> dict:
             times.append(time.perf_counter() - t0)
         t = statistics.median(times)
         return {"value": res["edges"] / t, "unit": "edges/s", "cores": threads, "kind": "oracle",
-                "sample": f"whole workload, median of 3 runs ({t:.3f} s each)", "count": res["count"]}
+                "sample": f"whole workload, median of 3 runs ({t:.3f} s each)", "count": res["count"],
+                "bytes": res["bytes"]}
     frac = max(1.0 / 64, min(1.0, (budget_s / 2) / max(est_full, 1e-9)))
     x_end = max(1, int(g.n * frac))
     t0 = time.perf_counter()
@@ -116,17 +102,17 @@ def cpu_baseline(el, pattern: int, budget_s: float = 20.0) -> dict:
     del probe
     return {"value": res["edges"] / t, "unit": "edges/s", "cores": threads, "kind": "oracle",
             "sample": f"outer vertices of rank < {x_end} ({res['edges']} of {g.m} oriented edges), "
-                      f"{t:.2f} s", "count": None}
+                      f"{t:.2f} s", "count": None, "bytes": None}
 
 
 def bench_graph(name, w, args, ctx, eh, torch):
     el = make_graph(w)
     log(f"[bench] {name}: generated n={el.n} raw pairs={el.m_raw}")
     tune = load_tuning(name)
-    layout = tune.pop("layout", w["layout"])
-    tau = tune.pop("tau", w["tau"])
-    if tune:
-        ctx.set_tuning(**tune)
+    layout = tune.get("layout", w["layout"])
+    tau = tune.get("tau", w["tau"])
+    if tune.get("tuning"):
+        ctx.set_tuning(**tune["tuning"])
     t0 = time.perf_counter()
     trie = ctx.build_edgelist(el, layout=layout, tau=tau)
     t_build = time.perf_counter() - t0
@@ -166,24 +152,24 @@ def bench_graph(name, w, args, ctx, eh, torch):
                    "bitset_sets": info["n_bitset_sets"], "tuning": ctx.get_tuning()},
         "count": count,
     }
-    bytes_per_launch = info["b_merge"] if pattern == 3 else None
-    if pattern == 4:
-        bytes_per_launch = args.b_k4
+    cb = None
+    if not args.no_cpu:
+        log("[bench] timing the CPU oracle")
+        cb = cpu_baseline(el, pattern, args.cpu_budget)
+        if cb.get("count") is not None:
+            result["parity_vs_oracle"] = cb["count"] == count
+    # algorithmic bytes: B_merge from the trie; B_K4 (needs every triangle) from the oracle's pass
+    bytes_per_launch = info["b_merge"] if pattern == 3 else (cb or {}).get("bytes")
     if bytes_per_launch:
         achieved = bytes_per_launch / (ms / 1e3) / 1e9
         result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name),
                               "algorithmic_bytes_per_launch": bytes_per_launch,
                               "model": "B_merge" if pattern == 3 else "B_K4"}
-    if not args.no_cpu:
-        log("[bench] timing the CPU oracle")
-        cb = cpu_baseline(el, pattern, args.cpu_budget)
-        if cb.get("count") is not None:
-            result["parity_vs_oracle"] = cb["count"] == count
+    if cb is not None:
         cb.pop("count", None)
+        cb.pop("bytes", None)
         result["cpu_baseline"] = cb
-        if pattern == 4 and not args.b_k4:
-            pass
     trie.free()
     return result
 
@@ -196,7 +182,6 @@ def main():
     ap.add_argument("--workload", default="rmat20_triangles", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--b-k4", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--rates", default="200,1000,5000", help="served: arrival rates (QPS)")
     ap.add_argument("--duration", type=float, default=3.0, help="served: seconds per rate")
     ap.add_argument("--max-requests", type=int, default=3000, help="served: cap per rate")

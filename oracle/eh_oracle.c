@@ -27,7 +27,7 @@
  *   sum over {a,b} in E of |N(a) & N(b)|            = 3 T
  *   sum over {a,b} in E of edges(N(a) & N(b))       = 6 K
  *   Generic-Join over the symmetric (unpruned) relation counts ordered
- *   tuples: 3! T and 4! K (appendix A.2, symmetric filtering).
+ *   tuples: 3! T and 4! K (appendix A.1.2, pruning symmetric queries).
  *
  * Byte models (the reads a list-merge implementation performs):
  *   B_merge = sum over oriented edges (x,y) of 4 (|N+(x)| + |N+(y)|)

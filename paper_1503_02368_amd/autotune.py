@@ -1,0 +1,189 @@
+"""Autotuner: picks the layout and kernel knobs per workload by measurement.
+
+The paper's lower-bound "oracle optimizer" (section 4.4) ran every layout and
+algorithm combination and kept the best; this tuner does the same over the
+knobs of this engine, per workload, on the real GPU: set layout (uint only,
+or the set optimizer at several tau), kernel (staged or pairwise), staging
+side, bitset use, work-item size, persistent waves per CU, and for the
+pairwise kernel lanes per pair, algorithm and the galloping ratio gamma.
+Counts never depend on these choices; every candidate's count must equal the
+first one measured or the search stops with an error.
+
+    python -m paper_1503_02368_amd.autotune --workload rmat20_triangles --out tuning.json
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_OUT = os.path.join(HERE, "tuning.json")
+
+BASE = dict(kernel=1, staging=2, algo=0, gamma=32.0, chunk_work=4096, waves_per_cu=32,
+            group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Timer:
+    def __init__(self, ctx, torch):
+        self.ctx = ctx
+        self.torch = torch
+        self.out = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+    def graph(self, trie, pattern, reps=5):
+        """(ms per launch, count) of `reps` accumulating launches after one warm-up."""
+        torch, ctx, out = self.torch, self.ctx, self.out
+        s = ctx.stream
+        s.wait_stream(torch.cuda.current_stream())
+        ctx.count_add_async(trie, pattern, out)   # warm-up (also builds the plan)
+        torch.cuda.synchronize()
+        out.zero_()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            ctx.count_add_async(trie, pattern, out)
+        e1.record(s)
+        torch.cuda.synchronize()
+        total = int(out.cpu().numpy().view(np.uint64)[0])
+        count, rem = divmod(total, reps)
+        if rem:
+            raise RuntimeError("accumulated count is not a multiple of the launch count")
+        return e0.elapsed_time(e1) / reps, count
+
+
+class Search:
+    def __init__(self):
+        self.ref = None
+        self.best = None
+        self.table = []
+
+    def record(self, cfg, ms, count):
+        if self.ref is None:
+            self.ref = count
+        elif count != self.ref:
+            raise RuntimeError(f"count {count} differs from {self.ref} under {cfg}")
+        self.table.append((ms, cfg))
+        if self.best is None or ms < self.best[0]:
+            self.best = (ms, cfg)
+        log(f"[tune] {ms:8.3f} ms  {cfg}")
+
+
+def tune_graph(el, pattern, layouts, ctx, torch, quick=False):
+    from paper_1503_02368_amd import eh
+    timer = Timer(ctx, torch)
+    S = Search()
+    for layout, tau in layouts:
+        trie = ctx.build_edgelist(el, layout=layout, tau=tau)
+        has_bits = trie.info["n_bitset_sets"] > 0
+        try:
+            kinds = [dict(kernel=1, staging=2), dict(kernel=1, staging=1)] if pattern == 3 else \
+                [dict(kernel=1, staging=1)]
+            if pattern == 3:
+                kinds.append(dict(kernel=2, group_lanes=0, algo=0))
+            local = None
+            for k, ub in itertools.product(kinds, [1, 0] if has_bits else [0]):
+                cfg = dict(BASE, **k, use_bitsets=ub)
+                ctx.set_tuning(**cfg)
+                ms, c = timer.graph(trie, pattern)
+                S.record(dict(layout=layout, tau=tau, tuning=cfg), ms, c)
+                if local is None or ms < local[0]:
+                    local = (ms, cfg)
+            # refine the schedule of the best kernel on this layout
+            chunks = [1024, 4096, 16384] if quick else [1024, 2048, 4096, 8192, 16384, 32768, 65536]
+            waves = [16, 32] if quick else [8, 16, 24, 32]
+            for ch, wv in itertools.product(chunks, waves):
+                cfg = dict(local[1], chunk_work=ch, waves_per_cu=wv)
+                ctx.set_tuning(**cfg)
+                ms, c = timer.graph(trie, pattern)
+                S.record(dict(layout=layout, tau=tau, tuning=cfg), ms, c)
+            if local[1]["kernel"] == eh.KERNEL_PAIRWISE:
+                for g, al, gm in itertools.product([4, 16, 64], [0, 1, 2], [8.0, 32.0, 128.0]):
+                    cfg = dict(local[1], group_lanes=g, algo=al, gamma=gm)
+                    ctx.set_tuning(**cfg)
+                    ms, c = timer.graph(trie, pattern)
+                    S.record(dict(layout=layout, tau=tau, tuning=cfg), ms, c)
+        finally:
+            trie.free()
+    return S
+
+
+def tune_batch(b, pattern, layouts, ctx, torch, quick=False):
+    S = Search()
+    G = b.n_graphs
+    out = torch.zeros(G, dtype=torch.int64, device="cuda")
+    for layout, tau in layouts:
+        trie = ctx.build_batch(b, layout=layout, tau=tau)
+        try:
+            chunks = [1024, 4096, 16384] if quick else [512, 1024, 2048, 4096, 8192, 16384]
+            for st, ch, wv in itertools.product([2, 1], chunks, [16, 32]):
+                cfg = dict(BASE, staging=st, chunk_work=ch, waves_per_cu=wv)
+                ctx.set_tuning(**cfg)
+                s = ctx.stream
+                ctx.count_batch_async(trie, pattern, 0, G, out)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                for _ in range(3):
+                    ctx.count_batch_async(trie, pattern, 0, G, out)
+                e1.record(s)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / 3
+                c = int(out.cpu().numpy().view(np.uint64).sum(dtype=np.uint64))
+                S.record(dict(layout=layout, tau=tau, tuning=cfg), ms, c)
+        finally:
+            trie.free()
+    return S
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", action="append", required=True)
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--quick", action="store_true")
+    args = ap.parse_args()
+    import torch
+    from paper_1503_02368_amd import eh
+    from paper_1503_02368_amd.workloads import WORKLOADS, make_batch, make_graph
+    ctx = eh.Context(0)
+    result = {}
+    if os.path.exists(args.out):
+        with open(args.out) as f:
+            result = json.load(f)
+    for name in args.workload:
+        w = WORKLOADS[name]
+        t0 = time.time()
+        if w["layout"] == 0:
+            layouts = [(0, 32.0)]           # the workload fixes the uint-only layout
+        else:
+            layouts = [(0, 32.0), (1, 8.0), (1, 32.0), (1, 256.0)] if not args.quick else \
+                [(1, 32.0), (1, 256.0)]
+        if w["kind"] == "batch":
+            S = tune_batch(make_batch(w), w["pattern"], layouts, ctx, torch, args.quick)
+        elif w["kind"] == "graph":
+            S = tune_graph(make_graph(w), w["pattern"], layouts, ctx, torch, args.quick)
+        else:
+            continue
+        ms, cfg = S.best
+        result[name] = {"layout": cfg["layout"], "tau": cfg["tau"], "tuning": cfg["tuning"],
+                        "ms": ms, "candidates": len(S.table), "count": S.ref,
+                        "searched_s": round(time.time() - t0, 1)}
+        log(f"[tune] {name}: best {ms:.3f} ms with {cfg}")
+        with open(args.out, "w") as f:
+            json.dump(result, f, indent=1, sort_keys=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

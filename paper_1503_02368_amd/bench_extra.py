@@ -25,6 +25,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def load_tuning(name: str) -> dict:
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f).get(name, {})
+    return {}
+
+
 def _pct(xs, q):
     if not xs:
         return None
@@ -39,8 +49,13 @@ def bench_batch(name, w, args, ctx, eh, torch, metric):
     b = inputs.batch_chung_lu(w["graphs"], seed=w["seed"])
     log(f"[bench] batch generated in {time.perf_counter() - t0:.1f} s: {b.n_graphs} graphs, "
         f"{b.src.size} raw pairs")
+    tune = load_tuning(name)
+    layout = tune.get("layout", w["layout"])
+    tau = tune.get("tau", w["tau"])
+    if tune.get("tuning"):
+        ctx.set_tuning(**tune["tuning"])
     t0 = time.perf_counter()
-    trie = ctx.build_batch(b, layout=w["layout"], tau=w["tau"])
+    trie = ctx.build_batch(b, layout=layout, tau=tau)
     info = trie.info
     log(f"[bench] batch trie built in {time.perf_counter() - t0:.1f} s: {info}")
     G = info["n_graphs"]
@@ -107,7 +122,8 @@ def bench_batch(name, w, args, ctx, eh, torch, metric):
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded generator)",
         "config": {"workload": name, "graphs": G, "n_total": info["n"], "m_plus": m_plus,
                    "generator": "Chung-Lu gamma 2.1, n log-U[64,16384], mean degree log-U[8,64]",
-                   "seed": w["seed"], "layout": "hybrid", "tau": w["tau"], "tuning": ctx.get_tuning()},
+                   "seed": w["seed"], "layout": ["uint", "hybrid", "bitset_all"][layout], "tau": tau,
+                   "tuning": ctx.get_tuning()},
         "count_total": int(one.sum(dtype=np.uint64)),
         "per_instance": {"ms_per_pass": ms_loop, "edges_per_s": m_plus / (ms_loop / 1e3),
                          "graph_replay_ms_per_pass": ms_graph,

@@ -1,0 +1,26 @@
+"""Named benchmark workloads (seeded synthetic inputs) shared by bench.py and
+the autotuner."""
+from __future__ import annotations
+
+WORKLOADS = {
+    "rmat20_triangles": dict(kind="graph", pattern=3, gen="rmat", scale=20, edge_factor=16, seed=20,
+                             layout=1, tau=32.0),
+    "rmat18_4cliques": dict(kind="graph", pattern=4, gen="rmat", scale=18, edge_factor=16, seed=18,
+                            layout=1, tau=32.0),
+    "er4096_triangles": dict(kind="graph", pattern=3, gen="er", n=4096, m=32768, seed=1, layout=0,
+                             tau=32.0),
+    "batch_triangles": dict(kind="batch", pattern=3, graphs=20000, seed=4, layout=1, tau=32.0),
+    "served": dict(kind="served", gen="rmat", scale=22, edge_factor=16, seed=22, layout=1, tau=32.0),
+}
+
+
+def make_graph(w: dict):
+    from paper_1503_02368_amd import inputs
+    if w["gen"] == "rmat":
+        return inputs.rmat(w["scale"], w["edge_factor"], seed=w["seed"])
+    return inputs.erdos_renyi_gnm(w["n"], w["m"], seed=w["seed"])
+
+
+def make_batch(w: dict):
+    from paper_1503_02368_amd import inputs
+    return inputs.batch_chung_lu(w["graphs"], seed=w["seed"])
