@@ -106,6 +106,9 @@ typedef struct eh_tuning {
   uint32_t dynamic;      /* 1: waves take work items from an atomic cursor; 0: static */
   uint32_t stage_words;  /* staged kernels: LDS words for a held set (bitset range / 32, or
                             list length), at most 1024; 0 means 1024 */
+  uint32_t xcds;         /* static schedule: blocks are dealt round-robin to this many L2
+                            domains (8 on MI355X); each then takes a contiguous slice of
+                            every window of work items.  0 or 1: no remapping */
 } eh_tuning;
 
 eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t);

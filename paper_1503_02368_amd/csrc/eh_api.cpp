@@ -84,7 +84,11 @@ eh_status upload(Ctx* c, DevBuf& b, const void* src, size_t bytes, const char* w
 
 void free_trie_device(Trie& t) {
   Ctx* c = t.ctx;
-  for (auto& p : t.plans) dev_free(c, p->items);
+  for (auto& p : t.plans) {
+    dev_free(c, p->items);
+    dev_free(c, p->sdesc);
+    dev_free(c, p->rec);
+  }
   t.plans.clear();
   dev_free(c, t.vdesc);
   dev_free(c, t.col);
@@ -147,6 +151,7 @@ LaunchArgs base_args(Ctx* c, const Trie& t) {
   a.group_lanes = c->tune.group_lanes;
   a.dmax = t.host.dmax;
   a.stage_words = c->tune.stage_words;
+  a.xcds = c->tune.xcds;
   return a;
 }
 
@@ -157,7 +162,11 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
   a.items = static_cast<const Item*>(p->items.p) + i0;
   a.n_items = i1 - i0;
   a.idx = static_cast<const uint32_t*>(t.col.p);
-  if (p->staging == EH_STAGE_TARGET) a.tin = static_cast<const uint2*>(t.tin_d.p);
+  if (p->staging == EH_STAGE_TARGET) {
+    a.tin = static_cast<const uint2*>(t.tin_d.p);
+    if (p->sdesc.p) a.sdesc = static_cast<const uint4*>(p->sdesc.p) + i0;
+    a.rec = static_cast<const uint4*>(p->rec.p);
+  }
   a.acc = acc;
   a.tag_base = tag_base;
   a.per_root = per_root;
@@ -322,6 +331,7 @@ eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t) {
     return EH_EINVAL;
   }
   u.stage_words = t->stage_words;
+  u.xcds = t->xcds;
   return EH_OK;
 }
 
@@ -338,6 +348,7 @@ eh_status eh_ctx_get_tuning(const eh_ctx* ctx, eh_tuning* out) {
   out->use_bitsets = u.use_bitsets;
   out->dynamic = u.dynamic;
   out->stage_words = u.stage_words;
+  out->xcds = u.xcds;
   return EH_OK;
 }
 

@@ -378,7 +378,7 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
   if (pattern == EH_4CLIQUE) staging = EH_STAGE_SOURCE;
   for (auto& p : t->plans) {
     if (p->pattern == pattern && p->staging == staging && p->chunk_work == chunk &&
-        p->use_bitsets == tu.use_bitsets) {
+        p->use_bitsets == tu.use_bitsets && p->stage_words == tu.stage_words) {
       *out = p.get();
       return EH_OK;
     }
@@ -390,6 +390,7 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
   plan->staging = staging;
   plan->chunk_work = chunk;
   plan->use_bitsets = tu.use_bitsets;
+  plan->stage_words = tu.stage_words;
   plan->g_item_off.assign(size_t(h.n_graphs) + 1, 0);
   const bool ub = tu.use_bitsets != 0;
   if (staging == EH_STAGE_TARGET) {
@@ -445,6 +446,57 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
       dev_free(c, plan->items);
       return st;
     }
+  if (staging == EH_STAGE_TARGET && pattern == EH_TRIANGLE) {
+    // Resolve on the host what each wave would otherwise look up through
+    // chains of dependent loads: the staged set's extent per item, and per
+    // in-edge u->v the streamed part of N+(u) above v (elements, or bitset
+    // words when fewer and v's set will be held as a bitmap).
+    const uint32_t cap = tu.stage_words && tu.stage_words < kStageWords ? tu.stage_words
+                                                                         : kStageWords;
+    auto staged_lo_al = [&](uint32_t v) { return h.col[h.row[v]] & ~31u; };
+    auto bitmap_mode = [&](uint32_t v) {
+      const uint32_t lo_al = staged_lo_al(v), hi = h.col[h.row[v + 1] - 1];
+      return hi - lo_al < cap * 32u;
+    };
+    std::vector<uint32_t> sd(4 * std::max<size_t>(items.size(), 1), 0);
+    for (size_t i = 0; i < items.size(); ++i) {
+      const uint32_t v = items[i].s;
+      sd[4 * i] = h.row[v];
+      sd[4 * i + 1] = h.row[v + 1] - h.row[v];
+      sd[4 * i + 2] = h.col[h.row[v]];
+      sd[4 * i + 3] = h.col[h.row[v + 1] - 1];
+    }
+    std::vector<uint32_t> rec(4 * std::max<uint64_t>(h.m, 1), 0);
+    for (uint64_t k = 0; k < h.m; ++k) {
+      const uint32_t u = t->tin[2 * k], e = t->tin[2 * k + 1], v = h.col[e];
+      const uint32_t len = h.row[u + 1] - e - 1;
+      uint32_t sb = e + 1, n = len;
+      int32_t sm = 0;
+      if (ub && len && h.bs_off[u] != kNoBitset && h.row[v + 1] > h.row[v] && bitmap_mode(v)) {
+        const uint32_t w0 = (v + 1 - h.bs_base[u]) >> 5;
+        const uint32_t nw = w0 < h.bs_nw[u] ? h.bs_nw[u] - w0 : 0u;
+        if (nw < len) {
+          sb = (uint32_t(h.m) + h.bs_off[u] + w0) | kHiBit;
+          n = nw;
+          sm = int32_t((h.bs_base[u] >> 5) + w0) - int32_t(staged_lo_al(v) >> 5);
+        }
+      }
+      rec[4 * k] = sb;
+      rec[4 * k + 1] = n;
+      rec[4 * k + 2] = uint32_t(sm);
+    }
+    if ((st = dev_alloc(c, plan->sdesc, sizeof(uint32_t) * sd.size())) != EH_OK ||
+        (st = dev_alloc(c, plan->rec, sizeof(uint32_t) * rec.size())) != EH_OK ||
+        (st = hip_check(c, hipMemcpy(plan->sdesc.p, sd.data(), sizeof(uint32_t) * sd.size(),
+                                     hipMemcpyHostToDevice), "upload stage table")) != EH_OK ||
+        (st = hip_check(c, hipMemcpy(plan->rec.p, rec.data(), sizeof(uint32_t) * rec.size(),
+                                     hipMemcpyHostToDevice), "upload segment records")) != EH_OK) {
+      dev_free(c, plan->items);
+      dev_free(c, plan->sdesc);
+      dev_free(c, plan->rec);
+      return st;
+    }
+  }
   *out = plan.get();
   t->plans.push_back(std::move(plan));
   return EH_OK;

@@ -22,6 +22,7 @@ namespace eh {
 constexpr uint32_t kNoBitset = 0xFFFFFFFFu;
 constexpr uint32_t kHiBit = 0x80000000u;   // vdesc.y: the set also has a bitset
 constexpr uint32_t kMaxIndex = 0x7FFFFFFFu;  // offsets must stay below 2^31
+constexpr uint32_t kStageWords = 1024;        // LDS words per wave for a staged set
 
 // One unit of scheduled work: the set N+(s) is held on chip while the sets
 // N+(t) of the streamed vertices t = idx[lbeg .. lbeg+llen) are intersected
@@ -81,6 +82,7 @@ struct Tuning {
   uint32_t use_bitsets = 1;
   uint32_t dynamic = 0;
   uint32_t stage_words = 0;
+  uint32_t xcds = 0;
 };
 
 struct Ctx;
@@ -97,8 +99,14 @@ struct Plan {
   uint32_t staging = 0;
   uint32_t chunk_work = 0;
   uint32_t use_bitsets = 0;
+  uint32_t stage_words = 0;
   uint64_t n_items = 0;
   DevBuf items;
+  // target staging only: per item {begin, length, min, max} of the staged set,
+  // and per in-edge the streamed segment {start | kHiBit for words, length,
+  // word offset from the staged bitmap, 0}
+  DevBuf sdesc;
+  DevBuf rec;
   std::vector<uint64_t> g_item_off;  // batch: items of graph g are [off[g], off[g+1])
 };
 
@@ -153,6 +161,8 @@ struct LaunchArgs {
   uint64_t n_items = 0;
   const uint32_t* idx = nullptr;       // streamed vertex list (source staging)
   const uint2* tin = nullptr;          // in-edges (target staging), else null
+  const uint4* sdesc = nullptr;        // per item staged-set descriptor, or null
+  const uint4* rec = nullptr;          // per in-edge segment record, or null
   const uint2* vdesc = nullptr;
   const uint32_t* col = nullptr;
   const uint4* bsdesc = nullptr;
@@ -169,6 +179,7 @@ struct LaunchArgs {
   uint32_t group_lanes = 0;
   uint32_t dmax = 0;
   uint32_t stage_words = 0;            // 0: kernel maximum
+  uint32_t xcds = 0;                   // L2 domains for the static schedule remap
 };
 eh_status launch_fill_u64(Ctx* c, hipStream_t s, unsigned long long* p, uint64_t n,
                           unsigned long long v);

@@ -45,6 +45,8 @@ struct DevArgs {
   uint64_t n_items;
   const uint32_t* idx;
   const uint2* tin;  // target staging: in-edges {u, position of the edge in col}
+  const uint4* sdesc;  // per item {begin, length, min, max} of the staged set, or null
+  const uint4* rec;    // per in-edge streamed segment {start, length, word delta, 0}, or null
   const uint2* vdesc;
   const uint32_t* col;
   const uint4* bsdesc;
@@ -59,6 +61,7 @@ struct DevArgs {
   uint32_t algo;
   float gamma;
   uint32_t stage_words;  // <= the kernel's region size
+  uint32_t xcds;
 };
 
 DevArgs to_dev(const LaunchArgs& a) {
@@ -67,6 +70,8 @@ DevArgs to_dev(const LaunchArgs& a) {
   d.n_items = a.n_items;
   d.idx = a.idx;
   d.tin = a.tin;
+  d.sdesc = a.sdesc;
+  d.rec = a.rec;
   d.vdesc = a.vdesc;
   d.col = a.col;
   d.bsdesc = a.bsdesc;
@@ -81,6 +86,7 @@ DevArgs to_dev(const LaunchArgs& a) {
   d.algo = a.algo;
   d.gamma = a.gamma;
   d.stage_words = a.stage_words;
+  d.xcds = a.xcds;
   return d;
 }
 
@@ -141,8 +147,18 @@ struct ItemIter {
     dyn = a.dynamic != 0;
     cursor = a.cursor;
     step = uint64_t(gridDim.x) * wpb;
-    if (dyn) i = fetch();
-    else i = uint64_t(blockIdx.x) * wpb + (threadIdx.x >> 6);
+    if (dyn) {
+      i = fetch();
+    } else {
+      // Blocks are dealt round-robin to the L2 domains (XCDs): block b runs on
+      // domain b % x.  Renumbering them so each domain holds a contiguous range
+      // of logical blocks gives each domain a contiguous slice of every window
+      // of items, whose streamed sets overlap, instead of every x-th block.
+      uint32_t b = blockIdx.x;
+      const uint32_t x = a.xcds, nb = gridDim.x;
+      if (x > 1 && nb % x == 0) b = (b % x) * (nb / x) + b / x;
+      i = uint64_t(b) * wpb + (threadIdx.x >> 6);
+    }
   }
   __device__ uint64_t fetch() {
     uint32_t v = 0;
@@ -173,17 +189,18 @@ struct Staged {
   uint32_t beg, len, lo, hi, lo_al, mode;
 };
 
-// Loads N+(s) into region R (RW words) and returns how it is held.
+// Loads the set col[beg .. beg+len) with known min lo and max hi into region
+// R (RW words) and returns how it is held.
 template <int RW>
-__device__ __forceinline__ Staged stage_set(const DevArgs& a, uint32_t s, uint32_t* R,
-                                            uint32_t lane) {
+__device__ __forceinline__ Staged stage_extent(const DevArgs& a, uint32_t beg, uint32_t len,
+                                               uint32_t lo, uint32_t hi, uint32_t* R,
+                                               uint32_t lane) {
   Staged st;
-  const uint2 sd = a.vdesc[s];
-  st.beg = uniform(sd.x);
-  st.len = uniform(sd.y & kMaxIndex);
+  st.beg = beg;
+  st.len = len;
   if (st.len == 0) { st.mode = kModeGlobal; st.lo = st.hi = st.lo_al = 0; return st; }
-  st.lo = uniform(a.col[st.beg]);
-  st.hi = uniform(a.col[st.beg + st.len - 1]);
+  st.lo = lo;
+  st.hi = hi;
   st.lo_al = st.lo & ~31u;
   const uint32_t cap = (a.stage_words && a.stage_words < uint32_t(RW)) ? a.stage_words : uint32_t(RW);
   if (st.hi - st.lo_al < cap * 32u) st.mode = kModeBitmap;
@@ -199,6 +216,16 @@ __device__ __forceinline__ Staged stage_set(const DevArgs& a, uint32_t s, uint32
   }
   wave_sync();
   return st;
+}
+
+// Loads N+(s) into region R, looking up its extent.
+template <int RW>
+__device__ __forceinline__ Staged stage_set(const DevArgs& a, uint32_t s, uint32_t* R,
+                                            uint32_t lane) {
+  const uint2 sd = a.vdesc[s];
+  const uint32_t beg = uniform(sd.x), len = uniform(sd.y & kMaxIndex);
+  if (len == 0) return stage_extent<RW>(a, beg, 0, 0, 0, R, lane);
+  return stage_extent<RW>(a, beg, len, uniform(a.col[beg]), uniform(a.col[beg + len - 1]), R, lane);
 }
 
 // Returns region R to all-zero after stage_set.
@@ -406,14 +433,30 @@ __global__ __launch_bounds__(WPB * kWave) void k_tri_staged(DevArgs a) {
   unsigned long long acc = 0;
   uint32_t cur_tag = 0;
   bool have_tag = false;
-  for (ItemIter it(a, WPB); it.i < a.n_items; it.next()) {
-    const Item item = a.items[it.i];
+  ItemIter it(a, WPB);
+  // the next item (and its staged-set descriptor) is loaded one item ahead
+  Item nitem{0, 0, 0, 0};
+  uint4 nsd{0, 0, 0, 0};
+  if (it.i < a.n_items) {
+    nitem = a.items[it.i];
+    if (a.sdesc) nsd = a.sdesc[it.i];
+  }
+  while (it.i < a.n_items) {
+    const Item item = nitem;
+    const uint4 sd = nsd;
+    it.next();
+    if (it.i < a.n_items) {
+      nitem = a.items[it.i];
+      if (a.sdesc) nsd = a.sdesc[it.i];
+    }
     const uint32_t s = uniform(item.s), lbeg = uniform(item.lbeg), llen = uniform(item.llen);
     const uint32_t tag = uniform(item.tag);
     if (have_tag && tag != cur_tag) flush_tag(a, acc, cur_tag, lane);
     cur_tag = tag;
     have_tag = true;
-    const Staged st = stage_set<RW>(a, s, R, lane);
+    const Staged st = a.sdesc ? stage_extent<RW>(a, uniform(sd.x), uniform(sd.y), uniform(sd.z),
+                                                 uniform(sd.w), R, lane)
+                              : stage_set<RW>(a, s, R, lane);
     if (st.len == 0) continue;
     const bool bitmap_ok = a.use_bitsets && st.mode == kModeBitmap;
     uint32_t cnt = 0;
@@ -421,7 +464,11 @@ __global__ __launch_bounds__(WPB * kWave) void k_tri_staged(DevArgs a) {
       const uint32_t nseg = min(uint32_t(kSeg), llen - b0);
       Seg g{0, 0, 0};
       if (lane < nseg) {
-        if (a.tin) {
+        if (a.rec) {
+          // resolved at plan time: one load per streamed set
+          const uint4 r = a.rec[lbeg + b0 + lane];
+          g = Seg{r.x, r.y, int32_t(r.z)};
+        } else if (a.tin) {
           const uint2 ie = a.tin[lbeg + b0 + lane];  // in-edge u -> s at position ie.y
           g = seg_suffix(a, ie.x, ie.y, s, bitmap_ok, st.lo_al);
         } else {
@@ -642,10 +689,10 @@ __global__ void k_scatter_roots(const unsigned long long* by_rank, const uint32_
 }
 
 constexpr int kTriWPB = 4;
-constexpr int kTriRW = 1024;  // 32768-bit staging range, or 1024-entry list
-constexpr int kTriU = 4;
+constexpr int kTriRW = int(kStageWords);  // 32768-bit staging range, or 1024-entry list
+constexpr int kTriU = 8;
 constexpr int kK4WPB = 2;
-constexpr int kK4RW = 1024;
+constexpr int kK4RW = int(kStageWords);
 constexpr int kK4U = 2;
 constexpr int kPairWPB = 4;
 
@@ -653,6 +700,9 @@ uint32_t grid_for(Ctx* c, uint64_t n_items, uint32_t wpb, uint32_t waves_per_cu)
   uint64_t want = (uint64_t(c->n_cu) * std::max<uint32_t>(waves_per_cu, wpb) + wpb - 1) / wpb;
   const uint64_t need = (n_items + wpb - 1) / wpb;
   if (want > need) want = need;
+  // a multiple of the L2-domain count keeps the block renumbering a bijection
+  const uint64_t x = c->tune.xcds;
+  if (x > 1 && want > x) want -= want % x;
   if (want < 1) want = 1;
   return uint32_t(std::min<uint64_t>(want, 1u << 20));
 }

@@ -54,7 +54,7 @@ class _Tuning(ctypes.Structure):
                 ("gamma", ctypes.c_float), ("chunk_work", ctypes.c_uint32),
                 ("waves_per_cu", ctypes.c_uint32), ("group_lanes", ctypes.c_uint32),
                 ("use_bitsets", ctypes.c_uint32), ("dynamic", ctypes.c_uint32),
-                ("stage_words", ctypes.c_uint32)]
+                ("stage_words", ctypes.c_uint32), ("xcds", ctypes.c_uint32)]
 
 
 class _BuildOpts(ctypes.Structure):
