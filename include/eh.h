@@ -219,6 +219,13 @@ eh_status eh_poll(eh_server* srv, uint64_t ticket, uint64_t* count, eh_req_stats
 /* Blocks until the ticket is done (or timeout_ms passes: EH_PENDING). */
 eh_status eh_wait(eh_server* srv, uint64_t ticket, uint32_t timeout_ms, uint64_t* count,
                   eh_req_stats* stats);
+/* Completion queue: waits up to timeout_ms until at least one request has
+ * finished, then retires up to cap finished requests in completion order,
+ * writing tickets[i], counts[i] and (if stats is not NULL) stats[i] for
+ * i < *n_out.  *n_out = 0 on timeout.  Requests already retired by eh_poll or
+ * eh_wait are skipped. */
+eh_status eh_server_drain(eh_server* srv, uint32_t cap, uint32_t timeout_ms, uint64_t* tickets,
+                          uint64_t* counts, eh_req_stats* stats, uint32_t* n_out);
 /* Finishes admitted work, cancels queued requests, joins the thread. */
 eh_status eh_server_destroy(eh_server* srv);
 

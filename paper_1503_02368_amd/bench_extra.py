@@ -261,26 +261,31 @@ def serve_run(ctx, eh, trie, reqs, mode):
 
     th = threading.Thread(target=submitter)
     th.start()
-    pending = set(range(n))
+    # completions arrive through the server's completion queue; a ticket can
+    # come back before the submitter thread has recorded it, so results are
+    # matched to requests lazily
+    by_ticket = {}
+    results = {}
+    recorded = 0  # requests are submitted in order
+    left = n
     last = time.monotonic()
-    while pending:
+    while left:
         if time.monotonic() - last > 120.0:
             srv.close()
-            raise RuntimeError(f"served run made no progress for 120 s ({len(pending)} pending)")
-        progressed = False
-        for i in list(pending):
-            if tickets[i] is None:
-                continue
-            res = srv.poll(tickets[i])
-            if res is not None:
-                due = start_ns[0] + int(reqs[i].t_arrival * 1e9)
-                lat[i] = (res.t_done_ns - due) / 1e9
-                counts[i] = res.count
-                pending.discard(i)
-                progressed = True
-                last = time.monotonic()
-        if not progressed:
-            time.sleep(100e-6)
+            raise RuntimeError(f"served run made no progress for 120 s ({left} pending)")
+        for t, res in srv.drain(1024, 20):
+            results[t] = res
+            last = time.monotonic()
+        while recorded < n and tickets[recorded] is not None:
+            by_ticket[tickets[recorded]] = recorded
+            recorded += 1
+        for t in [t for t in results if t in by_ticket]:
+            res = results.pop(t)
+            i = by_ticket[t]
+            due = start_ns[0] + int(reqs[i].t_arrival * 1e9)
+            lat[i] = (res.t_done_ns - due) / 1e9
+            counts[i] = res.count
+            left -= 1
     th.join()
     srv.close()
     return lat, counts

@@ -372,6 +372,18 @@ void make_items_source(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chu
   }
 }
 
+void make_items_estimated(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chunk_work,
+                          uint32_t pattern, std::vector<Item>& out) {
+  const uint32_t du = out_deg(h, u);
+  if (du < (pattern == EH_4CLIQUE ? 3u : 2u)) return;
+  // each out-neighbour's streamed work is taken to be about |N+(u)| (more
+  // for the 4-clique's second level), so only d+(u) is read
+  const uint64_t per = pattern == EH_4CLIQUE ? uint64_t(du) * 25 + 2 : uint64_t(du) + 2;
+  const uint32_t slice = uint32_t(std::max<uint64_t>(1, chunk_work / per));
+  for (uint32_t i = 0; i < du; i += slice)
+    out.push_back(Item{u, h.row[u] + i, std::min(slice, du - i), tag});
+}
+
 eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** out) {
   const Tuning& tu = c->tune;
   const uint32_t chunk = std::max<uint32_t>(tu.chunk_work, 64);

@@ -154,6 +154,9 @@ eh_status ensure_pinned(Ctx* c, size_t n);
 eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** out);
 void make_items_source(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chunk_work,
                        uint32_t pattern, bool use_bitsets, std::vector<Item>& out);
+// Same items cut from out-degrees alone: O(1 + items) per root.
+void make_items_estimated(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chunk_work,
+                          uint32_t pattern, std::vector<Item>& out);
 
 // Device launches (eh_kernels.hip).  All enqueue on `stream`.
 struct LaunchArgs {

@@ -183,80 +183,119 @@ __device__ __forceinline__ void flush_tag(const DevArgs& a, unsigned long long& 
 // Staged set: state shared by the triangle and 4-clique kernels
 // ---------------------------------------------------------------------------
 
-enum : uint32_t { kModeBitmap = 0, kModeList = 1, kModeGlobal = 2 };
+// How a set is held on chip.
+//  Bitmap:    one bitset over [base, base + 32 cap) covering the whole set
+//             (the bitset layout of section 4.1, block = the set's range).
+//  Composite: the set's range is too wide: the bitset covers the top window
+//             [base, hi] and the plen members below base (a sorted prefix of
+//             the set) are searched, in the wave's prefix list when at most
+//             kPrefixCap long, else in HBM -- a two-block instance of the
+//             block-level composite layout of section 4.3, dense block on top
+//             because degree order puts the dense hub neighbourhoods there.
+//  List:      a sorted list of len ids in R, searched (4-clique level 2).
+//  Empty:     nothing.
+enum : uint32_t { kModeBitmap = 0, kModeComposite = 1, kModeList = 2, kModeEmpty = 3 };
+constexpr int kPrefixCap = 128;
 
 struct Staged {
-  uint32_t beg, len, lo, hi, lo_al, mode;
+  uint32_t beg, len, lo, hi, base, plen, mode;
 };
 
 // Loads the set col[beg .. beg+len) with known min lo and max hi into region
-// R (RW words) and returns how it is held.
+// R (RW words) and prefix list Lp, and returns how it is held.
 template <int RW>
 __device__ __forceinline__ Staged stage_extent(const DevArgs& a, uint32_t beg, uint32_t len,
-                                               uint32_t lo, uint32_t hi, uint32_t* R,
+                                               uint32_t lo, uint32_t hi, uint32_t* R, uint32_t* Lp,
                                                uint32_t lane) {
   Staged st;
   st.beg = beg;
   st.len = len;
-  if (st.len == 0) { st.mode = kModeGlobal; st.lo = st.hi = st.lo_al = 0; return st; }
+  st.plen = 0;
+  if (st.len == 0) { st.mode = kModeEmpty; st.lo = st.hi = st.base = 0; return st; }
   st.lo = lo;
   st.hi = hi;
-  st.lo_al = st.lo & ~31u;
   const uint32_t cap = (a.stage_words && a.stage_words < uint32_t(RW)) ? a.stage_words : uint32_t(RW);
-  if (st.hi - st.lo_al < cap * 32u) st.mode = kModeBitmap;
-  else if (st.len <= cap) st.mode = kModeList;
-  else st.mode = kModeGlobal;
-  if (st.mode == kModeBitmap) {
-    for (uint32_t k = lane; k < st.len; k += kWave) {
-      const uint32_t d = a.col[st.beg + k] - st.lo_al;
-      atomicOr(&R[d >> 5], 1u << (d & 31));
-    }
-  } else if (st.mode == kModeList) {
-    for (uint32_t k = lane; k < st.len; k += kWave) R[k] = a.col[st.beg + k];
+  const uint32_t lo_al = lo & ~31u;
+  if (hi - lo_al < cap * 32u) {
+    st.mode = kModeBitmap;
+    st.base = lo_al;
+  } else {
+    // top window: hi - base < 32 cap, base a multiple of 32, base > lo
+    st.mode = kModeComposite;
+    st.base = (hi + 1u - cap * 32u + 31u) & ~31u;
   }
+  uint32_t below = 0;
+  for (uint32_t k0 = 0; k0 < st.len; k0 += kWave) {
+    const uint32_t k = k0 + lane;
+    bool low = false;
+    if (k < st.len) {
+      const uint32_t x = a.col[st.beg + k];
+      low = x < st.base;
+      if (!low) {
+        const uint32_t d = x - st.base;
+        atomicOr(&R[d >> 5], 1u << (d & 31));
+      } else if (k < uint32_t(kPrefixCap)) {
+        Lp[k] = x;
+      }
+    }
+    below += uint32_t(__popcll(__ballot(low)));
+  }
+  st.plen = below;
   wave_sync();
   return st;
 }
 
-// Loads N+(s) into region R, looking up its extent.
+// Loads N+(s), looking up its extent.
 template <int RW>
 __device__ __forceinline__ Staged stage_set(const DevArgs& a, uint32_t s, uint32_t* R,
-                                            uint32_t lane) {
+                                            uint32_t* Lp, uint32_t lane) {
   const uint2 sd = a.vdesc[s];
   const uint32_t beg = uniform(sd.x), len = uniform(sd.y & kMaxIndex);
-  if (len == 0) return stage_extent<RW>(a, beg, 0, 0, 0, R, lane);
-  return stage_extent<RW>(a, beg, len, uniform(a.col[beg]), uniform(a.col[beg + len - 1]), R, lane);
+  if (len == 0) return stage_extent<RW>(a, beg, 0, 0, 0, R, Lp, lane);
+  return stage_extent<RW>(a, beg, len, uniform(a.col[beg]), uniform(a.col[beg + len - 1]), R, Lp,
+                          lane);
 }
 
-// Returns region R to all-zero after stage_set.
+// Returns region R to all-zero after stage_extent (the prefix list needs no
+// clearing: only its first plen entries are ever read).
 template <int RW>
 __device__ __forceinline__ void unstage_set(const DevArgs& a, const Staged& st, uint32_t* R,
                                             uint32_t lane) {
   wave_sync();
-  if (st.mode == kModeBitmap) {
-    for (uint32_t k = lane; k < st.len; k += kWave) R[(a.col[st.beg + k] - st.lo_al) >> 5] = 0;
-  } else if (st.mode == kModeList) {
-    for (uint32_t k = lane; k < st.len; k += kWave) R[k] = 0;
+  if (st.mode == kModeBitmap || st.mode == kModeComposite) {
+    for (uint32_t k = st.plen + lane; k < st.len; k += kWave)
+      R[(a.col[st.beg + k] - st.base) >> 5] = 0;
   }
   wave_sync();
 }
 
-// Membership of x in the staged set (uint & bitset probe, or galloping search).
+// Membership of x in the composite set's prefix (below the window).
+__device__ __forceinline__ uint32_t prefix_has(const DevArgs& a, const Staged& st,
+                                               const uint32_t* Lp, uint32_t x) {
+  if (x < st.lo || x >= st.base) return 0u;
+  if (st.plen <= uint32_t(kPrefixCap)) {
+    const uint32_t p = lower_bound_lds(Lp, st.plen, x);
+    return (p < st.plen && Lp[p] == x) ? 1u : 0u;
+  }
+  const uint32_t* L = a.col + st.beg;
+  const uint32_t p = lower_bound_glb(L, st.plen, x);
+  return (p < st.plen && L[p] == x) ? 1u : 0u;
+}
+
+// Membership of x in the staged set: a bit probe (uint & bitset, section
+// 4.2), else a search of the prefix or of the list (galloping regime).
 template <int RW>
 __device__ __forceinline__ uint32_t staged_has(const DevArgs& a, const Staged& st,
-                                               const uint32_t* R, uint32_t x) {
-  if (st.mode == kModeBitmap) {
-    const uint32_t d = x - st.lo_al;
-    return d < uint32_t(RW) * 32u ? (R[d >> 5] >> (d & 31)) & 1u : 0u;
-  }
-  if (x < st.lo || x > st.hi) return 0u;
+                                               const uint32_t* R, const uint32_t* Lp, uint32_t x) {
   if (st.mode == kModeList) {
+    if (x < st.lo || x > st.hi) return 0u;
     const uint32_t p = lower_bound_lds(R, st.len, x);
     return R[p] == x ? 1u : 0u;
   }
-  const uint32_t* L = a.col + st.beg;
-  const uint32_t p = lower_bound_glb(L, st.len, x);
-  return L[p] == x ? 1u : 0u;
+  if (st.mode == kModeEmpty) return 0u;
+  const uint32_t d = x - st.base;
+  if (d < uint32_t(RW) * 32u) return (R[d >> 5] >> (d & 31)) & 1u;
+  return st.mode == kModeComposite ? prefix_has(a, st, Lp, x) : 0u;
 }
 
 // Segment table of one flat batch: P = prefix of lengths (kSeg+1),
@@ -275,19 +314,34 @@ struct Seg {
   int32_t sm;
 };
 
-// The whole set N+(t).  Bitset words are used only against a staged bitmap,
-// and only when they are fewer than the set's elements.
-__device__ __forceinline__ Seg seg_full(const DevArgs& a, uint32_t t, bool bitmap_ok,
-                                        uint32_t lo_al) {
+// When a streamed set may be read as bitset words against the staged set:
+// the staged set has a bitmap, and no word can hold a member of a composite
+// set's searched prefix (every word starts at or above the window base).
+struct WordRule {
+  bool ok;        // use_bitsets and the staged set has a bitmap
+  uint32_t base;  // bitmap base id
+  uint32_t wmin;  // lowest id a streamed word may start at (0 for a plain bitmap)
+};
+
+__device__ __forceinline__ WordRule word_rule(const DevArgs& a, const Staged& st) {
+  WordRule r;
+  r.ok = a.use_bitsets && (st.mode == kModeBitmap || st.mode == kModeComposite);
+  r.base = st.base;
+  r.wmin = st.mode == kModeComposite ? st.base : 0u;
+  return r;
+}
+
+// The whole set N+(t), as elements or, when fewer, as bitset words.
+__device__ __forceinline__ Seg seg_full(const DevArgs& a, uint32_t t, const WordRule& wr) {
   const uint2 td = a.vdesc[t];
   const uint32_t tl = td.y & kMaxIndex;
   Seg g{td.x, tl, 0};
-  if (bitmap_ok && (td.y & kHiBit)) {
+  if (wr.ok && (td.y & kHiBit)) {
     const uint4 bd = a.bsdesc[t];
-    if (bd.z < tl) {
+    if (bd.z < tl && bd.y >= wr.wmin) {
       g.sb = bd.x | kHiBit;
       g.len = bd.z;
-      g.sm = int32_t(bd.y >> 5) - int32_t(lo_al >> 5);
+      g.sm = int32_t(bd.y >> 5) - int32_t(wr.base >> 5);
     }
   }
   return g;
@@ -297,18 +351,18 @@ __device__ __forceinline__ Seg seg_full(const DevArgs& a, uint32_t t, bool bitma
 // position e: only these elements can lie in N+(v), all of whose members
 // exceed v.  As bitset words: from the word holding v+1 to the last.
 __device__ __forceinline__ Seg seg_suffix(const DevArgs& a, uint32_t u, uint32_t e, uint32_t v,
-                                          bool bitmap_ok, uint32_t lo_al) {
+                                          const WordRule& wr) {
   const uint2 ud = a.vdesc[u];
   const uint32_t end = ud.x + (ud.y & kMaxIndex);
   Seg g{e + 1, end - e - 1, 0};
-  if (bitmap_ok && (ud.y & kHiBit) && g.len) {
+  if (wr.ok && (ud.y & kHiBit) && g.len) {
     const uint4 bd = a.bsdesc[u];
     const uint32_t w0 = (v + 1 - bd.y) >> 5;  // v >= base since v is in the set
     const uint32_t nw = w0 < bd.z ? bd.z - w0 : 0u;
-    if (nw < g.len) {
+    if (nw < g.len && bd.y + 32u * w0 >= wr.wmin) {
       g.sb = (bd.x + w0) | kHiBit;
       g.len = nw;
-      g.sm = int32_t((bd.y >> 5) + w0) - int32_t(lo_al >> 5);
+      g.sm = int32_t((bd.y >> 5) + w0) - int32_t(wr.base >> 5);
     }
   }
   return g;
@@ -356,45 +410,56 @@ struct SegCursor {
 
 // Walks flat indices lane, lane+64, ... < E of the segment table and counts
 // the elements found in the staged set.  Against a staged bitmap every
-// element costs the same: a uint value x tests bit x - lo_al, a bitset word
-// is ANDed with the bitmap word it overlaps, both as popc(R[w] & mask).
-template <int RW, int U>
-__device__ __forceinline__ uint32_t flat_probe(const DevArgs& a, const SegTab& T, uint32_t E,
-                                               const Staged& st, const uint32_t* R,
-                                               uint32_t lane) {
+// element costs the same: a uint value x tests bit x - base, a bitset word
+// is ANDed with the bitmap word it overlaps, both as popc(R[w] & mask).  A
+// composite set's members below its window are found by searching its prefix.
+template <int RW, int U, bool kComposite>
+__device__ __forceinline__ uint32_t flat_probe_bits(const DevArgs& a, const SegTab& T, uint32_t E,
+                                                    const Staged& st, const uint32_t* R,
+                                                    const uint32_t* Lp, uint32_t lane) {
   const uint32_t* __restrict__ L = a.col;
   uint32_t cnt = 0;
   SegCursor c(T);
-  if (st.mode == kModeBitmap) {
-    const uint32_t lo_al = st.lo_al;
-    for (uint32_t f0 = 0; f0 < E; f0 += kWave * U) {
-      uint32_t val[U], key[U];
-      bool ok[U], bits[U];
+  const uint32_t base = st.base;
+  for (uint32_t f0 = 0; f0 < E; f0 += kWave * U) {
+    uint32_t val[U], key[U];
+    bool ok[U], bits[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t f = f0 + uint32_t(u) * kWave + lane;
-        ok[u] = f < E;
-        val[u] = 0;
-        key[u] = 0;
-        bits[u] = false;
-        if (ok[u]) {
-          c.seek(T, f);
-          val[u] = L[c.base + f];
-          key[u] = c.wbase + f;
-          bits[u] = c.bits;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t d = val[u] - lo_al;
-        const uint32_t w = bits[u] ? key[u] : (d >> 5);
-        const uint32_t m = bits[u] ? val[u] : (1u << (d & 31));
-        if (ok[u] && w < uint32_t(RW)) cnt += __popc(R[w] & m);
+    for (int u = 0; u < U; ++u) {
+      const uint32_t f = f0 + uint32_t(u) * kWave + lane;
+      ok[u] = f < E;
+      val[u] = 0;
+      key[u] = 0;
+      bits[u] = false;
+      if (ok[u]) {
+        c.seek(T, f);
+        val[u] = L[c.base + f];
+        key[u] = c.wbase + f;
+        bits[u] = c.bits;
       }
     }
-    return cnt;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t d = val[u] - base;
+      const uint32_t w = bits[u] ? key[u] : (d >> 5);
+      const uint32_t m = bits[u] ? val[u] : (1u << (d & 31));
+      if (ok[u] && w < uint32_t(RW)) cnt += __popc(R[w] & m);
+      else if (kComposite && ok[u] && !bits[u]) cnt += prefix_has(a, st, Lp, val[u]);
+    }
   }
-  // staged list or global list: uint elements only, searched
+  return cnt;
+}
+
+template <int RW, int U>
+__device__ __forceinline__ uint32_t flat_probe(const DevArgs& a, const SegTab& T, uint32_t E,
+                                               const Staged& st, const uint32_t* R,
+                                               const uint32_t* Lp, uint32_t lane) {
+  if (st.mode == kModeBitmap) return flat_probe_bits<RW, U, false>(a, T, E, st, R, Lp, lane);
+  if (st.mode == kModeComposite) return flat_probe_bits<RW, U, true>(a, T, E, st, R, Lp, lane);
+  const uint32_t* __restrict__ L = a.col;
+  uint32_t cnt = 0;
+  SegCursor c(T);
+  // list: uint elements only, searched
   for (uint32_t f0 = 0; f0 < E; f0 += kWave * U) {
     uint32_t val[U];
     bool ok[U];
@@ -410,7 +475,7 @@ __device__ __forceinline__ uint32_t flat_probe(const DevArgs& a, const SegTab& T
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (ok[u]) cnt += staged_has<RW>(a, st, R, val[u]);
+      if (ok[u]) cnt += staged_has<RW>(a, st, R, Lp, val[u]);
   }
   return cnt;
 }
@@ -425,8 +490,10 @@ __global__ __launch_bounds__(WPB * kWave) void k_tri_staged(DevArgs a) {
   __shared__ uint32_t s_pre[WPB][kSeg + 1];
   __shared__ uint32_t s_sb[WPB][kSeg];
   __shared__ int32_t s_sm[WPB][kSeg];
+  __shared__ uint32_t s_pref[WPB][kPrefixCap];
   const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
   uint32_t* R = s_region[wid];
+  uint32_t* Lp = s_pref[wid];
   const SegTab T{s_pre[wid], s_sb[wid], s_sm[wid]};
   for (uint32_t k = lane; k < uint32_t(RW); k += kWave) R[k] = 0;
   wave_sync();
@@ -455,10 +522,10 @@ __global__ __launch_bounds__(WPB * kWave) void k_tri_staged(DevArgs a) {
     cur_tag = tag;
     have_tag = true;
     const Staged st = a.sdesc ? stage_extent<RW>(a, uniform(sd.x), uniform(sd.y), uniform(sd.z),
-                                                 uniform(sd.w), R, lane)
-                              : stage_set<RW>(a, s, R, lane);
+                                                 uniform(sd.w), R, Lp, lane)
+                              : stage_set<RW>(a, s, R, Lp, lane);
     if (st.len == 0) continue;
-    const bool bitmap_ok = a.use_bitsets && st.mode == kModeBitmap;
+    const WordRule wr = word_rule(a, st);
     uint32_t cnt = 0;
     for (uint32_t b0 = 0; b0 < llen; b0 += kSeg) {
       const uint32_t nseg = min(uint32_t(kSeg), llen - b0);
@@ -470,13 +537,13 @@ __global__ __launch_bounds__(WPB * kWave) void k_tri_staged(DevArgs a) {
           g = Seg{r.x, r.y, int32_t(r.z)};
         } else if (a.tin) {
           const uint2 ie = a.tin[lbeg + b0 + lane];  // in-edge u -> s at position ie.y
-          g = seg_suffix(a, ie.x, ie.y, s, bitmap_ok, st.lo_al);
+          g = seg_suffix(a, ie.x, ie.y, s, wr);
         } else {
-          g = seg_full(a, a.idx[lbeg + b0 + lane], bitmap_ok, st.lo_al);
+          g = seg_full(a, a.idx[lbeg + b0 + lane], wr);
         }
       }
       const uint32_t E = publish_segments(T, g, lane);
-      cnt += flat_probe<RW, U>(a, T, E, st, R, lane);
+      cnt += flat_probe<RW, U>(a, T, E, st, R, Lp, lane);
     }
     acc += cnt;
     if (a.per_root) {
@@ -502,10 +569,12 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
   __shared__ uint32_t s_pre[WPB][kSeg + 1];
   __shared__ uint32_t s_sb[WPB][kSeg];
   __shared__ int32_t s_sm[WPB][kSeg];
+  __shared__ uint32_t s_pref[WPB][kPrefixCap];
   const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
   uint32_t* A = s_A[wid];
   uint32_t* B = s_B[wid];
   uint32_t* S = s_S[wid];
+  uint32_t* Lp = s_pref[wid];
   const SegTab T{s_pre[wid], s_sb[wid], s_sm[wid]};
   for (uint32_t k = lane; k < uint32_t(RW); k += kWave) { A[k] = 0; B[k] = 0; }
   wave_sync();
@@ -520,56 +589,63 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
     if (have_tag && tag != cur_tag) flush_tag(a, acc, cur_tag, lane);
     cur_tag = tag;
     have_tag = true;
-    const Staged su = stage_set<RW>(a, u, A, lane);
+    const Staged su = stage_set<RW>(a, u, A, Lp, lane);
     if (su.len == 0) continue;
+    const bool su_bits = su.mode == kModeBitmap || su.mode == kModeComposite;
     uint32_t cnt = 0;
     for (uint32_t q = 0; q < llen; ++q) {
       const uint32_t v = uniform(a.idx[lbeg + q]);
       const uint2 vd = a.vdesc[v];
       const uint32_t vb = uniform(vd.x), vl = uniform(vd.y & kMaxIndex);
-      // level 1: S = N+(u) & N+(v), compacted in ascending order
+      // level 1: S = N+(u) & N+(v), compacted in ascending order; members at
+      // or above the window base also go into bitmap B (same base as A)
       uint32_t ns = 0;
+      bool low = false;  // a member of S lies below the window base
       for (uint32_t k0 = 0; k0 < vl; k0 += kWave) {
         const uint32_t k = k0 + lane;
         uint32_t x = 0, hit = 0;
         if (k < vl) {
           x = a.col[vb + k];
-          hit = staged_has<RW>(a, su, A, x);
+          hit = staged_has<RW>(a, su, A, Lp, x);
         }
         const unsigned long long m = __ballot(hit);
         if (hit) {
           S[ns + __popcll(m & lt_mask)] = x;
-          if (su.mode == kModeBitmap) {
-            const uint32_t d = x - su.lo_al;
+          if (su_bits && x >= su.base) {
+            const uint32_t d = x - su.base;
             atomicOr(&B[d >> 5], 1u << (d & 31));
           }
         }
+        low = low || __ballot(hit && x < su.base) != 0ull;
         ns += uint32_t(__popcll(m));
       }
       wave_sync();
       if (ns >= 2) {
-        // level 2: sum over w in S of |S & N+(w)|
+        // level 2: sum over w in S of |S & N+(w)|, against bitmap B when it
+        // holds all of S, else by searching the sorted list S
         Staged ss;
         ss.beg = 0;
         ss.len = ns;
         ss.lo = S[0];
         ss.hi = S[ns - 1];
-        ss.lo_al = su.lo_al;
-        ss.mode = su.mode == kModeBitmap ? kModeBitmap : kModeList;
-        const uint32_t* probe = su.mode == kModeBitmap ? B : S;
-        const bool bitmap_ok = a.use_bitsets && ss.mode == kModeBitmap;
+        ss.plen = 0;
+        ss.base = su.base;
+        ss.mode = (su_bits && !low) ? kModeBitmap : kModeList;
+        const uint32_t* probe = ss.mode == kModeBitmap ? B : S;
+        const WordRule wr = word_rule(a, ss);
         for (uint32_t b0 = 0; b0 < ns; b0 += kSeg) {
           const uint32_t nseg = min(uint32_t(kSeg), ns - b0);
           Seg g{0, 0, 0};
-          if (lane < nseg) g = seg_full(a, S[b0 + lane], bitmap_ok, ss.lo_al);
+          if (lane < nseg) g = seg_full(a, S[b0 + lane], wr);
           const uint32_t E = publish_segments(T, g, lane);
           // bitmap bounds are B's (RW words); the list S is searched by length
-          cnt += flat_probe<RW, U>(a, T, E, ss, probe, lane);
+          cnt += flat_probe<RW, U>(a, T, E, ss, probe, Lp, lane);
         }
       }
       wave_sync();
-      if (su.mode == kModeBitmap)
-        for (uint32_t i = lane; i < ns; i += kWave) B[(S[i] - su.lo_al) >> 5] = 0;
+      if (su_bits)
+        for (uint32_t i = lane; i < ns; i += kWave)
+          if (S[i] >= su.base) B[(S[i] - su.base) >> 5] = 0;
       wave_sync();
     }
     acc += cnt;

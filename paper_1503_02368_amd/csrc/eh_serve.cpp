@@ -68,6 +68,10 @@ struct Server {
   bool stop = false;
   std::string fatal;  // first device error; every later request fails
   std::thread th;
+  std::deque<std::shared_ptr<Request>> done;  // finished, in completion order
+  std::mutex stamp_mu;                        // root de-duplication
+  std::vector<uint32_t> stamp;
+  uint32_t epoch = 0;
 
   void run();
   bool step();
@@ -173,6 +177,7 @@ bool Server::step() {
         footprint -= r->footprint;
         free_slots.push_back(r->slot);
         std::vector<Item>().swap(r->items);
+        done.push_back(r);
       } else {
         keep.push_back(r);
       }
@@ -257,6 +262,17 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
     return st;
   }
   for (uint32_t i = s.o.max_active; i-- > 0;) s.free_slots.push_back(i);
+  try {
+    s.stamp.assign(t->host.n, 0u);
+  } catch (const std::bad_alloc&) {
+    dev_free(c, s.items_d);
+    dev_free(c, s.acc_d);
+    (void)hipHostFree(s.items_h);
+    (void)hipHostFree(s.acc_h);
+    (void)hipStreamDestroy(s.stream);
+    delete x;
+    return EH_ENOMEM;
+  }
   s.th = std::thread([&s] { s.run(); });
   *out = x;
   return EH_OK;
@@ -271,17 +287,25 @@ eh_status eh_submit(eh_server* srv, int pattern, const uint32_t* roots, uint32_t
   auto r = std::make_shared<Request>();
   r->pattern = pattern;
   r->stats.t_submit_ns = now_ns();
-  std::vector<uint32_t> rk;
-  rk.reserve(n_roots);
-  for (uint32_t i = 0; i < n_roots; ++i) {
+  for (uint32_t i = 0; i < n_roots; ++i)
     if (roots[i] >= h.n) return EH_EINVAL;
-    rk.push_back(h.rank[roots[i]]);
+  // roots are a set: drop repeats with a stamp per vertex (O(n_roots)), then
+  // cut each root's out-list into items whose size is estimated from its
+  // out-degree alone, so a submit costs time proportional to its roots
+  const uint32_t chunk = std::max<uint32_t>(s.c->tune.chunk_work, 64);
+  {
+    std::lock_guard<std::mutex> lk(s.stamp_mu);
+    if (++s.epoch == 0) {
+      std::fill(s.stamp.begin(), s.stamp.end(), 0u);
+      s.epoch = 1;
+    }
+    for (uint32_t i = 0; i < n_roots; ++i) {
+      const uint32_t u = h.rank[roots[i]];
+      if (s.stamp[u] == s.epoch) continue;
+      s.stamp[u] = s.epoch;
+      make_items_estimated(h, u, 0, chunk, uint32_t(pattern), r->items);
+    }
   }
-  std::sort(rk.begin(), rk.end());
-  rk.erase(std::unique(rk.begin(), rk.end()), rk.end());
-  const uint32_t chunk = s.c->tune.chunk_work;
-  const bool ub = s.c->tune.use_bitsets != 0;
-  for (uint32_t u : rk) make_items_source(h, u, 0, chunk, uint32_t(pattern), ub, r->items);
   r->stats.items = r->items.size();
   r->footprint = sizeof(Item) * r->items.size() + sizeof(uint64_t);
   if (r->footprint > s.o.hbm_budget_bytes) return EH_ENOMEM;
@@ -297,6 +321,7 @@ eh_status eh_submit(eh_server* srv, int pattern, const uint32_t* roots, uint32_t
       // no instance can be rooted here: done without device work
       r->finished = true;
       r->stats.t_admit_ns = r->stats.t_done_ns = now_ns();
+      s.done.push_back(r);
     } else {
       s.queue.push_back(r);
     }
@@ -340,6 +365,35 @@ eh_status eh_wait(eh_server* srv, uint64_t ticket, uint32_t timeout_ms, uint64_t
     if (s.cv_done.wait_until(lk, deadline) == std::cv_status::timeout) {
       return take_result(s, ticket, count, stats);
     }
+  }
+}
+
+eh_status eh_server_drain(eh_server* srv, uint32_t cap, uint32_t timeout_ms, uint64_t* tickets,
+                          uint64_t* counts, eh_req_stats* stats, uint32_t* n_out) {
+  if (!srv || !tickets || !counts || !n_out || cap == 0) return EH_EINVAL;
+  Server& s = srv->s;
+  std::unique_lock<std::mutex> lk(s.mu);
+  *n_out = 0;
+  const auto deadline = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms);
+  for (;;) {
+    uint32_t n = 0;
+    while (n < cap && !s.done.empty()) {
+      std::shared_ptr<Request> r = s.done.front();
+      s.done.pop_front();
+      auto itr = s.by_ticket.find(r->ticket);
+      if (itr == s.by_ticket.end()) continue;  // already retired by eh_poll / eh_wait
+      s.by_ticket.erase(itr);
+      tickets[n] = r->ticket;
+      counts[n] = r->count;
+      if (stats) stats[n] = r->stats;
+      ++n;
+    }
+    if (n > 0) {
+      *n_out = n;
+      return s.fatal.empty() ? EH_OK : EH_EHIP;
+    }
+    if (!s.fatal.empty()) return EH_EHIP;
+    if (s.cv_done.wait_until(lk, deadline) == std::cv_status::timeout) return EH_OK;
   }
 }
 

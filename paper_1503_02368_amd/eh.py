@@ -32,7 +32,7 @@ SYMBOLS = [
     "eh_ctx_set_tuning", "eh_ctx_get_tuning", "eh_build_trie", "eh_build_batch",
     "eh_trie_info_get", "eh_trie_free", "eh_count_triangles", "eh_count_4cliques",
     "eh_count_async", "eh_count_add_async", "eh_count_rooted", "eh_count_batch", "eh_count_batch_async",
-    "eh_server_create", "eh_submit", "eh_poll", "eh_wait", "eh_server_destroy",
+    "eh_server_create", "eh_submit", "eh_poll", "eh_wait", "eh_server_drain", "eh_server_destroy",
     "eh_host_trie_build", "eh_host_trie_info", "eh_host_trie_arrays", "eh_host_trie_free",
 ]
 
@@ -119,6 +119,8 @@ def load():
             "eh_submit": [_vp, ctypes.c_int, _u32p, ctypes.c_uint32, _u64p],
             "eh_poll": [_vp, ctypes.c_uint64, _u64p, ctypes.POINTER(_ReqStats)],
             "eh_wait": [_vp, ctypes.c_uint64, ctypes.c_uint32, _u64p, ctypes.POINTER(_ReqStats)],
+            "eh_server_drain": [_vp, ctypes.c_uint32, ctypes.c_uint32, _u64p, _u64p,
+                                ctypes.POINTER(_ReqStats), ctypes.POINTER(ctypes.c_uint32)],
             "eh_server_destroy": [_vp],
             "eh_host_trie_build": [_u32p, _u32p, ctypes.c_uint64, ctypes.c_uint32,
                                    ctypes.POINTER(_BuildOpts), ctypes.POINTER(_vp)],
@@ -407,6 +409,20 @@ class Server:
         s = _ReqStats()
         return self._result(self._lib.eh_wait(self._h, int(ticket), int(timeout_ms), ctypes.byref(c),
                                               ctypes.byref(s)), c, s)
+
+    def drain(self, cap: int = 1024, timeout_ms: int = 10):
+        """Finished requests in completion order: a list of (ticket, ReqResult)."""
+        t = np.zeros(cap, np.uint64)
+        c = np.zeros(cap, np.uint64)
+        s = (_ReqStats * cap)()
+        n = ctypes.c_uint32(0)
+        st = self._lib.eh_server_drain(self._h, int(cap), int(timeout_ms), _p64(t), _p64(c), s,
+                                       ctypes.byref(n))
+        if st != EH_OK:
+            raise EHError(st, "drain: " + self._lib.eh_status_str(st).decode())
+        return [(int(t[i]), ReqResult(int(c[i]), int(s[i].t_submit_ns), int(s[i].t_admit_ns),
+                                      int(s[i].t_done_ns), int(s[i].items)))
+                for i in range(n.value)]
 
     def close(self):
         if self._h:

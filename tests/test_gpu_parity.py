@@ -294,3 +294,35 @@ def test_full_size_rmat20_triangles(ctx, eh):
             assert got == T, tname
     finally:
         trie.free()
+
+
+def test_server_drain(ctx, eh):
+    """Completion-queue retrieval returns every request once, with exact counts."""
+    tune(ctx)
+    el = inputs.rmat(12, 16, seed=41)
+    g = oracle.Graph.from_edgelist(el)
+    rt = g.triangles(rooted=True)["root"]
+    rk = g.cliques4(rooted=True)["root"]
+    trie = ctx.build_edgelist(el)
+    reqs = inputs.request_stream(el.n, rate_qps=2000, duration_s=0.05, seed=9, log2_lo=1, log2_hi=11)
+    srv = ctx.server(trie, step_items=256)
+    try:
+        want = {}
+        for r in reqs:
+            t = srv.submit(r.pattern, r.roots)
+            want[t] = oracle.rooted_count(rt if r.pattern == 3 else rk, r.roots)
+        # one request retired by poll/wait must not come back from drain
+        t0 = next(iter(want))
+        assert srv.wait(t0).count == want.pop(t0)
+        got = {}
+        deadline = 200
+        while len(got) < len(want) and deadline:
+            for t, res in srv.drain(16, 50):
+                assert t not in got
+                got[t] = res.count
+            deadline -= 1
+        assert got == want
+        assert srv.drain(8, 1) == []
+    finally:
+        srv.close()
+        trie.free()
