@@ -103,12 +103,16 @@ typedef struct eh_tuning {
   uint32_t waves_per_cu; /* persistent waves per compute unit (0: keep) */
   uint32_t group_lanes;  /* pairwise: lanes per pair, 4..64 power of two; 0: by size bins */
   uint32_t use_bitsets;  /* 1: dense sets are read through their bitset layout */
-  uint32_t dynamic;      /* 1: waves take work items from an atomic cursor; 0: static */
+  uint32_t dynamic;      /* schedule: 0 static interleave (item i to wave i mod waves),
+                            1 waves take items from an atomic cursor (work stealing),
+                            2 static blocks (each wave one contiguous range of items) */
   uint32_t stage_words;  /* staged kernels: LDS words for a held set (bitset range / 32, or
                             list length), at most 1024; 0 means 1024 */
   uint32_t xcds;         /* static schedule: blocks are dealt round-robin to this many L2
                             domains (8 on MI355X); each then takes a contiguous slice of
                             every window of work items.  0 or 1: no remapping */
+  uint32_t unroll;       /* staged triangle kernel: streamed elements in flight per lane,
+                            4 (more waves per CU) or 8; 0 means 8 */
 } eh_tuning;
 
 eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t);

@@ -26,7 +26,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tuning.json")
 
 BASE = dict(kernel=1, staging=2, algo=0, gamma=32.0, chunk_work=4096, waves_per_cu=32,
-            group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0)
+            group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0, xcds=0, unroll=8)
 
 
 def log(*a):
@@ -101,9 +101,18 @@ def tune_graph(el, pattern, layouts, ctx, torch, quick=False):
                     local = (ms, cfg)
             # refine the schedule of the best kernel on this layout
             chunks = [1024, 4096, 16384] if quick else [1024, 2048, 4096, 8192, 16384, 32768, 65536]
-            waves = [16, 32] if quick else [8, 16, 24, 32]
-            for ch, wv in itertools.product(chunks, waves):
-                cfg = dict(local[1], chunk_work=ch, waves_per_cu=wv)
+            waves = [16, 32] if quick else [8, 16, 24, 32, 40]
+            words = [0, 512] if pattern == 4 else [0]
+            unrolls = [4, 8] if pattern == 3 and local[1]["kernel"] == 1 else [8]
+            for ch, wv, sw, un in itertools.product(chunks, waves, words, unrolls):
+                cfg = dict(local[1], chunk_work=ch, waves_per_cu=wv, stage_words=sw, unroll=un)
+                ctx.set_tuning(**cfg)
+                ms, c = timer.graph(trie, pattern)
+                S.record(dict(layout=layout, tau=tau, tuning=cfg), ms, c)
+                if local is None or ms < local[0]:
+                    local = (ms, cfg)
+            for dyn in (1, 2):
+                cfg = dict(local[1], dynamic=dyn)
                 ctx.set_tuning(**cfg)
                 ms, c = timer.graph(trie, pattern)
                 S.record(dict(layout=layout, tau=tau, tuning=cfg), ms, c)
@@ -126,8 +135,10 @@ def tune_batch(b, pattern, layouts, ctx, torch, quick=False):
         trie = ctx.build_batch(b, layout=layout, tau=tau)
         try:
             chunks = [1024, 4096, 16384] if quick else [512, 1024, 2048, 4096, 8192, 16384]
-            for st, ch, wv in itertools.product([2, 1], chunks, [16, 32]):
-                cfg = dict(BASE, staging=st, chunk_work=ch, waves_per_cu=wv)
+            kinds = [dict(staging=2), dict(staging=1)]
+            kinds += [dict(kernel=2, group_lanes=g, algo=al) for g in (4, 8, 16) for al in (0, 1)]
+            for k, ch, wv, dyn in itertools.product(kinds, chunks, [16, 32], [0, 2]):
+                cfg = dict(BASE, **k, chunk_work=ch, waves_per_cu=wv, dynamic=dyn)
                 ctx.set_tuning(**cfg)
                 s = ctx.stream
                 ctx.count_batch_async(trie, pattern, 0, G, out)

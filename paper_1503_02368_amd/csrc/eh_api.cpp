@@ -152,6 +152,7 @@ LaunchArgs base_args(Ctx* c, const Trie& t) {
   a.dmax = t.host.dmax;
   a.stage_words = c->tune.stage_words;
   a.xcds = c->tune.xcds;
+  a.unroll = c->tune.unroll;
   return a;
 }
 
@@ -171,7 +172,7 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
   a.tag_base = tag_base;
   a.per_root = per_root;
   eh_status st;
-  if (a.dynamic)
+  if (a.dynamic == 1)
     if ((st = launch_fill_u64(c, c->stream, static_cast<unsigned long long*>(c->cursor.p), 1, 0)) !=
         EH_OK)
       return st;
@@ -325,13 +326,22 @@ eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t) {
   if (t->waves_per_cu) u.waves_per_cu = t->waves_per_cu;
   u.group_lanes = t->group_lanes;
   u.use_bitsets = t->use_bitsets ? 1 : 0;
-  u.dynamic = t->dynamic ? 1 : 0;
+  if (t->dynamic > 2) {
+    ctx->c.err = "dynamic must be 0 (interleaved), 1 (atomic cursor) or 2 (blocked)";
+    return EH_EINVAL;
+  }
+  u.dynamic = t->dynamic;
   if (t->stage_words > 1024) {
     ctx->c.err = "stage_words must be at most 1024";
     return EH_EINVAL;
   }
   u.stage_words = t->stage_words;
   u.xcds = t->xcds;
+  if (t->unroll != 0 && t->unroll != 4 && t->unroll != 8) {
+    ctx->c.err = "unroll must be 0, 4 or 8";
+    return EH_EINVAL;
+  }
+  u.unroll = t->unroll ? t->unroll : 8;
   return EH_OK;
 }
 
@@ -349,6 +359,7 @@ eh_status eh_ctx_get_tuning(const eh_ctx* ctx, eh_tuning* out) {
   out->dynamic = u.dynamic;
   out->stage_words = u.stage_words;
   out->xcds = u.xcds;
+  out->unroll = u.unroll;
   return EH_OK;
 }
 

@@ -83,6 +83,7 @@ struct Tuning {
   uint32_t dynamic = 0;
   uint32_t stage_words = 0;
   uint32_t xcds = 0;
+  uint32_t unroll = 8;
 };
 
 struct Ctx;
@@ -183,6 +184,7 @@ struct LaunchArgs {
   uint32_t dmax = 0;
   uint32_t stage_words = 0;            // 0: kernel maximum
   uint32_t xcds = 0;                   // L2 domains for the static schedule remap
+  uint32_t unroll = 8;                 // staged triangle kernel: 4 or 8
 };
 eh_status launch_fill_u64(Ctx* c, hipStream_t s, unsigned long long* p, uint64_t n,
                           unsigned long long v);

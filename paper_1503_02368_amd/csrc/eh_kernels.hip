@@ -139,27 +139,42 @@ __device__ __forceinline__ uint32_t lower_bound_glb(const uint32_t* __restrict__
 }
 
 // Work-item iteration: static interleave or an atomic cursor.
+// Schedules (DevArgs.dynamic): 0 interleaved (item i to wave i mod W),
+// 1 atomic cursor (work stealing), 2 blocked (wave w takes one contiguous
+// range of items, so consecutive items of one graph or request share a wave).
 struct ItemIter {
-  uint64_t i, step;
+  uint64_t i, step, end;
   bool dyn;
   uint32_t* cursor;
   __device__ ItemIter(const DevArgs& a, uint32_t wpb) {
-    dyn = a.dynamic != 0;
+    dyn = a.dynamic == 1;
     cursor = a.cursor;
-    step = uint64_t(gridDim.x) * wpb;
+    end = a.n_items;
     if (dyn) {
+      step = 0;
       i = fetch();
+      return;
+    }
+    // Blocks are dealt round-robin to the L2 domains (XCDs): block b runs on
+    // domain b % x.  Renumbering them so each domain holds a contiguous range
+    // of logical blocks gives each domain a contiguous slice of every window
+    // of items, whose streamed sets overlap, instead of every x-th block.
+    uint32_t b = blockIdx.x;
+    const uint32_t x = a.xcds, nb = gridDim.x;
+    if (x > 1 && nb % x == 0) b = (b % x) * (nb / x) + b / x;
+    const uint64_t w = uint64_t(b) * wpb + (threadIdx.x >> 6);
+    const uint64_t nw = uint64_t(gridDim.x) * wpb;
+    if (a.dynamic == 2) {
+      const uint64_t per = (a.n_items + nw - 1) / nw;
+      i = w * per;
+      end = i + per < a.n_items ? i + per : a.n_items;
+      step = 1;
     } else {
-      // Blocks are dealt round-robin to the L2 domains (XCDs): block b runs on
-      // domain b % x.  Renumbering them so each domain holds a contiguous range
-      // of logical blocks gives each domain a contiguous slice of every window
-      // of items, whose streamed sets overlap, instead of every x-th block.
-      uint32_t b = blockIdx.x;
-      const uint32_t x = a.xcds, nb = gridDim.x;
-      if (x > 1 && nb % x == 0) b = (b % x) * (nb / x) + b / x;
-      i = uint64_t(b) * wpb + (threadIdx.x >> 6);
+      i = w;
+      step = nw;
     }
   }
+  __device__ bool more() const { return i < end; }
   __device__ uint64_t fetch() {
     uint32_t v = 0;
     if ((threadIdx.x & 63) == 0) v = atomicAdd(cursor, 1u);
@@ -485,7 +500,9 @@ __device__ __forceinline__ uint32_t flat_probe(const DevArgs& a, const SegTab& T
 // ---------------------------------------------------------------------------
 
 template <int WPB, int RW, int U>
-__global__ __launch_bounds__(WPB * kWave) void k_tri_staged(DevArgs a) {
+// at least 6 waves per SIMD: the LDS budget allows 7 blocks of 4 waves per CU
+__global__ __launch_bounds__(WPB * kWave) __attribute__((amdgpu_waves_per_eu(6)))
+void k_tri_staged(DevArgs a) {
   __shared__ uint32_t s_region[WPB][RW];
   __shared__ uint32_t s_pre[WPB][kSeg + 1];
   __shared__ uint32_t s_sb[WPB][kSeg];
@@ -504,15 +521,15 @@ __global__ __launch_bounds__(WPB * kWave) void k_tri_staged(DevArgs a) {
   // the next item (and its staged-set descriptor) is loaded one item ahead
   Item nitem{0, 0, 0, 0};
   uint4 nsd{0, 0, 0, 0};
-  if (it.i < a.n_items) {
+  if (it.more()) {
     nitem = a.items[it.i];
     if (a.sdesc) nsd = a.sdesc[it.i];
   }
-  while (it.i < a.n_items) {
+  while (it.more()) {
     const Item item = nitem;
     const uint4 sd = nsd;
     it.next();
-    if (it.i < a.n_items) {
+    if (it.more()) {
       nitem = a.items[it.i];
       if (a.sdesc) nsd = a.sdesc[it.i];
     }
@@ -582,7 +599,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
   unsigned long long acc = 0;
   uint32_t cur_tag = 0;
   bool have_tag = false;
-  for (ItemIter it(a, WPB); it.i < a.n_items; it.next()) {
+  for (ItemIter it(a, WPB); it.more(); it.next()) {
     const Item item = a.items[it.i];
     const uint32_t u = uniform(item.s), lbeg = uniform(item.lbeg), llen = uniform(item.llen);
     const uint32_t tag = uniform(item.tag);
@@ -594,9 +611,14 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
     const bool su_bits = su.mode == kModeBitmap || su.mode == kModeComposite;
     uint32_t cnt = 0;
     for (uint32_t q = 0; q < llen; ++q) {
+      // S lies in N+(v) and in the part of N+(u) after v: with fewer than two
+      // members in either, no 4-clique extends (u, v)
+      const uint32_t after = su.beg + su.len - (lbeg + q) - 1;
+      if (after < 2) break;  // later v have even fewer
       const uint32_t v = uniform(a.idx[lbeg + q]);
       const uint2 vd = a.vdesc[v];
       const uint32_t vb = uniform(vd.x), vl = uniform(vd.y & kMaxIndex);
+      if (vl < 2) continue;
       // level 1: S = N+(u) & N+(v), compacted in ascending order; members at
       // or above the window base also go into bitmap B (same base as A)
       uint32_t ns = 0;
@@ -734,7 +756,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_tri_pairwise(DevArgs a) {
   unsigned long long acc = 0;
   uint32_t cur_tag = 0;
   bool have_tag = false;
-  for (ItemIter it(a, WPB); it.i < a.n_items; it.next()) {
+  for (ItemIter it(a, WPB); it.more(); it.next()) {
     const Item item = a.items[it.i];
     const uint32_t s = uniform(item.s), lbeg = uniform(item.lbeg), llen = uniform(item.llen);
     const uint32_t tag = uniform(item.tag);
@@ -825,8 +847,12 @@ eh_status launch_triangles(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t
     return hip_check(c, hipGetLastError(), "pairwise triangle kernel launch");
   }
   const uint32_t grid = grid_for(c, la.n_items, kTriWPB, waves_per_cu);
-  hipLaunchKernelGGL((k_tri_staged<kTriWPB, kTriRW, kTriU>), dim3(grid), dim3(kTriWPB * kWave), 0,
-                     s, a);
+  if (la.unroll == 4)
+    hipLaunchKernelGGL((k_tri_staged<kTriWPB, kTriRW, 4>), dim3(grid), dim3(kTriWPB * kWave), 0, s,
+                       a);
+  else
+    hipLaunchKernelGGL((k_tri_staged<kTriWPB, kTriRW, kTriU>), dim3(grid), dim3(kTriWPB * kWave), 0,
+                       s, a);
   return hip_check(c, hipGetLastError(), "staged triangle kernel launch");
 }
 
@@ -836,13 +862,21 @@ eh_status launch_4cliques(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t 
   const DevArgs a = to_dev(la);
   const uint32_t grid = grid_for(c, la.n_items, kK4WPB, waves_per_cu);
   const dim3 blk(kK4WPB * kWave);
-  if (la.dmax <= 512)
-    hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 512, kK4U>), dim3(grid), blk, 0, s, a);
-  else if (la.dmax <= 1024)
-    hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 1024, kK4U>), dim3(grid), blk, 0, s, a);
-  else if (la.dmax <= 2048)
+  // stage_words in (0, 512]: the half-size LDS instance (more waves per CU)
+  const bool half = la.stage_words > 0 && la.stage_words <= kK4RW / 2;
+  if (la.dmax <= 512) {
+    if (half)
+      hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW / 2, 512, kK4U>), dim3(grid), blk, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 512, kK4U>), dim3(grid), blk, 0, s, a);
+  } else if (la.dmax <= 1024) {
+    if (half)
+      hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW / 2, 1024, kK4U>), dim3(grid), blk, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 1024, kK4U>), dim3(grid), blk, 0, s, a);
+  } else if (la.dmax <= 2048) {
     hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 2048, kK4U>), dim3(grid), blk, 0, s, a);
-  else {
+  } else {
     c->err = "4-clique kernel supports out-degrees up to 2048";
     return EH_EOVERFLOW;
   }

@@ -102,6 +102,7 @@ eh_status server_launch(Server* s, const std::vector<Item>& v, uint64_t off, int
   a.dmax = t.host.dmax;
   a.stage_words = c->tune.stage_words;
   a.xcds = c->tune.xcds;
+  a.unroll = c->tune.unroll;
   if (pattern == EH_4CLIQUE) return launch_4cliques(c, s->stream, a, c->tune.kernel, c->tune.waves_per_cu);
   return launch_triangles(c, s->stream, a, c->tune.kernel, c->tune.waves_per_cu);
 }

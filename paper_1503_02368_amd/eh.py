@@ -54,7 +54,8 @@ class _Tuning(ctypes.Structure):
                 ("gamma", ctypes.c_float), ("chunk_work", ctypes.c_uint32),
                 ("waves_per_cu", ctypes.c_uint32), ("group_lanes", ctypes.c_uint32),
                 ("use_bitsets", ctypes.c_uint32), ("dynamic", ctypes.c_uint32),
-                ("stage_words", ctypes.c_uint32), ("xcds", ctypes.c_uint32)]
+                ("stage_words", ctypes.c_uint32), ("xcds", ctypes.c_uint32),
+                ("unroll", ctypes.c_uint32)]
 
 
 class _BuildOpts(ctypes.Structure):
@@ -219,7 +220,10 @@ class Context:
 
             @ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
             def _f(_self, ptr, _s):
-                torch.cuda.caching_allocator_delete(ptr)
+                try:
+                    torch.cuda.caching_allocator_delete(ptr)
+                except Exception:
+                    pass  # interpreter shutdown: torch is already gone, so is the memory
 
             self._alloc = _Allocator(_a, _f, None)
             alloc_p = ctypes.byref(self._alloc)

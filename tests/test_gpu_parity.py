@@ -63,12 +63,13 @@ def truth(el):
 TUNINGS = {
     "staged_target": dict(kernel=1, staging=2, use_bitsets=1, dynamic=0, stage_words=0),
     "staged_source": dict(kernel=1, staging=1, use_bitsets=1, dynamic=1, stage_words=0),
-    "staged_nobits": dict(kernel=1, staging=2, use_bitsets=0, dynamic=0, stage_words=0),
+    "staged_nobits": dict(kernel=1, staging=2, use_bitsets=0, dynamic=2, stage_words=0),
+    "staged_half": dict(kernel=1, staging=1, use_bitsets=1, dynamic=2, stage_words=512),
     "staged_list": dict(kernel=1, staging=2, use_bitsets=1, dynamic=0, stage_words=8),
     "staged_global": dict(kernel=1, staging=1, use_bitsets=1, dynamic=1, stage_words=1),
     "pair_auto": dict(kernel=2, algo=0, use_bitsets=1, group_lanes=0, dynamic=0),
     "pair_merge4": dict(kernel=2, algo=1, use_bitsets=0, group_lanes=4, dynamic=1),
-    "pair_search16": dict(kernel=2, algo=2, use_bitsets=0, group_lanes=16, dynamic=0),
+    "pair_search16": dict(kernel=2, algo=2, use_bitsets=0, group_lanes=16, dynamic=2),
     "pair_merge64": dict(kernel=2, algo=1, use_bitsets=1, group_lanes=64, dynamic=0),
 }
 DEFAULT = dict(kernel=1, staging=2, algo=0, gamma=32.0, chunk_work=4096, waves_per_cu=32,
@@ -100,7 +101,8 @@ def test_triangles_zoo(ctx, eh, tname, lay):
 
 
 @pytest.mark.parametrize("lay", LAYOUTS[:3], ids=lambda x: x[0])
-@pytest.mark.parametrize("tname", ["staged_source", "staged_nobits", "staged_list", "staged_global"])
+@pytest.mark.parametrize("tname", ["staged_source", "staged_nobits", "staged_list", "staged_global",
+                                   "staged_half"])
 def test_4cliques_zoo(ctx, eh, tname, lay):
     tune(ctx, **TUNINGS[tname])
     for el in ZOO:
