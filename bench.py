@@ -185,6 +185,8 @@ def main():
     ap.add_argument("--rates", default="200,1000,5000", help="served: arrival rates (QPS)")
     ap.add_argument("--duration", type=float, default=3.0, help="served: seconds per rate")
     ap.add_argument("--max-requests", type=int, default=3000, help="served: cap per rate")
+    ap.add_argument("--no-per-instance", action="store_true",
+                    help="batch: skip the one-launch-per-graph comparison (for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("this engine runs on one GPU; no multi-GPU path exists (use --gpus 1)", file=sys.stderr)

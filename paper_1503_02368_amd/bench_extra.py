@@ -75,6 +75,18 @@ def bench_batch(name, w, args, ctx, eh, torch, metric):
     ms = e0.elapsed_time(e1) / args.steps
     one = out.cpu().numpy().view(np.uint64).copy()
     log(f"[bench] one launch: {ms:.3f} ms per pass")
+    if getattr(args, "no_per_instance", False):
+        trie.free()
+        achieved = info["b_merge"] / (ms / 1e3) / 1e9
+        return {"metric": metric, "value": info["m_plus"] / (ms / 1e3), "unit": "edges/s",
+                "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+                "data": "synthetic (seeded generator)",
+                "config": {"workload": name, "graphs": G, "m_plus": info["m_plus"]},
+                "count_total": int(one.sum(dtype=np.uint64)),
+                "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                             "frac": achieved / 8000.0, "traffic": None,
+                             "algorithmic_bytes_per_launch": info["b_merge"], "model": "B_merge"}}
     # one launch per graph, eager
     per = torch.zeros(G, dtype=torch.int64, device="cuda")
     for i in range(min(G, 64)):

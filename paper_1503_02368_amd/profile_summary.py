@@ -1,0 +1,142 @@
+"""Summarises rocprofv3 CSV output for one kernel into profiles/.
+
+Reads a kernel-trace/stats directory and counter directories written by
+``rocprofv3 -f csv``, scales FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by
+what the same counters report for a plain copy of known size, and writes
+
+* a Markdown summary (commands, kernel statistics, counters, traffic), and
+* an entry in profiles/traffic.json: HBM bytes per launch of the kernel,
+  tagged with the hash of the kernel source so that bench.py drops it once
+  the kernel changes.
+
+    python -m paper_1503_02368_amd.profile_summary --workload rmat20_triangles \\
+        --kernel k_tri_staged --trace D --fetch D --write D --copy-fetch D \\
+        --copy-write D [--counters D ...] --copy-mib 1024 --commands FILE --out profiles/X.md
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+KERNEL_SRC = os.path.join(HERE, "csrc", "eh_kernels.hip")
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _csv(d: str, suffix: str):
+    files = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not files:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    rows = []
+    for p in files:
+        with open(p) as f:
+            rows += list(csv.DictReader(f))
+    return rows
+
+
+def counters(d: str, name_part: str):
+    """{counter: mean value per dispatch} over dispatches whose kernel name contains name_part."""
+    acc = {}
+    for r in _csv(d, "counter_collection.csv"):
+        if name_part in r["Kernel_Name"]:
+            acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return {k: (statistics.fmean(v), len(v)) for k, v in acc.items()}
+
+
+def kernel_stats(d: str):
+    return _csv(d, "kernel_stats.csv")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--kernel", required=True, help="substring of the kernel's symbol name")
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--copy-fetch", required=True)
+    ap.add_argument("--copy-write", required=True)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--counters", action="append", default=[])
+    ap.add_argument("--commands", required=True, help="text file with the commands that made the data")
+    ap.add_argument("--algorithmic-bytes", type=float, default=0.0)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    args = ap.parse_args()
+
+    stats = kernel_stats(args.trace)
+    mine = [r for r in stats if args.kernel in r["Name"]]
+    if not mine:
+        raise SystemExit(f"kernel {args.kernel} not in {args.trace}")
+    k = mine[0]
+    avg_us = float(k["AverageNs"]) / 1e3
+    known_kib = args.copy_mib * 1024.0
+    cf = counters(args.copy_fetch, "copyBuffer")["FETCH_SIZE"][0]
+    cw = counters(args.copy_write, "copyBuffer")["WRITE_SIZE"][0]
+    f_fac, w_fac = known_kib / cf, known_kib / cw
+    fk, fn = counters(args.fetch, args.kernel)["FETCH_SIZE"]
+    wk, wn = counters(args.write, args.kernel)["WRITE_SIZE"]
+    traffic = (fk * f_fac + wk * w_fac) * 1024.0
+    extra = {}
+    for d in args.counters:
+        for name, (v, n) in counters(d, args.kernel).items():
+            extra[name] = (v, n)
+
+    with open(args.commands) as f:
+        cmds = f.read().strip()
+    lines = [f"# {args.kernel} on {args.workload}", "",
+             "Commands (from the repository root, one MI355X):", "", "```", cmds, "```", "",
+             "## Kernel statistics (rocprofv3 --kernel-trace --stats)", "",
+             "| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |",
+             "|---|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs'])/1e3:.3f} | "
+                     f"{float(r['MinNs'])/1e3:.3f} | {float(r['MaxNs'])/1e3:.3f} | {float(r['Percentage']):.2f} % |")
+    lines += ["", "## Memory traffic (per dispatch of the kernel)", "",
+              f"* FETCH_SIZE: {fk:,.0f} KiB (mean of {fn} dispatches) x {f_fac:.3f} = "
+              f"{fk * f_fac * 1024 / 1e9:.3f} GB",
+              f"* WRITE_SIZE: {wk:,.0f} KiB (mean of {wn} dispatches) x {w_fac:.3f} = "
+              f"{wk * w_fac * 1024 / 1e6:.3f} MB",
+              f"* Calibration: a copy of {args.copy_mib} MiB reads {cf:,.0f} KiB by FETCH_SIZE and "
+              f"writes {cw:,.0f} KiB by WRITE_SIZE per dispatch (factors {f_fac:.3f}, {w_fac:.3f}).",
+              f"* HBM-side traffic per launch: {traffic / 1e9:.3f} GB; over the average duration "
+              f"{avg_us:.1f} us that is {traffic / (avg_us * 1e-6) / 1e9:.0f} GB/s "
+              f"({traffic / (avg_us * 1e-6) / 8e12 * 100:.1f} % of 8 TB/s)."]
+    if args.algorithmic_bytes:
+        lines.append(f"* Algorithmic bytes per launch: {args.algorithmic_bytes / 1e9:.3f} GB "
+                     f"({args.algorithmic_bytes / (avg_us * 1e-6) / 1e9:.0f} GB/s).")
+    if extra:
+        lines += ["", "## Other counters (mean per dispatch)", "", "| counter | value | dispatches |",
+                  "|---|---|---|"]
+        for name in sorted(extra):
+            v, n = extra[name]
+            lines.append(f"| {name} | {v:,.0f} | {n} |")
+    lines += ["", f"Kernel source hash (eh_kernels.hip, sha256 prefix): {kernel_sha()}", ""]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines))
+
+    tj = {}
+    if os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            tj = json.load(f)
+    tj[args.workload] = {"kernel": args.kernel, "kernel_sha": kernel_sha(),
+                         "bytes_per_launch": traffic, "avg_us": avg_us,
+                         "fetch_kib": fk, "write_kib": wk, "fetch_factor": f_fac,
+                         "write_factor": w_fac, "summary": os.path.relpath(args.out, ROOT)}
+    with open(args.traffic, "w") as f:
+        json.dump(tj, f, indent=1, sort_keys=True)
+    print(f"{args.workload}: {avg_us:.1f} us, traffic {traffic / 1e9:.3f} GB per launch")
+
+
+if __name__ == "__main__":
+    main()
