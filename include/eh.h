@@ -84,7 +84,9 @@ eh_status eh_ctx_create(int device, void* hip_stream, const eh_allocator* alloc,
 eh_status eh_ctx_destroy(eh_ctx* ctx);
 const char* eh_last_error(const eh_ctx* ctx);
 const char* eh_status_str(eh_status s);
-/* Version of this ABI (major * 10000 + minor * 100 + patch). */
+/* Version of this ABI (major * 10000 + minor * 100 + patch); a caller built
+ * against this header checks that the library returns EH_ABI_VERSION. */
+#define EH_ABI_VERSION 10100
 int32_t eh_abi_version(void);
 
 /* ---- tuning knobs (performance only; counts never depend on them) ------- */
@@ -105,14 +107,23 @@ typedef struct eh_tuning {
   uint32_t use_bitsets;  /* 1: dense sets are read through their bitset layout */
   uint32_t dynamic;      /* schedule: 0 static interleave (item i to wave i mod waves),
                             1 waves take items from an atomic cursor (work stealing),
-                            2 static blocks (each wave one contiguous range of items) */
+                            2 static blocks (each wave one contiguous range of items),
+                            3 partitioned interleave (the items cut into xcds contiguous
+                              ranges, each interleaved over the waves of one L2 domain),
+                            4 partitioned cursors (one atomic cursor per range; waves
+                              take `grab` items per fetch and move on to the next range
+                              when theirs is used up) */
   uint32_t stage_words;  /* staged kernels: LDS words for a held set (bitset range / 32, or
                             list length), at most 1024; 0 means 1024 */
-  uint32_t xcds;         /* static schedule: blocks are dealt round-robin to this many L2
-                            domains (8 on MI355X); each then takes a contiguous slice of
-                            every window of work items.  0 or 1: no remapping */
+  uint32_t xcds;         /* L2 domains blocks are dealt to round-robin (8 on MI355X), at
+                            most 32.  Schedules 0 and 2: each domain then takes a
+                            contiguous slice of every window of items (0 or 1: no
+                            remapping); schedules 3 and 4: the number of item ranges
+                            (0: 8) */
   uint32_t unroll;       /* staged triangle kernel: streamed elements in flight per lane,
                             4 (more waves per CU) or 8; 0 means 8 */
+  uint32_t grab;         /* schedule 4: consecutive items per cursor fetch, at most 4096;
+                            0 means 8 */
 } eh_tuning;
 
 eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t);

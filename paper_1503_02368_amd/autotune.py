@@ -26,7 +26,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tuning.json")
 
 BASE = dict(kernel=1, staging=2, algo=0, gamma=32.0, chunk_work=4096, waves_per_cu=32,
-            group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0, xcds=0, unroll=8)
+            group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0, xcds=0, unroll=8, grab=8)
+# schedules tried last: (dynamic, grab); 3 and 4 cut the items into one range per XCD
+SCHEDULES = [(1, 8), (2, 8), (3, 8), (4, 1), (4, 4), (4, 16)]
 
 
 def log(*a):
@@ -111,8 +113,8 @@ def tune_graph(el, pattern, layouts, ctx, torch, quick=False):
                 S.record(dict(layout=layout, tau=tau, tuning=cfg), ms, c)
                 if local is None or ms < local[0]:
                     local = (ms, cfg)
-            for dyn in (1, 2):
-                cfg = dict(local[1], dynamic=dyn)
+            for dyn, grab in SCHEDULES:
+                cfg = dict(local[1], dynamic=dyn, grab=grab)
                 ctx.set_tuning(**cfg)
                 ms, c = timer.graph(trie, pattern)
                 S.record(dict(layout=layout, tau=tau, tuning=cfg), ms, c)
@@ -133,26 +135,38 @@ def tune_batch(b, pattern, layouts, ctx, torch, quick=False):
     out = torch.zeros(G, dtype=torch.int64, device="cuda")
     for layout, tau in layouts:
         trie = ctx.build_batch(b, layout=layout, tau=tau)
-        try:
-            chunks = [1024, 4096, 16384] if quick else [512, 1024, 2048, 4096, 8192, 16384]
-            kinds = [dict(staging=2), dict(staging=1)]
-            kinds += [dict(kernel=2, group_lanes=g, algo=al) for g in (4, 8, 16) for al in (0, 1)]
-            for k, ch, wv, dyn in itertools.product(kinds, chunks, [16, 32], [0, 2]):
-                cfg = dict(BASE, **k, chunk_work=ch, waves_per_cu=wv, dynamic=dyn)
-                ctx.set_tuning(**cfg)
-                s = ctx.stream
+        def run(cfg):
+            ctx.set_tuning(**cfg)
+            s = ctx.stream
+            ctx.count_batch_async(trie, pattern, 0, G, out)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(3):
                 ctx.count_batch_async(trie, pattern, 0, G, out)
-                torch.cuda.synchronize()
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(s)
-                for _ in range(3):
-                    ctx.count_batch_async(trie, pattern, 0, G, out)
-                e1.record(s)
-                torch.cuda.synchronize()
-                ms = e0.elapsed_time(e1) / 3
-                c = int(out.cpu().numpy().view(np.uint64).sum(dtype=np.uint64))
-                S.record(dict(layout=layout, tau=tau, tuning=cfg), ms, c)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 3
+            c = int(out.cpu().numpy().view(np.uint64).sum(dtype=np.uint64))
+            S.record(dict(layout=layout, tau=tau, tuning=cfg), ms, c)
+            return ms
+
+        try:
+            chunks = [1024, 4096] if quick else [512, 1024, 2048, 4096, 8192, 16384]
+            kinds = [dict(staging=2), dict(staging=1)]
+            groups = (8,) if quick else (4, 8, 16)
+            kinds += [dict(kernel=2, group_lanes=g, algo=al) for g in groups for al in (0, 1)]
+            local = None
+            for k, ch, (dyn, grab) in itertools.product(kinds, chunks, [(0, 8), (4, 16)]):
+                cfg = dict(BASE, **k, chunk_work=ch, dynamic=dyn, grab=grab)
+                ms = run(cfg)
+                if local is None or ms < local[0]:
+                    local = (ms, cfg)
+            unrolls = [4, 8] if local[1]["kernel"] == 1 else [8]
+            for wv, un, (dyn, grab) in itertools.product([16, 24, 32], unrolls,
+                                                          [(0, 8), (3, 8), (4, 4), (4, 16), (4, 64)]):
+                run(dict(local[1], waves_per_cu=wv, unroll=un, dynamic=dyn, grab=grab))
         finally:
             trie.free()
     return S

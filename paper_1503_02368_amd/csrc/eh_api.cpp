@@ -153,6 +153,7 @@ LaunchArgs base_args(Ctx* c, const Trie& t) {
   a.stage_words = c->tune.stage_words;
   a.xcds = c->tune.xcds;
   a.unroll = c->tune.unroll;
+  a.grab = c->tune.grab;
   return a;
 }
 
@@ -172,9 +173,9 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
   a.tag_base = tag_base;
   a.per_root = per_root;
   eh_status st;
-  if (a.dynamic == 1)
-    if ((st = launch_fill_u64(c, c->stream, static_cast<unsigned long long*>(c->cursor.p), 1, 0)) !=
-        EH_OK)
+  if (a.dynamic == 1 || a.dynamic == 4)
+    if ((st = launch_fill_u64(c, c->stream, static_cast<unsigned long long*>(c->cursor.p),
+                              c->cursor.bytes / 8, 0)) != EH_OK)
       return st;
   if (p->pattern == EH_4CLIQUE) {
     if (t.host.dmax > k4_staged_max_degree()) {
@@ -230,7 +231,7 @@ using namespace eh;
 
 extern "C" {
 
-int32_t eh_abi_version(void) { return 10000; }
+int32_t eh_abi_version(void) { return EH_ABI_VERSION; }
 
 const char* eh_status_str(eh_status s) {
   switch (s) {
@@ -283,7 +284,8 @@ eh_status eh_ctx_create(int device, void* hip_stream, const eh_allocator* alloc,
       c->has_alloc = true;
     }
   }
-  if (st == EH_OK) st = dev_alloc(c, c->cursor, 8);
+  // one cursor per item partition, each on its own 256-byte line
+  if (st == EH_OK) st = dev_alloc(c, c->cursor, sizeof(uint32_t) * kCursorWords * kMaxParts);
   if (st == EH_OK) st = ensure_acc(c, 64);
   if (st != EH_OK) {
     g_err_no_ctx = c->err;
@@ -326,8 +328,17 @@ eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t) {
   if (t->waves_per_cu) u.waves_per_cu = t->waves_per_cu;
   u.group_lanes = t->group_lanes;
   u.use_bitsets = t->use_bitsets ? 1 : 0;
-  if (t->dynamic > 2) {
-    ctx->c.err = "dynamic must be 0 (interleaved), 1 (atomic cursor) or 2 (blocked)";
+  if (t->dynamic > 4) {
+    ctx->c.err = "dynamic must be 0 (interleaved), 1 (atomic cursor), 2 (blocked), "
+                 "3 (partitioned interleave) or 4 (partitioned cursors)";
+    return EH_EINVAL;
+  }
+  if (t->xcds > kMaxParts) {
+    ctx->c.err = "xcds must be at most " + std::to_string(kMaxParts);
+    return EH_EINVAL;
+  }
+  if (t->grab > 4096) {
+    ctx->c.err = "grab must be at most 4096";
     return EH_EINVAL;
   }
   u.dynamic = t->dynamic;
@@ -342,6 +353,7 @@ eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t) {
     return EH_EINVAL;
   }
   u.unroll = t->unroll ? t->unroll : 8;
+  u.grab = t->grab ? t->grab : 8;
   return EH_OK;
 }
 
@@ -360,6 +372,7 @@ eh_status eh_ctx_get_tuning(const eh_ctx* ctx, eh_tuning* out) {
   out->stage_words = u.stage_words;
   out->xcds = u.xcds;
   out->unroll = u.unroll;
+  out->grab = u.grab;
   return EH_OK;
 }
 

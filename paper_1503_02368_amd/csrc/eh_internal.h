@@ -23,6 +23,8 @@ constexpr uint32_t kNoBitset = 0xFFFFFFFFu;
 constexpr uint32_t kHiBit = 0x80000000u;   // vdesc.y: the set also has a bitset
 constexpr uint32_t kMaxIndex = 0x7FFFFFFFu;  // offsets must stay below 2^31
 constexpr uint32_t kStageWords = 1024;        // LDS words per wave for a staged set
+constexpr uint32_t kCursorWords = 64;         // uint32 words between work cursors
+constexpr uint32_t kMaxParts = 32;           // item partitions (L2 domains) at most
 
 // One unit of scheduled work: the set N+(s) is held on chip while the sets
 // N+(t) of the streamed vertices t = idx[lbeg .. lbeg+llen) are intersected
@@ -84,6 +86,7 @@ struct Tuning {
   uint32_t stage_words = 0;
   uint32_t xcds = 0;
   uint32_t unroll = 8;
+  uint32_t grab = 8;
 };
 
 struct Ctx;
@@ -139,7 +142,7 @@ struct Ctx {
   // scratch: accumulators and cursor
   DevBuf acc;       // uint64 accumulators
   size_t acc_cap = 0;
-  DevBuf cursor;    // uint32 work cursors
+  DevBuf cursor;    // uint32 work cursors, kCursorWords apart
   uint64_t* pinned = nullptr;  // host staging for results
   size_t pinned_cap = 0;
 };
@@ -185,6 +188,7 @@ struct LaunchArgs {
   uint32_t stage_words = 0;            // 0: kernel maximum
   uint32_t xcds = 0;                   // L2 domains for the static schedule remap
   uint32_t unroll = 8;                 // staged triangle kernel: 4 or 8
+  uint32_t grab = 8;                   // schedule 4: items per cursor fetch
 };
 eh_status launch_fill_u64(Ctx* c, hipStream_t s, unsigned long long* p, uint64_t n,
                           unsigned long long v);

@@ -62,6 +62,7 @@ struct DevArgs {
   float gamma;
   uint32_t stage_words;  // <= the kernel's region size
   uint32_t xcds;
+  uint32_t grab;
 };
 
 DevArgs to_dev(const LaunchArgs& a) {
@@ -87,6 +88,7 @@ DevArgs to_dev(const LaunchArgs& a) {
   d.gamma = a.gamma;
   d.stage_words = a.stage_words;
   d.xcds = a.xcds;
+  d.grab = a.grab;
   return d;
 }
 
@@ -138,21 +140,52 @@ __device__ __forceinline__ uint32_t lower_bound_glb(const uint32_t* __restrict__
   return lo;
 }
 
-// Work-item iteration: static interleave or an atomic cursor.
-// Schedules (DevArgs.dynamic): 0 interleaved (item i to wave i mod W),
-// 1 atomic cursor (work stealing), 2 blocked (wave w takes one contiguous
-// range of items, so consecutive items of one graph or request share a wave).
+// Work-item iteration.  Schedules (DevArgs.dynamic):
+//  0 interleaved: item i to wave i mod W;
+//  1 one atomic cursor (work stealing, one item per fetch);
+//  2 blocked: wave w takes one contiguous range of items, so consecutive
+//    items of one graph or request share a wave;
+//  3 partitioned interleave: the items are cut into P contiguous ranges, one
+//    per L2 domain (XCD; blocks are dealt to the P domains round-robin), and
+//    each range is interleaved over the waves of its domain, so the sets a
+//    window of items reads are fetched into one L2 instead of all P;
+//  4 partitioned cursors: as 3, but each range has its own atomic cursor,
+//    waves take `grab` consecutive items per fetch (the window of items in
+//    flight stays tight, so it stays in L2), and a wave whose range is used
+//    up moves on to the next range (work stealing across domains).
+// P = DevArgs.xcds (0: 8, the XCD count of MI355X).  Cursors are
+// kCursorWords words apart, one per partition, zeroed before the launch.
 struct ItemIter {
   uint64_t i, step, end;
-  bool dyn;
+  uint32_t mode;
   uint32_t* cursor;
+  uint64_t n;
+  uint32_t part, parts, left, grab;
   __device__ ItemIter(const DevArgs& a, uint32_t wpb) {
-    dyn = a.dynamic == 1;
+    mode = a.dynamic;
     cursor = a.cursor;
     end = a.n_items;
-    if (dyn) {
+    n = a.n_items;
+    if (mode == 1) {
       step = 0;
       i = fetch();
+      return;
+    }
+    if (mode == 3 || mode == 4) {
+      parts = a.xcds ? a.xcds : 8u;
+      const uint32_t nb = gridDim.x;
+      if (mode == 3 && nb % parts != 0) parts = 1;  // every range needs waves
+      part = blockIdx.x % parts;
+      if (mode == 3) {
+        const uint64_t nwp = uint64_t(nb / parts) * wpb;
+        i = range_lo(part) + uint64_t(blockIdx.x / parts) * wpb + (threadIdx.x >> 6);
+        end = range_lo(part + 1);
+        step = nwp;
+      } else {
+        grab = a.grab;
+        left = parts;
+        refill();
+      }
       return;
     }
     // Blocks are dealt round-robin to the L2 domains (XCDs): block b runs on
@@ -175,13 +208,33 @@ struct ItemIter {
     }
   }
   __device__ bool more() const { return i < end; }
+  __device__ uint64_t range_lo(uint32_t p) const { return n * p / parts; }
   __device__ uint64_t fetch() {
     uint32_t v = 0;
     if ((threadIdx.x & 63) == 0) v = atomicAdd(cursor, 1u);
     return uniform(__shfl(v, 0, kWave));
   }
+  // Takes the next `grab` items of the current range, else moves on; every
+  // range is tried at most once after it is found used up, so this ends.
+  __device__ void refill() {
+    while (left) {
+      uint32_t v = 0;
+      if ((threadIdx.x & 63) == 0) v = atomicAdd(cursor + part * kCursorWords, grab);
+      v = uniform(__shfl(v, 0, kWave));
+      const uint64_t s = range_lo(part) + v, hi = range_lo(part + 1);
+      if (s < hi) {
+        i = s;
+        end = s + grab < hi ? s + grab : hi;
+        return;
+      }
+      part = part + 1 == parts ? 0u : part + 1;
+      --left;
+    }
+    i = end = 0;
+  }
   __device__ void next() {
-    if (dyn) i = fetch();
+    if (mode == 1) i = fetch();
+    else if (mode == 4) { if (++i >= end) refill(); }
     else i += step;
   }
 };
@@ -214,6 +267,7 @@ constexpr int kPrefixCap = 128;
 
 struct Staged {
   uint32_t beg, len, lo, hi, base, plen, mode;
+  uint32_t x0;  // per lane: member number `lane` of the set (lane < len), kept to clear R
 };
 
 // Loads the set col[beg .. beg+len) with known min lo and max hi into region
@@ -226,6 +280,7 @@ __device__ __forceinline__ Staged stage_extent(const DevArgs& a, uint32_t beg, u
   st.beg = beg;
   st.len = len;
   st.plen = 0;
+  st.x0 = 0;
   if (st.len == 0) { st.mode = kModeEmpty; st.lo = st.hi = st.base = 0; return st; }
   st.lo = lo;
   st.hi = hi;
@@ -245,6 +300,7 @@ __device__ __forceinline__ Staged stage_extent(const DevArgs& a, uint32_t beg, u
     bool low = false;
     if (k < st.len) {
       const uint32_t x = a.col[st.beg + k];
+      if (k0 == 0) st.x0 = x;
       low = x < st.base;
       if (!low) {
         const uint32_t d = x - st.base;
@@ -278,8 +334,13 @@ __device__ __forceinline__ void unstage_set(const DevArgs& a, const Staged& st, 
                                             uint32_t lane) {
   wave_sync();
   if (st.mode == kModeBitmap || st.mode == kModeComposite) {
-    for (uint32_t k = st.plen + lane; k < st.len; k += kWave)
-      R[(a.col[st.beg + k] - st.base) >> 5] = 0;
+    if (st.len <= uint32_t(kWave)) {
+      // the members are still in registers (the prefix lies below base)
+      if (lane < st.len && st.x0 >= st.base) R[(st.x0 - st.base) >> 5] = 0;
+    } else {
+      for (uint32_t k = st.plen + lane; k < st.len; k += kWave)
+        R[(a.col[st.beg + k] - st.base) >> 5] = 0;
+    }
   }
   wave_sync();
 }
@@ -538,6 +599,9 @@ void k_tri_staged(DevArgs a) {
     if (have_tag && tag != cur_tag) flush_tag(a, acc, cur_tag, lane);
     cur_tag = tag;
     have_tag = true;
+    // the first batch of segment records is loaded beside the staged set
+    uint4 r0{0, 0, 0, 0};
+    if (a.rec && lane < min(uint32_t(kSeg), llen)) r0 = a.rec[lbeg + lane];
     const Staged st = a.sdesc ? stage_extent<RW>(a, uniform(sd.x), uniform(sd.y), uniform(sd.z),
                                                  uniform(sd.w), R, Lp, lane)
                               : stage_set<RW>(a, s, R, Lp, lane);
@@ -550,7 +614,7 @@ void k_tri_staged(DevArgs a) {
       if (lane < nseg) {
         if (a.rec) {
           // resolved at plan time: one load per streamed set
-          const uint4 r = a.rec[lbeg + b0 + lane];
+          const uint4 r = b0 == 0 ? r0 : a.rec[lbeg + b0 + lane];
           g = Seg{r.x, r.y, int32_t(r.z)};
         } else if (a.tin) {
           const uint2 ie = a.tin[lbeg + b0 + lane];  // in-edge u -> s at position ie.y
@@ -799,7 +863,7 @@ uint32_t grid_for(Ctx* c, uint64_t n_items, uint32_t wpb, uint32_t waves_per_cu)
   const uint64_t need = (n_items + wpb - 1) / wpb;
   if (want > need) want = need;
   // a multiple of the L2-domain count keeps the block renumbering a bijection
-  const uint64_t x = c->tune.xcds;
+  const uint64_t x = (c->tune.dynamic == 3 && !c->tune.xcds) ? 8 : c->tune.xcds;
   if (x > 1 && want > x) want -= want % x;
   if (want < 1) want = 1;
   return uint32_t(std::min<uint64_t>(want, 1u << 20));

@@ -49,13 +49,17 @@ class _Allocator(ctypes.Structure):
                 ("self", ctypes.c_void_p)]
 
 
+# struct layouts below are those of this ABI version of include/eh.h
+ABI_VERSION = 10100
+
+
 class _Tuning(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_uint32), ("staging", ctypes.c_uint32), ("algo", ctypes.c_uint32),
                 ("gamma", ctypes.c_float), ("chunk_work", ctypes.c_uint32),
                 ("waves_per_cu", ctypes.c_uint32), ("group_lanes", ctypes.c_uint32),
                 ("use_bitsets", ctypes.c_uint32), ("dynamic", ctypes.c_uint32),
                 ("stage_words", ctypes.c_uint32), ("xcds", ctypes.c_uint32),
-                ("unroll", ctypes.c_uint32)]
+                ("unroll", ctypes.c_uint32), ("grab", ctypes.c_uint32)]
 
 
 class _BuildOpts(ctypes.Structure):
@@ -139,6 +143,8 @@ def load():
         lib.eh_status_str.restype = ctypes.c_char_p
         lib.eh_abi_version.argtypes = []
         lib.eh_abi_version.restype = S
+        if lib.eh_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"libeh ABI {lib.eh_abi_version()} != binding ABI {ABI_VERSION}: rebuild")
         _lib = lib
         return lib
 

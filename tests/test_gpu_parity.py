@@ -71,9 +71,14 @@ TUNINGS = {
     "pair_merge4": dict(kernel=2, algo=1, use_bitsets=0, group_lanes=4, dynamic=1),
     "pair_search16": dict(kernel=2, algo=2, use_bitsets=0, group_lanes=16, dynamic=2),
     "pair_merge64": dict(kernel=2, algo=1, use_bitsets=1, group_lanes=64, dynamic=0),
+    # partitioned schedules: 8 ranges interleaved per L2 domain; 5 ranges with
+    # cursors taking 3 items per fetch (ranges of unequal size, stealing)
+    "staged_part": dict(kernel=1, staging=2, use_bitsets=1, dynamic=3, xcds=0),
+    "staged_steal": dict(kernel=1, staging=1, use_bitsets=1, dynamic=4, xcds=5, grab=3),
+    "pair_steal": dict(kernel=2, algo=0, use_bitsets=1, group_lanes=8, dynamic=4, xcds=8, grab=1),
 }
 DEFAULT = dict(kernel=1, staging=2, algo=0, gamma=32.0, chunk_work=4096, waves_per_cu=32,
-               group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0)
+               group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0, xcds=0, unroll=8, grab=8)
 
 
 def tune(ctx, **kw):
@@ -102,7 +107,7 @@ def test_triangles_zoo(ctx, eh, tname, lay):
 
 @pytest.mark.parametrize("lay", LAYOUTS[:3], ids=lambda x: x[0])
 @pytest.mark.parametrize("tname", ["staged_source", "staged_nobits", "staged_list", "staged_global",
-                                   "staged_half"])
+                                   "staged_half", "staged_steal"])
 def test_4cliques_zoo(ctx, eh, tname, lay):
     tune(ctx, **TUNINGS[tname])
     for el in ZOO:
@@ -133,9 +138,9 @@ def test_per_root(ctx, eh, tname):
 def test_chunking_and_grid(ctx, eh, chunk):
     el = inputs.rmat(13, 16, seed=31)
     T, K, _ = truth(el)
-    for wpc in (4, 32):
+    for wpc, dyn in ((4, 0), (32, 0), (1, 3), (1, 4), (32, 4)):
         for staging in (1, 2):
-            tune(ctx, chunk_work=chunk, waves_per_cu=wpc, staging=staging)
+            tune(ctx, chunk_work=chunk, waves_per_cu=wpc, staging=staging, dynamic=dyn)
             trie = ctx.build_edgelist(el)
             try:
                 assert ctx.count_triangles(trie) == T
@@ -190,7 +195,8 @@ def small_batch(num=120, seed=4):
     return inputs.batch_chung_lu(num, seed=seed, n_hi=2048)
 
 
-@pytest.mark.parametrize("tname", ["staged_target", "staged_source", "pair_auto"])
+@pytest.mark.parametrize("tname", ["staged_target", "staged_source", "pair_auto", "staged_part",
+                                   "staged_steal"])
 def test_batch(ctx, eh, tname):
     tune(ctx, **TUNINGS[tname])
     b = small_batch()
@@ -289,7 +295,7 @@ def test_full_size_rmat20_triangles(ctx, eh):
     say("oracle T", T)
     trie = ctx.build_edgelist(el)
     try:
-        for tname in ("staged_target", "staged_source", "pair_auto"):
+        for tname in ("staged_target", "staged_source", "pair_auto", "staged_part", "staged_steal"):
             tune(ctx, **TUNINGS[tname])
             got = ctx.count_triangles(trie)
             say(tname, got)

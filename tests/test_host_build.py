@@ -34,7 +34,9 @@ def test_status_strings():
     lib = eh.load()
     assert lib.eh_status_str(0) == b"ok"
     assert lib.eh_status_str(-1) == b"invalid argument"
-    assert lib.eh_abi_version() >= 10000
+    assert lib.eh_abi_version() == eh.ABI_VERSION
+    with open(os.path.join(ROOT, "include", "eh.h")) as f:
+        assert int(re.search(r"#define EH_ABI_VERSION (\d+)", f.read()).group(1)) == eh.ABI_VERSION
 
 
 GRAPHS = [inputs.rmat(10, 16, seed=3), inputs.messy(inputs.rmat(9, 8, seed=4), 2),
