@@ -200,16 +200,18 @@ eh_status eh_count_batch_async(eh_ctx* ctx, const eh_trie* batch, int pattern, u
 
 /* ---- serving ------------------------------------------------------------ */
 
-/* A server keeps `resident` in HBM and answers rooted count requests.  A
- * progress thread admits queued requests in arrival order while the summed
- * footprint of active requests stays within hbm_budget_bytes and fewer than
- * max_active are active, then advances all active requests together in
- * device steps of at most step_items work items.  Zero fields take defaults. */
+/* A server keeps `resident` in HBM and answers rooted count requests.
+ * Worker threads turn each submitted request into work items (its footprint:
+ * 16 bytes per item plus its 8-byte counter).  A progress thread admits
+ * expanded requests in arrival order while the summed footprint of active
+ * requests stays within hbm_budget_bytes and fewer than max_active are
+ * active, then advances all active requests together in device steps of at
+ * most step_items work items.  Zero fields take the defaults in brackets. */
 typedef struct eh_server_opts {
-  uint64_t hbm_budget_bytes;
-  uint32_t max_active;
-  uint32_t max_queued;
-  uint32_t step_items;
+  uint64_t hbm_budget_bytes;  /* [2 GiB] */
+  uint32_t max_active;        /* [256] */
+  uint32_t max_queued;        /* [4096] submitted, not yet admitted */
+  uint32_t step_items;        /* [262144] */
   uint32_t reserved;
 } eh_server_opts;
 
@@ -220,12 +222,16 @@ typedef struct eh_req_stats {
   uint64_t items;         /* work items the request was split into */
 } eh_req_stats;
 
-/* The server uses ctx's device and allocator but its own stream; do not use
- * ctx from another thread while the server lives. */
+/* The server uses ctx's device and allocator, a copy of ctx's tuning taken
+ * here, and its own stream and work cursors; do not use ctx from another
+ * thread while the server lives. */
 eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server_opts* opts,
                            eh_server** out);
 /* Copies roots; returns a ticket.  EH_EBUSY when max_queued are waiting,
- * EH_ENOMEM when the request alone exceeds the budget. */
+ * EH_ENOMEM when the request alone exceeds the budget.  When the budget holds
+ * the request with every vertex a root, the roots are only checked and copied
+ * here and expanded by a worker; otherwise this call expands them itself so
+ * that it can refuse the request. */
 eh_status eh_submit(eh_server* srv, int pattern, const uint32_t* roots, uint32_t n_roots,
                     uint64_t* ticket);
 /* EH_OK with *count (and stats) once done; the ticket is then retired.

@@ -174,7 +174,10 @@ def bench_served(name, w, args, ctx, eh, torch, metric):
     t0 = time.perf_counter()
     el = inputs.rmat(w["scale"], w["edge_factor"], seed=w["seed"])
     log(f"[bench] served graph generated in {time.perf_counter() - t0:.1f} s")
-    trie = ctx.build_edgelist(el, layout=w["layout"], tau=w["tau"])
+    tune = load_tuning(name)
+    if tune.get("tuning"):
+        ctx.set_tuning(**tune["tuning"])  # servers copy the tuning when created
+    trie = ctx.build_edgelist(el, layout=tune.get("layout", w["layout"]), tau=tune.get("tau", w["tau"]))
     info = trie.info
     log(f"[bench] resident trie: {info}")
     rates = [float(x) for x in args.rates.split(",")]

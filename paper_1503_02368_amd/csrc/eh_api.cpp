@@ -172,19 +172,9 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
   a.acc = acc;
   a.tag_base = tag_base;
   a.per_root = per_root;
-  eh_status st;
-  if (a.dynamic == 1 || a.dynamic == 4)
-    if ((st = launch_fill_u64(c, c->stream, static_cast<unsigned long long*>(c->cursor.p),
-                              c->cursor.bytes / 8, 0)) != EH_OK)
-      return st;
-  if (p->pattern == EH_4CLIQUE) {
-    if (t.host.dmax > k4_staged_max_degree()) {
-      c->err = "4-clique counting supports out-degrees up to " +
-               std::to_string(k4_staged_max_degree());
-      return EH_EOVERFLOW;
-    }
+  a.item_dmax = p->item_dmax;
+  if (p->pattern == EH_4CLIQUE)
     return launch_4cliques(c, c->stream, a, c->tune.kernel, c->tune.waves_per_cu);
-  }
   return launch_triangles(c, c->stream, a, c->tune.kernel, c->tune.waves_per_cu);
 }
 
@@ -538,9 +528,13 @@ eh_status eh_count_rooted(eh_ctx* ctx, const eh_trie* trie, int pattern, const u
   std::sort(r.begin(), r.end());
   r.erase(std::unique(r.begin(), r.end()), r.end());
   std::vector<Item> items;
-  for (uint32_t u : r)
+  uint32_t item_dmax = 0;
+  for (uint32_t u : r) {
+    const size_t before = items.size();
     make_items_source(h, u, 0, c->tune.chunk_work, uint32_t(pattern), c->tune.use_bitsets != 0,
                       items);
+    if (items.size() > before) item_dmax = std::max(item_dmax, h.row[u + 1] - h.row[u]);
+  }
   unsigned long long* acc = static_cast<unsigned long long*>(c->acc.p);
   eh_status st = launch_fill_u64(c, c->stream, acc, 1, 0);
   if (st != EH_OK) return st;
@@ -558,6 +552,7 @@ eh_status eh_count_rooted(eh_ctx* ctx, const eh_trie* trie, int pattern, const u
     p.staging = EH_STAGE_SOURCE;
     p.items = buf;
     p.n_items = items.size();
+    p.item_dmax = item_dmax;
     st = enqueue_count(c, t, &p, 0, items.size(), acc, 0, nullptr);
   }
   if (st == EH_OK) st = read_back(c, acc, total, 1);

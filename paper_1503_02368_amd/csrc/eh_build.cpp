@@ -372,16 +372,29 @@ void make_items_source(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chu
   }
 }
 
+// Out-neighbours per item when only d+(u) is known: each out-neighbour's
+// streamed work is taken to be about |N+(u)| (more for the 4-clique's second
+// level).  0: u roots no instance (too few out-neighbours).
+static uint32_t estimated_slice(uint32_t du, uint32_t chunk_work, uint32_t pattern) {
+  if (du < (pattern == EH_4CLIQUE ? 3u : 2u)) return 0;
+  const uint64_t per = pattern == EH_4CLIQUE ? uint64_t(du) * 25 + 2 : uint64_t(du) + 2;
+  return uint32_t(std::max<uint64_t>(1, chunk_work / per));
+}
+
 void make_items_estimated(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chunk_work,
                           uint32_t pattern, std::vector<Item>& out) {
   const uint32_t du = out_deg(h, u);
-  if (du < (pattern == EH_4CLIQUE ? 3u : 2u)) return;
-  // each out-neighbour's streamed work is taken to be about |N+(u)| (more
-  // for the 4-clique's second level), so only d+(u) is read
-  const uint64_t per = pattern == EH_4CLIQUE ? uint64_t(du) * 25 + 2 : uint64_t(du) + 2;
-  const uint32_t slice = uint32_t(std::max<uint64_t>(1, chunk_work / per));
+  const uint32_t slice = estimated_slice(du, chunk_work, pattern);
+  if (slice == 0) return;
   for (uint32_t i = 0; i < du; i += slice)
     out.push_back(Item{u, h.row[u] + i, std::min(slice, du - i), tag});
+}
+
+uint64_t count_items_estimated(const HostTrie& h, uint32_t u, uint32_t chunk_work,
+                               uint32_t pattern) {
+  const uint32_t du = out_deg(h, u);
+  const uint32_t slice = estimated_slice(du, chunk_work, pattern);
+  return slice ? (uint64_t(du) + slice - 1) / slice : 0;
 }
 
 eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** out) {
@@ -450,6 +463,7 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
   }
   plan->g_item_off[h.n_graphs] = items.size();
   plan->n_items = items.size();
+  for (const Item& it : items) plan->item_dmax = std::max(plan->item_dmax, out_deg(h, it.s));
   eh_status st = dev_alloc(c, plan->items, sizeof(Item) * std::max<size_t>(items.size(), 1));
   if (st != EH_OK) return st;
   if (!items.empty())

@@ -112,6 +112,7 @@ struct Plan {
   DevBuf sdesc;
   DevBuf rec;
   std::vector<uint64_t> g_item_off;  // batch: items of graph g are [off[g], off[g+1])
+  uint32_t item_dmax = 0;            // max out-degree of an item's source vertex
 };
 
 struct Trie {
@@ -161,6 +162,9 @@ void make_items_source(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chu
 // Same items cut from out-degrees alone: O(1 + items) per root.
 void make_items_estimated(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chunk_work,
                           uint32_t pattern, std::vector<Item>& out);
+// The number of items make_items_estimated makes for u.
+uint64_t count_items_estimated(const HostTrie& h, uint32_t u, uint32_t chunk_work,
+                               uint32_t pattern);
 
 // Device launches (eh_kernels.hip).  All enqueue on `stream`.
 struct LaunchArgs {
@@ -185,6 +189,9 @@ struct LaunchArgs {
   float gamma = 32.0f;
   uint32_t group_lanes = 0;
   uint32_t dmax = 0;
+  uint32_t item_dmax = 0;              // max d+(s) over the launch's items, 0: unknown (dmax)
+  uint32_t deg_lo = 0;                 // 4-clique launches take items with
+  uint32_t deg_hi = 0xFFFFFFFFu;       //   deg_lo < d+(s) <= deg_hi (set by the launcher)
   uint32_t stage_words = 0;            // 0: kernel maximum
   uint32_t xcds = 0;                   // L2 domains for the static schedule remap
   uint32_t unroll = 8;                 // staged triangle kernel: 4 or 8

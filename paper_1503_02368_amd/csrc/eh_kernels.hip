@@ -63,6 +63,7 @@ struct DevArgs {
   uint32_t stage_words;  // <= the kernel's region size
   uint32_t xcds;
   uint32_t grab;
+  uint32_t deg_lo, deg_hi;  // 4-clique: items with deg_lo < d+(u) <= deg_hi
 };
 
 DevArgs to_dev(const LaunchArgs& a) {
@@ -89,6 +90,8 @@ DevArgs to_dev(const LaunchArgs& a) {
   d.stage_words = a.stage_words;
   d.xcds = a.xcds;
   d.grab = a.grab;
+  d.deg_lo = a.deg_lo;
+  d.deg_hi = a.deg_hi;
   return d;
 }
 
@@ -670,6 +673,10 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
     if (have_tag && tag != cur_tag) flush_tag(a, acc, cur_tag, lane);
     cur_tag = tag;
     have_tag = true;
+    // |S| <= d+(u): a launch of this instance takes only the items whose S
+    // fits its list (the others go to an instance with a longer one)
+    const uint32_t du = uniform(a.vdesc[u].y & kMaxIndex);
+    if (du <= a.deg_lo || du > a.deg_hi) continue;
     const Staged su = stage_set<RW>(a, u, A, Lp, lane);
     if (su.len == 0) continue;
     const bool su_bits = su.mode == kModeBitmap || su.mode == kModeComposite;
@@ -889,10 +896,18 @@ eh_status launch_scatter_roots(Ctx* c, hipStream_t s, const unsigned long long* 
   return hip_check(c, hipGetLastError(), "scatter kernel launch");
 }
 
+// Zeroes the work cursors of schedules 1 and 4 ahead of a launch.
+eh_status reset_cursors(Ctx* c, hipStream_t s, const LaunchArgs& la) {
+  if (la.dynamic != 1 && la.dynamic != 4) return EH_OK;
+  return launch_fill_u64(c, s, reinterpret_cast<unsigned long long*>(la.cursor),
+                         uint64_t(kCursorWords) * kMaxParts / 2, 0);
+}
+
 eh_status launch_triangles(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t kernel,
                            uint32_t waves_per_cu) {
   if (la.n_items == 0) return EH_OK;
   const DevArgs a = to_dev(la);
+  if (eh_status st = reset_cursors(c, s, la); st != EH_OK) return st;
   if (kernel == EH_KERNEL_PAIRWISE) {
     uint32_t g = la.group_lanes;
     if (g == 0) g = la.dmax >= 256 ? 64 : la.dmax >= 64 ? 16 : 4;
@@ -923,28 +938,41 @@ eh_status launch_triangles(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t
 eh_status launch_4cliques(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t /*kernel*/,
                           uint32_t waves_per_cu) {
   if (la.n_items == 0) return EH_OK;
-  const DevArgs a = to_dev(la);
   const uint32_t grid = grid_for(c, la.n_items, kK4WPB, waves_per_cu);
   const dim3 blk(kK4WPB * kWave);
-  // stage_words in (0, 512]: the half-size LDS instance (more waves per CU)
-  const bool half = la.stage_words > 0 && la.stage_words <= kK4RW / 2;
-  if (la.dmax <= 512) {
-    if (half)
-      hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW / 2, 512, kK4U>), dim3(grid), blk, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 512, kK4U>), dim3(grid), blk, 0, s, a);
-  } else if (la.dmax <= 1024) {
-    if (half)
-      hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW / 2, 1024, kK4U>), dim3(grid), blk, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 1024, kK4U>), dim3(grid), blk, 0, s, a);
-  } else if (la.dmax <= 2048) {
-    hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 2048, kK4U>), dim3(grid), blk, 0, s, a);
-  } else {
-    c->err = "4-clique kernel supports out-degrees up to 2048";
+  // S = N+(u) & N+(v) has at most d+(u) members.  Items with d+(u) <= 512
+  // run in an instance with a 512-entry S list (and, for stage_words in
+  // (0, 512], a half-size staged region): less LDS, more waves per CU.  Only
+  // when some item's d+(u) exceeds 512 does a second launch, over the same
+  // items, take those with an S list sized for the largest out-degree.
+  const uint32_t bound = la.item_dmax ? la.item_dmax : la.dmax;
+  if (bound > k4_staged_max_degree()) {
+    c->err = "4-clique kernel supports out-degrees up to " + std::to_string(k4_staged_max_degree());
     return EH_EOVERFLOW;
   }
-  return hip_check(c, hipGetLastError(), "staged 4-clique kernel launch");
+  const bool half = la.stage_words > 0 && la.stage_words <= kK4RW / 2;
+  LaunchArgs light = la;
+  light.deg_lo = 0;
+  light.deg_hi = 512;
+  const DevArgs al = to_dev(light);
+  eh_status st = reset_cursors(c, s, la);
+  if (st != EH_OK) return st;
+  if (half)
+    hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW / 2, 512, kK4U>), dim3(grid), blk, 0, s, al);
+  else
+    hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 512, kK4U>), dim3(grid), blk, 0, s, al);
+  st = hip_check(c, hipGetLastError(), "staged 4-clique kernel launch");
+  if (st != EH_OK || bound <= 512) return st;
+  LaunchArgs heavy = la;
+  heavy.deg_lo = 512;
+  heavy.deg_hi = 0xFFFFFFFFu;
+  const DevArgs ah = to_dev(heavy);
+  if ((st = reset_cursors(c, s, la)) != EH_OK) return st;
+  if (bound <= 1024)
+    hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 1024, kK4U>), dim3(grid), blk, 0, s, ah);
+  else
+    hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 2048, kK4U>), dim3(grid), blk, 0, s, ah);
+  return hip_check(c, hipGetLastError(), "staged 4-clique kernel launch (high out-degree)");
 }
 
 }  // namespace eh

@@ -6,6 +6,13 @@
 // those vertices (appendix B.1 pushes such selections first).  Its work is
 // the source-staged items of each root.
 //
+// Submission only validates and copies the roots.  Expansion workers then
+// turn each request into work items (drop repeated roots, cut each root's
+// out-list into items), in parallel with one another and with the device,
+// and queue it for admission.  When a request could exceed the whole budget
+// (known from the item count with every vertex a root), the submitting
+// thread expands it itself, so that such a request is refused at submission.
+//
 // Continuous batching: a progress thread repeatedly (1) admits queued
 // requests in arrival order while the summed device footprint of active
 // requests fits the budget and a slot is free, (2) gathers up to step_items
@@ -34,7 +41,9 @@ uint64_t now_ns() {
 struct Request {
   uint64_t ticket = 0;
   int pattern = 0;
+  std::vector<uint32_t> roots;  // as submitted, until expanded
   std::vector<Item> items;  // tag filled at admission
+  uint32_t item_dmax = 0;   // max out-degree of an item's root
   uint64_t footprint = 0;
   uint64_t next_item = 0;   // next item to dispatch
   uint64_t done_items = 0;  // items whose step completed
@@ -52,6 +61,8 @@ struct Server {
   Trie* t = nullptr;
   eh_server_opts o{};
   hipStream_t stream = nullptr;
+  Tuning tune;             // the context's tuning when the server was created
+  DevBuf cursor;           // work cursors of the server's own launches
   DevBuf items_d;          // step_items Items
   DevBuf acc_d;            // max_active uint64
   Item* items_h = nullptr; // pinned staging
@@ -69,17 +80,31 @@ struct Server {
   std::string fatal;  // first device error; every later request fails
   std::thread th;
   std::deque<std::shared_ptr<Request>> done;  // finished, in completion order
-  std::mutex stamp_mu;                        // root de-duplication
-  std::vector<uint32_t> stamp;
-  uint32_t epoch = 0;
+  // root de-duplication: a stamp per vertex, one table per expanding thread
+  struct Dedup {
+    std::vector<uint32_t> stamp;
+    uint32_t epoch = 0;
+  };
+  std::mutex sync_mu;                          // guards sync_dedup
+  Dedup sync_dedup;                            // expansion in eh_submit
+  std::vector<Dedup> dedup;                    // one per worker
+  std::deque<std::shared_ptr<Request>> incoming;  // submitted, not yet expanded
+  std::condition_variable cv_incoming;
+  std::vector<std::thread> workers;
+  uint32_t chunk = 4096;                       // item size target, fixed at creation
+  bool async_ok[5] = {false, false, false, false, false};  // by pattern
 
   void run();
   bool step();
+  void expand(Request& r, Dedup& d) const;
+  void expand_loop(uint32_t w);
+  void enqueue_expanded(const std::shared_ptr<Request>& r);  // caller holds mu
 };
 
 namespace {
 
-eh_status server_launch(Server* s, const std::vector<Item>& v, uint64_t off, int pattern) {
+eh_status server_launch(Server* s, const std::vector<Item>& v, uint64_t off, int pattern,
+                        uint32_t item_dmax) {
   if (v.empty()) return EH_OK;
   Ctx* c = s->c;
   Trie& t = *s->t;
@@ -94,17 +119,21 @@ eh_status server_launch(Server* s, const std::vector<Item>& v, uint64_t off, int
   a.n_items = v.size();
   a.acc = static_cast<unsigned long long*>(s->acc_d.p);
   a.tag_base = 0;
-  a.use_bitsets = c->tune.use_bitsets && t.host.n_bs > 0;
-  a.dynamic = 0;  // items of many requests: static interleave needs no cursor
-  a.algo = c->tune.algo;
-  a.gamma = c->tune.gamma;
-  a.group_lanes = c->tune.group_lanes;
+  const Tuning& tu = s->tune;
+  a.use_bitsets = tu.use_bitsets && t.host.n_bs > 0;
+  a.dynamic = tu.dynamic;
+  a.grab = tu.grab;
+  a.cursor = static_cast<uint32_t*>(s->cursor.p);
+  a.algo = tu.algo;
+  a.gamma = tu.gamma;
+  a.group_lanes = tu.group_lanes;
   a.dmax = t.host.dmax;
-  a.stage_words = c->tune.stage_words;
-  a.xcds = c->tune.xcds;
-  a.unroll = c->tune.unroll;
-  if (pattern == EH_4CLIQUE) return launch_4cliques(c, s->stream, a, c->tune.kernel, c->tune.waves_per_cu);
-  return launch_triangles(c, s->stream, a, c->tune.kernel, c->tune.waves_per_cu);
+  a.item_dmax = item_dmax;
+  a.stage_words = tu.stage_words;
+  a.xcds = tu.xcds;
+  a.unroll = tu.unroll;
+  if (pattern == EH_4CLIQUE) return launch_4cliques(c, s->stream, a, tu.kernel, tu.waves_per_cu);
+  return launch_triangles(c, s->stream, a, tu.kernel, tu.waves_per_cu);
 }
 
 }  // namespace
@@ -114,6 +143,7 @@ bool Server::step() {
   std::vector<std::shared_ptr<Request>> batch_reqs;
   std::vector<uint32_t> to_zero;
   std::vector<Item> tri, k4;
+  uint32_t dmax_tri = 0, dmax_k4 = 0;
   std::vector<std::pair<std::shared_ptr<Request>, uint64_t>> dispatched;
   {
     std::unique_lock<std::mutex> lk(mu);
@@ -139,6 +169,8 @@ bool Server::step() {
       }
       const uint64_t take = std::min<uint64_t>(budget, r->items.size() - r->next_item);
       auto& dst = r->pattern == EH_4CLIQUE ? k4 : tri;
+      auto& dm = r->pattern == EH_4CLIQUE ? dmax_k4 : dmax_tri;
+      dm = std::max(dm, r->item_dmax);
       dst.insert(dst.end(), r->items.begin() + r->next_item, r->items.begin() + r->next_item + take);
       r->next_item += take;
       budget -= take;
@@ -158,8 +190,8 @@ bool Server::step() {
     st = hip_check(c, hipMemcpyAsync(items_d.p, items_h, (n_tri + n_k4) * sizeof(Item),
                                      hipMemcpyHostToDevice, stream), "upload step items");
   }
-  if (st == EH_OK) st = server_launch(this, tri, 0, EH_TRIANGLE);
-  if (st == EH_OK) st = server_launch(this, k4, n_tri, EH_4CLIQUE);
+  if (st == EH_OK) st = server_launch(this, tri, 0, EH_TRIANGLE, dmax_tri);
+  if (st == EH_OK) st = server_launch(this, k4, n_tri, EH_4CLIQUE, dmax_k4);
   if (st == EH_OK)
     st = hip_check(c, hipMemcpyAsync(acc_h, acc_d.p, o.max_active * sizeof(uint64_t),
                                      hipMemcpyDeviceToHost, stream), "read counters");
@@ -212,6 +244,84 @@ void Server::run() {
   }
 }
 
+// Turns r.roots into work items: repeated roots are dropped with a stamp per
+// vertex, and each root's out-list is cut into items whose size is estimated
+// from its out-degree alone, so the cost is proportional to the roots.  The
+// per-vertex tables are read at random: each pass prefetches a fixed distance
+// ahead so that the cache misses of many roots overlap.
+void Server::expand(Request& r, Dedup& d) const {
+  const HostTrie& h = t->host;
+  const uint32_t n_roots = uint32_t(r.roots.size());
+  constexpr uint32_t kAhead = 24;
+  std::vector<uint32_t> us(n_roots);
+  const uint32_t* rank = h.rank.data();
+  const uint32_t* roots = r.roots.data();
+  for (uint32_t i = 0; i < n_roots; ++i) {
+    if (i + kAhead < n_roots) __builtin_prefetch(rank + roots[i + kAhead]);
+    us[i] = rank[roots[i]];
+  }
+  r.items.reserve(size_t(n_roots) + n_roots / 4);
+  if (++d.epoch == 0) {
+    std::fill(d.stamp.begin(), d.stamp.end(), 0u);
+    d.epoch = 1;
+  }
+  uint32_t* stamp = d.stamp.data();
+  const uint32_t* row = h.row.data();
+  for (uint32_t i = 0; i < n_roots; ++i) {
+    if (i + kAhead < n_roots) {
+      __builtin_prefetch(stamp + us[i + kAhead], 1);
+      __builtin_prefetch(row + us[i + kAhead]);
+    }
+    const uint32_t u = us[i];
+    if (stamp[u] == d.epoch) continue;
+    stamp[u] = d.epoch;
+    const size_t before = r.items.size();
+    make_items_estimated(h, u, 0, chunk, uint32_t(r.pattern), r.items);
+    if (r.items.size() > before) r.item_dmax = std::max(r.item_dmax, row[u + 1] - row[u]);
+  }
+  r.stats.items = r.items.size();
+  r.footprint = sizeof(Item) * r.items.size() + sizeof(uint64_t);
+  std::vector<uint32_t>().swap(r.roots);
+}
+
+void Server::enqueue_expanded(const std::shared_ptr<Request>& r) {
+  if (r->items.empty()) {
+    // no instance can be rooted here: done without device work
+    r->finished = true;
+    r->stats.t_admit_ns = r->stats.t_done_ns = now_ns();
+    done.push_back(r);
+  } else {
+    queue.push_back(r);
+  }
+}
+
+void Server::expand_loop(uint32_t w) {
+  for (;;) {
+    std::shared_ptr<Request> r;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_incoming.wait(lk, [&] { return stop || !incoming.empty(); });
+      if (stop) return;  // eh_server_destroy cancels what is left
+      r = incoming.front();
+      incoming.pop_front();
+    }
+    expand(*r, dedup[w]);
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      if (stop) {
+        r->finished = true;
+        r->count = 0;
+        r->stats.t_done_ns = now_ns();
+        by_ticket.erase(r->ticket);
+      } else {
+        enqueue_expanded(r);
+      }
+    }
+    cv_work.notify_one();
+    cv_done.notify_all();
+  }
+}
+
 }  // namespace eh
 
 struct eh_server {
@@ -237,8 +347,9 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
   Server& s = x->s;
   s.c = c;
   s.t = t;
+  s.tune = c->tune;
   if (opts) s.o = *opts;
-  if (!s.o.hbm_budget_bytes) s.o.hbm_budget_bytes = 256ull << 20;
+  if (!s.o.hbm_budget_bytes) s.o.hbm_budget_bytes = 2ull << 30;
   if (!s.o.max_active) s.o.max_active = 256;
   if (!s.o.max_queued) s.o.max_queued = 4096;
   if (!s.o.step_items) s.o.step_items = 1 << 18;
@@ -247,6 +358,7 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
     st = hip_check(c, hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking), "server stream");
   if (st == EH_OK) st = dev_alloc(c, s.items_d, sizeof(Item) * s.o.step_items);
   if (st == EH_OK) st = dev_alloc(c, s.acc_d, sizeof(uint64_t) * s.o.max_active);
+  if (st == EH_OK) st = dev_alloc(c, s.cursor, sizeof(uint32_t) * kCursorWords * kMaxParts);
   if (st == EH_OK)
     st = hip_check(c, hipHostMalloc((void**)&s.items_h, sizeof(Item) * s.o.step_items,
                                     hipHostMallocDefault), "pinned items");
@@ -256,6 +368,7 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
   if (st != EH_OK) {
     dev_free(c, s.items_d);
     dev_free(c, s.acc_d);
+    dev_free(c, s.cursor);
     if (s.items_h) (void)hipHostFree(s.items_h);
     if (s.acc_h) (void)hipHostFree(s.acc_h);
     if (s.stream) (void)hipStreamDestroy(s.stream);
@@ -263,11 +376,26 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
     return st;
   }
   for (uint32_t i = s.o.max_active; i-- > 0;) s.free_slots.push_back(i);
+  const HostTrie& h = t->host;
+  s.chunk = std::max<uint32_t>(s.tune.chunk_work, 64);
+  // the items with every vertex a root bound any request's footprint: when
+  // that fits the budget, no request can be refused for its size, and
+  // submission can leave the expansion to the workers
+  for (uint32_t p : {uint32_t(EH_TRIANGLE), uint32_t(EH_4CLIQUE)}) {
+    uint64_t all = 0;
+    for (uint32_t u = 0; u < h.n; ++u) all += count_items_estimated(h, u, s.chunk, p);
+    s.async_ok[p] = all * sizeof(Item) + sizeof(uint64_t) <= s.o.hbm_budget_bytes;
+  }
+  const uint32_t hw = std::max(1u, std::thread::hardware_concurrency());
+  const uint32_t n_workers = std::min(4u, std::max(1u, hw / 4));
   try {
-    s.stamp.assign(t->host.n, 0u);
+    s.sync_dedup.stamp.assign(h.n, 0u);
+    s.dedup.resize(n_workers);
+    for (auto& d : s.dedup) d.stamp.assign(h.n, 0u);
   } catch (const std::bad_alloc&) {
     dev_free(c, s.items_d);
     dev_free(c, s.acc_d);
+    dev_free(c, s.cursor);
     (void)hipHostFree(s.items_h);
     (void)hipHostFree(s.acc_h);
     (void)hipStreamDestroy(s.stream);
@@ -275,6 +403,7 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
     return EH_ENOMEM;
   }
   s.th = std::thread([&s] { s.run(); });
+  for (uint32_t w = 0; w < n_workers; ++w) s.workers.emplace_back([&s, w] { s.expand_loop(w); });
   *out = x;
   return EH_OK;
 }
@@ -290,45 +419,34 @@ eh_status eh_submit(eh_server* srv, int pattern, const uint32_t* roots, uint32_t
   r->stats.t_submit_ns = now_ns();
   for (uint32_t i = 0; i < n_roots; ++i)
     if (roots[i] >= h.n) return EH_EINVAL;
-  // roots are a set: drop repeats with a stamp per vertex (O(n_roots)), then
-  // cut each root's out-list into items whose size is estimated from its
-  // out-degree alone, so a submit costs time proportional to its roots
-  const uint32_t chunk = std::max<uint32_t>(s.c->tune.chunk_work, 64);
-  {
-    std::lock_guard<std::mutex> lk(s.stamp_mu);
-    if (++s.epoch == 0) {
-      std::fill(s.stamp.begin(), s.stamp.end(), 0u);
-      s.epoch = 1;
+  r->roots.assign(roots, roots + n_roots);
+  const bool async = s.async_ok[pattern];
+  if (!async) {
+    {
+      std::lock_guard<std::mutex> lk(s.sync_mu);
+      s.expand(*r, s.sync_dedup);
     }
-    for (uint32_t i = 0; i < n_roots; ++i) {
-      const uint32_t u = h.rank[roots[i]];
-      if (s.stamp[u] == s.epoch) continue;
-      s.stamp[u] = s.epoch;
-      make_items_estimated(h, u, 0, chunk, uint32_t(pattern), r->items);
-    }
+    if (r->footprint > s.o.hbm_budget_bytes) return EH_ENOMEM;
   }
-  r->stats.items = r->items.size();
-  r->footprint = sizeof(Item) * r->items.size() + sizeof(uint64_t);
-  if (r->footprint > s.o.hbm_budget_bytes) return EH_ENOMEM;
   {
     std::unique_lock<std::mutex> lk(s.mu);
     if (s.stop) return EH_ESTATE;
     if (!s.fatal.empty()) return EH_EHIP;
-    if (s.queue.size() >= s.o.max_queued) return EH_EBUSY;
+    if (s.queue.size() + s.incoming.size() >= s.o.max_queued) return EH_EBUSY;
     r->ticket = s.next_ticket++;
     *ticket = r->ticket;
     s.by_ticket[r->ticket] = r;
-    if (r->items.empty()) {
-      // no instance can be rooted here: done without device work
-      r->finished = true;
-      r->stats.t_admit_ns = r->stats.t_done_ns = now_ns();
-      s.done.push_back(r);
-    } else {
-      s.queue.push_back(r);
-    }
+    if (async)
+      s.incoming.push_back(r);
+    else
+      s.enqueue_expanded(r);
   }
-  s.cv_work.notify_one();
-  s.cv_done.notify_all();
+  if (async) {
+    s.cv_incoming.notify_one();
+  } else {
+    s.cv_work.notify_one();
+    s.cv_done.notify_all();
+  }
   return EH_OK;
 }
 
@@ -405,11 +523,27 @@ eh_status eh_server_destroy(eh_server* srv) {
     std::unique_lock<std::mutex> lk(s.mu);
     s.stop = true;
   }
+  s.cv_incoming.notify_all();
   s.cv_work.notify_all();
+  for (auto& w : s.workers)
+    if (w.joinable()) w.join();
   if (s.th.joinable()) s.th.join();
+  {
+    // cancel what was never expanded
+    std::unique_lock<std::mutex> lk(s.mu);
+    for (auto& r : s.incoming) {
+      r->finished = true;
+      r->count = 0;
+      r->stats.t_done_ns = now_ns();
+      s.by_ticket.erase(r->ticket);
+    }
+    s.incoming.clear();
+  }
+  s.cv_done.notify_all();
   (void)hipStreamSynchronize(s.stream);
   dev_free(s.c, s.items_d);
   dev_free(s.c, s.acc_d);
+  dev_free(s.c, s.cursor);
   if (s.items_h) (void)hipHostFree(s.items_h);
   if (s.acc_h) (void)hipHostFree(s.acc_h);
   (void)hipStreamDestroy(s.stream);

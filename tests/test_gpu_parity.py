@@ -120,6 +120,53 @@ def test_4cliques_zoo(ctx, eh, tname, lay):
         assert got == K, (el.name, tname, lay[0])
 
 
+@pytest.mark.parametrize("dyn", [0, 4])
+def test_4cliques_high_out_degree(ctx, eh, dyn):
+    """Out-degrees above 512 and 1024, the S-list sizes of the 4-clique kernel
+    instances: items whose root has a longer out-list run in a second launch.
+    Complete graphs are pinned by closed forms (K = C(n, 4); all degrees tie,
+    so rank = id and vertex i roots C(n-1-i, 3) 4-cliques); a disjoint union
+    with a sparse graph adds the oracle's counts for the sparse part."""
+    from math import comb
+    tune(ctx, kernel=1, staging=1, dynamic=dyn, grab=2)
+    for n in (600, 1100):
+        trie = ctx.build_edgelist(inputs.complete(n))
+        try:
+            assert trie.info["max_out_degree"] == n - 1
+            assert ctx.count_4cliques(trie) == comb(n, 4)
+            roots = np.array([0, 1, 300, n // 2, n - 4, n - 1], np.uint32)  # a set: 300 may repeat
+            want = sum(comb(n - 1 - int(i), 3) for i in np.unique(roots))
+            assert ctx.count_rooted(trie, eh.CLIQUE4, roots) == want
+        finally:
+            trie.free()
+    sparse = inputs.rmat(9, 16, seed=9)
+    gs = oracle.Graph.from_edgelist(sparse).cliques4(rooted=True)
+    k = 600
+    un = inputs.disjoint_union(inputs.complete(k), sparse)
+    trie = ctx.build_edgelist(un)
+    srv = None
+    try:
+        assert ctx.count_4cliques(trie) == comb(k, 4) + gs["count"]
+
+        def want(roots):
+            return sum(comb(k - 1 - int(i), 3) if i < k else int(gs["root"][i - k]) for i in roots)
+
+        key = inputs.stream_key(11, 3)
+        sets = [np.array([0, 5, 599, 600, 601], np.uint32),
+                (inputs.rand_u64(key, 0, 300) % np.uint64(un.n)).astype(np.uint32),
+                np.arange(k, un.n, dtype=np.uint32), np.arange(0, 40, dtype=np.uint32)]
+        for r in sets:
+            assert ctx.count_rooted(trie, eh.CLIQUE4, r) == want(np.unique(r))
+        srv = ctx.server(trie, step_items=512)
+        tickets = [srv.submit(eh.CLIQUE4, r) for r in sets]
+        for t, r in zip(tickets, sets):
+            assert srv.wait(t).count == want(np.unique(r))
+    finally:
+        if srv is not None:
+            srv.close()
+        trie.free()
+
+
 @pytest.mark.parametrize("tname", ["staged_source", "pair_auto", "staged_global"])
 def test_per_root(ctx, eh, tname):
     tune(ctx, **TUNINGS[tname])
