@@ -223,10 +223,14 @@ def main():
     from paper_1503_02368_amd import eh
     from paper_1503_02368_amd.workloads import WORKLOADS, make_batch, make_graph
     ctx = eh.Context(0)
+    # entries of other workloads are kept: from --out if it exists, else
+    # from the package's tuning.json
     result = {}
-    if os.path.exists(args.out):
-        with open(args.out) as f:
-            result = json.load(f)
+    for src in (args.out, DEFAULT_OUT):
+        if os.path.exists(src):
+            with open(src) as f:
+                result = json.load(f)
+            break
     for name in args.workload:
         w = WORKLOADS[name]
         t0 = time.time()

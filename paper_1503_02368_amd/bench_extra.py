@@ -87,7 +87,10 @@ def bench_batch(name, w, args, ctx, eh, torch, metric):
                 "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                              "frac": achieved / 8000.0, "traffic": None,
                              "algorithmic_bytes_per_launch": info["b_merge"], "model": "B_merge"}}
-    # one launch per graph, eager
+    # one launch per graph, eager, on the static schedule: a per-graph launch
+    # is too small for the cursor schedules to pay for their reset
+    tuned = ctx.get_tuning()
+    ctx.set_tuning(dynamic=0)
     per = torch.zeros(G, dtype=torch.int64, device="cuda")
     for i in range(min(G, 64)):
         ctx.count_batch_async(trie, pattern, i, 1, per[i:i + 1])
@@ -125,6 +128,7 @@ def bench_batch(name, w, args, ctx, eh, torch, metric):
         if "differ" in str(e):
             raise
         log(f"[bench] graph capture unavailable: {e}")
+    ctx.set_tuning(**tuned)
     if not np.array_equal(per_np, one):
         raise RuntimeError("per-graph launches and the single launch disagree")
     m_plus = info["m_plus"]
