@@ -381,3 +381,65 @@ def test_server_drain(ctx, eh):
     finally:
         srv.close()
         trie.free()
+
+
+def test_server_concurrent_submitters(ctx, eh):
+    """Several host threads submit and wait at once (submission only copies
+    roots; expansion workers and the progress thread do the rest): every
+    answer equals the oracle's."""
+    import threading
+    tune(ctx)
+    el = inputs.rmat(12, 16, seed=43)
+    g = oracle.Graph.from_edgelist(el)
+    tabs = {3: g.triangles(rooted=True)["root"], 4: g.cliques4(rooted=True)["root"]}
+    trie = ctx.build_edgelist(el)
+    reqs = inputs.request_stream(el.n, rate_qps=4000, duration_s=0.05, seed=12, log2_lo=1, log2_hi=11)
+    srv = ctx.server(trie, step_items=300)
+    errors, got = [], {}
+
+    def client(k):
+        try:
+            mine = reqs[k::4]
+            tickets = [srv.submit(r.pattern, r.roots) for r in mine]
+            for r, t in zip(mine, tickets):
+                got[id(r)] = (srv.wait(t).count, oracle.rooted_count(tabs[r.pattern], r.roots))
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append(e)
+
+    try:
+        threads = [threading.Thread(target=client, args=(k,)) for k in range(4)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join(120)
+        assert not errors, errors
+        assert len(got) == len(reqs)
+        assert all(a == b for a, b in got.values())
+    finally:
+        srv.close()
+        trie.free()
+
+
+def test_server_close_with_pending(ctx, eh):
+    """Closing a server with requests still queued or being expanded returns
+    (finishing admitted work, cancelling the rest), and a new server on the
+    same trie answers correctly afterwards."""
+    tune(ctx)
+    el = inputs.rmat(13, 16, seed=44)
+    g = oracle.Graph.from_edgelist(el)
+    rk = g.cliques4(rooted=True)["root"]
+    trie = ctx.build_edgelist(el)
+    try:
+        big = np.arange(el.n, dtype=np.uint32)
+        srv = ctx.server(trie, step_items=64, max_active=2)
+        for _ in range(40):
+            srv.submit(eh.CLIQUE4, big)
+        srv.close()
+        srv = ctx.server(trie)
+        try:
+            t = srv.submit(eh.CLIQUE4, big[:1000])
+            assert srv.wait(t).count == oracle.rooted_count(rk, big[:1000])
+        finally:
+            srv.close()
+    finally:
+        trie.free()
