@@ -86,7 +86,7 @@ const char* eh_last_error(const eh_ctx* ctx);
 const char* eh_status_str(eh_status s);
 /* Version of this ABI (major * 10000 + minor * 100 + patch); a caller built
  * against this header checks that the library returns EH_ABI_VERSION. */
-#define EH_ABI_VERSION 10100
+#define EH_ABI_VERSION 10200
 int32_t eh_abi_version(void);
 
 /* ---- tuning knobs (performance only; counts never depend on them) ------- */
@@ -124,6 +124,10 @@ typedef struct eh_tuning {
                             4 (more waves per CU) or 8; 0 means 8 */
   uint32_t grab;         /* schedule 4: consecutive items per cursor fetch, at most 4096;
                             0 means 8 */
+  uint32_t search_below; /* staged kernels: when the streamed sets of a batch of 64 average
+                            fewer elements than this, each element's set is found by a
+                            binary search of the batch's length prefix instead of a walk
+                            along it; at most 4096, 0 never searches */
 } eh_tuning;
 
 eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t);

@@ -28,7 +28,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tuning.json")
 
 BASE = dict(kernel=1, staging=2, algo=0, gamma=32.0, chunk_work=4096, waves_per_cu=32,
-            group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0, xcds=0, unroll=8, grab=8)
+            group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0, xcds=0, unroll=8, grab=8,
+            search_below=24)
 # schedules tried last: (dynamic, grab); 3 and 4 cut the items into one range per XCD
 SCHEDULES = [(1, 8), (2, 8), (3, 8), (4, 1), (4, 4), (4, 16)]
 
@@ -120,6 +121,14 @@ def tune_graph(el, pattern, layouts, ctx, torch, quick=False):
                 ctx.set_tuning(**cfg)
                 ms, c = timer.graph(trie, pattern)
                 S.record(dict(layout=layout, tau=tau, tuning=cfg), ms, c)
+                if ms < local[0]:
+                    local = (ms, cfg)
+            if local[1]["kernel"] == 1:
+                for sb in (12, 16, 32, 48):
+                    cfg = dict(local[1], search_below=sb)
+                    ctx.set_tuning(**cfg)
+                    ms, c = timer.graph(trie, pattern)
+                    S.record(dict(layout=layout, tau=tau, tuning=cfg), ms, c)
             if local[1]["kernel"] == eh.KERNEL_PAIRWISE:
                 for g, al, gm in itertools.product([4, 16, 64], [0, 1, 2], [8.0, 32.0, 128.0]):
                     cfg = dict(local[1], group_lanes=g, algo=al, gamma=gm)
@@ -168,7 +177,12 @@ def tune_batch(b, pattern, layouts, ctx, torch, quick=False):
             unrolls = [4, 8] if local[1]["kernel"] == 1 else [8]
             for wv, un, (dyn, grab) in itertools.product([16, 24, 32], unrolls,
                                                           [(0, 8), (3, 8), (4, 4), (4, 16), (4, 64)]):
-                run(dict(local[1], waves_per_cu=wv, unroll=un, dynamic=dyn, grab=grab))
+                ms = run(dict(local[1], waves_per_cu=wv, unroll=un, dynamic=dyn, grab=grab))
+                if ms < local[0]:
+                    local = (ms, dict(local[1], waves_per_cu=wv, unroll=un, dynamic=dyn, grab=grab))
+            if local[1]["kernel"] == 1:
+                for sb in (12, 16, 32, 48):
+                    run(dict(local[1], search_below=sb))
         finally:
             trie.free()
     return S

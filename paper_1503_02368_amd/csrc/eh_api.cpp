@@ -154,6 +154,7 @@ LaunchArgs base_args(Ctx* c, const Trie& t) {
   a.xcds = c->tune.xcds;
   a.unroll = c->tune.unroll;
   a.grab = c->tune.grab;
+  a.search_below = c->tune.search_below;
   return a;
 }
 
@@ -344,6 +345,11 @@ eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t) {
   }
   u.unroll = t->unroll ? t->unroll : 8;
   u.grab = t->grab ? t->grab : 8;
+  if (t->search_below > 4096) {
+    ctx->c.err = "search_below must be at most 4096";
+    return EH_EINVAL;
+  }
+  u.search_below = t->search_below;
   return EH_OK;
 }
 
@@ -363,6 +369,7 @@ eh_status eh_ctx_get_tuning(const eh_ctx* ctx, eh_tuning* out) {
   out->xcds = u.xcds;
   out->unroll = u.unroll;
   out->grab = u.grab;
+  out->search_below = u.search_below;
   return EH_OK;
 }
 

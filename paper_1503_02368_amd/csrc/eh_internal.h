@@ -87,6 +87,7 @@ struct Tuning {
   uint32_t xcds = 0;
   uint32_t unroll = 8;
   uint32_t grab = 8;
+  uint32_t search_below = 24;
 };
 
 struct Ctx;
@@ -196,6 +197,7 @@ struct LaunchArgs {
   uint32_t xcds = 0;                   // L2 domains for the static schedule remap
   uint32_t unroll = 8;                 // staged triangle kernel: 4 or 8
   uint32_t grab = 8;                   // schedule 4: items per cursor fetch
+  uint32_t search_below = 24;          // average segment length below which the walk searches
 };
 eh_status launch_fill_u64(Ctx* c, hipStream_t s, unsigned long long* p, uint64_t n,
                           unsigned long long v);

@@ -64,6 +64,7 @@ struct DevArgs {
   uint32_t xcds;
   uint32_t grab;
   uint32_t deg_lo, deg_hi;  // 4-clique: items with deg_lo < d+(u) <= deg_hi
+  uint32_t search_below;    // segments shorter on average: the walk binary-searches
 };
 
 DevArgs to_dev(const LaunchArgs& a) {
@@ -92,6 +93,7 @@ DevArgs to_dev(const LaunchArgs& a) {
   d.grab = a.grab;
   d.deg_lo = a.deg_lo;
   d.deg_hi = a.deg_hi;
+  d.search_below = a.search_below;
   return d;
 }
 
@@ -485,6 +487,25 @@ struct SegCursor {
       bits = (sb & kHiBit) != 0;
     }
   }
+  // For short segments, where one step of 64 crosses several: the segment
+  // of f by a branch-free binary search of the prefix table (P[0] = 0 <= f
+  // < E, and entries past the last segment equal E), six LDS reads.
+  __device__ __forceinline__ void find(const SegTab& T, uint32_t f) {
+    uint32_t p = 0;
+#pragma unroll
+    for (uint32_t s = uint32_t(kSeg) / 2; s >= 1; s >>= 1)
+      if (T.P[p + s] <= f) p += s;
+    const uint32_t start = T.P[p];
+    const uint32_t sb = T.SB[p];
+    base = (sb & kMaxIndex) - start;
+    wbase = uint32_t(T.SM[p]) - start;
+    bits = (sb & kHiBit) != 0;
+  }
+  template <bool kSearch>
+  __device__ __forceinline__ void locate(const SegTab& T, uint32_t f) {
+    if (kSearch) find(T, f);
+    else seek(T, f);
+  }
 };
 
 // Walks flat indices lane, lane+64, ... < E of the segment table and counts
@@ -492,7 +513,7 @@ struct SegCursor {
 // element costs the same: a uint value x tests bit x - base, a bitset word
 // is ANDed with the bitmap word it overlaps, both as popc(R[w] & mask).  A
 // composite set's members below its window are found by searching its prefix.
-template <int RW, int U, bool kComposite>
+template <int RW, int U, bool kComposite, bool kSearch>
 __device__ __forceinline__ uint32_t flat_probe_bits(const DevArgs& a, const SegTab& T, uint32_t E,
                                                     const Staged& st, const uint32_t* R,
                                                     const uint32_t* Lp, uint32_t lane) {
@@ -511,7 +532,7 @@ __device__ __forceinline__ uint32_t flat_probe_bits(const DevArgs& a, const SegT
       key[u] = 0;
       bits[u] = false;
       if (ok[u]) {
-        c.seek(T, f);
+        c.locate<kSearch>(T, f);
         val[u] = L[c.base + f];
         key[u] = c.wbase + f;
         bits[u] = c.bits;
@@ -529,12 +550,19 @@ __device__ __forceinline__ uint32_t flat_probe_bits(const DevArgs& a, const SegT
   return cnt;
 }
 
+// nseg: segments in the table.  When they average fewer than search_below
+// elements, each element's segment is binary-searched instead of walked to.
 template <int RW, int U>
 __device__ __forceinline__ uint32_t flat_probe(const DevArgs& a, const SegTab& T, uint32_t E,
-                                               const Staged& st, const uint32_t* R,
+                                               uint32_t nseg, const Staged& st, const uint32_t* R,
                                                const uint32_t* Lp, uint32_t lane) {
-  if (st.mode == kModeBitmap) return flat_probe_bits<RW, U, false>(a, T, E, st, R, Lp, lane);
-  if (st.mode == kModeComposite) return flat_probe_bits<RW, U, true>(a, T, E, st, R, Lp, lane);
+  const bool search = E < nseg * a.search_below;
+  if (st.mode == kModeBitmap)
+    return search ? flat_probe_bits<RW, U, false, true>(a, T, E, st, R, Lp, lane)
+                  : flat_probe_bits<RW, U, false, false>(a, T, E, st, R, Lp, lane);
+  if (st.mode == kModeComposite)
+    return search ? flat_probe_bits<RW, U, true, true>(a, T, E, st, R, Lp, lane)
+                  : flat_probe_bits<RW, U, true, false>(a, T, E, st, R, Lp, lane);
   const uint32_t* __restrict__ L = a.col;
   uint32_t cnt = 0;
   SegCursor c(T);
@@ -627,7 +655,7 @@ void k_tri_staged(DevArgs a) {
         }
       }
       const uint32_t E = publish_segments(T, g, lane);
-      cnt += flat_probe<RW, U>(a, T, E, st, R, Lp, lane);
+      cnt += flat_probe<RW, U>(a, T, E, nseg, st, R, Lp, lane);
     }
     acc += cnt;
     if (a.per_root) {
@@ -732,7 +760,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
           if (lane < nseg) g = seg_full(a, S[b0 + lane], wr);
           const uint32_t E = publish_segments(T, g, lane);
           // bitmap bounds are B's (RW words); the list S is searched by length
-          cnt += flat_probe<RW, U>(a, T, E, ss, probe, Lp, lane);
+          cnt += flat_probe<RW, U>(a, T, E, nseg, ss, probe, Lp, lane);
         }
       }
       wave_sync();

@@ -50,7 +50,7 @@ class _Allocator(ctypes.Structure):
 
 
 # struct layouts below are those of this ABI version of include/eh.h
-ABI_VERSION = 10100
+ABI_VERSION = 10200
 
 
 class _Tuning(ctypes.Structure):
@@ -59,7 +59,8 @@ class _Tuning(ctypes.Structure):
                 ("waves_per_cu", ctypes.c_uint32), ("group_lanes", ctypes.c_uint32),
                 ("use_bitsets", ctypes.c_uint32), ("dynamic", ctypes.c_uint32),
                 ("stage_words", ctypes.c_uint32), ("xcds", ctypes.c_uint32),
-                ("unroll", ctypes.c_uint32), ("grab", ctypes.c_uint32)]
+                ("unroll", ctypes.c_uint32), ("grab", ctypes.c_uint32),
+                ("search_below", ctypes.c_uint32)]
 
 
 class _BuildOpts(ctypes.Structure):

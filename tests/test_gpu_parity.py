@@ -76,9 +76,14 @@ TUNINGS = {
     "staged_part": dict(kernel=1, staging=2, use_bitsets=1, dynamic=3, xcds=0),
     "staged_steal": dict(kernel=1, staging=1, use_bitsets=1, dynamic=4, xcds=5, grab=3),
     "pair_steal": dict(kernel=2, algo=0, use_bitsets=1, group_lanes=8, dynamic=4, xcds=8, grab=1),
+    # every streamed element's set found by binary search, or never
+    "staged_search": dict(kernel=1, staging=2, use_bitsets=1, search_below=4096),
+    "staged_search_src": dict(kernel=1, staging=1, use_bitsets=1, search_below=4096, stage_words=512),
+    "staged_walk": dict(kernel=1, staging=2, use_bitsets=1, search_below=0),
 }
 DEFAULT = dict(kernel=1, staging=2, algo=0, gamma=32.0, chunk_work=4096, waves_per_cu=32,
-               group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0, xcds=0, unroll=8, grab=8)
+               group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0, xcds=0, unroll=8, grab=8,
+               search_below=24)
 
 
 def tune(ctx, **kw):
@@ -107,7 +112,7 @@ def test_triangles_zoo(ctx, eh, tname, lay):
 
 @pytest.mark.parametrize("lay", LAYOUTS[:3], ids=lambda x: x[0])
 @pytest.mark.parametrize("tname", ["staged_source", "staged_nobits", "staged_list", "staged_global",
-                                   "staged_half", "staged_steal"])
+                                   "staged_half", "staged_steal", "staged_search_src"])
 def test_4cliques_zoo(ctx, eh, tname, lay):
     tune(ctx, **TUNINGS[tname])
     for el in ZOO:
@@ -243,7 +248,7 @@ def small_batch(num=120, seed=4):
 
 
 @pytest.mark.parametrize("tname", ["staged_target", "staged_source", "pair_auto", "staged_part",
-                                   "staged_steal"])
+                                   "staged_steal", "staged_search"])
 def test_batch(ctx, eh, tname):
     tune(ctx, **TUNINGS[tname])
     b = small_batch()
@@ -342,7 +347,8 @@ def test_full_size_rmat20_triangles(ctx, eh):
     say("oracle T", T)
     trie = ctx.build_edgelist(el)
     try:
-        for tname in ("staged_target", "staged_source", "pair_auto", "staged_part", "staged_steal"):
+        for tname in ("staged_target", "staged_source", "pair_auto", "staged_part", "staged_steal",
+                      "staged_search", "staged_walk"):
             tune(ctx, **TUNINGS[tname])
             got = ctx.count_triangles(trie)
             say(tname, got)
