@@ -30,8 +30,8 @@
  *     outputs are written only when the call returns EH_OK.
  *   - Blocking calls return after their result is on the host.  *_async
  *     calls only enqueue work on the context's stream.
- *   - A context is used by one host thread at a time; eh_submit and eh_poll
- *     are thread-safe.
+ *   - A context is used by one host thread at a time; eh_submit, eh_poll,
+ *     eh_wait and eh_server_drain are thread-safe.
  */
 #ifndef EH_H_
 #define EH_H_

@@ -8,17 +8,20 @@
 //
 // Two kernel families consume the same work items {s, idx[lbeg..+llen), tag}:
 //
-// * Staged ("k_*_staged"): one wave per item.  The set N+(s) is written into
-//   the wave's LDS region once, as a bitset over [min, max] when that range
-//   fits (the bitset layout of section 4.1 with one block of the set's range,
-//   as the set optimizer of section 4.4 builds it), else as a sorted list.
-//   The sets N+(t) of all streamed vertices t are concatenated into one flat
-//   index space that the 64 lanes walk with a per-lane segment cursor, so
-//   short and long lists alike keep every lane busy and reads coalesced.
-//   Each streamed element is tested against the staged set: a bit probe
-//   (uint & bitset, section 4.2), or, when t's set is stored as a bitset
-//   with fewer words than elements, a 32-bit word AND + popcount (bitset &
-//   bitset), or a binary search in the staged list (galloping).
+// * Staged ("k_*_staged"): one wave per item.  The staged set is written
+//   into the wave's LDS region once, as a bitset over [min, max] when that
+//   range fits (the bitset layout of section 4.1 with one block of the set's
+//   range, as the set optimizer of section 4.4 builds it), else as a bitset
+//   over its top window plus a searched prefix (a two-block composite,
+//   section 4.3).  The streamed sets are concatenated into one flat index
+//   space that the 64 lanes walk, each lane finding its element's set by a
+//   cursor along the batch's length prefix (long sets) or a binary search of
+//   it (short sets), so short and long lists alike keep every lane busy and
+//   reads coalesced.  Each streamed element is tested against the staged set:
+//   a bit probe (uint & bitset, section 4.2), or, when the streamed set is
+//   stored as a bitset with fewer words than elements, a 32-bit word AND +
+//   popcount (bitset & bitset), or a binary search of the composite's prefix
+//   (galloping).
 //
 // * Pairwise ("k_tri_pairwise"): a group of G lanes per pair (s, t) reading
 //   both sets from HBM, dispatching per pair on the layouts and sizes as in
@@ -379,12 +382,12 @@ __device__ __forceinline__ uint32_t staged_has(const DevArgs& a, const Staged& s
   return st.mode == kModeComposite ? prefix_has(a, st, Lp, x) : 0u;
 }
 
-// Segment table of one flat batch: P = prefix of lengths (kSeg+1),
-// SB = start in the list buffer (kHiBit: bitset words), SM = word delta.
+// Segment table of one flat batch: P = prefix of lengths (kSeg+1), and per
+// segment {start in the list buffer (kHiBit: bitset words), word delta},
+// read together as one 64-bit LDS load.
 struct SegTab {
   uint32_t* P;
-  uint32_t* SB;
-  int32_t* SM;
+  uint2* S;
 };
 
 // One streamed segment: start in the list buffer (col, then bitset words;
@@ -455,8 +458,7 @@ __device__ __forceinline__ uint32_t publish_segments(const SegTab& T, const Seg&
   wave_sync();  // previous batch's readers are done
   T.P[lane + 1] = incl;
   if (lane == 0) T.P[0] = 0;
-  T.SB[lane] = g.sb;
-  T.SM[lane] = g.sm;
+  T.S[lane] = uint2{g.sb, uint32_t(g.sm)};
   wave_sync();
   return uniform(__shfl(incl, kWave - 1, kWave));
 }
@@ -471,9 +473,10 @@ struct SegCursor {
   __device__ __forceinline__ explicit SegCursor(const SegTab& T) {
     j = 0;
     nxt = T.P[1];
-    const uint32_t sb = T.SB[0];
+    const uint2 sg = T.S[0];
+    const uint32_t sb = sg.x;
     base = sb & kMaxIndex;
-    wbase = uint32_t(T.SM[0]);
+    wbase = sg.y;
     bits = (sb & kHiBit) != 0;
   }
   __device__ __forceinline__ void seek(const SegTab& T, uint32_t f) {
@@ -481,9 +484,10 @@ struct SegCursor {
       const uint32_t start = nxt;
       ++j;
       nxt = T.P[j + 1];
-      const uint32_t sb = T.SB[j];
+      const uint2 sg = T.S[j];
+      const uint32_t sb = sg.x;
       base = (sb & kMaxIndex) - start;
-      wbase = uint32_t(T.SM[j]) - start;
+      wbase = sg.y - start;
       bits = (sb & kHiBit) != 0;
     }
   }
@@ -491,14 +495,19 @@ struct SegCursor {
   // of f by a branch-free binary search of the prefix table (P[0] = 0 <= f
   // < E, and entries past the last segment equal E), six LDS reads.
   __device__ __forceinline__ void find(const SegTab& T, uint32_t f) {
-    uint32_t p = 0;
+    uint32_t p = 0, start = 0;
 #pragma unroll
-    for (uint32_t s = uint32_t(kSeg) / 2; s >= 1; s >>= 1)
-      if (T.P[p + s] <= f) p += s;
-    const uint32_t start = T.P[p];
-    const uint32_t sb = T.SB[p];
+    for (uint32_t s = uint32_t(kSeg) / 2; s >= 1; s >>= 1) {
+      const uint32_t q = T.P[p + s];
+      if (q <= f) {
+        p += s;
+        start = q;
+      }
+    }
+    const uint2 sg = T.S[p];
+    const uint32_t sb = sg.x;
     base = (sb & kMaxIndex) - start;
-    wbase = uint32_t(T.SM[p]) - start;
+    wbase = sg.y - start;
     bits = (sb & kHiBit) != 0;
   }
   template <bool kSearch>
@@ -597,13 +606,12 @@ __global__ __launch_bounds__(WPB * kWave) __attribute__((amdgpu_waves_per_eu(6))
 void k_tri_staged(DevArgs a) {
   __shared__ uint32_t s_region[WPB][RW];
   __shared__ uint32_t s_pre[WPB][kSeg + 1];
-  __shared__ uint32_t s_sb[WPB][kSeg];
-  __shared__ int32_t s_sm[WPB][kSeg];
+  __shared__ uint2 s_seg[WPB][kSeg];
   __shared__ uint32_t s_pref[WPB][kPrefixCap];
   const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
   uint32_t* R = s_region[wid];
   uint32_t* Lp = s_pref[wid];
-  const SegTab T{s_pre[wid], s_sb[wid], s_sm[wid]};
+  const SegTab T{s_pre[wid], s_seg[wid]};
   for (uint32_t k = lane; k < uint32_t(RW); k += kWave) R[k] = 0;
   wave_sync();
   unsigned long long acc = 0;
@@ -679,15 +687,14 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
   __shared__ uint32_t s_B[WPB][RW];
   __shared__ uint32_t s_S[WPB][SCAP];
   __shared__ uint32_t s_pre[WPB][kSeg + 1];
-  __shared__ uint32_t s_sb[WPB][kSeg];
-  __shared__ int32_t s_sm[WPB][kSeg];
+  __shared__ uint2 s_seg[WPB][kSeg];
   __shared__ uint32_t s_pref[WPB][kPrefixCap];
   const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
   uint32_t* A = s_A[wid];
   uint32_t* B = s_B[wid];
   uint32_t* S = s_S[wid];
   uint32_t* Lp = s_pref[wid];
-  const SegTab T{s_pre[wid], s_sb[wid], s_sm[wid]};
+  const SegTab T{s_pre[wid], s_seg[wid]};
   for (uint32_t k = lane; k < uint32_t(RW); k += kWave) { A[k] = 0; B[k] = 0; }
   wave_sync();
   const unsigned long long lt_mask = (1ull << lane) - 1ull;

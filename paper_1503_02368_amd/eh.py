@@ -15,7 +15,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libeh.so")
+# the in-tree build; EH_LIBRARY names another build of the same ABI (for
+# comparing builds side by side)
+LIB_PATH = os.environ.get("EH_LIBRARY") or os.path.join(_HERE, "_lib", "libeh.so")
 
 # status codes and enums (eh.h)
 EH_OK, EH_PENDING = 0, 1
