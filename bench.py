@@ -20,7 +20,6 @@ Prints one JSON line.  Workloads (--workload):
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import statistics
@@ -35,20 +34,14 @@ import numpy as np  # noqa: E402
 
 METRIC = "edges/s triangle count (plain vs batched); HBM GB/s; p50/p99 query latency"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1503_02368_amd", "csrc", "eh_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 TUNING_FILE = os.path.join(ROOT, "paper_1503_02368_amd", "tuning.json")
 
+from paper_1503_02368_amd.bench_extra import measured_traffic  # noqa: E402
 from paper_1503_02368_amd.workloads import WORKLOADS, make_graph  # noqa: E402
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def kernel_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def load_tuning(name: str) -> dict:
@@ -57,18 +50,6 @@ def load_tuning(name: str) -> dict:
         with open(TUNING_FILE) as f:
             return json.load(f).get(name, {})
     return {}
-
-
-def measured_traffic(name: str, launches_per_step: int = 1):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
-    when the kernel source changed since they were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    with open(TRAFFIC_FILE) as f:
-        d = json.load(f).get(name)
-    if not d or d.get("kernel_sha") != kernel_sha():
-        return None
-    return d.get("bytes_per_launch")
 
 
 def cpu_baseline(el, pattern: int, budget_s: float = 20.0) -> dict:

@@ -13,6 +13,9 @@ request per blocking call on the same schedule runs beside it.
 """
 from __future__ import annotations
 
+import hashlib
+import json
+import os
 import statistics
 import sys
 import threading
@@ -20,9 +23,30 @@ import time
 
 import numpy as np
 
+_HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SRC = os.path.join(_HERE, "csrc", "eh_kernels.hip")
+TRAFFIC_FILE = os.path.join(os.path.dirname(_HERE), "profiles", "traffic.json")
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(name: str):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
+    when the kernel source changed since they were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        d = json.load(f).get(name)
+    if not d or d.get("kernel_sha") != kernel_sha():
+        return None
+    return d.get("bytes_per_launch")
 
 
 def load_tuning(name: str) -> dict:
@@ -85,7 +109,7 @@ def bench_batch(name, w, args, ctx, eh, torch, metric):
                 "config": {"workload": name, "graphs": G, "m_plus": info["m_plus"]},
                 "count_total": int(one.sum(dtype=np.uint64)),
                 "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                             "frac": achieved / 8000.0, "traffic": None,
+                             "frac": achieved / 8000.0, "traffic": measured_traffic(name),
                              "algorithmic_bytes_per_launch": info["b_merge"], "model": "B_merge"}}
     # one launch per graph, eager, on the static schedule: a per-graph launch
     # is too small for the cursor schedules to pay for their reset
@@ -148,7 +172,7 @@ def bench_batch(name, w, args, ctx, eh, torch, metric):
     }
     achieved = info["b_merge"] / (ms / 1e3) / 1e9
     res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                       "frac": achieved / 8000.0, "traffic": None,
+                       "frac": achieved / 8000.0, "traffic": measured_traffic(name),
                        "algorithmic_bytes_per_launch": info["b_merge"], "model": "B_merge"}
     if not args.no_cpu:
         import oracle

@@ -18,19 +18,14 @@ from __future__ import annotations
 import argparse
 import csv
 import glob
-import hashlib
 import json
 import os
 import statistics
 
+from paper_1503_02368_amd.bench_extra import kernel_sha
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-KERNEL_SRC = os.path.join(HERE, "csrc", "eh_kernels.hip")
-
-
-def kernel_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def _csv(d: str, suffix: str):
