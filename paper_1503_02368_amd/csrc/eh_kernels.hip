@@ -470,6 +470,7 @@ __device__ __forceinline__ uint32_t publish_segments(const SegTab& T, const Seg&
 struct SegCursor {
   uint32_t j, nxt, base, wbase;
   bool bits;
+  __device__ __forceinline__ SegCursor() {}
   __device__ __forceinline__ explicit SegCursor(const SegTab& T) {
     j = 0;
     nxt = T.P[1];
@@ -491,9 +492,9 @@ struct SegCursor {
       bits = (sb & kHiBit) != 0;
     }
   }
-  // For short segments, where one step of 64 crosses several: the segment
-  // of f by a branch-free binary search of the prefix table (P[0] = 0 <= f
-  // < E, and entries past the last segment equal E), six LDS reads.
+  // Places the cursor on the segment of f by a branch-free binary search of
+  // the prefix table (P[0] = 0 <= f < E, and entries past the last segment
+  // equal E): six LDS reads.
   __device__ __forceinline__ void find(const SegTab& T, uint32_t f) {
     uint32_t p = 0, start = 0;
 #pragma unroll
@@ -504,16 +505,13 @@ struct SegCursor {
         start = q;
       }
     }
+    j = p;
+    nxt = T.P[p + 1];
     const uint2 sg = T.S[p];
     const uint32_t sb = sg.x;
     base = (sb & kMaxIndex) - start;
     wbase = sg.y - start;
     bits = (sb & kHiBit) != 0;
-  }
-  template <bool kSearch>
-  __device__ __forceinline__ void locate(const SegTab& T, uint32_t f) {
-    if (kSearch) find(T, f);
-    else seek(T, f);
   }
 };
 
@@ -522,7 +520,7 @@ struct SegCursor {
 // element costs the same: a uint value x tests bit x - base, a bitset word
 // is ANDed with the bitmap word it overlaps, both as popc(R[w] & mask).  A
 // composite set's members below its window are found by searching its prefix.
-template <int RW, int U, bool kComposite, bool kSearch>
+template <int RW, int U, bool kComposite>
 __device__ __forceinline__ uint32_t flat_probe_bits(const DevArgs& a, const SegTab& T, uint32_t E,
                                                     const Staged& st, const uint32_t* R,
                                                     const uint32_t* Lp, uint32_t lane) {
@@ -541,7 +539,55 @@ __device__ __forceinline__ uint32_t flat_probe_bits(const DevArgs& a, const SegT
       key[u] = 0;
       bits[u] = false;
       if (ok[u]) {
-        c.locate<kSearch>(T, f);
+        c.seek(T, f);
+        val[u] = L[c.base + f];
+        key[u] = c.wbase + f;
+        bits[u] = c.bits;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t d = val[u] - base;
+      const uint32_t w = bits[u] ? key[u] : (d >> 5);
+      const uint32_t m = bits[u] ? val[u] : (1u << (d & 31));
+      if (ok[u] && w < uint32_t(RW)) cnt += __popc(R[w] & m);
+      else if (kComposite && ok[u] && !bits[u]) cnt += prefix_has(a, st, Lp, val[u]);
+    }
+  }
+  return cnt;
+}
+
+// The same count for short streamed sets, where one step of 64 would cross
+// several of them: lane l takes the contiguous flat range [l per, (l+1) per)
+// with per = ceil(E / 64), finds the set of its first element by a binary
+// search of the length prefix and walks on from there, so a set boundary
+// costs one cursor step instead of a search per element.
+template <int RW, int U, bool kComposite>
+__device__ __forceinline__ uint32_t flat_probe_bits_blocked(const DevArgs& a, const SegTab& T,
+                                                            uint32_t E, const Staged& st,
+                                                            const uint32_t* R, const uint32_t* Lp,
+                                                            uint32_t lane) {
+  const uint32_t* __restrict__ L = a.col;
+  const uint32_t per = (E + kWave - 1) / kWave;
+  const uint32_t f_beg = lane * per;
+  const uint32_t f_end = min(f_beg + per, E);
+  uint32_t cnt = 0;
+  if (f_beg >= f_end) return 0u;
+  SegCursor c;
+  c.find(T, f_beg);
+  const uint32_t base = st.base;
+  for (uint32_t f0 = f_beg; f0 < f_end; f0 += U) {
+    uint32_t val[U], key[U];
+    bool ok[U], bits[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t f = f0 + uint32_t(u);
+      ok[u] = f < f_end;
+      val[u] = 0;
+      key[u] = 0;
+      bits[u] = false;
+      if (ok[u]) {
+        c.seek(T, f);
         val[u] = L[c.base + f];
         key[u] = c.wbase + f;
         bits[u] = c.bits;
@@ -560,18 +606,18 @@ __device__ __forceinline__ uint32_t flat_probe_bits(const DevArgs& a, const SegT
 }
 
 // nseg: segments in the table.  When they average fewer than search_below
-// elements, each element's segment is binary-searched instead of walked to.
+// elements, lanes take contiguous ranges (flat_probe_bits_blocked).
 template <int RW, int U>
 __device__ __forceinline__ uint32_t flat_probe(const DevArgs& a, const SegTab& T, uint32_t E,
                                                uint32_t nseg, const Staged& st, const uint32_t* R,
                                                const uint32_t* Lp, uint32_t lane) {
   const bool search = E < nseg * a.search_below;
   if (st.mode == kModeBitmap)
-    return search ? flat_probe_bits<RW, U, false, true>(a, T, E, st, R, Lp, lane)
-                  : flat_probe_bits<RW, U, false, false>(a, T, E, st, R, Lp, lane);
+    return search ? flat_probe_bits_blocked<RW, U, false>(a, T, E, st, R, Lp, lane)
+                  : flat_probe_bits<RW, U, false>(a, T, E, st, R, Lp, lane);
   if (st.mode == kModeComposite)
-    return search ? flat_probe_bits<RW, U, true, true>(a, T, E, st, R, Lp, lane)
-                  : flat_probe_bits<RW, U, true, false>(a, T, E, st, R, Lp, lane);
+    return search ? flat_probe_bits_blocked<RW, U, true>(a, T, E, st, R, Lp, lane)
+                  : flat_probe_bits<RW, U, true>(a, T, E, st, R, Lp, lane);
   const uint32_t* __restrict__ L = a.col;
   uint32_t cnt = 0;
   SegCursor c(T);
