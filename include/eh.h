@@ -114,7 +114,9 @@ typedef struct eh_tuning {
                               take `grab` items per fetch and move on to the next range
                               when theirs is used up) */
   uint32_t stage_words;  /* staged kernels: LDS words for a held set (bitset range / 32, or
-                            list length), at most 1024; 0 means 1024 */
+                            list length), at most 1024; 0 means 1024.  At most 512
+                            selects the half-size kernel instances (more waves per CU;
+                            for triangles the unroll knob then does not apply) */
   uint32_t xcds;         /* L2 domains blocks are dealt to round-robin (8 on MI355X), at
                             most 32.  Schedules 0 and 2: each domain then takes a
                             contiguous slice of every window of items (0 or 1: no

@@ -107,7 +107,7 @@ def tune_graph(el, pattern, layouts, ctx, torch, quick=False):
             # refine the schedule of the best kernel on this layout
             chunks = [1024, 4096, 16384] if quick else [1024, 2048, 4096, 8192, 16384, 32768, 65536]
             waves = [16, 32] if quick else [8, 16, 24, 32, 40]
-            words = [0, 512] if pattern == 4 else [0]
+            words = [0, 512]
             unrolls = [4, 8] if pattern == 3 and local[1]["kernel"] == 1 else [8]
             for ch, wv, sw, un in itertools.product(chunks, waves, words, unrolls):
                 cfg = dict(local[1], chunk_work=ch, waves_per_cu=wv, stage_words=sw, unroll=un)
@@ -175,11 +175,15 @@ def tune_batch(b, pattern, layouts, ctx, torch, quick=False):
                 if local is None or ms < local[0]:
                     local = (ms, cfg)
             unrolls = [4, 8] if local[1]["kernel"] == 1 else [8]
-            for wv, un, (dyn, grab) in itertools.product([16, 24, 32], unrolls,
-                                                          [(0, 8), (3, 8), (4, 4), (4, 16), (4, 64)]):
-                ms = run(dict(local[1], waves_per_cu=wv, unroll=un, dynamic=dyn, grab=grab))
+            words = [0, 512] if local[1]["kernel"] == 1 else [0]
+            for wv, un, sw, (dyn, grab) in itertools.product([16, 24, 32, 40], unrolls, words,
+                                                              [(0, 8), (3, 8), (4, 4), (4, 16),
+                                                               (4, 64)]):
+                cfg = dict(local[1], waves_per_cu=wv, unroll=un, stage_words=sw, dynamic=dyn,
+                           grab=grab)
+                ms = run(cfg)
                 if ms < local[0]:
-                    local = (ms, dict(local[1], waves_per_cu=wv, unroll=un, dynamic=dyn, grab=grab))
+                    local = (ms, cfg)
             if local[1]["kernel"] == 1:
                 for sb in (12, 16, 32, 48):
                     run(dict(local[1], search_below=sb))

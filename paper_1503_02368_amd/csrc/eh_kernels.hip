@@ -647,9 +647,7 @@ __device__ __forceinline__ uint32_t flat_probe(const DevArgs& a, const SegTab& T
 // ---------------------------------------------------------------------------
 
 template <int WPB, int RW, int U>
-// at least 6 waves per SIMD: the LDS budget allows 7 blocks of 4 waves per CU
-__global__ __launch_bounds__(WPB * kWave) __attribute__((amdgpu_waves_per_eu(6)))
-void k_tri_staged(DevArgs a) {
+__device__ __forceinline__ void tri_staged(const DevArgs& a) {
   __shared__ uint32_t s_region[WPB][RW];
   __shared__ uint32_t s_pre[WPB][kSeg + 1];
   __shared__ uint2 s_seg[WPB][kSeg];
@@ -719,6 +717,22 @@ void k_tri_staged(DevArgs a) {
     unstage_set<RW>(a, st, R, lane);
   }
   if (have_tag) flush_tag(a, acc, cur_tag, lane);
+}
+
+// At least 6 waves per SIMD: the LDS budget allows 7 blocks of 4 waves per CU.
+template <int WPB, int RW, int U>
+__global__ __launch_bounds__(WPB * kWave) __attribute__((amdgpu_waves_per_eu(6)))
+void k_tri_staged(DevArgs a) {
+  tri_staged<WPB, RW, U>(a);
+}
+
+// Half-size staged region and two streamed elements in flight per lane: it
+// fits 64 VGPRs and 13 KB of LDS per block, so 8 waves per SIMD.  Many small
+// items are latency-bound, and more waves hide more of it.
+template <int WPB, int RW, int U>
+__global__ __launch_bounds__(WPB * kWave) __attribute__((amdgpu_waves_per_eu(8)))
+void k_tri_staged_lean(DevArgs a) {
+  tri_staged<WPB, RW, U>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1007,7 +1021,10 @@ eh_status launch_triangles(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t
     return hip_check(c, hipGetLastError(), "pairwise triangle kernel launch");
   }
   const uint32_t grid = grid_for(c, la.n_items, kTriWPB, waves_per_cu);
-  if (la.unroll == 4)
+  if (la.stage_words > 0 && la.stage_words <= uint32_t(kTriRW) / 2)
+    hipLaunchKernelGGL((k_tri_staged_lean<kTriWPB, kTriRW / 2, 2>), dim3(grid),
+                       dim3(kTriWPB * kWave), 0, s, a);
+  else if (la.unroll == 4)
     hipLaunchKernelGGL((k_tri_staged<kTriWPB, kTriRW, 4>), dim3(grid), dim3(kTriWPB * kWave), 0, s,
                        a);
   else

@@ -80,6 +80,8 @@ TUNINGS = {
     "staged_search": dict(kernel=1, staging=2, use_bitsets=1, search_below=4096),
     "staged_search_src": dict(kernel=1, staging=1, use_bitsets=1, search_below=4096, stage_words=512),
     "staged_walk": dict(kernel=1, staging=2, use_bitsets=1, search_below=0),
+    # half-size staged region: the 8-waves-per-SIMD triangle instance
+    "staged_lean": dict(kernel=1, staging=2, use_bitsets=1, stage_words=512, dynamic=4, grab=5),
 }
 DEFAULT = dict(kernel=1, staging=2, algo=0, gamma=32.0, chunk_work=4096, waves_per_cu=32,
                group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0, xcds=0, unroll=8, grab=8,
@@ -248,7 +250,7 @@ def small_batch(num=120, seed=4):
 
 
 @pytest.mark.parametrize("tname", ["staged_target", "staged_source", "pair_auto", "staged_part",
-                                   "staged_steal", "staged_search"])
+                                   "staged_steal", "staged_search", "staged_lean"])
 def test_batch(ctx, eh, tname):
     tune(ctx, **TUNINGS[tname])
     b = small_batch()
@@ -348,7 +350,7 @@ def test_full_size_rmat20_triangles(ctx, eh):
     trie = ctx.build_edgelist(el)
     try:
         for tname in ("staged_target", "staged_source", "pair_auto", "staged_part", "staged_steal",
-                      "staged_search", "staged_walk"):
+                      "staged_search", "staged_walk", "staged_lean"):
             tune(ctx, **TUNINGS[tname])
             got = ctx.count_triangles(trie)
             say(tname, got)
