@@ -451,3 +451,101 @@ def test_server_close_with_pending(ctx, eh):
             srv.close()
     finally:
         trie.free()
+
+
+def _el(n, pairs, name):
+    a = np.array(pairs, np.uint32).reshape(-1, 2)
+    return inputs.EdgeList(n, a[:, 0].copy(), a[:, 1].copy(), name)
+
+
+DEGENERATE = [
+    (_el(0, [], "no vertices"), 0, 0),
+    (_el(1, [], "one vertex"), 0, 0),
+    (_el(7, [], "no edges"), 0, 0),
+    (_el(3, [(0, 0), (1, 1), (2, 2)], "self-loops only"), 0, 0),
+    (_el(2, [(0, 1), (1, 0), (0, 1)], "one edge, repeated"), 0, 0),
+    (_el(5, [(0, 1), (1, 2), (2, 0)], "one triangle, isolated rest"), 1, 0),
+    (inputs.complete(4), 4, 1),
+]
+
+
+@pytest.mark.parametrize("tname", ["staged_target", "staged_source", "pair_auto", "staged_lean",
+                                   "staged_steal"])
+def test_degenerate_inputs(ctx, eh, tname):
+    """Empty and tiny graphs: zero vertices, no edges, self-loops only, one
+    edge, one triangle with isolated vertices, K4 -- totals, per-root
+    vectors, rooted requests and the server all give the exact answer."""
+    tune(ctx, **TUNINGS[tname])
+    for el, T, K in DEGENERATE:
+        trie = ctx.build_edgelist(el)
+        try:
+            assert ctx.count_triangles(trie) == T, el.name
+            assert ctx.count_4cliques(trie) == K, el.name
+            if tname == "staged_source":
+                tot, per = ctx.count_triangles(trie, per_root=True)
+                assert tot == T and int(per.sum()) == T and per.size == el.n, el.name
+            if el.n:
+                allv = np.arange(el.n, dtype=np.uint32)
+                assert ctx.count_rooted(trie, eh.TRIANGLE, allv) == T, el.name
+                assert ctx.count_rooted(trie, eh.CLIQUE4, allv) == K, el.name
+                srv = ctx.server(trie)
+                try:
+                    tickets = [srv.submit(eh.TRIANGLE, allv), srv.submit(eh.CLIQUE4, allv[:1])]
+                    assert srv.wait(tickets[0]).count == T, el.name
+                    assert srv.wait(tickets[1]).count == (K if el.n == 4 else 0), el.name
+                finally:
+                    srv.close()
+        finally:
+            trie.free()
+
+
+def test_batch_with_empty_graphs(ctx, eh):
+    """A batch mixing graphs with no vertices, no edges and tiny cliques with
+    ordinary ones: every per-graph count is exact, one launch or one per graph."""
+    tune(ctx)
+    parts = [el for el, _, _ in DEGENERATE] + [inputs.rmat(9, 8, seed=5), inputs.complete(40)]
+    parts = parts + parts[::-1]
+    srcs, dsts, off, nv = [], [], [0], []
+    for g in parts:
+        srcs.append(g.src)
+        dsts.append(g.dst)
+        off.append(off[-1] + g.m_raw)
+        nv.append(g.n)
+    b = inputs.BatchEdges(np.array(nv, np.uint32), np.array(off, np.uint64),
+                          np.concatenate(srcs), np.concatenate(dsts), "degenerate mix")
+    want_t = np.array([oracle.Graph.from_edgelist(g).triangles()["count"] for g in parts], np.uint64)
+    want_k = np.array([oracle.Graph.from_edgelist(g).cliques4()["count"] for g in parts], np.uint64)
+    trie = ctx.build_batch(b)
+    try:
+        for dyn in (0, 4):
+            tune(ctx, dynamic=dyn)
+            np.testing.assert_array_equal(ctx.count_batch(trie, eh.TRIANGLE), want_t)
+            np.testing.assert_array_equal(ctx.count_batch(trie, eh.CLIQUE4), want_k)
+            per = np.array([ctx.count_batch(trie, eh.TRIANGLE, i, 1)[0] for i in range(len(parts))],
+                           np.uint64)
+            np.testing.assert_array_equal(per, want_t)
+    finally:
+        trie.free()
+
+
+def test_out_degree_limits(ctx, eh):
+    """K_2050: triangles at out-degree 2049 (C(n, 3)); the 4-clique kernel's
+    S list holds at most 2048 entries, so its count is refused with
+    EH_EOVERFLOW instead of being computed wrongly."""
+    from math import comb
+    tune(ctx)
+    n = 2050
+    trie = ctx.build_edgelist(inputs.complete(n))
+    try:
+        assert trie.info["max_out_degree"] == n - 1
+        for tname in ("staged_target", "staged_source", "staged_lean", "pair_auto"):
+            tune(ctx, **TUNINGS[tname])
+            assert ctx.count_triangles(trie) == comb(n, 3), tname
+        with pytest.raises(eh.EHError) as e:
+            ctx.count_4cliques(trie)
+        assert e.value.status == eh.EH_EOVERFLOW
+        # roots of out-degree <= 2048 are still counted: vertex i roots C(n-1-i, 3)
+        roots = np.array([5, 100, 2000], np.uint32)
+        assert ctx.count_rooted(trie, eh.CLIQUE4, roots) == sum(comb(n - 1 - int(i), 3) for i in roots)
+    finally:
+        trie.free()
