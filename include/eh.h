@@ -86,7 +86,7 @@ const char* eh_last_error(const eh_ctx* ctx);
 const char* eh_status_str(eh_status s);
 /* Version of this ABI (major * 10000 + minor * 100 + patch); a caller built
  * against this header checks that the library returns EH_ABI_VERSION. */
-#define EH_ABI_VERSION 10200
+#define EH_ABI_VERSION 10300
 int32_t eh_abi_version(void);
 
 /* ---- tuning knobs (performance only; counts never depend on them) ------- */
@@ -130,6 +130,9 @@ typedef struct eh_tuning {
                             fewer elements than this, each element's set is found by a
                             binary search of the batch's length prefix instead of a walk
                             along it; at most 4096, 0 never searches */
+  uint32_t group;        /* staged triangle kernel, target staging: up to this many small
+                            consecutive work items of one graph share a wave (1, 2 or 4;
+                            0 means 1) */
 } eh_tuning;
 
 eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t);

@@ -88,6 +88,7 @@ void free_trie_device(Trie& t) {
     dev_free(c, p->items);
     dev_free(c, p->sdesc);
     dev_free(c, p->rec);
+    dev_free(c, p->gsub);
   }
   t.plans.clear();
   dev_free(c, t.vdesc);
@@ -169,6 +170,7 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
     a.tin = static_cast<const uint2*>(t.tin_d.p);
     if (p->sdesc.p) a.sdesc = static_cast<const uint4*>(p->sdesc.p) + i0;
     a.rec = static_cast<const uint4*>(p->rec.p);
+    if (p->group > 1) a.gsub = static_cast<const uint4*>(p->gsub.p);
   }
   a.acc = acc;
   a.tag_base = tag_base;
@@ -350,6 +352,11 @@ eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t) {
     return EH_EINVAL;
   }
   u.search_below = t->search_below;
+  if (t->group > 4 || t->group == 3) {
+    ctx->c.err = "group must be 0, 1, 2 or 4";
+    return EH_EINVAL;
+  }
+  u.group = t->group ? t->group : 1;
   return EH_OK;
 }
 
@@ -370,6 +377,7 @@ eh_status eh_ctx_get_tuning(const eh_ctx* ctx, eh_tuning* out) {
   out->unroll = u.unroll;
   out->grab = u.grab;
   out->search_below = u.search_below;
+  out->group = u.group;
   return EH_OK;
 }
 

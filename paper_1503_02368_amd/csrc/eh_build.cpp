@@ -402,8 +402,10 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
   const uint32_t chunk = std::max<uint32_t>(tu.chunk_work, 64);
   if (pattern == EH_4CLIQUE) staging = EH_STAGE_SOURCE;
   for (auto& p : t->plans) {
+    const uint32_t group = (staging == EH_STAGE_TARGET && pattern == EH_TRIANGLE) ? tu.group : 1u;
     if (p->pattern == pattern && p->staging == staging && p->chunk_work == chunk &&
-        p->use_bitsets == tu.use_bitsets && p->stage_words == tu.stage_words) {
+        p->use_bitsets == tu.use_bitsets && p->stage_words == tu.stage_words &&
+        p->group == group) {
       *out = p.get();
       return EH_OK;
     }
@@ -416,6 +418,7 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
   plan->chunk_work = chunk;
   plan->use_bitsets = tu.use_bitsets;
   plan->stage_words = tu.stage_words;
+  plan->group = (staging == EH_STAGE_TARGET && pattern == EH_TRIANGLE) ? tu.group : 1u;
   plan->g_item_off.assign(size_t(h.n_graphs) + 1, 0);
   const bool ub = tu.use_bitsets != 0;
   if (staging == EH_STAGE_TARGET) {
@@ -462,16 +465,8 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
     }
   }
   plan->g_item_off[h.n_graphs] = items.size();
-  plan->n_items = items.size();
   for (const Item& it : items) plan->item_dmax = std::max(plan->item_dmax, out_deg(h, it.s));
-  eh_status st = dev_alloc(c, plan->items, sizeof(Item) * std::max<size_t>(items.size(), 1));
-  if (st != EH_OK) return st;
-  if (!items.empty())
-    if ((st = hip_check(c, hipMemcpy(plan->items.p, items.data(), sizeof(Item) * items.size(),
-                                     hipMemcpyHostToDevice), "upload work items")) != EH_OK) {
-      dev_free(c, plan->items);
-      return st;
-    }
+  eh_status st = EH_OK;
   if (staging == EH_STAGE_TARGET && pattern == EH_TRIANGLE) {
     // Resolve on the host what each wave would otherwise look up through
     // chains of dependent loads: the staged set's extent per item, and per
@@ -484,21 +479,88 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
       const uint32_t lo_al = staged_lo_al(v), hi = h.col[h.row[v + 1] - 1];
       return hi - lo_al < cap * 32u;
     };
-    std::vector<uint32_t> sd(4 * std::max<size_t>(items.size(), 1), 0);
-    for (size_t i = 0; i < items.size(); ++i) {
-      const uint32_t v = items[i].s;
-      sd[4 * i] = h.row[v];
-      sd[4 * i + 1] = h.row[v + 1] - h.row[v];
-      sd[4 * i + 2] = h.col[h.row[v]];
-      sd[4 * i + 3] = h.col[h.row[v + 1] - 1];
+    std::vector<uint32_t> sd;   // per item: staged-set extent, or a group's descriptor
+    std::vector<uint32_t> gsub; // per grouped member
+    std::vector<uint8_t> grouped(h.n, 0);
+    auto single = [&](std::vector<Item>& out, const Item& it) {
+      const uint32_t v = it.s;
+      out.push_back(it);
+      sd.insert(sd.end(), {h.row[v], h.row[v + 1] - h.row[v], h.col[h.row[v]],
+                           h.col[h.row[v + 1] - 1]});
+    };
+    if (plan->group > 1) {
+      // Consecutive small items of one graph share a wave: up to `group`
+      // whole-vertex items whose records and staged members each total at
+      // most 64 and whose staged sets fit one bitmap interleaved K ways
+      // (bit (x - base) K + k marks x as a member of the k-th set), K the
+      // power of two >= the member count.  Their records carry no bitset
+      // words (a word does not line up with interleaved bits).
+      std::vector<Item> out;
+      std::vector<uint64_t> off(h.n_graphs + 1, 0);
+      for (uint32_t g = 0; g < h.n_graphs; ++g) {
+        off[g] = out.size();
+        const uint64_t i1 = plan->g_item_off[g + 1];
+        auto whole = [&](const Item& it) {
+          return it.lbeg == t->trow[it.s] && it.llen == t->trow[it.s + 1] - t->trow[it.s];
+        };
+        for (uint64_t i = plan->g_item_off[g]; i < i1;) {
+          const Item& a0 = items[i];
+          uint64_t j = i + 1;
+          if (whole(a0)) {
+            uint32_t base = h.col[h.row[a0.s]], top = h.col[h.row[a0.s + 1] - 1];
+            uint32_t recs = a0.llen, mem = h.row[a0.s + 1] - h.row[a0.s];
+            while (j < i1 && j - i < plan->group && whole(items[j])) {
+              const uint32_t v = items[j].s;
+              const uint32_t nb = std::min(base, h.col[h.row[v]]);
+              const uint32_t nt = std::max(top, h.col[h.row[v + 1] - 1]);
+              const uint64_t kk = (j - i + 1) <= 2 ? 2 : 4;
+              const uint32_t dv = h.row[v + 1] - h.row[v];
+              if (recs + items[j].llen > 64 || mem + dv > 64 ||
+                  (uint64_t(nt) - nb + 1) * kk > uint64_t(cap) * 32)
+                break;
+              base = nb;
+              top = nt;
+              recs += items[j].llen;
+              mem += dv;
+              ++j;
+            }
+            if (j - i > 1) {
+              const uint32_t cnt = uint32_t(j - i);
+              out.push_back(Item{uint32_t(gsub.size() / 4) | kHiBit, cnt, recs, a0.tag});
+              sd.insert(sd.end(), {base, cnt <= 2 ? 1u : 2u, mem, top});
+              for (uint64_t q = i; q < j; ++q) {
+                const uint32_t v = items[q].s;
+                grouped[v] = 1;
+                gsub.insert(gsub.end(),
+                            {items[q].lbeg, items[q].llen, h.row[v], h.row[v + 1] - h.row[v]});
+              }
+              i = j;
+              continue;
+            }
+          }
+          single(out, a0);
+          i = i + 1;
+        }
+      }
+      off[h.n_graphs] = out.size();
+      items.swap(out);
+      plan->g_item_off.swap(off);
+    } else {
+      for (const Item& it : items) {
+        const uint32_t v = it.s;
+        sd.insert(sd.end(), {h.row[v], h.row[v + 1] - h.row[v], h.col[h.row[v]],
+                             h.col[h.row[v + 1] - 1]});
+      }
     }
+    if (sd.empty()) sd.assign(4, 0);
     std::vector<uint32_t> rec(4 * std::max<uint64_t>(h.m, 1), 0);
     for (uint64_t k = 0; k < h.m; ++k) {
       const uint32_t u = t->tin[2 * k], e = t->tin[2 * k + 1], v = h.col[e];
       const uint32_t len = h.row[u + 1] - e - 1;
       uint32_t sb = e + 1, n = len;
       int32_t sm = 0;
-      if (ub && len && h.bs_off[u] != kNoBitset && h.row[v + 1] > h.row[v] && bitmap_mode(v)) {
+      if (ub && len && !grouped[v] && h.bs_off[u] != kNoBitset && h.row[v + 1] > h.row[v] &&
+          bitmap_mode(v)) {
         const uint32_t w0 = (v + 1 - h.bs_base[u]) >> 5;
         const uint32_t nw = w0 < h.bs_nw[u] ? h.bs_nw[u] - w0 : 0u;
         if (nw < len) {
@@ -511,18 +573,31 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
       rec[4 * k + 1] = n;
       rec[4 * k + 2] = uint32_t(sm);
     }
+    if (gsub.empty()) gsub.assign(4, 0);
     if ((st = dev_alloc(c, plan->sdesc, sizeof(uint32_t) * sd.size())) != EH_OK ||
         (st = dev_alloc(c, plan->rec, sizeof(uint32_t) * rec.size())) != EH_OK ||
+        (st = dev_alloc(c, plan->gsub, sizeof(uint32_t) * gsub.size())) != EH_OK ||
         (st = hip_check(c, hipMemcpy(plan->sdesc.p, sd.data(), sizeof(uint32_t) * sd.size(),
                                      hipMemcpyHostToDevice), "upload stage table")) != EH_OK ||
         (st = hip_check(c, hipMemcpy(plan->rec.p, rec.data(), sizeof(uint32_t) * rec.size(),
-                                     hipMemcpyHostToDevice), "upload segment records")) != EH_OK) {
-      dev_free(c, plan->items);
+                                     hipMemcpyHostToDevice), "upload segment records")) != EH_OK ||
+        (st = hip_check(c, hipMemcpy(plan->gsub.p, gsub.data(), sizeof(uint32_t) * gsub.size(),
+                                     hipMemcpyHostToDevice), "upload grouped members")) != EH_OK) {
       dev_free(c, plan->sdesc);
       dev_free(c, plan->rec);
+      dev_free(c, plan->gsub);
       return st;
     }
   }
+  plan->n_items = items.size();
+  if ((st = dev_alloc(c, plan->items, sizeof(Item) * std::max<size_t>(items.size(), 1))) != EH_OK)
+    return st;
+  if (!items.empty())
+    if ((st = hip_check(c, hipMemcpy(plan->items.p, items.data(), sizeof(Item) * items.size(),
+                                     hipMemcpyHostToDevice), "upload work items")) != EH_OK) {
+      dev_free(c, plan->items);
+      return st;
+    }
   *out = plan.get();
   t->plans.push_back(std::move(plan));
   return EH_OK;

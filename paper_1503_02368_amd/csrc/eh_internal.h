@@ -88,6 +88,7 @@ struct Tuning {
   uint32_t unroll = 8;
   uint32_t grab = 8;
   uint32_t search_below = 24;
+  uint32_t group = 1;
 };
 
 struct Ctx;
@@ -105,6 +106,7 @@ struct Plan {
   uint32_t chunk_work = 0;
   uint32_t use_bitsets = 0;
   uint32_t stage_words = 0;
+  uint32_t group = 1;                // most per-vertex items in one grouped item
   uint64_t n_items = 0;
   DevBuf items;
   // target staging only: per item {begin, length, min, max} of the staged set,
@@ -112,6 +114,11 @@ struct Plan {
   // word offset from the staged bitmap, 0}
   DevBuf sdesc;
   DevBuf rec;
+  // grouped items: per member {first record, records, first member in col,
+  // members}; a grouped item has s = first member entry | kHiBit, lbeg = its
+  // member count, llen = its records, and the descriptor {bitmap base, log2
+  // of the interleave, members, max member}
+  DevBuf gsub;
   std::vector<uint64_t> g_item_off;  // batch: items of graph g are [off[g], off[g+1])
   uint32_t item_dmax = 0;            // max out-degree of an item's source vertex
 };
@@ -198,6 +205,7 @@ struct LaunchArgs {
   uint32_t unroll = 8;                 // staged triangle kernel: 4 or 8
   uint32_t grab = 8;                   // schedule 4: items per cursor fetch
   uint32_t search_below = 24;          // average segment length below which the walk searches
+  const uint4* gsub = nullptr;         // grouped items' members, or null
 };
 eh_status launch_fill_u64(Ctx* c, hipStream_t s, unsigned long long* p, uint64_t n,
                           unsigned long long v);

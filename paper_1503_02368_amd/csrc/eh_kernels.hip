@@ -68,6 +68,7 @@ struct DevArgs {
   uint32_t grab;
   uint32_t deg_lo, deg_hi;  // 4-clique: items with deg_lo < d+(u) <= deg_hi
   uint32_t search_below;    // segments shorter on average: the walk binary-searches
+  const uint4* gsub;        // grouped items' members, or null
 };
 
 DevArgs to_dev(const LaunchArgs& a) {
@@ -97,6 +98,7 @@ DevArgs to_dev(const LaunchArgs& a) {
   d.deg_lo = a.deg_lo;
   d.deg_hi = a.deg_hi;
   d.search_below = a.search_below;
+  d.gsub = a.gsub;
   return d;
 }
 
@@ -270,11 +272,16 @@ __device__ __forceinline__ void flush_tag(const DevArgs& a, unsigned long long& 
 //             because degree order puts the dense hub neighbourhoods there.
 //  List:      a sorted list of len ids in R, searched (4-clique level 2).
 //  Empty:     nothing.
-enum : uint32_t { kModeBitmap = 0, kModeComposite = 1, kModeList = 2, kModeEmpty = 3 };
+//  Group:     the sets of K small items at once, interleaved: bit
+//             (x - base) K + k marks x as a member of set k (K = 2^glog);
+//             each streamed set is tested against its own item's set.
+enum : uint32_t { kModeBitmap = 0, kModeComposite = 1, kModeList = 2, kModeEmpty = 3,
+                  kModeGroup = 4 };
 constexpr int kPrefixCap = 128;
 
 struct Staged {
   uint32_t beg, len, lo, hi, base, plen, mode;
+  uint32_t glog, glim;  // group mode: log2 K, and the offsets x - base that fit
   uint32_t x0;  // per lane: member number `lane` of the set (lane < len), kept to clear R
 };
 
@@ -289,6 +296,8 @@ __device__ __forceinline__ Staged stage_extent(const DevArgs& a, uint32_t beg, u
   st.len = len;
   st.plen = 0;
   st.x0 = 0;
+  st.glog = 0;
+  st.glim = 0;
   if (st.len == 0) { st.mode = kModeEmpty; st.lo = st.hi = st.base = 0; return st; }
   st.lo = lo;
   st.hi = hi;
@@ -467,6 +476,9 @@ __device__ __forceinline__ uint32_t publish_segments(const SegTab& T, const Seg&
 // element's position in the list buffer (col followed by all bitset words)
 // and, for bitset words, the word's index in the staged bitmap.  Segment
 // bases are kept relative to f so each element costs one add.
+// kRaw (grouped items): wbase is the segment's stored value itself, the index
+// of the item whose set the segment is tested against.
+template <bool kRaw = false>
 struct SegCursor {
   uint32_t j, nxt, base, wbase;
   bool bits;
@@ -488,7 +500,7 @@ struct SegCursor {
       const uint2 sg = T.S[j];
       const uint32_t sb = sg.x;
       base = (sb & kMaxIndex) - start;
-      wbase = sg.y - start;
+      wbase = kRaw ? sg.y : sg.y - start;
       bits = (sb & kHiBit) != 0;
     }
   }
@@ -510,7 +522,7 @@ struct SegCursor {
     const uint2 sg = T.S[p];
     const uint32_t sb = sg.x;
     base = (sb & kMaxIndex) - start;
-    wbase = sg.y - start;
+    wbase = kRaw ? sg.y : sg.y - start;
     bits = (sb & kHiBit) != 0;
   }
 };
@@ -520,13 +532,14 @@ struct SegCursor {
 // element costs the same: a uint value x tests bit x - base, a bitset word
 // is ANDed with the bitmap word it overlaps, both as popc(R[w] & mask).  A
 // composite set's members below its window are found by searching its prefix.
-template <int RW, int U, bool kComposite>
+// Group mode counts x when bit (x - base) K + k is set, k the segment's item.
+template <int RW, int U, bool kComposite, bool kGroup = false>
 __device__ __forceinline__ uint32_t flat_probe_bits(const DevArgs& a, const SegTab& T, uint32_t E,
                                                     const Staged& st, const uint32_t* R,
                                                     const uint32_t* Lp, uint32_t lane) {
   const uint32_t* __restrict__ L = a.col;
   uint32_t cnt = 0;
-  SegCursor c(T);
+  SegCursor<kGroup> c(T);
   const uint32_t base = st.base;
   for (uint32_t f0 = 0; f0 < E; f0 += kWave * U) {
     uint32_t val[U], key[U];
@@ -541,13 +554,18 @@ __device__ __forceinline__ uint32_t flat_probe_bits(const DevArgs& a, const SegT
       if (ok[u]) {
         c.seek(T, f);
         val[u] = L[c.base + f];
-        key[u] = c.wbase + f;
+        key[u] = kGroup ? c.wbase : c.wbase + f;
         bits[u] = c.bits;
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t d = val[u] - base;
+      if (kGroup) {
+        const uint32_t pos = (d << st.glog) + key[u];
+        if (ok[u] && d < st.glim) cnt += (R[pos >> 5] >> (pos & 31)) & 1u;
+        continue;
+      }
       const uint32_t w = bits[u] ? key[u] : (d >> 5);
       const uint32_t m = bits[u] ? val[u] : (1u << (d & 31));
       if (ok[u] && w < uint32_t(RW)) cnt += __popc(R[w] & m);
@@ -562,7 +580,7 @@ __device__ __forceinline__ uint32_t flat_probe_bits(const DevArgs& a, const SegT
 // with per = ceil(E / 64), finds the set of its first element by a binary
 // search of the length prefix and walks on from there, so a set boundary
 // costs one cursor step instead of a search per element.
-template <int RW, int U, bool kComposite>
+template <int RW, int U, bool kComposite, bool kGroup = false>
 __device__ __forceinline__ uint32_t flat_probe_bits_blocked(const DevArgs& a, const SegTab& T,
                                                             uint32_t E, const Staged& st,
                                                             const uint32_t* R, const uint32_t* Lp,
@@ -573,7 +591,7 @@ __device__ __forceinline__ uint32_t flat_probe_bits_blocked(const DevArgs& a, co
   const uint32_t f_end = min(f_beg + per, E);
   uint32_t cnt = 0;
   if (f_beg >= f_end) return 0u;
-  SegCursor c;
+  SegCursor<kGroup> c;
   c.find(T, f_beg);
   const uint32_t base = st.base;
   for (uint32_t f0 = f_beg; f0 < f_end; f0 += U) {
@@ -589,13 +607,18 @@ __device__ __forceinline__ uint32_t flat_probe_bits_blocked(const DevArgs& a, co
       if (ok[u]) {
         c.seek(T, f);
         val[u] = L[c.base + f];
-        key[u] = c.wbase + f;
+        key[u] = kGroup ? c.wbase : c.wbase + f;
         bits[u] = c.bits;
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t d = val[u] - base;
+      if (kGroup) {
+        const uint32_t pos = (d << st.glog) + key[u];
+        if (ok[u] && d < st.glim) cnt += (R[pos >> 5] >> (pos & 31)) & 1u;
+        continue;
+      }
       const uint32_t w = bits[u] ? key[u] : (d >> 5);
       const uint32_t m = bits[u] ? val[u] : (1u << (d & 31));
       if (ok[u] && w < uint32_t(RW)) cnt += __popc(R[w] & m);
@@ -612,6 +635,9 @@ __device__ __forceinline__ uint32_t flat_probe(const DevArgs& a, const SegTab& T
                                                uint32_t nseg, const Staged& st, const uint32_t* R,
                                                const uint32_t* Lp, uint32_t lane) {
   const bool search = E < nseg * a.search_below;
+  if (st.mode == kModeGroup)
+    return search ? flat_probe_bits_blocked<RW, U, false, true>(a, T, E, st, R, Lp, lane)
+                  : flat_probe_bits<RW, U, false, true>(a, T, E, st, R, Lp, lane);
   if (st.mode == kModeBitmap)
     return search ? flat_probe_bits_blocked<RW, U, false>(a, T, E, st, R, Lp, lane)
                   : flat_probe_bits<RW, U, false>(a, T, E, st, R, Lp, lane);
@@ -639,6 +665,68 @@ __device__ __forceinline__ uint32_t flat_probe(const DevArgs& a, const SegTab& T
     for (int u = 0; u < U; ++u)
       if (ok[u]) cnt += staged_has<RW>(a, st, R, Lp, val[u]);
   }
+  return cnt;
+}
+
+// ---------------------------------------------------------------------------
+// Triangles, staged: a group of K small items in one pass
+// ---------------------------------------------------------------------------
+
+// Counts a grouped item: members gsub[gi .. gi+K) ({first record, records,
+// first staged member in col, staged members}), nrec records and descriptor
+// sd = {bitmap base, log2 of the interleave, staged members, max member} in
+// all.  Lane m < members stages one member of one set, lane r < nrec loads
+// one record; the sets share the region interleaved and the streamed sets of
+// all K items share one flat walk.  At most 4 members, 64 staged members and
+// 64 records (the plan guarantees it).
+template <int RW, int U>
+__device__ __forceinline__ uint32_t grouped_item(const DevArgs& a, const SegTab& T, uint32_t* R,
+                                                 const uint32_t* Lp, uint32_t gi, uint32_t K,
+                                                 uint32_t nrec, const uint4& sd, uint32_t lane) {
+  const uint32_t base = uniform(sd.x), glog = uniform(sd.y), nmem = uniform(sd.z);
+  uint4 gs{0, 0, 0, 0};
+  if (lane < K) gs = a.gsub[gi + lane];
+  // lanes at or past K hold zeros, so the prefix sums stop growing there
+  const uint32_t rb0 = __builtin_amdgcn_readlane(gs.x, 0), rb1 = __builtin_amdgcn_readlane(gs.x, 1);
+  const uint32_t rb2 = __builtin_amdgcn_readlane(gs.x, 2), rb3 = __builtin_amdgcn_readlane(gs.x, 3);
+  const uint32_t q1 = __builtin_amdgcn_readlane(gs.y, 0);
+  const uint32_t q2 = q1 + __builtin_amdgcn_readlane(gs.y, 1);
+  const uint32_t q3 = q2 + __builtin_amdgcn_readlane(gs.y, 2);
+  const uint32_t mb0 = __builtin_amdgcn_readlane(gs.z, 0), mb1 = __builtin_amdgcn_readlane(gs.z, 1);
+  const uint32_t mb2 = __builtin_amdgcn_readlane(gs.z, 2), mb3 = __builtin_amdgcn_readlane(gs.z, 3);
+  const uint32_t p1 = __builtin_amdgcn_readlane(gs.w, 0);
+  const uint32_t p2 = p1 + __builtin_amdgcn_readlane(gs.w, 1);
+  const uint32_t p3 = p2 + __builtin_amdgcn_readlane(gs.w, 2);
+  // records: lane r holds record r - q_k of item k
+  Seg g{0, 0, 0};
+  if (lane < nrec) {
+    const uint32_t k = uint32_t(lane >= q1) + uint32_t(lane >= q2) + uint32_t(lane >= q3);
+    const uint32_t qk = k == 0 ? 0u : k == 1 ? q1 : k == 2 ? q2 : q3;
+    const uint32_t bk = k == 0 ? rb0 : k == 1 ? rb1 : k == 2 ? rb2 : rb3;
+    const uint4 r = a.rec[bk + lane - qk];
+    g = Seg{r.x, r.y, int32_t(k)};
+  }
+  // staging: lane m holds member m - p_k of set k, at bit (x - base) K + k
+  uint32_t pos = 0;
+  if (lane < nmem) {
+    const uint32_t k = uint32_t(lane >= p1) + uint32_t(lane >= p2) + uint32_t(lane >= p3);
+    const uint32_t pk = k == 0 ? 0u : k == 1 ? p1 : k == 2 ? p2 : p3;
+    const uint32_t bk = k == 0 ? mb0 : k == 1 ? mb1 : k == 2 ? mb2 : mb3;
+    const uint32_t x = a.col[bk + lane - pk];
+    pos = ((x - base) << glog) + k;
+    atomicOr(&R[pos >> 5], 1u << (pos & 31));
+  }
+  const uint32_t E = publish_segments(T, g, lane);  // also orders the staging
+  Staged st;
+  st.beg = st.len = st.lo = st.hi = st.plen = st.x0 = 0;
+  st.mode = kModeGroup;
+  st.base = base;
+  st.glog = glog;
+  st.glim = (uint32_t(RW) * 32u) >> glog;
+  const uint32_t cnt = flat_probe<RW, U>(a, T, E, nrec, st, R, Lp, lane);
+  wave_sync();
+  if (lane < nmem) R[pos >> 5] = 0;
+  wave_sync();
   return cnt;
 }
 
@@ -682,6 +770,10 @@ __device__ __forceinline__ void tri_staged(const DevArgs& a) {
     if (have_tag && tag != cur_tag) flush_tag(a, acc, cur_tag, lane);
     cur_tag = tag;
     have_tag = true;
+    if (a.gsub && (s & kHiBit)) {
+      acc += grouped_item<RW, U>(a, T, R, Lp, s & kMaxIndex, lbeg, llen, sd, lane);
+      continue;
+    }
     // the first batch of segment records is loaded beside the staged set
     uint4 r0{0, 0, 0, 0};
     if (a.rec && lane < min(uint32_t(kSeg), llen)) r0 = a.rec[lbeg + lane];

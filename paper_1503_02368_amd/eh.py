@@ -52,7 +52,7 @@ class _Allocator(ctypes.Structure):
 
 
 # struct layouts below are those of this ABI version of include/eh.h
-ABI_VERSION = 10200
+ABI_VERSION = 10300
 
 
 class _Tuning(ctypes.Structure):
@@ -62,7 +62,7 @@ class _Tuning(ctypes.Structure):
                 ("use_bitsets", ctypes.c_uint32), ("dynamic", ctypes.c_uint32),
                 ("stage_words", ctypes.c_uint32), ("xcds", ctypes.c_uint32),
                 ("unroll", ctypes.c_uint32), ("grab", ctypes.c_uint32),
-                ("search_below", ctypes.c_uint32)]
+                ("search_below", ctypes.c_uint32), ("group", ctypes.c_uint32)]
 
 
 class _BuildOpts(ctypes.Structure):

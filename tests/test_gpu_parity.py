@@ -82,10 +82,14 @@ TUNINGS = {
     "staged_walk": dict(kernel=1, staging=2, use_bitsets=1, search_below=0),
     # half-size staged region: the 8-waves-per-SIMD triangle instance
     "staged_lean": dict(kernel=1, staging=2, use_bitsets=1, stage_words=512, dynamic=4, grab=5),
+    # small items grouped 4 (or 2) to a wave, interleaved bitmaps
+    "staged_group": dict(kernel=1, staging=2, use_bitsets=1, group=4, dynamic=4, grab=3),
+    "staged_group_lean": dict(kernel=1, staging=2, use_bitsets=1, group=2, stage_words=512,
+                              search_below=0),
 }
 DEFAULT = dict(kernel=1, staging=2, algo=0, gamma=32.0, chunk_work=4096, waves_per_cu=32,
                group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0, xcds=0, unroll=8, grab=8,
-               search_below=24)
+               search_below=24, group=1)
 
 
 def tune(ctx, **kw):
@@ -250,7 +254,8 @@ def small_batch(num=120, seed=4):
 
 
 @pytest.mark.parametrize("tname", ["staged_target", "staged_source", "pair_auto", "staged_part",
-                                   "staged_steal", "staged_search", "staged_lean"])
+                                   "staged_steal", "staged_search", "staged_lean", "staged_group",
+                                   "staged_group_lean"])
 def test_batch(ctx, eh, tname):
     tune(ctx, **TUNINGS[tname])
     b = small_batch()
@@ -350,7 +355,8 @@ def test_full_size_rmat20_triangles(ctx, eh):
     trie = ctx.build_edgelist(el)
     try:
         for tname in ("staged_target", "staged_source", "pair_auto", "staged_part", "staged_steal",
-                      "staged_search", "staged_walk", "staged_lean"):
+                      "staged_search", "staged_walk", "staged_lean", "staged_group",
+                      "staged_group_lean"):
             tune(ctx, **TUNINGS[tname])
             got = ctx.count_triangles(trie)
             say(tname, got)
@@ -470,7 +476,7 @@ DEGENERATE = [
 
 
 @pytest.mark.parametrize("tname", ["staged_target", "staged_source", "pair_auto", "staged_lean",
-                                   "staged_steal"])
+                                   "staged_steal", "staged_group"])
 def test_degenerate_inputs(ctx, eh, tname):
     """Empty and tiny graphs: zero vertices, no edges, self-loops only, one
     edge, one triangle with isolated vertices, K4 -- totals, per-root
