@@ -29,7 +29,7 @@ DEFAULT_OUT = os.path.join(HERE, "tuning.json")
 
 BASE = dict(kernel=1, staging=2, algo=0, gamma=32.0, chunk_work=4096, waves_per_cu=32,
             group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0, xcds=0, unroll=8, grab=8,
-            search_below=24)
+            search_below=24, group=1)
 # schedules tried last: (dynamic, grab); 3 and 4 cut the items into one range per XCD
 SCHEDULES = [(1, 8), (2, 8), (3, 8), (4, 1), (4, 4), (4, 16)]
 
@@ -129,6 +129,14 @@ def tune_graph(el, pattern, layouts, ctx, torch, quick=False):
                     ctx.set_tuning(**cfg)
                     ms, c = timer.graph(trie, pattern)
                     S.record(dict(layout=layout, tau=tau, tuning=cfg), ms, c)
+                    if ms < local[0]:
+                        local = (ms, cfg)
+            if pattern == 3 and local[1]["kernel"] == 1 and local[1]["staging"] == 2:
+                for grp, sw in itertools.product((2, 4), (0, 512)):
+                    cfg = dict(local[1], group=grp, stage_words=sw)
+                    ctx.set_tuning(**cfg)
+                    ms, c = timer.graph(trie, pattern)
+                    S.record(dict(layout=layout, tau=tau, tuning=cfg), ms, c)
             if local[1]["kernel"] == eh.KERNEL_PAIRWISE:
                 for g, al, gm in itertools.product([4, 16, 64], [0, 1, 2], [8.0, 32.0, 128.0]):
                     cfg = dict(local[1], group_lanes=g, algo=al, gamma=gm)
@@ -170,17 +178,18 @@ def tune_batch(b, pattern, layouts, ctx, torch, quick=False):
             kinds += [dict(kernel=2, group_lanes=g, algo=al) for g in groups for al in (0, 1)]
             local = None
             for k, ch, (dyn, grab) in itertools.product(kinds, chunks, [(0, 8), (4, 16)]):
-                cfg = dict(BASE, **k, chunk_work=ch, dynamic=dyn, grab=grab)
+                cfg = dict(BASE, **k, chunk_work=ch, dynamic=dyn, grab=grab,
+                           group=4 if k.get("staging") == 2 else 1)
                 ms = run(cfg)
                 if local is None or ms < local[0]:
                     local = (ms, cfg)
             unrolls = [4, 8] if local[1]["kernel"] == 1 else [8]
             words = [0, 512] if local[1]["kernel"] == 1 else [0]
-            for wv, un, sw, (dyn, grab) in itertools.product([16, 24, 32, 40], unrolls, words,
-                                                              [(0, 8), (3, 8), (4, 4), (4, 16),
-                                                               (4, 64)]):
-                cfg = dict(local[1], waves_per_cu=wv, unroll=un, stage_words=sw, dynamic=dyn,
-                           grab=grab)
+            groups = [1, 2, 4] if local[1]["group"] > 1 else [1]
+            for wv, un, sw, gr, (dyn, grab) in itertools.product([24, 32, 40], unrolls, words, groups,
+                                                                  [(0, 8), (4, 4), (4, 16), (4, 64)]):
+                cfg = dict(local[1], waves_per_cu=wv, unroll=un, stage_words=sw, group=gr,
+                           dynamic=dyn, grab=grab)
                 ms = run(cfg)
                 if ms < local[0]:
                     local = (ms, cfg)
