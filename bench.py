@@ -164,6 +164,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--rates", default="200,1000,5000", help="served: arrival rates (QPS)")
+    ap.add_argument("--policy", type=int, default=1, choices=(0, 1),
+                    help="served: 0 oldest request first, 1 fewest items left first")
     ap.add_argument("--duration", type=float, default=3.0, help="served: seconds per rate")
     ap.add_argument("--max-requests", type=int, default=3000, help="served: cap per rate")
     ap.add_argument("--no-per-instance", action="store_true",

@@ -221,8 +221,12 @@ typedef struct eh_server_opts {
   uint32_t max_active;        /* [256] */
   uint32_t max_queued;        /* [4096] submitted, not yet admitted */
   uint32_t step_items;        /* [262144] */
-  uint32_t reserved;
+  uint32_t policy;            /* which active requests' items fill a step first:
+                                 EH_SERVE_FIFO [default] oldest first, or
+                                 EH_SERVE_SHORTEST fewest items left first */
 } eh_server_opts;
+
+enum { EH_SERVE_FIFO = 0, EH_SERVE_SHORTEST = 1 };
 
 typedef struct eh_req_stats {
   uint64_t t_submit_ns;   /* CLOCK_MONOTONIC times */

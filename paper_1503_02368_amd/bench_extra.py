@@ -239,7 +239,7 @@ def bench_served(name, w, args, ctx, eh, torch, metric):
         log(f"[bench] rate {rate:g} QPS: {len(reqs)} requests over {dur:.2f} s")
         row = {"rate_qps": rate, "requests": len(reqs)}
         for mode in ("batched", "serial"):
-            lat, counts = serve_run(ctx, eh, trie, reqs, mode)
+            lat, counts = serve_run(ctx, eh, trie, reqs, mode, policy=args.policy)
             ok = all(c == want(r) for c, r in zip(counts, reqs)) if root_t is not None else None
             all_ok = all_ok and (ok is not False)
             span = max(l + r.t_arrival for l, r in zip(lat, reqs)) if reqs else 0.0
@@ -255,7 +255,8 @@ def bench_served(name, w, args, ctx, eh, torch, metric):
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded generator)",
         "config": {"workload": name, "scale": w["scale"], "edge_factor": w["edge_factor"], "seed": w["seed"],
                    "n": info["n"], "m_plus": info["m_plus"], "pattern_mix": "80% triangle / 20% 4-clique",
-                   "roots": "log-uniform 2^8..2^16 distinct ids", "tuning": ctx.get_tuning()},
+                   "roots": "log-uniform 2^8..2^16 distinct ids", "tuning": ctx.get_tuning(),
+                   "policy": ["oldest first", "fewest items left first"][args.policy]},
         "rates": table,
         "parity_vs_oracle": all_ok if root_t is not None else None,
     }
@@ -265,7 +266,7 @@ def bench_served(name, w, args, ctx, eh, torch, metric):
     return res
 
 
-def serve_run(ctx, eh, trie, reqs, mode):
+def serve_run(ctx, eh, trie, reqs, mode, policy=0):
     """Replays the arrival schedule; returns per-request latency (s) and counts."""
     n = len(reqs)
     lat = [0.0] * n
@@ -280,7 +281,7 @@ def serve_run(ctx, eh, trie, reqs, mode):
             counts[i] = ctx.count_rooted(trie, r.pattern, r.roots)
             lat[i] = time.monotonic() - due
         return lat, counts
-    srv = ctx.server(trie)
+    srv = ctx.server(trie, policy=policy)
     tickets = [None] * n
     start_ns = [0]
     submitted = threading.Event()

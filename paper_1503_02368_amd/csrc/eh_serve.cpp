@@ -145,7 +145,8 @@ bool Server::step() {
   std::vector<uint32_t> to_zero;
   std::vector<Item> tri, k4;
   uint32_t dmax_tri = 0, dmax_k4 = 0;
-  std::vector<std::pair<std::shared_ptr<Request>, uint64_t>> dispatched;
+  // requests stay alive in `active` until this thread retires them
+  std::vector<std::pair<Request*, uint64_t>> dispatched;
   {
     std::unique_lock<std::mutex> lk(mu);
     // admission, arrival order
@@ -161,9 +162,17 @@ bool Server::step() {
       queue.pop_front();
     }
     if (active.empty()) return false;
-    // gather items, oldest request first
+    // gather items: oldest request first, or (EH_SERVE_SHORTEST) the
+    // requests with the fewest items left first, ties by age
+    std::vector<Request*> order;
+    order.reserve(active.size());
+    for (auto& r : active) order.push_back(r.get());
+    if (o.policy == EH_SERVE_SHORTEST)
+      std::stable_sort(order.begin(), order.end(), [](const Request* x, const Request* y) {
+        return x->items.size() - x->next_item < y->items.size() - y->next_item;
+      });
     uint64_t budget = o.step_items;
-    for (auto& r : active) {
+    for (Request* r : order) {
       if (!r->zeroed) {
         to_zero.push_back(r->slot);
         r->zeroed = true;
@@ -171,7 +180,7 @@ bool Server::step() {
       const uint64_t take = std::min<uint64_t>(budget, r->items.size() - r->next_item);
       auto& dst = r->pattern == EH_4CLIQUE ? k4 : tri;
       auto& dm = r->pattern == EH_4CLIQUE ? dmax_k4 : dmax_tri;
-      dm = std::max(dm, r->item_dmax);
+      if (take) dm = std::max(dm, r->item_dmax);
       dst.insert(dst.end(), r->items.begin() + r->next_item, r->items.begin() + r->next_item + take);
       r->next_item += take;
       budget -= take;

@@ -79,7 +79,7 @@ class _TrieInfo(ctypes.Structure):
 class _ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
                 ("max_queued", ctypes.c_uint32), ("step_items", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("policy", ctypes.c_uint32)]
 
 
 class _ReqStats(ctypes.Structure):
@@ -351,8 +351,9 @@ class Context:
         self._check(self._lib.eh_count_batch_async(self._h, trie._h, int(pattern), int(first), int(count),
                                                    _vp(d_out.data_ptr())), "count_batch_async")
 
-    def server(self, trie, hbm_budget_bytes=0, max_active=0, max_queued=0, step_items=0) -> "Server":
-        return Server(self, trie, hbm_budget_bytes, max_active, max_queued, step_items)
+    def server(self, trie, hbm_budget_bytes=0, max_active=0, max_queued=0, step_items=0,
+               policy=0) -> "Server":
+        return Server(self, trie, hbm_budget_bytes, max_active, max_queued, step_items, policy)
 
 
 class Trie:
@@ -388,10 +389,11 @@ class ReqResult:
 
 
 class Server:
-    def __init__(self, ctx: Context, trie: Trie, budget, max_active, max_queued, step_items):
+    def __init__(self, ctx: Context, trie: Trie, budget, max_active, max_queued, step_items,
+                 policy=0):
         self.ctx = ctx
         self._lib = ctx._lib
-        o = _ServerOpts(int(budget), int(max_active), int(max_queued), int(step_items), 0)
+        o = _ServerOpts(int(budget), int(max_active), int(max_queued), int(step_items), int(policy))
         h = _vp()
         ctx._check(self._lib.eh_server_create(ctx._h, trie._h, ctypes.byref(o), ctypes.byref(h)),
                    "server_create")

@@ -302,7 +302,8 @@ def test_batch_order_invariant(ctx, eh):
         t2.free()
 
 
-def test_server_alone_equals_mix(ctx, eh):
+@pytest.mark.parametrize("policy", [0, 1])
+def test_server_alone_equals_mix(ctx, eh, policy):
     tune(ctx)
     el = inputs.rmat(13, 16, seed=13)
     g = oracle.Graph.from_edgelist(el)
@@ -312,7 +313,7 @@ def test_server_alone_equals_mix(ctx, eh):
     reqs = inputs.request_stream(el.n, rate_qps=1000, duration_s=0.06, seed=5, log2_lo=2, log2_hi=12)
     assert len(reqs) > 20
     want = [oracle.rooted_count(roots_t if r.pattern == 3 else roots_k, r.roots) for r in reqs]
-    srv = ctx.server(trie, step_items=512)
+    srv = ctx.server(trie, step_items=512, policy=policy)
     try:
         alone = []
         for r in reqs:
