@@ -95,7 +95,6 @@ void free_trie_device(Trie& t) {
   dev_free(c, t.col);
   dev_free(c, t.bsdesc);
   dev_free(c, t.vert);
-  dev_free(c, t.tin_d);
   t.device_bytes = 0;
 }
 
@@ -167,7 +166,6 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
   a.n_items = i1 - i0;
   a.idx = static_cast<const uint32_t*>(t.col.p);
   if (p->staging == EH_STAGE_TARGET) {
-    a.tin = static_cast<const uint2*>(t.tin_d.p);
     if (p->sdesc.p) a.sdesc = static_cast<const uint4*>(p->sdesc.p) + i0;
     a.rec = static_cast<const uint4*>(p->rec.p);
     if (p->group > 1) a.gsub = static_cast<const uint4*>(p->gsub.p);

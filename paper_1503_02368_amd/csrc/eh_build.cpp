@@ -435,13 +435,6 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
           t->tin[2 * k] = u;
           t->tin[2 * k + 1] = e;
         }
-      eh_status st = dev_alloc(c, t->tin_d, sizeof(uint32_t) * 2 * std::max<uint64_t>(h.m, 1));
-      if (st != EH_OK) return st;
-      if (h.m)
-        if ((st = hip_check(c, hipMemcpy(t->tin_d.p, t->tin.data(), sizeof(uint32_t) * 2 * h.m,
-                                         hipMemcpyHostToDevice), "upload in-edges")) != EH_OK)
-          return st;
-      t->device_bytes += t->tin_d.bytes;
       t->has_transpose = true;
     }
   }

@@ -134,7 +134,6 @@ struct Trie {
   DevBuf col;     // uint32 [m + W]: the uint sets, then every bitset's words
   DevBuf bsdesc;  // uint4 [n]: {position of first word in col, base, words, 0}
   DevBuf vert;    // uint32 [n]: rank -> id
-  DevBuf tin_d;   // uint2 [m]: in-edges (target staging)
   std::vector<std::unique_ptr<Plan>> plans;
   uint64_t device_bytes = 0;
 };
@@ -179,7 +178,6 @@ struct LaunchArgs {
   const Item* items = nullptr;
   uint64_t n_items = 0;
   const uint32_t* idx = nullptr;       // streamed vertex list (source staging)
-  const uint2* tin = nullptr;          // in-edges (target staging), else null
   const uint4* sdesc = nullptr;        // per item staged-set descriptor, or null
   const uint4* rec = nullptr;          // per in-edge segment record, or null
   const uint2* vdesc = nullptr;

@@ -47,7 +47,6 @@ struct DevArgs {
   const Item* items;
   uint64_t n_items;
   const uint32_t* idx;
-  const uint2* tin;  // target staging: in-edges {u, position of the edge in col}
   const uint4* sdesc;  // per item {begin, length, min, max} of the staged set, or null
   const uint4* rec;    // per in-edge streamed segment {start, length, word delta, 0}, or null
   const uint2* vdesc;
@@ -76,7 +75,6 @@ DevArgs to_dev(const LaunchArgs& a) {
   d.items = a.items;
   d.n_items = a.n_items;
   d.idx = a.idx;
-  d.tin = a.tin;
   d.sdesc = a.sdesc;
   d.rec = a.rec;
   d.vdesc = a.vdesc;
@@ -440,27 +438,6 @@ __device__ __forceinline__ Seg seg_full(const DevArgs& a, uint32_t t, const Word
   return g;
 }
 
-// The part of N+(u) above v, where v = col[e] is u's out-neighbour at edge
-// position e: only these elements can lie in N+(v), all of whose members
-// exceed v.  As bitset words: from the word holding v+1 to the last.
-__device__ __forceinline__ Seg seg_suffix(const DevArgs& a, uint32_t u, uint32_t e, uint32_t v,
-                                          const WordRule& wr) {
-  const uint2 ud = a.vdesc[u];
-  const uint32_t end = ud.x + (ud.y & kMaxIndex);
-  Seg g{e + 1, end - e - 1, 0};
-  if (wr.ok && (ud.y & kHiBit) && g.len) {
-    const uint4 bd = a.bsdesc[u];
-    const uint32_t w0 = (v + 1 - bd.y) >> 5;  // v >= base since v is in the set
-    const uint32_t nw = w0 < bd.z ? bd.z - w0 : 0u;
-    if (nw < g.len && bd.y + 32u * w0 >= wr.wmin) {
-      g.sb = (bd.x + w0) | kHiBit;
-      g.len = nw;
-      g.sm = int32_t((bd.y >> 5) + w0) - int32_t(wr.base >> 5);
-    }
-  }
-  return g;
-}
-
 // Publishes one segment per lane into the table and returns the flat length.
 __device__ __forceinline__ uint32_t publish_segments(const SegTab& T, const Seg& g, uint32_t lane) {
   const uint32_t incl = wave_incl_scan(g.len, lane);
@@ -791,9 +768,6 @@ __device__ __forceinline__ void tri_staged(const DevArgs& a) {
           // resolved at plan time: one load per streamed set
           const uint4 r = b0 == 0 ? r0 : a.rec[lbeg + b0 + lane];
           g = Seg{r.x, r.y, int32_t(r.z)};
-        } else if (a.tin) {
-          const uint2 ie = a.tin[lbeg + b0 + lane];  // in-edge u -> s at position ie.y
-          g = seg_suffix(a, ie.x, ie.y, s, wr);
         } else {
           g = seg_full(a, a.idx[lbeg + b0 + lane], wr);
         }
