@@ -167,7 +167,7 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
   a.idx = static_cast<const uint32_t*>(t.col.p);
   if (p->staging == EH_STAGE_TARGET) {
     if (p->sdesc.p) a.sdesc = static_cast<const uint4*>(p->sdesc.p) + i0;
-    a.rec = static_cast<const uint4*>(p->rec.p);
+    a.rec = static_cast<const uint2*>(p->rec.p);
     if (p->group > 1) a.gsub = static_cast<const uint4*>(p->gsub.p);
   }
   a.acc = acc;

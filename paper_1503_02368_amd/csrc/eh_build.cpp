@@ -464,7 +464,11 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
     // Resolve on the host what each wave would otherwise look up through
     // chains of dependent loads: the staged set's extent per item, and per
     // in-edge u->v the streamed part of N+(u) above v (elements, or bitset
-    // words when fewer and v's set will be held as a bitmap).
+    // words when fewer and v's set will be held as a bitmap).  A record is
+    // 8 bytes, {start | kHiBit for words, length | word offset << 16}: a
+    // length fits 16 bits because degree order bounds out-degrees by
+    // sqrt(2m) < 2^16, and words are clipped to the staged bitmap's window
+    // (words outside it cannot match), so the offset is in [0, cap).
     const uint32_t cap = tu.stage_words && tu.stage_words < kStageWords ? tu.stage_words
                                                                          : kStageWords;
     auto staged_lo_al = [&](uint32_t v) { return h.col[h.row[v]] & ~31u; };
@@ -546,25 +550,33 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
       }
     }
     if (sd.empty()) sd.assign(4, 0);
-    std::vector<uint32_t> rec(4 * std::max<uint64_t>(h.m, 1), 0);
+    std::vector<uint32_t> rec(2 * std::max<uint64_t>(h.m, 1), 0);
     for (uint64_t k = 0; k < h.m; ++k) {
       const uint32_t u = t->tin[2 * k], e = t->tin[2 * k + 1], v = h.col[e];
       const uint32_t len = h.row[u + 1] - e - 1;
-      uint32_t sb = e + 1, n = len;
-      int32_t sm = 0;
+      uint32_t sb = e + 1, n = len, sm = 0;
       if (ub && len && !grouped[v] && h.bs_off[u] != kNoBitset && h.row[v + 1] > h.row[v] &&
           bitmap_mode(v)) {
         const uint32_t w0 = (v + 1 - h.bs_base[u]) >> 5;
-        const uint32_t nw = w0 < h.bs_nw[u] ? h.bs_nw[u] - w0 : 0u;
-        if (nw < len) {
-          sb = (uint32_t(h.m) + h.bs_off[u] + w0) | kHiBit;
-          n = nw;
-          sm = int32_t((h.bs_base[u] >> 5) + w0) - int32_t(staged_lo_al(v) >> 5);
+        const int64_t nw = w0 < h.bs_nw[u] ? int64_t(h.bs_nw[u] - w0) : 0;
+        // the first streamed word's index in the staged bitmap, then the
+        // part of the words that overlaps the bitmap [0, cap)
+        const int64_t off = int64_t((h.bs_base[u] >> 5) + w0) - int64_t(staged_lo_al(v) >> 5);
+        const int64_t first = std::max<int64_t>(0, -off);
+        const int64_t last = std::min<int64_t>(nw, int64_t(cap) - off);
+        const int64_t words = last > first ? last - first : 0;
+        if (words < int64_t(len)) {
+          sb = (uint32_t(h.m) + h.bs_off[u] + w0 + uint32_t(first)) | kHiBit;
+          n = uint32_t(words);
+          sm = words ? uint32_t(off + first) : 0u;
         }
       }
-      rec[4 * k] = sb;
-      rec[4 * k + 1] = n;
-      rec[4 * k + 2] = uint32_t(sm);
+      if (n > 0xFFFFu || sm > 0xFFFFu) {
+        c->err = "segment record field beyond 16 bits";
+        return EH_EOVERFLOW;
+      }
+      rec[2 * k] = sb;
+      rec[2 * k + 1] = n | (sm << 16);
     }
     if (gsub.empty()) gsub.assign(4, 0);
     if ((st = dev_alloc(c, plan->sdesc, sizeof(uint32_t) * sd.size())) != EH_OK ||

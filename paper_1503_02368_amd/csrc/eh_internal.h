@@ -110,8 +110,8 @@ struct Plan {
   uint64_t n_items = 0;
   DevBuf items;
   // target staging only: per item {begin, length, min, max} of the staged set,
-  // and per in-edge the streamed segment {start | kHiBit for words, length,
-  // word offset from the staged bitmap, 0}
+  // and per in-edge the streamed segment {start | kHiBit for words, length |
+  // word offset from the staged bitmap << 16} (uint2)
   DevBuf sdesc;
   DevBuf rec;
   // grouped items: per member {first record, records, first member in col,
@@ -179,7 +179,7 @@ struct LaunchArgs {
   uint64_t n_items = 0;
   const uint32_t* idx = nullptr;       // streamed vertex list (source staging)
   const uint4* sdesc = nullptr;        // per item staged-set descriptor, or null
-  const uint4* rec = nullptr;          // per in-edge segment record, or null
+  const uint2* rec = nullptr;          // per in-edge segment record, or null
   const uint2* vdesc = nullptr;
   const uint32_t* col = nullptr;
   const uint4* bsdesc = nullptr;

@@ -48,7 +48,7 @@ struct DevArgs {
   uint64_t n_items;
   const uint32_t* idx;
   const uint4* sdesc;  // per item {begin, length, min, max} of the staged set, or null
-  const uint4* rec;    // per in-edge streamed segment {start, length, word delta, 0}, or null
+  const uint2* rec;    // per in-edge streamed segment {start, length | word offset << 16}, or null
   const uint2* vdesc;
   const uint32_t* col;
   const uint4* bsdesc;
@@ -680,8 +680,8 @@ __device__ __forceinline__ uint32_t grouped_item(const DevArgs& a, const SegTab&
     const uint32_t k = uint32_t(lane >= q1) + uint32_t(lane >= q2) + uint32_t(lane >= q3);
     const uint32_t qk = k == 0 ? 0u : k == 1 ? q1 : k == 2 ? q2 : q3;
     const uint32_t bk = k == 0 ? rb0 : k == 1 ? rb1 : k == 2 ? rb2 : rb3;
-    const uint4 r = a.rec[bk + lane - qk];
-    g = Seg{r.x, r.y, int32_t(k)};
+    const uint2 r = a.rec[bk + lane - qk];
+    g = Seg{r.x, r.y & 0xFFFFu, int32_t(k)};
   }
   // staging: lane m holds member m - p_k of set k, at bit (x - base) K + k
   uint32_t pos = 0;
@@ -752,7 +752,7 @@ __device__ __forceinline__ void tri_staged(const DevArgs& a) {
       continue;
     }
     // the first batch of segment records is loaded beside the staged set
-    uint4 r0{0, 0, 0, 0};
+    uint2 r0{0, 0};
     if (a.rec && lane < min(uint32_t(kSeg), llen)) r0 = a.rec[lbeg + lane];
     const Staged st = a.sdesc ? stage_extent<RW>(a, uniform(sd.x), uniform(sd.y), uniform(sd.z),
                                                  uniform(sd.w), R, Lp, lane)
@@ -766,8 +766,8 @@ __device__ __forceinline__ void tri_staged(const DevArgs& a) {
       if (lane < nseg) {
         if (a.rec) {
           // resolved at plan time: one load per streamed set
-          const uint4 r = b0 == 0 ? r0 : a.rec[lbeg + b0 + lane];
-          g = Seg{r.x, r.y, int32_t(r.z)};
+          const uint2 r = b0 == 0 ? r0 : a.rec[lbeg + b0 + lane];
+          g = Seg{r.x, r.y & 0xFFFFu, int32_t(r.y >> 16)};
         } else {
           g = seg_full(a, a.idx[lbeg + b0 + lane], wr);
         }
