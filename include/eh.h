@@ -190,8 +190,10 @@ eh_status eh_count_4cliques(eh_ctx* ctx, const eh_trie* trie, uint64_t* total);
  * when the stream reaches it.  pattern: EH_TRIANGLE or EH_4CLIQUE. */
 eh_status eh_count_async(eh_ctx* ctx, const eh_trie* trie, int pattern, uint64_t* d_total);
 /* As eh_count_async, but adds the count to *d_total instead of overwriting
- * it, so that with the default static schedule one call is exactly one
- * kernel launch: k calls on a zeroed d_total leave k times the count. */
+ * it: k calls on a zeroed d_total leave k times the count.  With the static
+ * schedules (0, 2, 3) a call is one counting launch; schedules 1 and 4 add
+ * a cursor reset before it, and a 4-clique count whose roots include
+ * out-degrees above 512 takes a second launch for those. */
 eh_status eh_count_add_async(eh_ctx* ctx, const eh_trie* trie, int pattern, uint64_t* d_total);
 
 /* Instances whose root is in the set {roots[i]} (original ids; duplicates are
@@ -200,7 +202,8 @@ eh_status eh_count_rooted(eh_ctx* ctx, const eh_trie* trie, int pattern, const u
                           uint32_t n_roots, uint64_t* total);
 
 /* Per-graph counts of graphs [first, first+count) of a batch trie, all in one
- * launch.  out_counts: host array of count uint64. */
+ * counting launch (see eh_count_add_async for the exceptions).  out_counts:
+ * host array of count uint64. */
 eh_status eh_count_batch(eh_ctx* ctx, const eh_trie* batch, int pattern, uint32_t first,
                          uint32_t count, uint64_t* out_counts);
 /* Enqueue-only batch form; d_out: device array of count uint64. */
