@@ -99,6 +99,36 @@ def bench_batch(name, w, args, ctx, eh, torch, metric):
     ms = e0.elapsed_time(e1) / args.steps
     one = out.cpu().numpy().view(np.uint64).copy()
     log(f"[bench] one launch: {ms:.3f} ms per pass")
+    # the same launch captured once into a HIP graph and replayed
+    ms_one_graph = None
+    try:
+        g1 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g1, stream=s):
+            ctx.count_batch_async(trie, pattern, 0, G, out)
+        # replays run on the context's stream, the one the events time
+        with torch.cuda.stream(s):
+            g1.replay()
+        torch.cuda.synchronize()
+        e0.record(s)
+        with torch.cuda.stream(s):
+            for _ in range(args.steps):
+                g1.replay()
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms_one_graph = e0.elapsed_time(e1) / args.steps
+        out.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g1.replay()
+        torch.cuda.synchronize()
+        if not np.array_equal(out.cpu().numpy().view(np.uint64), one):
+            raise RuntimeError("graph-replayed batch counts differ from the eager launch")
+        log(f"[bench] one launch, graph replay: {ms_one_graph:.3f} ms per pass")
+        del g1
+    except RuntimeError as e:
+        if "differ" in str(e):
+            raise
+        log(f"[bench] graph capture unavailable: {e}")
     if getattr(args, "no_per_instance", False):
         trie.free()
         achieved = info["b_merge"] / (ms / 1e3) / 1e9
@@ -135,15 +165,22 @@ def bench_batch(name, w, args, ctx, eh, torch, metric):
         with torch.cuda.graph(g, stream=s):
             for i in range(G):
                 ctx.count_batch_async(trie, pattern, i, 1, per_g[i:i + 1])
-        g.replay()
+        with torch.cuda.stream(s):
+            g.replay()
         torch.cuda.synchronize()
         e0.record(s)
         reps = 3
-        for _ in range(reps):
-            g.replay()
+        with torch.cuda.stream(s):
+            for _ in range(reps):
+                g.replay()
         e1.record(s)
         torch.cuda.synchronize()
         ms_graph = e0.elapsed_time(e1) / reps
+        per_g.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g.replay()
+        torch.cuda.synchronize()
         if not np.array_equal(per_g.cpu().numpy().view(np.uint64), one):
             raise RuntimeError("graph-replayed per-graph counts differ from the one-launch counts")
         log(f"[bench] one launch per graph, graph replay: {ms_graph:.3f} ms per pass")
@@ -165,6 +202,7 @@ def bench_batch(name, w, args, ctx, eh, torch, metric):
                    "seed": w["seed"], "layout": ["uint", "hybrid", "bitset_all"][layout], "tau": tau,
                    "tuning": ctx.get_tuning()},
         "count_total": int(one.sum(dtype=np.uint64)),
+        "one_launch_graph_replay_ms": ms_one_graph,
         "per_instance": {"ms_per_pass": ms_loop, "edges_per_s": m_plus / (ms_loop / 1e3),
                          "graph_replay_ms_per_pass": ms_graph,
                          "speedup_of_one_launch": ms_loop / ms,

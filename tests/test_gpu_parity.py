@@ -556,3 +556,48 @@ def test_out_degree_limits(ctx, eh):
         assert ctx.count_rooted(trie, eh.CLIQUE4, roots) == sum(comb(n - 1 - int(i), 3) for i in roots)
     finally:
         trie.free()
+
+
+def test_graph_capture_replay(ctx, eh):
+    """The one-launch batch count and an accumulating single-graph count are
+    captured into a HIP graph (after warm-up calls have built their plans) and
+    replayed several times, with eager counts and synchronizations in between;
+    every replay gives the eager result.  The capture holds the cursor-reset
+    and output-clearing kernels of schedule 4 (fill kernels, no memset nodes)."""
+    import torch
+    tune(ctx, dynamic=4, grab=4, group=4)
+    b = small_batch(60, seed=21)
+    want = np.array([oracle.Graph.from_edgelist(b.graph(i)).triangles()["count"]
+                     for i in range(b.n_graphs)], np.uint64)
+    el = inputs.rmat(12, 16, seed=22)
+    T = oracle.Graph.from_edgelist(el).triangles()["count"]
+    bt = ctx.build_batch(b)
+    gt = ctx.build_edgelist(el)
+    try:
+        G = bt.info["n_graphs"]
+        out_b = torch.zeros(G, dtype=torch.int64, device="cuda")
+        out_t = torch.zeros(1, dtype=torch.int64, device="cuda")
+        s = ctx.stream
+        s.wait_stream(torch.cuda.current_stream())
+        ctx.count_batch_async(bt, eh.TRIANGLE, 0, G, out_b)
+        ctx.count_add_async(gt, eh.TRIANGLE, out_t)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            ctx.count_batch_async(bt, eh.TRIANGLE, 0, G, out_b)
+            ctx.count_add_async(gt, eh.TRIANGLE, out_t)
+        out_b.zero_()
+        out_t.zero_()
+        torch.cuda.synchronize()
+        for rep in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(out_b.cpu().numpy().view(np.uint64), want)
+            assert int(out_t.cpu().numpy().view(np.uint64)[0]) == (rep + 1) * T
+            # eager work on the same context between replays
+            assert ctx.count_triangles(gt) == T
+            np.testing.assert_array_equal(ctx.count_batch(bt, eh.TRIANGLE), want)
+        del g
+    finally:
+        bt.free()
+        gt.free()
