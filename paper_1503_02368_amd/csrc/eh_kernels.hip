@@ -14,14 +14,16 @@
 //   range, as the set optimizer of section 4.4 builds it), else as a bitset
 //   over its top window plus a searched prefix (a two-block composite,
 //   section 4.3).  The streamed sets are concatenated into one flat index
-//   space that the 64 lanes walk, each lane finding its element's set by a
-//   cursor along the batch's length prefix (long sets) or a binary search of
-//   it (short sets), so short and long lists alike keep every lane busy and
-//   reads coalesced.  Each streamed element is tested against the staged set:
-//   a bit probe (uint & bitset, section 4.2), or, when the streamed set is
-//   stored as a bitset with fewer words than elements, a 32-bit word AND +
-//   popcount (bitset & bitset), or a binary search of the composite's prefix
-//   (galloping).
+//   space that the 64 lanes walk: long sets lane-strided, each lane moving a
+//   cursor along the batch's length prefix; short sets in contiguous runs
+//   per lane, each found by one binary search of the prefix.  Short and long
+//   lists alike keep every lane busy.  Each streamed element is tested
+//   against the staged set: a bit probe (uint & bitset, section 4.2), or,
+//   when the streamed set is stored as a bitset with fewer words than
+//   elements, a 32-bit word AND + popcount (bitset & bitset), or a binary
+//   search of the composite's prefix (galloping).  Small items can be
+//   grouped: up to four share a wave, their staged sets interleaved in one
+//   bitmap and their streamed sets in one walk.
 //
 // * Pairwise ("k_tri_pairwise"): a group of G lanes per pair (s, t) reading
 //   both sets from HBM, dispatching per pair on the layouts and sizes as in
