@@ -16,8 +16,10 @@
 // Continuous batching: a progress thread repeatedly (1) admits queued
 // requests in arrival order while the summed device footprint of active
 // requests fits the budget and a slot is free, (2) gathers up to step_items
-// work items from all active requests, oldest first, (3) runs them as one
-// device step (one launch per pattern) that adds into per-slot counters, and
+// work items from all active requests, oldest first (or, by option, those
+// with the fewest items left first), (3) runs them as one device step (one
+// launch per pattern, two for 4-cliques with roots of out-degree above 512)
+// that adds into per-slot counters, and
 // (4) retires every request whose items have all completed.  Requests that
 // arrive while a step runs join the next step; their work shares launches with
 // requests admitted earlier.  The step after the one that finishes a request
