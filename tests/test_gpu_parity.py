@@ -601,3 +601,45 @@ def test_graph_capture_replay(ctx, eh):
     finally:
         bt.free()
         gt.free()
+
+
+def test_randomized_parity(ctx, eh):
+    """Seeded random graphs (R-MAT, G(n,p), Chung-Lu, unions, messy input)
+    under seeded random settings of every tuning knob: each triangle and
+    4-clique count equals the oracle's."""
+    key = inputs.stream_key(77, 7)
+    draws = inputs.rand_u64(key, 0, 100 * 32)
+    pick = iter(int(x) for x in draws)
+
+    def choice(xs):
+        return xs[next(pick) % len(xs)]
+
+    for case in range(100):
+        kind = choice(["rmat", "gnp", "cl", "union", "messy"])
+        seed = 1000 + case
+        if kind == "rmat":
+            el = inputs.rmat(choice([6, 8, 10, 11]), choice([4, 16]), seed=seed)
+        elif kind == "gnp":
+            el = inputs.gnp(choice([20, 60, 150]), choice([0.05, 0.3, 0.7]), seed)
+        elif kind == "cl":
+            el = inputs.chung_lu(choice([300, 2000]), choice([4.0, 24.0]), 2.1, seed=seed, graph=case)
+        elif kind == "union":
+            el = inputs.disjoint_union(inputs.complete(choice([5, 30])), inputs.rmat(8, 8, seed=seed))
+        else:
+            el = inputs.messy(inputs.rmat(9, 8, seed=seed), seed)
+        t = dict(kernel=choice([1, 1, 2]), staging=choice([1, 2]), use_bitsets=choice([0, 1]),
+                 dynamic=choice([0, 1, 2, 3, 4]), grab=choice([1, 3, 16]), xcds=choice([0, 3, 8]),
+                 stage_words=choice([0, 8, 96, 512]), search_below=choice([0, 12, 4096]),
+                 group=choice([1, 2, 4]), chunk_work=choice([64, 1000, 32768]),
+                 waves_per_cu=choice([1, 8, 32]), unroll=choice([4, 8]),
+                 group_lanes=choice([0, 4, 64]), algo=choice([0, 1, 2]))
+        tune(ctx, **t)
+        layout, tau = choice([(0, 32.0), (1, 2.0), (1, 32.0), (1, 256.0), (2, 32.0)])
+        T, K, _ = truth(el)
+        trie = ctx.build_edgelist(el, layout=layout, tau=tau)
+        try:
+            assert ctx.count_triangles(trie) == T, (case, kind, t, layout, tau)
+            if trie.info["max_out_degree"] <= 2048:
+                assert ctx.count_4cliques(trie) == K, (case, kind, t, layout, tau)
+        finally:
+            trie.free()
