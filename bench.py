@@ -14,6 +14,8 @@ Prints one JSON line.  Workloads (--workload):
   er4096_triangles  G(n=4096, M=32768), uint-only layout
   batch_triangles   20,000 Chung-Lu graphs counted in one launch, beside one
                     launch per graph
+  orderings         node orderings of appendix A on Chung-Lu graphs (n = 2^20,
+                    degree exponents 1.75 .. 3): triangle counting per ordering
   served            resident R-MAT scale 22, Poisson stream of rooted
                     triangle / 4-clique requests: p50/p99 latency
 """
@@ -187,6 +189,9 @@ def main():
     elif w["kind"] == "batch":
         from paper_1503_02368_amd import bench_extra
         res = bench_extra.bench_batch(name, w, args, ctx, eh, torch, METRIC)
+    elif w["kind"] == "orderings":
+        from paper_1503_02368_amd import bench_extra
+        res = bench_extra.bench_orderings(name, w, args, ctx, eh, torch, METRIC)
     else:
         from paper_1503_02368_amd import bench_extra
         res = bench_extra.bench_served(name, w, args, ctx, eh, torch, METRIC)

@@ -86,7 +86,7 @@ const char* eh_last_error(const eh_ctx* ctx);
 const char* eh_status_str(eh_status s);
 /* Version of this ABI (major * 10000 + minor * 100 + patch); a caller built
  * against this header checks that the library returns EH_ABI_VERSION. */
-#define EH_ABI_VERSION 10300
+#define EH_ABI_VERSION 10400
 int32_t eh_abi_version(void);
 
 /* ---- tuning knobs (performance only; counts never depend on them) ------- */
@@ -97,7 +97,9 @@ enum { EH_ALGO_AUTO = 0, EH_ALGO_MERGE = 1, EH_ALGO_SEARCH = 2 };
 
 typedef struct eh_tuning {
   uint32_t kernel;       /* EH_KERNEL_*: staged (one set held in LDS) or pairwise */
-  uint32_t staging;      /* staged kernel, triangle totals: which end of an edge is held */
+  uint32_t staging;      /* staged kernel, triangle totals: which end of an edge is held;
+                            target staging needs out-degrees below 2^16 (always so under
+                            degree order) and tries beyond that stage sources */
   uint32_t algo;         /* pairwise uint & uint: EH_ALGO_AUTO applies the gamma rule */
   float gamma;           /* galloping when the longer list exceeds gamma x the shorter
                             (section 4.2 uses 32); <= 0 keeps the current value */
@@ -140,6 +142,37 @@ eh_status eh_ctx_get_tuning(const eh_ctx* ctx, eh_tuning* out);
 
 /* ---- tries -------------------------------------------------------------- */
 
+/* Node orderings (section 2.2 dictionary encoding; appendix A, node
+ * ordering).  An ordering is the sequence in which vertices receive their
+ * 32-bit labels; the paper then keeps each undirected edge once, from the
+ * larger label to the smaller.  The trie stores rank = n - 1 - label and
+ * directs edges from lower to higher rank: the same edges, and the same gaps
+ * inside every set.  Ties and traversal details:
+ *   DEGREE       degree descending, ties id descending (rank = (degree asc,
+ *                id asc)); out-degrees stay below sqrt(2m)
+ *   REV_DEGREE   degree ascending, ties id ascending
+ *   INPUT        the ids as given (label = id): a caller relabels first for
+ *                Random, Shingle or any other external ordering
+ *   BFS          breadth-first discovery order; each traversal starts at the
+ *                unvisited vertex of highest degree (ties: lowest id), and a
+ *                vertex's neighbours are discovered in ascending id order
+ *   HYBRID       the BFS labels, then a stable sort by degree descending
+ *   STRONG_RUNS  vertices visited by degree descending (ties id ascending);
+ *                a visited vertex takes the next label if it has none, then
+ *                its unlabelled neighbours take the next labels in ascending
+ *                id order
+ * Counts do not depend on the ordering; rooted counts (root = the vertex of
+ * smallest rank), set layouts and the work do.  Only DEGREE bounds the
+ * out-degree, and the 4-clique kernel accepts out-degrees up to 2048. */
+enum {
+  EH_ORDER_DEGREE = 0,
+  EH_ORDER_REV_DEGREE = 1,
+  EH_ORDER_INPUT = 2,
+  EH_ORDER_BFS = 3,
+  EH_ORDER_HYBRID = 4,
+  EH_ORDER_STRONG_RUNS = 5
+};
+
 /* Set optimizer of section 4.4: a set S becomes a bitset iff |S| >= s_min and
  * (max(S) - min(S) + 1) / |S| <= tau.  The paper's rule is one AVX register
  * (256 bits) per value: tau = 256.  tau <= 0 selects 32; s_min 0 selects 1. */
@@ -147,6 +180,7 @@ typedef struct eh_build_opts {
   uint32_t layout;  /* EH_LAYOUT_* */
   float tau;
   uint32_t s_min;
+  uint32_t order;   /* EH_ORDER_*; a value above 5 is EH_EINVAL */
 } eh_build_opts;
 
 typedef struct eh_trie_info {
@@ -163,7 +197,8 @@ typedef struct eh_trie_info {
 
 /* Builds the trie of one graph on the host (clean, rank, orient, CSR, set
  * layouts; section 2.2 dictionary encoding, section 5.2 pruning) and uploads
- * it.  src/dst: n_edges raw pairs.  opts may be NULL (hybrid, tau 32). */
+ * it.  src/dst: n_edges raw pairs.  opts may be NULL (hybrid layout, tau 32,
+ * degree order). */
 eh_status eh_build_trie(eh_ctx* ctx, const uint32_t* src, const uint32_t* dst, uint64_t n_edges,
                         uint32_t n_vertices, const eh_build_opts* opts, eh_trie** out);
 

@@ -10,7 +10,8 @@ Definitions (paper section 2.1 Generic-Join; section 3.3 triangle loop nest;
 section 5.2 pruning each undirected edge once by degree-assigned ids):
 self-loops are dropped and every other pair is an undirected edge; T counts
 3-vertex subsets that are triangles, K counts 4-vertex cliques; the root of
-an instance is its vertex of smallest rank, rank = (degree asc, id asc).
+an instance is its vertex of smallest rank, rank = (degree asc, id asc), or
+the ranks of another node ordering (appendix A; ``orderings.py``).
 """
 from __future__ import annotations
 
@@ -55,6 +56,8 @@ def _load():
         lib.orc_graph_new.argtypes = [ctypes.c_uint32, ctypes.c_uint64, _u32p, _u32p,
                                       ctypes.POINTER(ctypes.c_int)]
         lib.orc_graph_free.argtypes = [vp]
+        lib.orc_graph_rerank.restype = ctypes.c_int
+        lib.orc_graph_rerank.argtypes = [vp, _u32p]
         lib.orc_num_edges.restype = ctypes.c_uint64
         lib.orc_num_edges.argtypes = [vp]
         lib.orc_get_edges.argtypes = [vp, _u32p, _u32p]
@@ -91,7 +94,7 @@ def max_threads() -> int:
 class Graph:
     """The cleaned, ranked and oriented graph the oracle counts on."""
 
-    def __init__(self, n: int, src, dst):
+    def __init__(self, n: int, src, dst, order: str | None = None):
         lib = _load()
         self._lib = lib
         src = np.ascontiguousarray(src, dtype=np.uint32)
@@ -104,10 +107,22 @@ class Graph:
             raise ValueError("vertex id out of range" if err.value == 1 else "oracle out of memory")
         self.n = int(n)
         self.m = int(lib.orc_num_edges(self._h))
+        if order is not None and order != "degree":
+            from oracle.orderings import ranks
+            self.rerank(ranks(self, order))
+
+    def rerank(self, rank) -> None:
+        """Ranks vertices by rank[id] (a permutation) instead of (degree, id)."""
+        rank = np.ascontiguousarray(rank, dtype=np.uint32)
+        if rank.shape != (self.n,):
+            raise ValueError("rank needs one entry per vertex")
+        st = self._lib.orc_graph_rerank(self._h, _p32(rank))
+        if st:
+            raise ValueError("rank is not a permutation" if st == 1 else "oracle out of memory")
 
     @classmethod
-    def from_edgelist(cls, el) -> "Graph":
-        return cls(el.n, el.src, el.dst)
+    def from_edgelist(cls, el, order: str | None = None) -> "Graph":
+        return cls(el.n, el.src, el.dst, order)
 
     def __del__(self):
         h = getattr(self, "_h", None)

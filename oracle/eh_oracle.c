@@ -12,7 +12,8 @@
  *   T = number of 3-vertex subsets of V with all three edges in E.
  *   K = number of 4-vertex subsets of V with all six edges in E.
  *   Rooted counts: the root of an instance is its vertex of smallest rank,
- *   where rank orders vertices by (degree in G ascending, id ascending).
+ *   where rank orders vertices by (degree in G ascending, id ascending), or
+ *   is any permutation given by orc_graph_rerank (a node ordering).
  *
  * How (paper section 2.1, Algorithm 1 "Generic-Join", instantiated for the
  * triangle in section 3.3 "GHD Translation"; pruned input as in section 5.2):
@@ -79,6 +80,30 @@ void orc_graph_free(orc_graph* g) {
   free(g);
 }
 
+/* 6: oriented adjacency, lower rank -> higher rank, rows sorted */
+static int orient(orc_graph* g) {
+  uint32_t n = g->n;
+  uint64_t m = g->m;
+  memset(g->off, 0, ((size_t)n + 1) * sizeof(uint64_t));
+  for (uint64_t i = 0; i < m; ++i) {
+    uint32_t ra = g->rank[g->ea[i]], rb = g->rank[g->eb[i]];
+    g->off[(ra < rb ? ra : rb) + 1]++;
+  }
+  for (uint32_t r = 0; r < n; ++r) g->off[r + 1] += g->off[r];
+  uint64_t* fill = (uint64_t*)malloc(((size_t)n + 1) * sizeof(uint64_t));
+  if (!fill) return 1;
+  memcpy(fill, g->off, ((size_t)n + 1) * sizeof(uint64_t));
+  for (uint64_t i = 0; i < m; ++i) {
+    uint32_t ra = g->rank[g->ea[i]], rb = g->rank[g->eb[i]];
+    uint32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
+    g->nbr[fill[lo]++] = hi;
+  }
+  free(fill);
+  for (uint32_t r = 0; r < n; ++r)
+    qsort(g->nbr + g->off[r], g->off[r + 1] - g->off[r], sizeof(uint32_t), cmp_u32);
+  return 0;
+}
+
 /* err: 0 ok, 1 id out of range, 2 out of memory */
 orc_graph* orc_graph_new(uint32_t n, uint64_t m_raw, const uint32_t* src,
                          const uint32_t* dst, int* err) {
@@ -125,24 +150,28 @@ orc_graph* orc_graph_new(uint32_t n, uint64_t m_raw, const uint32_t* src,
   g_sort_deg = g->deg;
   qsort(g->vert, n, sizeof(uint32_t), cmp_deg_id);
   for (uint32_t r = 0; r < n; ++r) g->rank[g->vert[r]] = r;
-  /* 6: oriented adjacency, lower rank -> higher rank, rows sorted */
-  for (uint64_t i = 0; i < m; ++i) {
-    uint32_t ra = g->rank[g->ea[i]], rb = g->rank[g->eb[i]];
-    g->off[(ra < rb ? ra : rb) + 1]++;
-  }
-  for (uint32_t r = 0; r < n; ++r) g->off[r + 1] += g->off[r];
-  uint64_t* fill = (uint64_t*)malloc(((size_t)n + 1) * sizeof(uint64_t));
-  if (!fill) { *err = 2; orc_graph_free(g); return NULL; }
-  memcpy(fill, g->off, ((size_t)n + 1) * sizeof(uint64_t));
-  for (uint64_t i = 0; i < m; ++i) {
-    uint32_t ra = g->rank[g->ea[i]], rb = g->rank[g->eb[i]];
-    uint32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
-    g->nbr[fill[lo]++] = hi;
-  }
-  free(fill);
-  for (uint32_t r = 0; r < n; ++r)
-    qsort(g->nbr + g->off[r], g->off[r + 1] - g->off[r], sizeof(uint32_t), cmp_u32);
+  if (orient(g)) { *err = 2; orc_graph_free(g); return NULL; }
   return g;
+}
+
+/*
+ * Replaces the ranking by rank[id] (any permutation of 0..n-1: the node
+ * orderings of appendix A, "node ordering") and rebuilds the oriented
+ * adjacency.  Counts are the same under every ranking; rooted counts follow
+ * the new ranks.  Returns 0 ok, 1 not a permutation, 2 out of memory.
+ */
+int orc_graph_rerank(orc_graph* g, const uint32_t* rank) {
+  uint32_t n = g->n;
+  unsigned char* seen = (unsigned char*)calloc(n ? n : 1, 1);
+  if (!seen) return 2;
+  for (uint32_t v = 0; v < n; ++v) {
+    if (rank[v] >= n || seen[rank[v]]) { free(seen); return 1; }
+    seen[rank[v]] = 1;
+  }
+  free(seen);
+  for (uint32_t v = 0; v < n; ++v) g->vert[rank[v]] = v;
+  memcpy(g->rank, rank, (size_t)n * sizeof(uint32_t));
+  return orient(g) ? 2 : 0;
 }
 
 uint64_t orc_num_edges(const orc_graph* g) { return g->m; }

@@ -179,9 +179,13 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
   return launch_triangles(c, c->stream, a, c->tune.kernel, c->tune.waves_per_cu);
 }
 
-uint32_t tri_staging(const Ctx* c, bool per_root) {
+// Target staging describes each streamed suffix of N+(u) by a 16-bit length,
+// which degree order guarantees (out-degrees below sqrt(2m) < 2^16); tries
+// built under another node ordering may exceed it and then stage sources.
+uint32_t tri_staging(const Ctx* c, const Trie& t, bool per_root) {
   if (per_root) return EH_STAGE_SOURCE;
   if (c->tune.kernel == EH_KERNEL_PAIRWISE) return EH_STAGE_SOURCE;
+  if (t.host.dmax > 0xFFFFu) return EH_STAGE_SOURCE;
   return c->tune.staging == EH_STAGE_SOURCE ? EH_STAGE_SOURCE : EH_STAGE_TARGET;
 }
 
@@ -192,7 +196,7 @@ eh_status count_single(Ctx* c, Trie& t, int pattern, unsigned long long* d_total
     return EH_ESTATE;
   }
   Plan* p = nullptr;
-  const uint32_t staging = pattern == EH_TRIANGLE ? tri_staging(c, d_per_root != nullptr)
+  const uint32_t staging = pattern == EH_TRIANGLE ? tri_staging(c, t, d_per_root != nullptr)
                                                   : EH_STAGE_SOURCE;
   eh_status st = get_plan(c, &t, pattern, staging, &p);
   if (st != EH_OK) return st;
@@ -396,8 +400,8 @@ eh_status eh_build_trie(eh_ctx* ctx, const uint32_t* src, const uint32_t* dst, u
                         uint32_t n_vertices, const eh_build_opts* opts, eh_trie** out) {
   if (!ctx || !out || (n_edges && (!src || !dst))) return EH_EINVAL;
   *out = nullptr;
-  if (opts && opts->layout > EH_LAYOUT_BITSET_ALL) {
-    ctx->c.err = "unknown layout";
+  if (opts && (opts->layout > EH_LAYOUT_BITSET_ALL || opts->order > EH_ORDER_STRONG_RUNS)) {
+    ctx->c.err = "unknown layout or node ordering";
     return EH_EINVAL;
   }
   eh_trie* x = new (std::nothrow) eh_trie();
@@ -423,8 +427,8 @@ eh_status eh_build_batch(eh_ctx* ctx, uint32_t n_graphs, const uint32_t* n_verti
   if (!ctx || !out || !n_vertices || !edge_off || n_graphs == 0) return EH_EINVAL;
   if (edge_off[n_graphs] && (!src || !dst)) return EH_EINVAL;
   *out = nullptr;
-  if (opts && opts->layout > EH_LAYOUT_BITSET_ALL) {
-    ctx->c.err = "unknown layout";
+  if (opts && (opts->layout > EH_LAYOUT_BITSET_ALL || opts->order > EH_ORDER_STRONG_RUNS)) {
+    ctx->c.err = "unknown layout or node ordering";
     return EH_EINVAL;
   }
   eh_trie* x = new (std::nothrow) eh_trie();
@@ -588,7 +592,7 @@ static eh_status batch_enqueue(Ctx* c, Trie& t, int pattern, uint32_t first, uin
   Plan* p = nullptr;
   // per-graph tags need source staging, which also keeps graphs contiguous
   const uint32_t staging =
-      pattern == EH_TRIANGLE ? tri_staging(c, false) : uint32_t(EH_STAGE_SOURCE);
+      pattern == EH_TRIANGLE ? tri_staging(c, t, false) : uint32_t(EH_STAGE_SOURCE);
   eh_status st = get_plan(c, &t, uint32_t(pattern), staging, &p);
   if (st != EH_OK) return st;
   if ((st = launch_fill_u64(c, c->stream, d_out, count, 0)) != EH_OK) return st;
@@ -623,7 +627,8 @@ eh_status eh_host_trie_build(const uint32_t* src, const uint32_t* dst, uint64_t 
                              uint32_t n_vertices, const eh_build_opts* opts, eh_host_trie** out) {
   if (!out || (n_edges && (!src || !dst))) return EH_EINVAL;
   *out = nullptr;
-  if (opts && opts->layout > EH_LAYOUT_BITSET_ALL) return EH_EINVAL;
+  if (opts && (opts->layout > EH_LAYOUT_BITSET_ALL || opts->order > EH_ORDER_STRONG_RUNS))
+    return EH_EINVAL;
   eh_host_trie* x = new (std::nothrow) eh_host_trie();
   if (!x) return EH_ENOMEM;
   std::string err;

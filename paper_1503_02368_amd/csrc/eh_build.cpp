@@ -1,9 +1,10 @@
 // Host-side trie construction and work-item planning.
 //
-// Trie (paper section 2.2): ids are dictionary-encoded to dense 32-bit ranks
-// ordered by (degree ascending, id ascending); every undirected edge is kept
-// once, directed from lower to higher rank (the degree-based pruning of
-// section 5.2), giving a two-level trie stored as CSR.  Each non-empty
+// Trie (paper section 2.2): ids are dictionary-encoded to dense 32-bit ranks,
+// by default ordered by (degree ascending, id ascending), or by one of the
+// other node orderings of appendix A; every undirected edge is kept once,
+// directed from lower to higher rank (the pruning of section 5.2), giving a
+// two-level trie stored as CSR.  Each non-empty
 // neighbour set keeps its uint layout and, when the set optimizer of section
 // 4.4 calls it dense, also a bitset layout (section 4.1) with one block
 // spanning [min, max]: base = min rounded down to a multiple of 32, words of
@@ -23,6 +24,7 @@ BuildOpts resolve_opts(const eh_build_opts* o) {
   b.layout = o->layout;
   b.tau = o->tau > 0.0f ? o->tau : 32.0f;
   b.s_min = o->s_min ? o->s_min : 1;
+  b.order = o->order;
   return b;
 }
 
@@ -45,6 +47,137 @@ void radix_sort_u64(std::vector<uint64_t>& a) {
     for (auto& c : cnt) { uint64_t t = c; c = s; s += t; }
     for (size_t i = 0; i < n; ++i) tmp[cnt[(a[i] >> shift) & 0xFFFF]++] = a[i];
     a.swap(tmp);
+  }
+}
+
+// Vertices sorted by degree (descending when `desc`), ties by id ascending
+// (descending when `ids_desc`): a counting sort on degree.
+std::vector<uint32_t> by_degree(const std::vector<uint32_t>& deg, bool desc, bool ids_desc) {
+  const uint32_t n = uint32_t(deg.size());
+  uint32_t maxd = 0;
+  for (uint32_t d : deg) maxd = std::max(maxd, d);
+  std::vector<uint32_t> start(size_t(maxd) + 2, 0);
+  auto slot = [&](uint32_t d) { return desc ? maxd - d : d; };
+  for (uint32_t d : deg) start[slot(d) + 1]++;
+  for (size_t d = 1; d < start.size(); ++d) start[d] += start[d - 1];
+  std::vector<uint32_t> seq(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint32_t v = ids_desc ? n - 1 - i : i;
+    seq[start[slot(deg[v])]++] = v;
+  }
+  return seq;
+}
+
+// Symmetric adjacency of the cleaned pairs (a < b, sorted, unique): row v
+// lists v's neighbours in ascending id order.  Filling in pair order gives
+// sorted rows: the pairs (a, v), a < v, all precede the pairs (v, b).
+void symmetric_rows(uint32_t n, const std::vector<uint64_t>& key,
+                    const std::vector<uint32_t>& deg, std::vector<uint64_t>& off,
+                    std::vector<uint32_t>& adj) {
+  off.assign(size_t(n) + 1, 0);
+  for (uint32_t v = 0; v < n; ++v) off[v + 1] = off[v] + deg[v];
+  adj.resize(off[n]);
+  std::vector<uint64_t> fill(off.begin(), off.end() - 1);
+  for (uint64_t k : key) {
+    const uint32_t a = uint32_t(k >> 32), b = uint32_t(k & 0xFFFFFFFFu);
+    adj[fill[a]++] = b;
+    adj[fill[b]++] = a;
+  }
+}
+
+// Breadth-first labels (appendix A, node ordering): traversals start at the
+// unvisited vertex of highest degree (ties: lowest id); neighbours are
+// discovered in ascending id order.  Returns the vertices in label order.
+std::vector<uint32_t> bfs_sequence(uint32_t n, const std::vector<uint64_t>& off,
+                                   const std::vector<uint32_t>& adj,
+                                   const std::vector<uint32_t>& deg) {
+  std::vector<uint32_t> seq;
+  seq.reserve(n);
+  std::vector<uint8_t> seen(n, 0);
+  for (uint32_t root : by_degree(deg, true, false)) {
+    if (seen[root]) continue;
+    seen[root] = 1;
+    size_t head = seq.size();
+    seq.push_back(root);
+    while (head < seq.size()) {
+      const uint32_t v = seq[head++];
+      for (uint64_t e = off[v]; e < off[v + 1]; ++e) {
+        const uint32_t w = adj[e];
+        if (!seen[w]) { seen[w] = 1; seq.push_back(w); }
+      }
+    }
+  }
+  return seq;
+}
+
+// Strong runs (appendix A, node ordering): vertices visited by degree
+// descending (ties id ascending); a visited vertex takes the next label if it
+// has none, then its unlabelled neighbours take the next labels in ascending
+// id order.  Returns the vertices in label order.
+std::vector<uint32_t> strong_runs_sequence(uint32_t n, const std::vector<uint64_t>& off,
+                                           const std::vector<uint32_t>& adj,
+                                           const std::vector<uint32_t>& deg) {
+  std::vector<uint32_t> seq;
+  seq.reserve(n);
+  std::vector<uint8_t> seen(n, 0);
+  for (uint32_t v : by_degree(deg, true, false)) {
+    if (!seen[v]) { seen[v] = 1; seq.push_back(v); }
+    for (uint64_t e = off[v]; e < off[v + 1]; ++e) {
+      const uint32_t w = adj[e];
+      if (!seen[w]) { seen[w] = 1; seq.push_back(w); }
+    }
+  }
+  return seq;
+}
+
+// Dictionary encoding (section 2.2) under one of the node orderings of
+// appendix A.  `seq` lists the vertices in the order the ordering hands out
+// labels; the paper keeps each edge from the larger label to the smaller, so
+// rank = n - 1 - label with edges directed from lower to higher rank keeps
+// the same edges and the same gaps inside every set.
+void rank_vertices(uint32_t order, uint32_t n, const std::vector<uint64_t>& key,
+                   const std::vector<uint32_t>& deg, std::vector<uint32_t>& rank,
+                   std::vector<uint32_t>& vert) {
+  std::vector<uint32_t> seq;
+  switch (order) {
+    case EH_ORDER_REV_DEGREE:
+      seq = by_degree(deg, false, false);
+      break;
+    case EH_ORDER_INPUT:
+      seq.resize(n);
+      std::iota(seq.begin(), seq.end(), 0u);
+      break;
+    case EH_ORDER_BFS:
+    case EH_ORDER_HYBRID:
+    case EH_ORDER_STRONG_RUNS: {
+      std::vector<uint64_t> off;
+      std::vector<uint32_t> adj;
+      symmetric_rows(n, key, deg, off, adj);
+      seq = order == EH_ORDER_STRONG_RUNS ? strong_runs_sequence(n, off, adj, deg)
+                                          : bfs_sequence(n, off, adj, deg);
+      if (order == EH_ORDER_HYBRID) {
+        // stable sort of the BFS sequence by degree descending
+        std::vector<uint32_t> sorted(n);
+        uint32_t maxd = 0;
+        for (uint32_t d : deg) maxd = std::max(maxd, d);
+        std::vector<uint32_t> start(size_t(maxd) + 2, 0);
+        for (uint32_t d : deg) start[maxd - d + 1]++;
+        for (size_t d = 1; d < start.size(); ++d) start[d] += start[d - 1];
+        for (uint32_t v : seq) sorted[start[maxd - deg[v]]++] = v;
+        seq.swap(sorted);
+      }
+      break;
+    }
+    default:  // EH_ORDER_DEGREE
+      seq = by_degree(deg, true, true);
+      break;
+  }
+  rank.assign(n, 0);
+  vert.assign(n, 0);
+  for (uint32_t label = 0; label < n; ++label) {
+    const uint32_t r = n - 1 - label;
+    rank[seq[label]] = r;
+    vert[r] = seq[label];
   }
 }
 
@@ -79,19 +212,7 @@ eh_status build_one(const uint32_t* src, const uint32_t* dst, uint64_t m_raw, ui
   // degree in the simple undirected graph
   std::vector<uint32_t> deg(n, 0);
   for (uint64_t k : key) { deg[k >> 32]++; deg[k & 0xFFFFFFFFu]++; }
-  // rank by (degree asc, id asc): counting sort on degree, ids visited ascending
-  uint32_t maxd = 0;
-  for (uint32_t d : deg) maxd = std::max(maxd, d);
-  std::vector<uint32_t> start(size_t(maxd) + 2, 0);
-  for (uint32_t d : deg) start[d + 1]++;
-  for (size_t d = 1; d < start.size(); ++d) start[d] += start[d - 1];
-  h.rank.assign(n, 0);
-  h.vert.assign(n, 0);
-  for (uint32_t v = 0; v < n; ++v) {
-    const uint32_t r = start[deg[v]]++;
-    h.rank[v] = r;
-    h.vert[r] = v;
-  }
+  rank_vertices(opts.order, n, key, deg, h.rank, h.vert);
   // orient low rank -> high rank; rows sorted by scattering in target order
   std::vector<uint32_t> eu(m), ev(m);
   std::vector<uint32_t> by_v(size_t(n) + 1, 0);

@@ -62,6 +62,7 @@ struct BuildOpts {
   uint32_t layout = EH_LAYOUT_HYBRID;
   float tau = 32.0f;
   uint32_t s_min = 1;
+  uint32_t order = EH_ORDER_DEGREE;
 };
 BuildOpts resolve_opts(const eh_build_opts* o);
 

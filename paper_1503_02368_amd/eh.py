@@ -24,6 +24,9 @@ EH_OK, EH_PENDING = 0, 1
 EH_EINVAL, EH_ENOMEM, EH_EHIP, EH_EBUSY, EH_ENOTFOUND, EH_EOVERFLOW, EH_ESTATE = -1, -2, -3, -4, -5, -6, -7
 TRIANGLE, CLIQUE4 = 3, 4
 LAYOUT_UINT, LAYOUT_HYBRID, LAYOUT_BITSET_ALL = 0, 1, 2
+ORDER_DEGREE, ORDER_REV_DEGREE, ORDER_INPUT, ORDER_BFS, ORDER_HYBRID, ORDER_STRONG_RUNS = 0, 1, 2, 3, 4, 5
+ORDERS = {"degree": ORDER_DEGREE, "rev_degree": ORDER_REV_DEGREE, "input": ORDER_INPUT,
+          "bfs": ORDER_BFS, "hybrid": ORDER_HYBRID, "strong_runs": ORDER_STRONG_RUNS}
 KERNEL_AUTO, KERNEL_STAGED, KERNEL_PAIRWISE = 0, 1, 2
 STAGE_AUTO, STAGE_SOURCE, STAGE_TARGET = 0, 1, 2
 ALGO_AUTO, ALGO_MERGE, ALGO_SEARCH = 0, 1, 2
@@ -52,7 +55,7 @@ class _Allocator(ctypes.Structure):
 
 
 # struct layouts below are those of this ABI version of include/eh.h
-ABI_VERSION = 10300
+ABI_VERSION = 10400
 
 
 class _Tuning(ctypes.Structure):
@@ -66,7 +69,8 @@ class _Tuning(ctypes.Structure):
 
 
 class _BuildOpts(ctypes.Structure):
-    _fields_ = [("layout", ctypes.c_uint32), ("tau", ctypes.c_float), ("s_min", ctypes.c_uint32)]
+    _fields_ = [("layout", ctypes.c_uint32), ("tau", ctypes.c_float), ("s_min", ctypes.c_uint32),
+                ("order", ctypes.c_uint32)]
 
 
 class _TrieInfo(ctypes.Structure):
@@ -164,20 +168,20 @@ def _u32(a):
     return np.ascontiguousarray(a, dtype=np.uint32)
 
 
-def _opts(layout, tau, s_min):
-    return _BuildOpts(int(layout), float(tau), int(s_min))
+def _opts(layout, tau, s_min, order):
+    return _BuildOpts(int(layout), float(tau), int(s_min), int(order))
 
 
 def _info_dict(info: _TrieInfo) -> dict:
     return {k: int(getattr(info, k)) for k, _ in _TrieInfo._fields_ if k != "reserved"}
 
 
-def host_trie(n, src, dst, layout=LAYOUT_HYBRID, tau=32.0, s_min=1) -> dict:
+def host_trie(n, src, dst, layout=LAYOUT_HYBRID, tau=32.0, s_min=1, order=ORDER_DEGREE) -> dict:
     """Runs only the host half of the trie build (no GPU) and returns its arrays."""
     lib = load()
     src, dst = _u32(src), _u32(dst)
     h = _vp()
-    o = _opts(layout, tau, s_min)
+    o = _opts(layout, tau, s_min, order)
     st = lib.eh_host_trie_build(_p32(src), _p32(dst), src.size, int(n), ctypes.byref(o), ctypes.byref(h))
     if st != EH_OK:
         raise EHError(st, lib.eh_last_error(None).decode() or lib.eh_status_str(st).decode())
@@ -277,12 +281,13 @@ class Context:
         return self.get_tuning()
 
     # -- tries -------------------------------------------------------------
-    def build_trie(self, n, src, dst, layout=LAYOUT_HYBRID, tau=32.0, s_min=1) -> "Trie":
+    def build_trie(self, n, src, dst, layout=LAYOUT_HYBRID, tau=32.0, s_min=1,
+                   order=ORDER_DEGREE) -> "Trie":
         src, dst = _u32(src), _u32(dst)
         if src.shape != dst.shape:
             raise ValueError("src and dst differ in length")
         h = _vp()
-        o = _opts(layout, tau, s_min)
+        o = _opts(layout, tau, s_min, order)
         self._check(self._lib.eh_build_trie(self._h, _p32(src), _p32(dst), src.size, int(n),
                                             ctypes.byref(o), ctypes.byref(h)), "build_trie")
         return Trie(self, h)
@@ -290,12 +295,13 @@ class Context:
     def build_edgelist(self, el, **kw) -> "Trie":
         return self.build_trie(el.n, el.src, el.dst, **kw)
 
-    def build_batch(self, batch, layout=LAYOUT_HYBRID, tau=32.0, s_min=1) -> "Trie":
+    def build_batch(self, batch, layout=LAYOUT_HYBRID, tau=32.0, s_min=1,
+                    order=ORDER_DEGREE) -> "Trie":
         nv = _u32(batch.n_vertices)
         off = np.ascontiguousarray(batch.edge_off, dtype=np.uint64)
         src, dst = _u32(batch.src), _u32(batch.dst)
         h = _vp()
-        o = _opts(layout, tau, s_min)
+        o = _opts(layout, tau, s_min, order)
         self._check(self._lib.eh_build_batch(self._h, nv.size, _p32(nv), _p64(off), _p32(src), _p32(dst),
                                              ctypes.byref(o), ctypes.byref(h)), "build_batch")
         return Trie(self, h)

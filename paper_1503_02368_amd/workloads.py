@@ -10,6 +10,10 @@ WORKLOADS = {
     "er4096_triangles": dict(kind="graph", pattern=3, gen="er", n=4096, m=32768, seed=1, layout=0,
                              tau=32.0),
     "batch_triangles": dict(kind="batch", pattern=3, graphs=20000, seed=4, layout=1, tau=32.0),
+    # node-ordering study (appendix A): Chung-Lu graphs, degree exponents 1.75 .. 3
+    "orderings": dict(kind="orderings", n=1 << 20, avg_degree=16.0, gammas=[1.75, 2.0, 2.5, 3.0],
+                      orders=["random", "degree", "rev_degree", "bfs", "hybrid", "strong_runs"],
+                      seed=30, layout=1, tau=32.0),
     "served": dict(kind="served", gen="rmat", scale=22, edge_factor=16, seed=22, layout=1, tau=32.0),
 }
 

@@ -535,6 +535,95 @@ def test_batch_with_empty_graphs(ctx, eh):
         trie.free()
 
 
+ORDER_GRAPHS = [inputs.rmat(12, 16, seed=41), inputs.relabel(inputs.rmat(11, 16, seed=42), 3),
+                inputs.chung_lu(20000, 16, 1.8, seed=6), inputs.chung_lu(8000, 12, 2.6, seed=7),
+                inputs.erdos_renyi_gnm(3000, 4000, seed=8),
+                inputs.disjoint_union(inputs.complete(40), inputs.wheel(30), inputs.grid(9, 9))]
+_ORDER_TRUTH = {}
+
+
+def order_truth(el, order):
+    key = (el.name, order)
+    if key not in _ORDER_TRUTH:
+        g = oracle.Graph.from_edgelist(el, order)
+        t = g.triangles(rooted=True)
+        off, _ = g.oriented()
+        dmax = int(np.diff(off.astype(np.int64)).max())
+        k = g.cliques4(rooted=True) if dmax <= 2048 else None
+        _ORDER_TRUTH[key] = (t, k, dmax)
+    return _ORDER_TRUTH[key]
+
+
+@pytest.mark.parametrize("order", ["rev_degree", "input", "bfs", "hybrid", "strong_runs"])
+def test_node_orderings(ctx, eh, order):
+    """Node orderings (appendix A): totals equal the oracle's under every
+    ordering; per-root and rooted counts follow the ordering's ranks, which
+    the oracle computes with its own code.  Out-degrees above 2048 (only
+    possible away from degree order) refuse 4-cliques with EH_EOVERFLOW."""
+    for el in ORDER_GRAPHS:
+        t, k, dmax = order_truth(el, order)
+        say("order", order, el.name, "dmax", dmax)
+        trie = ctx.build_edgelist(el, order=eh.ORDERS[order])
+        try:
+            assert trie.info["max_out_degree"] == dmax
+            for tname in ("staged_target", "staged_source", "staged_lean", "staged_group",
+                          "pair_auto"):
+                tune(ctx, **TUNINGS[tname])
+                assert ctx.count_triangles(trie) == t["count"], (el.name, tname)
+            tune(ctx, **TUNINGS["staged_source"])
+            tot, per = ctx.count_triangles(trie, per_root=True)
+            assert tot == t["count"]
+            np.testing.assert_array_equal(per, t["root"])
+            roots = np.arange(0, el.n, 7, dtype=np.uint32)
+            assert ctx.count_rooted(trie, eh.TRIANGLE, roots) == oracle.rooted_count(t["root"], roots)
+            if k is None:
+                with pytest.raises(eh.EHError) as e:
+                    ctx.count_4cliques(trie)
+                assert e.value.status == eh.EH_EOVERFLOW
+            else:
+                for tname in ("staged_source", "staged_steal"):
+                    tune(ctx, **TUNINGS[tname])
+                    assert ctx.count_4cliques(trie) == k["count"], (el.name, tname)
+                assert ctx.count_rooted(trie, eh.CLIQUE4, roots) == oracle.rooted_count(k["root"], roots)
+        finally:
+            trie.free()
+
+
+def test_out_degree_beyond_16_bits(ctx, eh):
+    """Wheel W_70000 under reverse degree order: the hub's out-set holds all
+    70,000 rim vertices, beyond what target staging's 16-bit segment lengths
+    describe, so triangle totals stage sources instead: W_k has k triangles."""
+    k = 70000
+    el = inputs.wheel(k)
+    trie = ctx.build_edgelist(el, order=eh.ORDER_REV_DEGREE)
+    try:
+        assert trie.info["max_out_degree"] == k
+        for tname in ("staged_target", "staged_lean", "staged_group", "staged_source", "pair_auto"):
+            tune(ctx, **TUNINGS[tname])
+            assert ctx.count_triangles(trie) == k, tname
+        with pytest.raises(eh.EHError) as e:
+            ctx.count_4cliques(trie)
+        assert e.value.status == eh.EH_EOVERFLOW
+    finally:
+        trie.free()
+
+
+@pytest.mark.parametrize("order", ["bfs", "hybrid", "rev_degree"])
+def test_batch_node_orderings(ctx, eh, order):
+    tune(ctx, **TUNINGS["staged_group"])
+    b = small_batch(80, seed=13)
+    want = [order_truth(b.graph(i), order) for i in range(b.n_graphs)]
+    trie = ctx.build_batch(b, order=eh.ORDERS[order])
+    try:
+        np.testing.assert_array_equal(ctx.count_batch(trie, eh.TRIANGLE),
+                                      np.array([w[0]["count"] for w in want], np.uint64))
+        if all(w[1] is not None for w in want):
+            np.testing.assert_array_equal(ctx.count_batch(trie, eh.CLIQUE4),
+                                          np.array([w[1]["count"] for w in want], np.uint64))
+    finally:
+        trie.free()
+
+
 def test_out_degree_limits(ctx, eh):
     """K_2050: triangles at out-degree 2049 (C(n, 3)); the 4-clique kernel's
     S list holds at most 2048 entries, so its count is refused with

@@ -58,6 +58,28 @@ def test_trie_matches_oracle(el):
     assert h["max_out_degree"] == (d.max() if d.size else 0)
 
 
+ORDER_GRAPHS = [inputs.rmat(10, 16, seed=3), inputs.messy(inputs.rmat(9, 8, seed=4), 2),
+                inputs.chung_lu(3000, 24, 2.1, seed=1, graph=3),
+                inputs.disjoint_union(inputs.wheel(9), inputs.star(5), inputs.path(4),
+                                      inputs.complete(1), inputs.grid(4, 5))]
+
+
+@pytest.mark.parametrize("order", sorted(eh.ORDERS))
+@pytest.mark.parametrize("el", ORDER_GRAPHS, ids=lambda e: e.name)
+def test_node_orderings_match_oracle(el, order):
+    """Ranks (index work: bit-exact) and the oriented trie under each node
+    ordering of appendix A equal the oracle's, computed by its own code."""
+    h = eh.host_trie(el.n, el.src, el.dst, order=eh.ORDERS[order])
+    g = oracle.Graph.from_edgelist(el, order)
+    off, nbr = g.oriented()
+    np.testing.assert_array_equal(h["rank"], g.rank())
+    np.testing.assert_array_equal(h["row"], off.astype(np.uint32))
+    np.testing.assert_array_equal(h["col"], nbr)
+    assert h["b_merge"] == g.triangles()["bytes"]
+    d = np.diff(h["row"].astype(np.int64))
+    assert h["max_out_degree"] == (d.max() if d.size else 0)
+
+
 def expand_bitset(h, r):
     w = h["bs_words"][h["bs_off"][r]: h["bs_off"][r] + h["bs_nw"][r]]
     bits = np.unpackbits(w.view(np.uint8), bitorder="little")
@@ -102,6 +124,13 @@ def test_invalid_and_empty():
     with pytest.raises(eh.EHError) as e:
         eh.host_trie(4, np.array([0, 1], np.uint32), np.array([1, 4], np.uint32))
     assert e.value.status == eh.EH_EINVAL
+    with pytest.raises(eh.EHError) as e:
+        eh.host_trie(4, np.array([0], np.uint32), np.array([1], np.uint32), order=6)
+    assert e.value.status == eh.EH_EINVAL
+    for order in eh.ORDERS.values():
+        h = eh.host_trie(5, np.zeros(0, np.uint32), np.zeros(0, np.uint32), order=order)
+        assert h["m_plus"] == 0 and h["n"] == 5
+        assert sorted(h["rank"].tolist()) == list(range(5))
     h = eh.host_trie(7, np.zeros(0, np.uint32), np.zeros(0, np.uint32))
     assert h["m_plus"] == 0 and h["n"] == 7
     h = eh.host_trie(3, np.array([1, 2], np.uint32), np.array([1, 2], np.uint32))
