@@ -208,7 +208,36 @@ eh_status eh_build_batch(eh_ctx* ctx, uint32_t n_graphs, const uint32_t* n_verti
                          const uint64_t* edge_off, const uint32_t* src, const uint32_t* dst,
                          const eh_build_opts* opts, eh_trie** out);
 
+/* The trie of eh_build_trie, built on the GPU from raw pairs already in
+ * device memory (section 2.2 dictionary encoding, section 5.2 pruning,
+ * sections 4.1 and 4.4 layouts): the same arrays, and the same host copy
+ * (downloaded for work-item planning).  d_src/d_dst: device arrays of
+ * n_edges uint32, read on the context's stream and not kept; the caller
+ * keeps them valid until the call returns.  Orderings that are sorts only
+ * (EH_ORDER_DEGREE, EH_ORDER_REV_DEGREE, EH_ORDER_INPUT); the traversal
+ * orderings are EH_EINVAL here.  An id >= n is EH_EINVAL.  Scratch device
+ * memory of about 16 bytes per raw pair and 40 per vertex, plus the sorts'
+ * working space, is freed before it returns. */
+eh_status eh_build_trie_device(eh_ctx* ctx, const uint32_t* d_src, const uint32_t* d_dst,
+                               uint64_t n_edges, uint32_t n_vertices, const eh_build_opts* opts,
+                               eh_trie** out);
+
 eh_status eh_trie_info_get(const eh_trie* trie, eh_trie_info* out);
+/* Inspection: the host copy of a built trie, in the layout of
+ * eh_host_trie_arrays (rank[n], row[n+1], col[m_plus], bs_off[n],
+ * bs_base[n], bs_nw[n], bs_words[bitset_words]; any pointer may be NULL). */
+eh_status eh_trie_host_arrays(const eh_trie* trie, uint32_t* rank, uint32_t* row, uint32_t* col,
+                              uint32_t* bs_off, uint32_t* bs_base, uint32_t* bs_nw,
+                              uint32_t* bs_words);
+/* Inspection: the device arrays the counting kernels read, copied to host
+ * memory after the context's stream drains (any pointer may be NULL):
+ * vdesc[2n] = {first member, out-degree | 2^31 if the set has a bitset} per
+ * rank; col[m_plus + bitset_words] = every set's members, then every
+ * bitset's words; bsdesc[4n] = {position of the first word in col, first id
+ * covered, words, 0} per rank, only when n_bitset_sets > 0; vert[n] = the
+ * original id of each rank. */
+eh_status eh_trie_device_arrays(eh_ctx* ctx, const eh_trie* trie, uint32_t* vdesc, uint32_t* col,
+                                uint32_t* bsdesc, uint32_t* vert);
 /* Frees the trie's device memory.  Destroy every server using it first. */
 eh_status eh_trie_free(eh_trie* trie);
 

@@ -9,6 +9,10 @@ Orderings: the node-ordering study of appendix A on Chung-Lu power-law
 graphs of several exponents: triangle counting under each ordering, with
 the trie statistics that explain the differences.
 
+Build: the trie built on the host from host arrays (then uploaded) beside
+the same trie built on the GPU from pairs already in device memory, and the
+first count on each (which adds work-item planning) against a repeat.
+
 Served: a resident graph answers rooted count requests that arrive as an
 open-loop Poisson stream; latency is completion time (taken on the device
 step's completion) minus the request's scheduled arrival, so a backlog shows
@@ -407,6 +411,63 @@ def bench_orderings(name, w, args, ctx, eh, torch, metric):
                                       " on the R-MAT s20 tuning, per cell"},
         "table": table,
         "parity_vs_oracle": parity,
+    }
+
+
+def bench_build(name, w, args, ctx, eh, torch, metric):
+    from paper_1503_02368_amd import inputs
+    rows = []
+    for scale in w["scales"]:
+        el = inputs.rmat(scale, w["edge_factor"], seed=scale)
+        src = torch.from_numpy(np.ascontiguousarray(el.src).view(np.int32)).cuda()
+        dst = torch.from_numpy(np.ascontiguousarray(el.dst).view(np.int32)).cuda()
+        torch.cuda.synchronize()
+        ctx.set_tuning(**dict(ctx.get_tuning(), **load_tuning("rmat20_triangles").get("tuning", {})))
+        row = {"scale": scale, "raw_pairs": int(el.m_raw)}
+        for how in ("host", "device"):
+            times = []
+            for rep in range(args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if how == "host":
+                    trie = ctx.build_edgelist(el, layout=w["layout"], tau=w["tau"])
+                else:
+                    trie = ctx.build_trie_device(el.n, src, dst, layout=w["layout"], tau=w["tau"])
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                if rep < args.steps - 1:
+                    trie.free()
+            t_build = statistics.median(times)
+            t0 = time.perf_counter()
+            first = ctx.count_triangles(trie)
+            t_first = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            again = ctx.count_triangles(trie)
+            t_again = time.perf_counter() - t0
+            row[how] = {"build_ms": 1e3 * t_build, "build_ms_all": [1e3 * t for t in times],
+                        "first_count_ms": 1e3 * t_first, "repeat_count_ms": 1e3 * t_again,
+                        "count": first, "m_plus": trie.info["m_plus"]}
+            if first != again:
+                raise RuntimeError("counts differ between calls")
+            log(f"[bench] rmat{scale} {how} build {1e3 * t_build:.1f} ms (median of {len(times)}), "
+                f"first count {1e3 * t_first:.1f} ms, repeat {1e3 * t_again:.2f} ms")
+            trie.free()
+        row["speedup"] = row["host"]["build_ms"] / row["device"]["build_ms"]
+        row["same_count"] = row["host"]["count"] == row["device"]["count"]
+        rows.append(row)
+        del src, dst
+    top = rows[-1]
+    return {
+        "metric": metric, "value": top["raw_pairs"] / (top["device"]["build_ms"] / 1e3),
+        "unit": "raw pairs/s (GPU trie build)", "n_gpus": 1, "steps": args.steps, "warmup": 0,
+        "ms_per_step": top["device"]["build_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded generator)",
+        "config": {"workload": name, "scales": w["scales"], "edge_factor": w["edge_factor"],
+                   "layout": "hybrid", "tau": w["tau"],
+                   "host_build": "eh_build_trie from host arrays (host build plus upload)",
+                   "device_build": "eh_build_trie_device from pairs resident in HBM"},
+        "table": rows,
+        "same_counts": all(r["same_count"] for r in rows),
     }
 
 

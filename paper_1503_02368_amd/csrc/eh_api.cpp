@@ -421,6 +421,82 @@ eh_status eh_build_trie(eh_ctx* ctx, const uint32_t* src, const uint32_t* dst, u
   return finish_build(ctx, x, out);
 }
 
+eh_status eh_build_trie_device(eh_ctx* ctx, const uint32_t* d_src, const uint32_t* d_dst,
+                               uint64_t n_edges, uint32_t n_vertices, const eh_build_opts* opts,
+                               eh_trie** out) {
+  if (!ctx || !out || (n_edges && (!d_src || !d_dst))) return EH_EINVAL;
+  *out = nullptr;
+  if (opts && (opts->layout > EH_LAYOUT_BITSET_ALL || opts->order > EH_ORDER_STRONG_RUNS)) {
+    ctx->c.err = "unknown layout or node ordering";
+    return EH_EINVAL;
+  }
+  const BuildOpts o = resolve_opts(opts);
+  if (o.order != EH_ORDER_DEGREE && o.order != EH_ORDER_REV_DEGREE && o.order != EH_ORDER_INPUT) {
+    ctx->c.err = "traversal orderings (BFS, hybrid, strong runs) are built on the host";
+    return EH_EINVAL;
+  }
+  eh_trie* x = new (std::nothrow) eh_trie();
+  if (!x) return EH_ENOMEM;
+  x->t.ctx = &ctx->c;
+  eh_status st = hip_check(&ctx->c, hipSetDevice(ctx->c.device), "hipSetDevice");
+  if (st == EH_OK) {
+    try {
+      st = device_build(&ctx->c, d_src, d_dst, n_edges, n_vertices, o, x->t);
+    } catch (const std::bad_alloc&) {
+      ctx->c.err = "host memory exhausted while building the trie";
+      st = EH_ENOMEM;
+    }
+  }
+  if (st != EH_OK) {
+    (void)hipStreamSynchronize(ctx->c.stream);
+    free_trie_device(x->t);
+    delete x;
+    return st;
+  }
+  *out = x;
+  return EH_OK;
+}
+
+eh_status eh_trie_host_arrays(const eh_trie* trie, uint32_t* rank, uint32_t* row, uint32_t* col,
+                              uint32_t* bs_off, uint32_t* bs_base, uint32_t* bs_nw,
+                              uint32_t* bs_words) {
+  if (!trie) return EH_EINVAL;
+  const HostTrie& h = trie->t.host;
+  auto put = [](uint32_t* d, const std::vector<uint32_t>& v) {
+    if (d && !v.empty()) std::memcpy(d, v.data(), v.size() * sizeof(uint32_t));
+  };
+  put(rank, h.rank);
+  put(row, h.row);
+  put(col, h.col);
+  put(bs_off, h.bs_off);
+  put(bs_base, h.bs_base);
+  put(bs_nw, h.bs_nw);
+  put(bs_words, h.bs_words);
+  return EH_OK;
+}
+
+eh_status eh_trie_device_arrays(eh_ctx* ctx, const eh_trie* trie, uint32_t* vdesc, uint32_t* col,
+                                uint32_t* bsdesc, uint32_t* vert) {
+  if (!ctx || !trie) return EH_EINVAL;
+  Ctx* c = &ctx->c;
+  const Trie& t = trie->t;
+  const HostTrie& h = t.host;
+  const uint64_t W = h.bs_words.size();
+  eh_status st = hip_check(c, hipSetDevice(c->device), "hipSetDevice");
+  if (st != EH_OK) return st;
+  if ((st = hip_check(c, hipStreamSynchronize(c->stream), "stream sync")) != EH_OK) return st;
+  auto get = [&](uint32_t* d, const DevBuf& b, size_t bytes, const char* what) -> eh_status {
+    if (!d || !bytes) return EH_OK;
+    return hip_check(c, hipMemcpy(d, b.p, bytes, hipMemcpyDeviceToHost), what);
+  };
+  if ((st = get(vdesc, t.vdesc, 8ull * h.n, "download vertex table")) != EH_OK ||
+      (st = get(col, t.col, 4ull * (h.m + W), "download sets")) != EH_OK ||
+      (st = get(bsdesc, t.bsdesc, h.n_bs ? 16ull * h.n : 0, "download bitset table")) != EH_OK ||
+      (st = get(vert, t.vert, 4ull * h.n, "download ids")) != EH_OK)
+    return st;
+  return EH_OK;
+}
+
 eh_status eh_build_batch(eh_ctx* ctx, uint32_t n_graphs, const uint32_t* n_vertices,
                          const uint64_t* edge_off, const uint32_t* src, const uint32_t* dst,
                          const eh_build_opts* opts, eh_trie** out) {

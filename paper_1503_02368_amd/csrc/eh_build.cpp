@@ -434,6 +434,54 @@ namespace {
 
 inline uint32_t out_deg(const HostTrie& h, uint32_t v) { return h.row[v + 1] - h.row[v]; }
 
+// Host threads for planning: up to 16, one below 2^16 elements of work.
+unsigned plan_threads(uint64_t work) {
+  if (work < (1u << 16)) return 1;
+  return std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+}
+
+// Runs f(begin, end, part) over the ranges [b[p], b[p+1]) on one thread each.
+// Ranges follow part order, so per-part outputs concatenated in part order
+// equal a sequential pass.
+template <class F>
+void run_parts(const std::vector<uint64_t>& b, F f) {
+  const unsigned parts = unsigned(b.size() - 1);
+  if (parts == 1) {
+    f(b[0], b[1], 0u);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (unsigned p = 0; p < parts; ++p) th.emplace_back([&, p]() { f(b[p], b[p + 1], p); });
+  for (auto& t : th) t.join();
+}
+
+// Equal ranges of [0, n).
+std::vector<uint64_t> even_parts(uint64_t n, unsigned parts) {
+  std::vector<uint64_t> b(parts + 1);
+  for (unsigned p = 0; p <= parts; ++p) b[p] = n * p / parts;
+  return b;
+}
+
+// Ranges of [0, n) holding about equal shares of the work prefix[x+1] - prefix[x].
+std::vector<uint64_t> weighted_parts(const std::vector<uint32_t>& prefix, uint64_t n,
+                                     unsigned parts) {
+  std::vector<uint64_t> b(parts + 1, 0);
+  const uint64_t total = prefix[n];
+  for (unsigned p = 1; p < parts; ++p) {
+    const uint64_t want = total * p / parts;
+    b[p] = uint64_t(std::lower_bound(prefix.begin(), prefix.begin() + n, uint32_t(want)) -
+                    prefix.begin());
+    b[p] = std::max(b[p], b[p - 1]);
+  }
+  b[parts] = n;
+  return b;
+}
+
+template <class F>
+void parallel_ranges(uint64_t n, F f) {
+  run_parts(even_parts(n, plan_threads(n)), f);
+}
+
 // elements the kernel streams for set v: its words when the bitset is shorter
 inline uint32_t stream_len(const HostTrie& h, uint32_t v, bool use_bitsets) {
   const uint32_t d = out_deg(h, v);
@@ -544,41 +592,76 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
   const bool ub = tu.use_bitsets != 0;
   if (staging == EH_STAGE_TARGET) {
     if (!t->has_transpose) {
-      // in-edges of each v, ascending in u: {u, position of v in N+(u)}
+      // in-edges of each v, ascending in u: {u, position of v in N+(u)}.
+      // Each thread owns a range of targets and scans every edge in source
+      // order, so it writes its targets' in-edges in the sequential order
+      // with no shared counters; target ranges hold about equal in-edges.
+      const unsigned parts = plan_threads(h.m);
       t->trow.assign(size_t(h.n) + 1, 0);
-      for (uint64_t e = 0; e < h.m; ++e) t->trow[h.col[e] + 1]++;
+      run_parts(even_parts(h.n, parts), [&](uint64_t v0, uint64_t v1, unsigned) {
+        for (uint64_t e = 0; e < h.m; ++e) {
+          const uint32_t v = h.col[e];
+          if (v >= v0 && v < v1) t->trow[v + 1]++;
+        }
+      });
       for (uint32_t v = 0; v < h.n; ++v) t->trow[v + 1] += t->trow[v];
       t->tin.assign(2 * h.m, 0);
       std::vector<uint32_t> fill(t->trow.begin(), t->trow.end() - 1);
-      for (uint32_t u = 0; u < h.n; ++u)
-        for (uint32_t e = h.row[u]; e < h.row[u + 1]; ++e) {
-          const uint32_t k = fill[h.col[e]]++;
-          t->tin[2 * k] = u;
-          t->tin[2 * k + 1] = e;
-        }
+      run_parts(weighted_parts(t->trow, h.n, parts), [&](uint64_t v0, uint64_t v1, unsigned) {
+        for (uint32_t u = 0; u < h.n; ++u)
+          for (uint32_t e = h.row[u]; e < h.row[u + 1]; ++e) {
+            const uint32_t v = h.col[e];
+            if (v < v0 || v >= v1) continue;
+            const uint32_t k = fill[v]++;
+            t->tin[2 * k] = u;
+            t->tin[2 * k + 1] = e;
+          }
+      });
       t->has_transpose = true;
     }
   }
-  for (uint32_t g = 0; g < h.n_graphs; ++g) {
-    plan->g_item_off[g] = items.size();
-    const uint32_t v0 = h.g_vbase[g], v1 = h.g_vbase[g + 1];
-    const uint32_t tag = h.n_graphs > 1 ? g : 0;
-    if (staging == EH_STAGE_TARGET) {
-      for (uint32_t v = v0; v < v1; ++v) {
-        const uint32_t dv = out_deg(h, v);
-        const uint32_t lb = t->trow[v], len = t->trow[v + 1] - t->trow[v];
-        if (dv == 0 || len == 0) continue;
-        split_items(v, lb, len, tag, chunk, dv,
-                    [&](uint32_t k) {
-                      return uint64_t(suffix_len(h, t->tin[2 * k], t->tin[2 * k + 1], ub)) + 2;
-                    },
-                    items);
+  {
+    // items of each vertex in vertex order: threads take vertex ranges and
+    // their lists are joined in range order; graph g's items start at the
+    // first item whose vertex is at or above g's first rank
+    std::vector<std::vector<Item>> part(16);
+    const std::vector<uint32_t>& work = staging == EH_STAGE_TARGET ? t->trow : h.row;
+    run_parts(weighted_parts(work, h.n, plan_threads(h.m)), [&](uint64_t x0, uint64_t x1,
+                                                                 unsigned p) {
+      std::vector<Item>& out = part[p];
+      uint32_t g = uint32_t(std::upper_bound(h.g_vbase.begin(), h.g_vbase.end(), uint32_t(x0)) -
+                            h.g_vbase.begin()) - 1;
+      for (uint64_t x = x0; x < x1; ++x) {
+        while (x >= h.g_vbase[g + 1]) ++g;
+        const uint32_t tag = h.n_graphs > 1 ? g : 0;
+        const uint32_t v = uint32_t(x);
+        if (staging == EH_STAGE_TARGET) {
+          const uint32_t dv = out_deg(h, v);
+          const uint32_t lb = t->trow[v], len = t->trow[v + 1] - t->trow[v];
+          if (dv == 0 || len == 0) continue;
+          split_items(v, lb, len, tag, chunk, dv,
+                      [&](uint32_t k) {
+                        return uint64_t(suffix_len(h, t->tin[2 * k], t->tin[2 * k + 1], ub)) + 2;
+                      },
+                      out);
+        } else {
+          make_items_source(h, v, tag, chunk, pattern, ub, out);
+        }
       }
-    } else {
-      for (uint32_t u = v0; u < v1; ++u) make_items_source(h, u, tag, chunk, pattern, ub, items);
+    });
+    size_t total = 0;
+    for (auto& q : part) total += q.size();
+    items.reserve(total);
+    for (auto& q : part) {
+      items.insert(items.end(), q.begin(), q.end());
+      std::vector<Item>().swap(q);
     }
+    for (uint32_t g = 0; g <= h.n_graphs; ++g)
+      plan->g_item_off[g] = uint64_t(
+          std::lower_bound(items.begin(), items.end(), h.g_vbase[g],
+                           [](const Item& it, uint32_t v) { return it.s < v; }) -
+          items.begin());
   }
-  plan->g_item_off[h.n_graphs] = items.size();
   for (const Item& it : items) plan->item_dmax = std::max(plan->item_dmax, out_deg(h, it.s));
   eh_status st = EH_OK;
   if (staging == EH_STAGE_TARGET && pattern == EH_TRIANGLE) {
@@ -672,32 +755,52 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
     }
     if (sd.empty()) sd.assign(4, 0);
     std::vector<uint32_t> rec(2 * std::max<uint64_t>(h.m, 1), 0);
-    for (uint64_t k = 0; k < h.m; ++k) {
-      const uint32_t u = t->tin[2 * k], e = t->tin[2 * k + 1], v = h.col[e];
-      const uint32_t len = h.row[u + 1] - e - 1;
-      uint32_t sb = e + 1, n = len, sm = 0;
-      if (ub && len && !grouped[v] && h.bs_off[u] != kNoBitset && h.row[v + 1] > h.row[v] &&
-          bitmap_mode(v)) {
-        const uint32_t w0 = (v + 1 - h.bs_base[u]) >> 5;
-        const int64_t nw = w0 < h.bs_nw[u] ? int64_t(h.bs_nw[u] - w0) : 0;
-        // the first streamed word's index in the staged bitmap, then the
-        // part of the words that overlaps the bitmap [0, cap)
-        const int64_t off = int64_t((h.bs_base[u] >> 5) + w0) - int64_t(staged_lo_al(v) >> 5);
-        const int64_t first = std::max<int64_t>(0, -off);
-        const int64_t last = std::min<int64_t>(nw, int64_t(cap) - off);
-        const int64_t words = last > first ? last - first : 0;
-        if (words < int64_t(len)) {
-          sb = (uint32_t(h.m) + h.bs_off[u] + w0 + uint32_t(first)) | kHiBit;
-          n = uint32_t(words);
-          sm = words ? uint32_t(off + first) : 0u;
+    bool wide = false;
+    // per source set, the fields a record reads, packed in one 16-byte entry
+    std::vector<uint4> src_info(h.n);
+    parallel_ranges(h.n, [&](uint64_t u0, uint64_t u1, unsigned) {
+      for (uint64_t u = u0; u < u1; ++u)
+        src_info[u] = make_uint4(h.row[u + 1], h.bs_off[u], h.bs_base[u], h.bs_nw[u]);
+    });
+    // in-edges grouped by target v: v's own values are read once
+    run_parts(weighted_parts(t->trow, h.n, plan_threads(h.m)), [&](uint64_t v0, uint64_t v1,
+                                                                     unsigned) {
+      for (uint64_t vv = v0; vv < v1; ++vv) {
+        const uint32_t v = uint32_t(vv);
+        const bool words_ok = ub && !grouped[v] && h.row[v + 1] > h.row[v] && bitmap_mode(v);
+        const int64_t v_word = words_ok ? int64_t(staged_lo_al(v) >> 5) : 0;
+        for (uint32_t k = t->trow[v]; k < t->trow[v + 1]; ++k) {
+          const uint32_t u = t->tin[2 * k], e = t->tin[2 * k + 1];
+          const uint4 su = src_info[u];  // {row end, word offset, base, words}
+          const uint32_t len = su.x - e - 1;
+          uint32_t sb = e + 1, n = len, sm = 0;
+          if (words_ok && len && su.y != kNoBitset) {
+            const uint32_t w0 = (v + 1 - su.z) >> 5;
+            const int64_t nw = w0 < su.w ? int64_t(su.w - w0) : 0;
+            // the first streamed word's index in the staged bitmap, then the
+            // part of the words that overlaps the bitmap [0, cap)
+            const int64_t off = int64_t((su.z >> 5) + w0) - v_word;
+            const int64_t first = std::max<int64_t>(0, -off);
+            const int64_t last = std::min<int64_t>(nw, int64_t(cap) - off);
+            const int64_t words = last > first ? last - first : 0;
+            if (words < int64_t(len)) {
+              sb = (uint32_t(h.m) + su.y + w0 + uint32_t(first)) | kHiBit;
+              n = uint32_t(words);
+              sm = words ? uint32_t(off + first) : 0u;
+            }
+          }
+          if (n > 0xFFFFu || sm > 0xFFFFu) {
+            __atomic_store_n(&wide, true, __ATOMIC_RELAXED);
+            continue;
+          }
+          rec[2 * k] = sb;
+          rec[2 * k + 1] = n | (sm << 16);
         }
       }
-      if (n > 0xFFFFu || sm > 0xFFFFu) {
-        c->err = "segment record field beyond 16 bits";
-        return EH_EOVERFLOW;
-      }
-      rec[2 * k] = sb;
-      rec[2 * k + 1] = n | (sm << 16);
+    });
+    if (wide) {
+      c->err = "segment record field beyond 16 bits";
+      return EH_EOVERFLOW;
     }
     if (gsub.empty()) gsub.assign(4, 0);
     if ((st = dev_alloc(c, plan->sdesc, sizeof(uint32_t) * sd.size())) != EH_OK ||

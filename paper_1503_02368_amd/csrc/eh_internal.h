@@ -74,6 +74,13 @@ eh_status host_build_batch(uint32_t n_graphs, const uint32_t* n_vertices, const 
                            const uint32_t* src, const uint32_t* dst, const BuildOpts& opts,
                            HostTrie& h, std::string& err);
 
+struct Trie;
+// The same trie built on the GPU from device-resident raw pairs (orderings
+// that are sorts: degree, reverse degree, input), with its host copy.
+struct Ctx;
+eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_raw,
+                       uint32_t n, const BuildOpts& opts, Trie& t);
+
 struct Tuning {
   uint32_t kernel = EH_KERNEL_STAGED;
   uint32_t staging = EH_STAGE_TARGET;

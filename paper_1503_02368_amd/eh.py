@@ -39,6 +39,7 @@ SYMBOLS = [
     "eh_count_async", "eh_count_add_async", "eh_count_rooted", "eh_count_batch", "eh_count_batch_async",
     "eh_server_create", "eh_submit", "eh_poll", "eh_wait", "eh_server_drain", "eh_server_destroy",
     "eh_host_trie_build", "eh_host_trie_info", "eh_host_trie_arrays", "eh_host_trie_free",
+    "eh_build_trie_device", "eh_trie_host_arrays", "eh_trie_device_arrays",
 ]
 
 
@@ -139,6 +140,10 @@ def load():
             "eh_host_trie_info": [_vp, ctypes.POINTER(_TrieInfo)],
             "eh_host_trie_arrays": [_vp, _u32p, _u32p, _u32p, _u32p, _u32p, _u32p, _u32p],
             "eh_host_trie_free": [_vp],
+            "eh_build_trie_device": [_vp, _vp, _vp, ctypes.c_uint64, ctypes.c_uint32,
+                                     ctypes.POINTER(_BuildOpts), ctypes.POINTER(_vp)],
+            "eh_trie_host_arrays": [_vp, _u32p, _u32p, _u32p, _u32p, _u32p, _u32p, _u32p],
+            "eh_trie_device_arrays": [_vp, _vp, _u32p, _u32p, _u32p, _u32p],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -292,6 +297,39 @@ class Context:
                                             ctypes.byref(o), ctypes.byref(h)), "build_trie")
         return Trie(self, h)
 
+    def build_trie_device(self, n, d_src, d_dst, layout=LAYOUT_HYBRID, tau=32.0, s_min=1,
+                          order=ORDER_DEGREE) -> "Trie":
+        """The same trie, built on the GPU from device tensors of raw pairs (4-byte
+        elements, e.g. torch.int32 holding ids below 2^31)."""
+        if d_src.numel() != d_dst.numel():
+            raise ValueError("src and dst differ in length")
+        for t in (d_src, d_dst):
+            if not t.is_cuda or t.element_size() != 4 or not t.is_contiguous():
+                raise ValueError("pairs must be contiguous 4-byte device tensors")
+        import torch
+        # the pairs were written on torch's current stream; the build reads them on ours
+        self.stream.wait_stream(torch.cuda.current_stream())
+        h = _vp()
+        o = _opts(layout, tau, s_min, order)
+        self._check(self._lib.eh_build_trie_device(self._h, _vp(d_src.data_ptr()),
+                                                   _vp(d_dst.data_ptr()), d_src.numel(), int(n),
+                                                   ctypes.byref(o), ctypes.byref(h)),
+                    "build_trie_device")
+        return Trie(self, h)
+
+    def device_arrays(self, trie) -> dict:
+        """The device arrays the counting kernels read, copied to host memory."""
+        i = trie.info
+        n, m, w = i["n"], i["m_plus"], i["bitset_words"]
+        arr = {"vdesc": np.zeros(2 * n, np.uint32), "col": np.zeros(m + w, np.uint32),
+               "bsdesc": np.zeros(4 * n if i["n_bitset_sets"] else 0, np.uint32),
+               "vert": np.zeros(n, np.uint32)}
+        self._check(self._lib.eh_trie_device_arrays(self._h, trie._h, *(_p32(arr[k]) for k in
+                                                                       ("vdesc", "col", "bsdesc",
+                                                                        "vert"))),
+                    "trie_device_arrays")
+        return arr
+
     def build_edgelist(self, el, **kw) -> "Trie":
         return self.build_trie(el.n, el.src, el.dst, **kw)
 
@@ -376,6 +414,18 @@ class Trie:
         self.ctx._check(self.ctx._lib.eh_trie_info_get(self._h, ctypes.byref(info)), "trie_info")
         self.info = _info_dict(info)
         return self.info
+
+    def host_arrays(self) -> dict:
+        """The trie's host copy, in the layout of host_trie()."""
+        i = self.info
+        n, m, w = i["n"], i["m_plus"], i["bitset_words"]
+        arr = {k: np.zeros(sz, np.uint32) for k, sz in
+               (("rank", n), ("row", n + 1), ("col", m), ("bs_off", n), ("bs_base", n),
+                ("bs_nw", n), ("bs_words", w))}
+        self.ctx._check(self.ctx._lib.eh_trie_host_arrays(
+            self._h, *(_p32(arr[k]) for k in ("rank", "row", "col", "bs_off", "bs_base", "bs_nw",
+                                              "bs_words"))), "trie_host_arrays")
+        return arr
 
     def free(self):
         if self._h:

@@ -14,6 +14,8 @@ WORKLOADS = {
     "orderings": dict(kind="orderings", n=1 << 20, avg_degree=16.0, gammas=[1.75, 2.0, 2.5, 3.0],
                       orders=["random", "degree", "rev_degree", "bfs", "hybrid", "strong_runs"],
                       seed=30, layout=1, tau=32.0),
+    # trie construction, host against GPU, on R-MAT graphs
+    "build": dict(kind="build", scales=[20, 22], edge_factor=16, layout=1, tau=32.0),
     "served": dict(kind="served", gen="rmat", scale=22, edge_factor=16, seed=22, layout=1, tau=32.0),
 }
 

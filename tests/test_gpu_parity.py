@@ -624,6 +624,115 @@ def test_batch_node_orderings(ctx, eh, order):
         trie.free()
 
 
+def _device_pairs(el):
+    import torch
+    return (torch.from_numpy(np.ascontiguousarray(el.src).view(np.int32)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(el.dst).view(np.int32)).cuda())
+
+
+def _same_trie(ctx, a, b, where):
+    assert a.info == b.info, where
+    ha, hb = a.host_arrays(), b.host_arrays()
+    for k in ha:
+        np.testing.assert_array_equal(ha[k], hb[k], err_msg=f"{where}: host {k}")
+    da, db = ctx.device_arrays(a), ctx.device_arrays(b)
+    for k in da:
+        np.testing.assert_array_equal(da[k], db[k], err_msg=f"{where}: device {k}")
+
+
+DEVICE_BUILD_GRAPHS = [inputs.rmat(12, 16, seed=51), inputs.messy(inputs.rmat(10, 8, seed=52), 5),
+                       inputs.chung_lu(30000, 12, 2.1, seed=53), inputs.erdos_renyi_gnm(5000, 9000, seed=54),
+                       inputs.complete(70), inputs.grid(20, 30), inputs.wheel(100),
+                       inputs.disjoint_union(inputs.complete(33), inputs.star(40), inputs.path(1)),
+                       inputs.EdgeList(9, np.arange(9, dtype=np.uint32), np.arange(9, dtype=np.uint32),
+                                       "loops_only"),
+                       inputs.EdgeList(2, np.array([0, 1, 1, 0], np.uint32), np.array([1, 0, 1, 1], np.uint32),
+                                       "one_edge_repeated")]
+
+
+@pytest.mark.parametrize("order", ["degree", "rev_degree", "input"])
+@pytest.mark.parametrize("lay", LAYOUTS, ids=lambda x: x[0])
+def test_device_build_matches_host_build(ctx, eh, order, lay):
+    """The GPU trie build gives the host build's trie, array for array (index
+    work: bit-exact), host copy and device arrays alike; ranks and the
+    oriented CSR equal the oracle's; counts equal the oracle's."""
+    tune(ctx, **TUNINGS["staged_lean"])
+    for el in DEVICE_BUILD_GRAPHS:
+        say("device build", order, lay[0], el.name)
+        src, dst = _device_pairs(el)
+        ht = ctx.build_edgelist(el, layout=lay[1], tau=lay[2], order=eh.ORDERS[order])
+        dt = ctx.build_trie_device(el.n, src, dst, layout=lay[1], tau=lay[2], order=eh.ORDERS[order])
+        try:
+            _same_trie(ctx, dt, ht, f"{el.name} {order} {lay[0]}")
+            t, k, dmax = order_truth(el, order)
+            g = oracle.Graph.from_edgelist(el, order)
+            off, nbr = g.oriented()
+            h = dt.host_arrays()
+            np.testing.assert_array_equal(h["rank"], g.rank())
+            np.testing.assert_array_equal(h["row"], off.astype(np.uint32))
+            np.testing.assert_array_equal(h["col"], nbr)
+            assert ctx.count_triangles(dt) == t["count"]
+            if k is not None and lay[0] == "hybrid32":
+                assert ctx.count_4cliques(dt) == k["count"]
+        finally:
+            dt.free()
+            ht.free()
+
+
+def test_device_build_rejects(ctx, eh):
+    import torch
+    src = torch.tensor([0, 1, 2], dtype=torch.int32, device="cuda")
+    dst = torch.tensor([1, 2, 3], dtype=torch.int32, device="cuda")
+    with pytest.raises(eh.EHError) as e:
+        ctx.build_trie_device(3, src, dst)            # id 3 >= n
+    assert e.value.status == eh.EH_EINVAL
+    for order in ("bfs", "hybrid", "strong_runs"):
+        with pytest.raises(eh.EHError) as e:
+            ctx.build_trie_device(4, src, dst, order=eh.ORDERS[order])
+        assert e.value.status == eh.EH_EINVAL
+    with pytest.raises(eh.EHError) as e:
+        ctx.build_trie_device(0, src, dst)
+    assert e.value.status == eh.EH_EINVAL
+    empty = torch.zeros(0, dtype=torch.int32, device="cuda")
+    for n in (0, 1, 6):
+        t = ctx.build_trie_device(n, empty, empty)
+        try:
+            assert t.info["n"] == n and t.info["m_plus"] == 0
+            assert ctx.count_triangles(t) == 0 and ctx.count_4cliques(t) == 0
+        finally:
+            t.free()
+    # the context stays usable after a rejected build
+    t = ctx.build_trie_device(4, src, dst)
+    try:
+        assert t.info["m_plus"] == 3 and ctx.count_triangles(t) == 0
+    finally:
+        t.free()
+
+
+def test_device_build_full_size_rmat20(ctx, eh):
+    """R-MAT scale 20 built on the GPU: the host build's trie, array for array,
+    and the oracle's ranks, rows and columns."""
+    el = inputs.rmat(20, 16, seed=20)
+    src, dst = _device_pairs(el)
+    say("rmat20 pairs on device")
+    dt = ctx.build_trie_device(el.n, src, dst)
+    ht = ctx.build_edgelist(el)
+    try:
+        _same_trie(ctx, dt, ht, "rmat20")
+        say("device build equals host build")
+        g = oracle.Graph.from_edgelist(el)
+        off, nbr = g.oriented()
+        h = dt.host_arrays()
+        np.testing.assert_array_equal(h["rank"], g.rank())
+        np.testing.assert_array_equal(h["row"], off.astype(np.uint32))
+        np.testing.assert_array_equal(h["col"], nbr)
+        tune(ctx, **TUNINGS["staged_lean"])
+        assert ctx.count_triangles(dt) == g.triangles()["count"]
+    finally:
+        dt.free()
+        ht.free()
+
+
 def test_out_degree_limits(ctx, eh):
     """K_2050: triangles at out-degree 2049 (C(n, 3)); the 4-clique kernel's
     S list holds at most 2048 entries, so its count is refused with
