@@ -12,6 +12,12 @@ what the same counters report for a plain copy of known size, and writes
     python -m paper_1503_02368_amd.profile_summary --workload rmat20_triangles \\
         --kernel k_tri_staged --trace D --fetch D --write D --copy-fetch D \\
         --copy-write D [--counters D ...] --copy-mib 1024 --commands FILE --out profiles/X.md
+
+With --stats-only it writes the kernel statistics table alone (no counters,
+no traffic entry), for multi-kernel pipelines such as the GPU trie build:
+
+    python -m paper_1503_02368_amd.profile_summary --stats-only --workload build \\
+        --trace D --commands FILE --out profiles/X.md [--note TEXT]
 """
 from __future__ import annotations
 
@@ -52,15 +58,43 @@ def kernel_stats(d: str):
     return _csv(d, "kernel_stats.csv")
 
 
+def stats_only(args):
+    stats = kernel_stats(args.trace)
+    with open(args.commands) as f:
+        cmds = f.read().strip()
+    total = sum(float(r["TotalDurationNs"]) for r in stats)
+    lines = [f"# Kernels of the {args.workload} workload", "",
+             "Commands (from the repository root, one MI355X):", "", "```", cmds, "```", ""]
+    if args.note:
+        lines += [args.note, ""]
+    lines += ["## Kernel statistics (rocprofv3 --kernel-trace --stats)", "",
+              "| kernel | calls | average (us) | total (ms) | share of GPU time |",
+              "|---|---|---|---|---|"]
+    for r in stats:
+        name = r["Name"]
+        if "rocprim" in name:
+            name = "rocPRIM " + ("radix sort" if "radix" in name else "scan" if "scan" in name
+                                 else "select/unique" if ("select" in name or "unique" in name)
+                                 else "kernel") + " (" + name[name.find("<") + 1:][:40] + "...)"
+        lines.append(f"| {name[:100]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} % |")
+    lines += ["", f"Total GPU kernel time: {total / 1e6:.2f} ms.", ""]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines))
+    print(f"wrote {args.out}")
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--stats-only", action="store_true")
+    ap.add_argument("--note", default="")
     ap.add_argument("--workload", required=True)
-    ap.add_argument("--kernel", required=True, help="substring of the kernel's symbol name")
+    ap.add_argument("--kernel", help="substring of the kernel's symbol name")
     ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
-    ap.add_argument("--copy-fetch", required=True)
-    ap.add_argument("--copy-write", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-fetch")
+    ap.add_argument("--copy-write")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--counters", action="append", default=[])
     ap.add_argument("--commands", required=True, help="text file with the commands that made the data")
@@ -68,6 +102,11 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"))
     args = ap.parse_args()
+    if args.stats_only:
+        return stats_only(args)
+    for need in ("kernel", "fetch", "write", "copy_fetch", "copy_write"):
+        if getattr(args, need) is None:
+            ap.error(f"--{need.replace('_', '-')} is required without --stats-only")
 
     stats = kernel_stats(args.trace)
     mine = [r for r in stats if args.kernel in r["Name"]]
