@@ -18,6 +18,8 @@ Prints one JSON line.  Workloads (--workload):
                     degree exponents 1.75 .. 3): triangle counting per ordering
   build             trie construction on the host and on the GPU, R-MAT scales
                     20 and 22, with the first (planning) and a repeated count
+  unpruned          R-MAT scale 20 with both directions of every edge: ordered
+                    triangles and the Lollipop query, beside pruned triangles
   served            resident R-MAT scale 22, Poisson stream of rooted
                     triangle / 4-clique requests: p50/p99 latency
 """
@@ -191,6 +193,9 @@ def main():
     elif w["kind"] == "batch":
         from paper_1503_02368_amd import bench_extra
         res = bench_extra.bench_batch(name, w, args, ctx, eh, torch, METRIC)
+    elif w["kind"] == "unpruned":
+        from paper_1503_02368_amd import bench_extra
+        res = bench_extra.bench_unpruned(name, w, args, ctx, eh, torch, METRIC)
     elif w["kind"] == "build":
         from paper_1503_02368_amd import bench_extra
         res = bench_extra.bench_build(name, w, args, ctx, eh, torch, METRIC)

@@ -86,7 +86,7 @@ const char* eh_last_error(const eh_ctx* ctx);
 const char* eh_status_str(eh_status s);
 /* Version of this ABI (major * 10000 + minor * 100 + patch); a caller built
  * against this header checks that the library returns EH_ABI_VERSION. */
-#define EH_ABI_VERSION 10400
+#define EH_ABI_VERSION 10500
 int32_t eh_abi_version(void);
 
 /* ---- tuning knobs (performance only; counts never depend on them) ------- */
@@ -181,6 +181,13 @@ typedef struct eh_build_opts {
   float tau;
   uint32_t s_min;
   uint32_t order;   /* EH_ORDER_*; a value above 5 is EH_EINVAL */
+  uint32_t symmetric; /* 0: prune (each edge once, low rank -> high rank, section 5.2);
+                         1: keep the full undirected adjacency, both directions (the
+                         unpruned relation of appendix A, "pruning symmetric queries",
+                         on which the paper runs its Lollipop query, section 5.3).  On a
+                         symmetric trie the counting calls return the join's output on
+                         the unpruned relation: ordered triangles (6 T), ordered 4-cliques
+                         (24 K), rooted counts by the first attribute x. */
 } eh_build_opts;
 
 typedef struct eh_trie_info {
@@ -250,6 +257,14 @@ eh_status eh_count_triangles(eh_ctx* ctx, const eh_trie* trie, uint64_t* total,
                              uint64_t* d_per_root);
 /* 4-clique total of a single-graph trie (section 5.3, query K4 on pruned data). */
 eh_status eh_count_4cliques(eh_ctx* ctx, const eh_trie* trie, uint64_t* total);
+/* COUNT(*) of the Lollipop query of section 5.3,
+ *   Lollipop(x,y,z,w) :- R(x,y), S(y,z), T(x,z), U(x,w),
+ * evaluated as one Generic-Join over a symmetric trie (the paper runs it on
+ * undirected data): for every x, the ordered triangles (x, y, z) times the
+ * number of w adjacent to x, i.e. sum over x of t(x) deg(x).  EH_ESTATE on a
+ * pruned trie or a batch.  Allocates n uint64 of device scratch per call.
+ * Results above 2^64 - 1 wrap. */
+eh_status eh_count_lollipop(eh_ctx* ctx, const eh_trie* trie, uint64_t* total);
 /* Enqueue-only forms: the total is written to d_total (one uint64, device)
  * when the stream reaches it.  pattern: EH_TRIANGLE or EH_4CLIQUE. */
 eh_status eh_count_async(eh_ctx* ctx, const eh_trie* trie, int pattern, uint64_t* d_total);

@@ -75,6 +75,10 @@ def _load():
             f = getattr(lib, name)
             f.restype = ctypes.c_uint64
             f.argtypes = [vp]
+        lib.orc_sym_triangles_by_first.restype = ctypes.c_uint64
+        lib.orc_sym_triangles_by_first.argtypes = [vp, ctypes.c_int, _u64p]
+        lib.orc_sym_lollipop.restype = ctypes.c_uint64
+        lib.orc_sym_lollipop.argtypes = [vp, ctypes.c_int]
         _lib = lib
         return lib
 
@@ -198,6 +202,17 @@ class Graph:
 
     def sym_ordered_4cliques(self) -> int:
         return int(self._lib.orc_sym_ordered_4cliques(self._h))
+
+    # -- the unpruned relation (appendix A, pruning symmetric queries) ----------
+    def sym_triangles_by_first(self, threads: int = 0):
+        """(6T, t) with t[x] the ordered triangles (x, y, z), by original id."""
+        t = np.zeros(self.n, np.uint64)
+        total = int(self._lib.orc_sym_triangles_by_first(self._h, int(threads), _p64(t)))
+        return total, t
+
+    def sym_lollipop(self, threads: int = 0) -> int:
+        """COUNT(*) of Lollipop(x,y,z,w) :- R(x,y),S(y,z),T(x,z),U(x,w), unpruned."""
+        return int(self._lib.orc_sym_lollipop(self._h, int(threads)))
 
 
 def rooted_count(root_by_id: np.ndarray, roots) -> int:

@@ -453,3 +453,52 @@ uint64_t orc_sym_ordered_4cliques(orc_graph* g) {
   free(s2);
   return s;
 }
+
+/*
+ * Generic-Join on the unpruned symmetric relation with the first attribute
+ * kept: t_by_id[x] = number of ordered triangles (x, y, z), i.e. the sum over
+ * y in N(x) of |N(x) & N(y)|.  Returns the total (= 6T).
+ */
+uint64_t orc_sym_triangles_by_first(orc_graph* g, int threads, uint64_t* t_by_id) {
+  if (build_symmetric(g)) return UINT64_MAX;
+  set_threads(threads);
+  uint64_t s = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : s)
+  for (uint32_t x = 0; x < g->n; ++x) {
+    const uint32_t* nx = g->snbr + g->soff[x];
+    const uint64_t dx = g->soff[x + 1] - g->soff[x];
+    uint64_t tx = 0;
+    for (uint64_t i = 0; i < dx; ++i) {
+      const uint32_t y = nx[i];
+      tx += merge_count(nx, dx, g->snbr + g->soff[y], g->soff[y + 1] - g->soff[y]);
+    }
+    if (t_by_id) t_by_id[x] = tx;
+    s += tx;
+  }
+  return s;
+}
+
+/*
+ * COUNT(*) of the Lollipop query of section 5.3,
+ *   Lollipop(x,y,z,w) :- R(x,y), S(y,z), T(x,z), U(x,w),
+ * as one Generic-Join over the unpruned symmetric relation with attribute
+ * order x, y, z, w: for x, for y in N(x), for z in N(x) & N(y), for w in N(x)
+ * (w is constrained by U alone, so its level adds |N(x)| per (x, y, z)).
+ */
+uint64_t orc_sym_lollipop(orc_graph* g, int threads) {
+  if (build_symmetric(g)) return UINT64_MAX;
+  set_threads(threads);
+  uint64_t s = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : s)
+  for (uint32_t x = 0; x < g->n; ++x) {
+    const uint32_t* nx = g->snbr + g->soff[x];
+    const uint64_t dx = g->soff[x + 1] - g->soff[x];
+    for (uint64_t i = 0; i < dx; ++i) {
+      const uint32_t y = nx[i];
+      const uint64_t z_count =
+          merge_count(nx, dx, g->snbr + g->soff[y], g->soff[y + 1] - g->soff[y]);
+      s += z_count * dx;
+    }
+  }
+  return s;
+}

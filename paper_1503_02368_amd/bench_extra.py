@@ -13,6 +13,10 @@ Build: the trie built on the host from host arrays (then uploaded) beside
 the same trie built on the GPU from pairs already in device memory, and the
 first count on each (which adds work-item planning) against a repeat.
 
+Unpruned: the triangle and Lollipop queries on the full symmetric adjacency
+of R-MAT s20 (section 5.3 runs Lollipop on undirected data), beside triangle
+counting on the pruned trie.
+
 Served: a resident graph answers rooted count requests that arrive as an
 open-loop Poisson stream; latency is completion time (taken on the device
 step's completion) minus the request's scheduled arrival, so a backlog shows
@@ -469,6 +473,92 @@ def bench_build(name, w, args, ctx, eh, torch, metric):
         "table": rows,
         "same_counts": all(r["same_count"] for r in rows),
     }
+
+
+UNPRUNED_VARIANTS = {
+    "source": dict(staging=1),
+    "source_full_words": dict(staging=1, stage_words=0),
+    "pairwise": dict(kernel=2, algo=0, group_lanes=0),
+}
+
+
+def bench_unpruned(name, w, args, ctx, eh, torch, metric):
+    from paper_1503_02368_amd import inputs
+    el = inputs.rmat(w["scale"], w["edge_factor"], seed=w["seed"])
+    base = dict(ctx.get_tuning())
+    base.update(load_tuning("rmat20_triangles").get("tuning", {}))
+    rows = {}
+    pruned = ctx.build_edgelist(el, layout=w["layout"], tau=w["tau"])
+    ctx.set_tuning(**base)
+    ms_p, t_count = _time_counts(ctx, torch, pruned, 3, args.steps, args.warmup)
+    rows["pruned_triangles"] = {"ms": ms_p, "count": t_count, "m_plus": pruned.info["m_plus"],
+                                "b_merge": pruned.info["b_merge"]}
+    log(f"[bench] pruned triangles {ms_p:.3f} ms, T = {t_count}")
+    pruned.free()
+    t0 = time.perf_counter()
+    trie = ctx.build_edgelist(el, layout=w["layout"], tau=w["tau"], symmetric=True)
+    info = trie.info
+    log(f"[bench] symmetric trie in {time.perf_counter() - t0:.2f} s: {info}")
+    best = None
+    for vname, v in UNPRUNED_VARIANTS.items():
+        t = dict(base)
+        t.update(v)
+        ctx.set_tuning(**t)
+        ms, c6 = _time_counts(ctx, torch, trie, 3, args.steps, args.warmup)
+        log(f"[bench] unpruned triangles, {vname}: {ms:.3f} ms, count {c6}")
+        if best is None or ms < best[0]:
+            best = (ms, vname, c6)
+    ctx.set_tuning(**dict(base, **UNPRUNED_VARIANTS[best[1]]))
+    lol = []
+    lcount = None
+    for _ in range(max(3, args.steps // 4)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lcount = ctx.count_lollipop(trie)
+        lol.append(time.perf_counter() - t0)
+    rows["unpruned_triangles"] = {"ms": best[0], "kernel_setting": best[1], "count": best[2],
+                                  "m_plus": info["m_plus"], "b_merge": info["b_merge"],
+                                  "max_degree": info["max_out_degree"]}
+    rows["lollipop"] = {"ms": 1e3 * statistics.median(lol), "count": lcount,
+                        "includes": "per-root triangle launch, degree-weighted sum, read-back"}
+    log(f"[bench] Lollipop {rows['lollipop']['ms']:.3f} ms, count {lcount}")
+    parity = {"six_t": best[2] == 6 * t_count}
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        g = oracle.Graph.from_edgelist(el)
+        th = oracle.max_threads()
+        t0 = time.perf_counter()
+        six_t, _ = g.sym_triangles_by_first(threads=th)
+        t_tri = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ref_l = g.sym_lollipop(threads=th)
+        t_l = time.perf_counter() - t0
+        parity.update(six_t_oracle=six_t == best[2], lollipop_oracle=ref_l == lcount)
+        cpu = {"value": info["m_plus"] / t_tri, "unit": "stored edges/s", "cores": th,
+               "kind": "oracle", "sample": f"whole graph: unpruned triangles {t_tri:.2f} s, "
+                                           f"Lollipop {t_l:.2f} s"}
+        log(f"[bench] oracle: unpruned triangles {t_tri:.2f} s, Lollipop {t_l:.2f} s")
+    trie.free()
+    ms = best[0]
+    achieved = info["b_merge"] / (ms / 1e3) / 1e9
+    res = {
+        "metric": metric, "value": info["m_plus"] / (ms / 1e3), "unit": "stored edges/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic (seeded generator)",
+        "config": {"workload": name, "scale": w["scale"], "edge_factor": w["edge_factor"],
+                   "seed": w["seed"], "layout": "hybrid", "tau": w["tau"],
+                   "relation": "both directions of every edge (unpruned)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                     "frac": achieved / 8000.0, "traffic": None,
+                     "algorithmic_bytes_per_launch": info["b_merge"], "model": "B_merge (arcs)"},
+        "table": rows,
+        "parity_vs_oracle": all(parity.values()),
+    }
+    if cpu:
+        res["cpu_baseline"] = cpu
+    return res
 
 
 def serve_run(ctx, eh, trie, reqs, mode, policy=0):

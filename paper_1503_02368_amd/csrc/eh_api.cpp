@@ -155,6 +155,7 @@ LaunchArgs base_args(Ctx* c, const Trie& t) {
   a.unroll = c->tune.unroll;
   a.grab = c->tune.grab;
   a.search_below = c->tune.search_below;
+  a.symmetric = t.host.symmetric ? 1u : 0u;
   return a;
 }
 
@@ -181,11 +182,14 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
 
 // Target staging describes each streamed suffix of N+(u) by a 16-bit length,
 // which degree order guarantees (out-degrees below sqrt(2m) < 2^16); tries
-// built under another node ordering may exceed it and then stage sources.
+// built under another node ordering may exceed it and then stage sources, as
+// do symmetric tries.
 uint32_t tri_staging(const Ctx* c, const Trie& t, bool per_root) {
   if (per_root) return EH_STAGE_SOURCE;
   if (c->tune.kernel == EH_KERNEL_PAIRWISE) return EH_STAGE_SOURCE;
   if (t.host.dmax > 0xFFFFu) return EH_STAGE_SOURCE;
+  // suffix streaming relies on orientation (every member of N+(v) exceeds v)
+  if (t.host.symmetric) return EH_STAGE_SOURCE;
   return c->tune.staging == EH_STAGE_SOURCE ? EH_STAGE_SOURCE : EH_STAGE_TARGET;
 }
 
@@ -572,6 +576,33 @@ eh_status eh_count_4cliques(eh_ctx* ctx, const eh_trie* trie, uint64_t* total) {
       count_single(c, t, EH_4CLIQUE, static_cast<unsigned long long*>(c->acc.p), nullptr);
   if (st != EH_OK) return st;
   return read_back(c, static_cast<const unsigned long long*>(c->acc.p), total, 1);
+}
+
+eh_status eh_count_lollipop(eh_ctx* ctx, const eh_trie* trie, uint64_t* total) {
+  if (!ctx || !trie || !total) return EH_EINVAL;
+  Ctx* c = &ctx->c;
+  Trie& t = const_cast<eh_trie*>(trie)->t;
+  if (!t.host.symmetric || t.host.n_graphs != 1) {
+    c->err = "the Lollipop count needs a symmetric single-graph trie";
+    return EH_ESTATE;
+  }
+  eh_status st = hip_check(c, hipSetDevice(c->device), "hipSetDevice");
+  if (st != EH_OK) return st;
+  DevBuf per;  // t(x) by original id
+  if ((st = dev_alloc(c, per, sizeof(unsigned long long) * std::max<uint32_t>(t.host.n, 1))) !=
+      EH_OK)
+    return st;
+  auto* acc = static_cast<unsigned long long*>(c->acc.p);
+  st = count_single(c, t, EH_TRIANGLE, acc, static_cast<unsigned long long*>(per.p));
+  if (st == EH_OK) st = launch_fill_u64(c, c->stream, acc + 1, 1, 0);
+  if (st == EH_OK)
+    st = launch_degree_weighted_sum(c, c->stream, static_cast<const unsigned long long*>(per.p),
+                                    static_cast<const uint32_t*>(t.vert.p),
+                                    static_cast<const uint2*>(t.vdesc.p), t.host.n, acc + 1);
+  if (st == EH_OK) st = read_back(c, acc + 1, total, 1);
+  (void)hipStreamSynchronize(c->stream);
+  dev_free(c, per);
+  return st;
 }
 
 eh_status eh_count_async(eh_ctx* ctx, const eh_trie* trie, int pattern, uint64_t* d_total) {

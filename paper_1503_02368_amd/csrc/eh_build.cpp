@@ -25,6 +25,7 @@ BuildOpts resolve_opts(const eh_build_opts* o) {
   b.tau = o->tau > 0.0f ? o->tau : 32.0f;
   b.s_min = o->s_min ? o->s_min : 1;
   b.order = o->order;
+  b.symmetric = o->symmetric ? 1u : 0u;
   return b;
 }
 
@@ -213,8 +214,16 @@ eh_status build_one(const uint32_t* src, const uint32_t* dst, uint64_t m_raw, ui
   std::vector<uint32_t> deg(n, 0);
   for (uint64_t k : key) { deg[k >> 32]++; deg[k & 0xFFFFFFFFu]++; }
   rank_vertices(opts.order, n, key, deg, h.rank, h.vert);
-  // orient low rank -> high rank; rows sorted by scattering in target order
-  std::vector<uint32_t> eu(m), ev(m);
+  // orient low rank -> high rank (or keep both directions: the unpruned
+  // relation); rows sorted by scattering in target order
+  const uint64_t arcs = opts.symmetric ? 2 * m : m;
+  if (arcs > kMaxIndex) {
+    err = "graph has " + std::to_string(arcs) + " stored edges; at most 2^31-1 supported";
+    return EH_EOVERFLOW;
+  }
+  h.m = arcs;
+  h.symmetric = opts.symmetric != 0;
+  std::vector<uint32_t> eu(arcs), ev(arcs);
   std::vector<uint32_t> by_v(size_t(n) + 1, 0);
   h.row.assign(size_t(n) + 1, 0);
   for (uint64_t i = 0; i < m; ++i) {
@@ -224,18 +233,24 @@ eh_status build_one(const uint32_t* src, const uint32_t* dst, uint64_t m_raw, ui
     ev[i] = rb;
     h.row[ra + 1]++;
     by_v[rb + 1]++;
+    if (opts.symmetric) {
+      eu[m + i] = rb;
+      ev[m + i] = ra;
+      h.row[rb + 1]++;
+      by_v[ra + 1]++;
+    }
   }
   std::vector<uint64_t>().swap(key);
   for (uint32_t r = 0; r < n; ++r) { h.row[r + 1] += h.row[r]; by_v[r + 1] += by_v[r]; }
-  std::vector<uint32_t> order(m);  // edge ids sorted by target rank
+  std::vector<uint32_t> order(arcs);  // arc ids sorted by target rank
   {
     std::vector<uint32_t> fill(by_v.begin(), by_v.end() - 1);
-    for (uint64_t i = 0; i < m; ++i) order[fill[ev[i]]++] = uint32_t(i);
+    for (uint64_t i = 0; i < arcs; ++i) order[fill[ev[i]]++] = uint32_t(i);
   }
-  h.col.assign(m, 0);
+  h.col.assign(arcs, 0);
   {
     std::vector<uint32_t> fill(h.row.begin(), h.row.end() - 1);
-    for (uint64_t k = 0; k < m; ++k) {
+    for (uint64_t k = 0; k < arcs; ++k) {
       const uint32_t i = order[k];
       h.col[fill[eu[i]]++] = ev[i];
     }
@@ -350,6 +365,7 @@ eh_status host_build_batch(uint32_t n_graphs, const uint32_t* n_vertices, const 
   uint64_t M = 0, W = 0;
   h = HostTrie();
   h.n_graphs = n_graphs;
+  h.symmetric = opts.symmetric != 0;
   h.g_vbase.assign(size_t(n_graphs) + 1, 0);
   // each graph's rank range starts at a multiple of 32 so bitset words of
   // different sets stay aligned to one another; padding ranks are isolated

@@ -134,8 +134,10 @@ __global__ void __launch_bounds__(kB) k_ranks(const uint32_t* __restrict__ seq, 
   }
 }
 
+// Low rank << k | high rank per edge; a symmetric trie also gets the reverse
+// arc at m + i.
 __global__ void __launch_bounds__(kB) k_orient(const unsigned long long* __restrict__ key,
-                                               uint64_t m, uint32_t kb,
+                                               uint64_t m, uint32_t kb, uint32_t symmetric,
                                                const uint32_t* __restrict__ rank,
                                                unsigned long long* __restrict__ out) {
   const unsigned long long mask = (1ull << kb) - 1;
@@ -147,6 +149,7 @@ __global__ void __launch_bounds__(kB) k_orient(const unsigned long long* __restr
       rb = t;
     }
     out[i] = (static_cast<unsigned long long>(ra) << kb) | rb;
+    if (symmetric) out[m + i] = (static_cast<unsigned long long>(rb) << kb) | ra;
   }
 }
 
@@ -297,11 +300,12 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
   }
   const uint32_t kb = n > 1 ? 32u - uint32_t(__builtin_clz(n - 1)) : 1u;
   const uint64_t mr = std::max<uint64_t>(m_raw, 1);
+  const uint64_t kcap = opts.symmetric ? 2 * mr : mr;  // stored arcs fit 2 m <= 2 m_raw
   const uint32_t n1 = std::max<uint32_t>(n, 1);
   DevBuf keys_a, keys_b, tmp, deg, ids, deg_s, seq, rank, row, nw, base, off, bs_off, stats, cnt;
   Scratch sc(c);
   eh_status st;
-  if ((st = sc.get(keys_a, 8 * mr)) != EH_OK || (st = sc.get(keys_b, 8 * mr)) != EH_OK ||
+  if ((st = sc.get(keys_a, 8 * kcap)) != EH_OK || (st = sc.get(keys_b, 8 * kcap)) != EH_OK ||
       (st = sc.get(deg, 4ull * n1)) != EH_OK || (st = sc.get(ids, 4ull * n1)) != EH_OK ||
       (st = sc.get(deg_s, 4ull * n1)) != EH_OK || (st = sc.get(seq, 4ull * n1)) != EH_OK ||
       (st = sc.get(rank, 4ull * n1)) != EH_OK || (st = sc.get(row, 4ull * (n + 1))) != EH_OK ||
@@ -321,7 +325,7 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
   const unsigned key_bits = 2 * kb;
   auto chk = [&](hipError_t e, const char* what) { return hip_check(c, e, what); };
   rocprim::double_buffer<unsigned long long> db(ka, kbuf);
-  if ((st = chk(rocprim::radix_sort_keys(nullptr, b, db, size_t(mr), 0, key_bits, s),
+  if ((st = chk(rocprim::radix_sort_keys(nullptr, b, db, size_t(kcap), 0, key_bits, s),
                 "radix sort size")) != EH_OK)
     return st;
   need = std::max(need, b);
@@ -382,16 +386,18 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
       return st;
     m = h_cnt[0] - (h_cnt[0] && last == kSentinel ? 1 : 0);
   }
+  const uint64_t edges = m;
+  if (opts.symmetric) m *= 2;  // from here on, m counts stored arcs
   if (m > kMaxIndex) {
-    c->err = "graph has " + std::to_string(m) + " edges; at most 2^31-1 supported";
+    c->err = "graph has " + std::to_string(m) + " stored edges; at most 2^31-1 supported";
     return EH_EOVERFLOW;
   }
 
   // 3: degrees and ranks
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_of(n1)), dim3(kB), 0, s, ptr<uint32_t>(deg),
                      uint64_t(n1), 0u);
-  if (m)
-    hipLaunchKernelGGL(k_degrees, dim3(grid_of(m)), dim3(kB), 0, s, uniq, m, kb,
+  if (edges)
+    hipLaunchKernelGGL(k_degrees, dim3(grid_of(edges)), dim3(kB), 0, s, uniq, edges, kb,
                        ptr<uint32_t>(deg));
   hipLaunchKernelGGL(k_iota, dim3(grid_of(n1)), dim3(kB), 0, s, ptr<uint32_t>(ids), n1);
   if ((st = dev_alloc(c, t.vert, 4ull * n1)) != EH_OK) return st;
@@ -414,8 +420,8 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
 
   // 4: orientation and rows; `ka` then names the sorted oriented edges
   if (m) {
-    hipLaunchKernelGGL(k_orient, dim3(grid_of(m)), dim3(kB), 0, s, uniq, m, kb,
-                       ptr<uint32_t>(rank), spare);
+    hipLaunchKernelGGL(k_orient, dim3(grid_of(edges)), dim3(kB), 0, s, uniq, edges, kb,
+                       opts.symmetric ? 1u : 0u, ptr<uint32_t>(rank), spare);
     rocprim::double_buffer<unsigned long long> oriented(spare, uniq);
     tmp_bytes = tmp.bytes;
     if ((st = chk(rocprim::radix_sort_keys(tmp.p, tmp_bytes, oriented, size_t(m), 0, key_bits, s),
@@ -476,6 +482,7 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
   h.n_bs = n_bs;
   h.n_graphs = 1;
   h.g_vbase = {0, n};
+  h.symmetric = opts.symmetric != 0;
   h.rank.resize(n);
   h.vert.resize(n);
   h.row.resize(size_t(n) + 1);

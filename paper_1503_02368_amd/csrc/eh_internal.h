@@ -40,7 +40,7 @@ static_assert(sizeof(Item) == 16, "Item is one 128-bit load");
 // Host half of a trie: rank-space oriented CSR plus set layouts.
 struct HostTrie {
   uint32_t n = 0;
-  uint64_t m = 0;                    // oriented edges
+  uint64_t m = 0;                    // stored edges (oriented, or both directions)
   uint32_t dmax = 0;                 // max out-degree
   uint64_t b_merge = 0;
   std::vector<uint32_t> rank;        // rank[id]
@@ -56,6 +56,7 @@ struct HostTrie {
   // [row[g_vbase[g]], row[g_vbase[g+1]])
   std::vector<uint32_t> g_vbase;     // [G+1]
   uint32_t n_graphs = 1;
+  bool symmetric = false;            // both directions of every edge (unpruned relation)
 };
 
 struct BuildOpts {
@@ -63,6 +64,7 @@ struct BuildOpts {
   float tau = 32.0f;
   uint32_t s_min = 1;
   uint32_t order = EH_ORDER_DEGREE;
+  uint32_t symmetric = 0;
 };
 BuildOpts resolve_opts(const eh_build_opts* o);
 
@@ -212,6 +214,7 @@ struct LaunchArgs {
   uint32_t grab = 8;                   // schedule 4: items per cursor fetch
   uint32_t search_below = 24;          // average segment length below which the walk searches
   const uint4* gsub = nullptr;         // grouped items' members, or null
+  uint32_t symmetric = 0;              // both directions of every edge are stored
 };
 eh_status launch_fill_u64(Ctx* c, hipStream_t s, unsigned long long* p, uint64_t n,
                           unsigned long long v);
@@ -221,6 +224,10 @@ eh_status launch_4cliques(Ctx* c, hipStream_t s, const LaunchArgs& a, uint32_t k
                           uint32_t waves_per_cu);
 eh_status launch_scatter_roots(Ctx* c, hipStream_t s, const unsigned long long* by_rank,
                                const uint32_t* vert, unsigned long long* by_id, uint32_t n);
+// out[0] += sum over ranks r of t_by_id[vert[r]] * |N(r)| (Lollipop COUNT).
+eh_status launch_degree_weighted_sum(Ctx* c, hipStream_t s, const unsigned long long* t_by_id,
+                                     const uint32_t* vert, const uint2* vdesc, uint32_t n,
+                                     unsigned long long* out);
 // Largest out-degree the staged 4-clique kernel accepts.
 uint32_t k4_staged_max_degree();
 

@@ -70,6 +70,7 @@ struct DevArgs {
   uint32_t deg_lo, deg_hi;  // 4-clique: items with deg_lo < d+(u) <= deg_hi
   uint32_t search_below;    // segments shorter on average: the walk binary-searches
   const uint4* gsub;        // grouped items' members, or null
+  uint32_t symmetric;       // the trie holds both directions of every edge
 };
 
 DevArgs to_dev(const LaunchArgs& a) {
@@ -99,6 +100,7 @@ DevArgs to_dev(const LaunchArgs& a) {
   d.deg_hi = a.deg_hi;
   d.search_below = a.search_below;
   d.gsub = a.gsub;
+  d.symmetric = a.symmetric;
   return d;
 }
 
@@ -845,10 +847,11 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
     const bool su_bits = su.mode == kModeBitmap || su.mode == kModeComposite;
     uint32_t cnt = 0;
     for (uint32_t q = 0; q < llen; ++q) {
-      // S lies in N+(v) and in the part of N+(u) after v: with fewer than two
-      // members in either, no 4-clique extends (u, v)
-      const uint32_t after = su.beg + su.len - (lbeg + q) - 1;
-      if (after < 2) break;  // later v have even fewer
+      // S lies in N+(v) and, on pruned data, in the part of N+(u) after v:
+      // with fewer than two members in either, no 4-clique extends (u, v)
+      // (nor, for the second, any later v).  The unpruned relation has no
+      // such order: S may hold members of N(u) before v.
+      if (!a.symmetric && su.beg + su.len - (lbeg + q) - 1 < 2) break;
       const uint32_t v = uniform(a.idx[lbeg + q]);
       const uint2 vd = a.vdesc[v];
       const uint32_t vb = uniform(vd.x), vl = uniform(vd.y & kMaxIndex);

@@ -39,7 +39,7 @@ SYMBOLS = [
     "eh_count_async", "eh_count_add_async", "eh_count_rooted", "eh_count_batch", "eh_count_batch_async",
     "eh_server_create", "eh_submit", "eh_poll", "eh_wait", "eh_server_drain", "eh_server_destroy",
     "eh_host_trie_build", "eh_host_trie_info", "eh_host_trie_arrays", "eh_host_trie_free",
-    "eh_build_trie_device", "eh_trie_host_arrays", "eh_trie_device_arrays",
+    "eh_build_trie_device", "eh_trie_host_arrays", "eh_trie_device_arrays", "eh_count_lollipop",
 ]
 
 
@@ -56,7 +56,7 @@ class _Allocator(ctypes.Structure):
 
 
 # struct layouts below are those of this ABI version of include/eh.h
-ABI_VERSION = 10400
+ABI_VERSION = 10500
 
 
 class _Tuning(ctypes.Structure):
@@ -71,7 +71,7 @@ class _Tuning(ctypes.Structure):
 
 class _BuildOpts(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_uint32), ("tau", ctypes.c_float), ("s_min", ctypes.c_uint32),
-                ("order", ctypes.c_uint32)]
+                ("order", ctypes.c_uint32), ("symmetric", ctypes.c_uint32)]
 
 
 class _TrieInfo(ctypes.Structure):
@@ -144,6 +144,7 @@ def load():
                                      ctypes.POINTER(_BuildOpts), ctypes.POINTER(_vp)],
             "eh_trie_host_arrays": [_vp, _u32p, _u32p, _u32p, _u32p, _u32p, _u32p, _u32p],
             "eh_trie_device_arrays": [_vp, _vp, _u32p, _u32p, _u32p, _u32p],
+            "eh_count_lollipop": [_vp, _vp, _u64p],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -173,20 +174,21 @@ def _u32(a):
     return np.ascontiguousarray(a, dtype=np.uint32)
 
 
-def _opts(layout, tau, s_min, order):
-    return _BuildOpts(int(layout), float(tau), int(s_min), int(order))
+def _opts(layout, tau, s_min, order, symmetric=0):
+    return _BuildOpts(int(layout), float(tau), int(s_min), int(order), int(bool(symmetric)))
 
 
 def _info_dict(info: _TrieInfo) -> dict:
     return {k: int(getattr(info, k)) for k, _ in _TrieInfo._fields_ if k != "reserved"}
 
 
-def host_trie(n, src, dst, layout=LAYOUT_HYBRID, tau=32.0, s_min=1, order=ORDER_DEGREE) -> dict:
+def host_trie(n, src, dst, layout=LAYOUT_HYBRID, tau=32.0, s_min=1, order=ORDER_DEGREE,
+              symmetric=False) -> dict:
     """Runs only the host half of the trie build (no GPU) and returns its arrays."""
     lib = load()
     src, dst = _u32(src), _u32(dst)
     h = _vp()
-    o = _opts(layout, tau, s_min, order)
+    o = _opts(layout, tau, s_min, order, symmetric)
     st = lib.eh_host_trie_build(_p32(src), _p32(dst), src.size, int(n), ctypes.byref(o), ctypes.byref(h))
     if st != EH_OK:
         raise EHError(st, lib.eh_last_error(None).decode() or lib.eh_status_str(st).decode())
@@ -287,18 +289,18 @@ class Context:
 
     # -- tries -------------------------------------------------------------
     def build_trie(self, n, src, dst, layout=LAYOUT_HYBRID, tau=32.0, s_min=1,
-                   order=ORDER_DEGREE) -> "Trie":
+                   order=ORDER_DEGREE, symmetric=False) -> "Trie":
         src, dst = _u32(src), _u32(dst)
         if src.shape != dst.shape:
             raise ValueError("src and dst differ in length")
         h = _vp()
-        o = _opts(layout, tau, s_min, order)
+        o = _opts(layout, tau, s_min, order, symmetric)
         self._check(self._lib.eh_build_trie(self._h, _p32(src), _p32(dst), src.size, int(n),
                                             ctypes.byref(o), ctypes.byref(h)), "build_trie")
         return Trie(self, h)
 
     def build_trie_device(self, n, d_src, d_dst, layout=LAYOUT_HYBRID, tau=32.0, s_min=1,
-                          order=ORDER_DEGREE) -> "Trie":
+                          order=ORDER_DEGREE, symmetric=False) -> "Trie":
         """The same trie, built on the GPU from device tensors of raw pairs (4-byte
         elements, e.g. torch.int32 holding ids below 2^31)."""
         if d_src.numel() != d_dst.numel():
@@ -310,7 +312,7 @@ class Context:
         # the pairs were written on torch's current stream; the build reads them on ours
         self.stream.wait_stream(torch.cuda.current_stream())
         h = _vp()
-        o = _opts(layout, tau, s_min, order)
+        o = _opts(layout, tau, s_min, order, symmetric)
         self._check(self._lib.eh_build_trie_device(self._h, _vp(d_src.data_ptr()),
                                                    _vp(d_dst.data_ptr()), d_src.numel(), int(n),
                                                    ctypes.byref(o), ctypes.byref(h)),
@@ -334,12 +336,12 @@ class Context:
         return self.build_trie(el.n, el.src, el.dst, **kw)
 
     def build_batch(self, batch, layout=LAYOUT_HYBRID, tau=32.0, s_min=1,
-                    order=ORDER_DEGREE) -> "Trie":
+                    order=ORDER_DEGREE, symmetric=False) -> "Trie":
         nv = _u32(batch.n_vertices)
         off = np.ascontiguousarray(batch.edge_off, dtype=np.uint64)
         src, dst = _u32(batch.src), _u32(batch.dst)
         h = _vp()
-        o = _opts(layout, tau, s_min, order)
+        o = _opts(layout, tau, s_min, order, symmetric)
         self._check(self._lib.eh_build_batch(self._h, nv.size, _p32(nv), _p64(off), _p32(src), _p32(dst),
                                              ctypes.byref(o), ctypes.byref(h)), "build_batch")
         return Trie(self, h)
@@ -356,6 +358,12 @@ class Context:
                     "count_triangles")
         if per_root:
             return int(out.value), roots.cpu().numpy().view(np.uint64)
+        return int(out.value)
+
+    def count_lollipop(self, trie) -> int:
+        """COUNT(*) of Lollipop(x,y,z,w) :- R(x,y),S(y,z),T(x,z),U(x,w) on a symmetric trie."""
+        out = ctypes.c_uint64(0)
+        self._check(self._lib.eh_count_lollipop(self._h, trie._h, ctypes.byref(out)), "count_lollipop")
         return int(out.value)
 
     def count_4cliques(self, trie) -> int:

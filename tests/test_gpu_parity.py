@@ -733,6 +733,116 @@ def test_device_build_full_size_rmat20(ctx, eh):
         ht.free()
 
 
+SYM_GRAPHS = [inputs.rmat(12, 16, seed=71), inputs.chung_lu(6000, 12, 2.3, seed=72),
+              inputs.messy(inputs.rmat(10, 8, seed=73), 2), inputs.gnp(60, 0.3, seed=74),
+              inputs.complete(45), inputs.disjoint_union(inputs.wheel(25), inputs.star(12),
+                                                         inputs.path(1), inputs.grid(5, 5)),
+              inputs.chung_lu(30000, 8, 1.9, seed=75)]
+_SYM_TRUTH = {}
+
+
+def sym_truth(el):
+    """6T, t(x) by id, 24K and the Lollipop count, from the oracle (pinned:
+    the unpruned join equals 6T and 24K; t(x) = 2 c3(x))."""
+    if el.name not in _SYM_TRUTH:
+        g = oracle.Graph.from_edgelist(el)
+        six_t, t = g.sym_triangles_by_first()
+        _SYM_TRUTH[el.name] = (six_t, t, 24 * g.count(4), g.sym_lollipop())
+    return _SYM_TRUTH[el.name]
+
+
+@pytest.mark.parametrize("tname", ["staged_target", "staged_source", "staged_lean", "staged_group",
+                                   "staged_search", "staged_steal", "pair_auto", "pair_merge4"])
+def test_symmetric_triangles_and_lollipop(ctx, eh, tname):
+    """Unpruned relation: the join's ordered triangles (6T), t(x) by first
+    attribute, rooted counts, and the Lollipop count, under every kernel."""
+    tune(ctx, **TUNINGS[tname])
+    for el in SYM_GRAPHS:
+        six_t, t, _, lolli = sym_truth(el)
+        say("symmetric", tname, el.name)
+        trie = ctx.build_edgelist(el, symmetric=True)
+        try:
+            assert ctx.count_triangles(trie) == six_t
+            tot, per = ctx.count_triangles(trie, per_root=True)
+            assert tot == six_t
+            np.testing.assert_array_equal(per, t)
+            roots = np.arange(1, el.n, 5, dtype=np.uint32)
+            assert ctx.count_rooted(trie, eh.TRIANGLE, roots) == int(t[roots].sum(dtype=np.uint64))
+            assert ctx.count_lollipop(trie) == lolli
+        finally:
+            trie.free()
+
+
+@pytest.mark.parametrize("tname", ["staged_source", "staged_half", "staged_steal"])
+def test_symmetric_4cliques(ctx, eh, tname):
+    """Unpruned 4-cliques: 24K ordered tuples while every degree fits the
+    2048-entry S list, EH_EOVERFLOW beyond."""
+    tune(ctx, **TUNINGS[tname])
+    for el in SYM_GRAPHS:
+        _, _, k24, _ = sym_truth(el)
+        trie = ctx.build_edgelist(el, symmetric=True)
+        try:
+            if trie.info["max_out_degree"] <= 2048:
+                assert ctx.count_4cliques(trie) == k24, el.name
+            else:
+                with pytest.raises(eh.EHError) as e:
+                    ctx.count_4cliques(trie)
+                assert e.value.status == eh.EH_EOVERFLOW
+        finally:
+            trie.free()
+
+
+def test_symmetric_hub_of_100k(ctx, eh):
+    """W_100000 unpruned: the hub's set has 100,000 members (composite
+    staging, uint-bitset at scale); 6T = 6k, Lollipop = 2k^2 + 12k."""
+    k = 100000
+    trie = ctx.build_edgelist(inputs.wheel(k), symmetric=True)
+    try:
+        assert trie.info["max_out_degree"] == k
+        for tname in ("staged_source", "staged_lean", "pair_auto", "staged_steal"):
+            tune(ctx, **TUNINGS[tname])
+            assert ctx.count_triangles(trie) == 6 * k, tname
+            assert ctx.count_lollipop(trie) == 2 * k * k + 12 * k, tname
+    finally:
+        trie.free()
+
+
+def test_symmetric_batch_and_device_build(ctx, eh):
+    tune(ctx, **TUNINGS["staged_steal"])
+    b = small_batch(60, seed=17)
+    want = [(6 * order_truth(b.graph(i), "degree")[0]["count"],
+             24 * oracle.Graph.from_edgelist(b.graph(i)).count(4)) for i in range(b.n_graphs)]
+    trie = ctx.build_batch(b, symmetric=True)
+    try:
+        np.testing.assert_array_equal(ctx.count_batch(trie, eh.TRIANGLE),
+                                      np.array([w[0] for w in want], np.uint64))
+        if trie.info["max_out_degree"] <= 2048:
+            np.testing.assert_array_equal(ctx.count_batch(trie, eh.CLIQUE4),
+                                          np.array([w[1] for w in want], np.uint64))
+        with pytest.raises(eh.EHError) as e:
+            ctx.count_lollipop(trie)
+        assert e.value.status == eh.EH_ESTATE
+    finally:
+        trie.free()
+    for el in SYM_GRAPHS[:4]:
+        src, dst = _device_pairs(el)
+        ht = ctx.build_edgelist(el, symmetric=True)
+        dt = ctx.build_trie_device(el.n, src, dst, symmetric=True)
+        try:
+            _same_trie(ctx, dt, ht, el.name + " symmetric")
+            assert ctx.count_lollipop(dt) == sym_truth(el)[3]
+        finally:
+            dt.free()
+            ht.free()
+    pruned = ctx.build_edgelist(SYM_GRAPHS[0])
+    try:
+        with pytest.raises(eh.EHError) as e:
+            ctx.count_lollipop(pruned)
+        assert e.value.status == eh.EH_ESTATE
+    finally:
+        pruned.free()
+
+
 def test_out_degree_limits(ctx, eh):
     """K_2050: triangles at out-degree 2049 (C(n, 3)); the 4-clique kernel's
     S list holds at most 2048 entries, so its count is refused with
