@@ -479,18 +479,29 @@ std::vector<uint64_t> even_parts(uint64_t n, unsigned parts) {
 }
 
 // Ranges of [0, n) holding about equal shares of the work prefix[x+1] - prefix[x].
-std::vector<uint64_t> weighted_parts(const std::vector<uint32_t>& prefix, uint64_t n,
-                                     unsigned parts) {
+template <class T>
+std::vector<uint64_t> weighted_parts(const std::vector<T>& prefix, uint64_t n, unsigned parts) {
   std::vector<uint64_t> b(parts + 1, 0);
   const uint64_t total = prefix[n];
   for (unsigned p = 1; p < parts; ++p) {
     const uint64_t want = total * p / parts;
-    b[p] = uint64_t(std::lower_bound(prefix.begin(), prefix.begin() + n, uint32_t(want)) -
+    b[p] = uint64_t(std::lower_bound(prefix.begin(), prefix.begin() + n, T(want)) -
                     prefix.begin());
     b[p] = std::max(b[p], b[p - 1]);
   }
   b[parts] = n;
   return b;
+}
+
+// Sources whose out-edges can reach the targets [v0, v1): the vertices of the
+// graphs those targets belong to (the graphs of a batch share no edges).
+std::pair<uint64_t, uint64_t> source_span(const HostTrie& h, uint64_t v0, uint64_t v1) {
+  if (v0 >= v1) return {0, 0};
+  const auto& gb = h.g_vbase;
+  const size_t ga = size_t(std::upper_bound(gb.begin(), gb.end(), uint32_t(v0)) - gb.begin()) - 1;
+  const size_t gz =
+      size_t(std::upper_bound(gb.begin(), gb.end(), uint32_t(v1 - 1)) - gb.begin()) - 1;
+  return {gb[ga], gb[gz + 1]};
 }
 
 template <class F>
@@ -609,13 +620,16 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
   if (staging == EH_STAGE_TARGET) {
     if (!t->has_transpose) {
       // in-edges of each v, ascending in u: {u, position of v in N+(u)}.
-      // Each thread owns a range of targets and scans every edge in source
-      // order, so it writes its targets' in-edges in the sequential order
-      // with no shared counters; target ranges hold about equal in-edges.
+      // Each thread owns a range of targets and scans, in source order, every
+      // edge that can reach them (all of a single graph's, only its own
+      // graphs' in a batch), so it writes its targets' in-edges in the
+      // sequential order with no shared counters; target ranges hold about
+      // equal in-edges.
       const unsigned parts = plan_threads(h.m);
       t->trow.assign(size_t(h.n) + 1, 0);
-      run_parts(even_parts(h.n, parts), [&](uint64_t v0, uint64_t v1, unsigned) {
-        for (uint64_t e = 0; e < h.m; ++e) {
+      run_parts(weighted_parts(h.row, h.n, parts), [&](uint64_t v0, uint64_t v1, unsigned) {
+        const auto span = source_span(h, v0, v1);
+        for (uint64_t e = h.row[span.first]; e < h.row[span.second]; ++e) {
           const uint32_t v = h.col[e];
           if (v >= v0 && v < v1) t->trow[v + 1]++;
         }
@@ -624,7 +638,8 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
       t->tin.assign(2 * h.m, 0);
       std::vector<uint32_t> fill(t->trow.begin(), t->trow.end() - 1);
       run_parts(weighted_parts(t->trow, h.n, parts), [&](uint64_t v0, uint64_t v1, unsigned) {
-        for (uint32_t u = 0; u < h.n; ++u)
+        const auto span = source_span(h, v0, v1);
+        for (uint64_t u = span.first; u < span.second; ++u)
           for (uint32_t e = h.row[u]; e < h.row[u + 1]; ++e) {
             const uint32_t v = h.col[e];
             if (v < v0 || v >= v1) continue;
@@ -699,12 +714,6 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
     std::vector<uint32_t> sd;   // per item: staged-set extent, or a group's descriptor
     std::vector<uint32_t> gsub; // per grouped member
     std::vector<uint8_t> grouped(h.n, 0);
-    auto single = [&](std::vector<Item>& out, const Item& it) {
-      const uint32_t v = it.s;
-      out.push_back(it);
-      sd.insert(sd.end(), {h.row[v], h.row[v + 1] - h.row[v], h.col[h.row[v]],
-                           h.col[h.row[v + 1] - 1]});
-    };
     if (plan->group > 1) {
       // Consecutive small items of one graph share a wave: up to `group`
       // whole-vertex items whose records and staged members each total at
@@ -712,52 +721,92 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
       // (bit (x - base) K + k marks x as a member of the k-th set), K the
       // power of two >= the member count.  Their records carry no bitset
       // words (a word does not line up with interleaved bits).
+      // Groups never cross graphs: threads take graph ranges holding about
+      // equal item counts, and their outputs are joined in graph order (a
+      // grouped item's member index is then rebased).
+      struct Part {
+        std::vector<Item> out;
+        std::vector<uint32_t> sd, gsub;
+        std::vector<uint64_t> off;  // per graph of the range: first output item
+      };
+      const std::vector<uint64_t> gparts =
+          weighted_parts(plan->g_item_off, h.n_graphs,
+                         std::min<unsigned>(plan_threads(items.size()), h.n_graphs));
+      std::vector<Part> part(gparts.size() - 1);
+      auto whole = [&](const Item& it) {
+        return it.lbeg == t->trow[it.s] && it.llen == t->trow[it.s + 1] - t->trow[it.s];
+      };
+      run_parts(gparts, [&](uint64_t g0, uint64_t g1, unsigned pi) {
+        Part& q = part[pi];
+        for (uint64_t g = g0; g < g1; ++g) {
+          q.off.push_back(q.out.size());
+          const uint64_t i1 = plan->g_item_off[g + 1];
+          for (uint64_t i = plan->g_item_off[g]; i < i1;) {
+            const Item& a0 = items[i];
+            uint64_t j = i + 1;
+            if (whole(a0)) {
+              uint32_t base = h.col[h.row[a0.s]], top = h.col[h.row[a0.s + 1] - 1];
+              uint32_t recs = a0.llen, mem = h.row[a0.s + 1] - h.row[a0.s];
+              while (j < i1 && j - i < plan->group && whole(items[j])) {
+                const uint32_t v = items[j].s;
+                const uint32_t nb = std::min(base, h.col[h.row[v]]);
+                const uint32_t nt = std::max(top, h.col[h.row[v + 1] - 1]);
+                const uint64_t kk = (j - i + 1) <= 2 ? 2 : 4;
+                const uint32_t dv = h.row[v + 1] - h.row[v];
+                if (recs + items[j].llen > 64 || mem + dv > 64 ||
+                    (uint64_t(nt) - nb + 1) * kk > uint64_t(cap) * 32)
+                  break;
+                base = nb;
+                top = nt;
+                recs += items[j].llen;
+                mem += dv;
+                ++j;
+              }
+              if (j - i > 1) {
+                const uint32_t cnt = uint32_t(j - i);
+                q.out.push_back(Item{uint32_t(q.gsub.size() / 4) | kHiBit, cnt, recs, a0.tag});
+                q.sd.insert(q.sd.end(), {base, cnt <= 2 ? 1u : 2u, mem, top});
+                for (uint64_t k = i; k < j; ++k) {
+                  const uint32_t v = items[k].s;
+                  grouped[v] = 1;
+                  q.gsub.insert(q.gsub.end(),
+                                {items[k].lbeg, items[k].llen, h.row[v], h.row[v + 1] - h.row[v]});
+                }
+                i = j;
+                continue;
+              }
+            }
+            const uint32_t v = a0.s;
+            q.out.push_back(a0);
+            q.sd.insert(q.sd.end(), {h.row[v], h.row[v + 1] - h.row[v], h.col[h.row[v]],
+                                     h.col[h.row[v + 1] - 1]});
+            i = i + 1;
+          }
+        }
+      });
       std::vector<Item> out;
       std::vector<uint64_t> off(h.n_graphs + 1, 0);
-      for (uint32_t g = 0; g < h.n_graphs; ++g) {
-        off[g] = out.size();
-        const uint64_t i1 = plan->g_item_off[g + 1];
-        auto whole = [&](const Item& it) {
-          return it.lbeg == t->trow[it.s] && it.llen == t->trow[it.s + 1] - t->trow[it.s];
-        };
-        for (uint64_t i = plan->g_item_off[g]; i < i1;) {
-          const Item& a0 = items[i];
-          uint64_t j = i + 1;
-          if (whole(a0)) {
-            uint32_t base = h.col[h.row[a0.s]], top = h.col[h.row[a0.s + 1] - 1];
-            uint32_t recs = a0.llen, mem = h.row[a0.s + 1] - h.row[a0.s];
-            while (j < i1 && j - i < plan->group && whole(items[j])) {
-              const uint32_t v = items[j].s;
-              const uint32_t nb = std::min(base, h.col[h.row[v]]);
-              const uint32_t nt = std::max(top, h.col[h.row[v + 1] - 1]);
-              const uint64_t kk = (j - i + 1) <= 2 ? 2 : 4;
-              const uint32_t dv = h.row[v + 1] - h.row[v];
-              if (recs + items[j].llen > 64 || mem + dv > 64 ||
-                  (uint64_t(nt) - nb + 1) * kk > uint64_t(cap) * 32)
-                break;
-              base = nb;
-              top = nt;
-              recs += items[j].llen;
-              mem += dv;
-              ++j;
-            }
-            if (j - i > 1) {
-              const uint32_t cnt = uint32_t(j - i);
-              out.push_back(Item{uint32_t(gsub.size() / 4) | kHiBit, cnt, recs, a0.tag});
-              sd.insert(sd.end(), {base, cnt <= 2 ? 1u : 2u, mem, top});
-              for (uint64_t q = i; q < j; ++q) {
-                const uint32_t v = items[q].s;
-                grouped[v] = 1;
-                gsub.insert(gsub.end(),
-                            {items[q].lbeg, items[q].llen, h.row[v], h.row[v + 1] - h.row[v]});
-              }
-              i = j;
-              continue;
-            }
-          }
-          single(out, a0);
-          i = i + 1;
+      size_t n_out = 0, n_sd = 0, n_gsub = 0;
+      for (const Part& q : part) {
+        n_out += q.out.size();
+        n_sd += q.sd.size();
+        n_gsub += q.gsub.size();
+      }
+      out.reserve(n_out);
+      sd.reserve(n_sd);
+      gsub.reserve(n_gsub);
+      for (size_t pi = 0; pi < part.size(); ++pi) {
+        Part& q = part[pi];
+        const uint32_t gbase = uint32_t(gsub.size() / 4);
+        const uint64_t ibase = out.size();
+        for (Item it : q.out) {
+          if (it.s & kHiBit) it.s = ((it.s & kMaxIndex) + gbase) | kHiBit;
+          out.push_back(it);
         }
+        for (size_t k = 0; k < q.off.size(); ++k) off[gparts[pi] + k] = ibase + q.off[k];
+        sd.insert(sd.end(), q.sd.begin(), q.sd.end());
+        gsub.insert(gsub.end(), q.gsub.begin(), q.gsub.end());
+        Part().out.swap(q.out);
       }
       off[h.n_graphs] = out.size();
       items.swap(out);
