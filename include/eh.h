@@ -229,6 +229,15 @@ eh_status eh_build_trie_device(eh_ctx* ctx, const uint32_t* d_src, const uint32_
                                uint64_t n_edges, uint32_t n_vertices, const eh_build_opts* opts,
                                eh_trie** out);
 
+/* The batch trie of eh_build_batch, built on the GPU (as
+ * eh_build_trie_device): n_vertices and edge_off are host arrays as in
+ * eh_build_batch; d_src/d_dst are device arrays of local ids, graph g's pairs
+ * at [edge_off[g], edge_off[g+1]).  Same orderings and errors as
+ * eh_build_trie_device (an id >= its graph's n_vertices is EH_EINVAL). */
+eh_status eh_build_batch_device(eh_ctx* ctx, uint32_t n_graphs, const uint32_t* n_vertices,
+                                const uint64_t* edge_off, const uint32_t* d_src,
+                                const uint32_t* d_dst, const eh_build_opts* opts, eh_trie** out);
+
 eh_status eh_trie_info_get(const eh_trie* trie, eh_trie_info* out);
 /* Inspection: the host copy of a built trie, in the layout of
  * eh_host_trie_arrays (rank[n], row[n+1], col[m_plus], bs_off[n],

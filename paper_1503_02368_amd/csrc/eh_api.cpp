@@ -461,6 +461,67 @@ eh_status eh_build_trie_device(eh_ctx* ctx, const uint32_t* d_src, const uint32_
   return EH_OK;
 }
 
+eh_status eh_build_batch_device(eh_ctx* ctx, uint32_t n_graphs, const uint32_t* n_vertices,
+                                const uint64_t* edge_off, const uint32_t* d_src,
+                                const uint32_t* d_dst, const eh_build_opts* opts, eh_trie** out) {
+  if (!ctx || !out || !n_vertices || !edge_off || n_graphs == 0) return EH_EINVAL;
+  *out = nullptr;
+  if (edge_off[n_graphs] > edge_off[0] && (!d_src || !d_dst)) return EH_EINVAL;
+  if (opts && (opts->layout > EH_LAYOUT_BITSET_ALL || opts->order > EH_ORDER_STRONG_RUNS)) {
+    ctx->c.err = "unknown layout or node ordering";
+    return EH_EINVAL;
+  }
+  const BuildOpts o = resolve_opts(opts);
+  if (o.order != EH_ORDER_DEGREE && o.order != EH_ORDER_REV_DEGREE && o.order != EH_ORDER_INPUT) {
+    ctx->c.err = "traversal orderings (BFS, hybrid, strong runs) are built on the host";
+    return EH_EINVAL;
+  }
+  DeviceBatch b;
+  b.n_graphs = n_graphs;
+  b.n_vertices = n_vertices;
+  std::vector<uint64_t> eoff(size_t(n_graphs) + 1);
+  b.vbase.assign(size_t(n_graphs) + 1, 0);
+  uint64_t padded = 0;
+  for (uint32_t g = 0; g < n_graphs; ++g) {
+    if (edge_off[g + 1] < edge_off[g]) {
+      ctx->c.err = "edge_off is not monotone at graph " + std::to_string(g);
+      return EH_EINVAL;
+    }
+    eoff[g] = edge_off[g] - edge_off[0];
+    b.vbase[g] = uint32_t(std::min<uint64_t>(padded, kMaxIndex));
+    padded += (uint64_t(n_vertices[g]) + 31) & ~uint64_t(31);
+  }
+  eoff[n_graphs] = edge_off[n_graphs] - edge_off[0];
+  if (padded > kMaxIndex) {
+    ctx->c.err = "batch has more than 2^31-1 vertices";
+    return EH_EOVERFLOW;
+  }
+  b.vbase[n_graphs] = uint32_t(padded);
+  b.edge_off = eoff.data();
+  eh_trie* x = new (std::nothrow) eh_trie();
+  if (!x) return EH_ENOMEM;
+  x->t.ctx = &ctx->c;
+  eh_status st = hip_check(&ctx->c, hipSetDevice(ctx->c.device), "hipSetDevice");
+  if (st == EH_OK) {
+    try {
+      st = device_build(&ctx->c, d_src ? d_src + edge_off[0] : d_src,
+                        d_dst ? d_dst + edge_off[0] : d_dst, eoff[n_graphs], uint32_t(padded), o,
+                        x->t, &b);
+    } catch (const std::bad_alloc&) {
+      ctx->c.err = "host memory exhausted while building the batch";
+      st = EH_ENOMEM;
+    }
+  }
+  if (st != EH_OK) {
+    (void)hipStreamSynchronize(ctx->c.stream);
+    free_trie_device(x->t);
+    delete x;
+    return st;
+  }
+  *out = x;
+  return EH_OK;
+}
+
 eh_status eh_trie_host_arrays(const eh_trie* trie, uint32_t* rank, uint32_t* row, uint32_t* col,
                               uint32_t* bs_off, uint32_t* bs_base, uint32_t* bs_nw,
                               uint32_t* bs_words) {

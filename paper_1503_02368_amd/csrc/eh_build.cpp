@@ -414,7 +414,8 @@ eh_status host_build_batch(uint32_t n_graphs, const uint32_t* n_vertices, const 
         h.vert[vb + v] = vb + p.vert[v];
         h.row[vb + v] = eb + p.row[v];
         h.bs_off[vb + v] = p.bs_off[v] == kNoBitset ? kNoBitset : wb + p.bs_off[v];
-        h.bs_base[vb + v] = vb + p.bs_base[v];  // vb is a multiple of 32
+        // vb is a multiple of 32; a set without a bitset keeps base 0
+        h.bs_base[vb + v] = p.bs_off[v] == kNoBitset ? 0u : vb + p.bs_base[v];
         h.bs_nw[vb + v] = p.bs_nw[v];
       }
       for (uint32_t v = vb + p.n; v < h.g_vbase[g + 1]; ++v) {

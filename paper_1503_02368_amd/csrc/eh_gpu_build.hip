@@ -90,6 +90,93 @@ __global__ void __launch_bounds__(kB) k_pair_keys(const uint32_t* __restrict__ s
 // form runs: the first lane of each run within a wave adds the run's length
 // with one atomic (a hub's edges would otherwise serialise on one address).
 // Each wave walks 64 consecutive keys per step.
+// Batch form of k_pair_keys: pair i belongs to graph g with
+// edge_off[g] <= i < edge_off[g + 1]; its local ids become vbase[g] + id.
+__global__ void __launch_bounds__(kB) k_batch_pair_keys(const uint32_t* __restrict__ src,
+                                                        const uint32_t* __restrict__ dst,
+                                                        uint64_t m, uint32_t n_graphs,
+                                                        const unsigned long long* __restrict__ eoff,
+                                                        const uint32_t* __restrict__ vbase,
+                                                        const uint32_t* __restrict__ nv, uint32_t kb,
+                                                        unsigned long long* __restrict__ key,
+                                                        uint32_t* __restrict__ bad) {
+  for (uint64_t i = gtid(); i < m; i += gstride()) {
+    uint32_t lo = 0, hi = n_graphs;  // last g with eoff[g] <= i
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (eoff[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t g = lo;
+    uint32_t a = src[i], b = dst[i];
+    if (a >= nv[g] || b >= nv[g]) {
+      atomicOr(bad, 1u);
+      key[i] = kSentinel;
+      continue;
+    }
+    if (a == b) {
+      key[i] = kSentinel;
+      continue;
+    }
+    if (a > b) {
+      const uint32_t t = a;
+      a = b;
+      b = t;
+    }
+    key[i] = (static_cast<unsigned long long>(vbase[g] + a) << kb) | (vbase[g] + b);
+  }
+}
+
+// Graph of padded vertex v: the last g with vbase[g] <= v (empty graphs skipped).
+__device__ inline uint32_t graph_of(const uint32_t* vbase, uint32_t n_graphs, uint32_t v) {
+  uint32_t lo = 0, hi = n_graphs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (vbase[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Rank sort keys of a batch: graph, then degree; a graph's padding vertices
+// (the slots that round its rank range up to a multiple of 32) sort last.
+__global__ void __launch_bounds__(kB) k_batch_rank_keys(const uint32_t* __restrict__ deg,
+                                                        uint32_t n, uint32_t n_graphs,
+                                                        const uint32_t* __restrict__ vbase,
+                                                        const uint32_t* __restrict__ nv,
+                                                        unsigned long long* __restrict__ key,
+                                                        uint32_t* __restrict__ ids) {
+  for (uint64_t v = gtid(); v < n; v += gstride()) {
+    const uint32_t g = graph_of(vbase, n_graphs, uint32_t(v));
+    const bool pad = uint32_t(v) - vbase[g] >= nv[g];
+    key[v] = (static_cast<unsigned long long>(g) << 32) | (pad ? 0xFFFFFFFFu : deg[v]);
+    ids[v] = uint32_t(v);
+  }
+}
+
+// Ranks of a batch.  seq: vertices sorted by (graph, degree, id), or null for
+// the input order.  Graph g's ranks are [vbase[g], vbase[g] + n_g); padding
+// keeps rank = id.
+__global__ void __launch_bounds__(kB) k_batch_ranks(const uint32_t* __restrict__ seq, uint32_t n,
+                                                    uint32_t n_graphs,
+                                                    const uint32_t* __restrict__ vbase,
+                                                    const uint32_t* __restrict__ nv, uint32_t order,
+                                                    uint32_t* __restrict__ rank,
+                                                    uint32_t* __restrict__ vert) {
+  for (uint64_t p = gtid(); p < n; p += gstride()) {
+    const uint32_t v = seq ? seq[p] : uint32_t(p);
+    const uint32_t g = graph_of(vbase, n_graphs, v);
+    const uint32_t vb = vbase[g], nvg = nv[g];
+    uint32_t r;
+    if (v - vb >= nvg) r = v;
+    else if (order == EH_ORDER_DEGREE) r = uint32_t(p);
+    else if (order == EH_ORDER_REV_DEGREE) r = vb + nvg - 1 - (uint32_t(p) - vb);
+    else r = vb + nvg - 1 - (v - vb);
+    rank[v] = r;
+    vert[r] = v;
+  }
+}
+
 __global__ void __launch_bounds__(kB) k_degrees(const unsigned long long* __restrict__ key,
                                                 uint64_t m, uint32_t kb,
                                                 uint32_t* __restrict__ deg) {
@@ -292,7 +379,7 @@ eh_status download(Ctx* c, void* dst, const void* src, size_t bytes, const char*
 }  // namespace
 
 eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_raw,
-                       uint32_t n, const BuildOpts& opts, Trie& t) {
+                       uint32_t n, const BuildOpts& opts, Trie& t, const DeviceBatch* batch) {
   hipStream_t s = c->stream;
   if (n == 0 && m_raw) {
     c->err = "edges given for an empty vertex set";
@@ -303,8 +390,27 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
   const uint64_t kcap = opts.symmetric ? 2 * mr : mr;  // stored arcs fit 2 m <= 2 m_raw
   const uint32_t n1 = std::max<uint32_t>(n, 1);
   DevBuf keys_a, keys_b, tmp, deg, ids, deg_s, seq, rank, row, nw, base, off, bs_off, stats, cnt;
+  DevBuf b_eoff, b_vbase, b_nv, rk_in, rk_out;  // batch only
   Scratch sc(c);
   eh_status st;
+  const uint32_t G = batch ? batch->n_graphs : 1u;
+  if (batch) {
+    if ((st = sc.get(b_eoff, 8ull * (G + 1))) != EH_OK ||
+        (st = sc.get(b_vbase, 4ull * (G + 1))) != EH_OK || (st = sc.get(b_nv, 4ull * G)) != EH_OK ||
+        (st = sc.get(rk_in, 8ull * n1)) != EH_OK || (st = sc.get(rk_out, 8ull * n1)) != EH_OK)
+      return st;
+    if ((st = hip_check(c, hipMemcpyAsync(b_eoff.p, batch->edge_off, 8ull * (G + 1),
+                                          hipMemcpyHostToDevice, s), "upload edge offsets")) !=
+            EH_OK ||
+        (st = hip_check(c, hipMemcpyAsync(b_vbase.p, batch->vbase.data(), 4ull * (G + 1),
+                                          hipMemcpyHostToDevice, s), "upload graph bases")) !=
+            EH_OK ||
+        (st = hip_check(c, hipMemcpyAsync(b_nv.p, batch->n_vertices, 4ull * G,
+                                          hipMemcpyHostToDevice, s), "upload graph sizes")) !=
+            EH_OK ||
+        (st = hip_check(c, hipStreamSynchronize(s), "build sync")) != EH_OK)
+      return st;
+  }
   if ((st = sc.get(keys_a, 8 * kcap)) != EH_OK || (st = sc.get(keys_b, 8 * kcap)) != EH_OK ||
       (st = sc.get(deg, 4ull * n1)) != EH_OK || (st = sc.get(ids, 4ull * n1)) != EH_OK ||
       (st = sc.get(deg_s, 4ull * n1)) != EH_OK || (st = sc.get(seq, 4ull * n1)) != EH_OK ||
@@ -340,6 +446,14 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
                 "pair sort size")) != EH_OK)
     return st;
   need = std::max(need, b);
+  if (batch) {
+    if ((st = chk(rocprim::radix_sort_pairs(nullptr, b, ptr<unsigned long long>(rk_in),
+                                            ptr<unsigned long long>(rk_out), ptr<uint32_t>(ids),
+                                            ptr<uint32_t>(seq), size_t(n1), 0, 64, s),
+                  "batch rank sort size")) != EH_OK)
+      return st;
+    need = std::max(need, b);
+  }
   if ((st = chk(rocprim::exclusive_scan(nullptr, b, ptr<uint32_t>(nw),
                                         ptr<unsigned long long>(off), 0ull, size_t(n) + 1,
                                         rocprim::plus<unsigned long long>(), s),
@@ -355,8 +469,13 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
   unsigned long long* uniq = ka;
   unsigned long long* spare = kbuf;
   if (m_raw) {
-    hipLaunchKernelGGL(k_pair_keys, dim3(grid_of(m_raw)), dim3(kB), 0, s, d_src, d_dst, m_raw, n,
-                       kb, ka, ptr<uint32_t>(cnt) + 2);
+    if (batch)
+      hipLaunchKernelGGL(k_batch_pair_keys, dim3(grid_of(m_raw)), dim3(kB), 0, s, d_src, d_dst,
+                         m_raw, G, ptr<unsigned long long>(b_eoff), ptr<uint32_t>(b_vbase),
+                         ptr<uint32_t>(b_nv), kb, ka, ptr<uint32_t>(cnt) + 2);
+    else
+      hipLaunchKernelGGL(k_pair_keys, dim3(grid_of(m_raw)), dim3(kB), 0, s, d_src, d_dst, m_raw,
+                         n, kb, ka, ptr<uint32_t>(cnt) + 2);
     if ((st = chk(hipGetLastError(), "pair key kernel")) != EH_OK) return st;
     rocprim::double_buffer<unsigned long long> pairs(ka, kbuf);
     tmp_bytes = tmp.bytes;
@@ -376,7 +495,8 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
         (st = chk(hipStreamSynchronize(s), "build sync")) != EH_OK)
       return st;
     if (uint32_t(h_cnt[1])) {
-      c->err = "a vertex id is >= n = " + std::to_string(n);
+      c->err = batch ? std::string("a vertex id is >= its graph's vertex count")
+                     : "a vertex id is >= n = " + std::to_string(n);
       return EH_EINVAL;
     }
     unsigned long long last = 0;
@@ -401,7 +521,26 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
                        ptr<uint32_t>(deg));
   hipLaunchKernelGGL(k_iota, dim3(grid_of(n1)), dim3(kB), 0, s, ptr<uint32_t>(ids), n1);
   if ((st = dev_alloc(c, t.vert, 4ull * n1)) != EH_OK) return st;
-  if (opts.order == EH_ORDER_INPUT) {
+  if (batch) {
+    // ranks per graph: a stable sort by (graph, degree) keeps ids ascending
+    const uint32_t* order_seq = nullptr;
+    if (opts.order != EH_ORDER_INPUT) {
+      hipLaunchKernelGGL(k_batch_rank_keys, dim3(grid_of(n1)), dim3(kB), 0, s, ptr<uint32_t>(deg),
+                         n, G, ptr<uint32_t>(b_vbase), ptr<uint32_t>(b_nv),
+                         ptr<unsigned long long>(rk_in), ptr<uint32_t>(ids));
+      const unsigned gbits = 32u + (G > 1 ? 32u - uint32_t(__builtin_clz(G - 1)) : 1u);
+      tmp_bytes = tmp.bytes;
+      if ((st = chk(rocprim::radix_sort_pairs(tmp.p, tmp_bytes, ptr<unsigned long long>(rk_in),
+                                              ptr<unsigned long long>(rk_out), ptr<uint32_t>(ids),
+                                              ptr<uint32_t>(seq), size_t(n), 0, gbits, s),
+                    "batch degree sort")) != EH_OK)
+        return st;
+      order_seq = ptr<uint32_t>(seq);
+    }
+    hipLaunchKernelGGL(k_batch_ranks, dim3(grid_of(n1)), dim3(kB), 0, s, order_seq, n, G,
+                       ptr<uint32_t>(b_vbase), ptr<uint32_t>(b_nv), opts.order,
+                       ptr<uint32_t>(rank), ptr<uint32_t>(t.vert));
+  } else if (opts.order == EH_ORDER_INPUT) {
     hipLaunchKernelGGL(k_ranks, dim3(grid_of(n1)), dim3(kB), 0, s, ptr<uint32_t>(ids), n, 1u,
                        ptr<uint32_t>(rank), ptr<uint32_t>(t.vert));
   } else {
@@ -480,8 +619,8 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
   h.dmax = uint32_t(h_stat[1]);
   h.b_merge = h_stat[2];
   h.n_bs = n_bs;
-  h.n_graphs = 1;
-  h.g_vbase = {0, n};
+  h.n_graphs = G;
+  h.g_vbase = batch ? batch->vbase : std::vector<uint32_t>{0, n};
   h.symmetric = opts.symmetric != 0;
   h.rank.resize(n);
   h.vert.resize(n);

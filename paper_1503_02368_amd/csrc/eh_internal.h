@@ -77,11 +77,20 @@ eh_status host_build_batch(uint32_t n_graphs, const uint32_t* n_vertices, const 
                            HostTrie& h, std::string& err);
 
 struct Trie;
+// A batch for the GPU build: host arrays of the graphs' vertex counts and
+// pair offsets, and the padded first rank of each graph (multiples of 32).
+struct DeviceBatch {
+  uint32_t n_graphs = 0;
+  const uint32_t* n_vertices = nullptr;
+  const uint64_t* edge_off = nullptr;  // [n_graphs + 1]
+  std::vector<uint32_t> vbase;         // [n_graphs + 1]
+};
 // The same trie built on the GPU from device-resident raw pairs (orderings
 // that are sorts: degree, reverse degree, input), with its host copy.
 struct Ctx;
 eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_raw,
-                       uint32_t n, const BuildOpts& opts, Trie& t);
+                       uint32_t n, const BuildOpts& opts, Trie& t,
+                       const DeviceBatch* batch = nullptr);
 
 struct Tuning {
   uint32_t kernel = EH_KERNEL_STAGED;

@@ -40,6 +40,7 @@ SYMBOLS = [
     "eh_server_create", "eh_submit", "eh_poll", "eh_wait", "eh_server_drain", "eh_server_destroy",
     "eh_host_trie_build", "eh_host_trie_info", "eh_host_trie_arrays", "eh_host_trie_free",
     "eh_build_trie_device", "eh_trie_host_arrays", "eh_trie_device_arrays", "eh_count_lollipop",
+    "eh_build_batch_device",
 ]
 
 
@@ -145,6 +146,8 @@ def load():
             "eh_trie_host_arrays": [_vp, _u32p, _u32p, _u32p, _u32p, _u32p, _u32p, _u32p],
             "eh_trie_device_arrays": [_vp, _vp, _u32p, _u32p, _u32p, _u32p],
             "eh_count_lollipop": [_vp, _vp, _u64p],
+            "eh_build_batch_device": [_vp, ctypes.c_uint32, _u32p, _u64p, _vp, _vp,
+                                      ctypes.POINTER(_BuildOpts), ctypes.POINTER(_vp)],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -317,6 +320,27 @@ class Context:
                                                    _vp(d_dst.data_ptr()), d_src.numel(), int(n),
                                                    ctypes.byref(o), ctypes.byref(h)),
                     "build_trie_device")
+        return Trie(self, h)
+
+    def build_batch_device(self, batch, d_src, d_dst, layout=LAYOUT_HYBRID, tau=32.0, s_min=1,
+                           order=ORDER_DEGREE, symmetric=False) -> "Trie":
+        """The batch trie built on the GPU: sizes and offsets from `batch` (host),
+        local-id pairs from device tensors of 4-byte elements."""
+        import torch
+        for t in (d_src, d_dst):
+            if not t.is_cuda or t.element_size() != 4 or not t.is_contiguous():
+                raise ValueError("pairs must be contiguous 4-byte device tensors")
+        nv = _u32(batch.n_vertices)
+        off = np.ascontiguousarray(batch.edge_off, dtype=np.uint64)
+        if d_src.numel() < int(off[-1]) or d_dst.numel() < int(off[-1]):
+            raise ValueError("fewer pairs than edge_off names")
+        self.stream.wait_stream(torch.cuda.current_stream())
+        h = _vp()
+        o = _opts(layout, tau, s_min, order, symmetric)
+        self._check(self._lib.eh_build_batch_device(self._h, nv.size, _p32(nv), _p64(off),
+                                                    _vp(d_src.data_ptr()), _vp(d_dst.data_ptr()),
+                                                    ctypes.byref(o), ctypes.byref(h)),
+                    "build_batch_device")
         return Trie(self, h)
 
     def device_arrays(self, trie) -> dict:

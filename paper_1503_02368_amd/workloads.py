@@ -15,7 +15,7 @@ WORKLOADS = {
                       orders=["random", "degree", "rev_degree", "bfs", "hybrid", "strong_runs"],
                       seed=30, layout=1, tau=32.0),
     # trie construction, host against GPU, on R-MAT graphs
-    "build": dict(kind="build", scales=[20, 22], edge_factor=16, layout=1, tau=32.0),
+    "build": dict(kind="build", scales=[20, 22], edge_factor=16, layout=1, tau=32.0, batch=True),
     # the unpruned relation: triangles and Lollipop on R-MAT s20 in both directions
     "unpruned": dict(kind="unpruned", scale=20, edge_factor=16, seed=20, layout=1, tau=32.0),
     "served": dict(kind="served", gen="rmat", scale=22, edge_factor=16, seed=22, layout=1, tau=32.0),

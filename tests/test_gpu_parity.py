@@ -548,7 +548,8 @@ def order_truth(el, order):
         g = oracle.Graph.from_edgelist(el, order)
         t = g.triangles(rooted=True)
         off, _ = g.oriented()
-        dmax = int(np.diff(off.astype(np.int64)).max())
+        d = np.diff(off.astype(np.int64))
+        dmax = int(d.max()) if d.size else 0
         k = g.cliques4(rooted=True) if dmax <= 2048 else None
         _ORDER_TRUTH[key] = (t, k, dmax)
     return _ORDER_TRUTH[key]
@@ -841,6 +842,52 @@ def test_symmetric_batch_and_device_build(ctx, eh):
         assert e.value.status == eh.EH_ESTATE
     finally:
         pruned.free()
+
+
+def _degenerate_mix():
+    parts = [el for el, _, _ in DEGENERATE] + [inputs.rmat(9, 8, seed=5), inputs.complete(40)]
+    parts = parts + parts[::-1]
+    srcs, dsts, off, nv = [], [], [0], []
+    for g in parts:
+        srcs.append(g.src)
+        dsts.append(g.dst)
+        off.append(off[-1] + g.m_raw)
+        nv.append(g.n)
+    return inputs.BatchEdges(np.array(nv, np.uint32), np.array(off, np.uint64),
+                             np.concatenate(srcs), np.concatenate(dsts), "degenerate mix")
+
+
+@pytest.mark.parametrize("symmetric", [False, True])
+@pytest.mark.parametrize("order", ["degree", "rev_degree", "input"])
+def test_batch_device_build(ctx, eh, order, symmetric):
+    """The batch trie built on the GPU equals the host batch build array for
+    array, and its per-graph counts equal the oracle's."""
+    import torch
+    tune(ctx, **TUNINGS["staged_group"])
+    for b in (small_batch(70, seed=21), _degenerate_mix()):
+        say("batch device build", order, symmetric, b.name)
+        src = torch.from_numpy(np.ascontiguousarray(b.src).view(np.int32)).cuda()
+        dst = torch.from_numpy(np.ascontiguousarray(b.dst).view(np.int32)).cuda()
+        ht = ctx.build_batch(b, order=eh.ORDERS[order], symmetric=symmetric)
+        dt = ctx.build_batch_device(b, src, dst, order=eh.ORDERS[order], symmetric=symmetric)
+        try:
+            _same_trie(ctx, dt, ht, f"{b.name} {order} {symmetric}")
+            mult = 6 if symmetric else 1
+            want = np.array([mult * order_truth(b.graph(i), order)[0]["count"]
+                             for i in range(b.n_graphs)], np.uint64)
+            np.testing.assert_array_equal(ctx.count_batch(dt, eh.TRIANGLE), want)
+        finally:
+            dt.free()
+            ht.free()
+    # a local id at or beyond its graph's vertex count is refused
+    b = small_batch(5, seed=22)
+    bad_src = np.ascontiguousarray(b.src).copy()
+    bad_src[int(b.edge_off[2])] = b.n_vertices[2]  # graph 2's first pair names id n_2
+    src = torch.from_numpy(bad_src.view(np.int32)).cuda()
+    dst = torch.from_numpy(np.ascontiguousarray(b.dst).view(np.int32)).cuda()
+    with pytest.raises(eh.EHError) as e:
+        ctx.build_batch_device(b, src, dst)
+    assert e.value.status == eh.EH_EINVAL
 
 
 def test_out_degree_limits(ctx, eh):
