@@ -103,7 +103,7 @@ void free_trie_device(Trie& t) {
 // bsdesc.x is the absolute position of a set's first word in that buffer.
 eh_status upload_trie(Ctx* c, Trie& t) {
   const HostTrie& h = t.host;
-  const uint64_t W = h.bs_words.size();
+  const uint64_t W = h.n_words;
   if (h.m + W > kMaxIndex) {
     c->err = "edges plus bitset words exceed 2^31-1";
     return EH_EOVERFLOW;
@@ -536,6 +536,17 @@ eh_status eh_trie_host_arrays(const eh_trie* trie, uint32_t* rank, uint32_t* row
   put(bs_off, h.bs_off);
   put(bs_base, h.bs_base);
   put(bs_nw, h.bs_nw);
+  if (bs_words && h.words_on_device && h.n_words) {
+    // a GPU-built trie keeps its words on the device only
+    Ctx* c = trie->t.ctx;
+    eh_status st = hip_check(c, hipSetDevice(c->device), "hipSetDevice");
+    if (st == EH_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
+    if (st == EH_OK)
+      st = hip_check(c, hipMemcpy(bs_words, static_cast<const uint32_t*>(trie->t.col.p) + h.m,
+                                  sizeof(uint32_t) * h.n_words, hipMemcpyDeviceToHost),
+                     "download words");
+    return st;
+  }
   put(bs_words, h.bs_words);
   return EH_OK;
 }
@@ -546,7 +557,7 @@ eh_status eh_trie_device_arrays(eh_ctx* ctx, const eh_trie* trie, uint32_t* vdes
   Ctx* c = &ctx->c;
   const Trie& t = trie->t;
   const HostTrie& h = t.host;
-  const uint64_t W = h.bs_words.size();
+  const uint64_t W = h.n_words;
   eh_status st = hip_check(c, hipSetDevice(c->device), "hipSetDevice");
   if (st != EH_OK) return st;
   if ((st = hip_check(c, hipStreamSynchronize(c->stream), "stream sync")) != EH_OK) return st;
@@ -595,7 +606,7 @@ static void fill_info(const HostTrie& h, eh_trie_info* out) {
   out->n_graphs = h.n_graphs;
   out->m_plus = h.m;
   out->n_bitset_sets = h.n_bs;
-  out->bitset_words = h.bs_words.size();
+  out->bitset_words = h.n_words;
   out->device_bytes = 0;
   out->b_merge = h.b_merge;
   out->max_out_degree = h.dmax;

@@ -271,6 +271,7 @@ eh_status build_one(const uint32_t* src, const uint32_t* dst, uint64_t m_raw, ui
   h.bs_base.assign(n, 0);
   h.bs_nw.assign(n, 0);
   h.bs_words.clear();
+  h.n_words = 0;
   h.n_bs = 0;
   if (opts.layout != EH_LAYOUT_UINT) {
     uint64_t words = 0;
@@ -298,6 +299,7 @@ eh_status build_one(const uint32_t* src, const uint32_t* dst, uint64_t m_raw, ui
       h.n_bs++;
     }
     h.bs_words.assign(words, 0);
+    h.n_words = words;
     for (uint32_t u = 0; u < n; ++u) {
       if (h.bs_off[u] == kNoBitset) continue;
       uint32_t* w = h.bs_words.data() + h.bs_off[u];
@@ -395,6 +397,7 @@ eh_status host_build_batch(uint32_t n_graphs, const uint32_t* n_vertices, const 
   h.bs_base.resize(N);
   h.bs_nw.resize(N);
   h.bs_words.resize(W);
+  h.n_words = W;
   std::vector<uint64_t> ebase(n_graphs + 1, 0), wbase(n_graphs + 1, 0);
   for (uint32_t g = 0; g < n_graphs; ++g) {
     ebase[g + 1] = ebase[g] + parts[g].m;

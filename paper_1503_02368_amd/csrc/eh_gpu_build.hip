@@ -22,6 +22,7 @@
 #include <rocprim/rocprim.hpp>
 
 #include <algorithm>
+#include <thread>
 #include <vector>
 
 #include "eh_internal.h"
@@ -622,14 +623,20 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
   h.n_graphs = G;
   h.g_vbase = batch ? batch->vbase : std::vector<uint32_t>{0, n};
   h.symmetric = opts.symmetric != 0;
-  h.rank.resize(n);
-  h.vert.resize(n);
-  h.row.resize(size_t(n) + 1);
-  h.col.resize(m);
-  h.bs_off.resize(n);
-  h.bs_base.resize(n);
-  h.bs_nw.resize(n);
-  h.bs_words.resize(W);
+  {
+    // sizing a vector zero-fills and first-touches its pages: one thread per
+    // array, so the large ones (col) do not wait for the others
+    std::thread th[7] = {std::thread([&] { h.rank.resize(n); }),
+                         std::thread([&] { h.vert.resize(n); }),
+                         std::thread([&] { h.row.resize(size_t(n) + 1); }),
+                         std::thread([&] { h.col.resize(m); }),
+                         std::thread([&] { h.bs_off.resize(n); }),
+                         std::thread([&] { h.bs_base.resize(n); }),
+                         std::thread([&] { h.bs_nw.resize(n); })};
+    for (auto& x : th) x.join();
+  }
+  h.n_words = W;  // the words stay in the device list buffer: planning never reads them
+  h.words_on_device = true;
   if ((st = download(c, h.rank.data(), rank.p, 4ull * n, "download ranks")) != EH_OK ||
       (st = download(c, h.vert.data(), t.vert.p, 4ull * n, "download ids")) != EH_OK ||
       (st = download(c, h.row.data(), row.p, 4ull * (n + 1), "download rows")) != EH_OK ||
@@ -637,7 +644,6 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
       (st = download(c, h.bs_off.data(), bs_off.p, 4ull * n, "download word offsets")) != EH_OK ||
       (st = download(c, h.bs_base.data(), base.p, 4ull * n, "download bitset bases")) != EH_OK ||
       (st = download(c, h.bs_nw.data(), nw.p, 4ull * n, "download word counts")) != EH_OK ||
-      (st = download(c, h.bs_words.data(), col + m, 4ull * W, "download words")) != EH_OK ||
       (st = chk(hipStreamSynchronize(s), "build sync")) != EH_OK)
     return st;
   t.device_bytes = t.vdesc.bytes + t.col.bytes + t.bsdesc.bytes + t.vert.bytes;

@@ -50,7 +50,9 @@ struct HostTrie {
   std::vector<uint32_t> bs_off;      // [n] word offset or kNoBitset
   std::vector<uint32_t> bs_base;     // [n]
   std::vector<uint32_t> bs_nw;       // [n]
-  std::vector<uint32_t> bs_words;
+  std::vector<uint32_t> bs_words;    // empty when words_on_device
+  uint64_t n_words = 0;              // bitset words in total
+  bool words_on_device = false;      // GPU-built: the words live in the device list buffer only
   uint64_t n_bs = 0;
   // batch: graph g owns ranks [g_vbase[g], g_vbase[g+1]) and edges
   // [row[g_vbase[g]], row[g_vbase[g+1]])
