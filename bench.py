@@ -18,6 +18,7 @@ Prints one JSON line.  Workloads (--workload):
                     degree exponents 1.75 .. 3): triangle counting per ordering
   build             trie construction on the host and on the GPU, R-MAT scales
                     20 and 22, with the first (planning) and a repeated count
+  ablation          R-MAT scale 20 with layout / algorithm choices switched off
   unpruned          R-MAT scale 20 with both directions of every edge: ordered
                     triangles and the Lollipop query, beside pruned triangles
   served            resident R-MAT scale 22, Poisson stream of rooted
@@ -58,6 +59,35 @@ def load_tuning(name: str) -> dict:
     return {}
 
 
+def cpu_info() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def one_thread_rate(fn, n: int, budget_s: float) -> dict:
+    """The oracle on one thread: the whole workload if it fits the budget,
+    else the prefix of outer vertices that does (rate = edges visited / s)."""
+    t0 = time.perf_counter()
+    fn(threads=1, x_begin=0, x_end=max(1, n // 256))
+    est = (time.perf_counter() - t0) * 256
+    x_end = n if est <= budget_s else max(1, int(n * budget_s / est))
+    t0 = time.perf_counter()
+    res = fn(threads=1, x_begin=0, x_end=x_end)
+    t = time.perf_counter() - t0
+    return {"value": res["edges"] / t, "unit": "edges/s", "cores": 1,
+            "sample": "whole workload" if x_end == n else
+                      f"outer vertices of rank < {x_end} ({res['edges']} oriented edges)",
+            "seconds": t}
+
+
 def cpu_baseline(el, pattern: int, budget_s: float = 20.0) -> dict:
     """The oracle, as it stands, on this host's cores; full workload if it fits
     the time budget, else a prefix of outer vertices scaled by edges visited."""
@@ -80,7 +110,8 @@ def cpu_baseline(el, pattern: int, budget_s: float = 20.0) -> dict:
         t = statistics.median(times)
         return {"value": res["edges"] / t, "unit": "edges/s", "cores": threads, "kind": "oracle",
                 "sample": f"whole workload, median of 3 runs ({t:.3f} s each)", "count": res["count"],
-                "bytes": res["bytes"]}
+                "bytes": res["bytes"], "one_thread": one_thread_rate(fn, g.n, budget_s / 2),
+                **cpu_info()}
     frac = max(1.0 / 64, min(1.0, (budget_s / 2) / max(est_full, 1e-9)))
     x_end = max(1, int(g.n * frac))
     t0 = time.perf_counter()
@@ -89,7 +120,8 @@ def cpu_baseline(el, pattern: int, budget_s: float = 20.0) -> dict:
     del probe
     return {"value": res["edges"] / t, "unit": "edges/s", "cores": threads, "kind": "oracle",
             "sample": f"outer vertices of rank < {x_end} ({res['edges']} of {g.m} oriented edges), "
-                      f"{t:.2f} s", "count": None, "bytes": None}
+                      f"{t:.2f} s", "count": None, "bytes": None,
+            "one_thread": one_thread_rate(fn, g.n, budget_s / 2), **cpu_info()}
 
 
 def bench_graph(name, w, args, ctx, eh, torch):
@@ -148,11 +180,21 @@ def bench_graph(name, w, args, ctx, eh, torch):
     # algorithmic bytes: B_merge from the trie; B_K4 (needs every triangle) from the oracle's pass
     bytes_per_launch = info["b_merge"] if pattern == 3 else (cb or {}).get("bytes")
     if bytes_per_launch:
+        from paper_1503_02368_amd.calib import probe_gbs
         achieved = bytes_per_launch / (ms / 1e3) / 1e9
+        traffic = measured_traffic(name)
+        probe = probe_gbs()
         result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name),
+                              "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                               "algorithmic_bytes_per_launch": bytes_per_launch,
-                              "model": "B_merge" if pattern == 3 else "B_K4"}
+                              "model": "B_merge" if pattern == 3 else "B_K4",
+                              "achievable_read_gbs": probe["read"],
+                              "achievable_copy_gbs": probe["copy"]}
+        if traffic:
+            tg = traffic / (ms / 1e3) / 1e9
+            result["roofline"]["traffic_gbs"] = tg
+            result["roofline"]["traffic_frac_of_peak"] = tg / HBM_PEAK_GBS
+            result["roofline"]["traffic_frac_of_achievable_read"] = tg / probe["read"]
     if cb is not None:
         cb.pop("count", None)
         cb.pop("bytes", None)
@@ -193,6 +235,9 @@ def main():
     elif w["kind"] == "batch":
         from paper_1503_02368_amd import bench_extra
         res = bench_extra.bench_batch(name, w, args, ctx, eh, torch, METRIC)
+    elif w["kind"] == "ablation":
+        from paper_1503_02368_amd import bench_extra
+        res = bench_extra.bench_ablation(name, w, args, ctx, eh, torch, METRIC)
     elif w["kind"] == "unpruned":
         from paper_1503_02368_amd import bench_extra
         res = bench_extra.bench_unpruned(name, w, args, ctx, eh, torch, METRIC)

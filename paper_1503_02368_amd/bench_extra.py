@@ -17,6 +17,10 @@ Unpruned: the triangle and Lollipop queries on the full symmetric adjacency
 of R-MAT s20 (section 5.3 runs Lollipop on undirected data), beside triangle
 counting on the pruned trie.
 
+Ablation: R-MAT s20 triangle counting with the layout choices switched off
+one at a time (the paper's -R and -RA columns, section 5.4): uint-only and
+all-bitset layouts, no bitset reads, and the pairwise kernel with merges only.
+
 Served: a resident graph answers rooted count requests that arrive as an
 open-loop Poisson stream; latency is completion time (taken on the device
 step's completion) minus the request's scheduled arrival, so a backlog shows
@@ -596,6 +600,62 @@ def bench_unpruned(name, w, args, ctx, eh, torch, metric):
     if cpu:
         res["cpu_baseline"] = cpu
     return res
+
+
+# (name, layout, tau, tuning changes): each a performance choice; the count never changes
+ABLATION = [
+    ("hybrid, tuned", None, None, {}),
+    ("uint only (-R)", 0, 32.0, {}),
+    ("all bitset", 2, 32.0, {}),
+    ("hybrid layout, bitset words never streamed", None, None, {"use_bitsets": 0}),
+    ("pairwise, hybrid, merge or galloping", None, None, {"kernel": 2, "algo": 0, "group_lanes": 0}),
+    ("pairwise, uint only, merge only (-RA)", 0, 32.0,
+     {"kernel": 2, "algo": 1, "group_lanes": 0, "use_bitsets": 0}),
+]
+
+
+def bench_ablation(name, w, args, ctx, eh, torch, metric):
+    from paper_1503_02368_amd import inputs
+    el = inputs.rmat(w["scale"], w["edge_factor"], seed=w["seed"])
+    tuned = load_tuning("rmat20_triangles")
+    base = dict(ctx.get_tuning())
+    base.update(tuned.get("tuning", {}))
+    rows = []
+    counts = set()
+    cache = {}
+    for label, lay, tau, change in ABLATION:
+        lay = tuned.get("layout", 1) if lay is None else lay
+        tau = tuned.get("tau", 256.0) if tau is None else tau
+        if (lay, tau) not in cache:
+            for t in cache.values():
+                t.free()
+            cache.clear()
+            cache[(lay, tau)] = ctx.build_edgelist(el, layout=lay, tau=tau)
+        trie = cache[(lay, tau)]
+        ctx.set_tuning(**dict(base, **change))
+        ms, c = _time_counts(ctx, torch, trie, 3, args.steps, args.warmup)
+        counts.add(c)
+        info = trie.info
+        rows.append({"variant": label, "layout": ["uint", "hybrid", "bitset_all"][lay], "tau": tau,
+                     "ms": ms, "edges_per_s": info["m_plus"] / (ms / 1e3),
+                     "b_merge_per_s_gbs": info["b_merge"] / (ms / 1e3) / 1e9,
+                     "bitset_sets": info["n_bitset_sets"], "count": c})
+        log(f"[bench] {label:45s} {ms:8.3f} ms  count {c}")
+    for t in cache.values():
+        t.free()
+    ctx.set_tuning(**base)
+    ref = rows[0]["ms"]
+    for r in rows:
+        r["slowdown_vs_tuned"] = r["ms"] / ref
+    return {
+        "metric": metric, "value": rows[0]["edges_per_s"], "unit": "edges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ref, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded generator)",
+        "config": {"workload": name, "scale": w["scale"], "edge_factor": w["edge_factor"],
+                   "seed": w["seed"], "value_is": "the tuned hybrid row"},
+        "table": rows,
+        "same_count": len(counts) == 1,
+    }
 
 
 def serve_run(ctx, eh, trie, reqs, mode, policy=0):

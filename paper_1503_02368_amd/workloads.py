@@ -18,6 +18,8 @@ WORKLOADS = {
     "build": dict(kind="build", scales=[20, 22], edge_factor=16, layout=1, tau=32.0, batch=True),
     # the unpruned relation: triangles and Lollipop on R-MAT s20 in both directions
     "unpruned": dict(kind="unpruned", scale=20, edge_factor=16, seed=20, layout=1, tau=32.0),
+    # layout / algorithm ablation on R-MAT s20 (the paper's -R, -RA)
+    "ablation": dict(kind="ablation", scale=20, edge_factor=16, seed=20, layout=1, tau=256.0),
     "served": dict(kind="served", gen="rmat", scale=22, edge_factor=16, seed=22, layout=1, tau=32.0),
 }
 
