@@ -10,6 +10,7 @@
 // spanning [min, max]: base = min rounded down to a multiple of 32, words of
 // 32 bits.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <thread>
@@ -621,6 +622,19 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
   plan->group = (staging == EH_STAGE_TARGET && pattern == EH_TRIANGLE) ? tu.group : 1u;
   plan->g_item_off.assign(size_t(h.n_graphs) + 1, 0);
   const bool ub = tu.use_bitsets != 0;
+  // Target-staged triangle plans are built on the GPU, except grouped plans
+  // of a few large graphs (grouping walks each graph's items in one thread
+  // there) and when EH_HOST_PLAN is set.
+  if (staging == EH_STAGE_TARGET && pattern == EH_TRIANGLE && !std::getenv("EH_HOST_PLAN") &&
+      (plan->group <= 1 || h.n_graphs >= 256)) {
+    const uint32_t cap = tu.stage_words && tu.stage_words < kStageWords ? tu.stage_words
+                                                                         : kStageWords;
+    const eh_status st = device_plan_target(c, *t, *plan, chunk, ub, cap, plan->group);
+    if (st != EH_OK) return st;
+    *out = plan.get();
+    t->plans.push_back(std::move(plan));
+    return EH_OK;
+  }
   if (staging == EH_STAGE_TARGET) {
     if (!t->has_transpose) {
       // in-edges of each v, ascending in u: {u, position of v in N+(u)}.

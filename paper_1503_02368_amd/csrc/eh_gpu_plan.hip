@@ -1,0 +1,581 @@
+// Work-item plan for target staging, built on the GPU from the trie's device
+// arrays.  It follows the host planner (get_plan) rule for rule, so both give
+// the same items, descriptors, grouped members and segment records:
+//
+//   1. transpose: a radix sort of (target << 32 | position) keys orders the
+//      in-edges by target, then by source (positions grow with the source);
+//   2. items: per target v, the in-edges are cut greedily into items of about
+//      chunk_work streamed elements, each item charged |N+(v)| for staging
+//      (count, scan, write);
+//   3. grouping: per graph, consecutive small whole-vertex items share a wave
+//      under the host's limits (count, scan, write);
+//   4. records: per in-edge, the streamed part of N+(u) above v, as elements
+//      or as bitset words clipped to the staged bitmap's window.
+#include <cstring>
+#include <hip/hip_runtime.h>
+#include <rocprim/rocprim.hpp>
+
+#include <algorithm>
+#include <vector>
+
+#include "eh_internal.h"
+
+namespace eh {
+namespace {
+
+constexpr uint32_t kB = 256;
+
+uint32_t grid_of(uint64_t n) {
+  return uint32_t(std::max<uint64_t>(1, std::min<uint64_t>((n + kB - 1) / kB, 1u << 16)));
+}
+__device__ inline uint64_t gtid() { return uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; }
+__device__ inline uint64_t gstride() { return uint64_t(gridDim.x) * blockDim.x; }
+
+__global__ void __launch_bounds__(kB) k_fill_u32_plan(uint32_t* __restrict__ p, uint64_t n,
+                                                      uint32_t v) {
+  for (uint64_t i = gtid(); i < n; i += gstride()) p[i] = v;
+}
+
+__global__ void __launch_bounds__(kB) k_fill_u8_plan(uint8_t* __restrict__ p, uint64_t n) {
+  for (uint64_t i = gtid(); i < n; i += gstride()) p[i] = 0;
+}
+
+struct TrieView {
+  const uint2* vdesc;   // {row begin, out-degree | kHiBit if bitset}
+  const uint32_t* col;  // members, then words
+  const uint4* bsdesc;  // {first word, base, words, 0}, or null
+  uint32_t n;
+};
+
+__device__ inline uint32_t outdeg(const TrieView& t, uint32_t v) {
+  return t.vdesc[v].y & kMaxIndex;
+}
+
+// Streamed elements of the part of N+(u) above v = col[e] (the host's suffix_len).
+__device__ inline uint32_t suffix_len(const TrieView& t, uint32_t u, uint32_t e, bool ub) {
+  const uint2 du = t.vdesc[u];
+  const uint32_t len = du.x + (du.y & kMaxIndex) - e - 1;
+  if (ub && len && (du.y & kHiBit)) {
+    const uint4 b = t.bsdesc[u];
+    const uint32_t w0 = (t.col[e] + 1 - b.y) >> 5;
+    const uint32_t nw = w0 < b.z ? b.z - w0 : 0;
+    if (nw < len) return nw;
+  }
+  return len;
+}
+
+__global__ void __launch_bounds__(kB) k_sources(TrieView t, uint32_t* __restrict__ src) {
+  for (uint64_t u = gtid(); u < t.n; u += gstride()) {
+    const uint2 d = t.vdesc[u];
+    for (uint32_t e = d.x; e < d.x + (d.y & kMaxIndex); ++e) src[e] = uint32_t(u);
+  }
+}
+
+__global__ void __launch_bounds__(kB) k_target_keys(TrieView t, uint64_t m,
+                                                    unsigned long long* __restrict__ key) {
+  for (uint64_t e = gtid(); e < m; e += gstride())
+    key[e] = (static_cast<unsigned long long>(t.col[e]) << 32) | e;
+}
+
+// tin[k] = {u, e} of the k-th in-edge; trow[v] = first in-edge of v.
+__global__ void __launch_bounds__(kB) k_in_edges(const unsigned long long* __restrict__ key,
+                                                 uint64_t m, const uint32_t* __restrict__ src,
+                                                 uint2* __restrict__ tin) {
+  for (uint64_t k = gtid(); k < m; k += gstride()) {
+    const uint32_t e = uint32_t(key[k]);
+    tin[k] = make_uint2(src[e], e);
+  }
+}
+
+__global__ void __launch_bounds__(kB) k_in_rows(const unsigned long long* __restrict__ key,
+                                                uint64_t m, uint32_t n,
+                                                uint32_t* __restrict__ trow) {
+  for (uint64_t r = gtid(); r <= n; r += gstride()) {
+    const unsigned long long want = static_cast<unsigned long long>(r) << 32;
+    uint64_t lo = 0, hi = m;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (key[mid] < want) lo = mid + 1;
+      else hi = mid;
+    }
+    trow[r] = uint32_t(lo);
+  }
+}
+
+__device__ inline uint32_t graph_of(const uint32_t* vbase, uint32_t n_graphs, uint32_t v) {
+  uint32_t lo = 0, hi = n_graphs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (vbase[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Work of each in-edge for item cutting: its streamed elements plus 2.
+__global__ void __launch_bounds__(kB) k_in_edge_costs(TrieView t, const uint2* __restrict__ tin,
+                                                      uint64_t m, uint32_t ub,
+                                                      uint32_t* __restrict__ cost) {
+  for (uint64_t k = gtid(); k < m; k += gstride())
+    cost[k] = suffix_len(t, tin[k].x, tin[k].y, ub != 0) + 2;
+}
+
+// Greedy cut of v's in-edges (the host's split_items) over the precomputed
+// costs, which a thread reads contiguously: with `out` null it only counts
+// the items.
+__device__ inline uint32_t cut_items(const TrieView& t, const uint32_t* cost, const uint32_t* trow,
+                                     uint32_t v, uint32_t chunk, uint32_t tag, Item* out) {
+  const uint32_t dv = outdeg(t, v);
+  const uint32_t lb = trow[v], len = trow[v + 1] - lb;
+  if (dv == 0 || len == 0) return 0;
+  uint32_t n = 0, i = 0;
+  while (i < len) {
+    unsigned long long acc = dv;
+    uint32_t j = i;
+    while (j < len) {
+      acc += cost[lb + j];
+      ++j;
+      if (acc >= chunk) break;
+    }
+    if (out) out[n] = Item{v, lb + i, j - i, tag};
+    ++n;
+    i = j;
+  }
+  return n;
+}
+
+__global__ void __launch_bounds__(kB) k_count_items(TrieView t, const uint32_t* __restrict__ cost,
+                                                    const uint32_t* __restrict__ trow,
+                                                    uint32_t chunk, uint32_t* __restrict__ cnt) {
+  for (uint64_t v = gtid(); v <= t.n; v += gstride())
+    cnt[v] = v < t.n ? cut_items(t, cost, trow, uint32_t(v), chunk, 0, nullptr) : 0u;
+}
+
+__global__ void __launch_bounds__(kB) k_write_items(TrieView t, const uint32_t* __restrict__ cost,
+                                                    const uint32_t* __restrict__ trow,
+                                                    uint32_t chunk,
+                                                    const unsigned long long* __restrict__ ioff,
+                                                    const uint32_t* __restrict__ vbase,
+                                                    uint32_t n_graphs, Item* __restrict__ items,
+                                                    uint32_t* __restrict__ dmax) {
+  uint32_t mx = 0;
+  for (uint64_t v = gtid(); v < t.n; v += gstride()) {
+    if (ioff[v + 1] == ioff[v]) continue;
+    const uint32_t tag = n_graphs > 1 ? graph_of(vbase, n_graphs, uint32_t(v)) : 0u;
+    cut_items(t, cost, trow, uint32_t(v), chunk, tag, items + ioff[v]);
+    mx = max(mx, outdeg(t, uint32_t(v)));
+  }
+  if (mx) atomicMax(dmax, mx);
+}
+
+// Graph g's items start at the first item whose vertex is at or above vbase[g].
+__global__ void __launch_bounds__(kB) k_graph_offsets(const Item* __restrict__ items,
+                                                      uint64_t n_items,
+                                                      const uint32_t* __restrict__ vbase,
+                                                      uint32_t n_graphs,
+                                                      unsigned long long* __restrict__ goff) {
+  for (uint64_t g = gtid(); g <= n_graphs; g += gstride()) {
+    uint64_t lo = 0, hi = n_items;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (items[mid].s < vbase[g]) lo = mid + 1;
+      else hi = mid;
+    }
+    goff[g] = lo;
+  }
+}
+
+// Staged-set descriptor of a single vertex's item: {begin, length, min, max}.
+__device__ inline uint4 single_desc(const TrieView& t, uint32_t v) {
+  const uint2 d = t.vdesc[v];
+  const uint32_t len = d.y & kMaxIndex;
+  return make_uint4(d.x, len, t.col[d.x], t.col[d.x + len - 1]);
+}
+
+__global__ void __launch_bounds__(kB) k_single_descs(TrieView t, const Item* __restrict__ items,
+                                                     uint64_t n_items, uint4* __restrict__ sd) {
+  for (uint64_t i = gtid(); i < n_items; i += gstride()) sd[i] = single_desc(t, items[i].s);
+}
+
+// Per item, what the grouping pass reads: {|N+(v)| | 2^31 if the item holds
+// all of v's in-edges, min N+(v), max N+(v), in-edges of the item}.
+__global__ void __launch_bounds__(kB) k_item_info(TrieView t, const Item* __restrict__ items,
+                                                  uint64_t n_items,
+                                                  const uint32_t* __restrict__ trow,
+                                                  uint4* __restrict__ info) {
+  for (uint64_t i = gtid(); i < n_items; i += gstride()) {
+    const Item it = items[i];
+    const uint2 d = t.vdesc[it.s];
+    const uint32_t dv = d.y & kMaxIndex;
+    const bool whole = it.lbeg == trow[it.s] && it.llen == trow[it.s + 1] - trow[it.s];
+    info[i] = make_uint4(dv | (whole ? kHiBit : 0u), t.col[d.x], t.col[d.x + dv - 1], it.llen);
+  }
+}
+
+// One graph's grouping pass (the host's rule) over the item facts, read
+// contiguously: with the outputs null it only counts output items and grouped
+// members.
+__device__ inline void group_graph(const TrieView& t, const Item* items, const uint4* info,
+                                   uint64_t i0, uint64_t i1, uint32_t group, uint32_t cap,
+                                   uint64_t* n_out, uint64_t* n_mem, Item* out, uint4* sd,
+                                   uint4* gsub, uint64_t gsub_base, uint8_t* grouped) {
+  uint64_t no = 0, nm = 0;
+  for (uint64_t i = i0; i < i1;) {
+    const uint4 f0 = info[i];
+    uint64_t j = i + 1;
+    if (f0.x & kHiBit) {
+      uint32_t base = f0.y, top = f0.z;
+      uint32_t recs = f0.w, mem = f0.x & kMaxIndex;
+      while (j < i1 && j - i < group && (info[j].x & kHiBit)) {
+        const uint4 f = info[j];
+        const uint32_t dv = f.x & kMaxIndex;
+        const uint32_t nb = min(base, f.y);
+        const uint32_t nt = max(top, f.z);
+        const uint64_t kk = (j - i + 1) <= 2 ? 2 : 4;
+        if (recs + f.w > 64 || mem + dv > 64 || (uint64_t(nt) - nb + 1) * kk > uint64_t(cap) * 32)
+          break;
+        base = nb;
+        top = nt;
+        recs += f.w;
+        mem += dv;
+        ++j;
+      }
+      if (j - i > 1) {
+        const uint32_t cnt = uint32_t(j - i);
+        if (out) {
+          out[no] = Item{uint32_t((gsub_base + nm)) | kHiBit, cnt, recs, items[i].tag};
+          sd[no] = make_uint4(base, cnt <= 2 ? 1u : 2u, mem, top);
+          for (uint64_t q = i; q < j; ++q) {
+            const uint32_t v = items[q].s;
+            const uint2 d = t.vdesc[v];
+            grouped[v] = 1;
+            gsub[nm + (q - i)] = make_uint4(items[q].lbeg, items[q].llen, d.x, d.y & kMaxIndex);
+          }
+        }
+        ++no;
+        nm += j - i;
+        i = j;
+        continue;
+      }
+    }
+    if (out) {
+      out[no] = items[i];
+      sd[no] = single_desc(t, items[i].s);
+    }
+    ++no;
+    i = i + 1;
+  }
+  *n_out = no;
+  *n_mem = nm;
+}
+
+__global__ void __launch_bounds__(kB) k_group_count(TrieView t, const Item* __restrict__ items,
+                                                    const uint4* __restrict__ info,
+                                                    const unsigned long long* __restrict__ goff,
+                                                    uint32_t n_graphs, uint32_t group, uint32_t cap,
+                                                    unsigned long long* __restrict__ n_out,
+                                                    unsigned long long* __restrict__ n_mem) {
+  for (uint64_t g = gtid(); g <= n_graphs; g += gstride()) {
+    uint64_t no = 0, nm = 0;
+    if (g < n_graphs)
+      group_graph(t, items, info, goff[g], goff[g + 1], group, cap, &no, &nm, nullptr, nullptr,
+                  nullptr, 0, nullptr);
+    n_out[g] = no;
+    n_mem[g] = nm;
+  }
+}
+
+__global__ void __launch_bounds__(kB) k_group_write(TrieView t, const Item* __restrict__ items,
+                                                    const uint4* __restrict__ info,
+                                                    const unsigned long long* __restrict__ goff,
+                                                    uint32_t n_graphs, uint32_t group, uint32_t cap,
+                                                    const unsigned long long* __restrict__ o_off,
+                                                    const unsigned long long* __restrict__ m_off,
+                                                    Item* __restrict__ out, uint4* __restrict__ sd,
+                                                    uint4* __restrict__ gsub,
+                                                    uint8_t* __restrict__ grouped) {
+  for (uint64_t g = gtid(); g < n_graphs; g += gstride()) {
+    uint64_t no = 0, nm = 0;
+    group_graph(t, items, info, goff[g], goff[g + 1], group, cap, &no, &nm, out + o_off[g],
+                sd + o_off[g], gsub + m_off[g], m_off[g], grouped);
+  }
+}
+
+// The host's segment record per in-edge k (target v = col[e]): {start |
+// kHiBit for words, length | word offset << 16}; *wide flags a field beyond
+// 16 bits.
+__global__ void __launch_bounds__(kB) k_records(TrieView t, const unsigned long long* __restrict__ key,
+                                                const uint2* __restrict__ tin, uint64_t m,
+                                                const uint8_t* __restrict__ grouped, uint32_t ub,
+                                                uint32_t cap, uint2* __restrict__ rec,
+                                                uint32_t* __restrict__ wide) {
+  for (uint64_t k = gtid(); k < m; k += gstride()) {
+    const uint32_t v = uint32_t(key[k] >> 32);
+    const uint32_t u = tin[k].x, e = tin[k].y;
+    const uint2 du = t.vdesc[u], dv = t.vdesc[v];
+    const uint32_t len = du.x + (du.y & kMaxIndex) - e - 1;
+    uint32_t sb = e + 1, n = len, sm = 0;
+    const uint32_t lv = dv.y & kMaxIndex;
+    if (ub && len && !grouped[v] && (du.y & kHiBit) && lv > 0) {
+      const uint32_t lo_al = t.col[dv.x] & ~31u, hi = t.col[dv.x + lv - 1];
+      if (hi - lo_al < cap * 32u) {
+        const uint4 b = t.bsdesc[u];
+        const uint32_t w0 = (v + 1 - b.y) >> 5;
+        const int64_t nw = w0 < b.z ? int64_t(b.z - w0) : 0;
+        const int64_t off = int64_t((b.y >> 5) + w0) - int64_t(lo_al >> 5);
+        const int64_t first = off < 0 ? -off : 0;
+        const int64_t last = min(nw, int64_t(cap) - off);
+        const int64_t words = last > first ? last - first : 0;
+        if (words < int64_t(len)) {
+          sb = (b.x + w0 + uint32_t(first)) | kHiBit;
+          n = uint32_t(words);
+          sm = words ? uint32_t(off + first) : 0u;
+        }
+      }
+    }
+    if (n > 0xFFFFu || sm > 0xFFFFu) {
+      atomicOr(wide, 1u);
+      continue;
+    }
+    rec[k] = make_uint2(sb, n | (sm << 16));
+  }
+}
+
+template <class T>
+T* ptr(DevBuf& b) {
+  return static_cast<T*>(b.p);
+}
+
+struct Scratch {
+  Ctx* c;
+  std::vector<DevBuf*> bufs;
+  explicit Scratch(Ctx* ctx) : c(ctx) {}
+  eh_status get(DevBuf& b, size_t bytes) {
+    bufs.push_back(&b);
+    return dev_alloc(c, b, bytes);
+  }
+  ~Scratch() {
+    (void)hipStreamSynchronize(c->stream);
+    for (DevBuf* b : bufs) dev_free(c, *b);
+  }
+};
+
+}  // namespace
+
+eh_status device_plan_target(Ctx* c, Trie& tr, Plan& plan, uint32_t chunk, bool ub, uint32_t cap,
+                             uint32_t group) {
+  const HostTrie& h = tr.host;
+  hipStream_t s = c->stream;
+  const uint32_t n = h.n, G = h.n_graphs;
+  const uint64_t m = h.m;
+  const uint64_t m1 = std::max<uint64_t>(m, 1);
+  TrieView tv{static_cast<const uint2*>(tr.vdesc.p), static_cast<const uint32_t*>(tr.col.p),
+              h.n_bs ? static_cast<const uint4*>(tr.bsdesc.p) : nullptr, n};
+  DevBuf src, key_a, key_b, tin, trow, cnt, ioff, items, vbase, goff, small, tmp;
+  DevBuf n_out, n_mem, o_off, m_off, grouped, cost, info;
+  Scratch sc(c);
+  eh_status st;
+  auto chk = [&](hipError_t e, const char* what) { return hip_check(c, e, what); };
+  if ((st = sc.get(src, 4 * m1)) != EH_OK || (st = sc.get(key_a, 8 * m1)) != EH_OK ||
+      (st = sc.get(key_b, 8 * m1)) != EH_OK || (st = sc.get(tin, 8 * m1)) != EH_OK ||
+      (st = sc.get(trow, 4ull * (n + 1))) != EH_OK || (st = sc.get(cnt, 4ull * (n + 1))) != EH_OK ||
+      (st = sc.get(ioff, 8ull * (n + 1))) != EH_OK || (st = sc.get(vbase, 4ull * (G + 1))) != EH_OK ||
+      (st = sc.get(goff, 8ull * (G + 1))) != EH_OK || (st = sc.get(small, 64)) != EH_OK ||
+      (st = sc.get(grouped, std::max<uint32_t>(n, 1))) != EH_OK ||
+      (st = sc.get(cost, 4 * m1)) != EH_OK)
+    return st;
+  const unsigned key_bits = 32u + (n > 1 ? 32u - uint32_t(__builtin_clz(n - 1)) : 1u);
+  size_t need = 0, b = 0;
+  rocprim::double_buffer<unsigned long long> db(ptr<unsigned long long>(key_a),
+                                                ptr<unsigned long long>(key_b));
+  if ((st = chk(rocprim::radix_sort_keys(nullptr, b, db, size_t(m1), 0, key_bits, s),
+                "plan sort size")) != EH_OK)
+    return st;
+  need = std::max(need, b);
+  const uint64_t gcap = uint64_t(G) + 1;
+  if ((st = chk(rocprim::exclusive_scan(nullptr, b, ptr<uint32_t>(cnt),
+                                        ptr<unsigned long long>(ioff), 0ull, size_t(n) + 1,
+                                        rocprim::plus<unsigned long long>(), s),
+                "plan scan size")) != EH_OK)
+    return st;
+  need = std::max(need, b);
+  if ((st = chk(rocprim::exclusive_scan(nullptr, b, ptr<unsigned long long>(goff),
+                                        ptr<unsigned long long>(goff), 0ull, size_t(gcap),
+                                        rocprim::plus<unsigned long long>(), s),
+                "plan scan size")) != EH_OK)
+    return st;
+  need = std::max(need, b);
+  if ((st = sc.get(tmp, need)) != EH_OK) return st;
+  if ((st = chk(hipMemcpyAsync(vbase.p, h.g_vbase.data(), 4ull * (G + 1), hipMemcpyHostToDevice, s),
+                "upload graph bases")) != EH_OK)
+    return st;
+  hipLaunchKernelGGL(k_fill_u32_plan, dim3(1), dim3(kB), 0, s, ptr<uint32_t>(small), uint64_t(16),
+                     0u);
+
+  // 1. transpose
+  unsigned long long* sorted = ptr<unsigned long long>(key_a);
+  if (m) {
+    hipLaunchKernelGGL(k_sources, dim3(grid_of(n)), dim3(kB), 0, s, tv, ptr<uint32_t>(src));
+    hipLaunchKernelGGL(k_target_keys, dim3(grid_of(m)), dim3(kB), 0, s, tv, m,
+                       ptr<unsigned long long>(key_a));
+    size_t tb = tmp.bytes;
+    if ((st = chk(rocprim::radix_sort_keys(tmp.p, tb, db, size_t(m), 0, key_bits, s),
+                  "in-edge sort")) != EH_OK)
+      return st;
+    sorted = db.current();
+    hipLaunchKernelGGL(k_in_edges, dim3(grid_of(m)), dim3(kB), 0, s, sorted, m,
+                       ptr<uint32_t>(src), ptr<uint2>(tin));
+  }
+  hipLaunchKernelGGL(k_in_rows, dim3(grid_of(uint64_t(n) + 1)), dim3(kB), 0, s, sorted, m, n,
+                     ptr<uint32_t>(trow));
+
+  // 2. items
+  if (m)
+    hipLaunchKernelGGL(k_in_edge_costs, dim3(grid_of(m)), dim3(kB), 0, s, tv, ptr<uint2>(tin), m,
+                       ub ? 1u : 0u, ptr<uint32_t>(cost));
+  hipLaunchKernelGGL(k_count_items, dim3(grid_of(uint64_t(n) + 1)), dim3(kB), 0, s, tv,
+                     ptr<uint32_t>(cost), ptr<uint32_t>(trow), chunk, ptr<uint32_t>(cnt));
+  size_t tb = tmp.bytes;
+  if ((st = chk(rocprim::exclusive_scan(tmp.p, tb, ptr<uint32_t>(cnt),
+                                        ptr<unsigned long long>(ioff), 0ull, size_t(n) + 1,
+                                        rocprim::plus<unsigned long long>(), s),
+                "item scan")) != EH_OK)
+    return st;
+  unsigned long long n_items = 0;
+  if ((st = chk(hipMemcpyAsync(&n_items, ptr<unsigned long long>(ioff) + n, 8,
+                               hipMemcpyDeviceToHost, s), "read item count")) != EH_OK ||
+      (st = chk(hipStreamSynchronize(s), "plan sync")) != EH_OK)
+    return st;
+  if ((st = sc.get(items, sizeof(Item) * std::max<uint64_t>(n_items, 1))) != EH_OK) return st;
+  hipLaunchKernelGGL(k_write_items, dim3(grid_of(n)), dim3(kB), 0, s, tv, ptr<uint32_t>(cost),
+                     ptr<uint32_t>(trow), chunk, ptr<unsigned long long>(ioff),
+                     ptr<uint32_t>(vbase), G, ptr<Item>(items), ptr<uint32_t>(small));
+  hipLaunchKernelGGL(k_graph_offsets, dim3(grid_of(gcap)), dim3(kB), 0, s, ptr<Item>(items),
+                     uint64_t(n_items), ptr<uint32_t>(vbase), G, ptr<unsigned long long>(goff));
+  if ((st = chk(hipGetLastError(), "plan kernels")) != EH_OK) return st;
+
+  // 3. grouping (or one descriptor per item)
+  uint64_t n_final = n_items, n_members = 0;
+  DevBuf out_items, sd, gsub;
+  std::vector<unsigned long long> g_off(gcap);
+  hipLaunchKernelGGL(k_fill_u8_plan, dim3(grid_of(n)), dim3(kB), 0, s, ptr<uint8_t>(grouped),
+                     uint64_t(std::max<uint32_t>(n, 1)));
+  if (group > 1) {
+    if ((st = sc.get(n_out, 8 * gcap)) != EH_OK || (st = sc.get(n_mem, 8 * gcap)) != EH_OK ||
+        (st = sc.get(o_off, 8 * gcap)) != EH_OK || (st = sc.get(m_off, 8 * gcap)) != EH_OK ||
+        (st = sc.get(info, 16 * std::max<uint64_t>(n_items, 1))) != EH_OK)
+      return st;
+    if (n_items)
+      hipLaunchKernelGGL(k_item_info, dim3(grid_of(n_items)), dim3(kB), 0, s, tv, ptr<Item>(items),
+                         uint64_t(n_items), ptr<uint32_t>(trow), ptr<uint4>(info));
+    hipLaunchKernelGGL(k_group_count, dim3(grid_of(gcap)), dim3(kB), 0, s, tv, ptr<Item>(items),
+                       ptr<uint4>(info), ptr<unsigned long long>(goff), G, group, cap,
+                       ptr<unsigned long long>(n_out), ptr<unsigned long long>(n_mem));
+    tb = tmp.bytes;
+    if ((st = chk(rocprim::exclusive_scan(tmp.p, tb, ptr<unsigned long long>(n_out),
+                                          ptr<unsigned long long>(o_off), 0ull, size_t(gcap),
+                                          rocprim::plus<unsigned long long>(), s),
+                  "group scan")) != EH_OK)
+      return st;
+    tb = tmp.bytes;
+    if ((st = chk(rocprim::exclusive_scan(tmp.p, tb, ptr<unsigned long long>(n_mem),
+                                          ptr<unsigned long long>(m_off), 0ull, size_t(gcap),
+                                          rocprim::plus<unsigned long long>(), s),
+                  "group scan")) != EH_OK)
+      return st;
+    unsigned long long tot[2] = {0, 0};
+    if ((st = chk(hipMemcpyAsync(&tot[0], ptr<unsigned long long>(o_off) + G, 8,
+                                 hipMemcpyDeviceToHost, s), "read group count")) != EH_OK ||
+        (st = chk(hipMemcpyAsync(&tot[1], ptr<unsigned long long>(m_off) + G, 8,
+                                 hipMemcpyDeviceToHost, s), "read member count")) != EH_OK ||
+        (st = chk(hipStreamSynchronize(s), "plan sync")) != EH_OK)
+      return st;
+    n_final = tot[0];
+    n_members = tot[1];
+    if (n_members > kMaxIndex) {
+      c->err = "grouped members exceed 2^31-1";
+      return EH_EOVERFLOW;
+    }
+    if ((st = dev_alloc(c, out_items, sizeof(Item) * std::max<uint64_t>(n_final, 1))) != EH_OK ||
+        (st = dev_alloc(c, sd, 16 * std::max<uint64_t>(n_final, 1))) != EH_OK ||
+        (st = dev_alloc(c, gsub, 16 * std::max<uint64_t>(n_members, 1))) != EH_OK) {
+      dev_free(c, out_items);
+      dev_free(c, sd);
+      dev_free(c, gsub);
+      return st;
+    }
+    hipLaunchKernelGGL(k_group_write, dim3(grid_of(G)), dim3(kB), 0, s, tv, ptr<Item>(items),
+                       ptr<uint4>(info), ptr<unsigned long long>(goff), G, group, cap,
+                       ptr<unsigned long long>(o_off), ptr<unsigned long long>(m_off),
+                       ptr<Item>(out_items), ptr<uint4>(sd), ptr<uint4>(gsub),
+                       ptr<uint8_t>(grouped));
+    if ((st = chk(hipMemcpyAsync(g_off.data(), o_off.p, 8 * gcap, hipMemcpyDeviceToHost, s),
+                  "read graph offsets")) != EH_OK) {
+      dev_free(c, out_items);
+      dev_free(c, sd);
+      dev_free(c, gsub);
+      return st;
+    }
+    g_off[G] = n_final;
+  } else {
+    // the item list itself is the plan's; only the descriptors are added
+    out_items = items;
+    items = DevBuf();
+    if ((st = dev_alloc(c, sd, 16 * std::max<uint64_t>(n_final, 1))) != EH_OK ||
+        (st = dev_alloc(c, gsub, 16)) != EH_OK) {
+      dev_free(c, out_items);
+      dev_free(c, sd);
+      dev_free(c, gsub);
+      return st;
+    }
+    if (n_final)
+      hipLaunchKernelGGL(k_single_descs, dim3(grid_of(n_final)), dim3(kB), 0, s, tv,
+                         ptr<Item>(out_items), uint64_t(n_final), ptr<uint4>(sd));
+    if ((st = chk(hipMemcpyAsync(g_off.data(), goff.p, 8 * gcap, hipMemcpyDeviceToHost, s),
+                  "read graph offsets")) != EH_OK) {
+      dev_free(c, out_items);
+      dev_free(c, sd);
+      dev_free(c, gsub);
+      return st;
+    }
+  }
+
+  // 4. records
+  DevBuf rec;
+  if ((st = dev_alloc(c, rec, 8 * m1)) != EH_OK) {
+    dev_free(c, out_items);
+    dev_free(c, sd);
+    dev_free(c, gsub);
+    return st;
+  }
+  if (m)
+    hipLaunchKernelGGL(k_records, dim3(grid_of(m)), dim3(kB), 0, s, tv, sorted, ptr<uint2>(tin), m,
+                       ptr<uint8_t>(grouped), ub ? 1u : 0u, cap, ptr<uint2>(rec),
+                       ptr<uint32_t>(small) + 1);
+  uint32_t flags[2] = {0, 0};
+  st = chk(hipGetLastError(), "plan kernels");
+  if (st == EH_OK)
+    st = chk(hipMemcpyAsync(flags, small.p, 8, hipMemcpyDeviceToHost, s), "read plan flags");
+  if (st == EH_OK) st = chk(hipStreamSynchronize(s), "plan sync");
+  if (st == EH_OK && flags[1]) {
+    c->err = "segment record field beyond 16 bits";
+    st = EH_EOVERFLOW;
+  }
+  if (st != EH_OK) {
+    dev_free(c, out_items);
+    dev_free(c, sd);
+    dev_free(c, gsub);
+    dev_free(c, rec);
+    return st;
+  }
+  plan.items = out_items;
+  plan.sdesc = sd;
+  plan.rec = rec;
+  plan.gsub = gsub;
+  plan.n_items = n_final;
+  plan.item_dmax = flags[0];
+  plan.g_item_off.assign(g_off.begin(), g_off.end());
+  return EH_OK;
+}
+
+}  // namespace eh

@@ -235,6 +235,11 @@ eh_status launch_4cliques(Ctx* c, hipStream_t s, const LaunchArgs& a, uint32_t k
                           uint32_t waves_per_cu);
 eh_status launch_scatter_roots(Ctx* c, hipStream_t s, const unsigned long long* by_rank,
                                const uint32_t* vert, unsigned long long* by_id, uint32_t n);
+// The target-staging plan of a triangle count built on the GPU from the
+// trie's device arrays (items, descriptors, grouped members, records), equal
+// to the host planner's.
+eh_status device_plan_target(Ctx* c, Trie& t, Plan& plan, uint32_t chunk, bool ub, uint32_t cap,
+                             uint32_t group);
 // out[0] += sum over ranks r of t_by_id[vert[r]] * |N(r)| (Lollipop COUNT).
 eh_status launch_degree_weighted_sum(Ctx* c, hipStream_t s, const unsigned long long* t_by_id,
                                      const uint32_t* vert, const uint2* vdesc, uint32_t n,

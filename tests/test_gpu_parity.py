@@ -890,6 +890,30 @@ def test_batch_device_build(ctx, eh, order, symmetric):
     assert e.value.status == eh.EH_EINVAL
 
 
+def test_host_planner_path(ctx, eh, monkeypatch):
+    """Target-staged triangle plans are built on the GPU unless EH_HOST_PLAN is
+    set; the host planner (kept for grouped plans of a few large graphs) must
+    give the same counts."""
+    monkeypatch.setenv("EH_HOST_PLAN", "1")
+    for tname in ("staged_target", "staged_lean", "staged_group", "staged_group_lean"):
+        tune(ctx, **TUNINGS[tname])
+        for el in ZOO[-8:]:
+            T, _, _ = truth(el)
+            trie = ctx.build_edgelist(el)
+            try:
+                assert ctx.count_triangles(trie) == T, (tname, el.name)
+            finally:
+                trie.free()
+        b = small_batch(50, seed=23)
+        want = np.array([oracle.Graph.from_edgelist(b.graph(i)).triangles()["count"]
+                         for i in range(b.n_graphs)], np.uint64)
+        trie = ctx.build_batch(b)
+        try:
+            np.testing.assert_array_equal(ctx.count_batch(trie, eh.TRIANGLE), want)
+        finally:
+            trie.free()
+
+
 def test_out_degree_limits(ctx, eh):
     """K_2050: triangles at out-degree 2049 (C(n, 3)); the 4-clique kernel's
     S list holds at most 2048 entries, so its count is refused with
