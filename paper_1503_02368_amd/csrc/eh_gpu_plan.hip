@@ -120,22 +120,33 @@ __global__ void __launch_bounds__(kB) k_in_edge_costs(TrieView t, const uint2* _
     cost[k] = suffix_len(t, tin[k].x, tin[k].y, ub != 0) + 2;
 }
 
-// Greedy cut of v's in-edges (the host's split_items) over the precomputed
-// costs, which a thread reads contiguously: with `out` null it only counts
-// the items.
-__device__ inline uint32_t cut_items(const TrieView& t, const uint32_t* cost, const uint32_t* trow,
-                                     uint32_t v, uint32_t chunk, uint32_t tag, Item* out) {
+// Greedy cut of v's in-edges (the host's split_items): an item starting at
+// in-edge i, charged |N+(v)| for staging, ends after the first in-edge at
+// which its work reaches chunk.  Costs are positive, so with Q the inclusive
+// prefix of the costs that end is a lower bound on Q: one binary search per
+// item instead of a walk.  With `out` null it only counts the items.
+__device__ inline uint32_t cut_items(const TrieView& t, const unsigned long long* Q,
+                                     const uint32_t* trow, uint32_t v, uint32_t chunk,
+                                     uint32_t tag, Item* out) {
   const uint32_t dv = outdeg(t, v);
   const uint32_t lb = trow[v], len = trow[v + 1] - lb;
   if (dv == 0 || len == 0) return 0;
   uint32_t n = 0, i = 0;
   while (i < len) {
-    unsigned long long acc = dv;
-    uint32_t j = i;
-    while (j < len) {
-      acc += cost[lb + j];
-      ++j;
-      if (acc >= chunk) break;
+    uint32_t j;
+    if (dv >= chunk) {
+      j = i + 1;  // the first in-edge already reaches chunk
+    } else {
+      // smallest k in [lb+i, lb+len) with Q[k] - Q[lb+i-1] >= chunk - dv
+      const unsigned long long before = lb + i > 0 ? Q[lb + i - 1] : 0ull;
+      const unsigned long long want = before + (chunk - dv);
+      uint32_t lo = lb + i, hi = lb + len;
+      while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (Q[mid] < want) lo = mid + 1;
+        else hi = mid;
+      }
+      j = lo < lb + len ? lo - lb + 1 : len;
     }
     if (out) out[n] = Item{v, lb + i, j - i, tag};
     ++n;
@@ -144,14 +155,16 @@ __device__ inline uint32_t cut_items(const TrieView& t, const uint32_t* cost, co
   return n;
 }
 
-__global__ void __launch_bounds__(kB) k_count_items(TrieView t, const uint32_t* __restrict__ cost,
+__global__ void __launch_bounds__(kB) k_count_items(TrieView t,
+                                                    const unsigned long long* __restrict__ Q,
                                                     const uint32_t* __restrict__ trow,
                                                     uint32_t chunk, uint32_t* __restrict__ cnt) {
   for (uint64_t v = gtid(); v <= t.n; v += gstride())
-    cnt[v] = v < t.n ? cut_items(t, cost, trow, uint32_t(v), chunk, 0, nullptr) : 0u;
+    cnt[v] = v < t.n ? cut_items(t, Q, trow, uint32_t(v), chunk, 0, nullptr) : 0u;
 }
 
-__global__ void __launch_bounds__(kB) k_write_items(TrieView t, const uint32_t* __restrict__ cost,
+__global__ void __launch_bounds__(kB) k_write_items(TrieView t,
+                                                    const unsigned long long* __restrict__ Q,
                                                     const uint32_t* __restrict__ trow,
                                                     uint32_t chunk,
                                                     const unsigned long long* __restrict__ ioff,
@@ -162,7 +175,7 @@ __global__ void __launch_bounds__(kB) k_write_items(TrieView t, const uint32_t* 
   for (uint64_t v = gtid(); v < t.n; v += gstride()) {
     if (ioff[v + 1] == ioff[v]) continue;
     const uint32_t tag = n_graphs > 1 ? graph_of(vbase, n_graphs, uint32_t(v)) : 0u;
-    cut_items(t, cost, trow, uint32_t(v), chunk, tag, items + ioff[v]);
+    cut_items(t, Q, trow, uint32_t(v), chunk, tag, items + ioff[v]);
     mx = max(mx, outdeg(t, uint32_t(v)));
   }
   if (mx) atomicMax(dmax, mx);
@@ -221,13 +234,17 @@ __device__ inline void group_graph(const TrieView& t, const Item* items, const u
                                    uint4* gsub, uint64_t gsub_base, uint8_t* grouped) {
   uint64_t no = 0, nm = 0;
   for (uint64_t i = i0; i < i1;) {
-    const uint4 f0 = info[i];
+    // the facts of the at most 4 items a group can span, loaded together
+    uint4 fa[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) fa[q] = i + q < i1 ? info[i + q] : make_uint4(0, 0, 0, 0);
+    const uint4 f0 = fa[0];
     uint64_t j = i + 1;
     if (f0.x & kHiBit) {
       uint32_t base = f0.y, top = f0.z;
       uint32_t recs = f0.w, mem = f0.x & kMaxIndex;
-      while (j < i1 && j - i < group && (info[j].x & kHiBit)) {
-        const uint4 f = info[j];
+      while (j < i1 && j - i < group && (fa[j - i].x & kHiBit)) {
+        const uint4 f = fa[j - i];
         const uint32_t dv = f.x & kMaxIndex;
         const uint32_t nb = min(base, f.y);
         const uint32_t nt = max(top, f.z);
@@ -372,7 +389,7 @@ eh_status device_plan_target(Ctx* c, Trie& tr, Plan& plan, uint32_t chunk, bool 
   TrieView tv{static_cast<const uint2*>(tr.vdesc.p), static_cast<const uint32_t*>(tr.col.p),
               h.n_bs ? static_cast<const uint4*>(tr.bsdesc.p) : nullptr, n};
   DevBuf src, key_a, key_b, tin, trow, cnt, ioff, items, vbase, goff, small, tmp;
-  DevBuf n_out, n_mem, o_off, m_off, grouped, cost, info;
+  DevBuf n_out, n_mem, o_off, m_off, grouped, cost, info, qsum;
   Scratch sc(c);
   eh_status st;
   auto chk = [&](hipError_t e, const char* what) { return hip_check(c, e, what); };
@@ -382,7 +399,7 @@ eh_status device_plan_target(Ctx* c, Trie& tr, Plan& plan, uint32_t chunk, bool 
       (st = sc.get(ioff, 8ull * (n + 1))) != EH_OK || (st = sc.get(vbase, 4ull * (G + 1))) != EH_OK ||
       (st = sc.get(goff, 8ull * (G + 1))) != EH_OK || (st = sc.get(small, 64)) != EH_OK ||
       (st = sc.get(grouped, std::max<uint32_t>(n, 1))) != EH_OK ||
-      (st = sc.get(cost, 4 * m1)) != EH_OK)
+      (st = sc.get(cost, 4 * m1)) != EH_OK || (st = sc.get(qsum, 8 * m1)) != EH_OK)
     return st;
   const unsigned key_bits = 32u + (n > 1 ? 32u - uint32_t(__builtin_clz(n - 1)) : 1u);
   size_t need = 0, b = 0;
@@ -403,6 +420,12 @@ eh_status device_plan_target(Ctx* c, Trie& tr, Plan& plan, uint32_t chunk, bool 
                                         ptr<unsigned long long>(goff), 0ull, size_t(gcap),
                                         rocprim::plus<unsigned long long>(), s),
                 "plan scan size")) != EH_OK)
+    return st;
+  need = std::max(need, b);
+  if ((st = chk(rocprim::inclusive_scan(nullptr, b, ptr<uint32_t>(cost),
+                                        ptr<unsigned long long>(qsum), size_t(m1),
+                                        rocprim::plus<unsigned long long>(), s),
+                "cost scan size")) != EH_OK)
     return st;
   need = std::max(need, b);
   if ((st = sc.get(tmp, need)) != EH_OK) return st;
@@ -433,8 +456,17 @@ eh_status device_plan_target(Ctx* c, Trie& tr, Plan& plan, uint32_t chunk, bool 
   if (m)
     hipLaunchKernelGGL(k_in_edge_costs, dim3(grid_of(m)), dim3(kB), 0, s, tv, ptr<uint2>(tin), m,
                        ub ? 1u : 0u, ptr<uint32_t>(cost));
+  if (m) {
+    size_t qb = tmp.bytes;
+    if ((st = chk(rocprim::inclusive_scan(tmp.p, qb, ptr<uint32_t>(cost),
+                                          ptr<unsigned long long>(qsum), size_t(m),
+                                          rocprim::plus<unsigned long long>(), s),
+                  "cost scan")) != EH_OK)
+      return st;
+  }
   hipLaunchKernelGGL(k_count_items, dim3(grid_of(uint64_t(n) + 1)), dim3(kB), 0, s, tv,
-                     ptr<uint32_t>(cost), ptr<uint32_t>(trow), chunk, ptr<uint32_t>(cnt));
+                     ptr<unsigned long long>(qsum), ptr<uint32_t>(trow), chunk,
+                     ptr<uint32_t>(cnt));
   size_t tb = tmp.bytes;
   if ((st = chk(rocprim::exclusive_scan(tmp.p, tb, ptr<uint32_t>(cnt),
                                         ptr<unsigned long long>(ioff), 0ull, size_t(n) + 1,
@@ -447,7 +479,8 @@ eh_status device_plan_target(Ctx* c, Trie& tr, Plan& plan, uint32_t chunk, bool 
       (st = chk(hipStreamSynchronize(s), "plan sync")) != EH_OK)
     return st;
   if ((st = sc.get(items, sizeof(Item) * std::max<uint64_t>(n_items, 1))) != EH_OK) return st;
-  hipLaunchKernelGGL(k_write_items, dim3(grid_of(n)), dim3(kB), 0, s, tv, ptr<uint32_t>(cost),
+  hipLaunchKernelGGL(k_write_items, dim3(grid_of(n)), dim3(kB), 0, s, tv,
+                     ptr<unsigned long long>(qsum),
                      ptr<uint32_t>(trow), chunk, ptr<unsigned long long>(ioff),
                      ptr<uint32_t>(vbase), G, ptr<Item>(items), ptr<uint32_t>(small));
   hipLaunchKernelGGL(k_graph_offsets, dim3(grid_of(gcap)), dim3(kB), 0, s, ptr<Item>(items),
