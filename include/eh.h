@@ -259,6 +259,12 @@ eh_status eh_trie_free(eh_trie* trie);
 
 /* ---- counting ----------------------------------------------------------- */
 
+/* Work-item plans are made on the first count of each (pattern, staging,
+ * tuning) and cached in the trie.  Target-staged triangle plans are built on
+ * the GPU (transient device memory of about 40 bytes per stored edge); setting
+ * EH_HOST_PLAN in the environment builds them on the host instead (the same
+ * plans; for tests and comparisons). */
+
 /* Triangle total of a single-graph trie.  d_per_root: NULL, or a device array
  * of n uint64 that receives, per original vertex id, the triangles rooted at
  * it (it is overwritten, not accumulated). */
