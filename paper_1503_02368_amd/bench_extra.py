@@ -263,6 +263,10 @@ def bench_served(name, w, args, ctx, eh, torch, metric):
     info = trie.info
     log(f"[bench] resident trie: {info}")
     rates = [float(x) for x in args.rates.split(",")]
+    # out-degree of each original id: a request's root out-edges are its work
+    ha = trie.host_arrays()
+    dplus_by_id = np.diff(ha["row"].astype(np.int64))[ha["rank"].astype(np.int64)]
+    del ha
     root_t = root_k = None
     cpu = None
     if not args.no_cpu:
@@ -292,6 +296,7 @@ def bench_served(name, w, args, ctx, eh, torch, metric):
         reqs = inputs.request_stream(el.n, rate_qps=rate, duration_s=dur, seed=w["seed"] + int(rate))
         log(f"[bench] rate {rate:g} QPS: {len(reqs)} requests over {dur:.2f} s")
         row = {"rate_qps": rate, "requests": len(reqs)}
+        req_edges = sum(int(dplus_by_id[np.unique(r.roots.astype(np.int64))].sum()) for r in reqs)
         for mode in ("batched", "serial"):
             lat, counts = serve_run(ctx, eh, trie, reqs, mode, policy=args.policy)
             ok = all(c == want(r) for c, r in zip(counts, reqs)) if root_t is not None else None
@@ -299,7 +304,7 @@ def bench_served(name, w, args, ctx, eh, torch, metric):
             span = max(l + r.t_arrival for l, r in zip(lat, reqs)) if reqs else 0.0
             row[mode] = {"p50_ms": 1e3 * _pct(lat, 50), "p99_ms": 1e3 * _pct(lat, 99),
                          "mean_ms": 1e3 * statistics.fmean(lat), "completed_qps": len(reqs) / span,
-                         "exact": ok}
+                         "root_out_edges_per_s": req_edges / span, "exact": ok}
             log(f"[bench]   {mode}: p50 {row[mode]['p50_ms']:.2f} ms, p99 {row[mode]['p99_ms']:.2f} ms, exact {ok}")
         table.append(row)
     top = table[-1]
