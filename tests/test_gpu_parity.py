@@ -1022,3 +1022,65 @@ def test_randomized_parity(ctx, eh):
                 assert ctx.count_4cliques(trie) == K, (case, kind, t, layout, tau)
         finally:
             trie.free()
+
+
+def test_randomized_build_paths(ctx, eh):
+    """Seeded random graphs under seeded random choices of node ordering,
+    pruned or unpruned relation, host or GPU build and tuning knobs: totals,
+    per-root vectors and (where out-degrees allow) 4-cliques equal the
+    oracle's under that ordering's ranks (unpruned: 6T, 2 c3 by first
+    attribute, 24K)."""
+    import torch
+    key = inputs.stream_key(78, 8)
+    draws = inputs.rand_u64(key, 0, 40 * 32)
+    pick = iter(int(x) for x in draws)
+
+    def choice(xs):
+        return xs[next(pick) % len(xs)]
+
+    for case in range(40):
+        kind = choice(["rmat", "gnp", "cl", "messy"])
+        seed = 2000 + case
+        if kind == "rmat":
+            el = inputs.rmat(choice([7, 9, 11]), choice([4, 16]), seed=seed)
+        elif kind == "gnp":
+            el = inputs.gnp(choice([30, 90]), choice([0.1, 0.5]), seed)
+        elif kind == "cl":
+            el = inputs.chung_lu(choice([500, 3000]), choice([6.0, 20.0]), choice([1.9, 2.5]),
+                                 seed=seed, graph=case)
+        else:
+            el = inputs.messy(inputs.rmat(8, 8, seed=seed), seed)
+        order = choice(["degree", "rev_degree", "input", "bfs", "hybrid", "strong_runs"])
+        symmetric = choice([False, False, True])
+        device = choice([False, True]) and order in ("degree", "rev_degree", "input")
+        t = dict(kernel=choice([1, 1, 2]), staging=choice([1, 2]), use_bitsets=choice([0, 1]),
+                 dynamic=choice([0, 2, 4]), stage_words=choice([0, 96, 512]),
+                 group=choice([1, 2, 4]), chunk_work=choice([64, 4096]),
+                 search_below=choice([0, 24]), unroll=choice([4, 8]))
+        tune(ctx, **t)
+        layout, tau = choice([(0, 32.0), (1, 32.0), (1, 256.0), (2, 32.0)])
+        where = (case, kind, order, symmetric, device, t, layout, tau)
+        say("random build path", where)
+        if symmetric:
+            six_t, t_first, k24, _ = sym_truth(el)
+            want_t, want_root = six_t, t_first
+        else:
+            tr, kr, _ = order_truth(el, order)
+            want_t, want_root = tr["count"], tr["root"]
+            k24 = None if kr is None else kr["count"]
+        if device:
+            src, dst = _device_pairs(el)
+            trie = ctx.build_trie_device(el.n, src, dst, layout=layout, tau=tau,
+                                         order=eh.ORDERS[order], symmetric=symmetric)
+        else:
+            trie = ctx.build_edgelist(el, layout=layout, tau=tau, order=eh.ORDERS[order],
+                                      symmetric=symmetric)
+        try:
+            assert ctx.count_triangles(trie) == want_t, where
+            tot, per = ctx.count_triangles(trie, per_root=True)
+            assert tot == want_t, where
+            np.testing.assert_array_equal(per, want_root, err_msg=str(where))
+            if trie.info["max_out_degree"] <= 2048 and k24 is not None:
+                assert ctx.count_4cliques(trie) == k24, where
+        finally:
+            trie.free()
