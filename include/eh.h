@@ -218,7 +218,8 @@ eh_status eh_build_batch(eh_ctx* ctx, uint32_t n_graphs, const uint32_t* n_verti
 /* The trie of eh_build_trie, built on the GPU from raw pairs already in
  * device memory (section 2.2 dictionary encoding, section 5.2 pruning,
  * sections 4.1 and 4.4 layouts): the same arrays, and the same host copy
- * (downloaded for work-item planning).  d_src/d_dst: device arrays of
+ * (downloaded for work-item planning, except the bitset words, which stay in
+ * device memory only).  Symmetric tries are built too.  d_src/d_dst: device arrays of
  * n_edges uint32, read on the context's stream and not kept; the caller
  * keeps them valid until the call returns.  Orderings that are sorts only
  * (EH_ORDER_DEGREE, EH_ORDER_REV_DEGREE, EH_ORDER_INPUT); the traversal
@@ -241,7 +242,10 @@ eh_status eh_build_batch_device(eh_ctx* ctx, uint32_t n_graphs, const uint32_t* 
 eh_status eh_trie_info_get(const eh_trie* trie, eh_trie_info* out);
 /* Inspection: the host copy of a built trie, in the layout of
  * eh_host_trie_arrays (rank[n], row[n+1], col[m_plus], bs_off[n],
- * bs_base[n], bs_nw[n], bs_words[bitset_words]; any pointer may be NULL). */
+ * bs_base[n], bs_nw[n], bs_words[bitset_words]; any pointer may be NULL;
+ * the caller owns the buffers, sized from eh_trie_info).  A GPU-built trie's
+ * words are copied from device memory (after its context's stream drains);
+ * EH_EHIP if that copy fails. */
 eh_status eh_trie_host_arrays(const eh_trie* trie, uint32_t* rank, uint32_t* row, uint32_t* col,
                               uint32_t* bs_off, uint32_t* bs_base, uint32_t* bs_nw,
                               uint32_t* bs_words);
