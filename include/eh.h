@@ -217,15 +217,15 @@ eh_status eh_build_batch(eh_ctx* ctx, uint32_t n_graphs, const uint32_t* n_verti
 
 /* The trie of eh_build_trie, built on the GPU from raw pairs already in
  * device memory (section 2.2 dictionary encoding, section 5.2 pruning,
- * sections 4.1 and 4.4 layouts): the same arrays, and the same host copy
- * (downloaded for work-item planning, except the bitset words, which stay in
- * device memory only).  Symmetric tries are built too.  d_src/d_dst: device arrays of
- * n_edges uint32, read on the context's stream and not kept; the caller
- * keeps them valid until the call returns.  Orderings that are sorts only
+ * sections 4.1 and 4.4 layouts): the same arrays, pruned or symmetric, and
+ * the same host copy (downloaded for work-item planning; the bitset words
+ * stay in device memory only).  d_src/d_dst: device arrays of n_edges
+ * uint32, read on the context's stream and not kept; the caller keeps them
+ * valid until the call returns.  Orderings that are sorts only
  * (EH_ORDER_DEGREE, EH_ORDER_REV_DEGREE, EH_ORDER_INPUT); the traversal
  * orderings are EH_EINVAL here.  An id >= n is EH_EINVAL.  Scratch device
- * memory of about 16 bytes per raw pair and 40 per vertex, plus the sorts'
- * working space, is freed before it returns. */
+ * memory of about 16 bytes per raw pair (32 for a symmetric trie) and 40 per
+ * vertex, plus the sorts' working space, is freed before it returns. */
 eh_status eh_build_trie_device(eh_ctx* ctx, const uint32_t* d_src, const uint32_t* d_dst,
                                uint64_t n_edges, uint32_t n_vertices, const eh_build_opts* opts,
                                eh_trie** out);
