@@ -432,11 +432,19 @@ def bench_build(name, w, args, ctx, eh, torch, metric):
     rows = []
     for scale in w["scales"]:
         el = inputs.rmat(scale, w["edge_factor"], seed=scale)
-        src = torch.from_numpy(np.ascontiguousarray(el.src).view(np.int32)).cuda()
-        dst = torch.from_numpy(np.ascontiguousarray(el.dst).view(np.int32)).cuda()
+        hs = torch.from_numpy(np.ascontiguousarray(el.src).view(np.int32)).pin_memory()
+        hd = torch.from_numpy(np.ascontiguousarray(el.dst).view(np.int32)).pin_memory()
         torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        src = hs.cuda(non_blocking=True)
+        dst = hd.cuda(non_blocking=True)
+        torch.cuda.synchronize()
+        t_copy = time.perf_counter() - t0
+        del hs, hd
         ctx.set_tuning(**dict(ctx.get_tuning(), **load_tuning("rmat20_triangles").get("tuning", {})))
-        row = {"scale": scale, "raw_pairs": int(el.m_raw)}
+        row = {"scale": scale, "raw_pairs": int(el.m_raw), "pairs_h2d_ms": 1e3 * t_copy,
+               "pairs_h2d_gbs": 8 * el.m_raw / t_copy / 1e9}
+        log(f"[bench] rmat{scale}: pairs to HBM (pinned) {1e3 * t_copy:.1f} ms")
         for how in ("host", "device"):
             times = []
             for rep in range(args.steps):
