@@ -79,6 +79,9 @@ def _load():
         lib.orc_sym_triangles_by_first.argtypes = [vp, ctypes.c_int, _u64p]
         lib.orc_sym_lollipop.restype = ctypes.c_uint64
         lib.orc_sym_lollipop.argtypes = [vp, ctypes.c_int]
+        lib.orc_pair_intersections.restype = ctypes.c_uint64
+        lib.orc_pair_intersections.argtypes = [ctypes.c_uint32, _u64p, _u32p, ctypes.c_uint64,
+                                               _u32p, ctypes.c_int, _u64p]
         _lib = lib
         return lib
 
@@ -213,6 +216,21 @@ class Graph:
     def sym_lollipop(self, threads: int = 0) -> int:
         """COUNT(*) of Lollipop(x,y,z,w) :- R(x,y),S(y,z),T(x,z),U(x,w), unpruned."""
         return int(self._lib.orc_sym_lollipop(self._h, int(threads)))
+
+
+def pair_intersections(off, members, pairs, threads: int = 0):
+    """|A & B| per pair (section 4.2; layout-independent, section 4.3): set i is
+    members[off[i]:off[i+1]], sorted without repeats; pairs is [n, 2] of set
+    indices.  Returns (total, per-pair uint64 counts)."""
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    members = np.ascontiguousarray(members, dtype=np.uint32)
+    pairs = np.ascontiguousarray(pairs, dtype=np.uint32).reshape(-1, 2)
+    out = np.zeros(pairs.shape[0], np.uint64)
+    tot = _load().orc_pair_intersections(off.size - 1, _p64(off), _p32(members), pairs.shape[0],
+                                         _p32(pairs), int(threads), _p64(out))
+    if tot == 2**64 - 1:
+        raise ValueError("a pair names a set index out of range")
+    return int(tot), out
 
 
 def rooted_count(root_by_id: np.ndarray, roots) -> int:

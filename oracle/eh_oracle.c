@@ -502,3 +502,29 @@ uint64_t orc_sym_lollipop(orc_graph* g, int threads) {
   }
   return s;
 }
+
+/*
+ * Pairwise set intersection (section 4.2): out[p] = |A & B| for the sets
+ * A = members[off[s] .. off[s+1]) and B = members[off[t] .. off[t+1]) with
+ * (s, t) = (pairs[2p], pairs[2p+1]); each set sorted ascending without
+ * repeats.  The count does not depend on how a set is laid out (section
+ * 4.3), so one definition serves every layout.  Returns the sum, or
+ * UINT64_MAX if a pair names a set >= n_sets.
+ */
+uint64_t orc_pair_intersections(uint32_t n_sets, const uint64_t* off, const uint32_t* members,
+                                uint64_t n_pairs, const uint32_t* pairs, int threads,
+                                uint64_t* out) {
+  for (uint64_t p = 0; p < n_pairs; ++p)
+    if (pairs[2 * p] >= n_sets || pairs[2 * p + 1] >= n_sets) return UINT64_MAX;
+  set_threads(threads);
+  uint64_t s = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : s)
+  for (uint64_t p = 0; p < n_pairs; ++p) {
+    const uint32_t a = pairs[2 * p], b = pairs[2 * p + 1];
+    const uint64_t c = merge_count(members + off[a], off[a + 1] - off[a], members + off[b],
+                                   off[b + 1] - off[b]);
+    if (out) out[p] = c;
+    s += c;
+  }
+  return s;
+}

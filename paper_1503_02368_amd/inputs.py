@@ -26,6 +26,13 @@ not available here; these synthetic families stand in for them):
 * Batched Chung-Lu: n_i = round(exp U[ln 64, ln 16384]),
   dbar_i = exp U[ln 8, ln 64], gamma = 2.1, one key per graph.
 * Small structured graphs (complete, grid, cycle, wheel, ...) for pins.
+* Sets with a dense region (pairwise intersection by layout): 2 P sets of
+  `size` distinct ids in [0, domain).  Pair p = (2p, 2p+1) shares one region
+  [c_p, c_p + r) with c_p uniform; each of its sets holds
+  k_d = round(dense_frac * size) ids of the region (r = the larger of k_d and
+  ceil(k_d / density)) and size - k_d ids of the rest of the domain, each part
+  by jittered sampling: the part's range is cut into as many equal strata as
+  it has members and each stratum gives one uniform id.
 """
 from __future__ import annotations
 
@@ -471,3 +478,52 @@ def request_stream(n_vertices: int, rate_qps: float, duration_s: float, seed: in
         reqs.append(Request(t, pat, got[:size].copy()))
         i += 1
     return reqs
+
+
+# ---------------------------------------------------------------------------
+# Sets with a dense region
+# ---------------------------------------------------------------------------
+
+@dataclass
+class SetPairs:
+    """Sets members[off[i]:off[i+1]] (ascending, distinct) and pairs [P, 2] of set indices."""
+    off: np.ndarray      # uint64 [n_sets + 1]
+    members: np.ndarray  # uint32
+    pairs: np.ndarray    # uint32 [P, 2]
+    name: str = ""
+
+    @property
+    def n_sets(self) -> int:
+        return int(self.off.size - 1)
+
+
+def _jittered(key: int, n_sets: int, k: int, span: int) -> np.ndarray:
+    """[n_sets, k] ascending distinct values in [0, span): value i of a set is
+    uniform in the i-th of k equal strata of [0, span)."""
+    if k == 0:
+        return np.empty((n_sets, 0), np.int64)
+    lo = (np.arange(k, dtype=np.int64) * span) // k
+    width = np.diff(np.append(lo, span))
+    u = rand_uniform(key, 0, n_sets * k).reshape(n_sets, k)
+    return lo + np.minimum((u * width).astype(np.int64), width - 1)
+
+
+def dense_region_sets(n_pairs: int, size: int, dense_frac: float, domain: int = 1 << 21,
+                      density: float = 0.5, seed: int = 0) -> SetPairs:
+    """2 n_pairs sets with a dense region shared by the two sets of a pair."""
+    k_d = int(round(dense_frac * size))
+    k_s = size - k_d
+    r = max(k_d, int(math.ceil(k_d / density))) if k_d else 0
+    if k_s > domain - r:
+        raise ValueError("domain too small for the sparse members")
+    n_sets = 2 * n_pairs
+    c = (rand_u64(stream_key(seed, 1), 0, n_pairs) % np.uint64(domain - r + 1)).astype(np.int64)
+    cs = np.repeat(c, 2)[:, None]
+    dense = _jittered(stream_key(seed, 2), n_sets, k_d, r) + cs
+    sparse = _jittered(stream_key(seed, 3), n_sets, k_s, domain - r)
+    sparse = np.where(sparse >= cs, sparse + r, sparse)
+    members = np.sort(np.concatenate([dense, sparse], axis=1), axis=1).astype(np.uint32).ravel()
+    off = np.arange(n_sets + 1, dtype=np.uint64) * np.uint64(size)
+    sets = np.arange(n_sets, dtype=np.uint32)
+    pairs = np.stack([sets[0::2], sets[1::2]], axis=1)
+    return SetPairs(off, members, pairs, f"dense_region_{n_pairs}x{size}_f{dense_frac:g}")
