@@ -21,6 +21,9 @@ Prints one JSON line.  Workloads (--workload):
   ablation          R-MAT scale 20 with layout / algorithm choices switched off
   unpruned          R-MAT scale 20 with both directions of every edge: ordered
                     triangles and the Lollipop query, beside pruned triangles
+  composite         set layouts at relation, set and block level: pairs of sets
+                    with a shared dense region, and R-MAT s20 triangles as
+                    pairwise intersections per layout
   served            resident R-MAT scale 22, Poisson stream of rooted
                     triangle / 4-clique requests: p50/p99 latency
 """
@@ -244,6 +247,9 @@ def main():
     elif w["kind"] == "build":
         from paper_1503_02368_amd import bench_extra
         res = bench_extra.bench_build(name, w, args, ctx, eh, torch, METRIC)
+    elif w["kind"] == "composite":
+        from paper_1503_02368_amd import bench_extra
+        res = bench_extra.bench_composite(name, w, args, ctx, eh, torch, METRIC)
     elif w["kind"] == "orderings":
         from paper_1503_02368_amd import bench_extra
         res = bench_extra.bench_orderings(name, w, args, ctx, eh, torch, METRIC)

@@ -86,7 +86,7 @@ const char* eh_last_error(const eh_ctx* ctx);
 const char* eh_status_str(eh_status s);
 /* Version of this ABI (major * 10000 + minor * 100 + patch); a caller built
  * against this header checks that the library returns EH_ABI_VERSION. */
-#define EH_ABI_VERSION 10500
+#define EH_ABI_VERSION 10600
 int32_t eh_abi_version(void);
 
 /* ---- tuning knobs (performance only; counts never depend on them) ------- */
@@ -363,6 +363,96 @@ eh_status eh_server_drain(eh_server* srv, uint32_t cap, uint32_t timeout_ms, uin
                           uint64_t* counts, eh_req_stats* stats, uint32_t* n_out);
 /* Finishes admitted work, cancels queued requests, joins the thread. */
 eh_status eh_server_destroy(eh_server* srv);
+
+/* ---- set stores and pairwise intersection (section 4.3, "Tradeoffs") ----
+ *
+ * A set store holds many sorted sets of uint32 ids in one of the layouts the
+ * paper compares at its three granularities.  The id domain is cut into
+ * fixed blocks of 2^block_log ids (the paper's default block is 256 ids, one
+ * AVX register).  Each set is stored as a sequence of segments, ascending and
+ * disjoint in blocks; a segment is either a uint run (sorted members, 4 bytes
+ * each) or a bitset run (2^block_log / 32 words per block for consecutive
+ * blocks).  Adjacent blocks of the same kind share one segment, which stores
+ * the same members and words as one header per block would.
+ *   EH_SETS_UINT       relation level, uint: one uint run per set;
+ *   EH_SETS_SET        set level (section 4.4): one bitset run over every block
+ *                      from the set's first to its last if the set is dense by
+ *                      the rule of eh_build_opts (|S| >= s_min and
+ *                      (max - min + 1) / |S| <= tau), else one uint run;
+ *   EH_SETS_BITSET     relation level, bitset (section 4.1, Figure 3): every
+ *                      non-empty block as a bitset block, empty blocks omitted;
+ *   EH_SETS_COMPOSITE  block level ("composite set"): a block holding at least
+ *                      block_min members is a bitset block, the members of the
+ *                      other blocks form uint runs.
+ * Intersections (section 4.2) walk the two segment lists in block order and,
+ * for each overlap, AND words (bitset & bitset), probe words with members
+ * (uint & bitset), or merge members, searching the longer run instead when
+ * it is more than 32 times the shorter (uint & uint). */
+enum { EH_SETS_UINT = 0, EH_SETS_SET = 1, EH_SETS_BITSET = 2, EH_SETS_COMPOSITE = 3 };
+
+typedef struct eh_set_opts {
+  uint32_t layout;     /* EH_SETS_*; a value above 3 is EH_EINVAL */
+  uint32_t block_log;  /* log2 of the block size in ids, 5..16; 0 selects 8 (256 ids) */
+  uint32_t block_min;  /* composite: members that make a block dense; 0 selects
+                          2^block_log / 32, the count at which a block's members
+                          take as many bytes as its bitset */
+  float tau;           /* set level: as eh_build_opts.tau; <= 0 selects 32 */
+  uint32_t s_min;      /* set level: as eh_build_opts.s_min; 0 selects 1 */
+} eh_set_opts;
+
+typedef struct eh_sets_info {
+  uint32_t n_sets;
+  uint32_t block_log;
+  uint64_t n_members;       /* members over all sets */
+  uint64_t n_segments;      /* segments over all sets */
+  uint64_t n_bitset_segments;
+  uint64_t uint_members;    /* members stored in uint runs */
+  uint64_t bitset_blocks;   /* blocks stored as bitsets (empty ones included at set level) */
+  uint64_t bitset_words;    /* 32-bit words over all bitset runs */
+  uint64_t device_bytes;    /* HBM held by the store (0 for a host store) */
+} eh_sets_info;
+
+typedef struct eh_sets eh_sets;
+typedef struct eh_host_sets eh_host_sets;
+
+/* Encodes n_sets sets on the host and uploads them.  Set i is
+ * members[off[i] .. off[i+1]), strictly ascending (EH_EINVAL otherwise);
+ * off has n_sets + 1 entries with off[0] = 0.  opts may be NULL (composite,
+ * 256-id blocks).  EH_EOVERFLOW when members, words or segments exceed
+ * 2^31 - 1. */
+eh_status eh_sets_build(eh_ctx* ctx, uint32_t n_sets, const uint64_t* off, const uint32_t* members,
+                        const eh_set_opts* opts, eh_sets** out);
+eh_status eh_sets_info_get(const eh_sets* sets, eh_sets_info* out);
+eh_status eh_sets_free(eh_sets* sets);
+
+/* |A_p & B_p| for the pairs d_pairs[2p], d_pairs[2p+1] (set indices, device
+ * array of 2 n_pairs uint32), p < n_pairs < 2^32.  d_counts: NULL, or a
+ * device array of n_pairs uint32 that receives each pair's count.  *total:
+ * the sum over all pairs.  lanes: lanes per pair, 4, 16 or 64; 0 picks by
+ * the store's mean set size.  A pair naming a set >= n_sets counts 0 and
+ * makes the call return EH_EINVAL (after the launch has finished). */
+eh_status eh_intersect_pairs(eh_ctx* ctx, const eh_sets* sets, uint64_t n_pairs,
+                             const uint32_t* d_pairs, uint32_t* d_counts, uint32_t lanes,
+                             uint64_t* total);
+/* Enqueue-only form: adds the sum to *d_total (one uint64, device).  Pairs
+ * naming a set >= n_sets count 0 and are not reported. */
+eh_status eh_intersect_pairs_async(eh_ctx* ctx, const eh_sets* sets, uint64_t n_pairs,
+                                   const uint32_t* d_pairs, uint32_t* d_counts, uint32_t lanes,
+                                   uint64_t* d_total);
+
+/* The host half of eh_sets_build, for checks without a GPU. */
+eh_status eh_host_sets_build(uint32_t n_sets, const uint64_t* off, const uint32_t* members,
+                             const eh_set_opts* opts, eh_host_sets** out);
+eh_status eh_host_sets_info(const eh_host_sets* h, eh_sets_info* out);
+/* Copies out (any pointer may be NULL): seg_off[n_sets + 1] (set i owns
+ * segments [seg_off[i], seg_off[i+1])); seg[4 n_segments] = per segment
+ * {first block, last block, first member in vals or first word in words,
+ * members | 2^31 for a bitset run}; vals[uint_members]; words[bitset_words],
+ * bit (x mod 32) of word (x / 32 - first block * 2^block_log / 32) of a run
+ * holding id x. */
+eh_status eh_host_sets_arrays(const eh_host_sets* h, uint32_t* seg_off, uint32_t* seg,
+                              uint32_t* vals, uint32_t* words);
+eh_status eh_host_sets_free(eh_host_sets* h);
 
 /* ---- host-side trie (no device needed) ----------------------------------- */
 

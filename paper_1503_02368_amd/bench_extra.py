@@ -671,6 +671,122 @@ def bench_ablation(name, w, args, ctx, eh, torch, metric):
     }
 
 
+SET_LAYOUTS = ("uint", "set", "bitset", "composite")
+
+
+def _time_pairs(ctx, torch, st, d_pairs, steps, warmup):
+    """Average ms of one pairwise-intersection launch over `steps` launches on
+    the context's stream, and the total."""
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    s = ctx.stream
+    s.wait_stream(torch.cuda.current_stream())
+    for _ in range(warmup):
+        ctx.intersect_pairs_async(st, d_pairs, out)
+    torch.cuda.synchronize()
+    out.zero_()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(s)
+    for _ in range(steps):
+        ctx.intersect_pairs_async(st, d_pairs, out)
+    ev1.record(s)
+    torch.cuda.synchronize()
+    total, rem = divmod(int(out.cpu().numpy().view(np.uint64)[0]), steps)
+    if rem:
+        raise RuntimeError("accumulated total is not a multiple of the step count")
+    return ev0.elapsed_time(ev1) / steps, total
+
+
+def _layout_rows(ctx, eh, torch, off, members, pairs, args, expect, tau, extra):
+    d_pairs = torch.from_numpy(np.ascontiguousarray(pairs, np.uint32).view(np.int32)).cuda()
+    n_members = int(members.size)
+    touched = int(np.sum(np.diff(off.astype(np.int64))[pairs.ravel()]))  # members over both sides
+    rows = []
+    for lay in SET_LAYOUTS:
+        t0 = time.perf_counter()
+        st = ctx.build_sets(off, members, layout=eh.SET_LAYOUTS[lay], tau=tau)
+        enc = time.perf_counter() - t0
+        ms, tot = _time_pairs(ctx, torch, st, d_pairs, args.steps, args.warmup)
+        i = st.info
+        st.free()
+        stored = i["device_bytes"] - 4 * (i["n_sets"] + 1)
+        row = dict(extra, layout=lay, ms=ms, total=tot,
+                   correct=None if expect is None else tot == expect,
+                   members_per_s=touched / (ms / 1e3), store_bytes=stored,
+                   store_read_gbs=stored / (ms / 1e3) / 1e9, segments=i["n_segments"],
+                   bitset_segments=i["n_bitset_segments"], uint_members=i["uint_members"],
+                   bitset_words=i["bitset_words"], encode_s=enc)
+        rows.append(row)
+        log(f"[bench] {str(extra.get('dense_frac', extra.get('graph'))):8s} {lay:9s} {ms:9.3f} ms  {stored / 2**20:9.1f} MiB stored"
+            f"  segments {i['n_segments']:>10d}  total {tot}{'' if tot == expect else ' MISMATCH'}")
+    del d_pairs
+    best = min(r["ms"] for r in rows)
+    for r in rows:
+        r["vs_best"] = r["ms"] / best
+    return rows
+
+
+def bench_composite(name, w, args, ctx, eh, torch, metric):
+    """Section 4.3 layouts at relation (uint, bitset), set and block
+    (composite) level: (1) batches of pairs of sets whose members lie partly
+    in one shared dense region (the dense-region sweep of Figure 5); (2)
+    triangle counting of R-MAT s20 as one pairwise intersection per oriented
+    edge under each layout (the level comparison of Table 6), beside the
+    staged kernel."""
+    from paper_1503_02368_amd import inputs
+    sweep = []
+    for frac in w["fracs"]:
+        sp = inputs.dense_region_sets(w["n_pairs"], w["size"], frac, domain=w["domain"],
+                                      density=w["density"], seed=w["seed"])
+        expect = None
+        extra = {"dense_frac": frac}
+        if not args.no_cpu:
+            import oracle
+            t0 = time.perf_counter()
+            expect, _ = oracle.pair_intersections(sp.off, sp.members, sp.pairs)
+            extra["oracle_s"] = time.perf_counter() - t0
+        sweep += _layout_rows(ctx, eh, torch, sp.off, sp.members, sp.pairs, args, expect, 32.0,
+                              extra)
+        del sp
+    # triangle counting as pairwise intersections of out-sets
+    el = inputs.rmat(w["scale"], w["edge_factor"], seed=w["graph_seed"])
+    tuned = load_tuning("rmat20_triangles")
+    base = dict(ctx.get_tuning())
+    base.update(tuned.get("tuning", {}))
+    ctx.set_tuning(**base)
+    tau = tuned.get("tau", 32.0)
+    trie = ctx.build_edgelist(el, layout=tuned.get("layout", 1), tau=tau)
+    staged_ms, t_count = _time_counts(ctx, torch, trie, 3, args.steps, args.warmup)
+    h = trie.host_arrays()
+    trie.free()
+    off = h["row"].astype(np.uint64)
+    rows_u = np.repeat(np.arange(off.size - 1, dtype=np.uint32), np.diff(off.astype(np.int64)))
+    pairs = np.stack([rows_u, h["col"]], axis=1)
+    m_plus = int(pairs.shape[0])
+    levels = _layout_rows(ctx, eh, torch, off, h["col"], pairs, args, t_count, tau,
+                          {"graph": f"rmat{w['scale']}"})
+    for r in levels:
+        r["edges_per_s"] = m_plus / (r["ms"] / 1e3)
+        r["vs_staged"] = r["ms"] / staged_ms
+    log(f"[bench] staged kernel on the same graph: {staged_ms:.3f} ms")
+    head = [r for r in sweep if r["dense_frac"] == 0.5 and r["layout"] == "composite"][0]
+    res = {
+        "metric": "set members intersected per second (composite layout, half of each set dense)",
+        "value": head["members_per_s"], "unit": "members/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded generator)",
+        "config": {"workload": name, "n_pairs": w["n_pairs"], "size": w["size"],
+                   "domain": w["domain"], "density": w["density"], "seed": w["seed"],
+                   "block_ids": 256},
+        "dense_region_sweep": sweep,
+        "levels_rmat_triangles": {"staged_ms": staged_ms, "count": t_count, "tau": tau,
+                                  "rows": levels},
+        "all_correct": all(r["correct"] for r in sweep + levels) if not args.no_cpu else None,
+    }
+    return res
+
+
 def serve_run(ctx, eh, trie, reqs, mode, policy=0):
     """Replays the arrival schedule; returns per-request latency (s) and counts."""
     n = len(reqs)

@@ -224,6 +224,8 @@ eh_status read_back(Ctx* c, const unsigned long long* d, uint64_t* out, size_t n
 thread_local std::string g_err_no_ctx;
 
 }  // namespace
+
+void set_no_ctx_error(const std::string& e) { g_err_no_ctx = e; }
 }  // namespace eh
 
 using namespace eh;

@@ -247,6 +247,36 @@ eh_status launch_degree_weighted_sum(Ctx* c, hipStream_t s, const unsigned long 
 // Largest out-degree the staged 4-clique kernel accepts.
 uint32_t k4_staged_max_degree();
 
+// Set store (section 4.3): per set, segments {first block, last block, first
+// member in vals or first word in words, members | kHiBit for a bitset run}.
+struct HostSets {
+  uint32_t n_sets = 0;
+  uint32_t block_log = 8;
+  std::vector<uint32_t> seg_off;  // [n_sets + 1]
+  std::vector<uint4> seg;
+  std::vector<uint32_t> vals;
+  std::vector<uint32_t> words;
+  uint64_t n_members = 0;
+  uint64_t n_bitset_segs = 0;
+  uint64_t bitset_blocks = 0;
+};
+// The text eh_last_error(NULL) returns (calls made without a context).
+void set_no_ctx_error(const std::string& e);
+eh_status host_sets_build(uint32_t n_sets, const uint64_t* off, const uint32_t* members,
+                          const eh_set_opts* opts, HostSets& h, std::string& err);
+
+struct Sets {
+  Ctx* ctx = nullptr;
+  eh_sets_info info{};
+  DevBuf seg_off, seg, vals, words;
+};
+// *total += sum over pairs of |A_p & B_p|; counts[p] = |A_p & B_p| when
+// counts is not null; *bad |= 1 when a pair names a set >= n_sets and bad is
+// not null.  lanes: 4, 16 or 64 per pair.
+eh_status launch_intersect_pairs(Ctx* c, hipStream_t s, const Sets& st, uint64_t n_pairs,
+                                 const uint32_t* pairs, uint32_t* counts, uint32_t lanes,
+                                 unsigned long long* total, unsigned long long* bad);
+
 }  // namespace eh
 
 struct eh_ctx {
@@ -257,4 +287,10 @@ struct eh_trie {
 };
 struct eh_host_trie {
   eh::HostTrie h;
+};
+struct eh_sets {
+  eh::Sets s;
+};
+struct eh_host_sets {
+  eh::HostSets h;
 };

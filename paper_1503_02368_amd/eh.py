@@ -30,6 +30,8 @@ ORDERS = {"degree": ORDER_DEGREE, "rev_degree": ORDER_REV_DEGREE, "input": ORDER
 KERNEL_AUTO, KERNEL_STAGED, KERNEL_PAIRWISE = 0, 1, 2
 STAGE_AUTO, STAGE_SOURCE, STAGE_TARGET = 0, 1, 2
 ALGO_AUTO, ALGO_MERGE, ALGO_SEARCH = 0, 1, 2
+SETS_UINT, SETS_SET, SETS_BITSET, SETS_COMPOSITE = 0, 1, 2, 3
+SET_LAYOUTS = {"uint": SETS_UINT, "set": SETS_SET, "bitset": SETS_BITSET, "composite": SETS_COMPOSITE}
 
 # every symbol include/eh.h declares
 SYMBOLS = [
@@ -40,7 +42,9 @@ SYMBOLS = [
     "eh_server_create", "eh_submit", "eh_poll", "eh_wait", "eh_server_drain", "eh_server_destroy",
     "eh_host_trie_build", "eh_host_trie_info", "eh_host_trie_arrays", "eh_host_trie_free",
     "eh_build_trie_device", "eh_trie_host_arrays", "eh_trie_device_arrays", "eh_count_lollipop",
-    "eh_build_batch_device",
+    "eh_build_batch_device", "eh_sets_build", "eh_sets_info_get", "eh_sets_free",
+    "eh_intersect_pairs", "eh_intersect_pairs_async", "eh_host_sets_build", "eh_host_sets_info",
+    "eh_host_sets_arrays", "eh_host_sets_free",
 ]
 
 
@@ -57,7 +61,7 @@ class _Allocator(ctypes.Structure):
 
 
 # struct layouts below are those of this ABI version of include/eh.h
-ABI_VERSION = 10500
+ABI_VERSION = 10600
 
 
 class _Tuning(ctypes.Structure):
@@ -80,6 +84,19 @@ class _TrieInfo(ctypes.Structure):
                 ("n_bitset_sets", ctypes.c_uint64), ("bitset_words", ctypes.c_uint64),
                 ("device_bytes", ctypes.c_uint64), ("b_merge", ctypes.c_uint64),
                 ("max_out_degree", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class _SetOpts(ctypes.Structure):
+    _fields_ = [("layout", ctypes.c_uint32), ("block_log", ctypes.c_uint32),
+                ("block_min", ctypes.c_uint32), ("tau", ctypes.c_float), ("s_min", ctypes.c_uint32)]
+
+
+class _SetsInfo(ctypes.Structure):
+    _fields_ = [("n_sets", ctypes.c_uint32), ("block_log", ctypes.c_uint32),
+                ("n_members", ctypes.c_uint64), ("n_segments", ctypes.c_uint64),
+                ("n_bitset_segments", ctypes.c_uint64), ("uint_members", ctypes.c_uint64),
+                ("bitset_blocks", ctypes.c_uint64), ("bitset_words", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64)]
 
 
 class _ServerOpts(ctypes.Structure):
@@ -148,6 +165,17 @@ def load():
             "eh_count_lollipop": [_vp, _vp, _u64p],
             "eh_build_batch_device": [_vp, ctypes.c_uint32, _u32p, _u64p, _vp, _vp,
                                       ctypes.POINTER(_BuildOpts), ctypes.POINTER(_vp)],
+            "eh_sets_build": [_vp, ctypes.c_uint32, _u64p, _u32p, ctypes.POINTER(_SetOpts),
+                              ctypes.POINTER(_vp)],
+            "eh_sets_info_get": [_vp, ctypes.POINTER(_SetsInfo)],
+            "eh_sets_free": [_vp],
+            "eh_intersect_pairs": [_vp, _vp, ctypes.c_uint64, _vp, _vp, ctypes.c_uint32, _u64p],
+            "eh_intersect_pairs_async": [_vp, _vp, ctypes.c_uint64, _vp, _vp, ctypes.c_uint32, _vp],
+            "eh_host_sets_build": [ctypes.c_uint32, _u64p, _u32p, ctypes.POINTER(_SetOpts),
+                                   ctypes.POINTER(_vp)],
+            "eh_host_sets_info": [_vp, ctypes.POINTER(_SetsInfo)],
+            "eh_host_sets_arrays": [_vp, _u32p, _u32p, _u32p, _u32p],
+            "eh_host_sets_free": [_vp],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -211,6 +239,49 @@ def host_trie(n, src, dst, layout=LAYOUT_HYBRID, tau=32.0, s_min=1, order=ORDER_
         lib.eh_host_trie_free(h)
 
 
+def _set_opts(layout, block_log, block_min, tau, s_min):
+    return _SetOpts(int(layout), int(block_log), int(block_min), float(tau), int(s_min))
+
+
+def _sets_input(off, members):
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    members = np.ascontiguousarray(members, dtype=np.uint32)
+    if off.ndim != 1 or off.size < 1:
+        raise ValueError("off needs n_sets + 1 entries")
+    if int(off[-1]) != members.size:
+        raise ValueError("off[-1] must equal the number of members")
+    return off, members
+
+
+def host_sets(off, members, layout=SETS_COMPOSITE, block_log=8, block_min=0, tau=32.0,
+              s_min=1) -> dict:
+    """Runs only the host encoding of a set store (no GPU) and returns its arrays:
+    seg_off[n_sets+1], seg[n_segments, 4] = {first block, last block, start, members |
+    2^31 for a bitset run}, vals, words, plus the sizes of eh_sets_info."""
+    lib = load()
+    off, members = _sets_input(off, members)
+    h = _vp()
+    o = _set_opts(layout, block_log, block_min, tau, s_min)
+    st = lib.eh_host_sets_build(off.size - 1, _p64(off), _p32(members), ctypes.byref(o),
+                                ctypes.byref(h))
+    if st != EH_OK:
+        raise EHError(st, lib.eh_last_error(None).decode() or lib.eh_status_str(st).decode())
+    try:
+        info = _SetsInfo()
+        lib.eh_host_sets_info(h, ctypes.byref(info))
+        d = {k: int(getattr(info, k)) for k, _ in _SetsInfo._fields_}
+        arr = {"seg_off": np.zeros(d["n_sets"] + 1, np.uint32),
+               "seg": np.zeros(4 * d["n_segments"], np.uint32),
+               "vals": np.zeros(d["uint_members"], np.uint32),
+               "words": np.zeros(d["bitset_words"], np.uint32)}
+        lib.eh_host_sets_arrays(h, *(_p32(arr[k]) for k in ("seg_off", "seg", "vals", "words")))
+        arr["seg"] = arr["seg"].reshape(-1, 4)
+        d.update(arr)
+        return d
+    finally:
+        lib.eh_host_sets_free(h)
+
+
 class Context:
     """An eh_ctx on one device, launching on torch's current stream by default."""
 
@@ -256,6 +327,7 @@ class Context:
             raise EHError(st, "eh_ctx_create: " + self._lib.eh_last_error(None).decode())
         self._h = h
         self._tries = []
+        self._sets = []
 
     def _check(self, st, what):
         if st != EH_OK:
@@ -264,6 +336,8 @@ class Context:
     def close(self):
         if getattr(self, "_h", None):
             for t in list(self._tries):
+                t.free()
+            for t in list(self._sets):
                 t.free()
             self._lib.eh_ctx_destroy(self._h)
             self._h = None
@@ -427,6 +501,36 @@ class Context:
         self._check(self._lib.eh_count_batch_async(self._h, trie._h, int(pattern), int(first), int(count),
                                                    _vp(d_out.data_ptr())), "count_batch_async")
 
+    # -- set stores ---------------------------------------------------------
+    def build_sets(self, off, members, layout=SETS_COMPOSITE, block_log=8, block_min=0, tau=32.0,
+                   s_min=1) -> "Sets":
+        """Encodes sets members[off[i]:off[i+1]] (each strictly ascending) and uploads them."""
+        off, members = _sets_input(off, members)
+        h = _vp()
+        o = _set_opts(layout, block_log, block_min, tau, s_min)
+        self._check(self._lib.eh_sets_build(self._h, off.size - 1, _p64(off), _p32(members),
+                                            ctypes.byref(o), ctypes.byref(h)), "sets_build")
+        return Sets(self, h)
+
+    def intersect_pairs(self, sets, d_pairs, d_counts=None, lanes: int = 0) -> int:
+        """Sum of |A & B| over the pairs of d_pairs (an int32 CUDA tensor of shape
+        [n, 2] of set indices); d_counts (int32 CUDA tensor of n) receives each pair's count."""
+        n = int(d_pairs.numel()) // 2
+        out = ctypes.c_uint64(0)
+        self._check(self._lib.eh_intersect_pairs(
+            self._h, sets._h, n, _vp(d_pairs.data_ptr()) if n else None,
+            _vp(d_counts.data_ptr()) if d_counts is not None else None, int(lanes),
+            ctypes.byref(out)), "intersect_pairs")
+        return int(out.value)
+
+    def intersect_pairs_async(self, sets, d_pairs, d_total, d_counts=None, lanes: int = 0) -> None:
+        """Enqueues the intersections; adds their sum into d_total (a 1-element int64 CUDA tensor)."""
+        n = int(d_pairs.numel()) // 2
+        self._check(self._lib.eh_intersect_pairs_async(
+            self._h, sets._h, n, _vp(d_pairs.data_ptr()) if n else None,
+            _vp(d_counts.data_ptr()) if d_counts is not None else None, int(lanes),
+            _vp(d_total.data_ptr())), "intersect_pairs_async")
+
     def server(self, trie, hbm_budget_bytes=0, max_active=0, max_queued=0, step_items=0,
                policy=0) -> "Server":
         return Server(self, trie, hbm_budget_bytes, max_active, max_queued, step_items, policy)
@@ -465,6 +569,23 @@ class Trie:
             self._h = None
             if self in self.ctx._tries:
                 self.ctx._tries.remove(self)
+
+
+class Sets:
+    def __init__(self, ctx: Context, h):
+        self.ctx = ctx
+        self._h = h
+        ctx._sets.append(self)
+        info = _SetsInfo()
+        ctx._check(ctx._lib.eh_sets_info_get(h, ctypes.byref(info)), "sets_info")
+        self.info = {k: int(getattr(info, k)) for k, _ in _SetsInfo._fields_}
+
+    def free(self):
+        if self._h:
+            self.ctx._lib.eh_sets_free(self._h)
+            self._h = None
+            if self in self.ctx._sets:
+                self.ctx._sets.remove(self)
 
 
 @dataclass

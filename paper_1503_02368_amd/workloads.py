@@ -20,6 +20,11 @@ WORKLOADS = {
     "unpruned": dict(kind="unpruned", scale=20, edge_factor=16, seed=20, layout=1, tau=32.0),
     # layout / algorithm ablation on R-MAT s20 (the paper's -R, -RA)
     "ablation": dict(kind="ablation", scale=20, edge_factor=16, seed=20, layout=1, tau=256.0),
+    # set layouts at relation, set and block level (section 4.3): pairwise
+    # intersection of sets with a dense region, then triangle counting as
+    # pairwise intersections of R-MAT s20 out-sets
+    "composite": dict(kind="composite", n_pairs=8192, size=4096, fracs=[0.0, 0.25, 0.5, 0.75, 1.0],
+                      domain=1 << 21, density=0.5, seed=7, scale=20, edge_factor=16, graph_seed=20),
     "served": dict(kind="served", gen="rmat", scale=22, edge_factor=16, seed=22, layout=1, tau=32.0),
 }
 

@@ -1,0 +1,184 @@
+"""GPU parity of pairwise set intersection over set stores (section 4.2
+algorithms on the section 4.3 layouts): every per-pair count and every total
+equals the oracle's, bit for bit, under each layout, block size and lane
+grouping, which are performance choices only."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_02368_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+LAYOUTS = ("uint", "set", "bitset", "composite")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(eh):
+    c = eh.Context(0)
+    yield c
+    c.close()
+
+
+def _csr(sets):
+    off = np.zeros(len(sets) + 1, np.uint64)
+    off[1:] = np.cumsum([len(s) for s in sets])
+    parts = [np.asarray(sorted(s), np.uint32) for s in sets]
+    return off, (np.concatenate(parts) if parts else np.empty(0, np.uint32)).astype(np.uint32)
+
+
+def _to_dev(a, torch):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+
+def _run(eh, ctx, off, members, pairs, layout, bl=8, lanes=0, block_min=0):
+    import torch
+    pairs = np.ascontiguousarray(pairs, dtype=np.uint32).reshape(-1, 2)
+    say(f"[sets] layout={layout} bl={bl} lanes={lanes} sets={off.size - 1} pairs={pairs.shape[0]}")
+    st = ctx.build_sets(off, members, layout=eh.SET_LAYOUTS[layout], block_log=bl,
+                        block_min=block_min)
+    try:
+        d_pairs = _to_dev(pairs, torch)
+        d_counts = torch.zeros(max(pairs.shape[0], 1), dtype=torch.int32, device="cuda")
+        tot = ctx.intersect_pairs(st, d_pairs, d_counts, lanes=lanes)
+        per = d_counts.cpu().numpy().view(np.uint32)[:pairs.shape[0]]
+    finally:
+        st.free()
+    return tot, per
+
+
+def _mixed_sets():
+    rng = np.random.default_rng(11)
+    sets = []
+    for k in range(48):
+        size = int(rng.integers(0, 900))
+        dom = int(rng.choice([600, 5000, 1 << 16, 1 << 22]))
+        sets.append(set(rng.choice(dom, size=min(size, dom), replace=False).tolist()))
+    # edge cases: empty, single, whole blocks, the top of the id range, long runs
+    sets += [set(), {0}, {2 ** 32 - 1}, set(range(256)), set(range(255, 1025)),
+             set(range(2 ** 32 - 700, 2 ** 32)), set(range(2 ** 32 - 5000, 2 ** 32, 3)),
+             set(range(0, 1 << 15, 2)), set(range(0, 1 << 20, 131))]
+    return sets
+
+
+MIXED = _mixed_sets()
+
+
+def _mixed_pairs():
+    rng = np.random.default_rng(12)
+    n = len(MIXED)
+    p = rng.integers(0, n, size=(1500, 2))
+    same = np.stack([np.arange(n), np.arange(n)], axis=1)
+    return np.concatenate([p, same]).astype(np.uint32)
+
+
+MIXED_PAIRS = _mixed_pairs()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("bl", [5, 8, 12])
+@pytest.mark.parametrize("lanes", [0, 4, 16, 64])
+def test_mixed_sets_every_layout(eh, ctx, layout, bl, lanes):
+    off, members = _csr(MIXED)
+    tot_o, per_o = oracle.pair_intersections(off, members, MIXED_PAIRS)
+    tot, per = _run(eh, ctx, off, members, MIXED_PAIRS, layout, bl, lanes, block_min=3)
+    assert np.array_equal(per.astype(np.uint64), per_o)
+    assert tot == tot_o
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("frac", [0.0, 0.3, 0.7, 1.0])
+def test_dense_region_sets(eh, ctx, layout, frac):
+    sp = inputs.dense_region_sets(96, 3000, frac, domain=1 << 20, seed=21)
+    tot_o, per_o = oracle.pair_intersections(sp.off, sp.members, sp.pairs)
+    tot, per = _run(eh, ctx, sp.off, sp.members, sp.pairs, layout)
+    assert np.array_equal(per.astype(np.uint64), per_o) and tot == tot_o
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("lanes", [4, 64])
+def test_search_and_merge_regimes(eh, ctx, layout, lanes):
+    """Runs whose lengths differ by more than 32 times take the search branch;
+    the rest merge; both must count the same."""
+    big = set(range(0, 1 << 18, 3))
+    sets = [big, set(range(0, 1 << 18, 1500)), set(range(7, 1 << 18, 2000)),
+            set(range(0, 1 << 18, 5)), set(range(1 << 17, (1 << 17) + 90))]
+    off, members = _csr(sets)
+    pairs = np.array([[0, 1], [1, 0], [0, 2], [0, 3], [3, 0], [4, 0], [2, 4], [3, 3]], np.uint32)
+    tot_o, per_o = oracle.pair_intersections(off, members, pairs)
+    tot, per = _run(eh, ctx, off, members, pairs, layout, lanes=lanes)
+    assert np.array_equal(per.astype(np.uint64), per_o) and tot == tot_o
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_triangles_as_pair_intersections(eh, ctx, layout):
+    """Pairs = oriented edges over the sets N+(v): the total is the triangle count."""
+    el = inputs.rmat(13, 16, seed=31)
+    g = oracle.Graph.from_edgelist(el)
+    off, nbr = g.oriented()
+    rows = np.repeat(np.arange(g.n, dtype=np.uint32), np.diff(off.astype(np.int64)))
+    pairs = np.stack([rows, nbr], axis=1)
+    tot, per = _run(eh, ctx, off, nbr, pairs, layout)
+    assert tot == g.count(3)
+    _, per_o = oracle.pair_intersections(off, nbr, pairs)
+    assert np.array_equal(per.astype(np.uint64), per_o)
+
+
+def test_async_accumulates_and_no_counts(eh, ctx):
+    import torch
+    off, members = _csr(MIXED)
+    tot_o, _ = oracle.pair_intersections(off, members, MIXED_PAIRS)
+    st = ctx.build_sets(off, members)
+    try:
+        d_pairs = _to_dev(MIXED_PAIRS, torch)
+        d_total = torch.zeros(1, dtype=torch.int64, device="cuda")
+        with torch.cuda.stream(ctx.stream):
+            ctx.intersect_pairs_async(st, d_pairs, d_total)
+            ctx.intersect_pairs_async(st, d_pairs, d_total)
+        ctx.stream.synchronize()
+        assert int(d_total.item()) == 2 * tot_o
+        assert ctx.intersect_pairs(st, d_pairs) == tot_o
+    finally:
+        st.free()
+
+
+def test_empty_and_invalid_pairs(eh, ctx):
+    import torch
+    off, members = _csr([{1, 2, 3}, {2, 3, 4}, set()])
+    st = ctx.build_sets(off, members)
+    try:
+        none = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+        assert ctx.intersect_pairs(st, none) == 0
+        good = _to_dev(np.array([[0, 1], [2, 0]], np.uint32), torch)
+        assert ctx.intersect_pairs(st, good) == 2
+        bad = _to_dev(np.array([[0, 1], [3, 0]], np.uint32), torch)
+        counts = torch.full((2,), 7, dtype=torch.int32, device="cuda")
+        with pytest.raises(eh.EHError) as e:
+            ctx.intersect_pairs(st, bad, counts)
+        assert e.value.status == eh.EH_EINVAL
+        assert counts.cpu().tolist() == [2, 0]  # the bad pair counts 0
+        with pytest.raises(eh.EHError):
+            ctx.intersect_pairs(st, good, lanes=8)
+        # the store still works after the error
+        assert ctx.intersect_pairs(st, good) == 2
+    finally:
+        st.free()
+    empty = ctx.build_sets(np.zeros(1, np.uint64), np.empty(0, np.uint32))
+    assert empty.info["n_sets"] == 0
+    empty.free()
+
+
+def test_full_size_dense_region_workload(eh, ctx):
+    """The benchmark's workload (8192 pairs of 4096-member sets, half of each
+    set in the shared dense region), every pair checked, composite layout."""
+    sp = inputs.dense_region_sets(8192, 4096, 0.5, seed=7)
+    tot_o, per_o = oracle.pair_intersections(sp.off, sp.members, sp.pairs)
+    tot, per = _run(eh, ctx, sp.off, sp.members, sp.pairs, "composite")
+    assert np.array_equal(per.astype(np.uint64), per_o) and tot == tot_o
