@@ -7,11 +7,10 @@
 // cover it spreads the work over its lanes:
 //   bitset & bitset  AND of the overlapping words, popcount;
 //   uint & bitset    each member of the uint run tests its bit;
-//   uint & uint      partitioned merge (lane l merges its slice of the
-//                    shorter run from the lower bound of the slice's first
-//                    member in the longer), or, when the longer run is more
-//                    than 32 times the shorter, a binary search of each
-//                    member of the shorter (the galloping regime).
+//   uint & uint      when the longer run is more than 32 times the shorter,
+//                    a binary search of each member of the shorter (the
+//                    galloping regime); otherwise a merge of LDS windows of
+//                    both runs (tiled_count).
 // A run restricted to blocks [lo, hi] is found by binary searches on the
 // block of its members, done only when the run reaches outside [lo, hi].
 #include <hip/hip_runtime.h>
@@ -62,6 +61,71 @@ __device__ __forceinline__ uint32_t lower_value(const uint32_t* __restrict__ v, 
   return k0;
 }
 
+// Orders the wave's LDS accesses before and after this point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// |S & L| for sorted runs S (na >= 1) and L (nb >= 1) by a group of G lanes:
+// windows of 4 G members of each run are staged in LDS (tS, tL) with
+// coalesced loads and merged window by window, as a two-pointer merge over
+// the windows' value ranges: the window that ends first advances (both when
+// they end together).  When two windows overlap in value, each member of
+// the S window within the L window's range is searched there.  A member of
+// S matches at most one member of L, and the two windows holding them
+// overlap and are visited together once, so each match is counted once.
+template <uint32_t G>
+__device__ __forceinline__ uint32_t tiled_count(const uint32_t* __restrict__ S, uint32_t na,
+                                                const uint32_t* __restrict__ L, uint32_t nb,
+                                                uint32_t* tS, uint32_t* tL, uint32_t gl) {
+  constexpr uint32_t T = 4 * G;
+  uint32_t cnt = 0, s0 = 0, l0 = 0;
+  uint32_t tn = min(T, na), cn = min(T, nb);
+  for (uint32_t k = gl; k < tn; k += G) tS[k] = S[k];
+  for (uint32_t k = gl; k < cn; k += G) tL[k] = L[k];
+  wave_sync();
+  for (;;) {
+    const uint32_t s_first = tS[0], s_last = tS[tn - 1];
+    const uint32_t l_first = tL[0], l_last = tL[cn - 1];
+    if (s_first <= l_last && l_first <= s_last) {
+      for (uint32_t k = gl; k < tn; k += G) {
+        const uint32_t x = tS[k];
+        if (x < l_first || x > l_last) continue;
+        uint32_t lo = 0, len = cn;
+        while (len > 0) {
+          const uint32_t half = len >> 1;
+          if (tL[lo + half] < x) {
+            lo += half + 1;
+            len -= half + 1;
+          } else {
+            len = half;
+          }
+        }
+        cnt += tL[lo] == x ? 1u : 0u;  // lo < cn: x <= l_last
+      }
+    }
+    const bool next_s = s_last <= l_last, next_l = l_last <= s_last;
+    wave_sync();
+    if (next_s) {
+      s0 += T;
+      if (s0 >= na) break;
+      tn = min(T, na - s0);
+      for (uint32_t k = gl; k < tn; k += G) tS[k] = S[s0 + k];
+    }
+    if (next_l) {
+      l0 += T;
+      if (l0 >= nb) break;
+      cn = min(T, nb - l0);
+      for (uint32_t k = gl; k < cn; k += G) tL[k] = L[l0 + k];
+    }
+    wave_sync();
+  }
+  wave_sync();
+  return cnt;
+}
+
 // positions in vals of the members of uint run r that lie in blocks [lo, hi]
 __device__ __forceinline__ uint2 run_members(const PairArgs& a, const uint4& r, uint32_t lo,
                                              uint32_t hi) {
@@ -74,7 +138,8 @@ __device__ __forceinline__ uint2 run_members(const PairArgs& a, const uint4& r, 
 
 template <uint32_t G>
 __device__ __forceinline__ uint32_t segment_pair(const PairArgs& a, const uint4& A, const uint4& B,
-                                                 uint32_t lo, uint32_t hi, uint32_t gl) {
+                                                 uint32_t lo, uint32_t hi, uint32_t gl,
+                                                 uint32_t* tS, uint32_t* tL) {
   const bool a_bits = (A.w & kHiBit) != 0, b_bits = (B.w & kHiBit) != 0;
   uint32_t cnt = 0;
   if (a_bits && b_bits) {
@@ -119,32 +184,17 @@ __device__ __forceinline__ uint32_t segment_pair(const PairArgs& a, const uint4&
     }
     return cnt;
   }
-  // every member of S belongs to one lane's slice, so each match is counted once
-  const uint32_t chunk = (na + G - 1) / G;
-  const uint32_t s0 = gl * chunk;
-  if (s0 >= na) return 0;
-  const uint32_t s1 = min(s0 + chunk, na);
-  uint32_t i = s0, j = lower_value(L, nb, S[s0]);
-  uint32_t x = S[i];
-  uint32_t y = j < nb ? L[j] : 0u;
-  while (i < s1 && j < nb) {
-    if (x < y) {
-      if (++i < s1) x = S[i];
-    } else if (x > y) {
-      if (++j < nb) y = L[j];
-    } else {
-      ++cnt;
-      if (++i < s1) x = S[i];
-      if (++j < nb) y = L[j];
-    }
-  }
-  return cnt;
+  return tiled_count<G>(S, na, L, nb, tS, tL, gl);
 }
 
 template <uint32_t G>
 __global__ __launch_bounds__(kPairWPB * 64) void k_intersect_pairs(PairArgs a) {
   constexpr uint32_t kGroups = kPairWPB * 64 / G;  // groups per block
+  // LDS windows of the uint & uint merge, per group
+  __shared__ uint32_t s_win[kGroups][2][4 * G];
   const uint32_t lane = threadIdx.x & 63u, gl = threadIdx.x % G;
+  uint32_t* tS = s_win[threadIdx.x / G][0];
+  uint32_t* tL = s_win[threadIdx.x / G][1];
   const uint64_t stride = uint64_t(gridDim.x) * kGroups;
   unsigned long long tot = 0;
   bool bad = false;
@@ -160,7 +210,7 @@ __global__ __launch_bounds__(kPairWPB * 64) void k_intersect_pairs(PairArgs a) {
         uint4 A = a.seg[i], B = a.seg[j];
         for (;;) {
           const uint32_t lo = max(A.x, B.x), hi = min(A.y, B.y);
-          if (lo <= hi) cnt += segment_pair<G>(a, A, B, lo, hi, gl);
+          if (lo <= hi) cnt += segment_pair<G>(a, A, B, lo, hi, gl, tS, tL);
           // advance the run that ends first (both when they end together)
           const bool next_a = A.y <= B.y, next_b = B.y <= A.y;
           if (next_a) {
