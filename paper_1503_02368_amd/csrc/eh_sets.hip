@@ -22,6 +22,7 @@ namespace {
 
 constexpr uint32_t kPairWPB = 4;        // waves per block
 constexpr uint64_t kGallopRatio = 32;   // longer / shorter above which uint & uint searches
+constexpr uint32_t kWinPerLane = 8;     // members per lane in an LDS window of the uint merge
 
 struct PairArgs {
   const uint32_t* seg_off;
@@ -69,7 +70,7 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // |S & L| for sorted runs S (na >= 1) and L (nb >= 1) by a group of G lanes:
-// windows of 4 G members of each run are staged in LDS (tS, tL) with
+// windows of kWinPerLane G members of each run are staged in LDS (tS, tL) with
 // coalesced loads and merged window by window, as a two-pointer merge over
 // the windows' value ranges: the window that ends first advances (both when
 // they end together).  When two windows overlap in value, each member of
@@ -80,7 +81,7 @@ template <uint32_t G>
 __device__ __forceinline__ uint32_t tiled_count(const uint32_t* __restrict__ S, uint32_t na,
                                                 const uint32_t* __restrict__ L, uint32_t nb,
                                                 uint32_t* tS, uint32_t* tL, uint32_t gl) {
-  constexpr uint32_t T = 4 * G;
+  constexpr uint32_t T = kWinPerLane * G;
   uint32_t cnt = 0, s0 = 0, l0 = 0;
   uint32_t tn = min(T, na), cn = min(T, nb);
   for (uint32_t k = gl; k < tn; k += G) tS[k] = S[k];
@@ -191,7 +192,7 @@ template <uint32_t G>
 __global__ __launch_bounds__(kPairWPB * 64) void k_intersect_pairs(PairArgs a) {
   constexpr uint32_t kGroups = kPairWPB * 64 / G;  // groups per block
   // LDS windows of the uint & uint merge, per group
-  __shared__ uint32_t s_win[kGroups][2][4 * G];
+  __shared__ uint32_t s_win[kGroups][2][kWinPerLane * G];
   const uint32_t lane = threadIdx.x & 63u, gl = threadIdx.x % G;
   uint32_t* tS = s_win[threadIdx.x / G][0];
   uint32_t* tL = s_win[threadIdx.x / G][1];
@@ -231,10 +232,19 @@ __global__ __launch_bounds__(kPairWPB * 64) void k_intersect_pairs(PairArgs a) {
       tot += cnt;
     }
   }
+  // one atomic per block: waves that finish together would queue on the
+  // total's address
+  __shared__ unsigned long long s_part[kPairWPB];
   for (uint32_t o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
-  if (lane == 0 && tot) atomicAdd(a.total, tot);
+  if (lane == 0) s_part[threadIdx.x >> 6] = tot;
   const bool any_bad = __ballot(bad) != 0ull;
   if (a.bad && any_bad && lane == 0) atomicOr(a.bad, 1ull);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long sum = 0;
+    for (uint32_t w = 0; w < kPairWPB; ++w) sum += s_part[w];
+    if (sum) atomicAdd(a.total, sum);
+  }
 }
 
 }  // namespace
