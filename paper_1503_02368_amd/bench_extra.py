@@ -41,6 +41,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(_HERE, "csrc", "eh_kernels.hip")
+SETS_SRC = os.path.join(_HERE, "csrc", "eh_sets.hip")
 TRAFFIC_FILE = os.path.join(os.path.dirname(_HERE), "profiles", "traffic.json")
 
 
@@ -48,19 +49,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
+def kernel_sha(src: str = KERNEL_SRC) -> str:
+    with open(src, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(name: str):
+def measured_traffic(name: str, src: str = KERNEL_SRC):
     """HBM bytes per launch from the committed rocprofv3 counter runs, or None
-    when the kernel source changed since they were taken."""
+    when the kernel source (src) changed since they were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
         d = json.load(f).get(name)
-    if not d or d.get("kernel_sha") != kernel_sha():
+    if not d or d.get("kernel_sha") != kernel_sha(src):
         return None
     return d.get("bytes_per_launch")
 
@@ -672,6 +673,7 @@ def bench_ablation(name, w, args, ctx, eh, torch, metric):
 
 
 SET_LAYOUTS = ("uint", "set", "bitset", "composite")
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
 def _time_pairs(ctx, torch, st, d_pairs, steps, warmup):
@@ -698,12 +700,13 @@ def _time_pairs(ctx, torch, st, d_pairs, steps, warmup):
     return ev0.elapsed_time(ev1) / steps, total
 
 
-def _layout_rows(ctx, eh, torch, off, members, pairs, args, expect, tau, extra):
+def _layout_rows(ctx, eh, torch, off, members, pairs, args, expect, tau, extra,
+                 layouts=SET_LAYOUTS):
     d_pairs = torch.from_numpy(np.ascontiguousarray(pairs, np.uint32).view(np.int32)).cuda()
     n_members = int(members.size)
     touched = int(np.sum(np.diff(off.astype(np.int64))[pairs.ravel()]))  # members over both sides
     rows = []
-    for lay in SET_LAYOUTS:
+    for lay in layouts:
         t0 = time.perf_counter()
         st = ctx.build_sets(off, members, layout=eh.SET_LAYOUTS[lay], tau=tau)
         enc = time.perf_counter() - t0
@@ -714,7 +717,8 @@ def _layout_rows(ctx, eh, torch, off, members, pairs, args, expect, tau, extra):
         row = dict(extra, layout=lay, ms=ms, total=tot,
                    correct=None if expect is None else tot == expect,
                    members_per_s=touched / (ms / 1e3), store_bytes=stored,
-                   store_read_gbs=stored / (ms / 1e3) / 1e9, segments=i["n_segments"],
+                   store_read_gbs=stored / (ms / 1e3) / 1e9,
+                   bytes_per_launch=stored + 8 * int(pairs.shape[0]), segments=i["n_segments"],
                    bitset_segments=i["n_bitset_segments"], uint_members=i["uint_members"],
                    bitset_words=i["bitset_words"], encode_s=enc)
         rows.append(row)
@@ -747,8 +751,46 @@ def bench_composite(name, w, args, ctx, eh, torch, metric):
             expect, _ = oracle.pair_intersections(sp.off, sp.members, sp.pairs)
             extra["oracle_s"] = time.perf_counter() - t0
         sweep += _layout_rows(ctx, eh, torch, sp.off, sp.members, sp.pairs, args, expect, 32.0,
-                              extra)
+                              extra, w.get("layouts", SET_LAYOUTS))
         del sp
+    levels_out = None
+    if w.get("levels", True):
+        levels_out = _levels_rmat(name, w, args, ctx, eh, torch)
+    head = [r for r in sweep if r["dense_frac"] == 0.5 and r["layout"] == "composite"][0]
+    res = {
+        "metric": "set members intersected per second (composite layout, half of each set dense)",
+        "value": head["members_per_s"], "unit": "members/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded generator)",
+        "config": {"workload": name, "n_pairs": w["n_pairs"], "size": w["size"],
+                   "domain": w["domain"], "density": w["density"], "seed": w["seed"],
+                   "block_ids": 256},
+        "dense_region_sweep": sweep,
+        "levels_rmat_triangles": levels_out,
+        "all_correct": (all(r["correct"] for r in sweep)
+                        and (levels_out is None or all(r["correct"] for r in levels_out["rows"])))
+                       if not args.no_cpu else None,
+    }
+    # roofline of the reported cell: each set is in one pair, so a launch reads
+    # every stored segment, member and word once, plus the pair list
+    gbs = head["bytes_per_launch"] / (head["ms"] / 1e3) / 1e9
+    traffic = measured_traffic("composite_half", SETS_SRC) if head["dense_frac"] == 0.5 else None
+    res["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                       "bytes_per_launch": head["bytes_per_launch"]}
+    if "oracle_s" in head:
+        import oracle
+        touched = head["members_per_s"] * head["ms"] / 1e3
+        res["cpu_baseline"] = {"value": touched / head["oracle_s"], "unit": "members/s",
+                               "cores": oracle.max_threads(), "kind": "oracle",
+                               "sample": "the whole cell (every pair, two-pointer merges)"}
+    return res
+
+
+def _levels_rmat(name, w, args, ctx, eh, torch):
+    """Triangle counting of R-MAT as one pairwise intersection per oriented
+    edge under each layout, beside the staged kernel."""
+    from paper_1503_02368_amd import inputs
     # triangle counting as pairwise intersections of out-sets
     el = inputs.rmat(w["scale"], w["edge_factor"], seed=w["graph_seed"])
     tuned = load_tuning("rmat20_triangles")
@@ -770,21 +812,7 @@ def bench_composite(name, w, args, ctx, eh, torch, metric):
         r["edges_per_s"] = m_plus / (r["ms"] / 1e3)
         r["vs_staged"] = r["ms"] / staged_ms
     log(f"[bench] staged kernel on the same graph: {staged_ms:.3f} ms")
-    head = [r for r in sweep if r["dense_frac"] == 0.5 and r["layout"] == "composite"][0]
-    res = {
-        "metric": "set members intersected per second (composite layout, half of each set dense)",
-        "value": head["members_per_s"], "unit": "members/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded generator)",
-        "config": {"workload": name, "n_pairs": w["n_pairs"], "size": w["size"],
-                   "domain": w["domain"], "density": w["density"], "seed": w["seed"],
-                   "block_ids": 256},
-        "dense_region_sweep": sweep,
-        "levels_rmat_triangles": {"staged_ms": staged_ms, "count": t_count, "tau": tau,
-                                  "rows": levels},
-        "all_correct": all(r["correct"] for r in sweep + levels) if not args.no_cpu else None,
-    }
-    return res
+    return {"staged_ms": staged_ms, "count": t_count, "tau": tau, "rows": levels}
 
 
 def serve_run(ctx, eh, trie, reqs, mode, policy=0):

@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--algorithmic-bytes", type=float, default=0.0)
     ap.add_argument("--out", required=True)
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--source", default="eh_kernels.hip",
+                    help="file under csrc/ that holds the kernel (its hash tags the entry)")
     args = ap.parse_args()
     if args.stats_only:
         return stats_only(args)
@@ -155,7 +157,9 @@ def main():
         for name in sorted(extra):
             v, n = extra[name]
             lines.append(f"| {name} | {v:,.0f} | {n} |")
-    lines += ["", f"Kernel source hash (eh_kernels.hip, sha256 prefix): {kernel_sha()}", ""]
+    src = os.path.join(ROOT, "paper_1503_02368_amd", "csrc", args.source)
+    sha = kernel_sha(src)
+    lines += ["", f"Kernel source hash ({args.source}, sha256 prefix): {sha}", ""]
     with open(args.out, "w") as f:
         f.write("\n".join(lines))
 
@@ -163,7 +167,7 @@ def main():
     if os.path.exists(args.traffic):
         with open(args.traffic) as f:
             tj = json.load(f)
-    tj[args.workload] = {"kernel": args.kernel, "kernel_sha": kernel_sha(),
+    tj[args.workload] = {"kernel": args.kernel, "kernel_sha": sha, "source": args.source,
                          "bytes_per_launch": traffic, "avg_us": avg_us,
                          "fetch_kib": fk, "write_kib": wk, "fetch_factor": f_fac,
                          "write_factor": w_fac, "summary": os.path.relpath(args.out, ROOT)}

@@ -25,6 +25,9 @@ WORKLOADS = {
     # pairwise intersections of R-MAT s20 out-sets
     "composite": dict(kind="composite", n_pairs=8192, size=4096, fracs=[0.0, 0.25, 0.5, 0.75, 1.0],
                       domain=1 << 21, density=0.5, seed=7, scale=20, edge_factor=16, graph_seed=20),
+    # its composite-layout, half-dense cell alone (for profiles)
+    "composite_half": dict(kind="composite", n_pairs=8192, size=4096, fracs=[0.5], domain=1 << 21,
+                           density=0.5, seed=7, layouts=["composite"], levels=False),
     "served": dict(kind="served", gen="rmat", scale=22, edge_factor=16, seed=22, layout=1, tau=32.0),
 }
 
