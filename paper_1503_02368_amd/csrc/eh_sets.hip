@@ -22,7 +22,7 @@ namespace {
 
 constexpr uint32_t kPairWPB = 4;        // waves per block
 constexpr uint64_t kGallopRatio = 32;   // longer / shorter above which uint & uint searches
-constexpr uint32_t kWinPerLane = 8;     // members per lane in an LDS window of the uint merge
+constexpr uint32_t kWinPerLane = 4;     // members per lane in an LDS window of the uint merge
 
 struct PairArgs {
   const uint32_t* seg_off;
@@ -77,6 +77,24 @@ __device__ __forceinline__ void wave_sync() {
 // the S window within the L window's range is searched there.  A member of
 // S matches at most one member of L, and the two windows holding them
 // overlap and are visited together once, so each match is counted once.
+// dst[0 .. n) = src[0 .. n), n <= kWinPerLane G, by a group of G lanes: every
+// load is issued before the first store, so a window costs one round trip
+template <uint32_t G>
+__device__ __forceinline__ void copy_window(uint32_t* dst, const uint32_t* __restrict__ src,
+                                            uint32_t n, uint32_t gl) {
+  uint32_t v[kWinPerLane];
+#pragma unroll
+  for (uint32_t i = 0; i < kWinPerLane; ++i) {
+    const uint32_t k = gl + i * G;
+    v[i] = k < n ? src[k] : 0u;
+  }
+#pragma unroll
+  for (uint32_t i = 0; i < kWinPerLane; ++i) {
+    const uint32_t k = gl + i * G;
+    if (k < n) dst[k] = v[i];
+  }
+}
+
 template <uint32_t G>
 __device__ __forceinline__ uint32_t tiled_count(const uint32_t* __restrict__ S, uint32_t na,
                                                 const uint32_t* __restrict__ L, uint32_t nb,
@@ -84,8 +102,8 @@ __device__ __forceinline__ uint32_t tiled_count(const uint32_t* __restrict__ S, 
   constexpr uint32_t T = kWinPerLane * G;
   uint32_t cnt = 0, s0 = 0, l0 = 0;
   uint32_t tn = min(T, na), cn = min(T, nb);
-  for (uint32_t k = gl; k < tn; k += G) tS[k] = S[k];
-  for (uint32_t k = gl; k < cn; k += G) tL[k] = L[k];
+  copy_window<G>(tS, S, tn, gl);
+  copy_window<G>(tL, L, cn, gl);
   wave_sync();
   for (;;) {
     const uint32_t s_first = tS[0], s_last = tS[tn - 1];
@@ -113,13 +131,13 @@ __device__ __forceinline__ uint32_t tiled_count(const uint32_t* __restrict__ S, 
       s0 += T;
       if (s0 >= na) break;
       tn = min(T, na - s0);
-      for (uint32_t k = gl; k < tn; k += G) tS[k] = S[s0 + k];
+      copy_window<G>(tS, S + s0, tn, gl);
     }
     if (next_l) {
       l0 += T;
       if (l0 >= nb) break;
       cn = min(T, nb - l0);
-      for (uint32_t k = gl; k < cn; k += G) tL[k] = L[l0 + k];
+      copy_window<G>(tL, L + l0, cn, gl);
     }
     wave_sync();
   }
@@ -189,7 +207,8 @@ __device__ __forceinline__ uint32_t segment_pair(const PairArgs& a, const uint4&
 }
 
 template <uint32_t G>
-__global__ __launch_bounds__(kPairWPB * 64) void k_intersect_pairs(PairArgs a) {
+__global__ __launch_bounds__(kPairWPB * 64) __attribute__((amdgpu_waves_per_eu(8)))
+void k_intersect_pairs(PairArgs a) {
   constexpr uint32_t kGroups = kPairWPB * 64 / G;  // groups per block
   // LDS windows of the uint & uint merge, per group
   __shared__ uint32_t s_win[kGroups][2][kWinPerLane * G];
