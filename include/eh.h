@@ -99,7 +99,11 @@ typedef struct eh_tuning {
   uint32_t kernel;       /* EH_KERNEL_*: staged (one set held in LDS) or pairwise */
   uint32_t staging;      /* staged kernel, triangle totals: which end of an edge is held;
                             target staging needs out-degrees below 2^16 (always so under
-                            degree order) and tries beyond that stage sources */
+                            degree order) and tries beyond that stage sources.  On a
+                            symmetric trie a total is counted over each undirected edge
+                            once, at its higher-ranked end (|N(x) & N(u)| is the same for
+                            the arcs (x,u) and (u,x)) and doubled, unless this is
+                            EH_STAGE_SOURCE, which evaluates every arc */
   uint32_t algo;         /* pairwise uint & uint: EH_ALGO_AUTO applies the gamma rule */
   float gamma;           /* galloping when the longer list exceeds gamma x the shorter
                             (section 4.2 uses 32); <= 0 keeps the current value */

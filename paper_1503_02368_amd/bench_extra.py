@@ -530,10 +530,15 @@ def bench_build(name, w, args, ctx, eh, torch, metric):
     }
 
 
+# every arc evaluated (source staging), or each undirected edge once at its
+# higher-ranked end and doubled (any other staging)
 UNPRUNED_VARIANTS = {
     "source": dict(staging=1),
     "source_full_words": dict(staging=1, stage_words=0),
-    "pairwise": dict(kernel=2, algo=0, group_lanes=0),
+    "edge_once": dict(staging=2),
+    "edge_once_full_words": dict(staging=2, stage_words=0),
+    "edge_once_unroll4": dict(staging=2, stage_words=0, unroll=4),
+    "pairwise_edge_once": dict(kernel=2, algo=0, group_lanes=0),
 }
 
 
@@ -577,7 +582,17 @@ def bench_unpruned(name, w, args, ctx, eh, torch, metric):
     rows["lollipop"] = {"ms": 1e3 * statistics.median(lol), "count": lcount,
                         "includes": "per-root triangle launch, degree-weighted sum, read-back"}
     log(f"[bench] Lollipop {rows['lollipop']['ms']:.3f} ms, count {lcount}")
-    parity = {"six_t": best[2] == 6 * t_count}
+    # the same ordered-triangle count as one pairwise intersection per arc over a
+    # set store: a hub's set is met by probing its bitset with the smaller set
+    h = trie.host_arrays()
+    off = h["row"].astype(np.uint64)
+    src = np.repeat(np.arange(off.size - 1, dtype=np.uint32), np.diff(off.astype(np.int64)))
+    pair_rows = _layout_rows(ctx, eh, torch, off, h["col"], np.stack([src, h["col"]], axis=1),
+                             args, best[2], w["tau"], {"graph": "unpruned"})
+    del h, src
+    rows["pairwise_by_layout"] = pair_rows
+    parity = {"six_t": best[2] == 6 * t_count,
+              "pairwise": all(r["correct"] for r in pair_rows)}
     cpu = None
     if not args.no_cpu:
         import oracle

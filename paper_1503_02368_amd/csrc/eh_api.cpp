@@ -182,16 +182,23 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
 
 // Target staging describes each streamed suffix of N+(u) by a 16-bit length,
 // which degree order guarantees (out-degrees below sqrt(2m) < 2^16); tries
-// built under another node ordering may exceed it and then stage sources, as
-// do symmetric tries.
-uint32_t tri_staging(const Ctx* c, const Trie& t, bool per_root) {
+// built under another node ordering may exceed it and then stage sources.
+// Symmetric tries stage sources; a single total (half_ok) is counted with
+// each undirected edge once (kStageHalf) unless the tuning asks for source
+// staging.
+uint32_t tri_staging(const Ctx* c, const Trie& t, bool per_root, bool half_ok = false) {
   if (per_root) return EH_STAGE_SOURCE;
+  // suffix streaming relies on orientation (every member of N+(v) exceeds v)
+  if (t.host.symmetric)
+    return half_ok && c->tune.staging != EH_STAGE_SOURCE ? kStageHalf : EH_STAGE_SOURCE;
   if (c->tune.kernel == EH_KERNEL_PAIRWISE) return EH_STAGE_SOURCE;
   if (t.host.dmax > 0xFFFFu) return EH_STAGE_SOURCE;
-  // suffix streaming relies on orientation (every member of N+(v) exceeds v)
-  if (t.host.symmetric) return EH_STAGE_SOURCE;
   return c->tune.staging == EH_STAGE_SOURCE ? EH_STAGE_SOURCE : EH_STAGE_TARGET;
 }
+
+// Accumulator slot for the half count of a symmetric trie (slots 0 and 1
+// serve the blocking calls).
+constexpr size_t kAccHalf = 4;
 
 eh_status count_single(Ctx* c, Trie& t, int pattern, unsigned long long* d_total,
                        unsigned long long* d_per_root, bool accumulate = false) {
@@ -200,13 +207,20 @@ eh_status count_single(Ctx* c, Trie& t, int pattern, unsigned long long* d_total
     return EH_ESTATE;
   }
   Plan* p = nullptr;
-  const uint32_t staging = pattern == EH_TRIANGLE ? tri_staging(c, t, d_per_root != nullptr)
-                                                  : EH_STAGE_SOURCE;
+  const uint32_t staging =
+      pattern == EH_TRIANGLE ? tri_staging(c, t, d_per_root != nullptr, true) : EH_STAGE_SOURCE;
   eh_status st = get_plan(c, &t, pattern, staging, &p);
   if (st != EH_OK) return st;
   if (!accumulate && (st = launch_fill_u64(c, c->stream, d_total, 1, 0)) != EH_OK) return st;
   if (d_per_root && (st = launch_fill_u64(c, c->stream, d_per_root, t.host.n, 0)) != EH_OK)
     return st;
+  if (staging == kStageHalf) {
+    // each undirected edge once: the ordered count is twice the launch's sum
+    auto* half = static_cast<unsigned long long*>(c->acc.p) + kAccHalf;
+    if ((st = launch_fill_u64(c, c->stream, half, 1, 0)) != EH_OK) return st;
+    if ((st = enqueue_count(c, t, p, 0, p->n_items, half, 0, nullptr)) != EH_OK) return st;
+    return launch_add_scaled(c, c->stream, half, 2, d_total);
+  }
   return enqueue_count(c, t, p, 0, p->n_items, d_total, 0, d_per_root);
 }
 

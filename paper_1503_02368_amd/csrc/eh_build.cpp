@@ -573,6 +573,19 @@ void make_items_source(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chu
   }
 }
 
+// Symmetric relation, totals only (kStageHalf): N(u) staged, N(x) streamed
+// for the members x of N(u) ranked below u, a prefix of u's sorted row.
+void make_items_half(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chunk_work,
+                     bool use_bitsets, std::vector<Item>& out) {
+  const uint32_t lb = h.row[u], du = out_deg(h, u);
+  const auto first = h.col.begin() + lb;
+  const uint32_t below = uint32_t(std::lower_bound(first, first + du, u) - first);
+  if (below == 0) return;
+  split_items(u, lb, below, tag, chunk_work, du,
+              [&](uint32_t e) { return uint64_t(stream_len(h, h.col[e], use_bitsets)) + 2; },
+              out);
+}
+
 // Out-neighbours per item when only d+(u) is known: each out-neighbour's
 // streamed work is taken to be about |N+(u)| (more for the 4-clique's second
 // level).  0: u roots no instance (too few out-neighbours).
@@ -693,6 +706,8 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
                         return uint64_t(suffix_len(h, t->tin[2 * k], t->tin[2 * k + 1], ub)) + 2;
                       },
                       out);
+        } else if (staging == kStageHalf) {
+          make_items_half(h, v, tag, chunk, ub, out);
         } else {
           make_items_source(h, v, tag, chunk, pattern, ub, out);
         }

@@ -23,6 +23,11 @@ constexpr uint32_t kNoBitset = 0xFFFFFFFFu;
 constexpr uint32_t kHiBit = 0x80000000u;   // vdesc.y: the set also has a bitset
 constexpr uint32_t kMaxIndex = 0x7FFFFFFFu;  // offsets must stay below 2^31
 constexpr uint32_t kStageWords = 1024;        // LDS words per wave for a staged set
+// Plan staging beside EH_STAGE_SOURCE / EH_STAGE_TARGET, internal: on a
+// symmetric trie, each undirected edge {x, u} (x ranked below u) once, at u:
+// N(u) is staged and N(x) streamed for the members of N(u) below u.  It
+// counts each triangle 3 times instead of the join's 6 (totals only).
+constexpr uint32_t kStageHalf = 3;
 constexpr uint32_t kCursorWords = 64;         // uint32 words between work cursors
 constexpr uint32_t kMaxParts = 32;           // item partitions (L2 domains) at most
 
@@ -240,6 +245,9 @@ eh_status launch_scatter_roots(Ctx* c, hipStream_t s, const unsigned long long* 
 // to the host planner's.
 eh_status device_plan_target(Ctx* c, Trie& t, Plan& plan, uint32_t chunk, bool ub, uint32_t cap,
                              uint32_t group);
+// out[0] += f * in[0]
+eh_status launch_add_scaled(Ctx* c, hipStream_t s, const unsigned long long* in,
+                            unsigned long long f, unsigned long long* out);
 // out[0] += sum over ranks r of t_by_id[vert[r]] * |N(r)| (Lollipop COUNT).
 eh_status launch_degree_weighted_sum(Ctx* c, hipStream_t s, const unsigned long long* t_by_id,
                                      const uint32_t* vert, const uint2* vdesc, uint32_t n,

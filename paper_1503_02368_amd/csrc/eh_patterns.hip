@@ -34,7 +34,22 @@ __global__ void __launch_bounds__(kB) k_degree_weighted_sum(const unsigned long 
   }
 }
 
+// out[0] += f * in[0], one thread
+__global__ void k_add_scaled(const unsigned long long* __restrict__ in, unsigned long long f,
+                             unsigned long long* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    const unsigned long long v = f * in[0];
+    if (v) atomicAdd(out, v);
+  }
+}
+
 }  // namespace
+
+eh_status launch_add_scaled(Ctx* c, hipStream_t s, const unsigned long long* in,
+                            unsigned long long f, unsigned long long* out) {
+  hipLaunchKernelGGL(k_add_scaled, dim3(1), dim3(64), 0, s, in, f, out);
+  return hip_check(c, hipGetLastError(), "scaled add launch");
+}
 
 eh_status launch_degree_weighted_sum(Ctx* c, hipStream_t s, const unsigned long long* t_by_id,
                                      const uint32_t* vert, const uint2* vdesc, uint32_t n,

@@ -774,6 +774,31 @@ def test_symmetric_triangles_and_lollipop(ctx, eh, tname):
             trie.free()
 
 
+@pytest.mark.parametrize("tname", ["staged_target", "staged_lean", "pair_auto"])
+def test_symmetric_totals_each_edge_once(ctx, eh, tname):
+    """Symmetric totals are counted over each undirected edge once and doubled
+    (unless the tuning asks for source staging): overwrite and accumulate
+    forms, against the oracle's 6T and the every-arc evaluation."""
+    import torch
+    for el in SYM_GRAPHS:
+        six_t = sym_truth(el)[0]
+        say("symmetric totals", tname, el.name)
+        trie = ctx.build_edgelist(el, symmetric=True)
+        try:
+            tune(ctx, **TUNINGS[tname])
+            d = torch.full((1,), 12345, dtype=torch.int64, device="cuda")
+            ctx.stream.wait_stream(torch.cuda.current_stream())
+            ctx.count_async(trie, eh.TRIANGLE, d)
+            ctx.count_add_async(trie, eh.TRIANGLE, d)
+            ctx.count_add_async(trie, eh.TRIANGLE, d)
+            ctx.stream.synchronize()
+            assert int(d.item()) == 3 * six_t
+            tune(ctx, **dict(TUNINGS[tname], staging=eh.STAGE_SOURCE))
+            assert ctx.count_triangles(trie) == six_t
+        finally:
+            trie.free()
+
+
 @pytest.mark.parametrize("tname", ["staged_source", "staged_half", "staged_steal"])
 def test_symmetric_4cliques(ctx, eh, tname):
     """Unpruned 4-cliques: 24K ordered tuples while every degree fits the
