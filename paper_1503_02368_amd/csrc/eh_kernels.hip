@@ -285,6 +285,9 @@ struct Staged {
   uint32_t beg, len, lo, hi, base, plen, mode;
   uint32_t glog, glim;  // group mode: log2 K, and the offsets x - base that fit
   uint32_t x0;  // per lane: member number `lane` of the set (lane < len), kept to clear R
+  // composite mode: the set's own bitset in HBM (position of its first word in
+  // the list buffer, first id covered), gw = kNoBitset if it has none
+  uint32_t gw, gb;
 };
 
 // Loads the set col[beg .. beg+len) with known min lo and max hi into region
@@ -298,6 +301,8 @@ __device__ __forceinline__ Staged stage_extent(const DevArgs& a, uint32_t beg, u
   st.len = len;
   st.plen = 0;
   st.x0 = 0;
+  st.gw = kNoBitset;
+  st.gb = 0;
   st.glog = 0;
   st.glim = 0;
   if (st.len == 0) { st.mode = kModeEmpty; st.lo = st.hi = st.base = 0; return st; }
@@ -342,8 +347,16 @@ __device__ __forceinline__ Staged stage_set(const DevArgs& a, uint32_t s, uint32
   const uint2 sd = a.vdesc[s];
   const uint32_t beg = uniform(sd.x), len = uniform(sd.y & kMaxIndex);
   if (len == 0) return stage_extent<RW>(a, beg, 0, 0, 0, R, Lp, lane);
-  return stage_extent<RW>(a, beg, len, uniform(a.col[beg]), uniform(a.col[beg + len - 1]), R, Lp,
-                          lane);
+  Staged st = stage_extent<RW>(a, beg, len, uniform(a.col[beg]), uniform(a.col[beg + len - 1]), R,
+                               Lp, lane);
+  // a composite set that also has the bitset layout answers its prefix with
+  // one word of that bitset instead of a search
+  if (st.mode == kModeComposite && a.use_bitsets && (sd.y & kHiBit)) {
+    const uint4 bd = a.bsdesc[s];
+    st.gw = uniform(bd.x);
+    st.gb = uniform(bd.y);
+  }
+  return st;
 }
 
 // Returns region R to all-zero after stage_extent (the prefix list needs no
@@ -368,6 +381,11 @@ __device__ __forceinline__ void unstage_set(const DevArgs& a, const Staged& st, 
 __device__ __forceinline__ uint32_t prefix_has(const DevArgs& a, const Staged& st,
                                                const uint32_t* Lp, uint32_t x) {
   if (x < st.lo || x >= st.base) return 0u;
+  if (st.gw != kNoBitset) {
+    // st.gb <= lo <= x < base <= hi: inside the bitset's words
+    const uint32_t d = x - st.gb;
+    return (a.bsw[st.gw + (d >> 5)] >> (d & 31)) & 1u;
+  }
   if (st.plen <= uint32_t(kPrefixCap)) {
     const uint32_t p = lower_bound_lds(Lp, st.plen, x);
     return (p < st.plen && Lp[p] == x) ? 1u : 0u;
@@ -699,7 +717,8 @@ __device__ __forceinline__ uint32_t grouped_item(const DevArgs& a, const SegTab&
   }
   const uint32_t E = publish_segments(T, g, lane);  // also orders the staging
   Staged st;
-  st.beg = st.len = st.lo = st.hi = st.plen = st.x0 = 0;
+  st.beg = st.len = st.lo = st.hi = st.plen = st.x0 = st.gb = 0;
+  st.gw = kNoBitset;
   st.mode = kModeGroup;
   st.base = base;
   st.glog = glog;
@@ -888,6 +907,8 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
         ss.lo = S[0];
         ss.hi = S[ns - 1];
         ss.plen = 0;
+        ss.x0 = ss.gb = 0;
+        ss.gw = kNoBitset;
         ss.base = su.base;
         ss.mode = (su_bits && !low) ? kModeBitmap : kModeList;
         const uint32_t* probe = ss.mode == kModeBitmap ? B : S;
