@@ -41,7 +41,8 @@ eh_status resolve(const eh_set_opts* o, SetRule& r, std::string& err) {
 struct Encoder {
   HostSets& h;
   const uint32_t* m;
-  uint32_t wpb;  // words per block
+  uint32_t wpb;           // words per block
+  bool overflow = false;  // a run would take the words past 2^31 - 1
 
   void put_uint(uint32_t b0, uint32_t b1, uint64_t k0, uint64_t k1) {
     h.seg.push_back(uint4{b0, b1, uint32_t(h.vals.size()), uint32_t(k1 - k0)});
@@ -49,7 +50,12 @@ struct Encoder {
   }
   void put_bits(uint32_t b0, uint32_t b1, uint64_t k0, uint64_t k1) {
     const size_t w0 = h.words.size();
-    h.words.resize(w0 + size_t(b1 - b0 + 1) * wpb, 0u);
+    const uint64_t nw = (uint64_t(b1) - b0 + 1) * wpb;
+    if (w0 + nw > kMaxIndex) {
+      overflow = true;
+      return;
+    }
+    h.words.resize(w0 + nw, 0u);
     const uint32_t first_word = b0 * wpb;  // = (b0 << block_log) / 32
     for (uint64_t k = k0; k < k1; ++k) {
       const uint32_t x = m[k];
@@ -204,7 +210,7 @@ eh_status host_sets_build(uint32_t n_sets, const uint64_t* off, const uint32_t* 
     h.seg_off[i] = uint32_t(h.seg.size());
     Encoder e{h, members + off[i], wpb};
     encode_set(e, off[i + 1] - off[i], r);
-    if (h.seg.size() > kMaxIndex || h.words.size() > kMaxIndex) {
+    if (e.overflow || h.seg.size() > kMaxIndex || h.words.size() > kMaxIndex) {
       err = "segments or bitset words exceed 2^31-1";
       return EH_EOVERFLOW;
     }
