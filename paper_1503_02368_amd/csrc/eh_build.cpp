@@ -559,7 +559,11 @@ void make_items_source(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chu
   if (du < (pattern == EH_4CLIQUE ? 3u : 2u)) return;
   const uint32_t lb = h.row[u];
   if (pattern == EH_TRIANGLE) {
-    split_items(u, lb, du, tag, chunk_work, du,
+    // a staged set larger than an item's work (hub lists of a symmetric
+    // trie) would be staged again for every streamed set: such items stream
+    // at least as much as they stage instead
+    const bool wide = du > chunk_work;
+    split_items(u, lb, du, tag, wide ? du : chunk_work, wide ? 0 : du,
                 [&](uint32_t e) { return uint64_t(stream_len(h, h.col[e], use_bitsets)) + 2; },
                 out);
   } else {
@@ -581,7 +585,8 @@ void make_items_half(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chunk
   const auto first = h.col.begin() + lb;
   const uint32_t below = uint32_t(std::lower_bound(first, first + du, u) - first);
   if (below == 0) return;
-  split_items(u, lb, below, tag, chunk_work, du,
+  const bool wide = du > chunk_work;  // as in make_items_source
+  split_items(u, lb, below, tag, wide ? du : chunk_work, wide ? 0 : du,
               [&](uint32_t e) { return uint64_t(stream_len(h, h.col[e], use_bitsets)) + 2; },
               out);
 }
