@@ -285,7 +285,11 @@ def host_sets(off, members, layout=SETS_COMPOSITE, block_log=8, block_min=0, tau
 class Context:
     """An eh_ctx on one device, launching on torch's current stream by default."""
 
-    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True):
+    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True,
+                 allocator=None):
+        """allocator: an object with alloc(nbytes, stream) -> device pointer (int) or
+        None, and free(ptr, stream), that the library calls for all its device memory
+        (in place of torch's caching allocator)."""
         import torch
         self._lib = load()
         if not torch.cuda.is_available():
@@ -302,7 +306,24 @@ class Context:
         handle = _vp(stream.cuda_stream)
         self._alloc = None
         alloc_p = None
-        if torch_allocator:
+        if allocator is not None:
+            @ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+            def _ua(_self, nbytes, s):
+                try:
+                    return allocator.alloc(int(nbytes), s or 0)
+                except Exception:
+                    return None
+
+            @ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+            def _uf(_self, ptr, s):
+                try:
+                    allocator.free(ptr, s or 0)
+                except Exception:
+                    pass
+
+            self._alloc = _Allocator(_ua, _uf, None)
+            alloc_p = ctypes.byref(self._alloc)
+        elif torch_allocator:
             dev = device
 
             @ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
