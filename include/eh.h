@@ -421,9 +421,12 @@ typedef struct eh_host_sets eh_host_sets;
 
 /* Encodes n_sets sets on the host and uploads them.  Set i is
  * members[off[i] .. off[i+1]), strictly ascending (EH_EINVAL otherwise);
- * off has n_sets + 1 entries with off[0] = 0.  opts may be NULL (composite,
- * 256-id blocks).  EH_EOVERFLOW when members, words or segments exceed
- * 2^31 - 1. */
+ * off has n_sets + 1 entries with off[0] = 0; both arrays are only read
+ * during the call.  opts may be NULL (composite, 256-id blocks).  The store
+ * owns its device memory (through the context's allocator) until
+ * eh_sets_free, and is used with the context that built it only (another
+ * context gets EH_EINVAL).  EH_EOVERFLOW when members, words or segments
+ * exceed 2^31 - 1; EH_ENOMEM when an allocation fails (nothing is kept). */
 eh_status eh_sets_build(eh_ctx* ctx, uint32_t n_sets, const uint64_t* off, const uint32_t* members,
                         const eh_set_opts* opts, eh_sets** out);
 eh_status eh_sets_info_get(const eh_sets* sets, eh_sets_info* out);
