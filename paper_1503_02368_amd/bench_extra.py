@@ -538,6 +538,7 @@ UNPRUNED_VARIANTS = {
     "edge_once": dict(staging=2),
     "edge_once_full_words": dict(staging=2, stage_words=0),
     "edge_once_unroll4": dict(staging=2, stage_words=0, unroll=4),
+    "edge_once_cursors": dict(staging=2, stage_words=0, dynamic=4, search_below=64),
     "pairwise_edge_once": dict(kernel=2, algo=0, group_lanes=0),
 }
 
