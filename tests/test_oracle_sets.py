@@ -98,3 +98,28 @@ def test_generator_recipe():
     assert np.sum((a >= lo) & (a < lo + 520)) >= 250 and np.sum((b >= lo) & (b < lo + 520)) >= 250
     again = inputs.dense_region_sets(6, 512, 0.5, domain=1 << 16, density=0.5, seed=9)
     assert np.array_equal(again.members, sp.members)
+
+
+# ---- properties over generated sets (hypothesis) ---------------------------------
+
+from hypothesis import given, settings, strategies as hs
+
+_sets = hs.lists(hs.sets(hs.integers(0, 2 ** 32 - 1), max_size=60), min_size=1, max_size=8)
+
+
+@settings(max_examples=150, deadline=None)
+@given(_sets, hs.data())
+def test_oracle_inclusion_exclusion(sets, data):
+    """|A & B| = |A| + |B| - |A | B|, with the union from numpy; the count is
+    symmetric and |A & A| = |A|."""
+    off, members = _csr(sets)
+    k = len(sets)
+    pairs = data.draw(hs.lists(hs.tuples(hs.integers(0, k - 1), hs.integers(0, k - 1)),
+                               min_size=1, max_size=20))
+    both = [(a, b) for a, b in pairs] + [(b, a) for a, b in pairs] + [(a, a) for a in range(k)]
+    tot, per = oracle.pair_intersections(off, members, np.array(both, np.uint32))
+    for (a, b), c in zip(both, per.tolist()):
+        A = np.asarray(sorted(sets[a]), np.uint32)
+        B = np.asarray(sorted(sets[b]), np.uint32)
+        assert c == A.size + B.size - np.union1d(A, B).size
+    assert tot == int(per.sum())

@@ -138,3 +138,25 @@ def test_host_encoding_rejects_bad_input():
         eh.host_sets(np.array([0, 2, 1, 3], np.uint64), good)          # decreasing
     h = eh.host_sets(np.zeros(1, np.uint64), np.empty(0, np.uint32))    # no sets
     assert h["n_sets"] == 0 and h["n_segments"] == 0
+
+
+# ---- generated sets (hypothesis) ---------------------------------------------------
+
+from hypothesis import given, settings, strategies as hs
+
+
+@settings(max_examples=120, deadline=None)
+@given(hs.lists(hs.one_of(hs.sets(hs.integers(0, 2 ** 32 - 1), max_size=40),
+                          hs.builds(lambda lo, n, step: set(range(lo, lo + n * step, step)),
+                                    hs.integers(0, 2 ** 20), hs.integers(0, 600),
+                                    hs.integers(1, 4))),
+                min_size=0, max_size=6),
+       hs.sampled_from(list(LAYOUTS)), hs.integers(5, 16), hs.integers(0, 40))
+def test_host_encoding_generated(sets, layout, bl, block_min):
+    """Any sets, layout, block size and density threshold: the encoding decodes
+    to its input and follows the layout's rule."""
+    off, members = _csr(sets)
+    h = eh.host_sets(off, members, layout=LAYOUTS[layout], block_log=bl, block_min=block_min)
+    for got, s in zip(_decode(h, len(sets)), sets):
+        assert got.tolist() == sorted(s)
+    _check_rules(h, sets, layout, bl, block_min if block_min else (1 << bl) // 32)
