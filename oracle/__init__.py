@@ -11,7 +11,8 @@ section 5.2 pruning each undirected edge once by degree-assigned ids):
 self-loops are dropped and every other pair is an undirected edge; T counts
 3-vertex subsets that are triangles, K counts 4-vertex cliques; the root of
 an instance is its vertex of smallest rank, rank = (degree asc, id asc), or
-the ranks of another node ordering (appendix A; ``orderings.py``).
+the ranks of another node ordering (appendix A; ``orderings.py``).  Pairwise
+set intersection (section 4.2) counts |A & B| for given pairs of sorted sets.
 """
 from __future__ import annotations
 

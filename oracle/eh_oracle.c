@@ -30,6 +30,10 @@
  *   Generic-Join over the symmetric (unpruned) relation counts ordered
  *   tuples: 3! T and 4! K (appendix A.1.2, pruning symmetric queries).
  *
+ * Pairwise set intersection (section 4.2): |A & B| for given pairs of
+ * sorted sets, by the same two-pointer merge; the layouts of section 4.3
+ * change how a set is stored, never this count.
+ *
  * Byte models (the reads a list-merge implementation performs):
  *   B_merge = sum over oriented edges (x,y) of 4 (|N+(x)| + |N+(y)|)
  *   B_K4    = B_merge + sum over triangles x<y<z of 4 (|S_xy| + |N+(z)|)
