@@ -182,3 +182,39 @@ def test_full_size_dense_region_workload(eh, ctx):
     tot_o, per_o = oracle.pair_intersections(sp.off, sp.members, sp.pairs)
     tot, per = _run(eh, ctx, sp.off, sp.members, sp.pairs, "composite")
     assert np.array_equal(per.astype(np.uint64), per_o) and tot == tot_o
+
+
+def _random_case(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n_sets = int(rng.integers(1, 200))
+    sets = []
+    for _ in range(n_sets):
+        kind = rng.integers(0, 3)
+        size = int(rng.integers(0, 3000))
+        if kind == 0:      # uniform over a random domain
+            dom = int(rng.choice([1 << 10, 1 << 16, 1 << 24, 1 << 32]))
+            s = set(rng.integers(0, dom, size=size, dtype=np.uint64).tolist())
+        elif kind == 1:    # a dense stretch
+            lo = int(rng.integers(0, 1 << 31))
+            s = set(range(lo, lo + 2 * size, int(rng.integers(1, 3))))
+        else:              # dense stretch plus sparse members
+            lo = int(rng.integers(0, 1 << 20))
+            s = set(range(lo, lo + size)) | set(rng.integers(0, 1 << 22, size=size // 4).tolist())
+        sets.append(s)
+    pairs = rng.integers(0, n_sets, size=(int(rng.integers(1, 2000)), 2)).astype(np.uint32)
+    layout = LAYOUTS[int(rng.integers(0, 4))]
+    bl = int(rng.integers(5, 17))
+    block_min = int(rng.integers(0, 65))
+    lanes = int(rng.choice([0, 4, 16, 64]))
+    return sets, pairs, layout, bl, block_min, lanes
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_stores(eh, ctx, seed):
+    """Seeded random sets (uniform, dense stretches, mixtures), pairs, layout,
+    block size, density threshold and lanes per pair."""
+    sets, pairs, layout, bl, block_min, lanes = _random_case(seed)
+    off, members = _csr(sets)
+    tot_o, per_o = oracle.pair_intersections(off, members, pairs)
+    tot, per = _run(eh, ctx, off, members, pairs, layout, bl, lanes, block_min=block_min)
+    assert np.array_equal(per.astype(np.uint64), per_o) and tot == tot_o
