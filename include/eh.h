@@ -86,7 +86,7 @@ const char* eh_last_error(const eh_ctx* ctx);
 const char* eh_status_str(eh_status s);
 /* Version of this ABI (major * 10000 + minor * 100 + patch); a caller built
  * against this header checks that the library returns EH_ABI_VERSION. */
-#define EH_ABI_VERSION 10600
+#define EH_ABI_VERSION 10700
 int32_t eh_abi_version(void);
 
 /* ---- tuning knobs (performance only; counts never depend on them) ------- */
@@ -204,6 +204,13 @@ typedef struct eh_trie_info {
   uint64_t b_merge;         /* sum over oriented edges (u,v) of 4 (d+(u) + d+(v)) */
   uint32_t max_out_degree;  /* max d+ */
   uint32_t reserved;
+  uint64_t b_target;        /* what triangle counting with target staging must read
+                               (pruned tries; 0 for a symmetric trie): for each vertex
+                               v with a non-empty N+(v) and an in-edge, 4 |N+(v)| + 32
+                               (the set, its work item and extent); for each in-edge
+                               u -> v of such a v, 4 |N+(u) after v| + 8 (the part of
+                               N+(u) above v, which is all that can meet N+(v), and its
+                               record).  Summed over the graphs of a batch. */
 } eh_trie_info;
 
 /* Builds the trie of one graph on the host (clean, rank, orient, CSR, set

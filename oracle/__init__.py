@@ -66,11 +66,17 @@ def _load():
         lib.orc_get_degree.argtypes = [vp, _u32p]
         lib.orc_get_oriented.argtypes = [vp, _u64p, _u32p]
         lib.orc_max_threads.restype = ctypes.c_int
-        for name in ("orc_triangles_range", "orc_4cliques_range"):
-            f = getattr(lib, name)
-            f.restype = ctypes.c_uint64
-            f.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, _u64p, _u64p,
-                          _u64p, _u64p]
+        lib.orc_triangles_range.restype = ctypes.c_uint64
+        lib.orc_triangles_range.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                            _u64p, _u64p, _u64p, _u64p]
+        lib.orc_4cliques_range.restype = ctypes.c_uint64
+        lib.orc_4cliques_range.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                           _u64p, _u64p, _u64p, _u64p, _u64p]
+        lib.orc_target_reads.restype = ctypes.c_uint64
+        lib.orc_target_reads.argtypes = [vp, _u64p]
+        lib.orc_batch_triangles.restype = ctypes.c_int
+        lib.orc_batch_triangles.argtypes = [ctypes.c_uint32, _u32p, _u64p, _u32p, _u32p,
+                                            ctypes.c_int, _u64p, _u64p, _u64p]
         for name in ("orc_sym_triangle_sum", "orc_sym_4clique_sum", "orc_sym_ordered_triangles",
                      "orc_sym_ordered_4cliques"):
             f = getattr(lib, name)
@@ -163,16 +169,21 @@ class Graph:
         return off, nbr
 
     # -- counts --------------------------------------------------------------
-    def _run(self, fn, threads, rooted, per_vertex, x_begin, x_end):
+    def _run(self, fn, threads, rooted, per_vertex, x_begin, x_end, held=False):
         root = np.zeros(self.n, np.uint64) if rooted else None
         cv = np.zeros(self.n, np.uint64) if per_vertex else None
         b = ctypes.c_uint64(0)
         e = ctypes.c_uint64(0)
+        h = ctypes.c_uint64(0)
         xe = self.n if x_end is None else int(x_end)
+        extra = (ctypes.byref(h),) if held else ()
         total = fn(self._h, int(x_begin), xe, int(threads), _p64(root), _p64(cv), ctypes.byref(b),
-                   ctypes.byref(e))
-        return {"count": int(total), "root": root, "per_vertex": cv, "bytes": int(b.value),
-                "edges": int(e.value)}
+                   ctypes.byref(e), *extra)
+        out = {"count": int(total), "root": root, "per_vertex": cv, "bytes": int(b.value),
+               "edges": int(e.value)}
+        if held:
+            out["held_bytes"] = int(h.value)
+        return out
 
     def triangles(self, threads: int = 0, rooted: bool = False, per_vertex: bool = False,
                   x_begin: int = 0, x_end: int | None = None) -> dict:
@@ -184,8 +195,21 @@ class Graph:
 
     def cliques4(self, threads: int = 0, rooted: bool = False, per_vertex: bool = False,
                  x_begin: int = 0, x_end: int | None = None) -> dict:
-        """K; ``bytes`` is B_K4 over the visited oriented edges."""
-        return self._run(self._lib.orc_4cliques_range, threads, rooted, per_vertex, x_begin, x_end)
+        """K; ``bytes`` is B_K4 over the visited oriented edges, ``held_bytes``
+        B_K4_held (the reads when N+(x) and S_xy are held on chip)."""
+        return self._run(self._lib.orc_4cliques_range, threads, rooted, per_vertex, x_begin, x_end,
+                         held=True)
+
+    def target_reads(self) -> dict:
+        """B_target: the reads of the triangle sum with N+(y) of the middle
+        attribute held and only the part of N+(x) above y streamed per in-edge
+        x -> y.  Returns the bytes and their four parts."""
+        out = np.zeros(4, np.uint64)
+        b = int(self._lib.orc_target_reads(self._h, _p64(out)))
+        if b == 2**64 - 1:
+            raise MemoryError("oracle out of memory")
+        return {"bytes": b, "held_sets": int(out[0]), "held_members": int(out[1]),
+                "parts": int(out[2]), "streamed": int(out[3])}
 
     def count(self, pattern: int, threads: int = 0) -> int:
         if pattern == 3:
@@ -232,6 +256,29 @@ def pair_intersections(off, members, pairs, threads: int = 0):
     if tot == 2**64 - 1:
         raise ValueError("a pair names a set index out of range")
     return int(tot), out
+
+
+def batch_triangles(n_vertices, edge_off, src, dst, threads: int = 0):
+    """Per-graph T of many independent graphs, graphs counted in parallel:
+    graph i has n_vertices[i] vertices and the raw pairs src/dst[edge_off[i]:
+    edge_off[i+1]] with local ids.  Returns (counts, b_merge, b_target), each
+    uint64 per graph."""
+    nv = np.ascontiguousarray(n_vertices, dtype=np.uint32)
+    off = np.ascontiguousarray(edge_off, dtype=np.uint64)
+    src = np.ascontiguousarray(src, dtype=np.uint32)
+    dst = np.ascontiguousarray(dst, dtype=np.uint32)
+    if off.size != nv.size + 1 or src.shape != dst.shape or int(off[-1]) > src.size:
+        raise ValueError("batch arrays do not agree")
+    counts = np.zeros(nv.size, np.uint64)
+    bm = np.zeros(nv.size, np.uint64)
+    bt = np.zeros(nv.size, np.uint64)
+    st = _load().orc_batch_triangles(nv.size, _p32(nv), _p64(off), _p32(src), _p32(dst),
+                                     int(threads), _p64(counts), _p64(bm), _p64(bt))
+    if st == 1:
+        raise ValueError("vertex id out of range")
+    if st == 2:
+        raise MemoryError("oracle out of memory")
+    return counts, bm, bt
 
 
 def rooted_count(root_by_id: np.ndarray, roots) -> int:

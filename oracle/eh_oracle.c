@@ -34,9 +34,23 @@
  * sorted sets, by the same two-pointer merge; the layouts of section 4.3
  * change how a set is stored, never this count.
  *
- * Byte models (the reads a list-merge implementation performs):
+ * Byte models.  What a list-merge implementation reads (section 4.2: both
+ * sets of every intersection read once):
  *   B_merge = sum over oriented edges (x,y) of 4 (|N+(x)| + |N+(y)|)
  *   B_K4    = B_merge + sum over triangles x<y<z of 4 (|S_xy| + |N+(z)|)
+ * What an implementation that holds one set of each intersection on chip
+ * must read (a model of that design, not of the paper; sizes in bytes):
+ *   B_target (triangles, the held set is N+(y) of the middle attribute): for
+ *     every y with a non-empty N+(y) and at least one in-edge, N+(y) once
+ *     (4 per member) plus 32 for its work descriptor; for every in-edge
+ *     x -> y of such a y, the part of N+(x) above y (4 per member: every
+ *     member of N+(y) is above y, so nothing below can match) plus an
+ *     8-byte descriptor of that part.
+ *   B_K4_held (4-cliques, N+(x) held, S_xy kept on chip): the pair (x,y) is
+ *     extended only when N+(x) after y and N+(y) both hold two or more
+ *     members (a 4-clique needs two more vertices in each); per extended
+ *     pair 4 (the id y) + 8 (its set's extent) + 4 |N+(y)|; when |S_xy| >= 2,
+ *     per z in S_xy 8 + 4 |N+(z)|; per x with an extended pair 16 + 4 |N+(x)|.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -68,14 +82,6 @@ static int cmp_u32(const void* a, const void* b) {
   return x < y ? -1 : (x > y ? 1 : 0);
 }
 
-/* vertices sorted by (degree ascending, id ascending) */
-static const uint32_t* g_sort_deg;
-static int cmp_deg_id(const void* a, const void* b) {
-  uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
-  uint32_t dx = g_sort_deg[x], dy = g_sort_deg[y];
-  if (dx != dy) return dx < dy ? -1 : 1;
-  return x < y ? -1 : (x > y ? 1 : 0);
-}
 
 void orc_graph_free(orc_graph* g) {
   if (!g) return;
@@ -149,10 +155,13 @@ orc_graph* orc_graph_new(uint32_t n, uint64_t m_raw, const uint32_t* src,
   free(key);
   /* 4: degree in G */
   for (uint64_t i = 0; i < m; ++i) { g->deg[g->ea[i]]++; g->deg[g->eb[i]]++; }
-  /* 5: rank by (degree asc, id asc) */
-  for (uint32_t v = 0; v < n; ++v) g->vert[v] = v;
-  g_sort_deg = g->deg;
-  qsort(g->vert, n, sizeof(uint32_t), cmp_deg_id);
+  /* 5: rank by (degree asc, id asc): sort the keys degree * 2^32 + id */
+  uint64_t* dk = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
+  if (!dk) { *err = 2; orc_graph_free(g); return NULL; }
+  for (uint32_t v = 0; v < n; ++v) dk[v] = ((uint64_t)g->deg[v] << 32) | v;
+  qsort(dk, n, sizeof(uint64_t), cmp_u64);
+  for (uint32_t r = 0; r < n; ++r) g->vert[r] = (uint32_t)(dk[r] & 0xffffffffu);
+  free(dk);
   for (uint32_t r = 0; r < n; ++r) g->rank[g->vert[r]] = r;
   if (orient(g)) { *err = 2; orc_graph_free(g); return NULL; }
   return g;
@@ -297,15 +306,15 @@ uint64_t orc_triangles(const orc_graph* g, int threads, uint64_t* root_by_id, ui
 /* 4-cliques over outer vertices x in [x_begin, x_end); same optional outputs */
 uint64_t orc_4cliques_range(const orc_graph* g, uint32_t x_begin, uint32_t x_end, int threads,
                             uint64_t* root_by_id, uint64_t* c4_by_id, uint64_t* bytes,
-                            uint64_t* edges) {
+                            uint64_t* edges, uint64_t* held_bytes) {
   set_threads(threads);
-  uint64_t total = 0, b = 0, e = 0;
+  uint64_t total = 0, b = 0, e = 0, hb = 0;
   if (x_end > g->n) x_end = g->n;
   const int64_t xb = x_begin, xe = x_end;
   uint64_t dmax = 0;
   for (uint32_t r = 0; r < g->n; ++r)
     if (g->off[r + 1] - g->off[r] > dmax) dmax = g->off[r + 1] - g->off[r];
-#pragma omp parallel reduction(+ : total, b, e)
+#pragma omp parallel reduction(+ : total, b, e, hb)
   {
     uint32_t* s = (uint32_t*)malloc((dmax ? dmax : 1) * sizeof(uint32_t));
     uint32_t* t = (uint32_t*)malloc((dmax ? dmax : 1) * sizeof(uint32_t));
@@ -314,18 +323,25 @@ uint64_t orc_4cliques_range(const orc_graph* g, uint32_t x_begin, uint32_t x_end
       const uint32_t* nx = g->nbr + g->off[x];
       const uint64_t dx = g->off[x + 1] - g->off[x];
       uint64_t kx = 0;
+      int extended = 0;
       for (uint64_t i = 0; i < dx; ++i) {
         const uint32_t y = nx[i];
         const uint32_t* ny = g->nbr + g->off[y];
         const uint64_t dy = g->off[y + 1] - g->off[y];
         const uint64_t ns = merge_list(nx, dx, ny, dy, s);   /* S = N+(x) & N+(y) */
         b += 4 * (dx + dy);
+        const int ext = dx - i - 1 >= 2 && dy >= 2;
+        if (ext) {
+          extended = 1;
+          hb += 4 + 8 + 4 * dy;
+        }
         uint64_t kxy = 0;
         for (uint64_t j = 0; j < ns; ++j) {
           const uint32_t z = s[j];
           const uint32_t* nz = g->nbr + g->off[z];
           const uint64_t dz = g->off[z + 1] - g->off[z];
           b += 4 * (ns + dz);
+          if (ext && ns >= 2) hb += 8 + 4 * dz;
           if (c4_by_id) {
             const uint64_t c = merge_list(s, ns, nz, dz, t);   /* w in S & N+(z) */
             for (uint64_t q = 0; q < c; ++q) add_u64(&c4_by_id[g->vert[t[q]]], 1);
@@ -341,6 +357,7 @@ uint64_t orc_4cliques_range(const orc_graph* g, uint32_t x_begin, uint32_t x_end
         }
         kx += kxy;
       }
+      if (extended) hb += 16 + 4 * dx;
       e += dx;
       total += kx;
       if (root_by_id) root_by_id[g->vert[x]] += kx;
@@ -350,12 +367,100 @@ uint64_t orc_4cliques_range(const orc_graph* g, uint32_t x_begin, uint32_t x_end
   }
   if (bytes) *bytes = b;
   if (edges) *edges = e;
+  if (held_bytes) *held_bytes = hb;
   return total;
 }
 
 uint64_t orc_4cliques(const orc_graph* g, int threads, uint64_t* root_by_id, uint64_t* c4_by_id,
                       uint64_t* bytes) {
-  return orc_4cliques_range(g, 0, g->n, threads, root_by_id, c4_by_id, bytes, NULL);
+  return orc_4cliques_range(g, 0, g->n, threads, root_by_id, c4_by_id, bytes, NULL, NULL);
+}
+
+/*
+ * The reads of B_target (see the header): the triangle sum taken with the
+ * middle attribute y outermost, N+(y) held, and for each in-edge x -> y only
+ * N+(x) after y streamed.  out[0] = held sets, out[1] = their members,
+ * out[2] = streamed parts (in-edges of held sets), out[3] = streamed members.
+ * Returns B_target = 32 out[0] + 4 out[1] + 8 out[2] + 4 out[3].
+ */
+uint64_t orc_target_reads(const orc_graph* g, uint64_t* out) {
+  const uint32_t n = g->n;
+  unsigned char* has_in = (unsigned char*)calloc(n ? n : 1, 1);
+  if (!has_in) return UINT64_MAX;
+  uint64_t parts = 0, streamed = 0;
+  for (uint32_t x = 0; x < n; ++x) {
+    const uint64_t dx = g->off[x + 1] - g->off[x];
+    for (uint64_t i = 0; i < dx; ++i) {
+      const uint32_t y = g->nbr[g->off[x] + i];
+      if (g->off[y + 1] == g->off[y]) continue;  /* N+(y) empty: nothing to meet */
+      has_in[y] = 1;
+      parts += 1;
+      streamed += dx - i - 1;                    /* members of N+(x) after y */
+    }
+  }
+  uint64_t held = 0, held_members = 0;
+  for (uint32_t y = 0; y < n; ++y)
+    if (has_in[y]) {
+      held += 1;
+      held_members += g->off[y + 1] - g->off[y];
+    }
+  free(has_in);
+  if (out) {
+    out[0] = held;
+    out[1] = held_members;
+    out[2] = parts;
+    out[3] = streamed;
+  }
+  return 32 * held + 4 * held_members + 8 * parts + 4 * streamed;
+}
+
+/*
+ * Many independent graphs: graph i has n_vertices[i] vertices and the raw
+ * pairs src/dst[edge_off[i] .. edge_off[i+1]) with local ids.  Graphs are
+ * counted in parallel, each by the same definition as orc_triangles on one
+ * thread.  Per graph: counts[i] = T, and (optional) b_merge[i], b_target[i].
+ * Returns 0, 1 if an id is out of range (that graph's count is then
+ * UINT64_MAX), 2 if memory ran out.
+ */
+int orc_batch_triangles(uint32_t n_graphs, const uint32_t* n_vertices, const uint64_t* edge_off,
+                        const uint32_t* src, const uint32_t* dst, int threads, uint64_t* counts,
+                        uint64_t* b_merge, uint64_t* b_target) {
+  set_threads(threads);
+  int status = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < (int64_t)n_graphs; ++i) {
+    int err = 0;
+    const uint64_t e0 = edge_off[i], e1 = edge_off[i + 1];
+    orc_graph* g = orc_graph_new(n_vertices[i], e1 - e0, src + e0, dst + e0, &err);
+    if (!g) {
+      counts[i] = UINT64_MAX;
+#pragma omp critical
+      if (err > status) status = err;
+      continue;
+    }
+    uint64_t t = 0, b = 0;
+    for (uint32_t x = 0; x < g->n; ++x) {
+      const uint32_t* nx = g->nbr + g->off[x];
+      const uint64_t dx = g->off[x + 1] - g->off[x];
+      for (uint64_t j = 0; j < dx; ++j) {
+        const uint32_t y = nx[j];
+        const uint64_t dy = g->off[y + 1] - g->off[y];
+        t += merge_count(nx, dx, g->nbr + g->off[y], dy);
+        b += 4 * (dx + dy);
+      }
+    }
+    counts[i] = t;
+    if (b_merge) b_merge[i] = b;
+    if (b_target) {
+      b_target[i] = orc_target_reads(g, NULL);
+      if (b_target[i] == UINT64_MAX) {
+#pragma omp critical
+        status = 2;
+      }
+    }
+    orc_graph_free(g);
+  }
+  return status;
 }
 
 /* ---- cross-checks without orientation ---------------------------------- */

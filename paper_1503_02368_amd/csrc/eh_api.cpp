@@ -627,6 +627,7 @@ static void fill_info(const HostTrie& h, eh_trie_info* out) {
   out->b_merge = h.b_merge;
   out->max_out_degree = h.dmax;
   out->reserved = 0;
+  out->b_target = h.b_target;
 }
 
 eh_status eh_trie_info_get(const eh_trie* trie, eh_trie_info* out) {

@@ -256,16 +256,30 @@ eh_status build_one(const uint32_t* src, const uint32_t* dst, uint64_t m_raw, ui
       h.col[fill[eu[i]]++] = ev[i];
     }
   }
-  // statistics
+  // statistics: B_merge (both sets of every intersection read once), and
+  // B_target (target staging on a pruned trie: N+(v) read once, with a
+  // 32-byte item and extent, for each v with a non-empty set and an in-edge;
+  // per such in-edge u->v the members of N+(u) after v and an 8-byte record)
   h.dmax = 0;
   h.b_merge = 0;
-  for (uint32_t u = 0; u < n; ++u) {
-    const uint32_t du = h.row[u + 1] - h.row[u];
-    h.dmax = std::max(h.dmax, du);
-    for (uint32_t e = h.row[u]; e < h.row[u + 1]; ++e) {
-      const uint32_t v = h.col[e];
-      h.b_merge += 4ull * (du + (h.row[v + 1] - h.row[v]));
+  h.b_target = 0;
+  {
+    std::vector<uint8_t> held(opts.symmetric ? 0 : n, 0);
+    for (uint32_t u = 0; u < n; ++u) {
+      const uint32_t du = h.row[u + 1] - h.row[u];
+      h.dmax = std::max(h.dmax, du);
+      for (uint32_t e = h.row[u]; e < h.row[u + 1]; ++e) {
+        const uint32_t v = h.col[e];
+        const uint32_t dv = h.row[v + 1] - h.row[v];
+        h.b_merge += 4ull * (du + dv);
+        if (!opts.symmetric && dv) {
+          held[v] = 1;
+          h.b_target += 8ull + 4ull * (h.row[u + 1] - e - 1);
+        }
+      }
     }
+    for (uint32_t v = 0; v < held.size(); ++v)
+      if (held[v]) h.b_target += 32ull + 4ull * (h.row[v + 1] - h.row[v]);
   }
   // set layouts
   h.bs_off.assign(n, kNoBitset);
@@ -440,10 +454,12 @@ eh_status host_build_batch(uint32_t n_graphs, const uint32_t* n_vertices, const 
   h.row[N] = uint32_t(M);
   h.dmax = 0;
   h.b_merge = 0;
+  h.b_target = 0;
   h.n_bs = 0;
   for (uint32_t g = 0; g < n_graphs; ++g) {
     h.dmax = std::max(h.dmax, parts[g].dmax);
     h.b_merge += parts[g].b_merge;
+    h.b_target += parts[g].b_target;
     h.n_bs += parts[g].n_bs;
   }
   return EH_OK;

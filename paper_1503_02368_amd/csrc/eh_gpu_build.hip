@@ -298,18 +298,44 @@ __global__ void __launch_bounds__(kB) k_layout(const unsigned long long* __restr
 }
 
 // stats[2] += B_merge = sum over oriented edges (u, v) of 4 (d+(u) + d+(v)).
+// target != 0 (pruned tries): stats[3] += the streamed part of B_target, per
+// edge u -> v with a non-empty N+(v) an 8-byte record and 4 bytes for each
+// member of N+(u) after v (edge i is member i - row[u] of N+(u)).
 __global__ void __launch_bounds__(kB) k_bmerge(const unsigned long long* __restrict__ key,
                                                const uint32_t* __restrict__ row, uint64_t m,
-                                               uint32_t kb, unsigned long long* __restrict__ stats) {
+                                               uint32_t kb, uint32_t target,
+                                               unsigned long long* __restrict__ stats) {
   const unsigned long long mask = (1ull << kb) - 1;
-  unsigned long long sum = 0;
+  unsigned long long sum = 0, tsum = 0;
   uint32_t unused = 0;
   for (uint64_t i = gtid(); i < m; i += gstride()) {
     const uint64_t u = key[i] >> kb, v = key[i] & mask;
-    sum += 4ull * ((row[u + 1] - row[u]) + (row[v + 1] - row[v]));
+    const uint32_t dv = row[v + 1] - row[v];
+    sum += 4ull * ((row[u + 1] - row[u]) + dv);
+    if (target && dv) tsum += 8ull + 4ull * (row[u + 1] - i - 1);
   }
   block_sum_max(sum, unused);
   if (threadIdx.x == 0 && sum) atomicAdd(&stats[2], sum);
+  if (!target) return;
+  __syncthreads();  // block_sum_max's shared slots are reused
+  block_sum_max(tsum, unused);
+  if (threadIdx.x == 0 && tsum) atomicAdd(&stats[3], tsum);
+}
+
+// stats[3] += the held part of B_target: 32 + 4 d+(r) for each rank r with a
+// non-empty out-set and an in-edge (its degree in G exceeds its out-degree).
+__global__ void __launch_bounds__(kB) k_btarget_held(const uint32_t* __restrict__ row,
+                                                     const uint32_t* __restrict__ deg,
+                                                     const uint32_t* __restrict__ vert, uint32_t n,
+                                                     unsigned long long* __restrict__ stats) {
+  unsigned long long sum = 0;
+  uint32_t unused = 0;
+  for (uint64_t r = gtid(); r < n; r += gstride()) {
+    const uint32_t d = row[r + 1] - row[r];
+    if (d && deg[vert[r]] > d) sum += 32ull + 4ull * d;
+  }
+  block_sum_max(sum, unused);
+  if (threadIdx.x == 0 && sum) atomicAdd(&stats[3], sum);
 }
 
 // col[i] = the member; a bitset set also gets its bit in the words that
@@ -578,7 +604,10 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
                      ptr<uint32_t>(nw), ptr<uint32_t>(base), stat);
   if (m)
     hipLaunchKernelGGL(k_bmerge, dim3(grid_of(m)), dim3(kB), 0, s, ka, ptr<uint32_t>(row), m, kb,
-                       stat);
+                       opts.symmetric ? 0u : 1u, stat);
+  if (n && !opts.symmetric)
+    hipLaunchKernelGGL(k_btarget_held, dim3(grid_of(n)), dim3(kB), 0, s, ptr<uint32_t>(row),
+                       ptr<uint32_t>(deg), ptr<uint32_t>(t.vert), n, stat);
   tmp_bytes = tmp.bytes;
   if ((st = chk(rocprim::exclusive_scan(tmp.p, tmp_bytes, ptr<uint32_t>(nw),
                                         ptr<unsigned long long>(off), 0ull, size_t(n) + 1,
@@ -586,8 +615,8 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
                 "word offset scan")) != EH_OK)
     return st;
   if ((st = chk(hipGetLastError(), "build kernels")) != EH_OK) return st;
-  unsigned long long h_stat[3] = {0, 0, 0}, W = 0;
-  if ((st = download(c, h_stat, stat, 24, "read build statistics")) != EH_OK ||
+  unsigned long long h_stat[4] = {0, 0, 0, 0}, W = 0;
+  if ((st = download(c, h_stat, stat, 32, "read build statistics")) != EH_OK ||
       (st = download(c, &W, ptr<unsigned long long>(off) + n, 8, "read word count")) != EH_OK ||
       (st = chk(hipStreamSynchronize(s), "build sync")) != EH_OK)
     return st;
@@ -619,6 +648,7 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
   h.m = m;
   h.dmax = uint32_t(h_stat[1]);
   h.b_merge = h_stat[2];
+  h.b_target = h_stat[3];
   h.n_bs = n_bs;
   h.n_graphs = G;
   h.g_vbase = batch ? batch->vbase : std::vector<uint32_t>{0, n};

@@ -48,6 +48,7 @@ struct HostTrie {
   uint64_t m = 0;                    // stored edges (oriented, or both directions)
   uint32_t dmax = 0;                 // max out-degree
   uint64_t b_merge = 0;
+  uint64_t b_target = 0;             // reads of target-staged triangle counting (0: symmetric)
   std::vector<uint32_t> rank;        // rank[id]
   std::vector<uint32_t> vert;        // vert[rank] = id
   std::vector<uint32_t> row;         // [n+1]

@@ -61,7 +61,7 @@ class _Allocator(ctypes.Structure):
 
 
 # struct layouts below are those of this ABI version of include/eh.h
-ABI_VERSION = 10600
+ABI_VERSION = 10700
 
 
 class _Tuning(ctypes.Structure):
@@ -83,7 +83,8 @@ class _TrieInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("n_graphs", ctypes.c_uint32), ("m_plus", ctypes.c_uint64),
                 ("n_bitset_sets", ctypes.c_uint64), ("bitset_words", ctypes.c_uint64),
                 ("device_bytes", ctypes.c_uint64), ("b_merge", ctypes.c_uint64),
-                ("max_out_degree", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("max_out_degree", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("b_target", ctypes.c_uint64)]
 
 
 class _SetOpts(ctypes.Structure):

@@ -54,6 +54,7 @@ def test_trie_matches_oracle(el):
     np.testing.assert_array_equal(h["row"], off.astype(np.uint32))
     np.testing.assert_array_equal(h["col"], nbr)
     assert h["b_merge"] == g.triangles()["bytes"]
+    assert h["b_target"] == g.target_reads()["bytes"]
     d = np.diff(h["row"].astype(np.int64))
     assert h["max_out_degree"] == (d.max() if d.size else 0)
 
@@ -76,8 +77,15 @@ def test_node_orderings_match_oracle(el, order):
     np.testing.assert_array_equal(h["row"], off.astype(np.uint32))
     np.testing.assert_array_equal(h["col"], nbr)
     assert h["b_merge"] == g.triangles()["bytes"]
+    assert h["b_target"] == g.target_reads()["bytes"]
     d = np.diff(h["row"].astype(np.int64))
     assert h["max_out_degree"] == (d.max() if d.size else 0)
+
+
+def test_symmetric_trie_has_no_target_model():
+    el = inputs.rmat(9, 16, seed=5)
+    assert eh.host_trie(el.n, el.src, el.dst, symmetric=True)["b_target"] == 0
+    assert eh.host_trie(el.n, el.src, el.dst)["b_target"] > 0
 
 
 def expand_bitset(h, r):

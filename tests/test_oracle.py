@@ -106,6 +106,121 @@ def test_complete_closed_form(n):
     assert t["bytes"] == 2 * n * (n - 1) ** 2
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 9, 33, 64, 101])
+def test_complete_byte_models(n):
+    """The byte models on K_n, summed by hand over its ranks 0..n-1, where
+    N+(r) = {r+1, ..., n-1}.
+
+    B_K4: for x<y<z, |S_xy| = n-1-y and |N+(z)| = n-1-z; the triple sum of
+    y + z is C(n,3) (3(n-1)/2 - (n-3)/4), which gives (3n-5) C(n,3) beside
+    B_merge = 2n(n-1)^2.
+    B_K4_held: the pair (x,y) extends iff y <= n-3; with k = n-1-y its reads
+    are 12 + 4k, its level-2 reads 2k^2 + 6k, and each x <= n-4 adds
+    16 + 4(n-1-x): 4 C(n+3,4) + 2n(n-1) - 24n for n >= 3.
+    B_target: held sets y = 1..n-2 (n-2 of them, (n-1)(n-2)/2 members); y has
+    y in-edges, each streaming the n-1-y members above y, C(n,3) in all.
+    """
+    g = oracle.Graph.from_edgelist(inputs.complete(n))
+    k = g.cliques4()
+    assert k["bytes"] == 2 * n * (n - 1) ** 2 + (3 * n - 5) * math.comb(n, 3)
+    want_held = 4 * math.comb(n + 3, 4) + 2 * n * (n - 1) - 24 * n if n >= 3 else 0
+    assert k["held_bytes"] == want_held
+    r = g.target_reads()
+    if n >= 2:
+        assert r["held_sets"] == n - 2
+        assert r["held_members"] == r["parts"] == (n - 1) * (n - 2) // 2
+        assert r["streamed"] == math.comb(n, 3)
+        assert r["bytes"] == 6 * (n - 1) * (n - 2) + 32 * (n - 2) + 4 * math.comb(n, 3)
+    else:
+        assert r["bytes"] == 0
+
+
+def brute_bytes(el):
+    """The byte models by brute force over rank-ordered vertex triples, with
+    ranks and out-sets derived here from the adjacency sets."""
+    n = el.n
+    adj = [set() for _ in range(n)]
+    for a, b in zip(el.src.tolist(), el.dst.tolist()):
+        if a != b:
+            adj[a].add(b)
+            adj[b].add(a)
+    order = sorted(range(n), key=lambda v: (len(adj[v]), v))
+    rk = {v: i for i, v in enumerate(order)}
+    up = {v: {w for w in adj[v] if rk[w] > rk[v]} for v in range(n)}
+    d = {v: len(up[v]) for v in range(n)}
+    b_merge = sum(4 * (d[x] + d[y]) for x in range(n) for y in up[x])
+    b_k4 = b_merge
+    held = 0
+    extended_roots = set()
+    for x in range(n):
+        for y in up[x]:
+            after = sum(1 for w in up[x] if rk[w] > rk[y])
+            ext = after >= 2 and d[y] >= 2
+            s = up[x] & up[y]
+            if ext:
+                extended_roots.add(x)
+                held += 12 + 4 * d[y]
+            for z in s:                     # triangle x < y < z in rank order
+                b_k4 += 4 * (len(s) + d[z])
+                if ext and len(s) >= 2:
+                    held += 8 + 4 * d[z]
+    held += sum(16 + 4 * d[x] for x in extended_roots)
+    # target staging: y held when some x -> y exists and N+(y) is not empty
+    tgt = 0
+    for y in range(n):
+        ins = [x for x in range(n) if y in up[x]]
+        if ins and d[y] > 0:
+            tgt += 32 + 4 * d[y]
+            for x in ins:
+                tgt += 8 + 4 * sum(1 for w in up[x] if rk[w] > rk[y])
+    return b_merge, b_k4, held, tgt
+
+
+@pytest.mark.parametrize("n,p,seed", [(n, p, s) for n in (7, 13, 22, 30)
+                                      for p in (0.2, 0.5, 0.85) for s in (1, 2)])
+def test_byte_models_brute_force(n, p, seed):
+    el = inputs.gnp(n, p, seed)
+    g = oracle.Graph.from_edgelist(el)
+    b_merge, b_k4, held, tgt = brute_bytes(el)
+    assert g.triangles()["bytes"] == b_merge
+    k = g.cliques4()
+    assert (k["bytes"], k["held_bytes"]) == (b_k4, held)
+    assert g.target_reads()["bytes"] == tgt
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_byte_models_messy_and_sparse(seed):
+    """Sinks (empty out-sets), isolated vertices and messy input."""
+    el = inputs.messy(inputs.disjoint_union(inputs.gnp(18, 0.3, seed), inputs.star(6),
+                                            inputs.path(5)), seed)
+    g = oracle.Graph.from_edgelist(el)
+    b_merge, b_k4, held, tgt = brute_bytes(el)
+    k = g.cliques4()
+    assert (g.triangles()["bytes"], k["bytes"], k["held_bytes"]) == (b_merge, b_k4, held)
+    assert g.target_reads()["bytes"] == tgt
+
+
+def test_batch_oracle_equals_single_graphs():
+    """The parallel batch count is the single-graph count of each graph, in
+    any order of the graphs."""
+    b = inputs.batch_chung_lu(60, seed=11)
+    counts, bm, bt = oracle.batch_triangles(b.n_vertices, b.edge_off, b.src, b.dst)
+    for i in range(60):
+        g = oracle.Graph.from_edgelist(b.graph(i))
+        t = g.triangles()
+        assert (int(counts[i]), int(bm[i])) == (t["count"], t["bytes"])
+        assert int(bt[i]) == g.target_reads()["bytes"]
+    perm = np.random.default_rng(3).permutation(60)
+    nv = np.asarray(b.n_vertices)[perm]
+    parts_s = [b.graph(i).src for i in perm]
+    parts_d = [b.graph(i).dst for i in perm]
+    off = np.concatenate([[0], np.cumsum([len(x) for x in parts_s])]).astype(np.uint64)
+    c2, _, _ = oracle.batch_triangles(nv, off, np.concatenate(parts_s), np.concatenate(parts_d))
+    np.testing.assert_array_equal(c2, counts[perm])
+    with pytest.raises(ValueError):
+        oracle.batch_triangles([3], [0, 1], np.array([0], np.uint32), np.array([3], np.uint32))
+
+
 @pytest.mark.parametrize("el", [inputs.grid(7, 9), inputs.complete_bipartite(6, 9), inputs.star(40),
                                 inputs.random_tree(300, 3), inputs.path(50), inputs.cycle(4),
                                 inputs.cycle(5), inputs.cycle(97)], ids=lambda e: e.name)
