@@ -86,7 +86,7 @@ const char* eh_last_error(const eh_ctx* ctx);
 const char* eh_status_str(eh_status s);
 /* Version of this ABI (major * 10000 + minor * 100 + patch); a caller built
  * against this header checks that the library returns EH_ABI_VERSION. */
-#define EH_ABI_VERSION 10700
+#define EH_ABI_VERSION 10800
 int32_t eh_abi_version(void);
 
 /* ---- tuning knobs (performance only; counts never depend on them) ------- */
@@ -318,6 +318,21 @@ eh_status eh_count_batch(eh_ctx* ctx, const eh_trie* batch, int pattern, uint32_
 /* Enqueue-only batch form; d_out: device array of count uint64. */
 eh_status eh_count_batch_async(eh_ctx* ctx, const eh_trie* batch, int pattern, uint32_t first,
                                uint32_t count, uint64_t* d_out);
+
+/* ---- measurement ---------------------------------------------------------- */
+
+/* Streaming-read probe (not part of the method): enqueues one kernel that
+ * reads every byte of d_buf once, with 128-bit loads over a grid-stride loop,
+ * and XORs a fold of what it read into *d_sink (one uint64, device), so that
+ * timing it (events on the context's stream) gives the read bandwidth a plain
+ * read-only kernel reaches on this GPU, the practical ceiling beside the
+ * nominal HBM peak for the counting kernels' byte models.  d_buf: device
+ * memory of `bytes` bytes, 16-byte aligned, bytes a positive multiple of 16
+ * (EH_EINVAL otherwise); only read.  blocks_per_cu: blocks of 256 lanes per
+ * compute unit, 1..64 (0 means 8).  A buffer larger than the 256 MB
+ * last-level cache measures HBM. */
+eh_status eh_stream_read(eh_ctx* ctx, const void* d_buf, uint64_t bytes, uint32_t blocks_per_cu,
+                         uint64_t* d_sink);
 
 /* ---- serving ------------------------------------------------------------ */
 

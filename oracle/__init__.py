@@ -72,6 +72,8 @@ def _load():
         lib.orc_4cliques_range.restype = ctypes.c_uint64
         lib.orc_4cliques_range.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
                                            _u64p, _u64p, _u64p, _u64p, _u64p]
+        lib.orc_4cliques_rooted_at.restype = ctypes.c_uint64
+        lib.orc_4cliques_rooted_at.argtypes = [vp, _u32p, ctypes.c_uint64, ctypes.c_int, _u64p]
         lib.orc_target_reads.restype = ctypes.c_uint64
         lib.orc_target_reads.argtypes = [vp, _u64p]
         lib.orc_batch_triangles.restype = ctypes.c_int
@@ -199,6 +201,16 @@ class Graph:
         B_K4_held (the reads when N+(x) and S_xy are held on chip)."""
         return self._run(self._lib.orc_4cliques_range, threads, rooted, per_vertex, x_begin, x_end,
                          held=True)
+
+    def cliques4_rooted_at(self, ids, threads: int = 0) -> np.ndarray:
+        """Per original id, the 4-cliques rooted there (vertex of smallest rank),
+        computed only for the ids listed (repeats ignored); 0 elsewhere."""
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        root = np.zeros(self.n, np.uint64)
+        tot = self._lib.orc_4cliques_rooted_at(self._h, _p32(ids), ids.size, int(threads), _p64(root))
+        if tot == 2**64 - 1:
+            raise ValueError("id out of range, or oracle out of memory")
+        return root
 
     def target_reads(self) -> dict:
         """B_target: the reads of the triangle sum with N+(y) of the middle

@@ -377,6 +377,68 @@ uint64_t orc_4cliques(const orc_graph* g, int threads, uint64_t* root_by_id, uin
 }
 
 /*
+ * 4-cliques rooted at given vertices: for each distinct original id r in
+ * ids[0 .. n_ids), root_by_id[r] = the 4-cliques whose vertex of smallest
+ * rank is r, by the same loop nest as orc_4cliques_range with x = rank(r).
+ * Entries of ids not listed are left untouched.  Returns the sum over the
+ * distinct ids, UINT64_MAX if an id is out of range or memory ran out.
+ */
+uint64_t orc_4cliques_rooted_at(const orc_graph* g, const uint32_t* ids, uint64_t n_ids,
+                                int threads, uint64_t* root_by_id) {
+  set_threads(threads);
+  for (uint64_t k = 0; k < n_ids; ++k)
+    if (ids[k] >= g->n) return UINT64_MAX;
+  unsigned char* seen = (unsigned char*)calloc(g->n ? g->n : 1, 1);
+  uint32_t* xs = (uint32_t*)malloc((n_ids ? n_ids : 1) * sizeof(uint32_t));
+  if (!seen || !xs) {
+    free(seen);
+    free(xs);
+    return UINT64_MAX;
+  }
+  int64_t nx_roots = 0;
+  for (uint64_t k = 0; k < n_ids; ++k)
+    if (!seen[ids[k]]) {
+      seen[ids[k]] = 1;
+      xs[nx_roots++] = g->rank[ids[k]];
+    }
+  free(seen);
+  uint64_t dmax = 0;
+  for (uint32_t r = 0; r < g->n; ++r)
+    if (g->off[r + 1] - g->off[r] > dmax) dmax = g->off[r + 1] - g->off[r];
+  uint64_t total = 0;
+  int oom = 0;
+#pragma omp parallel reduction(+ : total)
+  {
+    uint32_t* s = (uint32_t*)malloc((dmax ? dmax : 1) * sizeof(uint32_t));
+    if (!s) {
+#pragma omp atomic write
+      oom = 1;
+    }
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t k = 0; k < nx_roots; ++k) {
+      if (!s) continue;
+      const uint32_t x = xs[k];
+      const uint32_t* nx = g->nbr + g->off[x];
+      const uint64_t dx = g->off[x + 1] - g->off[x];
+      uint64_t kx = 0;
+      for (uint64_t i = 0; i < dx; ++i) {
+        const uint32_t y = nx[i];
+        const uint64_t ns = merge_list(nx, dx, g->nbr + g->off[y], g->off[y + 1] - g->off[y], s);
+        for (uint64_t j = 0; j < ns; ++j) {
+          const uint32_t z = s[j];
+          kx += merge_count(s, ns, g->nbr + g->off[z], g->off[z + 1] - g->off[z]);
+        }
+      }
+      root_by_id[g->vert[x]] = kx;
+      total += kx;
+    }
+    free(s);
+  }
+  free(xs);
+  return oom ? UINT64_MAX : total;
+}
+
+/*
  * The reads of B_target (see the header): the triangle sum taken with the
  * middle attribute y outermost, N+(y) held, and for each in-edge x -> y only
  * N+(x) after y streamed.  out[0] = held sets, out[1] = their members,

@@ -4,40 +4,41 @@ divide the known bytes by what the counter reports per dispatch.
 
     python -m paper_1503_02368_amd.calib [MiB]
 
-``probe_gbs()`` measures the bandwidth a plain streaming read and a copy
-reach on this GPU (the achievable ceiling beside the 8 TB/s nominal peak).
+``probe_gbs(ctx)`` times the library's hand-written streaming-read kernel
+over a buffer larger than the last-level cache: the read bandwidth a plain
+read-only kernel reaches on this GPU, the achievable ceiling beside the
+8 TB/s nominal peak.
 """
 import sys
 
 
-def probe_gbs(mib: int = 4096, reps: int = 10) -> dict:
-    """GB/s of a streaming read and of a copy (read + write) over `mib` MiB,
-    timed with HIP events over `reps` repetitions after a warm-up.  The read
-    figure is the best of three plain reductions over float32 data (sum, max
-    and a norm), each of which reads every byte once."""
+def probe_gbs(ctx, mib: int = 4096, reps: int = 10, blocks=(4, 8, 16)) -> dict:
+    """GB/s of the library's streaming-read kernel (eh_stream_read: 128-bit
+    loads over a grid-stride loop, every byte read once) over `mib` MiB, far
+    larger than the 256 MB last-level cache, timed with HIP events on the
+    context's stream over `reps` launches after a warm-up, for each count of
+    blocks per compute unit in `blocks`.  read = the best of them."""
     import torch
-    n = mib * (1 << 20) // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-
-    def gbs(fn, factor):
-        fn()
-        torch.cuda.synchronize()
+    nbytes = mib * (1 << 20)
+    buf = torch.zeros(nbytes // 8, dtype=torch.int64, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    s = ctx.stream
+    s.wait_stream(torch.cuda.current_stream())
+    by_blocks = {}
+    for b in blocks:
+        ctx.stream_read_async(buf, sink, b)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
+        e0.record(s)
         for _ in range(reps):
-            fn()
-        e1.record()
+            ctx.stream_read_async(buf, sink, b)
+        e1.record(s)
         torch.cuda.synchronize()
-        return factor * n * 4 / (e0.elapsed_time(e1) / reps / 1e3) / 1e9
-
-    reads = {"sum": gbs(lambda: a.sum(), 1), "max": gbs(lambda: a.amax(), 1),
-             "norm": gbs(lambda: torch.linalg.vector_norm(a, 1), 1)}
-    out = {"read": max(reads.values()), "read_by_op": reads, "copy": gbs(lambda: b.copy_(a), 2)}
-    del a, b
+        by_blocks[str(b)] = nbytes / (e0.elapsed_time(e1) / reps / 1e3) / 1e9
+    del buf, sink
     torch.cuda.empty_cache()
-    return out
+    return {"read": max(by_blocks.values()), "read_by_blocks_per_cu": by_blocks,
+            "kernel": "k_stream_read", "mib": mib}
 
 
 def main():

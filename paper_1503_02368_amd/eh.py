@@ -44,7 +44,7 @@ SYMBOLS = [
     "eh_build_trie_device", "eh_trie_host_arrays", "eh_trie_device_arrays", "eh_count_lollipop",
     "eh_build_batch_device", "eh_sets_build", "eh_sets_info_get", "eh_sets_free",
     "eh_intersect_pairs", "eh_intersect_pairs_async", "eh_host_sets_build", "eh_host_sets_info",
-    "eh_host_sets_arrays", "eh_host_sets_free",
+    "eh_host_sets_arrays", "eh_host_sets_free", "eh_stream_read",
 ]
 
 
@@ -61,7 +61,7 @@ class _Allocator(ctypes.Structure):
 
 
 # struct layouts below are those of this ABI version of include/eh.h
-ABI_VERSION = 10700
+ABI_VERSION = 10800
 
 
 class _Tuning(ctypes.Structure):
@@ -172,6 +172,7 @@ def load():
             "eh_sets_free": [_vp],
             "eh_intersect_pairs": [_vp, _vp, ctypes.c_uint64, _vp, _vp, ctypes.c_uint32, _u64p],
             "eh_intersect_pairs_async": [_vp, _vp, ctypes.c_uint64, _vp, _vp, ctypes.c_uint32, _vp],
+            "eh_stream_read": [_vp, _vp, ctypes.c_uint64, ctypes.c_uint32, _vp],
             "eh_host_sets_build": [ctypes.c_uint32, _u64p, _u32p, ctypes.POINTER(_SetOpts),
                                    ctypes.POINTER(_vp)],
             "eh_host_sets_info": [_vp, ctypes.POINTER(_SetsInfo)],
@@ -503,6 +504,14 @@ class Context:
         """Enqueues one counting launch that adds its count into d_total."""
         self._check(self._lib.eh_count_add_async(self._h, trie._h, int(pattern), _vp(d_total.data_ptr())),
                     "count_add_async")
+
+    def stream_read_async(self, d_buf, d_sink, blocks_per_cu: int = 0) -> None:
+        """Enqueues the streaming-read probe over the tensor d_buf (every byte
+        read once), folding what it read into the uint64 tensor d_sink."""
+        nbytes = d_buf.numel() * d_buf.element_size()
+        self._check(self._lib.eh_stream_read(self._h, _vp(d_buf.data_ptr()), nbytes,
+                                             int(blocks_per_cu), _vp(d_sink.data_ptr())),
+                    "stream_read")
 
     def count_rooted(self, trie, pattern: int, roots) -> int:
         r = _u32(roots)

@@ -26,12 +26,32 @@ import csv
 import glob
 import json
 import os
+import hashlib
 import statistics
-
-from paper_1503_02368_amd.bench_extra import kernel_sha
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
+KERNEL_SRC = os.path.join(HERE, "csrc", "eh_kernels.hip")
+SETS_SRC = os.path.join(HERE, "csrc", "eh_sets.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_sha(src: str = KERNEL_SRC) -> str:
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(name: str, src: str = KERNEL_SRC):
+    """L2-to-fabric bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)
+    from the committed rocprofv3 counter runs, or None when the kernel source
+    (src) changed since they were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        d = json.load(f).get(name)
+    if not d or d.get("kernel_sha") != kernel_sha(src):
+        return None
+    return d.get("bytes_per_launch")
 
 
 def _csv(d: str, suffix: str):

@@ -66,6 +66,23 @@ def test_brute_force_random(n, p, seed):
     np.testing.assert_array_equal(k["per_vertex"], c4)
 
 
+@pytest.mark.parametrize("n,p,seed", [(n, p, s) for n in (9, 20, 26) for p in (0.3, 0.8) for s in (1, 2)])
+def test_4cliques_rooted_at_brute_force(n, p, seed):
+    """4-cliques rooted at a chosen vertex subset (repeats in the list
+    ignored) against brute force over 4-subsets; unlisted ids stay 0."""
+    el = inputs.gnp(n, p, seed)
+    _, _, _, r4, _, _ = brute(el)
+    g = oracle.Graph.from_edgelist(el)
+    pick = np.arange(0, n, 3, dtype=np.uint32)
+    got = g.cliques4_rooted_at(np.concatenate([pick, pick[:2]]))
+    want = np.zeros(n, np.uint64)
+    want[pick] = r4[pick]
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(g.cliques4_rooted_at(np.arange(n)), r4)
+    with pytest.raises(ValueError):
+        g.cliques4_rooted_at([n])
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_brute_force_messy_input(seed):
     el = inputs.messy(inputs.gnp(16, 0.5, seed), seed)
