@@ -137,7 +137,8 @@ def bench_graph(name, w, args, ctx, eh, torch):
     if tune.get("tuning"):
         ctx.set_tuning(**tune["tuning"])
     t0 = time.perf_counter()
-    trie = ctx.build_edgelist(el, layout=layout, tau=tau)
+    s_min = tune.get("s_min", 1)
+    trie = ctx.build_edgelist(el, layout=layout, tau=tau, s_min=s_min)
     t_build = time.perf_counter() - t0
     info = trie.info
     log(f"[bench] trie built in {t_build:.2f} s: {info}")
@@ -177,7 +178,7 @@ def bench_graph(name, w, args, ctx, eh, torch):
         "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic (seeded generator)",
         "config": {"workload": name, **{k: v for k, v in w.items() if k not in ("kind",)},
-                   "layout": ["uint", "hybrid", "bitset_all"][layout], "tau": tau,
+                   "layout": ["uint", "hybrid", "bitset_all"][layout], "tau": tau, "s_min": s_min,
                    "n": info["n"], "m_plus": m_plus, "max_out_degree": info["max_out_degree"],
                    "bitset_sets": info["n_bitset_sets"], "tuning": ctx.get_tuning()},
         "count": count,

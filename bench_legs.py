@@ -78,7 +78,7 @@ def bench_batch(name, w, args, ctx, eh, torch, metric):
     if tune.get("tuning"):
         ctx.set_tuning(**tune["tuning"])
     t0 = time.perf_counter()
-    trie = ctx.build_batch(b, layout=layout, tau=tau)
+    trie = ctx.build_batch(b, layout=layout, tau=tau, s_min=tune.get("s_min", 1))
     info = trie.info
     log(f"[bench] batch trie built in {time.perf_counter() - t0:.1f} s: {info}")
     G = info["n_graphs"]
@@ -255,7 +255,8 @@ def bench_served(name, w, args, ctx, eh, torch, metric):
     tune = load_tuning(name)
     if tune.get("tuning"):
         ctx.set_tuning(**tune["tuning"])  # servers copy the tuning when created
-    trie = ctx.build_edgelist(el, layout=tune.get("layout", w["layout"]), tau=tune.get("tau", w["tau"]))
+    trie = ctx.build_edgelist(el, layout=tune.get("layout", w["layout"]), tau=tune.get("tau", w["tau"]),
+                              s_min=tune.get("s_min", 1))
     info = trie.info
     log(f"[bench] resident trie: {info}")
     rates = [float(x) for x in args.rates.split(",")]

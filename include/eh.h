@@ -302,8 +302,30 @@ eh_status eh_count_async(eh_ctx* ctx, const eh_trie* trie, int pattern, uint64_t
  * it: k calls on a zeroed d_total leave k times the count.  With the static
  * schedules (0, 2, 3) a call is one counting launch; schedules 1 and 4 add
  * a cursor reset before it, and a 4-clique count whose roots include
- * out-degrees above 512 takes a second launch for those. */
+ * out-degrees above 512 takes a second launch for those.  A total over a
+ * symmetric trie (each undirected edge once, doubled) enqueues a fill of the
+ * context's half-count word, the counting launch into it, and a kernel adding
+ * twice that word to *d_total; the word is allocated with the context and
+ * never moved, so a HIP graph captured from these calls stays valid for the
+ * context's life. */
 eh_status eh_count_add_async(eh_ctx* ctx, const eh_trie* trie, int pattern, uint64_t* d_total);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * eh_count_add_async, but the launches allocate nothing.  Their scratch -- the
+ * work cursors of the cursor schedules and, on a symmetric trie, the
+ * accumulator of the half count -- lives in a static device array of 16 KiB
+ * that the library holds on each GPU until the process ends.  Every call on a
+ * GPU shares that GPU's array (the cursors and the accumulator are cleared by
+ * a fill kernel on the stream before each use), so calls that overlap on one
+ * GPU (two contexts or streams in flight at once) race and must not be made.
+ * The work-item plan of (pattern, tuning) must already be cached in the trie
+ * by an earlier count with the same tuning (any eh_count_* call on this
+ * trie): EH_ESTATE otherwise, as for a batch trie.  EH_EOVERFLOW if the
+ * tuning's item partitions need more cursors than the scratch holds (never
+ * with the limits of eh_ctx_set_tuning).  d_total: one uint64, device; the
+ * count is added to it. */
+eh_status eh_count_add_noalloc(eh_ctx* ctx, const eh_trie* trie, int pattern, uint64_t* d_total);
 
 /* Instances whose root is in the set {roots[i]} (original ids; duplicates are
  * ignored): a selection on the first attribute of the join (appendix B.1). */

@@ -159,10 +159,13 @@ LaunchArgs base_args(Ctx* c, const Trie& t) {
   return a;
 }
 
-// Enqueues one counting launch over items [i0, i1) of a plan.
+// Enqueues one counting launch over items [i0, i1) of a plan.  cursor: the
+// work cursors to use instead of the context's (null: the context's).
 eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
-                        unsigned long long* acc, uint32_t tag_base, unsigned long long* per_root) {
+                        unsigned long long* acc, uint32_t tag_base, unsigned long long* per_root,
+                        uint32_t* cursor = nullptr) {
   LaunchArgs a = base_args(c, t);
+  if (cursor) a.cursor = cursor;
   a.items = static_cast<const Item*>(p->items.p) + i0;
   a.n_items = i1 - i0;
   a.idx = static_cast<const uint32_t*>(t.col.p);
@@ -196,9 +199,6 @@ uint32_t tri_staging(const Ctx* c, const Trie& t, bool per_root, bool half_ok = 
   return c->tune.staging == EH_STAGE_SOURCE ? EH_STAGE_SOURCE : EH_STAGE_TARGET;
 }
 
-// Accumulator slot for the half count of a symmetric trie (slots 0 and 1
-// serve the blocking calls).
-constexpr size_t kAccHalf = 4;
 
 eh_status count_single(Ctx* c, Trie& t, int pattern, unsigned long long* d_total,
                        unsigned long long* d_per_root, bool accumulate = false) {
@@ -216,7 +216,7 @@ eh_status count_single(Ctx* c, Trie& t, int pattern, unsigned long long* d_total
     return st;
   if (staging == kStageHalf) {
     // each undirected edge once: the ordered count is twice the launch's sum
-    auto* half = static_cast<unsigned long long*>(c->acc.p) + kAccHalf;
+    auto* half = static_cast<unsigned long long*>(c->half.p);
     if ((st = launch_fill_u64(c, c->stream, half, 1, 0)) != EH_OK) return st;
     if ((st = enqueue_count(c, t, p, 0, p->n_items, half, 0, nullptr)) != EH_OK) return st;
     return launch_add_scaled(c, c->stream, half, 2, d_total);
@@ -302,6 +302,8 @@ eh_status eh_ctx_create(int device, void* hip_stream, const eh_allocator* alloc,
   // one cursor per item partition, each on its own 256-byte line
   if (st == EH_OK) st = dev_alloc(c, c->cursor, sizeof(uint32_t) * kCursorWords * kMaxParts);
   if (st == EH_OK) st = ensure_acc(c, 64);
+  if (st == EH_OK) st = dev_alloc(c, c->half, sizeof(uint64_t));
+  if (st == EH_OK) st = noalloc_scratch_init(c);
   if (st != EH_OK) {
     g_err_no_ctx = c->err;
     eh_ctx_destroy(x);
@@ -317,6 +319,7 @@ eh_status eh_ctx_destroy(eh_ctx* ctx) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   dev_free(c, c->acc);
   dev_free(c, c->cursor);
+  dev_free(c, c->half);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete ctx;
@@ -713,6 +716,50 @@ eh_status eh_count_add_async(eh_ctx* ctx, const eh_trie* trie, int pattern, uint
   Trie& t = const_cast<eh_trie*>(trie)->t;
   return count_single(&ctx->c, t, pattern, reinterpret_cast<unsigned long long*>(d_total), nullptr,
                       true);
+}
+
+eh_status eh_count_add_noalloc(eh_ctx* ctx, const eh_trie* trie, int pattern, uint64_t* d_total) {
+  if (!ctx || !trie || !d_total) return EH_EINVAL;
+  Ctx* c = &ctx->c;
+  if (pattern != EH_TRIANGLE && pattern != EH_4CLIQUE) {
+    c->err = "pattern must be EH_TRIANGLE or EH_4CLIQUE";
+    return EH_EINVAL;
+  }
+  Trie& t = const_cast<eh_trie*>(trie)->t;
+  if (t.host.n_graphs != 1) {
+    c->err = "single-graph count called on a batch trie";
+    return EH_ESTATE;
+  }
+  if (!c->noalloc_scratch) {
+    c->err = "the context has no static scratch";
+    return EH_ESTATE;
+  }
+  // the cursors the schedule uses must fit the scratch's cursor region
+  const uint32_t parts = c->tune.xcds ? c->tune.xcds : 8u;
+  if (size_t(parts) * kCursorWords * sizeof(uint32_t) > kNoAllocCursorBytes) {
+    c->err = "the tuning's " + std::to_string(parts) + " item partitions need more cursors than "
+             "the " + std::to_string(kNoAllocCursorBytes) + "-byte static scratch holds";
+    return EH_EOVERFLOW;
+  }
+  const uint32_t staging = pattern == EH_TRIANGLE ? tri_staging(c, t, false, true) : EH_STAGE_SOURCE;
+  Plan* p = find_plan(c, &t, pattern, staging);
+  if (!p) {
+    c->err = "no cached work-item plan for this pattern and tuning: count once with "
+             "eh_count_async, eh_count_add_async or a blocking count first";
+    return EH_ESTATE;
+  }
+  auto* base = static_cast<unsigned char*>(c->noalloc_scratch);
+  auto* cursor = reinterpret_cast<uint32_t*>(base);
+  auto* total = reinterpret_cast<unsigned long long*>(d_total);
+  if (staging == kStageHalf) {
+    // each undirected edge once: the ordered count is twice the launch's sum
+    auto* half = reinterpret_cast<unsigned long long*>(base + kNoAllocCursorBytes);
+    eh_status st = launch_fill_u64(c, c->stream, half, 1, 0);
+    if (st != EH_OK) return st;
+    if ((st = enqueue_count(c, t, p, 0, p->n_items, half, 0, nullptr, cursor)) != EH_OK) return st;
+    return launch_add_scaled(c, c->stream, half, 2, total);
+  }
+  return enqueue_count(c, t, p, 0, p->n_items, total, 0, nullptr, cursor);
 }
 
 eh_status eh_count_rooted(eh_ctx* ctx, const eh_trie* trie, int pattern, const uint32_t* roots,

@@ -632,18 +632,26 @@ uint64_t count_items_estimated(const HostTrie& h, uint32_t u, uint32_t chunk_wor
   return slice ? (uint64_t(du) + slice - 1) / slice : 0;
 }
 
+Plan* find_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging) {
+  const Tuning& tu = c->tune;
+  const uint32_t chunk = std::max<uint32_t>(tu.chunk_work, 64);
+  if (pattern == EH_4CLIQUE) staging = EH_STAGE_SOURCE;
+  const uint32_t group = (staging == EH_STAGE_TARGET && pattern == EH_TRIANGLE) ? tu.group : 1u;
+  for (auto& p : t->plans)
+    if (p->pattern == pattern && p->staging == staging && p->chunk_work == chunk &&
+        p->use_bitsets == tu.use_bitsets && p->stage_words == tu.stage_words &&
+        p->group == group)
+      return p.get();
+  return nullptr;
+}
+
 eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** out) {
   const Tuning& tu = c->tune;
   const uint32_t chunk = std::max<uint32_t>(tu.chunk_work, 64);
   if (pattern == EH_4CLIQUE) staging = EH_STAGE_SOURCE;
-  for (auto& p : t->plans) {
-    const uint32_t group = (staging == EH_STAGE_TARGET && pattern == EH_TRIANGLE) ? tu.group : 1u;
-    if (p->pattern == pattern && p->staging == staging && p->chunk_work == chunk &&
-        p->use_bitsets == tu.use_bitsets && p->stage_words == tu.stage_words &&
-        p->group == group) {
-      *out = p.get();
-      return EH_OK;
-    }
+  if (Plan* found = find_plan(c, t, pattern, staging)) {
+    *out = found;
+    return EH_OK;
   }
   const HostTrie& h = t->host;
   std::vector<Item> items;

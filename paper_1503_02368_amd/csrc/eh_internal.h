@@ -30,6 +30,11 @@ constexpr uint32_t kStageWords = 1024;        // LDS words per wave for a staged
 constexpr uint32_t kStageHalf = 3;
 constexpr uint32_t kCursorWords = 64;         // uint32 words between work cursors
 constexpr uint32_t kMaxParts = 32;           // item partitions (L2 domains) at most
+// Allocation-free counting: cursors (kCursorWords * kMaxParts uint32 words)
+// then one uint64 accumulator, in a static device array of this many bytes.
+constexpr size_t kNoAllocCursorBytes = size_t(kCursorWords) * kMaxParts * sizeof(uint32_t);
+constexpr size_t kNoAllocScratchBytes = 16384;
+static_assert(kNoAllocCursorBytes + 256 <= kNoAllocScratchBytes, "scratch holds cursors + 1 word");
 
 // One unit of scheduled work: the set N+(s) is held on chip while the sets
 // N+(t) of the streamed vertices t = idx[lbeg .. lbeg+llen) are intersected
@@ -178,8 +183,11 @@ struct Ctx {
   DevBuf acc;       // uint64 accumulators
   size_t acc_cap = 0;
   DevBuf cursor;    // uint32 work cursors, kCursorWords apart
+  DevBuf half;      // uint64: the half count of a symmetric trie; allocated with the
+                    // context and never reallocated, so captured launches stay valid
   uint64_t* pinned = nullptr;  // host staging for results
   size_t pinned_cap = 0;
+  void* noalloc_scratch = nullptr;  // this device's static scratch (eh_count_add_noalloc)
 };
 
 // Allocation through the context.
@@ -191,6 +199,8 @@ eh_status ensure_pinned(Ctx* c, size_t n);
 
 // Work-item construction (host) and the plan cache.
 eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** out);
+// The cached plan for the context's current tuning, or null (never builds).
+Plan* find_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging);
 void make_items_source(const HostTrie& h, uint32_t u, uint32_t tag, uint32_t chunk_work,
                        uint32_t pattern, bool use_bitsets, std::vector<Item>& out);
 // Same items cut from out-degrees alone: O(1 + items) per root.
@@ -255,6 +265,9 @@ eh_status launch_degree_weighted_sum(Ctx* c, hipStream_t s, const unsigned long 
                                      unsigned long long* out);
 // Largest out-degree the staged 4-clique kernel accepts.
 uint32_t k4_staged_max_degree();
+// Sets c->noalloc_scratch to the current device's static scratch (looked up
+// once per device).
+eh_status noalloc_scratch_init(Ctx* c);
 
 // Set store (section 4.3): per set, segments {first block, last block, first
 // member in vals or first word in words, members | kHiBit for a bitset run}.

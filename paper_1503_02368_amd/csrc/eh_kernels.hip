@@ -37,7 +37,18 @@
 // reduction and one 64-bit atomic per output slot change.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <unordered_map>
+
 #include "eh_internal.h"
+
+// Scratch of the allocation-free counting entry point (eh_count_add_noalloc):
+// the work cursors of the cursor schedules, then one accumulator, in device
+// memory the library holds from load until the process ends (one copy per
+// GPU).  Host code must not pass this name to a kernel: on the host it is a
+// stand-in, not a device address; eh::noalloc_scratch_init looks up each
+// device's address once.
+static __device__ __align__(256) unsigned long long scratch[eh::kNoAllocScratchBytes / 8];
 
 namespace eh {
 namespace {
@@ -1066,6 +1077,28 @@ uint32_t grid_for(Ctx* c, uint64_t n_items, uint32_t wpb, uint32_t waves_per_cu)
 }  // namespace
 
 uint32_t k4_staged_max_degree() { return 2048; }
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the first context created on it) and kept for the process.
+eh_status noalloc_scratch_init(Ctx* c) {
+  static std::mutex mu;
+  static std::unordered_map<int, void*> by_device;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = by_device.find(c->device);
+  if (it == by_device.end()) {
+    void* p = nullptr;
+    const eh_status st = hip_check(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)),
+                                   "hipGetSymbolAddress(scratch)");
+    if (st != EH_OK) return st;
+    if (!p) {
+      c->err = "hipGetSymbolAddress(scratch) returned a null address";
+      return EH_EHIP;
+    }
+    it = by_device.emplace(c->device, p).first;
+  }
+  c->noalloc_scratch = it->second;
+  return EH_OK;
+}
 
 eh_status launch_fill_u64(Ctx* c, hipStream_t s, unsigned long long* p, uint64_t n,
                           unsigned long long v) {

@@ -44,7 +44,7 @@ SYMBOLS = [
     "eh_build_trie_device", "eh_trie_host_arrays", "eh_trie_device_arrays", "eh_count_lollipop",
     "eh_build_batch_device", "eh_sets_build", "eh_sets_info_get", "eh_sets_free",
     "eh_intersect_pairs", "eh_intersect_pairs_async", "eh_host_sets_build", "eh_host_sets_info",
-    "eh_host_sets_arrays", "eh_host_sets_free", "eh_stream_read",
+    "eh_host_sets_arrays", "eh_host_sets_free", "eh_stream_read", "eh_count_add_noalloc",
 ]
 
 
@@ -173,6 +173,7 @@ def load():
             "eh_intersect_pairs": [_vp, _vp, ctypes.c_uint64, _vp, _vp, ctypes.c_uint32, _u64p],
             "eh_intersect_pairs_async": [_vp, _vp, ctypes.c_uint64, _vp, _vp, ctypes.c_uint32, _vp],
             "eh_stream_read": [_vp, _vp, ctypes.c_uint64, ctypes.c_uint32, _vp],
+            "eh_count_add_noalloc": [_vp, _vp, ctypes.c_int, _vp],
             "eh_host_sets_build": [ctypes.c_uint32, _u64p, _u32p, ctypes.POINTER(_SetOpts),
                                    ctypes.POINTER(_vp)],
             "eh_host_sets_info": [_vp, ctypes.POINTER(_SetsInfo)],
@@ -504,6 +505,12 @@ class Context:
         """Enqueues one counting launch that adds its count into d_total."""
         self._check(self._lib.eh_count_add_async(self._h, trie._h, int(pattern), _vp(d_total.data_ptr())),
                     "count_add_async")
+
+    def count_add_noalloc(self, trie, pattern: int, d_total) -> None:
+        """As count_add_async, allocating nothing (static scratch; needs the
+        plan cached by an earlier count with the same tuning)."""
+        self._check(self._lib.eh_count_add_noalloc(self._h, trie._h, int(pattern),
+                                                   _vp(d_total.data_ptr())), "count_add_noalloc")
 
     def stream_read_async(self, d_buf, d_sink, blocks_per_cu: int = 0) -> None:
         """Enqueues the streaming-read probe over the tensor d_buf (every byte

@@ -57,7 +57,7 @@ def test_full_size_rmat18_4cliques(ctx, eh):
     K = oracle.Graph.from_edgelist(el).cliques4()["count"]
     say(f"oracle K {K} in {time.perf_counter() - t0:.1f} s")
     ctx.set_tuning(**t["tuning"])
-    trie = ctx.build_edgelist(el, layout=t["layout"], tau=t["tau"])
+    trie = ctx.build_edgelist(el, layout=t["layout"], tau=t["tau"], s_min=t.get("s_min", 1))
     try:
         got = ctx.count_4cliques(trie)
         say("tuned", got)
@@ -93,7 +93,7 @@ def test_full_size_batch_20000_graphs(ctx, eh):
     # built on the GPU from the pairs in device memory, as a production caller would
     src = torch.from_numpy(b.src.view(np.int32)).cuda()
     dst = torch.from_numpy(b.dst.view(np.int32)).cuda()
-    trie = ctx.build_batch_device(b, src, dst, layout=t["layout"], tau=t["tau"])
+    trie = ctx.build_batch_device(b, src, dst, layout=t["layout"], tau=t["tau"], s_min=t.get("s_min", 1))
     del src, dst
     try:
         G = trie.info["n_graphs"]
@@ -129,7 +129,7 @@ def test_full_size_served_rmat22(ctx, eh):
     want = [oracle.rooted_count(root_t if r.pattern == 3 else root_k, r.roots) for r in reqs]
     del g
     ctx.set_tuning(**t["tuning"])
-    trie = ctx.build_edgelist(el, layout=t["layout"], tau=t["tau"])
+    trie = ctx.build_edgelist(el, layout=t["layout"], tau=t["tau"], s_min=t.get("s_min", 1))
     srv = ctx.server(trie, policy=1)
     try:
         tickets = [srv.submit(r.pattern, r.roots) for r in reqs]
