@@ -748,7 +748,7 @@ def bench_composite(name, w, args, ctx, eh, torch, metric):
     (composite) level: (1) batches of pairs of sets whose members lie partly
     in one shared dense region (the dense-region sweep of Figure 5); (2)
     triangle counting of R-MAT s20 as one pairwise intersection per oriented
-    edge under each layout (the level comparison of Table 6), beside the
+    edge under each layout (the level comparison of Table 4), beside the
     staged kernel."""
     from paper_1503_02368_amd import inputs
     sweep = []

@@ -179,7 +179,7 @@ enum {
 
 /* Set optimizer of section 4.4: a set S becomes a bitset iff |S| >= s_min and
  * (max(S) - min(S) + 1) / |S| <= tau.  The paper's rule is one AVX register
- * (256 bits) per value: tau = 256.  tau <= 0 selects 32; s_min 0 selects 1. */
+ * (256 bits) per value: tau = 256.  tau <= 0 selects 256; s_min 0 selects 1. */
 typedef struct eh_build_opts {
   uint32_t layout;  /* EH_LAYOUT_* */
   float tau;
@@ -215,8 +215,8 @@ typedef struct eh_trie_info {
 
 /* Builds the trie of one graph on the host (clean, rank, orient, CSR, set
  * layouts; section 2.2 dictionary encoding, section 5.2 pruning) and uploads
- * it.  src/dst: n_edges raw pairs.  opts may be NULL (hybrid layout, tau 32,
- * degree order). */
+ * it.  src/dst: n_edges raw pairs.  opts may be NULL (hybrid layout, tau 256,
+ * s_min 1, degree order, pruned). */
 eh_status eh_build_trie(eh_ctx* ctx, const uint32_t* src, const uint32_t* dst, uint64_t n_edges,
                         uint32_t n_vertices, const eh_build_opts* opts, eh_trie** out);
 

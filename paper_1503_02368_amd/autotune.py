@@ -180,7 +180,7 @@ def tune_batch(b, pattern, layouts, ctx, torch, quick=False, expect=None):
             e1.record(s)
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / 3
-            c = int(out.cpu().numpy().view(np.uint64).sum(dtype=np.uint64))
+            c = tuple(int(x) for x in out.cpu().numpy().view(np.uint64))
             S.record(dict(layout=layout, tau=tau, s_min=s_min, tuning=cfg), ms, c)
             return ms
 

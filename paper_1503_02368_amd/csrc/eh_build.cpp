@@ -23,7 +23,7 @@ BuildOpts resolve_opts(const eh_build_opts* o) {
   BuildOpts b;
   if (!o) return b;
   b.layout = o->layout;
-  b.tau = o->tau > 0.0f ? o->tau : 32.0f;
+  b.tau = o->tau > 0.0f ? o->tau : 256.0f;
   b.s_min = o->s_min ? o->s_min : 1;
   b.order = o->order;
   b.symmetric = o->symmetric ? 1u : 0u;

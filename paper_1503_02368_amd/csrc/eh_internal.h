@@ -74,7 +74,7 @@ struct HostTrie {
 
 struct BuildOpts {
   uint32_t layout = EH_LAYOUT_HYBRID;
-  float tau = 32.0f;
+  float tau = 256.0f;  // the paper's rule: one 256-bit register per member
   uint32_t s_min = 1;
   uint32_t order = EH_ORDER_DEGREE;
   uint32_t symmetric = 0;
