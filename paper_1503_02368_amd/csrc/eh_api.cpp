@@ -89,6 +89,7 @@ void free_trie_device(Trie& t) {
     dev_free(c, p->sdesc);
     dev_free(c, p->rec);
     dev_free(c, p->gsub);
+    dev_free(c, p->k4s);
   }
   t.plans.clear();
   dev_free(c, t.vdesc);
@@ -178,6 +179,9 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
   a.tag_base = tag_base;
   a.per_root = per_root;
   a.item_dmax = p->item_dmax;
+  a.k4s = static_cast<uint32_t*>(p->k4s.p);
+  a.k4s_stride = p->k4s_stride;
+  a.k4s_waves = p->k4s_waves;
   if (p->pattern == EH_4CLIQUE)
     return launch_4cliques(c, c->stream, a, c->tune.kernel, c->tune.waves_per_cu);
   return launch_triangles(c, c->stream, a, c->tune.kernel, c->tune.waves_per_cu);
@@ -798,7 +802,7 @@ eh_status eh_count_rooted(eh_ctx* ctx, const eh_trie* trie, int pattern, const u
   unsigned long long* acc = static_cast<unsigned long long*>(c->acc.p);
   eh_status st = launch_fill_u64(c, c->stream, acc, 1, 0);
   if (st != EH_OK) return st;
-  DevBuf buf;
+  DevBuf buf, lists;
   if (!items.empty()) {
     if ((st = dev_alloc(c, buf, sizeof(Item) * items.size())) != EH_OK) return st;
     if ((st = hip_check(c, hipMemcpyAsync(buf.p, items.data(), sizeof(Item) * items.size(),
@@ -813,11 +817,15 @@ eh_status eh_count_rooted(eh_ctx* ctx, const eh_trie* trie, int pattern, const u
     p.items = buf;
     p.n_items = items.size();
     p.item_dmax = item_dmax;
-    st = enqueue_count(c, t, &p, 0, items.size(), acc, 0, nullptr);
+    if (pattern == EH_4CLIQUE)
+      st = prepare_k4_lists(c, h, items.data(), items.size(), lists, p.k4s_waves, p.k4s_stride);
+    p.k4s = lists;
+    if (st == EH_OK) st = enqueue_count(c, t, &p, 0, items.size(), acc, 0, nullptr);
   }
   if (st == EH_OK) st = read_back(c, acc, total, 1);
   (void)hipStreamSynchronize(c->stream);
   dev_free(c, buf);
+  dev_free(c, lists);
   return st;
 }
 

@@ -945,13 +945,20 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
       return st;
     }
   }
-  plan->n_items = items.size();
-  if ((st = dev_alloc(c, plan->items, sizeof(Item) * std::max<size_t>(items.size(), 1))) != EH_OK)
+  if (pattern == EH_4CLIQUE &&
+      (st = prepare_k4_lists(c, h, items.data(), items.size(), plan->k4s, plan->k4s_waves,
+                             plan->k4s_stride)) != EH_OK)
     return st;
+  plan->n_items = items.size();
+  if ((st = dev_alloc(c, plan->items, sizeof(Item) * std::max<size_t>(items.size(), 1))) != EH_OK) {
+    dev_free(c, plan->k4s);
+    return st;
+  }
   if (!items.empty())
     if ((st = hip_check(c, hipMemcpy(plan->items.p, items.data(), sizeof(Item) * items.size(),
                                      hipMemcpyHostToDevice), "upload work items")) != EH_OK) {
       dev_free(c, plan->items);
+      dev_free(c, plan->k4s);
       return st;
     }
   *out = plan.get();

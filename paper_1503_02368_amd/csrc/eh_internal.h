@@ -153,6 +153,12 @@ struct Plan {
   DevBuf gsub;
   std::vector<uint64_t> g_item_off;  // batch: items of graph g are [off[g], off[g+1])
   uint32_t item_dmax = 0;            // max out-degree of an item's source vertex
+  // 4-cliques whose root's out-degree exceeds kK4ListMax: S = N+(u) & N+(v)
+  // is kept in HBM, one list of k4s_stride words per wave of the launch over
+  // those items (k4s_waves waves)
+  DevBuf k4s;
+  uint32_t k4s_waves = 0;
+  uint32_t k4s_stride = 0;
 };
 
 struct Trie {
@@ -242,6 +248,9 @@ struct LaunchArgs {
   uint32_t search_below = 24;          // average segment length below which the walk searches
   const uint4* gsub = nullptr;         // grouped items' members, or null
   uint32_t symmetric = 0;              // both directions of every edge are stored
+  uint32_t* k4s = nullptr;             // 4-cliques: per-wave S lists in HBM for roots
+  uint32_t k4s_stride = 0;             //   of out-degree > kK4ListMax, or null
+  uint32_t k4s_waves = 0;
 };
 eh_status launch_fill_u64(Ctx* c, hipStream_t s, unsigned long long* p, uint64_t n,
                           unsigned long long v);
@@ -263,8 +272,14 @@ eh_status launch_add_scaled(Ctx* c, hipStream_t s, const unsigned long long* in,
 eh_status launch_degree_weighted_sum(Ctx* c, hipStream_t s, const unsigned long long* t_by_id,
                                      const uint32_t* vert, const uint2* vdesc, uint32_t n,
                                      unsigned long long* out);
-// Largest out-degree the staged 4-clique kernel accepts.
-uint32_t k4_staged_max_degree();
+// Largest out-degree whose 4-clique S list the kernel holds in LDS; beyond it
+// the lists live in HBM (Plan::k4s).
+constexpr uint32_t kK4ListMax = 2048;
+// Sizes and allocates the HBM S lists of a 4-clique launch over `items` when
+// a root's out-degree exceeds kK4ListMax (nothing otherwise): one list of
+// the largest such out-degree per wave, at most 4 waves per compute unit.
+eh_status prepare_k4_lists(Ctx* c, const HostTrie& h, const Item* items, uint64_t n_items,
+                           DevBuf& buf, uint32_t& waves, uint32_t& stride);
 // Sets c->noalloc_scratch to the current device's static scratch (looked up
 // once per device).
 eh_status noalloc_scratch_init(Ctx* c);

@@ -82,6 +82,8 @@ struct DevArgs {
   uint32_t search_below;    // segments shorter on average: the walk binary-searches
   const uint4* gsub;        // grouped items' members, or null
   uint32_t symmetric;       // the trie holds both directions of every edge
+  uint32_t* k4s;            // 4-cliques: per-wave S lists in HBM (the HBM-list instance)
+  uint32_t k4s_stride;      //   words per wave's list
 };
 
 DevArgs to_dev(const LaunchArgs& a) {
@@ -112,6 +114,8 @@ DevArgs to_dev(const LaunchArgs& a) {
   d.search_below = a.search_below;
   d.gsub = a.gsub;
   d.symmetric = a.symmetric;
+  d.k4s = a.k4s;
+  d.k4s_stride = a.k4s_stride;
   return d;
 }
 
@@ -299,6 +303,9 @@ struct Staged {
   // composite mode: the set's own bitset in HBM (position of its first word in
   // the list buffer, first id covered), gw = kNoBitset if it has none
   uint32_t gw, gb;
+  // composite mode: when not null, the sorted prefix is gp[0 .. plen) in HBM
+  // (a 4-clique S list kept there) instead of Lp / the set's own members
+  const uint32_t* gp;
 };
 
 // Loads the set col[beg .. beg+len) with known min lo and max hi into region
@@ -316,6 +323,7 @@ __device__ __forceinline__ Staged stage_extent(const DevArgs& a, uint32_t beg, u
   st.gb = 0;
   st.glog = 0;
   st.glim = 0;
+  st.gp = nullptr;
   if (st.len == 0) { st.mode = kModeEmpty; st.lo = st.hi = st.base = 0; return st; }
   st.lo = lo;
   st.hi = hi;
@@ -396,6 +404,10 @@ __device__ __forceinline__ uint32_t prefix_has(const DevArgs& a, const Staged& s
     // st.gb <= lo <= x < base <= hi: inside the bitset's words
     const uint32_t d = x - st.gb;
     return (a.bsw[st.gw + (d >> 5)] >> (d & 31)) & 1u;
+  }
+  if (st.gp) {
+    const uint32_t p = lower_bound_glb(st.gp, st.plen, x);
+    return (p < st.plen && st.gp[p] == x) ? 1u : 0u;
   }
   if (st.plen <= uint32_t(kPrefixCap)) {
     const uint32_t p = lower_bound_lds(Lp, st.plen, x);
@@ -730,6 +742,7 @@ __device__ __forceinline__ uint32_t grouped_item(const DevArgs& a, const SegTab&
   Staged st;
   st.beg = st.len = st.lo = st.hi = st.plen = st.x0 = st.gb = 0;
   st.gw = kNoBitset;
+  st.gp = nullptr;
   st.mode = kModeGroup;
   st.base = base;
   st.glog = glog;
@@ -841,18 +854,22 @@ void k_tri_staged_lean(DevArgs a) {
 // for w in S against B (or searches the list S).
 // ---------------------------------------------------------------------------
 
+// SCAP > 0: S is an LDS list of SCAP entries.  SCAP == 0: S lives in HBM, in
+// wave w's list a.k4s[w k4s_stride ..] (roots whose out-degree exceeds any
+// LDS list); S's members below the staged window are then searched there.
 template <int WPB, int RW, int SCAP, int U>
 __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
+  constexpr bool kGlb = SCAP == 0;
   __shared__ uint32_t s_A[WPB][RW];
   __shared__ uint32_t s_B[WPB][RW];
-  __shared__ uint32_t s_S[WPB][SCAP];
+  __shared__ uint32_t s_S[WPB][kGlb ? 1 : SCAP];
   __shared__ uint32_t s_pre[WPB][kSeg + 1];
   __shared__ uint2 s_seg[WPB][kSeg];
   __shared__ uint32_t s_pref[WPB][kPrefixCap];
   const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
   uint32_t* A = s_A[wid];
   uint32_t* B = s_B[wid];
-  uint32_t* S = s_S[wid];
+  uint32_t* S = kGlb ? a.k4s + size_t(blockIdx.x * WPB + wid) * a.k4s_stride : s_S[wid];
   uint32_t* Lp = s_pref[wid];
   const SegTab T{s_pre[wid], s_seg[wid]};
   for (uint32_t k = lane; k < uint32_t(RW); k += kWave) { A[k] = 0; B[k] = 0; }
@@ -888,8 +905,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
       if (vl < 2) continue;
       // level 1: S = N+(u) & N+(v), compacted in ascending order; members at
       // or above the window base also go into bitmap B (same base as A)
-      uint32_t ns = 0;
-      bool low = false;  // a member of S lies below the window base
+      uint32_t ns = 0, nlow = 0;
       for (uint32_t k0 = 0; k0 < vl; k0 += kWave) {
         const uint32_t k = k0 + lane;
         uint32_t x = 0, hit = 0;
@@ -905,13 +921,16 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
             atomicOr(&B[d >> 5], 1u << (d & 31));
           }
         }
-        low = low || __ballot(hit && x < su.base) != 0ull;
+        nlow += uint32_t(__popcll(__ballot(hit && x < su.base)));
         ns += uint32_t(__popcll(m));
       }
+      if (kGlb) __threadfence_block();  // the list's stores before its loads
       wave_sync();
       if (ns >= 2) {
         // level 2: sum over w in S of |S & N+(w)|, against bitmap B when it
-        // holds all of S, else by searching the sorted list S
+        // holds all of S; else (LDS list) by searching the sorted list S, or
+        // (HBM list) B for members in the window and a search of S's prefix
+        // below it
         Staged ss;
         ss.beg = 0;
         ss.len = ns;
@@ -920,9 +939,17 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
         ss.plen = 0;
         ss.x0 = ss.gb = 0;
         ss.gw = kNoBitset;
+        ss.gp = nullptr;
         ss.base = su.base;
-        ss.mode = (su_bits && !low) ? kModeBitmap : kModeList;
-        const uint32_t* probe = ss.mode == kModeBitmap ? B : S;
+        ss.glog = ss.glim = 0;
+        if (kGlb) {
+          ss.mode = nlow ? kModeComposite : kModeBitmap;
+          ss.plen = nlow;
+          ss.gp = S;
+        } else {
+          ss.mode = (su_bits && nlow == 0) ? kModeBitmap : kModeList;
+        }
+        const uint32_t* probe = ss.mode == kModeList ? S : B;
         const WordRule wr = word_rule(a, ss);
         for (uint32_t b0 = 0; b0 < ns; b0 += kSeg) {
           const uint32_t nseg = min(uint32_t(kSeg), ns - b0);
@@ -935,8 +962,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
       }
       wave_sync();
       if (su_bits)
-        for (uint32_t i = lane; i < ns; i += kWave)
-          if (S[i] >= su.base) B[(S[i] - su.base) >> 5] = 0;
+        for (uint32_t i = nlow + lane; i < ns; i += kWave) B[(S[i] - su.base) >> 5] = 0;
       wave_sync();
     }
     acc += cnt;
@@ -1076,8 +1102,6 @@ uint32_t grid_for(Ctx* c, uint64_t n_items, uint32_t wpb, uint32_t waves_per_cu)
 
 }  // namespace
 
-uint32_t k4_staged_max_degree() { return 2048; }
-
 // Device address of `scratch` on the current device, looked up once per
 // device (the first context created on it) and kept for the process.
 eh_status noalloc_scratch_init(Ctx* c) {
@@ -1167,10 +1191,14 @@ eh_status launch_4cliques(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t 
   // run in an instance with a 512-entry S list (and, for stage_words in
   // (0, 512], a half-size staged region): less LDS, more waves per CU.  Only
   // when some item's d+(u) exceeds 512 does a second launch, over the same
-  // items, take those with an S list sized for the largest out-degree.
+  // items, take those with an S list sized for the largest out-degree up to
+  // kK4ListMax, and only when some exceeds that does a third take them with
+  // S in HBM (per-wave lists the caller provides).
   const uint32_t bound = la.item_dmax ? la.item_dmax : la.dmax;
-  if (bound > k4_staged_max_degree()) {
-    c->err = "4-clique kernel supports out-degrees up to " + std::to_string(k4_staged_max_degree());
+  if (bound > kK4ListMax && (!la.k4s || la.k4s_stride < bound || la.k4s_waves < kK4WPB)) {
+    c->err = "4-clique roots of out-degree above " + std::to_string(kK4ListMax) +
+             " need per-wave S lists in HBM of at least " + std::to_string(bound) +
+             " entries, which this launch was not given";
     return EH_EOVERFLOW;
   }
   const bool half = la.stage_words > 0 && la.stage_words <= kK4RW / 2;
@@ -1188,14 +1216,48 @@ eh_status launch_4cliques(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t 
   if (st != EH_OK || bound <= 512) return st;
   LaunchArgs heavy = la;
   heavy.deg_lo = 512;
-  heavy.deg_hi = 0xFFFFFFFFu;
+  heavy.deg_hi = kK4ListMax;
   const DevArgs ah = to_dev(heavy);
   if ((st = reset_cursors(c, s, la)) != EH_OK) return st;
   if (bound <= 1024)
     hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 1024, kK4U>), dim3(grid), blk, 0, s, ah);
   else
     hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 2048, kK4U>), dim3(grid), blk, 0, s, ah);
-  return hip_check(c, hipGetLastError(), "staged 4-clique kernel launch (high out-degree)");
+  st = hip_check(c, hipGetLastError(), "staged 4-clique kernel launch (high out-degree)");
+  if (st != EH_OK || bound <= kK4ListMax) return st;
+  // S in HBM: one list per wave, so the grid is exactly the lists' waves
+  LaunchArgs hub = la;
+  hub.deg_lo = kK4ListMax;
+  hub.deg_hi = 0xFFFFFFFFu;
+  const DevArgs ahub = to_dev(hub);
+  if ((st = reset_cursors(c, s, la)) != EH_OK) return st;
+  hipLaunchKernelGGL((k_k4_staged<kK4WPB, kK4RW, 0, kK4U>), dim3(la.k4s_waves / kK4WPB), blk, 0, s,
+                     ahub);
+  return hip_check(c, hipGetLastError(), "staged 4-clique kernel launch (S lists in HBM)");
+}
+
+eh_status prepare_k4_lists(Ctx* c, const HostTrie& h, const Item* items, uint64_t n_items,
+                           DevBuf& buf, uint32_t& waves, uint32_t& stride) {
+  uint64_t heavy = 0;
+  uint32_t dmax = 0;
+  for (uint64_t i = 0; i < n_items; ++i) {
+    const uint32_t d = h.row[items[i].s + 1] - h.row[items[i].s];
+    if (d > kK4ListMax) {
+      ++heavy;
+      dmax = std::max(dmax, d);
+    }
+  }
+  if (!heavy) return EH_OK;
+  uint64_t w = std::min<uint64_t>(uint64_t(c->n_cu) * 4, heavy);
+  w = (w + kK4WPB - 1) / kK4WPB * kK4WPB;
+  if (buf.p && stride >= dmax && waves >= w) return EH_OK;
+  dev_free(c, buf);
+  waves = stride = 0;
+  const eh_status st = dev_alloc(c, buf, sizeof(uint32_t) * size_t(dmax) * w);
+  if (st != EH_OK) return st;
+  waves = uint32_t(w);
+  stride = dmax;
+  return EH_OK;
 }
 
 }  // namespace eh

@@ -67,6 +67,8 @@ struct Server {
   DevBuf cursor;           // work cursors of the server's own launches
   DevBuf items_d;          // step_items Items
   DevBuf acc_d;            // max_active uint64
+  DevBuf k4s;              // 4-clique S lists in HBM, when some out-degree exceeds kK4ListMax
+  uint32_t k4s_waves = 0, k4s_stride = 0;
   Item* items_h = nullptr; // pinned staging
   uint64_t* acc_h = nullptr;
   std::mutex mu;
@@ -126,6 +128,9 @@ eh_status server_launch(Server* s, const std::vector<Item>& v, uint64_t off, int
   a.dynamic = tu.dynamic;
   a.grab = tu.grab;
   a.cursor = static_cast<uint32_t*>(s->cursor.p);
+  a.k4s = static_cast<uint32_t*>(s->k4s.p);
+  a.k4s_stride = s->k4s_stride;
+  a.k4s_waves = s->k4s_waves;
   a.algo = tu.algo;
   a.gamma = tu.gamma;
   a.group_lanes = tu.group_lanes;
@@ -372,6 +377,13 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
   if (st == EH_OK) st = dev_alloc(c, s.items_d, sizeof(Item) * s.o.step_items);
   if (st == EH_OK) st = dev_alloc(c, s.acc_d, sizeof(uint64_t) * s.o.max_active);
   if (st == EH_OK) st = dev_alloc(c, s.cursor, sizeof(uint32_t) * kCursorWords * kMaxParts);
+  if (st == EH_OK && t->host.dmax > kK4ListMax) {
+    // 4-clique requests rooted at hubs keep S in HBM: lists for 4 waves per
+    // compute unit, each as long as the largest out-degree
+    s.k4s_waves = 4 * uint32_t(c->n_cu);
+    s.k4s_stride = t->host.dmax;
+    st = dev_alloc(c, s.k4s, sizeof(uint32_t) * size_t(s.k4s_stride) * s.k4s_waves);
+  }
   if (st == EH_OK)
     st = hip_check(c, hipHostMalloc((void**)&s.items_h, sizeof(Item) * s.o.step_items,
                                     hipHostMallocDefault), "pinned items");
@@ -382,6 +394,7 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
     dev_free(c, s.items_d);
     dev_free(c, s.acc_d);
     dev_free(c, s.cursor);
+    dev_free(c, s.k4s);
     if (s.items_h) (void)hipHostFree(s.items_h);
     if (s.acc_h) (void)hipHostFree(s.acc_h);
     if (s.stream) (void)hipStreamDestroy(s.stream);
@@ -409,6 +422,7 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
     dev_free(c, s.items_d);
     dev_free(c, s.acc_d);
     dev_free(c, s.cursor);
+    dev_free(c, s.k4s);
     (void)hipHostFree(s.items_h);
     (void)hipHostFree(s.acc_h);
     (void)hipStreamDestroy(s.stream);
@@ -557,6 +571,7 @@ eh_status eh_server_destroy(eh_server* srv) {
   dev_free(s.c, s.items_d);
   dev_free(s.c, s.acc_d);
   dev_free(s.c, s.cursor);
+  dev_free(s.c, s.k4s);
   if (s.items_h) (void)hipHostFree(s.items_h);
   if (s.acc_h) (void)hipHostFree(s.acc_h);
   (void)hipStreamDestroy(s.stream);

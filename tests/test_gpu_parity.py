@@ -550,7 +550,7 @@ def order_truth(el, order):
         off, _ = g.oriented()
         d = np.diff(off.astype(np.int64))
         dmax = int(d.max()) if d.size else 0
-        k = g.cliques4(rooted=True) if dmax <= 2048 else None
+        k = g.cliques4(rooted=True)
         _ORDER_TRUTH[key] = (t, k, dmax)
     return _ORDER_TRUTH[key]
 
@@ -560,7 +560,7 @@ def test_node_orderings(ctx, eh, order):
     """Node orderings (appendix A): totals equal the oracle's under every
     ordering; per-root and rooted counts follow the ordering's ranks, which
     the oracle computes with its own code.  Out-degrees above 2048 (only
-    possible away from degree order) refuse 4-cliques with EH_EOVERFLOW."""
+    possible away from degree order) keep the 4-clique S lists in HBM.""" 
     for el in ORDER_GRAPHS:
         t, k, dmax = order_truth(el, order)
         say("order", order, el.name, "dmax", dmax)
@@ -577,15 +577,10 @@ def test_node_orderings(ctx, eh, order):
             np.testing.assert_array_equal(per, t["root"])
             roots = np.arange(0, el.n, 7, dtype=np.uint32)
             assert ctx.count_rooted(trie, eh.TRIANGLE, roots) == oracle.rooted_count(t["root"], roots)
-            if k is None:
-                with pytest.raises(eh.EHError) as e:
-                    ctx.count_4cliques(trie)
-                assert e.value.status == eh.EH_EOVERFLOW
-            else:
-                for tname in ("staged_source", "staged_steal"):
-                    tune(ctx, **TUNINGS[tname])
-                    assert ctx.count_4cliques(trie) == k["count"], (el.name, tname)
-                assert ctx.count_rooted(trie, eh.CLIQUE4, roots) == oracle.rooted_count(k["root"], roots)
+            for tname in ("staged_source", "staged_steal"):
+                tune(ctx, **TUNINGS[tname])
+                assert ctx.count_4cliques(trie) == k["count"], (el.name, tname)
+            assert ctx.count_rooted(trie, eh.CLIQUE4, roots) == oracle.rooted_count(k["root"], roots)
         finally:
             trie.free()
 
@@ -593,7 +588,8 @@ def test_node_orderings(ctx, eh, order):
 def test_out_degree_beyond_16_bits(ctx, eh):
     """Wheel W_70000 under reverse degree order: the hub's out-set holds all
     70,000 rim vertices, beyond what target staging's 16-bit segment lengths
-    describe, so triangle totals stage sources instead: W_k has k triangles."""
+    describe, so triangle totals stage sources instead: W_k has k triangles,
+    and no 4-clique (its hub's S lists are kept in HBM)."""
     k = 70000
     el = inputs.wheel(k)
     trie = ctx.build_edgelist(el, order=eh.ORDER_REV_DEGREE)
@@ -602,9 +598,8 @@ def test_out_degree_beyond_16_bits(ctx, eh):
         for tname in ("staged_target", "staged_lean", "staged_group", "staged_source", "pair_auto"):
             tune(ctx, **TUNINGS[tname])
             assert ctx.count_triangles(trie) == k, tname
-        with pytest.raises(eh.EHError) as e:
-            ctx.count_4cliques(trie)
-        assert e.value.status == eh.EH_EOVERFLOW
+        tune(ctx, **TUNINGS["staged_source"])
+        assert ctx.count_4cliques(trie) == 0
     finally:
         trie.free()
 
@@ -618,9 +613,8 @@ def test_batch_node_orderings(ctx, eh, order):
     try:
         np.testing.assert_array_equal(ctx.count_batch(trie, eh.TRIANGLE),
                                       np.array([w[0]["count"] for w in want], np.uint64))
-        if all(w[1] is not None for w in want):
-            np.testing.assert_array_equal(ctx.count_batch(trie, eh.CLIQUE4),
-                                          np.array([w[1]["count"] for w in want], np.uint64))
+        np.testing.assert_array_equal(ctx.count_batch(trie, eh.CLIQUE4),
+                                      np.array([w[1]["count"] for w in want], np.uint64))
     finally:
         trie.free()
 
@@ -801,19 +795,14 @@ def test_symmetric_totals_each_edge_once(ctx, eh, tname):
 
 @pytest.mark.parametrize("tname", ["staged_source", "staged_half", "staged_steal"])
 def test_symmetric_4cliques(ctx, eh, tname):
-    """Unpruned 4-cliques: 24K ordered tuples while every degree fits the
-    2048-entry S list, EH_EOVERFLOW beyond."""
+    """Unpruned 4-cliques: 24K ordered tuples, with S in LDS lists up to
+    degree 2048 and in HBM lists beyond."""
     tune(ctx, **TUNINGS[tname])
     for el in SYM_GRAPHS:
         _, _, k24, _ = sym_truth(el)
         trie = ctx.build_edgelist(el, symmetric=True)
         try:
-            if trie.info["max_out_degree"] <= 2048:
-                assert ctx.count_4cliques(trie) == k24, el.name
-            else:
-                with pytest.raises(eh.EHError) as e:
-                    ctx.count_4cliques(trie)
-                assert e.value.status == eh.EH_EOVERFLOW
+            assert ctx.count_4cliques(trie) == k24, el.name
         finally:
             trie.free()
 
@@ -842,9 +831,8 @@ def test_symmetric_batch_and_device_build(ctx, eh):
     try:
         np.testing.assert_array_equal(ctx.count_batch(trie, eh.TRIANGLE),
                                       np.array([w[0] for w in want], np.uint64))
-        if trie.info["max_out_degree"] <= 2048:
-            np.testing.assert_array_equal(ctx.count_batch(trie, eh.CLIQUE4),
-                                          np.array([w[1] for w in want], np.uint64))
+        np.testing.assert_array_equal(ctx.count_batch(trie, eh.CLIQUE4),
+                                      np.array([w[1] for w in want], np.uint64))
         with pytest.raises(eh.EHError) as e:
             ctx.count_lollipop(trie)
         assert e.value.status == eh.EH_ESTATE
@@ -940,9 +928,8 @@ def test_host_planner_path(ctx, eh, monkeypatch):
 
 
 def test_out_degree_limits(ctx, eh):
-    """K_2050: triangles at out-degree 2049 (C(n, 3)); the 4-clique kernel's
-    S list holds at most 2048 entries, so its count is refused with
-    EH_EOVERFLOW instead of being computed wrongly."""
+    """K_2050: triangles at out-degree 2049 (C(n, 3)); 4-cliques C(n, 4),
+    the root of out-degree 2049 with its S lists in HBM."""
     from math import comb
     tune(ctx)
     n = 2050
@@ -952,10 +939,9 @@ def test_out_degree_limits(ctx, eh):
         for tname in ("staged_target", "staged_source", "staged_lean", "pair_auto"):
             tune(ctx, **TUNINGS[tname])
             assert ctx.count_triangles(trie) == comb(n, 3), tname
-        with pytest.raises(eh.EHError) as e:
-            ctx.count_4cliques(trie)
-        assert e.value.status == eh.EH_EOVERFLOW
-        # roots of out-degree <= 2048 are still counted: vertex i roots C(n-1-i, 3)
+        tune(ctx, **TUNINGS["staged_source"])
+        assert ctx.count_4cliques(trie) == comb(n, 4)
+        # vertex i roots C(n-1-i, 3)
         roots = np.array([5, 100, 2000], np.uint32)
         assert ctx.count_rooted(trie, eh.CLIQUE4, roots) == sum(comb(n - 1 - int(i), 3) for i in roots)
     finally:
@@ -1043,8 +1029,7 @@ def test_randomized_parity(ctx, eh):
         trie = ctx.build_edgelist(el, layout=layout, tau=tau)
         try:
             assert ctx.count_triangles(trie) == T, (case, kind, t, layout, tau)
-            if trie.info["max_out_degree"] <= 2048:
-                assert ctx.count_4cliques(trie) == K, (case, kind, t, layout, tau)
+            assert ctx.count_4cliques(trie) == K, (case, kind, t, layout, tau)
         finally:
             trie.free()
 
@@ -1092,7 +1077,7 @@ def test_randomized_build_paths(ctx, eh):
         else:
             tr, kr, _ = order_truth(el, order)
             want_t, want_root = tr["count"], tr["root"]
-            k24 = None if kr is None else kr["count"]
+            k24 = kr["count"]
         if device:
             src, dst = _device_pairs(el)
             trie = ctx.build_trie_device(el.n, src, dst, layout=layout, tau=tau,
@@ -1105,7 +1090,6 @@ def test_randomized_build_paths(ctx, eh):
             tot, per = ctx.count_triangles(trie, per_root=True)
             assert tot == want_t, where
             np.testing.assert_array_equal(per, want_root, err_msg=str(where))
-            if trie.info["max_out_degree"] <= 2048 and k24 is not None:
-                assert ctx.count_4cliques(trie) == k24, where
+            assert ctx.count_4cliques(trie) == k24, where
         finally:
             trie.free()
