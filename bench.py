@@ -212,7 +212,7 @@ def bench_graph(name, w, args, ctx, eh, torch):
         from paper_1503_02368_amd.calib import probe_gbs
         achieved = model_bytes / (ms / 1e3) / 1e9
         traffic = measured_traffic(name)
-        probe = probe_gbs(ctx)
+        probe = {"read": None, "kernel": None} if args.no_probe else probe_gbs(ctx)
         result["roofline"] = {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -222,7 +222,7 @@ def bench_graph(name, w, args, ctx, eh, torch):
             "model": model, "algorithmic_bytes_per_launch": model_bytes,
             "kernel_ms_per_launch": ms,
             "achievable_read_gbs": probe["read"], "achievable_read_kernel": probe["kernel"],
-            "frac_of_achievable_read": achieved / probe["read"]}
+            "frac_of_achievable_read": achieved / probe["read"] if probe["read"] else None}
         if merge_bytes:
             result["roofline"]["merge_equivalent"] = {
                 "model": "B_merge" if pattern == 3 else "B_K4", "bytes_per_launch": merge_bytes,
@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--workload", default="rmat20_triangles", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the streaming-read probe (for profiling runs)")
     ap.add_argument("--rates", default="200,1000,5000", help="served: arrival rates (QPS)")
     ap.add_argument("--policy", type=int, default=1, choices=(0, 1),
                     help="served: 0 oldest request first, 1 fewest items left first")

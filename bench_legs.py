@@ -590,6 +590,11 @@ def bench_unpruned(name, w, args, ctx, eh, torch, metric):
     rows["pairwise_by_layout"] = pair_rows
     parity = {"six_t": best[2] == 6 * t_count,
               "pairwise": all(r["correct"] for r in pair_rows)}
+    k4 = unpruned_4cliques(ctx, eh, torch, args, w.get("k4_scale", 16), w["edge_factor"], base)
+    rows["unpruned_4cliques"] = k4
+    parity["twenty_four_k"] = k4["count_unpruned"] == 24 * k4["count_pruned"]
+    if "oracle_k" in k4:
+        parity["k4_oracle"] = k4["oracle_k"] == k4["count_pruned"]
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -626,6 +631,41 @@ def bench_unpruned(name, w, args, ctx, eh, torch, metric):
     if cpu:
         res["cpu_baseline"] = cpu
     return res
+
+
+def unpruned_4cliques(ctx, eh, torch, args, scale, edge_factor, base):
+    """4-cliques on R-MAT at `scale` (seed = scale): pruned (K) beside the
+    unpruned relation (24 K ordered tuples), whose hub roots keep S in HBM
+    lists; times of single blocking counts (median of 3, plan cached)."""
+    from paper_1503_02368_amd import inputs
+    el = inputs.rmat(scale, edge_factor, seed=scale)
+    out = {"graph": f"rmat{scale} edge factor {edge_factor}, seed {scale}"}
+    ctx.set_tuning(**dict(base, kernel=1, staging=1, dynamic=4, grab=2, chunk_work=4096,
+                          stage_words=0))
+    for key, kw in (("pruned", {}), ("unpruned", {"symmetric": True})):
+        trie = ctx.build_edgelist(el, layout=1, tau=32.0, **kw)
+        try:
+            c = ctx.count_4cliques(trie)   # builds the plan
+            ts = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                c2 = ctx.count_4cliques(trie)
+                ts.append(time.perf_counter() - t0)
+                if c2 != c:
+                    raise RuntimeError("4-clique counts differ between repeats")
+            out[f"ms_{key}"] = 1e3 * statistics.median(ts)
+            out[f"count_{key}"] = c
+            out[f"max_degree_{key}"] = trie.info["max_out_degree"]
+            log(f"[bench] {key} 4-cliques on rmat{scale}: {out[f'ms_{key}']:.2f} ms, count {c}")
+        finally:
+            trie.free()
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        out["oracle_k"] = oracle.Graph.from_edgelist(el).count(4, threads=oracle.max_threads())
+        out["oracle_s"] = time.perf_counter() - t0
+    return out
 
 
 # (name, layout, tau, tuning changes): each a performance choice; the count never changes

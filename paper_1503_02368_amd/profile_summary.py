@@ -78,6 +78,44 @@ def kernel_stats(d: str):
     return _csv(d, "kernel_stats.csv")
 
 
+N_XCD, N_CU, N_SIMD = 8, 256, 1024
+
+
+def derived(c, avg_us):
+    """Issue, residency and busy fractions from the SQ/GRBM counters, when present.
+
+    GRBM_GUI_ACTIVE counts GPU-busy cycles summed over the 8 XCDs, so /8 over the
+    kernel's average duration gives the clock.  SQ_ACTIVE_INST_VALU counts the
+    VALU issue slots of wave64 instructions (it equals SQ_INSTS_VALU here), each
+    of which holds its SIMD for 4 cycles; SQ_WAVE_CYCLES and SQ_WAIT_ANY are in
+    the same 4-cycle units; SQ_BUSY_CU_CYCLES counts cycles summed over the CUs."""
+    g = {k: v for k, (v, _) in c.items()}
+    if "GRBM_GUI_ACTIVE" not in g:
+        return []
+    cyc = g["GRBM_GUI_ACTIVE"] / N_XCD
+    out = ["", "## Derived (per dispatch)", "",
+           f"* clock: {cyc / (avg_us * 1e-6) / 1e9:.2f} GHz ({cyc:,.0f} cycles per XCD over "
+           f"{avg_us:.1f} us)"]
+    if "SQ_ACTIVE_INST_VALU" in g:
+        out.append(f"* VALU busy: {4 * g['SQ_ACTIVE_INST_VALU'] / (N_SIMD * cyc) * 100:.1f} % of "
+                   f"{N_SIMD} SIMDs x cycles (4 cycles per wave64 VALU instruction)")
+    if "SQ_BUSY_CU_CYCLES" in g:
+        out.append(f"* CUs busy: {g['SQ_BUSY_CU_CYCLES'] / (N_CU * cyc) * 100:.1f} % of {N_CU} CUs x cycles")
+    if "SQ_WAVE_CYCLES" in g:
+        res = 4 * g["SQ_WAVE_CYCLES"] / cyc
+        waves = g.get("SQ_WAVES", 0)
+        out.append(f"* waves resident on average: {res:,.0f} (of {waves:,.0f} launched)")
+        if "SQ_WAIT_ANY" in g:
+            out.append(f"* share of wave time waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES): "
+                       f"{g['SQ_WAIT_ANY'] / g['SQ_WAVE_CYCLES'] * 100:.1f} %")
+    if "TCC_HIT_sum" in g and "TCC_MISS_sum" in g:
+        out.append(f"* L2 hit rate: {g['TCC_HIT_sum'] / (g['TCC_HIT_sum'] + g['TCC_MISS_sum']) * 100:.1f} %")
+    if "SQ_LDS_BANK_CONFLICT" in g and "SQ_ACTIVE_INST_LDS" in g:
+        out.append(f"* LDS bank-conflict cycles per LDS issue cycle: "
+                   f"{g['SQ_LDS_BANK_CONFLICT'] / g['SQ_ACTIVE_INST_LDS']:.2f}")
+    return out
+
+
 def stats_only(args):
     stats = kernel_stats(args.trace)
     with open(args.commands) as f:
@@ -165,7 +203,8 @@ def main():
               f"{wk * w_fac * 1024 / 1e6:.3f} MB",
               f"* Calibration: a copy of {args.copy_mib} MiB reads {cf:,.0f} KiB by FETCH_SIZE and "
               f"writes {cw:,.0f} KiB by WRITE_SIZE per dispatch (factors {f_fac:.3f}, {w_fac:.3f}).",
-              f"* HBM-side traffic per launch: {traffic / 1e9:.3f} GB; over the average duration "
+              f"* L2-to-fabric traffic per launch (reads the 256 MB last-level cache serves are "
+              f"included): {traffic / 1e9:.3f} GB; over the average duration "
               f"{avg_us:.1f} us that is {traffic / (avg_us * 1e-6) / 1e9:.0f} GB/s "
               f"({traffic / (avg_us * 1e-6) / 8e12 * 100:.1f} % of 8 TB/s)."]
     if args.algorithmic_bytes:
@@ -177,6 +216,7 @@ def main():
         for name in sorted(extra):
             v, n = extra[name]
             lines.append(f"| {name} | {v:,.0f} | {n} |")
+    lines += derived(extra, avg_us)
     src = os.path.join(ROOT, "paper_1503_02368_amd", "csrc", args.source)
     sha = kernel_sha(src)
     lines += ["", f"Kernel source hash ({args.source}, sha256 prefix): {sha}", ""]
