@@ -86,7 +86,7 @@ const char* eh_last_error(const eh_ctx* ctx);
 const char* eh_status_str(eh_status s);
 /* Version of this ABI (major * 10000 + minor * 100 + patch); a caller built
  * against this header checks that the library returns EH_ABI_VERSION. */
-#define EH_ABI_VERSION 10800
+#define EH_ABI_VERSION 10900
 int32_t eh_abi_version(void);
 
 /* ---- tuning knobs (performance only; counts never depend on them) ------- */
@@ -139,6 +139,10 @@ typedef struct eh_tuning {
   uint32_t group;        /* staged triangle kernel, target staging: up to this many small
                             consecutive work items of one graph share a wave (1, 2 or 4;
                             0 means 1) */
+  uint32_t reverse;      /* 1: waves take the work items from the last to the first (every
+                            schedule).  Items follow the held vertex's rank, and under degree
+                            order the highest ranks hold the heaviest sets, so they start
+                            first instead of forming the launch's tail */
 } eh_tuning;
 
 eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t);

@@ -37,9 +37,10 @@ DEFAULT_OUT = os.path.join(HERE, "tuning.json")
 
 BASE = dict(kernel=1, staging=2, algo=0, gamma=32.0, chunk_work=4096, waves_per_cu=32,
             group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0, xcds=0, unroll=8, grab=8,
-            search_below=24, group=1)
-# schedules tried last: (dynamic, grab); 3 and 4 cut the items into one range per XCD
-SCHEDULES = [(1, 8), (2, 8), (3, 8), (4, 1), (4, 4), (4, 16)]
+            search_below=24, group=1, reverse=0)
+# schedules tried last: (dynamic, grab); 3 and 4 cut the items into one range per XCD,
+# 5 deals items sorted by decreasing cost boustrophedon
+SCHEDULES = [(1, 8), (2, 8), (3, 8), (4, 1), (4, 4), (4, 16), (5, 8)]
 
 
 def log(*a):
@@ -135,6 +136,13 @@ def tune_graph(el, pattern, layouts, ctx, torch, quick=False, expect=None):
                 S.record(dict(layout=layout, tau=tau, s_min=s_min, tuning=cfg), ms, c)
                 if ms < local[0]:
                     local = (ms, cfg)
+            # the same schedule dealing the items from the last to the first
+            cfg = dict(local[1], reverse=1)
+            ctx.set_tuning(**cfg)
+            ms, c = timer.graph(trie, pattern)
+            S.record(dict(layout=layout, tau=tau, s_min=s_min, tuning=cfg), ms, c)
+            if ms < local[0]:
+                local = (ms, cfg)
             if local[1]["kernel"] == 1:
                 for sb in (12, 16, 32, 48):
                     cfg = dict(local[1], search_below=sb)

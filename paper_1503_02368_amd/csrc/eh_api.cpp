@@ -157,6 +157,7 @@ LaunchArgs base_args(Ctx* c, const Trie& t) {
   a.grab = c->tune.grab;
   a.search_below = c->tune.search_below;
   a.symmetric = t.host.symmetric ? 1u : 0u;
+  a.reverse = c->tune.reverse;
   return a;
 }
 
@@ -350,9 +351,9 @@ eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t) {
   if (t->waves_per_cu) u.waves_per_cu = t->waves_per_cu;
   u.group_lanes = t->group_lanes;
   u.use_bitsets = t->use_bitsets ? 1 : 0;
-  if (t->dynamic > 4) {
+  if (t->dynamic > 5) {
     ctx->c.err = "dynamic must be 0 (interleaved), 1 (atomic cursor), 2 (blocked), "
-                 "3 (partitioned interleave) or 4 (partitioned cursors)";
+                 "3 (partitioned interleave), 4 (partitioned cursors) or 5 (snake)";
     return EH_EINVAL;
   }
   if (t->xcds > kMaxParts) {
@@ -386,6 +387,11 @@ eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t) {
     return EH_EINVAL;
   }
   u.group = t->group ? t->group : 1;
+  if (t->reverse > 1) {
+    ctx->c.err = "reverse must be 0 or 1";
+    return EH_EINVAL;
+  }
+  u.reverse = t->reverse;
   return EH_OK;
 }
 
@@ -407,6 +413,7 @@ eh_status eh_ctx_get_tuning(const eh_ctx* ctx, eh_tuning* out) {
   out->grab = u.grab;
   out->search_below = u.search_below;
   out->group = u.group;
+  out->reverse = u.reverse;
   return EH_OK;
 }
 

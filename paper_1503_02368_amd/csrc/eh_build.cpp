@@ -632,15 +632,31 @@ uint64_t count_items_estimated(const HostTrie& h, uint32_t u, uint32_t chunk_wor
   return slice ? (uint64_t(du) + slice - 1) / slice : 0;
 }
 
+// The snake schedule deals items sorted by decreasing cost; a batch keeps
+// each graph's items contiguous (per-graph launches take ranges of them), so
+// its plans are not sorted and snake then only changes the dealing order.
+static void free_plan(Ctx* c, Plan& p) {
+  dev_free(c, p.items);
+  dev_free(c, p.sdesc);
+  dev_free(c, p.rec);
+  dev_free(c, p.gsub);
+  dev_free(c, p.k4s);
+}
+
+static bool wants_balance(const Tuning& tu, const HostTrie& h) {
+  return tu.dynamic == 5 && h.n_graphs == 1;
+}
+
 Plan* find_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging) {
   const Tuning& tu = c->tune;
   const uint32_t chunk = std::max<uint32_t>(tu.chunk_work, 64);
   if (pattern == EH_4CLIQUE) staging = EH_STAGE_SOURCE;
   const uint32_t group = (staging == EH_STAGE_TARGET && pattern == EH_TRIANGLE) ? tu.group : 1u;
+  const bool balanced = wants_balance(tu, t->host);
   for (auto& p : t->plans)
     if (p->pattern == pattern && p->staging == staging && p->chunk_work == chunk &&
         p->use_bitsets == tu.use_bitsets && p->stage_words == tu.stage_words &&
-        p->group == group)
+        p->group == group && p->balanced == balanced)
       return p.get();
   return nullptr;
 }
@@ -671,8 +687,15 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
       (plan->group <= 1 || h.n_graphs >= 256)) {
     const uint32_t cap = tu.stage_words && tu.stage_words < kStageWords ? tu.stage_words
                                                                          : kStageWords;
-    const eh_status st = device_plan_target(c, *t, *plan, chunk, ub, cap, plan->group);
-    if (st != EH_OK) return st;
+    eh_status st = device_plan_target(c, *t, *plan, chunk, ub, cap, plan->group);
+    if (st == EH_OK && wants_balance(tu, h)) {
+      plan->balanced = true;
+      st = device_plan_balance(c, *t, *plan);
+    }
+    if (st != EH_OK) {
+      free_plan(c, *plan);
+      return st;
+    }
     *out = plan.get();
     t->plans.push_back(std::move(plan));
     return EH_OK;
@@ -961,6 +984,13 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
       dev_free(c, plan->k4s);
       return st;
     }
+  if (wants_balance(tu, h)) {
+    plan->balanced = true;
+    if ((st = device_plan_balance(c, *t, *plan)) != EH_OK) {
+      free_plan(c, *plan);
+      return st;
+    }
+  }
   *out = plan.get();
   t->plans.push_back(std::move(plan));
   return EH_OK;

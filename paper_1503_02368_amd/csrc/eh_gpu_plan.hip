@@ -379,6 +379,128 @@ struct Scratch {
 
 }  // namespace
 
+namespace {
+
+// Estimated cost of each work item, in the planners' units (streamed
+// elements plus 2 per streamed set, plus the held set's members), as the key
+// (~cost << 32 | item) whose ascending sort puts the costliest items first.
+// Target staging reads the records (grouped items: their members' records);
+// source staging the streamed vertices' out-degrees, and for 4-cliques the
+// second level's estimate min(d+(u), d+(v)) * 24 per streamed vertex.
+__global__ void __launch_bounds__(kB) k_item_cost_keys(TrieView t, const Item* __restrict__ items,
+                                                       uint64_t n_items,
+                                                       const uint4* __restrict__ sdesc,
+                                                       const uint2* __restrict__ rec,
+                                                       const uint4* __restrict__ gsub,
+                                                       uint32_t target, uint32_t k4,
+                                                       unsigned long long* __restrict__ key) {
+  for (uint64_t i = gtid(); i < n_items; i += gstride()) {
+    const Item it = items[i];
+    uint64_t cost = 0;
+    if (target) {
+      if (gsub && (it.s & kHiBit)) {
+        const uint32_t gi = it.s & kMaxIndex;
+        for (uint32_t k = 0; k < it.lbeg; ++k) {
+          const uint4 g = gsub[gi + k];
+          cost += g.w;
+          for (uint32_t r = 0; r < g.y; ++r) cost += (rec[g.x + r].y & 0xFFFFu) + 2;
+        }
+      } else {
+        if (sdesc) cost += sdesc[i].y;
+        for (uint32_t r = 0; r < it.llen; ++r) cost += (rec[it.lbeg + r].y & 0xFFFFu) + 2;
+      }
+    } else {
+      const uint32_t du = outdeg(t, it.s);
+      cost = du;
+      for (uint32_t q = 0; q < it.llen; ++q) {
+        const uint32_t dv = outdeg(t, t.col[it.lbeg + q]);
+        cost += uint64_t(dv) + 2 + (k4 ? uint64_t(min(du, dv)) * 24 : 0);
+      }
+    }
+    const uint32_t c32 = cost > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(cost);
+    key[i] = (uint64_t(~c32) << 32) | uint64_t(i);
+  }
+}
+
+__global__ void __launch_bounds__(kB) k_permute_items(const unsigned long long* __restrict__ key,
+                                                      uint64_t n_items, const Item* __restrict__ in,
+                                                      const uint4* __restrict__ sd_in,
+                                                      Item* __restrict__ out,
+                                                      uint4* __restrict__ sd_out) {
+  for (uint64_t j = gtid(); j < n_items; j += gstride()) {
+    const uint32_t i = uint32_t(key[j] & 0xFFFFFFFFull);
+    out[j] = in[i];
+    if (sd_in) sd_out[j] = sd_in[i];
+  }
+}
+
+}  // namespace
+
+eh_status device_plan_balance(Ctx* c, Trie& tr, Plan& plan) {
+  const uint64_t n = plan.n_items;
+  if (n < 2) return EH_OK;
+  if (n > 0xFFFFFFFFull) {
+    c->err = "too many work items to sort by cost";
+    return EH_EOVERFLOW;
+  }
+  const HostTrie& h = tr.host;
+  hipStream_t s = c->stream;
+  TrieView tv{static_cast<const uint2*>(tr.vdesc.p), static_cast<const uint32_t*>(tr.col.p),
+              h.n_bs ? static_cast<const uint4*>(tr.bsdesc.p) : nullptr, h.n};
+  const bool target = plan.staging == EH_STAGE_TARGET && plan.pattern == EH_TRIANGLE;
+  DevBuf key_a, key_b, tmp, items2, sd2;
+  auto cleanup = [&]() {
+    dev_free(c, key_a);
+    dev_free(c, key_b);
+    dev_free(c, tmp);
+    dev_free(c, items2);
+    dev_free(c, sd2);
+  };
+  auto chk = [&](hipError_t e, const char* what) { return hip_check(c, e, what); };
+  eh_status st;
+  if ((st = dev_alloc(c, key_a, 8 * n)) != EH_OK || (st = dev_alloc(c, key_b, 8 * n)) != EH_OK ||
+      (st = dev_alloc(c, items2, sizeof(Item) * n)) != EH_OK ||
+      (plan.sdesc.p && (st = dev_alloc(c, sd2, sizeof(uint4) * n)) != EH_OK)) {
+    cleanup();
+    return st;
+  }
+  rocprim::double_buffer<unsigned long long> db(static_cast<unsigned long long*>(key_a.p),
+                                                static_cast<unsigned long long*>(key_b.p));
+  size_t tb = 0;
+  if ((st = chk(rocprim::radix_sort_keys(nullptr, tb, db, size_t(n), 0, 64, s),
+                "balance sort size")) != EH_OK ||
+      (st = dev_alloc(c, tmp, tb)) != EH_OK) {
+    cleanup();
+    return st;
+  }
+  hipLaunchKernelGGL(k_item_cost_keys, dim3(grid_of(n)), dim3(kB), 0, s, tv,
+                     static_cast<const Item*>(plan.items.p), n,
+                     target ? static_cast<const uint4*>(plan.sdesc.p) : nullptr,
+                     target ? static_cast<const uint2*>(plan.rec.p) : nullptr,
+                     target && plan.group > 1 ? static_cast<const uint4*>(plan.gsub.p) : nullptr,
+                     target ? 1u : 0u, plan.pattern == EH_4CLIQUE ? 1u : 0u,
+                     static_cast<unsigned long long*>(key_a.p));
+  tb = tmp.bytes;
+  if ((st = chk(rocprim::radix_sort_keys(tmp.p, tb, db, size_t(n), 0, 64, s), "balance sort")) !=
+      EH_OK) {
+    cleanup();
+    return st;
+  }
+  hipLaunchKernelGGL(k_permute_items, dim3(grid_of(n)), dim3(kB), 0, s, db.current(), n,
+                     static_cast<const Item*>(plan.items.p),
+                     static_cast<const uint4*>(plan.sdesc.p), static_cast<Item*>(items2.p),
+                     static_cast<uint4*>(sd2.p));
+  if ((st = chk(hipGetLastError(), "balance kernels")) != EH_OK ||
+      (st = chk(hipStreamSynchronize(s), "balance sync")) != EH_OK) {
+    cleanup();
+    return st;
+  }
+  std::swap(plan.items, items2);
+  if (plan.sdesc.p) std::swap(plan.sdesc, sd2);
+  cleanup();
+  return EH_OK;
+}
+
 eh_status device_plan_target(Ctx* c, Trie& tr, Plan& plan, uint32_t chunk, bool ub, uint32_t cap,
                              uint32_t group) {
   const HostTrie& h = tr.host;

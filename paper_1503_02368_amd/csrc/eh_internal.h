@@ -121,6 +121,7 @@ struct Tuning {
   uint32_t grab = 8;
   uint32_t search_below = 24;
   uint32_t group = 1;
+  uint32_t reverse = 0;
 };
 
 struct Ctx;
@@ -139,6 +140,7 @@ struct Plan {
   uint32_t use_bitsets = 0;
   uint32_t stage_words = 0;
   uint32_t group = 1;                // most per-vertex items in one grouped item
+  bool balanced = false;             // items sorted by decreasing estimated cost (schedule 5)
   uint64_t n_items = 0;
   DevBuf items;
   // target staging only: per item {begin, length, min, max} of the staged set,
@@ -248,6 +250,7 @@ struct LaunchArgs {
   uint32_t search_below = 24;          // average segment length below which the walk searches
   const uint4* gsub = nullptr;         // grouped items' members, or null
   uint32_t symmetric = 0;              // both directions of every edge are stored
+  uint32_t reverse = 0;                // items taken from the last to the first
   uint32_t* k4s = nullptr;             // 4-cliques: per-wave S lists in HBM for roots
   uint32_t k4s_stride = 0;             //   of out-degree > kK4ListMax, or null
   uint32_t k4s_waves = 0;
@@ -260,6 +263,9 @@ eh_status launch_4cliques(Ctx* c, hipStream_t s, const LaunchArgs& a, uint32_t k
                           uint32_t waves_per_cu);
 eh_status launch_scatter_roots(Ctx* c, hipStream_t s, const unsigned long long* by_rank,
                                const uint32_t* vert, unsigned long long* by_id, uint32_t n);
+// Sorts a built plan's items (and per-item descriptors) by decreasing
+// estimated cost, for the snake schedule.
+eh_status device_plan_balance(Ctx* c, Trie& t, Plan& plan);
 // The target-staging plan of a triangle count built on the GPU from the
 // trie's device arrays (items, descriptors, grouped members, records), equal
 // to the host planner's.

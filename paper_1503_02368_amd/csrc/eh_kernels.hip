@@ -82,6 +82,7 @@ struct DevArgs {
   uint32_t search_below;    // segments shorter on average: the walk binary-searches
   const uint4* gsub;        // grouped items' members, or null
   uint32_t symmetric;       // the trie holds both directions of every edge
+  uint32_t reverse;         // items taken from the last to the first
   uint32_t* k4s;            // 4-cliques: per-wave S lists in HBM (the HBM-list instance)
   uint32_t k4s_stride;      //   words per wave's list
 };
@@ -114,6 +115,7 @@ DevArgs to_dev(const LaunchArgs& a) {
   d.search_below = a.search_below;
   d.gsub = a.gsub;
   d.symmetric = a.symmetric;
+  d.reverse = a.reverse;
   d.k4s = a.k4s;
   d.k4s_stride = a.k4s_stride;
   return d;
@@ -180,22 +182,36 @@ __device__ __forceinline__ uint32_t lower_bound_glb(const uint32_t* __restrict__
 //    waves take `grab` consecutive items per fetch (the window of items in
 //    flight stays tight, so it stays in L2), and a wave whose range is used
 //    up moves on to the next range (work stealing across domains).
+//  5 snake: wave w of W takes positions w, 2W-1-w, 2W+w, 4W-1-w, ...; over
+//    items sorted by decreasing estimated cost (the plan sorts them for this
+//    schedule) every wave's sum of costs stays close to the mean, with no
+//    atomics.
 // P = DevArgs.xcds (0: 8, the XCD count of MI355X).  Cursors are
 // kCursorWords words apart, one per partition, zeroed before the launch.
 struct ItemIter {
   uint64_t i, step, end;
   uint32_t mode;
+  bool rev;
   uint32_t* cursor;
   uint64_t n;
   uint32_t part, parts, left, grab;
+  uint64_t sw, sid, sk;  // snake: waves, this wave, round
   __device__ ItemIter(const DevArgs& a, uint32_t wpb) {
     mode = a.dynamic;
+    rev = a.reverse != 0;
     cursor = a.cursor;
     end = a.n_items;
     n = a.n_items;
     if (mode == 1) {
       step = 0;
       i = fetch();
+      return;
+    }
+    if (mode == 5) {
+      sw = uint64_t(gridDim.x) * wpb;
+      sid = uint64_t(blockIdx.x) * wpb + (threadIdx.x >> 6);
+      sk = 0;
+      i = sid;
       return;
     }
     if (mode == 3 || mode == 4) {
@@ -235,6 +251,9 @@ struct ItemIter {
     }
   }
   __device__ bool more() const { return i < end; }
+  // The item the current position stands for: under `reverse`, position i
+  // takes item n - 1 - i, so the schedule deals the items last first.
+  __device__ uint64_t idx() const { return rev ? n - 1 - i : i; }
   __device__ uint64_t range_lo(uint32_t p) const { return n * p / parts; }
   __device__ uint64_t fetch() {
     uint32_t v = 0;
@@ -260,7 +279,10 @@ struct ItemIter {
     i = end = 0;
   }
   __device__ void next() {
-    if (mode == 1) i = fetch();
+    if (mode == 5) {
+      ++sk;
+      i = sk * sw + ((sk & 1) ? sw - 1 - sid : sid);
+    } else if (mode == 1) i = fetch();
     else if (mode == 4) { if (++i >= end) refill(); }
     else i += step;
   }
@@ -778,16 +800,16 @@ __device__ __forceinline__ void tri_staged(const DevArgs& a) {
   Item nitem{0, 0, 0, 0};
   uint4 nsd{0, 0, 0, 0};
   if (it.more()) {
-    nitem = a.items[it.i];
-    if (a.sdesc) nsd = a.sdesc[it.i];
+    nitem = a.items[it.idx()];
+    if (a.sdesc) nsd = a.sdesc[it.idx()];
   }
   while (it.more()) {
     const Item item = nitem;
     const uint4 sd = nsd;
     it.next();
     if (it.more()) {
-      nitem = a.items[it.i];
-      if (a.sdesc) nsd = a.sdesc[it.i];
+      nitem = a.items[it.idx()];
+      if (a.sdesc) nsd = a.sdesc[it.idx()];
     }
     const uint32_t s = uniform(item.s), lbeg = uniform(item.lbeg), llen = uniform(item.llen);
     const uint32_t tag = uniform(item.tag);
@@ -879,7 +901,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
   uint32_t cur_tag = 0;
   bool have_tag = false;
   for (ItemIter it(a, WPB); it.more(); it.next()) {
-    const Item item = a.items[it.i];
+    const Item item = a.items[it.idx()];
     const uint32_t u = uniform(item.s), lbeg = uniform(item.lbeg), llen = uniform(item.llen);
     const uint32_t tag = uniform(item.tag);
     if (have_tag && tag != cur_tag) flush_tag(a, acc, cur_tag, lane);
@@ -1052,7 +1074,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_tri_pairwise(DevArgs a) {
   uint32_t cur_tag = 0;
   bool have_tag = false;
   for (ItemIter it(a, WPB); it.more(); it.next()) {
-    const Item item = a.items[it.i];
+    const Item item = a.items[it.idx()];
     const uint32_t s = uniform(item.s), lbeg = uniform(item.lbeg), llen = uniform(item.llen);
     const uint32_t tag = uniform(item.tag);
     if (have_tag && tag != cur_tag) flush_tag(a, acc, cur_tag, lane);

@@ -141,6 +141,7 @@ eh_status server_launch(Server* s, const std::vector<Item>& v, uint64_t off, int
   a.unroll = tu.unroll;
   a.search_below = tu.search_below;
   a.symmetric = t.host.symmetric ? 1u : 0u;
+  a.reverse = tu.reverse;
   if (pattern == EH_4CLIQUE) return launch_4cliques(c, s->stream, a, tu.kernel, tu.waves_per_cu);
   return launch_triangles(c, s->stream, a, tu.kernel, tu.waves_per_cu);
 }

@@ -86,10 +86,18 @@ TUNINGS = {
     "staged_group": dict(kernel=1, staging=2, use_bitsets=1, group=4, dynamic=4, grab=3),
     "staged_group_lean": dict(kernel=1, staging=2, use_bitsets=1, group=2, stage_words=512,
                               search_below=0),
+    # items dealt from the last to the first
+    "staged_reverse": dict(kernel=1, staging=2, use_bitsets=1, stage_words=512, dynamic=4, grab=2,
+                           reverse=1),
+    "staged_source_rev": dict(kernel=1, staging=1, use_bitsets=1, dynamic=0, reverse=1),
+    # items sorted by decreasing estimated cost, dealt boustrophedon
+    "staged_snake": dict(kernel=1, staging=2, use_bitsets=1, stage_words=512, dynamic=5),
+    "staged_source_snake": dict(kernel=1, staging=1, use_bitsets=1, dynamic=5, chunk_work=512),
+    "staged_group_snake": dict(kernel=1, staging=2, use_bitsets=1, group=4, dynamic=5),
 }
 DEFAULT = dict(kernel=1, staging=2, algo=0, gamma=32.0, chunk_work=4096, waves_per_cu=32,
                group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0, xcds=0, unroll=8, grab=8,
-               search_below=24, group=1)
+               search_below=24, group=1, reverse=0)
 
 
 def tune(ctx, **kw):
@@ -118,7 +126,8 @@ def test_triangles_zoo(ctx, eh, tname, lay):
 
 @pytest.mark.parametrize("lay", LAYOUTS[:3], ids=lambda x: x[0])
 @pytest.mark.parametrize("tname", ["staged_source", "staged_nobits", "staged_list", "staged_global",
-                                   "staged_half", "staged_steal", "staged_search_src"])
+                                   "staged_half", "staged_steal", "staged_search_src",
+                                   "staged_source_rev", "staged_source_snake"])
 def test_4cliques_zoo(ctx, eh, tname, lay):
     tune(ctx, **TUNINGS[tname])
     for el in ZOO:
@@ -1018,9 +1027,10 @@ def test_randomized_parity(ctx, eh):
         else:
             el = inputs.messy(inputs.rmat(9, 8, seed=seed), seed)
         t = dict(kernel=choice([1, 1, 2]), staging=choice([1, 2]), use_bitsets=choice([0, 1]),
-                 dynamic=choice([0, 1, 2, 3, 4]), grab=choice([1, 3, 16]), xcds=choice([0, 3, 8]),
+                 dynamic=choice([0, 1, 2, 3, 4, 5]), grab=choice([1, 3, 16]), xcds=choice([0, 3, 8]),
                  stage_words=choice([0, 8, 96, 512]), search_below=choice([0, 12, 4096]),
                  group=choice([1, 2, 4]), chunk_work=choice([64, 1000, 32768]),
+                 reverse=choice([0, 1]),
                  waves_per_cu=choice([1, 8, 32]), unroll=choice([4, 8]),
                  group_lanes=choice([0, 4, 64]), algo=choice([0, 1, 2]))
         tune(ctx, **t)
@@ -1066,7 +1076,7 @@ def test_randomized_build_paths(ctx, eh):
         t = dict(kernel=choice([1, 1, 2]), staging=choice([1, 2]), use_bitsets=choice([0, 1]),
                  dynamic=choice([0, 2, 4]), stage_words=choice([0, 96, 512]),
                  group=choice([1, 2, 4]), chunk_work=choice([64, 4096]),
-                 search_below=choice([0, 24]), unroll=choice([4, 8]))
+                 search_below=choice([0, 24]), unroll=choice([4, 8]), reverse=choice([0, 1]))
         tune(ctx, **t)
         layout, tau = choice([(0, 32.0), (1, 32.0), (1, 256.0), (2, 32.0)])
         where = (case, kind, order, symmetric, device, t, layout, tau)
