@@ -195,7 +195,6 @@ struct ItemIter {
   uint32_t* cursor;
   uint64_t n;
   uint32_t part, parts, left, grab;
-  uint64_t sw, sid, sk;  // snake: waves, this wave, round
   __device__ ItemIter(const DevArgs& a, uint32_t wpb) {
     mode = a.dynamic;
     rev = a.reverse != 0;
@@ -208,10 +207,12 @@ struct ItemIter {
       return;
     }
     if (mode == 5) {
-      sw = uint64_t(gridDim.x) * wpb;
-      sid = uint64_t(blockIdx.x) * wpb + (threadIdx.x >> 6);
-      sk = 0;
-      i = sid;
+      // position k*W + w (k even) or k*W + W-1-w (k odd): the steps from one
+      // to the next alternate between 2(W-w)-1 and 2w+1, which sum to 2W
+      const uint32_t w = blockIdx.x * wpb + (threadIdx.x >> 6), W = gridDim.x * wpb;
+      i = w;
+      step = 2ull * (W - w) - 1;
+      left = 2u * W;
       return;
     }
     if (mode == 3 || mode == 4) {
@@ -280,8 +281,8 @@ struct ItemIter {
   }
   __device__ void next() {
     if (mode == 5) {
-      ++sk;
-      i = sk * sw + ((sk & 1) ? sw - 1 - sid : sid);
+      i += step;
+      step = left - step;
     } else if (mode == 1) i = fetch();
     else if (mode == 4) { if (++i >= end) refill(); }
     else i += step;
@@ -489,13 +490,19 @@ __device__ __forceinline__ WordRule word_rule(const DevArgs& a, const Staged& st
   return r;
 }
 
-// The whole set N+(t), as elements or, when fewer, as bitset words.
+// The whole set N+(t), as elements or, when fewer, as bitset words.  kEager:
+// when words may be used, the set's bitset descriptor is loaded beside its
+// extent instead of after it (one round trip to memory per batch of sets, for
+// two more registers).
+template <bool kEager = false>
 __device__ __forceinline__ Seg seg_full(const DevArgs& a, uint32_t t, const WordRule& wr) {
   const uint2 td = a.vdesc[t];
+  uint4 bd{0, 0, 0, 0};
+  if (kEager && wr.ok) bd = a.bsdesc[t];  // wr.ok implies a bitset table
   const uint32_t tl = td.y & kMaxIndex;
   Seg g{td.x, tl, 0};
   if (wr.ok && (td.y & kHiBit)) {
-    const uint4 bd = a.bsdesc[t];
+    if (!kEager) bd = a.bsdesc[t];
     if (bd.z < tl && bd.y >= wr.wmin) {
       g.sb = bd.x | kHiBit;
       g.len = bd.z;
@@ -976,7 +983,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
         for (uint32_t b0 = 0; b0 < ns; b0 += kSeg) {
           const uint32_t nseg = min(uint32_t(kSeg), ns - b0);
           Seg g{0, 0, 0};
-          if (lane < nseg) g = seg_full(a, S[b0 + lane], wr);
+          if (lane < nseg) g = seg_full<true>(a, S[b0 + lane], wr);
           const uint32_t E = publish_segments(T, g, lane);
           // bitmap bounds are B's (RW words); the list S is searched by length
           cnt += flat_probe<RW, U>(a, T, E, nseg, ss, probe, Lp, lane);
