@@ -252,11 +252,14 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the streaming-read probe (for profiling runs)")
-    ap.add_argument("--rates", default="200,1000,5000", help="served: arrival rates (QPS)")
+    ap.add_argument("--rates", default="100,200,500,1000,2000,5000",
+                    help="served: arrival rates (QPS)")
     ap.add_argument("--policy", type=int, default=1, choices=(0, 1),
                     help="served: 0 oldest request first, 1 fewest items left first")
-    ap.add_argument("--duration", type=float, default=3.0, help="served: seconds per rate")
-    ap.add_argument("--max-requests", type=int, default=3000, help="served: cap per rate")
+    ap.add_argument("--duration", type=float, default=10.0, help="served: measured seconds per rate")
+    ap.add_argument("--warmup-s", type=float, default=1.0, help="served: warm-up seconds per rate")
+    ap.add_argument("--max-requests", type=int, default=0,
+                    help="served: cap on requests per rate (0: none)")
     ap.add_argument("--no-per-instance", action="store_true",
                     help="batch: skip the one-launch-per-graph comparison (for profiling runs)")
     args = ap.parse_args()

@@ -363,14 +363,21 @@ eh_status eh_stream_read(eh_ctx* ctx, const void* d_buf, uint64_t bytes, uint32_
 /* ---- serving ------------------------------------------------------------ */
 
 /* A server keeps `resident` in HBM and answers rooted count requests.
- * Worker threads turn each submitted request into work items (its footprint:
- * 16 bytes per item plus its 8-byte counter).  A progress thread admits
- * expanded requests in arrival order while the summed footprint of active
- * requests stays within hbm_budget_bytes and fewer than max_active are
- * active, then advances all active requests together in device steps of at
- * most step_items work items.  Zero fields take the defaults in brackets. */
+ * Worker threads turn each submitted request into work items of 16 bytes
+ * (its footprint).  The server owns an HBM arena of hbm_budget_bytes: a
+ * progress thread admits expanded requests in arrival order while the next
+ * one's items fit a free extent of the arena (first fit) and fewer than
+ * max_active are active, uploads them into it, and advances all active
+ * requests together in device steps of at most step_items work items, which
+ * a gather kernel copies from the arena into the step's item list; a request
+ * frees its extent when it completes.  Besides the arena the server holds
+ * step_items * 16 bytes for the step's items, 8 bytes per active slot, its
+ * work cursors and, for a trie with an out-degree above 2048, the 4-clique
+ * S lists (4 per compute unit, each of the largest out-degree).  Zero fields
+ * take the defaults in brackets. */
 typedef struct eh_server_opts {
-  uint64_t hbm_budget_bytes;  /* [2 GiB] */
+  uint64_t hbm_budget_bytes;  /* [2 GiB] size of the arena of admitted work items, at most
+                                 64 GiB (EH_EINVAL beyond, or below 16 bytes) */
   uint32_t max_active;        /* [256] */
   uint32_t max_queued;        /* [4096] submitted, not yet admitted */
   uint32_t step_items;        /* [262144] */
@@ -394,7 +401,7 @@ typedef struct eh_req_stats {
 eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server_opts* opts,
                            eh_server** out);
 /* Copies roots; returns a ticket.  EH_EBUSY when max_queued are waiting,
- * EH_ENOMEM when the request alone exceeds the budget.  When the budget holds
+ * EH_ENOMEM when the request's items alone exceed the arena.  When the budget holds
  * the request with every vertex a root, the roots are only checked and copied
  * here and expanded by a worker; otherwise this call expands them itself so
  * that it can refuse the request. */

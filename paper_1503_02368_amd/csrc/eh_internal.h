@@ -261,6 +261,9 @@ eh_status launch_triangles(Ctx* c, hipStream_t s, const LaunchArgs& a, uint32_t 
                            uint32_t waves_per_cu);
 eh_status launch_4cliques(Ctx* c, hipStream_t s, const LaunchArgs& a, uint32_t kernel,
                           uint32_t waves_per_cu);
+// dst[piece.y + k] = src[piece.x + k] for k < piece.z, for every piece.
+eh_status launch_gather_items(Ctx* c, hipStream_t s, const Item* src, const uint4* pieces,
+                              uint32_t n_pieces, Item* dst);
 eh_status launch_scatter_roots(Ctx* c, hipStream_t s, const unsigned long long* by_rank,
                                const uint32_t* vert, unsigned long long* by_id, uint32_t n);
 // Sorts a built plan's items (and per-item descriptors) by decreasing

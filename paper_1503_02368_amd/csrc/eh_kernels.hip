@@ -1104,6 +1104,16 @@ __global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long
     p[i] = v;
 }
 
+// Copies pieces {first source item, first destination item, items, 0} of
+// work items: one block per piece, its lanes striding over the piece.
+__global__ void k_gather_items(const Item* __restrict__ src, const uint4* __restrict__ pieces,
+                               uint32_t n_pieces, Item* __restrict__ dst) {
+  for (uint32_t p = blockIdx.x; p < n_pieces; p += gridDim.x) {
+    const uint4 pc = pieces[p];
+    for (uint32_t k = threadIdx.x; k < pc.z; k += blockDim.x) dst[pc.y + k] = src[pc.x + k];
+  }
+}
+
 __global__ void k_scatter_roots(const unsigned long long* by_rank, const uint32_t* vert,
                                 unsigned long long* by_id, uint32_t n) {
   for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
@@ -1159,6 +1169,14 @@ eh_status launch_fill_u64(Ctx* c, hipStream_t s, unsigned long long* p, uint64_t
   const uint32_t blocks = uint32_t(std::min<uint64_t>((n + 255) / 256, 4096));
   hipLaunchKernelGGL(k_fill_u64, dim3(blocks), dim3(256), 0, s, p, n, v);
   return hip_check(c, hipGetLastError(), "fill kernel launch");
+}
+
+eh_status launch_gather_items(Ctx* c, hipStream_t s, const Item* src, const uint4* pieces,
+                              uint32_t n_pieces, Item* dst) {
+  if (n_pieces == 0) return EH_OK;
+  hipLaunchKernelGGL(k_gather_items, dim3(std::min<uint32_t>(n_pieces, 4096)), dim3(256), 0, s, src,
+                     pieces, n_pieces, dst);
+  return hip_check(c, hipGetLastError(), "gather kernel launch");
 }
 
 eh_status launch_scatter_roots(Ctx* c, hipStream_t s, const unsigned long long* by_rank,

@@ -14,13 +14,15 @@
 // thread expands it itself, so that such a request is refused at submission.
 //
 // Continuous batching: a progress thread repeatedly (1) admits queued
-// requests in arrival order while the summed device footprint of active
-// requests fits the budget and a slot is free, (2) gathers up to step_items
-// work items from all active requests, oldest first (or, by option, those
-// with the fewest items left first), (3) runs them as one device step (one
-// launch per pattern, two for 4-cliques with roots of out-degree above 512)
-// that adds into per-slot counters, and
-// (4) retires every request whose items have all completed.  Requests that
+// requests in arrival order while their work items fit the server's HBM
+// arena (hbm_budget_bytes, first fit) and a counter slot is free, uploading
+// each admitted request's items into its extent of the arena, (2) chooses up
+// to step_items of the active requests' items, oldest request first (or, by
+// option, those with the fewest items left first), which a gather kernel
+// copies from the arena into the step's item list, (3) runs them as one
+// device step (one launch per pattern, more for 4-cliques with roots of high
+// out-degree) that adds into per-slot counters, and (4) retires every request
+// whose items have all completed, freeing its extent.  Requests that
 // arrive while a step runs join the next step; their work shares launches with
 // requests admitted earlier.  The step after the one that finishes a request
 // never waits for that request to be polled.
@@ -28,6 +30,8 @@
 #include <chrono>
 #include <cstring>
 #include <ctime>
+#include <iterator>
+#include <map>
 
 #include "eh_internal.h"
 
@@ -46,7 +50,8 @@ struct Request {
   std::vector<uint32_t> roots;  // as submitted, until expanded
   std::vector<Item> items;  // tag filled at admission
   uint32_t item_dmax = 0;   // max out-degree of an item's root
-  uint64_t footprint = 0;
+  uint64_t footprint = 0;   // bytes its items take in the arena
+  uint64_t arena_off = 0;   // item index of its extent in the arena
   uint64_t next_item = 0;   // next item to dispatch
   uint64_t done_items = 0;  // items whose step completed
   uint32_t slot = 0;
@@ -67,9 +72,12 @@ struct Server {
   DevBuf cursor;           // work cursors of the server's own launches
   DevBuf items_d;          // step_items Items
   DevBuf acc_d;            // max_active uint64
+  DevBuf arena;             // admitted requests' work items (hbm_budget_bytes)
+  std::map<uint64_t, uint64_t> free_ext;  // free arena extents: first item -> items
+  DevBuf pieces_d;         // per step: {first arena item, first step item, items, 0}
+  uint4* pieces_h = nullptr;
   DevBuf k4s;              // 4-clique S lists in HBM, when some out-degree exceeds kK4ListMax
   uint32_t k4s_waves = 0, k4s_stride = 0;
-  Item* items_h = nullptr; // pinned staging
   uint64_t* acc_h = nullptr;
   std::mutex mu;
   std::condition_variable cv_work;   // progress thread waits for work
@@ -96,10 +104,13 @@ struct Server {
   std::condition_variable cv_incoming;
   std::vector<std::thread> workers;
   uint32_t chunk = 4096;                       // item size target, fixed at creation
+  uint64_t arena_items = 0;                    // the arena's capacity in items
   bool async_ok[5] = {false, false, false, false, false};  // by pattern
 
   void run();
   bool step();
+  bool arena_take(uint64_t n_items, uint64_t& off);
+  void arena_give(uint64_t off, uint64_t n_items);
   void expand(Request& r, Dedup& d) const;
   void expand_loop(uint32_t w);
   void enqueue_expanded(const std::shared_ptr<Request>& r);  // caller holds mu
@@ -107,9 +118,9 @@ struct Server {
 
 namespace {
 
-eh_status server_launch(Server* s, const std::vector<Item>& v, uint64_t off, int pattern,
+eh_status server_launch(Server* s, uint64_t n_items, uint64_t off, int pattern,
                         uint32_t item_dmax) {
-  if (v.empty()) return EH_OK;
+  if (n_items == 0) return EH_OK;
   Ctx* c = s->c;
   Trie& t = *s->t;
   LaunchArgs a;
@@ -120,7 +131,7 @@ eh_status server_launch(Server* s, const std::vector<Item>& v, uint64_t off, int
   a.vert = static_cast<const uint32_t*>(t.vert.p);
   a.idx = static_cast<const uint32_t*>(t.col.p);
   a.items = static_cast<const Item*>(s->items_d.p) + off;
-  a.n_items = v.size();
+  a.n_items = n_items;
   a.acc = static_cast<unsigned long long*>(s->acc_d.p);
   a.tag_base = 0;
   const Tuning& tu = s->tune;
@@ -148,26 +159,62 @@ eh_status server_launch(Server* s, const std::vector<Item>& v, uint64_t off, int
 
 }  // namespace
 
+// First fit over the free extents of the arena (in items).
+bool Server::arena_take(uint64_t n_items, uint64_t& off) {
+  for (auto it = free_ext.begin(); it != free_ext.end(); ++it) {
+    if (it->second < n_items) continue;
+    off = it->first;
+    const uint64_t rest = it->second - n_items;
+    free_ext.erase(it);
+    if (rest) free_ext.emplace(off + n_items, rest);
+    return true;
+  }
+  return false;
+}
+
+// Returns an extent, merged with free neighbours.
+void Server::arena_give(uint64_t off, uint64_t n_items) {
+  auto next = free_ext.lower_bound(off);
+  if (next != free_ext.end() && off + n_items == next->first) {
+    n_items += next->second;
+    next = free_ext.erase(next);
+  }
+  if (next != free_ext.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      prev->second += n_items;
+      return;
+    }
+  }
+  free_ext.emplace(off, n_items);
+}
+
 // One device step.  Returns false when there is nothing to do.
 bool Server::step() {
   std::vector<std::shared_ptr<Request>> batch_reqs;
   std::vector<uint32_t> to_zero;
-  std::vector<Item> tri, k4;
+  std::vector<Request*> admitted;
+  std::vector<uint4> tri, k4;  // pieces {first arena item, first step item, items, 0}
+  uint64_t n_tri = 0, n_k4 = 0;
   uint32_t dmax_tri = 0, dmax_k4 = 0;
   // requests stay alive in `active` until this thread retires them
   std::vector<std::pair<Request*, uint64_t>> dispatched;
   {
     std::unique_lock<std::mutex> lk(mu);
-    // admission, arrival order
+    // admission, arrival order: the request's items must fit the arena (a
+    // request larger than the whole arena was refused at submission)
     while (!queue.empty() && !free_slots.empty() && !stop) {
       auto& r = queue.front();
-      if (footprint + r->footprint > o.hbm_budget_bytes && !active.empty()) break;
+      uint64_t off = 0;
+      if (!arena_take(r->items.size(), off)) break;
+      r->arena_off = off;
       r->slot = free_slots.back();
       free_slots.pop_back();
       for (auto& it : r->items) it.tag = r->slot;
       r->stats.t_admit_ns = now_ns();
       footprint += r->footprint;
       active.push_back(r);
+      admitted.push_back(r.get());
       queue.pop_front();
     }
     if (active.empty()) return false;
@@ -187,30 +234,49 @@ bool Server::step() {
         r->zeroed = true;
       }
       const uint64_t take = std::min<uint64_t>(budget, r->items.size() - r->next_item);
-      auto& dst = r->pattern == EH_4CLIQUE ? k4 : tri;
-      auto& dm = r->pattern == EH_4CLIQUE ? dmax_k4 : dmax_tri;
-      if (take) dm = std::max(dm, r->item_dmax);
-      dst.insert(dst.end(), r->items.begin() + r->next_item, r->items.begin() + r->next_item + take);
+      const bool is_k4 = r->pattern == EH_4CLIQUE;
+      auto& dst = is_k4 ? k4 : tri;
+      auto& dm = is_k4 ? dmax_k4 : dmax_tri;
+      uint64_t& filled = is_k4 ? n_k4 : n_tri;
+      if (take) {
+        dm = std::max(dm, r->item_dmax);
+        dst.push_back(make_uint4(uint32_t(r->arena_off + r->next_item), uint32_t(filled),
+                                 uint32_t(take), 0u));
+        filled += take;
+      }
       r->next_item += take;
       budget -= take;
       dispatched.emplace_back(r, take);
       if (budget == 0) break;
     }
   }
-  // device step: zero new slots, upload items, launch, read counters
+  // device step: upload the newly admitted requests' items into their
+  // extents, zero new slots, gather the step's items from the arena, launch,
+  // read counters.  The items of an active request stay in host memory
+  // until it retires, so the uploads can be asynchronous.
   eh_status st = EH_OK;
+  Item* arena_items = static_cast<Item*>(arena.p);
+  for (Request* r : admitted)
+    if (st == EH_OK)
+      st = hip_check(c, hipMemcpyAsync(arena_items + r->arena_off, r->items.data(),
+                                       r->items.size() * sizeof(Item), hipMemcpyHostToDevice,
+                                       stream), "upload request items");
   for (uint32_t slot : to_zero)
     if (st == EH_OK)
       st = launch_fill_u64(c, stream, static_cast<unsigned long long*>(acc_d.p) + slot, 1, 0);
-  const uint64_t n_tri = tri.size(), n_k4 = k4.size();
-  if (st == EH_OK && n_tri + n_k4) {
-    std::memcpy(items_h, tri.data(), n_tri * sizeof(Item));
-    std::memcpy(items_h + n_tri, k4.data(), n_k4 * sizeof(Item));
-    st = hip_check(c, hipMemcpyAsync(items_d.p, items_h, (n_tri + n_k4) * sizeof(Item),
-                                     hipMemcpyHostToDevice, stream), "upload step items");
+  for (uint4& pc : k4) pc.y += uint32_t(n_tri);  // the 4-clique items follow the triangles'
+  const size_t n_pieces = tri.size() + k4.size();
+  if (st == EH_OK && n_pieces) {
+    std::memcpy(pieces_h, tri.data(), tri.size() * sizeof(uint4));
+    std::memcpy(pieces_h + tri.size(), k4.data(), k4.size() * sizeof(uint4));
+    st = hip_check(c, hipMemcpyAsync(pieces_d.p, pieces_h, n_pieces * sizeof(uint4),
+                                     hipMemcpyHostToDevice, stream), "upload step pieces");
+    if (st == EH_OK)
+      st = launch_gather_items(c, stream, arena_items, static_cast<const uint4*>(pieces_d.p),
+                               uint32_t(n_pieces), static_cast<Item*>(items_d.p));
   }
-  if (st == EH_OK) st = server_launch(this, tri, 0, EH_TRIANGLE, dmax_tri);
-  if (st == EH_OK) st = server_launch(this, k4, n_tri, EH_4CLIQUE, dmax_k4);
+  if (st == EH_OK) st = server_launch(this, n_tri, 0, EH_TRIANGLE, dmax_tri);
+  if (st == EH_OK) st = server_launch(this, n_k4, n_tri, EH_4CLIQUE, dmax_k4);
   if (st == EH_OK)
     st = hip_check(c, hipMemcpyAsync(acc_h, acc_d.p, o.max_active * sizeof(uint64_t),
                                      hipMemcpyDeviceToHost, stream), "read counters");
@@ -227,6 +293,7 @@ bool Server::step() {
         r->stats.t_done_ns = t_done;
         r->finished = true;
         footprint -= r->footprint;
+        arena_give(r->arena_off, r->items.size());
         free_slots.push_back(r->slot);
         std::vector<Item>().swap(r->items);
         done.push_back(r);
@@ -299,7 +366,7 @@ void Server::expand(Request& r, Dedup& d) const {
     if (r.items.size() > before) r.item_dmax = std::max(r.item_dmax, row[u + 1] - row[u]);
   }
   r.stats.items = r.items.size();
-  r.footprint = sizeof(Item) * r.items.size() + sizeof(uint64_t);
+  r.footprint = sizeof(Item) * r.items.size();
   std::vector<uint32_t>().swap(r.roots);
 }
 
@@ -385,9 +452,21 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
     s.k4s_stride = t->host.dmax;
     st = dev_alloc(c, s.k4s, sizeof(uint32_t) * size_t(s.k4s_stride) * s.k4s_waves);
   }
+  s.arena_items = s.o.hbm_budget_bytes / sizeof(Item);
+  if (st == EH_OK && s.arena_items > 0xFFFFFFFFull) {
+    c->err = "hbm_budget_bytes above 64 GiB (2^32 work items)";
+    st = EH_EINVAL;
+  }
+  if (st == EH_OK && s.arena_items == 0) {
+    c->err = "hbm_budget_bytes holds no work item";
+    st = EH_EINVAL;
+  }
+  if (st == EH_OK) st = dev_alloc(c, s.arena, s.arena_items * sizeof(Item));
+  if (st == EH_OK) s.free_ext.emplace(0, s.arena_items);
+  if (st == EH_OK) st = dev_alloc(c, s.pieces_d, sizeof(uint4) * s.o.max_active);
   if (st == EH_OK)
-    st = hip_check(c, hipHostMalloc((void**)&s.items_h, sizeof(Item) * s.o.step_items,
-                                    hipHostMallocDefault), "pinned items");
+    st = hip_check(c, hipHostMalloc((void**)&s.pieces_h, sizeof(uint4) * s.o.max_active,
+                                    hipHostMallocDefault), "pinned pieces");
   if (st == EH_OK)
     st = hip_check(c, hipHostMalloc((void**)&s.acc_h, sizeof(uint64_t) * s.o.max_active,
                                     hipHostMallocDefault), "pinned counters");
@@ -396,7 +475,9 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
     dev_free(c, s.acc_d);
     dev_free(c, s.cursor);
     dev_free(c, s.k4s);
-    if (s.items_h) (void)hipHostFree(s.items_h);
+    dev_free(c, s.arena);
+    dev_free(c, s.pieces_d);
+    if (s.pieces_h) (void)hipHostFree(s.pieces_h);
     if (s.acc_h) (void)hipHostFree(s.acc_h);
     if (s.stream) (void)hipStreamDestroy(s.stream);
     delete x;
@@ -411,7 +492,7 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
   for (uint32_t p : {uint32_t(EH_TRIANGLE), uint32_t(EH_4CLIQUE)}) {
     uint64_t all = 0;
     for (uint32_t u = 0; u < h.n; ++u) all += count_items_estimated(h, u, s.chunk, p);
-    s.async_ok[p] = all * sizeof(Item) + sizeof(uint64_t) <= s.o.hbm_budget_bytes;
+    s.async_ok[p] = all <= s.arena_items;
   }
   const uint32_t hw = std::max(1u, std::thread::hardware_concurrency());
   const uint32_t n_workers = std::min(4u, std::max(1u, hw / 4));
@@ -424,7 +505,9 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
     dev_free(c, s.acc_d);
     dev_free(c, s.cursor);
     dev_free(c, s.k4s);
-    (void)hipHostFree(s.items_h);
+    dev_free(c, s.arena);
+    dev_free(c, s.pieces_d);
+    (void)hipHostFree(s.pieces_h);
     (void)hipHostFree(s.acc_h);
     (void)hipStreamDestroy(s.stream);
     delete x;
@@ -454,7 +537,7 @@ eh_status eh_submit(eh_server* srv, int pattern, const uint32_t* roots, uint32_t
       std::lock_guard<std::mutex> lk(s.sync_mu);
       s.expand(*r, s.sync_dedup);
     }
-    if (r->footprint > s.o.hbm_budget_bytes) return EH_ENOMEM;
+    if (r->items.size() > s.arena_items) return EH_ENOMEM;
   }
   {
     std::unique_lock<std::mutex> lk(s.mu);
@@ -573,7 +656,9 @@ eh_status eh_server_destroy(eh_server* srv) {
   dev_free(s.c, s.acc_d);
   dev_free(s.c, s.cursor);
   dev_free(s.c, s.k4s);
-  if (s.items_h) (void)hipHostFree(s.items_h);
+  dev_free(s.c, s.arena);
+  dev_free(s.c, s.pieces_d);
+  if (s.pieces_h) (void)hipHostFree(s.pieces_h);
   if (s.acc_h) (void)hipHostFree(s.acc_h);
   (void)hipStreamDestroy(s.stream);
   delete srv;

@@ -354,6 +354,55 @@ def test_server_alone_equals_mix(ctx, eh, policy):
     trie.free()
 
 
+def test_server_arena_first_fit(ctx, eh):
+    """Admission by the HBM arena: requests of very different sizes under a
+    budget a little above the largest one's items wait for extents to free up
+    (first fit, merged on release) and still answer exactly; a request whose
+    items exceed the arena is refused, and so is an arena of no item."""
+    tune(ctx, staging=1)
+    el = inputs.rmat(12, 16, seed=31)
+    g = oracle.Graph.from_edgelist(el)
+    rt = g.triangles(rooted=True)["root"]
+    rk = g.cliques4(rooted=True)["root"]
+    trie = ctx.build_edgelist(el)
+    key = inputs.stream_key(31, 7)
+    sizes = [int(x) for x in (inputs.rand_u64(key, 0, 40) % np.uint64(1200)) + np.uint64(1)]
+    reqs = []
+    for i, k in enumerate(sizes):
+        roots = (inputs.rand_u64(inputs.stream_key(32, i), 0, k) % np.uint64(el.n)).astype(np.uint32)
+        reqs.append((3 if i % 3 else 4, roots))
+    want = [oracle.rooted_count(rt if p == 3 else rk, r) for p, r in reqs]
+    everything = (4, np.arange(el.n, dtype=np.uint32))
+    # the items of each request, from a server whose arena holds them all
+    srv = ctx.server(trie)
+    try:
+        res = [srv.wait(srv.submit(p, r)) for p, r in reqs + [everything]]
+    finally:
+        srv.close()
+    assert [x.count for x in res[:-1]] == want
+    items = [x.items for x in res]
+    budget = max(items[:-1]) + 3
+    assert sum(items[:-1]) > 3 * budget   # most requests wait for room
+    srv = ctx.server(trie, hbm_budget_bytes=16 * budget, max_active=8, step_items=300, policy=1)
+    try:
+        tickets = [srv.submit(p, r) for p, r in reqs]
+        assert [srv.wait(t).count for t in tickets] == want
+        if items[-1] > budget:
+            with pytest.raises(eh.EHError) as e:
+                srv.submit(*everything)
+            assert e.value.status == eh.EH_ENOMEM
+    finally:
+        srv.close()
+        trie.free()
+    small = ctx.build_edgelist(inputs.complete(5))
+    try:
+        with pytest.raises(eh.EHError) as e:
+            ctx.server(small, hbm_budget_bytes=8)
+        assert e.value.status == eh.EH_EINVAL
+    finally:
+        small.free()
+
+
 def test_full_size_rmat20_triangles(ctx, eh):
     """The measured workload: R-MAT scale 20, edge factor 16, hybrid layout."""
     tune(ctx)
