@@ -236,9 +236,13 @@ eh_status eh_build_batch(eh_ctx* ctx, uint32_t n_graphs, const uint32_t* n_verti
  * the same host copy (downloaded for work-item planning; the bitset words
  * stay in device memory only).  d_src/d_dst: device arrays of n_edges
  * uint32, read on the context's stream and not kept; the caller keeps them
- * valid until the call returns.  Orderings that are sorts only
- * (EH_ORDER_DEGREE, EH_ORDER_REV_DEGREE, EH_ORDER_INPUT); the traversal
- * orderings are EH_EINVAL here.  An id >= n is EH_EINVAL.  Scratch device
+ * valid until the call returns.  Every node ordering: the sorts (degree,
+ * reverse degree, input) and the traversals (BFS, hybrid, strong runs), whose
+ * label sequences are computed in parallel (strong runs by each vertex's
+ * first visit among itself and its neighbours; BFS level by level over the
+ * connected components, a level ordered by (label of the first-visiting
+ * parent, id)), equal to the host's sequential ones.  An id >= n is
+ * EH_EINVAL; a traversal ordering of 2^31 vertices or more EH_EOVERFLOW.  Scratch device
  * memory of about 16 bytes per raw pair (32 for a symmetric trie) and 40 per
  * vertex, plus the sorts' working space, is freed before it returns. */
 eh_status eh_build_trie_device(eh_ctx* ctx, const uint32_t* d_src, const uint32_t* d_dst,
@@ -248,8 +252,10 @@ eh_status eh_build_trie_device(eh_ctx* ctx, const uint32_t* d_src, const uint32_
 /* The batch trie of eh_build_batch, built on the GPU (as
  * eh_build_trie_device): n_vertices and edge_off are host arrays as in
  * eh_build_batch; d_src/d_dst are device arrays of local ids, graph g's pairs
- * at [edge_off[g], edge_off[g+1]).  Same orderings and errors as
- * eh_build_trie_device (an id >= its graph's n_vertices is EH_EINVAL). */
+ * at [edge_off[g], edge_off[g+1]).  The orderings that are sorts (degree,
+ * reverse degree, input); the traversal orderings are EH_EINVAL for a batch
+ * (build it with eh_build_batch).  An id >= its graph's n_vertices is
+ * EH_EINVAL. */
 eh_status eh_build_batch_device(eh_ctx* ctx, uint32_t n_graphs, const uint32_t* n_vertices,
                                 const uint64_t* edge_off, const uint32_t* d_src,
                                 const uint32_t* d_dst, const eh_build_opts* opts, eh_trie** out);

@@ -465,10 +465,6 @@ eh_status eh_build_trie_device(eh_ctx* ctx, const uint32_t* d_src, const uint32_
     return EH_EINVAL;
   }
   const BuildOpts o = resolve_opts(opts);
-  if (o.order != EH_ORDER_DEGREE && o.order != EH_ORDER_REV_DEGREE && o.order != EH_ORDER_INPUT) {
-    ctx->c.err = "traversal orderings (BFS, hybrid, strong runs) are built on the host";
-    return EH_EINVAL;
-  }
   eh_trie* x = new (std::nothrow) eh_trie();
   if (!x) return EH_ENOMEM;
   x->t.ctx = &ctx->c;
@@ -503,7 +499,7 @@ eh_status eh_build_batch_device(eh_ctx* ctx, uint32_t n_graphs, const uint32_t* 
   }
   const BuildOpts o = resolve_opts(opts);
   if (o.order != EH_ORDER_DEGREE && o.order != EH_ORDER_REV_DEGREE && o.order != EH_ORDER_INPUT) {
-    ctx->c.err = "traversal orderings (BFS, hybrid, strong runs) are built on the host";
+    ctx->c.err = "traversal orderings (BFS, hybrid, strong runs) of a batch are built on the host";
     return EH_EINVAL;
   }
   DeviceBatch b;

@@ -8,7 +8,8 @@
 //   2. radix sort and unique: the simple undirected edge set;
 //   3. degrees (atomic counts), then ranks from a stable radix sort of
 //      (degree, id) pairs: degree order, reverse degree order or the input
-//      ids (the orderings that are sorts; traversal orderings need the host);
+//      ids; for a single graph also the traversal orderings (BFS, hybrid,
+//      strong runs), whose label sequences eh_gpu_order.hip computes;
 //   4. each edge becomes low rank << k | high rank; a second radix sort gives
 //      the oriented CSR (rows found by binary search of the sorted keys);
 //   5. per set the density rule picks the bitset layout, a scan places the
@@ -378,21 +379,6 @@ __global__ void __launch_bounds__(kB) k_tables(const uint32_t* __restrict__ row,
   }
 }
 
-// Device buffers of one build; freed on every exit path.
-struct Scratch {
-  Ctx* c;
-  std::vector<DevBuf*> bufs;
-  explicit Scratch(Ctx* ctx) : c(ctx) {}
-  eh_status get(DevBuf& b, size_t bytes) {
-    bufs.push_back(&b);
-    return dev_alloc(c, b, bytes);
-  }
-  ~Scratch() {
-    (void)hipStreamSynchronize(c->stream);
-    for (DevBuf* b : bufs) dev_free(c, *b);
-  }
-};
-
 template <class T>
 T* ptr(DevBuf& b) {
   return static_cast<T*>(b.p);
@@ -569,6 +555,14 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
                        ptr<uint32_t>(rank), ptr<uint32_t>(t.vert));
   } else if (opts.order == EH_ORDER_INPUT) {
     hipLaunchKernelGGL(k_ranks, dim3(grid_of(n1)), dim3(kB), 0, s, ptr<uint32_t>(ids), n, 1u,
+                       ptr<uint32_t>(rank), ptr<uint32_t>(t.vert));
+  } else if (opts.order == EH_ORDER_BFS || opts.order == EH_ORDER_HYBRID ||
+             opts.order == EH_ORDER_STRONG_RUNS) {
+    // traversal orderings: the label sequence, then rank = n - 1 - label
+    if ((st = device_traversal_sequence(c, uniq, edges, kb, n, ptr<uint32_t>(deg), opts.order,
+                                        ptr<uint32_t>(seq))) != EH_OK)
+      return st;
+    hipLaunchKernelGGL(k_ranks, dim3(grid_of(n1)), dim3(kB), 0, s, ptr<uint32_t>(seq), n, 1u,
                        ptr<uint32_t>(rank), ptr<uint32_t>(t.vert));
   } else {
     // stable: equal degrees keep ids ascending

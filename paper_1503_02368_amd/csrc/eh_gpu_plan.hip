@@ -363,20 +363,6 @@ T* ptr(DevBuf& b) {
   return static_cast<T*>(b.p);
 }
 
-struct Scratch {
-  Ctx* c;
-  std::vector<DevBuf*> bufs;
-  explicit Scratch(Ctx* ctx) : c(ctx) {}
-  eh_status get(DevBuf& b, size_t bytes) {
-    bufs.push_back(&b);
-    return dev_alloc(c, b, bytes);
-  }
-  ~Scratch() {
-    (void)hipStreamSynchronize(c->stream);
-    for (DevBuf* b : bufs) dev_free(c, *b);
-  }
-};
-
 }  // namespace
 
 namespace {

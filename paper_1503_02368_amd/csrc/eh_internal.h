@@ -203,6 +203,21 @@ eh_status dev_alloc(Ctx* c, DevBuf& b, size_t bytes);
 void dev_free(Ctx* c, DevBuf& b);
 eh_status hip_check(Ctx* c, hipError_t e, const char* what);
 eh_status ensure_acc(Ctx* c, size_t n);
+
+// Device buffers of one call, freed (after the stream drains) when it returns.
+struct Scratch {
+  Ctx* c;
+  std::vector<DevBuf*> bufs;
+  explicit Scratch(Ctx* ctx) : c(ctx) {}
+  eh_status get(DevBuf& b, size_t bytes) {
+    bufs.push_back(&b);
+    return dev_alloc(c, b, bytes);
+  }
+  ~Scratch() {
+    (void)hipStreamSynchronize(c->stream);
+    for (DevBuf* b : bufs) dev_free(c, *b);
+  }
+};
 eh_status ensure_pinned(Ctx* c, size_t n);
 
 // Work-item construction (host) and the plan cache.
@@ -266,6 +281,12 @@ eh_status launch_gather_items(Ctx* c, hipStream_t s, const Item* src, const uint
                               uint32_t n_pieces, Item* dst);
 eh_status launch_scatter_roots(Ctx* c, hipStream_t s, const unsigned long long* by_rank,
                                const uint32_t* vert, unsigned long long* by_id, uint32_t n);
+// The label sequence (vertices in the order they receive labels) of a
+// traversal ordering (EH_ORDER_BFS, _HYBRID, _STRONG_RUNS) of one graph, from
+// its m deduplicated edges (min << kb | max) and degrees, into seq (n words).
+eh_status device_traversal_sequence(Ctx* c, const unsigned long long* edges, uint64_t m,
+                                    uint32_t kb, uint32_t n, const uint32_t* deg, uint32_t order,
+                                    uint32_t* seq);
 // Sorts a built plan's items (and per-item descriptors) by decreasing
 // estimated cost, for the snake schedule.
 eh_status device_plan_balance(Ctx* c, Trie& t, Plan& plan);
