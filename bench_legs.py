@@ -275,7 +275,14 @@ def bench_served(name, w, args, ctx, eh, torch, metric):
         t_tri = time.perf_counter() - tt
         root_t = rt["root"]
         tt = time.perf_counter()
-        root_k = og.cliques4(threads=threads, rooted=True)["root"]
+        # the rooted 4-clique table in 16 ranges of outer vertices (a progress
+        # line each: the whole table takes minutes at scale 22)
+        root_k = np.zeros(og.n, np.uint64)
+        cuts = np.linspace(0, og.n, 17).astype(np.int64)
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            root_k += og.cliques4(threads=threads, rooted=True, x_begin=int(a), x_end=int(b))["root"]
+            log(f"[bench] oracle 4-clique table: outer ranks < {b} done, "
+                f"{time.perf_counter() - tt:.0f} s")
         t_k4 = time.perf_counter() - tt
         cpu = {"value": og.m / t_tri, "unit": "edges/s", "cores": threads, "kind": "oracle",
                "sample": f"whole graph: rooted triangle table {t_tri:.2f} s, rooted 4-clique table "

@@ -105,8 +105,8 @@ void free_trie_device(Trie& t) {
 eh_status upload_trie(Ctx* c, Trie& t) {
   const HostTrie& h = t.host;
   const uint64_t W = h.n_words;
-  if (h.m + W > kMaxIndex) {
-    c->err = "edges plus bitset words exceed 2^31-1";
+  if (h.m + W > kMaxPosition) {
+    c->err = "edges plus bitset words exceed 2^32-2";
     return EH_EOVERFLOW;
   }
   std::vector<uint2> vd(std::max<uint32_t>(h.n, 1));

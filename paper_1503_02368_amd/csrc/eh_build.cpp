@@ -303,8 +303,8 @@ eh_status build_one(const uint32_t* src, const uint32_t* dst, uint64_t m_raw, ui
       if (!dense) continue;
       const uint32_t base = lo & ~31u;
       const uint32_t nw = ((hi - base) >> 5) + 1;
-      if (words + nw > kMaxIndex) {
-        err = "bitset words exceed 2^31-1";
+      if (h.m + words + nw > kMaxPosition) {
+        err = "edges plus bitset words exceed 2^32-2";
         return EH_EOVERFLOW;
       }
       h.bs_off[u] = uint32_t(words);
@@ -397,8 +397,8 @@ eh_status host_build_batch(uint32_t n_graphs, const uint32_t* n_vertices, const 
     M += parts[g].m;
     W += parts[g].bs_words.size();
   }
-  if (M > kMaxIndex || W > kMaxIndex) {
-    err = "batch exceeds 2^31-1 edges or bitset words";
+  if (M > kMaxIndex || M + W > kMaxPosition) {
+    err = "batch exceeds 2^31-1 edges or 2^32-2 edges plus bitset words";
     return EH_EOVERFLOW;
   }
   const uint32_t N = uint32_t(padded);
@@ -785,7 +785,7 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
     // chains of dependent loads: the staged set's extent per item, and per
     // in-edge u->v the streamed part of N+(u) above v (elements, or bitset
     // words when fewer and v's set will be held as a bitmap).  A record is
-    // 8 bytes, {start | kHiBit for words, length | word offset << 16}: a
+    // 8 bytes, {start, length | word offset << 16 | kHiBit for words}: a
     // length fits 16 bits because degree order bounds out-degrees by
     // sqrt(2m) < 2^16, and words are clipped to the staged bitmap's window
     // (words outside it cannot match), so the offset is in [0, cap).
@@ -923,7 +923,7 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
           const uint32_t u = t->tin[2 * k], e = t->tin[2 * k + 1];
           const uint4 su = src_info[u];  // {row end, word offset, base, words}
           const uint32_t len = su.x - e - 1;
-          uint32_t sb = e + 1, n = len, sm = 0;
+          uint32_t sb = e + 1, n = len, sm = 0, wf = 0;
           if (words_ok && len && su.y != kNoBitset) {
             const uint32_t w0 = (v + 1 - su.z) >> 5;
             const int64_t nw = w0 < su.w ? int64_t(su.w - w0) : 0;
@@ -934,17 +934,18 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
             const int64_t last = std::min<int64_t>(nw, int64_t(cap) - off);
             const int64_t words = last > first ? last - first : 0;
             if (words < int64_t(len)) {
-              sb = (uint32_t(h.m) + su.y + w0 + uint32_t(first)) | kHiBit;
+              sb = uint32_t(h.m) + su.y + w0 + uint32_t(first);
               n = uint32_t(words);
               sm = words ? uint32_t(off + first) : 0u;
+              wf = kHiBit;
             }
           }
-          if (n > 0xFFFFu || sm > 0xFFFFu) {
+          if (n > 0xFFFFu || sm > 0x7FFFu) {
             __atomic_store_n(&wide, true, __ATOMIC_RELAXED);
             continue;
           }
           rec[2 * k] = sb;
-          rec[2 * k + 1] = n | (sm << 16);
+          rec[2 * k + 1] = n | (sm << 16) | wf;
         }
       }
     });

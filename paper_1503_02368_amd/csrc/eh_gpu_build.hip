@@ -614,8 +614,8 @@ eh_status device_build(Ctx* c, const uint32_t* d_src, const uint32_t* d_dst, uin
       (st = download(c, &W, ptr<unsigned long long>(off) + n, 8, "read word count")) != EH_OK ||
       (st = chk(hipStreamSynchronize(s), "build sync")) != EH_OK)
     return st;
-  if (W > kMaxIndex || m + W > kMaxIndex) {
-    c->err = "edges plus bitset words exceed 2^31-1";
+  if (m + W > kMaxPosition) {
+    c->err = "edges plus bitset words exceed 2^32-2";
     return EH_EOVERFLOW;
   }
   const uint64_t n_bs = h_stat[0];

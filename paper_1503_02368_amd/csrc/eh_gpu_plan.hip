@@ -318,9 +318,9 @@ __global__ void __launch_bounds__(kB) k_group_write(TrieView t, const Item* __re
   }
 }
 
-// The host's segment record per in-edge k (target v = col[e]): {start |
-// kHiBit for words, length | word offset << 16}; *wide flags a field beyond
-// 16 bits.
+// The host's segment record per in-edge k (target v = col[e]): {start,
+// length | word offset << 16 | kHiBit for words}; *wide flags a length beyond
+// 16 bits or an offset beyond 15.
 __global__ void __launch_bounds__(kB) k_records(TrieView t, const unsigned long long* __restrict__ key,
                                                 const uint2* __restrict__ tin, uint64_t m,
                                                 const uint8_t* __restrict__ grouped, uint32_t ub,
@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(kB) k_records(TrieView t, const unsigned long 
     const uint32_t u = tin[k].x, e = tin[k].y;
     const uint2 du = t.vdesc[u], dv = t.vdesc[v];
     const uint32_t len = du.x + (du.y & kMaxIndex) - e - 1;
-    uint32_t sb = e + 1, n = len, sm = 0;
+    uint32_t sb = e + 1, n = len, sm = 0, wf = 0;
     const uint32_t lv = dv.y & kMaxIndex;
     if (ub && len && !grouped[v] && (du.y & kHiBit) && lv > 0) {
       const uint32_t lo_al = t.col[dv.x] & ~31u, hi = t.col[dv.x + lv - 1];
@@ -344,17 +344,18 @@ __global__ void __launch_bounds__(kB) k_records(TrieView t, const unsigned long 
         const int64_t last = min(nw, int64_t(cap) - off);
         const int64_t words = last > first ? last - first : 0;
         if (words < int64_t(len)) {
-          sb = (b.x + w0 + uint32_t(first)) | kHiBit;
+          sb = b.x + w0 + uint32_t(first);
           n = uint32_t(words);
           sm = words ? uint32_t(off + first) : 0u;
+          wf = kHiBit;
         }
       }
     }
-    if (n > 0xFFFFu || sm > 0xFFFFu) {
+    if (n > 0xFFFFu || sm > 0x7FFFu) {
       atomicOr(wide, 1u);
       continue;
     }
-    rec[k] = make_uint2(sb, n | (sm << 16));
+    rec[k] = make_uint2(sb, n | (sm << 16) | wf);
   }
 }
 

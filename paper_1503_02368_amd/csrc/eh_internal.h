@@ -21,7 +21,10 @@ namespace eh {
 
 constexpr uint32_t kNoBitset = 0xFFFFFFFFu;
 constexpr uint32_t kHiBit = 0x80000000u;   // vdesc.y: the set also has a bitset
-constexpr uint32_t kMaxIndex = 0x7FFFFFFFu;  // offsets must stay below 2^31
+constexpr uint32_t kMaxIndex = 0x7FFFFFFFu;  // edges (and set sizes) stay below 2^31
+// Positions in a trie's list buffer (members, then bitset words) use all 32
+// bits; 0xFFFFFFFF is the no-bitset sentinel.
+constexpr uint64_t kMaxPosition = 0xFFFFFFFEull;
 constexpr uint32_t kStageWords = 1024;        // LDS words per wave for a staged set
 // Plan staging beside EH_STAGE_SOURCE / EH_STAGE_TARGET, internal: on a
 // symmetric trie, each undirected edge {x, u} (x ranked below u) once, at u:

@@ -458,16 +458,17 @@ __device__ __forceinline__ uint32_t staged_has(const DevArgs& a, const Staged& s
 }
 
 // Segment table of one flat batch: P = prefix of lengths (kSeg+1), and per
-// segment {start in the list buffer (kHiBit: bitset words), word delta},
-// read together as one 64-bit LDS load.
+// segment {start in the list buffer, word delta (kNoWords: not words)}, read
+// together as one 64-bit LDS load.  Starts use all 32 bits.
 struct SegTab {
   uint32_t* P;
   uint2* S;
 };
 
-// One streamed segment: start in the list buffer (col, then bitset words;
-// kHiBit marks words), length,
-// and for bitset words the offset of its first word from the staged bitmap's.
+// One streamed segment: start in the list buffer (col, then bitset words),
+// length, and for bitset words the offset of its first word from the staged
+// bitmap's (kNoWords for members).
+constexpr int32_t kNoWords = INT32_MIN;
 struct Seg {
   uint32_t sb, len;
   int32_t sm;
@@ -500,11 +501,11 @@ __device__ __forceinline__ Seg seg_full(const DevArgs& a, uint32_t t, const Word
   uint4 bd{0, 0, 0, 0};
   if (kEager && wr.ok) bd = a.bsdesc[t];  // wr.ok implies a bitset table
   const uint32_t tl = td.y & kMaxIndex;
-  Seg g{td.x, tl, 0};
+  Seg g{td.x, tl, kNoWords};
   if (wr.ok && (td.y & kHiBit)) {
     if (!kEager) bd = a.bsdesc[t];
     if (bd.z < tl && bd.y >= wr.wmin) {
-      g.sb = bd.x | kHiBit;
+      g.sb = bd.x;
       g.len = bd.z;
       g.sm = int32_t(bd.y >> 5) - int32_t(wr.base >> 5);
     }
@@ -538,10 +539,9 @@ struct SegCursor {
     j = 0;
     nxt = T.P[1];
     const uint2 sg = T.S[0];
-    const uint32_t sb = sg.x;
-    base = sb & kMaxIndex;
+    base = sg.x;
     wbase = sg.y;
-    bits = (sb & kHiBit) != 0;
+    bits = !kRaw && sg.y != uint32_t(kNoWords);
   }
   __device__ __forceinline__ void seek(const SegTab& T, uint32_t f) {
     while (nxt <= f) {
@@ -549,10 +549,9 @@ struct SegCursor {
       ++j;
       nxt = T.P[j + 1];
       const uint2 sg = T.S[j];
-      const uint32_t sb = sg.x;
-      base = (sb & kMaxIndex) - start;
+      base = sg.x - start;
       wbase = kRaw ? sg.y : sg.y - start;
-      bits = (sb & kHiBit) != 0;
+      bits = !kRaw && sg.y != uint32_t(kNoWords);
     }
   }
   // Places the cursor on the segment of f by a branch-free binary search of
@@ -571,10 +570,9 @@ struct SegCursor {
     j = p;
     nxt = T.P[p + 1];
     const uint2 sg = T.S[p];
-    const uint32_t sb = sg.x;
-    base = (sb & kMaxIndex) - start;
+    base = sg.x - start;
     wbase = kRaw ? sg.y : sg.y - start;
-    bits = (sb & kHiBit) != 0;
+    bits = !kRaw && sg.y != uint32_t(kNoWords);
   }
 };
 
@@ -749,7 +747,7 @@ __device__ __forceinline__ uint32_t grouped_item(const DevArgs& a, const SegTab&
   const uint32_t p2 = p1 + __builtin_amdgcn_readlane(gs.w, 1);
   const uint32_t p3 = p2 + __builtin_amdgcn_readlane(gs.w, 2);
   // records: lane r holds record r - q_k of item k
-  Seg g{0, 0, 0};
+  Seg g{0, 0, 0};  // kRaw: sm is the item index
   if (lane < nrec) {
     const uint32_t k = uint32_t(lane >= q1) + uint32_t(lane >= q2) + uint32_t(lane >= q3);
     const uint32_t qk = k == 0 ? 0u : k == 1 ? q1 : k == 2 ? q2 : q3;
@@ -838,12 +836,12 @@ __device__ __forceinline__ void tri_staged(const DevArgs& a) {
     uint32_t cnt = 0;
     for (uint32_t b0 = 0; b0 < llen; b0 += kSeg) {
       const uint32_t nseg = min(uint32_t(kSeg), llen - b0);
-      Seg g{0, 0, 0};
+      Seg g{0, 0, kNoWords};
       if (lane < nseg) {
         if (a.rec) {
           // resolved at plan time: one load per streamed set
           const uint2 r = b0 == 0 ? r0 : a.rec[lbeg + b0 + lane];
-          g = Seg{r.x, r.y & 0xFFFFu, int32_t(r.y >> 16)};
+          g = Seg{r.x, r.y & 0xFFFFu, (r.y & kHiBit) ? int32_t((r.y >> 16) & 0x7FFFu) : kNoWords};
         } else {
           g = seg_full(a, a.idx[lbeg + b0 + lane], wr);
         }
@@ -982,7 +980,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
         const WordRule wr = word_rule(a, ss);
         for (uint32_t b0 = 0; b0 < ns; b0 += kSeg) {
           const uint32_t nseg = min(uint32_t(kSeg), ns - b0);
-          Seg g{0, 0, 0};
+          Seg g{0, 0, kNoWords};
           if (lane < nseg) g = seg_full<true>(a, S[b0 + lane], wr);
           const uint32_t E = publish_segments(T, g, lane);
           // bitmap bounds are B's (RW words); the list S is searched by length

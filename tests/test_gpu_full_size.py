@@ -94,7 +94,6 @@ def test_full_size_batch_20000_graphs(ctx, eh):
     src = torch.from_numpy(b.src.view(np.int32)).cuda()
     dst = torch.from_numpy(b.dst.view(np.int32)).cuda()
     trie = ctx.build_batch_device(b, src, dst, layout=t["layout"], tau=t["tau"], s_min=t.get("s_min", 1))
-    del src, dst
     try:
         G = trie.info["n_graphs"]
         assert G == 20000
@@ -108,6 +107,23 @@ def test_full_size_batch_20000_graphs(ctx, eh):
         # the blocking call on a slice of the batch
         got2 = ctx.count_batch(trie, eh.TRIANGLE, 1234, 777)
         assert np.array_equal(np.asarray(got2, np.uint64), want[1234:2011])
+    finally:
+        trie.free()
+    # the set optimizer at tau = 1024: edges plus bitset words pass 2^31
+    # (list-buffer positions use all 32 bits)
+    trie = ctx.build_batch_device(b, src, dst, layout=1, tau=1024.0)
+    del src, dst
+    try:
+        info = trie.info
+        say(f"tau 1024: {info['m_plus']} edges + {info['bitset_words']} words")
+        assert info["m_plus"] + info["bitset_words"] > 2**31
+        out = torch.zeros(info["n_graphs"], dtype=torch.int64, device="cuda")
+        ctx.stream.wait_stream(torch.cuda.current_stream())
+        ctx.count_batch_async(trie, eh.TRIANGLE, 0, info["n_graphs"], out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().view(np.uint64)
+        bad = np.flatnonzero(got != want)
+        assert bad.size == 0, f"tau 1024: {bad.size} graphs differ, first {bad[:5].tolist()}"
     finally:
         trie.free()
 
