@@ -176,15 +176,16 @@ class Graph:
         cv = np.zeros(self.n, np.uint64) if per_vertex else None
         b = ctypes.c_uint64(0)
         e = ctypes.c_uint64(0)
-        h = ctypes.c_uint64(0)
+        h = (ctypes.c_uint64 * 2)()
         xe = self.n if x_end is None else int(x_end)
-        extra = (ctypes.byref(h),) if held else ()
+        extra = (h,) if held else ()
         total = fn(self._h, int(x_begin), xe, int(threads), _p64(root), _p64(cv), ctypes.byref(b),
                    ctypes.byref(e), *extra)
         out = {"count": int(total), "root": root, "per_vertex": cv, "bytes": int(b.value),
                "edges": int(e.value)}
         if held:
-            out["held_bytes"] = int(h.value)
+            out["held_bytes"] = int(h[0])
+            out["held_tests"] = int(h[1])
         return out
 
     def triangles(self, threads: int = 0, rooted: bool = False, per_vertex: bool = False,
@@ -198,7 +199,8 @@ class Graph:
     def cliques4(self, threads: int = 0, rooted: bool = False, per_vertex: bool = False,
                  x_begin: int = 0, x_end: int | None = None) -> dict:
         """K; ``bytes`` is B_K4 over the visited oriented edges, ``held_bytes``
-        B_K4_held (the reads when N+(x) and S_xy are held on chip)."""
+        B_K4_held (the reads when N+(x) and S_xy are held on chip) and
+        ``held_tests`` its element tests (the streamed members)."""
         return self._run(self._lib.orc_4cliques_range, threads, rooted, per_vertex, x_begin, x_end,
                          held=True)
 

@@ -51,6 +51,8 @@
  *     members (a 4-clique needs two more vertices in each); per extended
  *     pair 4 (the id y) + 8 (its set's extent) + 4 |N+(y)|; when |S_xy| >= 2,
  *     per z in S_xy 8 + 4 |N+(z)|; per x with an extended pair 16 + 4 |N+(x)|.
+ *     Its element tests are the streamed members: |N+(y)| per extended pair
+ *     and |N+(z)| per such z (orc_4cliques_range returns bytes and tests).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -306,15 +308,15 @@ uint64_t orc_triangles(const orc_graph* g, int threads, uint64_t* root_by_id, ui
 /* 4-cliques over outer vertices x in [x_begin, x_end); same optional outputs */
 uint64_t orc_4cliques_range(const orc_graph* g, uint32_t x_begin, uint32_t x_end, int threads,
                             uint64_t* root_by_id, uint64_t* c4_by_id, uint64_t* bytes,
-                            uint64_t* edges, uint64_t* held_bytes) {
+                            uint64_t* edges, uint64_t* held) {
   set_threads(threads);
-  uint64_t total = 0, b = 0, e = 0, hb = 0;
+  uint64_t total = 0, b = 0, e = 0, hb = 0, ht = 0;
   if (x_end > g->n) x_end = g->n;
   const int64_t xb = x_begin, xe = x_end;
   uint64_t dmax = 0;
   for (uint32_t r = 0; r < g->n; ++r)
     if (g->off[r + 1] - g->off[r] > dmax) dmax = g->off[r + 1] - g->off[r];
-#pragma omp parallel reduction(+ : total, b, e, hb)
+#pragma omp parallel reduction(+ : total, b, e, hb, ht)
   {
     uint32_t* s = (uint32_t*)malloc((dmax ? dmax : 1) * sizeof(uint32_t));
     uint32_t* t = (uint32_t*)malloc((dmax ? dmax : 1) * sizeof(uint32_t));
@@ -334,6 +336,7 @@ uint64_t orc_4cliques_range(const orc_graph* g, uint32_t x_begin, uint32_t x_end
         if (ext) {
           extended = 1;
           hb += 4 + 8 + 4 * dy;
+          ht += dy;
         }
         uint64_t kxy = 0;
         for (uint64_t j = 0; j < ns; ++j) {
@@ -341,7 +344,10 @@ uint64_t orc_4cliques_range(const orc_graph* g, uint32_t x_begin, uint32_t x_end
           const uint32_t* nz = g->nbr + g->off[z];
           const uint64_t dz = g->off[z + 1] - g->off[z];
           b += 4 * (ns + dz);
-          if (ext && ns >= 2) hb += 8 + 4 * dz;
+          if (ext && ns >= 2) {
+            hb += 8 + 4 * dz;
+            ht += dz;
+          }
           if (c4_by_id) {
             const uint64_t c = merge_list(s, ns, nz, dz, t);   /* w in S & N+(z) */
             for (uint64_t q = 0; q < c; ++q) add_u64(&c4_by_id[g->vert[t[q]]], 1);
@@ -367,7 +373,10 @@ uint64_t orc_4cliques_range(const orc_graph* g, uint32_t x_begin, uint32_t x_end
   }
   if (bytes) *bytes = b;
   if (edges) *edges = e;
-  if (held_bytes) *held_bytes = hb;
+  if (held) {
+    held[0] = hb;
+    held[1] = ht;
+  }
   return total;
 }
 

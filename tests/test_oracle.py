@@ -142,6 +142,9 @@ def test_complete_byte_models(n):
     assert k["bytes"] == 2 * n * (n - 1) ** 2 + (3 * n - 5) * math.comb(n, 3)
     want_held = 4 * math.comb(n + 3, 4) + 2 * n * (n - 1) - 24 * n if n >= 3 else 0
     assert k["held_bytes"] == want_held
+    # its element tests: y extended pairs end at y, each testing k = n-1-y
+    # members of N+(y) and, for z in S_xy = {y+1, ..., n-1}, k(k-1)/2 more
+    assert k["held_tests"] == sum(y * math.comb(n - y, 2) for y in range(1, n - 2))
     r = g.target_reads()
     if n >= 2:
         assert r["held_sets"] == n - 2
@@ -167,7 +170,7 @@ def brute_bytes(el):
     d = {v: len(up[v]) for v in range(n)}
     b_merge = sum(4 * (d[x] + d[y]) for x in range(n) for y in up[x])
     b_k4 = b_merge
-    held = 0
+    held = tests = 0
     extended_roots = set()
     for x in range(n):
         for y in up[x]:
@@ -177,10 +180,12 @@ def brute_bytes(el):
             if ext:
                 extended_roots.add(x)
                 held += 12 + 4 * d[y]
+                tests += d[y]
             for z in s:                     # triangle x < y < z in rank order
                 b_k4 += 4 * (len(s) + d[z])
                 if ext and len(s) >= 2:
                     held += 8 + 4 * d[z]
+                    tests += d[z]
     held += sum(16 + 4 * d[x] for x in extended_roots)
     # target staging: y held when some x -> y exists and N+(y) is not empty
     tgt = 0
@@ -190,7 +195,7 @@ def brute_bytes(el):
             tgt += 32 + 4 * d[y]
             for x in ins:
                 tgt += 8 + 4 * sum(1 for w in up[x] if rk[w] > rk[y])
-    return b_merge, b_k4, held, tgt
+    return b_merge, b_k4, held, tgt, tests
 
 
 @pytest.mark.parametrize("n,p,seed", [(n, p, s) for n in (7, 13, 22, 30)
@@ -198,10 +203,10 @@ def brute_bytes(el):
 def test_byte_models_brute_force(n, p, seed):
     el = inputs.gnp(n, p, seed)
     g = oracle.Graph.from_edgelist(el)
-    b_merge, b_k4, held, tgt = brute_bytes(el)
+    b_merge, b_k4, held, tgt, tests = brute_bytes(el)
     assert g.triangles()["bytes"] == b_merge
     k = g.cliques4()
-    assert (k["bytes"], k["held_bytes"]) == (b_k4, held)
+    assert (k["bytes"], k["held_bytes"], k["held_tests"]) == (b_k4, held, tests)
     assert g.target_reads()["bytes"] == tgt
 
 
@@ -211,7 +216,7 @@ def test_byte_models_messy_and_sparse(seed):
     el = inputs.messy(inputs.disjoint_union(inputs.gnp(18, 0.3, seed), inputs.star(6),
                                             inputs.path(5)), seed)
     g = oracle.Graph.from_edgelist(el)
-    b_merge, b_k4, held, tgt = brute_bytes(el)
+    b_merge, b_k4, held, tgt, _ = brute_bytes(el)
     k = g.cliques4()
     assert (g.triangles()["bytes"], k["bytes"], k["held_bytes"]) == (b_merge, b_k4, held)
     assert g.target_reads()["bytes"] == tgt
