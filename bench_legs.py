@@ -611,7 +611,7 @@ def bench_unpruned(name, w, args, ctx, eh, torch, metric):
                                   "m_plus": info["m_plus"], "b_merge": info["b_merge"],
                                   "max_degree": info["max_out_degree"]}
     rows["lollipop"] = {"ms": 1e3 * statistics.median(lol), "count": lcount,
-                        "includes": "per-root triangle launch, degree-weighted sum, read-back"}
+                        "includes": "one edge-once launch weighted by degree, read-back"}
     log(f"[bench] Lollipop {rows['lollipop']['ms']:.3f} ms, count {lcount}")
     # the same ordered-triangle count as one pairwise intersection per arc over a
     # set store: a hub's set is met by probing its bitset with the smaller set

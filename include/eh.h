@@ -301,9 +301,13 @@ eh_status eh_count_4cliques(eh_ctx* ctx, const eh_trie* trie, uint64_t* total);
  *   Lollipop(x,y,z,w) :- R(x,y), S(y,z), T(x,z), U(x,w),
  * evaluated as one Generic-Join over a symmetric trie (the paper runs it on
  * undirected data): for every x, the ordered triangles (x, y, z) times the
- * number of w adjacent to x, i.e. sum over x of t(x) deg(x).  EH_ESTATE on a
- * pruned trie or a batch.  Allocates n uint64 of device scratch per call.
- * Results above 2^64 - 1 wrap. */
+ * number of w adjacent to x, i.e. sum over x of t(x) deg(x).  Unless the
+ * tuning asks for source staging it is counted over each undirected edge
+ * {x, u} once, as |N(x) & N(u)| (deg(x) + deg(u)) summed in one launch of the
+ * staged kernel (the edge-once plan of the symmetric triangle total); under
+ * source staging t(x) is counted by first attribute over every arc and then
+ * weighted, which allocates n uint64 of device scratch per call.  EH_ESTATE
+ * on a pruned trie or a batch.  Results above 2^64 - 1 wrap. */
 eh_status eh_count_lollipop(eh_ctx* ctx, const eh_trie* trie, uint64_t* total);
 /* Enqueue-only forms: the total is written to d_total (one uint64, device)
  * when the stream reaches it.  pattern: EH_TRIANGLE or EH_4CLIQUE. */

@@ -163,9 +163,10 @@ LaunchArgs base_args(Ctx* c, const Trie& t) {
 
 // Enqueues one counting launch over items [i0, i1) of a plan.  cursor: the
 // work cursors to use instead of the context's (null: the context's).
+// lollipop: the Lollipop launch over an edge-once plan instead of triangles.
 eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
                         unsigned long long* acc, uint32_t tag_base, unsigned long long* per_root,
-                        uint32_t* cursor = nullptr) {
+                        uint32_t* cursor = nullptr, bool lollipop = false) {
   LaunchArgs a = base_args(c, t);
   if (cursor) a.cursor = cursor;
   a.items = static_cast<const Item*>(p->items.p) + i0;
@@ -185,6 +186,7 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
   a.k4s_waves = p->k4s_waves;
   if (p->pattern == EH_4CLIQUE)
     return launch_4cliques(c, c->stream, a, c->tune.kernel, c->tune.waves_per_cu);
+  if (lollipop) return launch_lollipop(c, c->stream, a, c->tune.waves_per_cu);
   return launch_triangles(c, c->stream, a, c->tune.kernel, c->tune.waves_per_cu);
 }
 
@@ -687,11 +689,22 @@ eh_status eh_count_lollipop(eh_ctx* ctx, const eh_trie* trie, uint64_t* total) {
   }
   eh_status st = hip_check(c, hipSetDevice(c->device), "hipSetDevice");
   if (st != EH_OK) return st;
+  auto* acc = static_cast<unsigned long long*>(c->acc.p);
+  if (c->tune.staging != EH_STAGE_SOURCE) {
+    // each undirected edge {x, u} once, weighted by |N(x)| + |N(u)|
+    Plan* p = nullptr;
+    if ((st = get_plan(c, &t, EH_TRIANGLE, kStageHalf, &p)) != EH_OK) return st;
+    if ((st = launch_fill_u64(c, c->stream, acc + 1, 1, 0)) != EH_OK) return st;
+    if ((st = enqueue_count(c, t, p, 0, p->n_items, acc + 1, 0, nullptr, nullptr, true)) != EH_OK)
+      return st;
+    return read_back(c, acc + 1, total, 1);
+  }
+  // source staging: t(x) by first attribute over every arc, then the
+  // degree-weighted sum
   DevBuf per;  // t(x) by original id
   if ((st = dev_alloc(c, per, sizeof(unsigned long long) * std::max<uint32_t>(t.host.n, 1))) !=
       EH_OK)
     return st;
-  auto* acc = static_cast<unsigned long long*>(c->acc.p);
   st = count_single(c, t, EH_TRIANGLE, acc, static_cast<unsigned long long*>(per.p));
   if (st == EH_OK) st = launch_fill_u64(c, c->stream, acc + 1, 1, 0);
   if (st == EH_OK)

@@ -279,6 +279,9 @@ eh_status launch_triangles(Ctx* c, hipStream_t s, const LaunchArgs& a, uint32_t 
                            uint32_t waves_per_cu);
 eh_status launch_4cliques(Ctx* c, hipStream_t s, const LaunchArgs& a, uint32_t kernel,
                           uint32_t waves_per_cu);
+// Lollipop COUNT over a symmetric trie's edge-once (kStageHalf) plan: adds
+// sum over undirected edges {x, u} of |N(x) & N(u)| (|N(x)| + |N(u)|) to a.acc.
+eh_status launch_lollipop(Ctx* c, hipStream_t s, const LaunchArgs& a, uint32_t waves_per_cu);
 // dst[piece.y + k] = src[piece.x + k] for k < piece.z, for every piece.
 eh_status launch_gather_items(Ctx* c, hipStream_t s, const Item* src, const uint4* pieces,
                               uint32_t n_pieces, Item* dst);

@@ -717,6 +717,51 @@ __device__ __forceinline__ uint32_t flat_probe(const DevArgs& a, const SegTab& T
   return cnt;
 }
 
+// The Lollipop count's walk: as flat_probe_bits over a bitmap or composite
+// staged set, and each element found also adds the weight W[j] of its
+// segment j (the degree of the streamed set's vertex) to wsum.
+template <int RW, int U>
+__device__ __forceinline__ uint32_t flat_probe_weighted(const DevArgs& a, const SegTab& T,
+                                                        const uint32_t* W, uint32_t E,
+                                                        const Staged& st, const uint32_t* R,
+                                                        const uint32_t* Lp, uint32_t lane,
+                                                        unsigned long long& wsum) {
+  const uint32_t* __restrict__ L = a.col;
+  const bool comp = st.mode == kModeComposite;
+  uint32_t cnt = 0;
+  SegCursor<false> c(T);
+  for (uint32_t f0 = 0; f0 < E; f0 += kWave * U) {
+    uint32_t val[U], key[U], wt[U];
+    bool ok[U], bits[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t f = f0 + uint32_t(u) * kWave + lane;
+      ok[u] = f < E;
+      val[u] = key[u] = wt[u] = 0;
+      bits[u] = false;
+      if (ok[u]) {
+        c.seek(T, f);
+        val[u] = L[c.base + f];
+        key[u] = c.wbase + f;
+        bits[u] = c.bits;
+        wt[u] = W[c.j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t d = val[u] - st.base;
+      const uint32_t w = bits[u] ? key[u] : (d >> 5);
+      const uint32_t m = bits[u] ? val[u] : (1u << (d & 31));
+      uint32_t h = 0;
+      if (ok[u] && w < uint32_t(RW)) h = __popc(R[w] & m);
+      else if (comp && ok[u] && !bits[u]) h = prefix_has(a, st, Lp, val[u]);
+      cnt += h;
+      wsum += static_cast<unsigned long long>(h) * wt[u];
+    }
+  }
+  return cnt;
+}
+
 // ---------------------------------------------------------------------------
 // Triangles, staged: a group of K small items in one pass
 // ---------------------------------------------------------------------------
@@ -785,12 +830,17 @@ __device__ __forceinline__ uint32_t grouped_item(const DevArgs& a, const SegTab&
 // Triangles, staged
 // ---------------------------------------------------------------------------
 
-template <int WPB, int RW, int U>
+// kLollipop: the symmetric relation's Lollipop count over each undirected
+// edge once (kStageHalf plans, no grouped items): an edge {x, u} with c common
+// neighbours adds c (|N(x)| + |N(u)|) -- u's part per item, x's per element
+// found, weighted by its segment's degree.
+template <int WPB, int RW, int U, bool kLollipop = false>
 __device__ __forceinline__ void tri_staged(const DevArgs& a) {
   __shared__ uint32_t s_region[WPB][RW];
   __shared__ uint32_t s_pre[WPB][kSeg + 1];
   __shared__ uint2 s_seg[WPB][kSeg];
   __shared__ uint32_t s_pref[WPB][kPrefixCap];
+  __shared__ uint32_t s_wt[kLollipop ? WPB : 1][kLollipop ? kSeg : 1];
   const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
   uint32_t* R = s_region[wid];
   uint32_t* Lp = s_pref[wid];
@@ -837,19 +887,30 @@ __device__ __forceinline__ void tri_staged(const DevArgs& a) {
     for (uint32_t b0 = 0; b0 < llen; b0 += kSeg) {
       const uint32_t nseg = min(uint32_t(kSeg), llen - b0);
       Seg g{0, 0, kNoWords};
+      uint32_t wt = 0;
       if (lane < nseg) {
         if (a.rec) {
           // resolved at plan time: one load per streamed set
           const uint2 r = b0 == 0 ? r0 : a.rec[lbeg + b0 + lane];
           g = Seg{r.x, r.y & 0xFFFFu, (r.y & kHiBit) ? int32_t((r.y >> 16) & 0x7FFFu) : kNoWords};
         } else {
-          g = seg_full(a, a.idx[lbeg + b0 + lane], wr);
+          const uint32_t t = a.idx[lbeg + b0 + lane];
+          g = seg_full(a, t, wr);
+          if (kLollipop) wt = a.vdesc[t].y & kMaxIndex;
         }
       }
       const uint32_t E = publish_segments(T, g, lane);
-      cnt += flat_probe<RW, U>(a, T, E, nseg, st, R, Lp, lane);
+      if constexpr (kLollipop) {
+        // the previous batch's readers finished before publish_segments
+        s_wt[wid][lane] = wt;
+        wave_sync();
+        cnt += flat_probe_weighted<RW, U>(a, T, s_wt[wid], E, st, R, Lp, lane, acc);
+      } else {
+        cnt += flat_probe<RW, U>(a, T, E, nseg, st, R, Lp, lane);
+      }
     }
-    acc += cnt;
+    if constexpr (kLollipop) acc += static_cast<unsigned long long>(cnt) * st.len;
+    else acc += cnt;
     if (a.per_root) {
       const unsigned long long tot = wave_sum((unsigned long long)cnt);
       if (lane == 0 && tot) atomicAdd(&a.per_root[a.vert[s]], tot);
@@ -873,6 +934,12 @@ template <int WPB, int RW, int U>
 __global__ __launch_bounds__(WPB * kWave) __attribute__((amdgpu_waves_per_eu(8)))
 void k_tri_staged_lean(DevArgs a) {
   tri_staged<WPB, RW, U>(a);
+}
+
+template <int WPB, int RW, int U>
+__global__ __launch_bounds__(WPB * kWave) __attribute__((amdgpu_waves_per_eu(6)))
+void k_lollipop_staged(DevArgs a) {
+  tri_staged<WPB, RW, U, true>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1225,6 +1292,19 @@ eh_status launch_triangles(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t
     hipLaunchKernelGGL((k_tri_staged<kTriWPB, kTriRW, kTriU>), dim3(grid), dim3(kTriWPB * kWave), 0,
                        s, a);
   return hip_check(c, hipGetLastError(), "staged triangle kernel launch");
+}
+
+eh_status launch_lollipop(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t waves_per_cu) {
+  if (la.n_items == 0) return EH_OK;
+  if (la.rec || la.gsub || la.sdesc || !la.symmetric) {
+    c->err = "the Lollipop launch takes a symmetric trie's edge-once plan";
+    return EH_EINVAL;
+  }
+  if (eh_status st = reset_cursors(c, s, la); st != EH_OK) return st;
+  const uint32_t grid = grid_for(c, la.n_items, kTriWPB, waves_per_cu);
+  hipLaunchKernelGGL((k_lollipop_staged<kTriWPB, kTriRW, 4>), dim3(grid),
+                     dim3(kTriWPB * kWave), 0, s, to_dev(la));
+  return hip_check(c, hipGetLastError(), "Lollipop kernel launch");
 }
 
 eh_status launch_4cliques(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t /*kernel*/,

@@ -903,6 +903,29 @@ def test_symmetric_hub_of_100k(ctx, eh):
         trie.free()
 
 
+@pytest.mark.parametrize("tname", ["staged_target", "staged_nobits", "staged_list", "staged_lean",
+                                   "staged_part", "staged_snake"])
+def test_lollipop_edge_once(ctx, eh, tname):
+    """The Lollipop count over each undirected edge {x, u} once, weighted by
+    |N(x)| + |N(u)|, equals the oracle's and the every-arc evaluation (source
+    staging: t(x) by first attribute, then degree-weighted): staged sets as
+    bitmaps, composites with searched prefixes (8-word windows), with and
+    without streamed bitset words, under four schedules."""
+    graphs = SYM_GRAPHS + [inputs.rmat(14, 16, seed=141)]
+    for el in graphs:
+        lolli = sym_truth(el)[3]
+        say("lollipop edge once", tname, el.name)
+        trie = ctx.build_edgelist(el, symmetric=True)
+        try:
+            tune(ctx, **TUNINGS[tname])
+            assert ctx.count_lollipop(trie) == lolli, el.name
+            assert ctx.count_lollipop(trie) == lolli, el.name   # cached plan
+            tune(ctx, **dict(TUNINGS[tname], staging=eh.STAGE_SOURCE))
+            assert ctx.count_lollipop(trie) == lolli, el.name
+        finally:
+            trie.free()
+
+
 def test_symmetric_batch_and_device_build(ctx, eh):
     tune(ctx, **TUNINGS["staged_steal"])
     b = small_batch(60, seed=17)
