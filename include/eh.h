@@ -86,7 +86,7 @@ const char* eh_last_error(const eh_ctx* ctx);
 const char* eh_status_str(eh_status s);
 /* Version of this ABI (major * 10000 + minor * 100 + patch); a caller built
  * against this header checks that the library returns EH_ABI_VERSION. */
-#define EH_ABI_VERSION 10900
+#define EH_ABI_VERSION 11000
 int32_t eh_abi_version(void);
 
 /* ---- tuning knobs (performance only; counts never depend on them) ------- */
@@ -143,6 +143,11 @@ typedef struct eh_tuning {
                             schedule).  Items follow the held vertex's rank, and under degree
                             order the highest ranks hold the heaviest sets, so they start
                             first instead of forming the launch's tail */
+  uint32_t k4_local;     /* 4-cliques on a pruned single-graph trie: 1 counts each root u with
+                            3 <= d+(u) <= 512 over its induced out-neighbourhood (rows
+                            N+(v) & N+(u) as bitsets over local ids in LDS, the third level
+                            as word ANDs); the other roots, and every root when 0, go to the
+                            staged S-list kernel.  A context starts with 1 */
 } eh_tuning;
 
 eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t);

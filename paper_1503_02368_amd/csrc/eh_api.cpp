@@ -184,8 +184,15 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
   a.k4s = static_cast<uint32_t*>(p->k4s.p);
   a.k4s_stride = p->k4s_stride;
   a.k4s_waves = p->k4s_waves;
-  if (p->pattern == EH_4CLIQUE)
+  if (p->pattern == EH_4CLIQUE) {
+    if (p->k4l.p) {
+      // single-graph plans only: the whole range of items and every root
+      LaunchArgs la = a;
+      la.roots = static_cast<const uint32_t*>(p->k4l.p);
+      if (eh_status st = launch_4cliques_local(c, c->stream, la, p->k4l_n); st != EH_OK) return st;
+    }
     return launch_4cliques(c, c->stream, a, c->tune.kernel, c->tune.waves_per_cu);
+  }
   if (lollipop) return launch_lollipop(c, c->stream, a, c->tune.waves_per_cu);
   return launch_triangles(c, c->stream, a, c->tune.kernel, c->tune.waves_per_cu);
 }
@@ -394,6 +401,11 @@ eh_status eh_ctx_set_tuning(eh_ctx* ctx, const eh_tuning* t) {
     return EH_EINVAL;
   }
   u.reverse = t->reverse;
+  if (t->k4_local > 1) {
+    ctx->c.err = "k4_local must be 0 or 1";
+    return EH_EINVAL;
+  }
+  u.k4_local = t->k4_local;
   return EH_OK;
 }
 
@@ -416,6 +428,7 @@ eh_status eh_ctx_get_tuning(const eh_ctx* ctx, eh_tuning* out) {
   out->search_below = u.search_below;
   out->group = u.group;
   out->reverse = u.reverse;
+  out->k4_local = u.k4_local;
   return EH_OK;
 }
 

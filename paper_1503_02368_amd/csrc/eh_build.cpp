@@ -641,6 +641,17 @@ static void free_plan(Ctx* c, Plan& p) {
   dev_free(c, p.rec);
   dev_free(c, p.gsub);
   dev_free(c, p.k4s);
+  dev_free(c, p.k4l);
+}
+
+// 4-cliques on a pruned single graph: roots that fit the induced-neighbourhood
+// kernel are counted there (tuning k4_local).
+static bool wants_k4_local(const Tuning& tu, const HostTrie& h, uint32_t pattern) {
+  return pattern == EH_4CLIQUE && tu.k4_local && h.n_graphs == 1 && !h.symmetric;
+}
+
+static int local_class(const HostTrie& h, uint32_t u) {
+  return k4_local_class(h.row[u + 1] - h.row[u]);
 }
 
 static bool wants_balance(const Tuning& tu, const HostTrie& h) {
@@ -656,7 +667,8 @@ Plan* find_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging) {
   for (auto& p : t->plans)
     if (p->pattern == pattern && p->staging == staging && p->chunk_work == chunk &&
         p->use_bitsets == tu.use_bitsets && p->stage_words == tu.stage_words &&
-        p->group == group && p->balanced == balanced)
+        p->group == group && p->balanced == balanced &&
+        p->k4_local == wants_k4_local(tu, t->host, pattern))
       return p.get();
   return nullptr;
 }
@@ -679,6 +691,7 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
   plan->stage_words = tu.stage_words;
   plan->group = (staging == EH_STAGE_TARGET && pattern == EH_TRIANGLE) ? tu.group : 1u;
   plan->g_item_off.assign(size_t(h.n_graphs) + 1, 0);
+  plan->k4_local = wants_k4_local(tu, h, pattern);
   const bool ub = tu.use_bitsets != 0;
   // Target-staged triangle plans are built on the GPU, except grouped plans
   // of a few large graphs (grouping walks each graph's items in one thread
@@ -760,7 +773,7 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
                       out);
         } else if (staging == kStageHalf) {
           make_items_half(h, v, tag, chunk, ub, out);
-        } else {
+        } else if (!plan->k4_local || local_class(h, v) < 0) {
           make_items_source(h, v, tag, chunk, pattern, ub, out);
         }
       }
@@ -985,6 +998,33 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
       dev_free(c, plan->k4s);
       return st;
     }
+  if (plan->k4_local) {
+    // the roots the items left out, by out-degree class, each class by
+    // decreasing estimated cost (members streamed at the first level plus
+    // the square of the out-degree for the pairs of the second)
+    std::vector<std::pair<uint64_t, uint32_t>> cls[kK4LocalClasses];
+    for (uint32_t u = 0; u < h.n; ++u) {
+      const int k = local_class(h, u);
+      if (k < 0) continue;
+      uint64_t cost = uint64_t(out_deg(h, u)) * out_deg(h, u);
+      for (uint32_t e = h.row[u]; e < h.row[u + 1]; ++e) cost += out_deg(h, h.col[e]);
+      cls[k].emplace_back(cost, u);
+    }
+    std::vector<uint32_t> roots;
+    for (uint32_t k = 0; k < kK4LocalClasses; ++k) {
+      std::stable_sort(cls[k].begin(), cls[k].end(),
+                       [](const auto& x, const auto& y) { return x.first > y.first; });
+      for (const auto& e : cls[k]) roots.push_back(e.second);
+      plan->k4l_n[k] = cls[k].size();
+    }
+    if (!roots.empty() &&
+        ((st = dev_alloc(c, plan->k4l, sizeof(uint32_t) * roots.size())) != EH_OK ||
+         (st = hip_check(c, hipMemcpy(plan->k4l.p, roots.data(), sizeof(uint32_t) * roots.size(),
+                                      hipMemcpyHostToDevice), "upload 4-clique roots")) != EH_OK)) {
+      free_plan(c, *plan);
+      return st;
+    }
+  }
   if (wants_balance(tu, h)) {
     plan->balanced = true;
     if ((st = device_plan_balance(c, *t, *plan)) != EH_OK) {

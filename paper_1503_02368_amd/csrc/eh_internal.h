@@ -125,6 +125,7 @@ struct Tuning {
   uint32_t search_below = 24;
   uint32_t group = 1;
   uint32_t reverse = 0;
+  uint32_t k4_local = 1;
 };
 
 struct Ctx;
@@ -164,6 +165,12 @@ struct Plan {
   DevBuf k4s;
   uint32_t k4s_waves = 0;
   uint32_t k4s_stride = 0;
+  // 4-cliques over induced neighbourhoods: roots counted by k_k4_local
+  // (absent from items), out-degree classes (<= 64, <= 128, <= 256, <= 512)
+  // stored one after another, each by decreasing estimated cost
+  bool k4_local = false;
+  DevBuf k4l;
+  uint64_t k4l_n[4] = {0, 0, 0, 0};
 };
 
 struct Trie {
@@ -272,6 +279,8 @@ struct LaunchArgs {
   uint32_t* k4s = nullptr;             // 4-cliques: per-wave S lists in HBM for roots
   uint32_t k4s_stride = 0;             //   of out-degree > kK4ListMax, or null
   uint32_t k4s_waves = 0;
+  const uint32_t* roots = nullptr;     // 4-cliques over induced neighbourhoods
+  uint64_t n_roots = 0;
 };
 eh_status launch_fill_u64(Ctx* c, hipStream_t s, unsigned long long* p, uint64_t n,
                           unsigned long long v);
@@ -311,6 +320,20 @@ eh_status launch_degree_weighted_sum(Ctx* c, hipStream_t s, const unsigned long 
 // Largest out-degree whose 4-clique S list the kernel holds in LDS; beyond it
 // the lists live in HBM (Plan::k4s).
 constexpr uint32_t kK4ListMax = 2048;
+// 4-cliques over a root's induced out-neighbourhood (k_k4_local): roots of
+// out-degree 3 .. kK4LocalMax, in classes by out-degree (-1: not such a root);
+// the membership filter has kK4LocalWords words (half at out-degree <= 128).
+constexpr uint32_t kK4LocalMax = 512;
+constexpr uint32_t kK4LocalWords = 512;
+constexpr uint32_t kK4LocalClasses = 4;
+inline int k4_local_class(uint32_t d) {
+  if (d < 3 || d > kK4LocalMax) return -1;
+  return d <= 64 ? 0 : d <= 128 ? 1 : d <= 256 ? 2 : 3;
+}
+// Counts the roots a.roots: n[0] of out-degree <= 64, then n[1] <= 128,
+// n[2] <= 256 and n[3] <= 512 (each in k4_local_class), into a.acc[0].
+eh_status launch_4cliques_local(Ctx* c, hipStream_t s, const LaunchArgs& a,
+                               const uint64_t n[kK4LocalClasses]);
 // Sizes and allocates the HBM S lists of a 4-clique launch over `items` when
 // a root's out-degree exceeds kK4ListMax (nothing otherwise): one list of
 // the largest such out-degree per wave, at most 4 waves per compute unit.

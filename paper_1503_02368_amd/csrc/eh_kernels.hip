@@ -85,6 +85,8 @@ struct DevArgs {
   uint32_t reverse;         // items taken from the last to the first
   uint32_t* k4s;            // 4-cliques: per-wave S lists in HBM (the HBM-list instance)
   uint32_t k4s_stride;      //   words per wave's list
+  const uint32_t* roots;    // 4-cliques over induced neighbourhoods: the roots
+  uint64_t n_roots;
 };
 
 DevArgs to_dev(const LaunchArgs& a) {
@@ -118,6 +120,8 @@ DevArgs to_dev(const LaunchArgs& a) {
   d.reverse = a.reverse;
   d.k4s = a.k4s;
   d.k4s_stride = a.k4s_stride;
+  d.roots = a.roots;
+  d.n_roots = a.n_roots;
   return d;
 }
 
@@ -1070,6 +1074,177 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// 4-cliques over a root's induced out-neighbourhood
+// ---------------------------------------------------------------------------
+
+// For a root u with N+(u) = {v_0 < ... < v_{d-1}}, row i holds
+// T_i = N+(v_i) & N+(u) as a bitset over local ids (v_j is bit j): the join's
+// second-level set for (u, v_i), in the bitset layout over the root's own
+// domain.  The third level's sets are then T_i & T_j for j in T_i (bits of
+// T_j all lie above j), counted by word AND and popcount in LDS (section
+// 4.2's bitset-bitset intersection), so each N+(v) is read once per root
+// instead of once per triangle it closes.
+// N+(u) is held as a composite set (section 4.3): a bitmap of RW words over
+// the top window [wb, max] and the plen members below wb (the first plen of
+// the sorted list), which a streamed element below the window is searched
+// in.  A member's local id is its index in the list: below the window, the
+// search's result; in it, plen plus the members in the words below and
+// below it in its word.  Bitset words are streamed only from sets whose
+// bitset starts inside the window.  Blocks of WPB waves take roots
+// a.roots[blockIdx.x + k gridDim.x], each with 3 <= d <= DMAX.
+template <int WPB, int RW, int DMAX, int U>
+__global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
+  constexpr uint32_t W = DMAX / 32;       // words per row
+  constexpr uint32_t RS = W + 1;          // row stride: rows start in different banks
+  constexpr uint32_t NT = WPB * kWave;
+  __shared__ uint32_t s_a[RW];            // the window's bitmap
+  __shared__ uint16_t s_p[RW];            // members in the window's words below
+  __shared__ uint32_t s_u[DMAX];          // N+(u), sorted
+  __shared__ uint32_t s_m[DMAX * RS];     // rows T_i
+  __shared__ uint32_t s_pre[WPB][kSeg + 1];
+  __shared__ uint2 s_seg[WPB][kSeg];
+  __shared__ uint32_t s_plen;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
+  const SegTab T{s_pre[wid], s_seg[wid]};
+  const uint32_t* __restrict__ L = a.col;
+  for (uint32_t k = tid; k < uint32_t(RW); k += NT) s_a[k] = 0;
+  for (uint32_t k = tid; k < DMAX * RS; k += NT) s_m[k] = 0;
+  if (tid == 0) s_plen = 0;
+  __syncthreads();
+  unsigned long long acc = 0;
+  // roots come by decreasing estimated cost; block b takes b, 2G-1-b, 2G+b,
+  // 4G-1-b, ... (G blocks), so that every block's share costs about the same
+  const uint64_t G = gridDim.x;
+  for (uint64_t k = 0;; ++k) {
+    const uint64_t r = k * G + ((k & 1) ? G - 1 - blockIdx.x : blockIdx.x);
+    if (r >= a.n_roots) break;
+    const uint32_t u = a.roots[r];
+    const uint2 ud = a.vdesc[u];
+    const uint32_t beg = ud.x, d = ud.y & kMaxIndex;
+    const uint32_t lo = L[beg], hi = L[beg + d - 1];
+    // window base: a multiple of 32 with hi - wb < 32 RW, as low as possible
+    const uint32_t wb = hi - (lo & ~31u) < uint32_t(RW) * 32u
+                            ? (lo & ~31u)
+                            : ((hi + 1u - uint32_t(RW) * 32u + 31u) & ~31u);
+    const uint32_t nw = ((hi - wb) >> 5) + 1;
+    for (uint32_t k = tid; k < d; k += NT) {
+      const uint32_t x = L[beg + k];
+      s_u[k] = x;
+      if (x >= wb) {
+        atomicOr(&s_a[(x - wb) >> 5], 1u << ((x - wb) & 31));
+        if (k == 0 || L[beg + k - 1] < wb) s_plen = k;
+      }
+    }
+    __syncthreads();
+    const uint32_t plen = s_plen;
+    if (wid == 0) {
+      // s_p[w]: window members in words [0, w), lane l summing a run of words
+      const uint32_t per = (nw + kWave - 1) / kWave, w0 = lane * per, w1 = min(w0 + per, nw);
+      uint32_t sum = 0;
+      for (uint32_t w = w0; w < w1; ++w) sum += __popc(s_a[w]);
+      uint32_t run = wave_incl_scan(sum, lane) - sum;
+      for (uint32_t w = w0; w < w1; ++w) {
+        s_p[w] = uint16_t(run);
+        run += __popc(s_a[w]);
+      }
+    }
+    __syncthreads();
+    // rows T_0 .. T_{d-2} (v_{d-1} has no later member in N+(u)), 64 rows per
+    // flat batch, batches dealt to the waves
+    const WordRule wr{a.use_bitsets != 0, wb, plen ? wb : 0u};
+    for (uint32_t b0 = wid * kWave; b0 + 1 < d; b0 += NT) {
+      const uint32_t nseg = min(uint32_t(kSeg), d - 1 - b0);
+      Seg g{0, 0, kNoWords};
+      if (lane < nseg) g = seg_full<true>(a, s_u[b0 + lane], wr);
+      const uint32_t E = publish_segments(T, g, lane);
+      SegCursor<false> c(T);
+      for (uint32_t f0 = 0; f0 < E; f0 += kWave * U) {
+        uint32_t val[U], key[U], row[U];
+        bool ok[U], bits[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          const uint32_t f = f0 + uint32_t(q) * kWave + lane;
+          ok[q] = f < E;
+          val[q] = key[q] = row[q] = 0;
+          bits[q] = false;
+          if (ok[q]) {
+            c.seek(T, f);
+            val[q] = L[c.base + f];
+            key[q] = c.wbase + f;
+            bits[q] = c.bits;
+            row[q] = b0 + c.j;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          // an element x tests bit x - wb; a bitset word (key: its index from
+          // wb's word) is ANDed whole; an element below the window is searched
+          const uint32_t dx = val[q] - wb;
+          const uint32_t w = bits[q] ? key[q] : (dx >> 5);
+          uint32_t m = 0;
+          if (ok[q] && w < nw) m = s_a[w] & (bits[q] ? val[q] : (1u << (dx & 31)));
+          uint32_t* R = s_m + row[q] * RS;
+          while (m) {
+            const uint32_t b = uint32_t(__builtin_ctz(m));
+            m &= m - 1u;
+            const uint32_t j = plen + s_p[w] + __popc(s_a[w] & ((1u << b) - 1u));
+            atomicOr(&R[j >> 5], 1u << (j & 31));
+          }
+          if (plen && ok[q] && !bits[q] && val[q] < wb) {
+            const uint32_t j = lower_bound_lds(s_u, plen, val[q]);
+            if (j < plen && s_u[j] == val[q]) atomicOr(&R[j >> 5], 1u << (j & 31));
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // sum over rows i and members j of T_i of |T_i & T_j|, one row per lane
+    // (rows i <= d-3: a pair needs two later members); T_j's bits lie above
+    // j, so only the words from j's on are ANDed
+    uint32_t cnt = 0;
+    const uint32_t wd = (d + 31) >> 5;  // words that can hold a member
+    for (uint32_t i = wid * kWave + lane; i + 2 < d; i += NT) {
+      const uint32_t* Ti = s_m + i * RS;
+      if constexpr (W <= 4) {
+        // short rows: T_i in registers
+        uint32_t t[W];
+#pragma unroll
+        for (uint32_t w = 0; w < W; ++w) t[w] = Ti[w];
+#pragma unroll
+        for (uint32_t w = 0; w < W; ++w) {
+          uint32_t bm = t[w];
+          while (bm) {
+            const uint32_t j = w * 32u + uint32_t(__builtin_ctz(bm));
+            bm &= bm - 1u;
+            const uint32_t* Tj = s_m + j * RS;
+#pragma unroll
+            for (uint32_t v = w; v < W; ++v) cnt += __popc(t[v] & Tj[v]);
+          }
+        }
+      } else {
+        for (uint32_t w = (i + 1) >> 5; w < wd; ++w) {
+          uint32_t bm = Ti[w];
+          while (bm) {
+            const uint32_t j = w * 32u + uint32_t(__builtin_ctz(bm));
+            bm &= bm - 1u;
+            const uint32_t* Tj = s_m + j * RS;
+            for (uint32_t v = w; v < wd; ++v) cnt += __popc(Ti[v] & Tj[v]);
+          }
+        }
+      }
+    }
+    acc += cnt;
+    __syncthreads();
+    for (uint32_t k = tid; k < d * RS; k += NT) s_m[k] = 0;
+    for (uint32_t k = plen + tid; k < d; k += NT) s_a[(s_u[k] - wb) >> 5] = 0;
+    if (tid == 0) s_plen = 0;
+    __syncthreads();
+  }
+  const unsigned long long tot = wave_sum(acc);
+  if (lane == 0 && tot) atomicAdd(&a.acc[0], tot);
+}
+
+// ---------------------------------------------------------------------------
 // Triangles, pairwise (both sets from HBM), G lanes per pair
 // ---------------------------------------------------------------------------
 
@@ -1305,6 +1480,34 @@ eh_status launch_lollipop(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t 
   hipLaunchKernelGGL((k_lollipop_staged<kTriWPB, kTriRW, 4>), dim3(grid),
                      dim3(kTriWPB * kWave), 0, s, to_dev(la));
   return hip_check(c, hipGetLastError(), "Lollipop kernel launch");
+}
+
+eh_status launch_4cliques_local(Ctx* c, hipStream_t s, const LaunchArgs& la,
+                               const uint64_t n[kK4LocalClasses]) {
+  // blocks per CU as the LDS allows: one wave per root at out-degree <= 64
+  // and <= 128 (a 256-word window), four at <= 256 and eight at <= 512
+  static constexpr uint32_t kPerCu[kK4LocalClasses] = {32, 28, 9, 3};
+  uint64_t off = 0;
+  for (int k = 0; k < int(kK4LocalClasses); ++k) {
+    if (n[k] == 0) continue;
+    DevArgs d = to_dev(la);
+    d.roots = la.roots + off;
+    d.n_roots = n[k];
+    off += n[k];
+    const uint32_t grid = uint32_t(std::min<uint64_t>(n[k], uint64_t(c->n_cu) * kPerCu[k]));
+    constexpr int RW = int(kK4LocalWords);
+    if (k == 0)
+      hipLaunchKernelGGL((k_k4_local<1, RW / 2, 64, 4>), dim3(grid), dim3(kWave), 0, s, d);
+    else if (k == 1)
+      hipLaunchKernelGGL((k_k4_local<1, RW / 2, 128, 4>), dim3(grid), dim3(kWave), 0, s, d);
+    else if (k == 2)
+      hipLaunchKernelGGL((k_k4_local<4, RW, 256, 4>), dim3(grid), dim3(4 * kWave), 0, s, d);
+    else
+      hipLaunchKernelGGL((k_k4_local<8, RW, 512, 4>), dim3(grid), dim3(8 * kWave), 0, s, d);
+    const eh_status st = hip_check(c, hipGetLastError(), "induced-neighbourhood 4-clique launch");
+    if (st != EH_OK) return st;
+  }
+  return EH_OK;
 }
 
 eh_status launch_4cliques(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t /*kernel*/,

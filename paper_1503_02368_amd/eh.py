@@ -61,7 +61,7 @@ class _Allocator(ctypes.Structure):
 
 
 # struct layouts below are those of this ABI version of include/eh.h
-ABI_VERSION = 10900
+ABI_VERSION = 11000
 
 
 class _Tuning(ctypes.Structure):
@@ -72,7 +72,7 @@ class _Tuning(ctypes.Structure):
                 ("stage_words", ctypes.c_uint32), ("xcds", ctypes.c_uint32),
                 ("unroll", ctypes.c_uint32), ("grab", ctypes.c_uint32),
                 ("search_below", ctypes.c_uint32), ("group", ctypes.c_uint32),
-                ("reverse", ctypes.c_uint32)]
+                ("reverse", ctypes.c_uint32), ("k4_local", ctypes.c_uint32)]
 
 
 class _BuildOpts(ctypes.Structure):

@@ -97,7 +97,7 @@ TUNINGS = {
 }
 DEFAULT = dict(kernel=1, staging=2, algo=0, gamma=32.0, chunk_work=4096, waves_per_cu=32,
                group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0, xcds=0, unroll=8, grab=8,
-               search_below=24, group=1, reverse=0)
+               search_below=24, group=1, reverse=0, k4_local=1)
 
 
 def tune(ctx, **kw):
@@ -138,6 +138,67 @@ def test_4cliques_zoo(ctx, eh, tname, lay):
         finally:
             trie.free()
         assert got == K, (el.name, tname, lay[0])
+
+
+def _k4_local_graphs():
+    """Roots in every out-degree class of the induced-neighbourhood kernel
+    (<= 128, <= 256, <= 512) and just beyond it (513), out-sets spanning more
+    ids than its window, sinks and messy input."""
+    star_of_cliques = inputs.disjoint_union(*[inputs.complete(6) for _ in range(4000)])
+    # one vertex adjacent to a member of every clique: its out-set spans the ids
+    hub = star_of_cliques.n
+    src = np.concatenate([star_of_cliques.src, np.full(4000, hub, np.uint32)])
+    dst = np.concatenate([star_of_cliques.dst, np.arange(0, 24000, 6, dtype=np.uint32)])
+    spread = inputs.EdgeList(hub + 1, src, dst, "hub_over_4000_K6")
+    return [inputs.complete(130), inputs.complete(257), inputs.complete(513), inputs.complete(514),
+            inputs.disjoint_union(inputs.complete(200), inputs.rmat(12, 16, seed=81),
+                                  inputs.complete(40)),
+            inputs.rmat(14, 16, seed=82), inputs.gnp(3000, 0.05, seed=83),
+            inputs.chung_lu(40000, 24, 2.1, seed=84), spread,
+            inputs.messy(inputs.rmat(11, 16, seed=85), 3)]
+
+
+@pytest.mark.parametrize("lay", [("uint", 0, 32.0), ("hybrid256", 1, 256.0), ("bitset_all", 2, 32.0)],
+                         ids=lambda x: x[0])
+def test_4cliques_induced_neighbourhoods(ctx, eh, lay):
+    """4-cliques with roots counted over their induced out-neighbourhoods
+    (k4_local = 1) equal the oracle's and the staged S-list kernel's
+    (k4_local = 0), with and without streamed bitset words, under two
+    schedules of the roots the first leaves to the second."""
+    from math import comb
+    for el in _k4_local_graphs():
+        # complete graphs by the closed form C(n, 4), the rest by the oracle
+        K = comb(el.n, 4) if el.name == f"K{el.n}" else oracle.Graph.from_edgelist(el).count(4)
+        say("k4 local", lay[0], el.name, K)
+        trie = ctx.build_edgelist(el, layout=lay[1], tau=lay[2])
+        try:
+            for kw in (dict(k4_local=1, staging=1, dynamic=0), dict(k4_local=1, use_bitsets=0),
+                       dict(k4_local=1, dynamic=4, grab=2, chunk_work=512),
+                       dict(k4_local=0, staging=1, dynamic=4, grab=2)):
+                tune(ctx, **kw)
+                assert ctx.count_4cliques(trie) == K, (el.name, kw)
+        finally:
+            trie.free()
+
+
+def test_4cliques_induced_accumulate_and_noalloc(ctx, eh):
+    """The accumulating and allocation-free counts run both 4-clique launches
+    of a plan whose roots are split between them."""
+    import torch
+    el = inputs.disjoint_union(inputs.complete(600), inputs.rmat(12, 16, seed=86))
+    K = oracle.Graph.from_edgelist(el).count(4)
+    tune(ctx, k4_local=1, staging=1, dynamic=4, grab=2)
+    trie = ctx.build_edgelist(el)
+    try:
+        assert ctx.count_4cliques(trie) == K
+        out = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ctx.stream.wait_stream(torch.cuda.current_stream())
+        ctx.count_add_async(trie, eh.CLIQUE4, out)
+        ctx.count_add_noalloc(trie, eh.CLIQUE4, out)
+        torch.cuda.synchronize()
+        assert int(out.cpu().numpy().view(np.uint64)[0]) == 2 * K
+    finally:
+        trie.free()
 
 
 @pytest.mark.parametrize("dyn", [0, 4])
@@ -1127,7 +1188,7 @@ def test_randomized_parity(ctx, eh):
                  group=choice([1, 2, 4]), chunk_work=choice([64, 1000, 32768]),
                  reverse=choice([0, 1]),
                  waves_per_cu=choice([1, 8, 32]), unroll=choice([4, 8]),
-                 group_lanes=choice([0, 4, 64]), algo=choice([0, 1, 2]))
+                 group_lanes=choice([0, 4, 64]), algo=choice([0, 1, 2]), k4_local=choice([0, 1]))
         tune(ctx, **t)
         layout, tau = choice([(0, 32.0), (1, 2.0), (1, 32.0), (1, 256.0), (2, 32.0)])
         T, K, _ = truth(el)
