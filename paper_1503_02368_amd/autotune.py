@@ -37,7 +37,7 @@ DEFAULT_OUT = os.path.join(HERE, "tuning.json")
 
 BASE = dict(kernel=1, staging=2, algo=0, gamma=32.0, chunk_work=4096, waves_per_cu=32,
             group_lanes=0, use_bitsets=1, dynamic=0, stage_words=0, xcds=0, unroll=8, grab=8,
-            search_below=24, group=1, reverse=0)
+            search_below=24, group=1, reverse=0, k4_local=1)
 # schedules tried last: (dynamic, grab); 3 and 4 cut the items into one range per XCD,
 # 5 deals items sorted by decreasing cost boustrophedon
 SCHEDULES = [(1, 8), (2, 8), (3, 8), (4, 1), (4, 4), (4, 16), (5, 8)]
@@ -106,7 +106,7 @@ def tune_graph(el, pattern, layouts, ctx, torch, quick=False, expect=None):
         has_bits = trie.info["n_bitset_sets"] > 0
         try:
             kinds = [dict(kernel=1, staging=2), dict(kernel=1, staging=1)] if pattern == 3 else \
-                [dict(kernel=1, staging=1)]
+                [dict(kernel=1, staging=1), dict(kernel=1, staging=1, k4_local=0)]
             if pattern == 3:
                 kinds.append(dict(kernel=2, group_lanes=0, algo=0))
             local = None

@@ -84,13 +84,7 @@ eh_status upload(Ctx* c, DevBuf& b, const void* src, size_t bytes, const char* w
 
 void free_trie_device(Trie& t) {
   Ctx* c = t.ctx;
-  for (auto& p : t.plans) {
-    dev_free(c, p->items);
-    dev_free(c, p->sdesc);
-    dev_free(c, p->rec);
-    dev_free(c, p->gsub);
-    dev_free(c, p->k4s);
-  }
+  for (auto& p : t.plans) free_plan(c, *p);
   t.plans.clear();
   dev_free(c, t.vdesc);
   dev_free(c, t.col);
@@ -188,7 +182,8 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
     if (p->k4l.p) {
       // single-graph plans only: the whole range of items and every root
       LaunchArgs la = a;
-      la.roots = static_cast<const uint32_t*>(p->k4l.p);
+      la.roots = static_cast<const uint4*>(p->k4l.p);
+      la.rec = static_cast<const uint2*>(p->rec.p);
       if (eh_status st = launch_4cliques_local(c, c->stream, la, p->k4l_n); st != EH_OK) return st;
     }
     return launch_4cliques(c, c->stream, a, c->tune.kernel, c->tune.waves_per_cu);
@@ -313,6 +308,13 @@ eh_status eh_ctx_create(int device, void* hip_stream, const eh_allocator* alloc,
       c->has_alloc = true;
     }
   }
+  for (int k = 0; st == EH_OK && k < Ctx::kSide; ++k) {
+    st = hip_check(c, hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking), "side stream");
+    if (st == EH_OK)
+      st = hip_check(c, hipEventCreateWithFlags(&c->join[k], hipEventDisableTiming), "join event");
+  }
+  if (st == EH_OK)
+    st = hip_check(c, hipEventCreateWithFlags(&c->fork, hipEventDisableTiming), "fork event");
   // one cursor per item partition, each on its own 256-byte line
   if (st == EH_OK) st = dev_alloc(c, c->cursor, sizeof(uint32_t) * kCursorWords * kMaxParts);
   if (st == EH_OK) st = ensure_acc(c, 64);
@@ -335,6 +337,14 @@ eh_status eh_ctx_destroy(eh_ctx* ctx) {
   dev_free(c, c->cursor);
   dev_free(c, c->half);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  for (int k = 0; k < Ctx::kSide; ++k) {
+    if (c->side[k]) {
+      (void)hipStreamSynchronize(c->side[k]);
+      (void)hipStreamDestroy(c->side[k]);
+    }
+    if (c->join[k]) (void)hipEventDestroy(c->join[k]);
+  }
+  if (c->fork) (void)hipEventDestroy(c->fork);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete ctx;
   return EH_OK;

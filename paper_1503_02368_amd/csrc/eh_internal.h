@@ -165,9 +165,9 @@ struct Plan {
   DevBuf k4s;
   uint32_t k4s_waves = 0;
   uint32_t k4s_stride = 0;
-  // 4-cliques over induced neighbourhoods: roots counted by k_k4_local
-  // (absent from items), out-degree classes (<= 64, <= 128, <= 256, <= 512)
-  // stored one after another, each by decreasing estimated cost
+  // 4-cliques over induced neighbourhoods: root records (uint4) of the roots
+  // counted by k_k4_local (absent from items), out-degree classes (<= 64,
+  // <= 128, <= 256, <= 512) one after another, their segment records in rec
   bool k4_local = false;
   DevBuf k4l;
   uint64_t k4l_n[4] = {0, 0, 0, 0};
@@ -206,6 +206,12 @@ struct Ctx {
   uint64_t* pinned = nullptr;  // host staging for results
   size_t pinned_cap = 0;
   void* noalloc_scratch = nullptr;  // this device's static scratch (eh_count_add_noalloc)
+  // launches that run side by side with the stream's: streams of the default
+  // priority, forked from and joined back into `stream` by events
+  static constexpr int kSide = 3;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kSide] = {};
 };
 
 // Allocation through the context.
@@ -279,8 +285,8 @@ struct LaunchArgs {
   uint32_t* k4s = nullptr;             // 4-cliques: per-wave S lists in HBM for roots
   uint32_t k4s_stride = 0;             //   of out-degree > kK4ListMax, or null
   uint32_t k4s_waves = 0;
-  const uint32_t* roots = nullptr;     // 4-cliques over induced neighbourhoods
-  uint64_t n_roots = 0;
+  const uint4* roots = nullptr;        // 4-cliques over induced neighbourhoods: root
+  uint64_t n_roots = 0;                //   records (segment records in rec)
 };
 eh_status launch_fill_u64(Ctx* c, hipStream_t s, unsigned long long* p, uint64_t n,
                           unsigned long long v);
@@ -302,6 +308,8 @@ eh_status launch_scatter_roots(Ctx* c, hipStream_t s, const unsigned long long* 
 eh_status device_traversal_sequence(Ctx* c, const unsigned long long* edges, uint64_t m,
                                     uint32_t kb, uint32_t n, const uint32_t* deg, uint32_t order,
                                     uint32_t* seq);
+// Frees every device buffer of a plan.
+void free_plan(Ctx* c, Plan& p);
 // Sorts a built plan's items (and per-item descriptors) by decreasing
 // estimated cost, for the snake schedule.
 eh_status device_plan_balance(Ctx* c, Trie& t, Plan& plan);
@@ -326,12 +334,16 @@ constexpr uint32_t kK4ListMax = 2048;
 constexpr uint32_t kK4LocalMax = 512;
 constexpr uint32_t kK4LocalWords = 512;
 constexpr uint32_t kK4LocalClasses = 4;
+static_assert(Ctx::kSide + 1 >= int(kK4LocalClasses), "a side stream per further class");
 inline int k4_local_class(uint32_t d) {
   if (d < 3 || d > kK4LocalMax) return -1;
   return d <= 64 ? 0 : d <= 128 ? 1 : d <= 256 ? 2 : 3;
 }
-// Counts the roots a.roots: n[0] of out-degree <= 64, then n[1] <= 128,
-// n[2] <= 256 and n[3] <= 512 (each in k4_local_class), into a.acc[0].
+// words of the bitmap window of class k
+constexpr uint32_t k4_local_window(int k) { return k <= 1 ? kK4LocalWords / 2 : kK4LocalWords; }
+// Counts the roots of the root records a.roots (segment records a.rec):
+// n[0] of out-degree <= 64, then n[1] <= 128, n[2] <= 256 and n[3] <= 512
+// (each in k4_local_class), into a.acc[0].
 eh_status launch_4cliques_local(Ctx* c, hipStream_t s, const LaunchArgs& a,
                                const uint64_t n[kK4LocalClasses]);
 // Sizes and allocates the HBM S lists of a 4-clique launch over `items` when

@@ -85,7 +85,7 @@ struct DevArgs {
   uint32_t reverse;         // items taken from the last to the first
   uint32_t* k4s;            // 4-cliques: per-wave S lists in HBM (the HBM-list instance)
   uint32_t k4s_stride;      //   words per wave's list
-  const uint32_t* roots;    // 4-cliques over induced neighbourhoods: the roots
+  const uint4* roots;       // 4-cliques over induced neighbourhoods: root records
   uint64_t n_roots;
 };
 
@@ -1084,14 +1084,16 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
 // T_j all lie above j), counted by word AND and popcount in LDS (section
 // 4.2's bitset-bitset intersection), so each N+(v) is read once per root
 // instead of once per triangle it closes.
-// N+(u) is held as a composite set (section 4.3): a bitmap of RW words over
-// the top window [wb, max] and the plen members below wb (the first plen of
-// the sorted list), which a streamed element below the window is searched
-// in.  A member's local id is its index in the list: below the window, the
-// search's result; in it, plen plus the members in the words below and
-// below it in its word.  Bitset words are streamed only from sets whose
-// bitset starts inside the window.  Blocks of WPB waves take roots
-// a.roots[blockIdx.x + k gridDim.x], each with 3 <= d <= DMAX.
+// N+(u) is held as a composite set (section 4.3): a bitmap of nw <= RW words
+// from wb (the top window, or all of N+(u)) and the plen members below wb
+// (the first plen of the sorted list), which a streamed element below the
+// window is searched in.  A member's local id is its index in the list:
+// below the window, the search's result; in it, plen plus the members in the
+// words below and below it in its word.  The plan resolves per root
+// {position of N+(u), d | plen << 10 | nw << 20, first segment record, wb}
+// and per row the streamed part of N+(v_i) as a segment record, so a root
+// costs one dependent load before its members and records arrive.  Blocks
+// of WPB waves take the roots, each with 3 <= d <= DMAX.
 template <int WPB, int RW, int DMAX, int U>
 __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
   constexpr uint32_t W = DMAX / 32;       // words per row
@@ -1103,13 +1105,11 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
   __shared__ uint32_t s_m[DMAX * RS];     // rows T_i
   __shared__ uint32_t s_pre[WPB][kSeg + 1];
   __shared__ uint2 s_seg[WPB][kSeg];
-  __shared__ uint32_t s_plen;
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
   const SegTab T{s_pre[wid], s_seg[wid]};
   const uint32_t* __restrict__ L = a.col;
   for (uint32_t k = tid; k < uint32_t(RW); k += NT) s_a[k] = 0;
   for (uint32_t k = tid; k < DMAX * RS; k += NT) s_m[k] = 0;
-  if (tid == 0) s_plen = 0;
   __syncthreads();
   unsigned long long acc = 0;
   // roots come by decreasing estimated cost; block b takes b, 2G-1-b, 2G+b,
@@ -1118,25 +1118,18 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
   for (uint64_t k = 0;; ++k) {
     const uint64_t r = k * G + ((k & 1) ? G - 1 - blockIdx.x : blockIdx.x);
     if (r >= a.n_roots) break;
-    const uint32_t u = a.roots[r];
-    const uint2 ud = a.vdesc[u];
-    const uint32_t beg = ud.x, d = ud.y & kMaxIndex;
-    const uint32_t lo = L[beg], hi = L[beg + d - 1];
-    // window base: a multiple of 32 with hi - wb < 32 RW, as low as possible
-    const uint32_t wb = hi - (lo & ~31u) < uint32_t(RW) * 32u
-                            ? (lo & ~31u)
-                            : ((hi + 1u - uint32_t(RW) * 32u + 31u) & ~31u);
-    const uint32_t nw = ((hi - wb) >> 5) + 1;
+    const uint4 rr = a.roots[r];
+    const uint32_t beg = rr.x, d = rr.y & 1023u, plen = (rr.y >> 10) & 1023u, nw = rr.y >> 20;
+    const uint32_t roff = rr.z, wb = rr.w;
+    // the first batch of segment records is loaded beside the members
+    uint2 rc0{0, 0};
+    if (tid < min(uint32_t(kSeg), d - 1)) rc0 = a.rec[roff + tid];
     for (uint32_t k = tid; k < d; k += NT) {
       const uint32_t x = L[beg + k];
       s_u[k] = x;
-      if (x >= wb) {
-        atomicOr(&s_a[(x - wb) >> 5], 1u << ((x - wb) & 31));
-        if (k == 0 || L[beg + k - 1] < wb) s_plen = k;
-      }
+      if (k >= plen) atomicOr(&s_a[(x - wb) >> 5], 1u << ((x - wb) & 31));
     }
     __syncthreads();
-    const uint32_t plen = s_plen;
     if (wid == 0) {
       // s_p[w]: window members in words [0, w), lane l summing a run of words
       const uint32_t per = (nw + kWave - 1) / kWave, w0 = lane * per, w1 = min(w0 + per, nw);
@@ -1151,59 +1144,118 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
     __syncthreads();
     // rows T_0 .. T_{d-2} (v_{d-1} has no later member in N+(u)), 64 rows per
     // flat batch, batches dealt to the waves
-    const WordRule wr{a.use_bitsets != 0, wb, plen ? wb : 0u};
     for (uint32_t b0 = wid * kWave; b0 + 1 < d; b0 += NT) {
       const uint32_t nseg = min(uint32_t(kSeg), d - 1 - b0);
       Seg g{0, 0, kNoWords};
-      if (lane < nseg) g = seg_full<true>(a, s_u[b0 + lane], wr);
+      if (lane < nseg) {
+        const uint2 rc = b0 == 0 ? rc0 : a.rec[roff + b0 + lane];
+        g = Seg{rc.x, rc.y & 0x3FFFFFu, (rc.y & kHiBit) ? int32_t((rc.y >> 22) & 0x1FFu) : kNoWords};
+      }
       const uint32_t E = publish_segments(T, g, lane);
-      SegCursor<false> c(T);
-      for (uint32_t f0 = 0; f0 < E; f0 += kWave * U) {
-        uint32_t val[U], key[U], row[U];
-        bool ok[U], bits[U];
+      // an element x tests bit x - wb; a bitset word (key: its index from
+      // wb's word) is ANDed whole; an element below the window is searched
+      // an element's segment, packed to save registers: its row (bits 0-9),
+      // whether it is a bitset word (bit 10) and, for a word, its index from
+      // wb's word (bits 16-31; 0xFFFF when outside the window)
+      constexpr uint32_t kNone = 0xFFFFFFFFu;
+      auto pack = [&](const SegCursor<false>& c, uint32_t f) {
+        const uint32_t key = c.wbase + f;
+        return (b0 + c.j) | (c.bits ? (1u << 10) : 0u) | ((key < nw ? key : 0xFFFFu) << 16);
+      };
+      auto take = [&](uint32_t val, uint32_t info) {
+        const bool bits = (info >> 10) & 1u;
+        const uint32_t row = info & 1023u;
+        const uint32_t dx = val - wb;
+        const uint32_t w = bits ? (info >> 16) : (dx >> 5);
+        uint32_t m = 0;
+        if (w < nw) m = s_a[w] & (bits ? val : (1u << (dx & 31)));
+        uint32_t* R = s_m + row * RS;
+        while (m) {
+          const uint32_t b = uint32_t(__builtin_ctz(m));
+          m &= m - 1u;
+          const uint32_t j = plen + s_p[w] + __popc(s_a[w] & ((1u << b) - 1u));
+          atomicOr(&R[j >> 5], 1u << (j & 31));
+        }
+        if (plen && !bits && val < wb) {
+          const uint32_t j = lower_bound_lds(s_u, plen, val);
+          if (j < plen && s_u[j] == val) atomicOr(&R[j >> 5], 1u << (j & 31));
+        }
+      };
+      if (E < nseg * a.search_below) {
+        // short sets: lane l walks the contiguous flat range [l per, (l+1) per)
+        const uint32_t per = (E + kWave - 1) / kWave;
+        const uint32_t f_beg = lane * per, f_end = min(f_beg + per, E);
+        if (f_beg < f_end) {
+          SegCursor<false> c;
+          c.find(T, f_beg);
+          for (uint32_t f0 = f_beg; f0 < f_end; f0 += U) {
+            uint32_t val[U], info[U];
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
-          const uint32_t f = f0 + uint32_t(q) * kWave + lane;
-          ok[q] = f < E;
-          val[q] = key[q] = row[q] = 0;
-          bits[q] = false;
-          if (ok[q]) {
-            c.seek(T, f);
-            val[q] = L[c.base + f];
-            key[q] = c.wbase + f;
-            bits[q] = c.bits;
-            row[q] = b0 + c.j;
+            for (int q = 0; q < U; ++q) {
+              const uint32_t f = f0 + uint32_t(q);
+              val[q] = 0;
+              info[q] = kNone;
+              if (f < f_end) {
+                c.seek(T, f);
+                val[q] = L[c.base + f];
+                info[q] = pack(c, f);
+              }
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q)
+              if (info[q] != kNone) take(val[q], info[q]);
           }
         }
+      } else {
+        SegCursor<false> c(T);
+        for (uint32_t f0 = 0; f0 < E; f0 += kWave * U) {
+          uint32_t val[U], info[U];
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
-          // an element x tests bit x - wb; a bitset word (key: its index from
-          // wb's word) is ANDed whole; an element below the window is searched
-          const uint32_t dx = val[q] - wb;
-          const uint32_t w = bits[q] ? key[q] : (dx >> 5);
-          uint32_t m = 0;
-          if (ok[q] && w < nw) m = s_a[w] & (bits[q] ? val[q] : (1u << (dx & 31)));
-          uint32_t* R = s_m + row[q] * RS;
-          while (m) {
-            const uint32_t b = uint32_t(__builtin_ctz(m));
-            m &= m - 1u;
-            const uint32_t j = plen + s_p[w] + __popc(s_a[w] & ((1u << b) - 1u));
-            atomicOr(&R[j >> 5], 1u << (j & 31));
+          for (int q = 0; q < U; ++q) {
+            const uint32_t f = f0 + uint32_t(q) * kWave + lane;
+            val[q] = 0;
+            info[q] = kNone;
+            if (f < E) {
+              c.seek(T, f);
+              val[q] = L[c.base + f];
+              info[q] = pack(c, f);
+            }
           }
-          if (plen && ok[q] && !bits[q] && val[q] < wb) {
-            const uint32_t j = lower_bound_lds(s_u, plen, val[q]);
-            if (j < plen && s_u[j] == val[q]) atomicOr(&R[j >> 5], 1u << (j & 31));
-          }
+#pragma unroll
+          for (int q = 0; q < U; ++q)
+            if (info[q] != kNone) take(val[q], info[q]);
         }
       }
     }
     __syncthreads();
-    // sum over rows i and members j of T_i of |T_i & T_j|, one row per lane
-    // (rows i <= d-3: a pair needs two later members); T_j's bits lie above
-    // j, so only the words from j's on are ANDed
+    // sum over rows i and members j of T_i of |T_i & T_j| (rows i <= d-3: a
+    // pair needs two later members); T_j's bits lie above j, so only the
+    // words from j's on are ANDed
     uint32_t cnt = 0;
     const uint32_t wd = (d + 31) >> 5;  // words that can hold a member
-    for (uint32_t i = wid * kWave + lane; i + 2 < d; i += NT) {
+    if constexpr (W > 4) {
+      // W lanes per row, lane v taking word v: the members j of T_i in words
+      // up to v, each adding |T_i & T_j| within word v (nothing when T_i's
+      // word v is empty), so a long row is spread over W lanes
+      constexpr uint32_t RPW = kWave / W;
+      const uint32_t v = lane % W, sub = lane / W;
+      for (uint32_t i0 = wid * RPW; i0 + 2 < d; i0 += NT / W) {
+        const uint32_t i = i0 + sub;
+        if (i + 2 >= d || v >= wd) continue;
+        const uint32_t* Ti = s_m + i * RS;
+        const uint32_t tv = Ti[v];
+        if (!tv) continue;
+        for (uint32_t w = (i + 1) >> 5; w <= v; ++w) {
+          uint32_t bm = Ti[w];
+          while (bm) {
+            const uint32_t j = w * 32u + uint32_t(__builtin_ctz(bm));
+            bm &= bm - 1u;
+            cnt += __popc(tv & s_m[j * RS + v]);
+          }
+        }
+      }
+    }
+    for (uint32_t i = wid * kWave + lane; W <= 4 && i + 2 < d; i += NT) {
       const uint32_t* Ti = s_m + i * RS;
       if constexpr (W <= 4) {
         // short rows: T_i in registers
@@ -1221,23 +1273,12 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
             for (uint32_t v = w; v < W; ++v) cnt += __popc(t[v] & Tj[v]);
           }
         }
-      } else {
-        for (uint32_t w = (i + 1) >> 5; w < wd; ++w) {
-          uint32_t bm = Ti[w];
-          while (bm) {
-            const uint32_t j = w * 32u + uint32_t(__builtin_ctz(bm));
-            bm &= bm - 1u;
-            const uint32_t* Tj = s_m + j * RS;
-            for (uint32_t v = w; v < wd; ++v) cnt += __popc(Ti[v] & Tj[v]);
-          }
-        }
       }
     }
     acc += cnt;
     __syncthreads();
     for (uint32_t k = tid; k < d * RS; k += NT) s_m[k] = 0;
     for (uint32_t k = plen + tid; k < d; k += NT) s_a[(s_u[k] - wb) >> 5] = 0;
-    if (tid == 0) s_plen = 0;
     __syncthreads();
   }
   const unsigned long long tot = wave_sum(acc);
@@ -1487,6 +1528,9 @@ eh_status launch_4cliques_local(Ctx* c, hipStream_t s, const LaunchArgs& la,
   // blocks per CU as the LDS allows: one wave per root at out-degree <= 64
   // and <= 128 (a 256-word window), four at <= 256 and eight at <= 512
   static constexpr uint32_t kPerCu[kK4LocalClasses] = {32, 28, 9, 3};
+  // the classes run side by side: the first on s, each other on a side
+  // stream of the context forked from s, joined back into s at the end
+  bool forked = false;
   uint64_t off = 0;
   for (int k = 0; k < int(kK4LocalClasses); ++k) {
     if (n[k] == 0) continue;
@@ -1494,17 +1538,36 @@ eh_status launch_4cliques_local(Ctx* c, hipStream_t s, const LaunchArgs& la,
     d.roots = la.roots + off;
     d.n_roots = n[k];
     off += n[k];
+    hipStream_t ks = s;
+    if (k > 0) {
+      if (!forked) {
+        if (eh_status st = hip_check(c, hipEventRecord(c->fork, s), "fork event"); st != EH_OK)
+          return st;
+        forked = true;
+      }
+      ks = c->side[k - 1];
+      if (eh_status st = hip_check(c, hipStreamWaitEvent(ks, c->fork, 0), "fork wait");
+          st != EH_OK)
+        return st;
+    }
     const uint32_t grid = uint32_t(std::min<uint64_t>(n[k], uint64_t(c->n_cu) * kPerCu[k]));
     constexpr int RW = int(kK4LocalWords);
+    static_assert(RW / 2 == int(k4_local_window(0)) && RW / 2 == int(k4_local_window(1)) &&
+                  RW == int(k4_local_window(2)) && RW == int(k4_local_window(3)),
+                  "the planner's windows are the kernels'");
     if (k == 0)
-      hipLaunchKernelGGL((k_k4_local<1, RW / 2, 64, 4>), dim3(grid), dim3(kWave), 0, s, d);
+      hipLaunchKernelGGL((k_k4_local<1, RW / 2, 64, 8>), dim3(grid), dim3(kWave), 0, ks, d);
     else if (k == 1)
-      hipLaunchKernelGGL((k_k4_local<1, RW / 2, 128, 4>), dim3(grid), dim3(kWave), 0, s, d);
+      hipLaunchKernelGGL((k_k4_local<1, RW / 2, 128, 8>), dim3(grid), dim3(kWave), 0, ks, d);
     else if (k == 2)
-      hipLaunchKernelGGL((k_k4_local<4, RW, 256, 4>), dim3(grid), dim3(4 * kWave), 0, s, d);
+      hipLaunchKernelGGL((k_k4_local<4, RW, 256, 8>), dim3(grid), dim3(4 * kWave), 0, ks, d);
     else
-      hipLaunchKernelGGL((k_k4_local<8, RW, 512, 4>), dim3(grid), dim3(8 * kWave), 0, s, d);
-    const eh_status st = hip_check(c, hipGetLastError(), "induced-neighbourhood 4-clique launch");
+      hipLaunchKernelGGL((k_k4_local<8, RW, 512, 8>), dim3(grid), dim3(8 * kWave), 0, ks, d);
+    eh_status st = hip_check(c, hipGetLastError(), "induced-neighbourhood 4-clique launch");
+    if (st == EH_OK && k > 0) {
+      st = hip_check(c, hipEventRecord(c->join[k - 1], ks), "join event");
+      if (st == EH_OK) st = hip_check(c, hipStreamWaitEvent(s, c->join[k - 1], 0), "join wait");
+    }
     if (st != EH_OK) return st;
   }
   return EH_OK;
