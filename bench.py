@@ -212,23 +212,26 @@ def bench_graph(name, w, args, ctx, eh, torch):
         merge_bytes = (cb or {}).get("bytes")
         tests = (cb or {}).get("held_tests")
         if tests:
-            # 4-cliques re-read the sets of S from L2 (their held-design bytes
-            # exceed what HBM could deliver in the time), so the bound is the
-            # vector ALU: every element test takes at least one lane
-            # operation, and 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz issue
-            # 39.3 T lane operations per second
+            # 4-cliques are not bound by HBM (the sets a launch reads stay in
+            # L2 and the last-level cache), so the bound is the vector ALU:
+            # the join's member tests against 256 CUs x 4 SIMDs x 16 lanes x
+            # 2.4 GHz = 39.3 T lane operations per second.  The induced-
+            # neighbourhood kernel makes the third level's tests as 32-bit
+            # word ANDs, so this is an algorithmic rate, not an issue rate
             achieved = tests / (ms / 1e3) / 1e9
             result["roofline"] = {
                 "bound": "alu", "achieved": achieved, "peak": ALU_PEAK_GOPS, "unit": "G tests/s",
                 "frac": achieved / ALU_PEAK_GOPS, "traffic": measured_traffic(name),
                 "traffic_kind": "L2-to-fabric bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                                "copy-calibrated)",
-                "model": "element tests of the held design (N+(u) and S_uv on chip)",
+                                "copy-calibrated), summed over the launch's kernels",
+                "model": "member tests of the join's intersections with N+(u) and S_uv held "
+                         "(N+(v) against N+(u), N+(w) against S_uv)",
                 "algorithmic_tests_per_launch": tests, "kernel_ms_per_launch": ms,
                 "held_design_bytes_per_launch": model_bytes,
                 "held_design_gbs": model_bytes / (ms / 1e3) / 1e9,
-                "note": "held-design bytes per second exceed the HBM peak: the sets of S are re-read "
-                        "from L2; the per-test lane operations the kernel spends are in profiles/"}
+                "note": "the kernel tests the third level 32 members per lane operation (bitset "
+                        "words over each root's local ids); per-kernel issue and residency "
+                        "figures are in profiles/"}
             if merge_bytes:
                 result["roofline"]["merge_equivalent"] = {
                     "model": "B_K4", "bytes_per_launch": merge_bytes,

@@ -688,13 +688,19 @@ Plan* find_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging) {
 // row below the window, only when the bitset starts inside it), else its
 // members.
 eh_status plan_k4_local(Ctx* c, const HostTrie& h, bool ub, Plan& plan) {
+  std::vector<uint64_t> cost(h.n, 0);
+  run_parts(weighted_parts(h.row, h.n, plan_threads(h.m)), [&](uint64_t u0, uint64_t u1, unsigned) {
+    for (uint64_t u = u0; u < u1; ++u) {
+      if (local_class(h, uint32_t(u)) < 0) continue;
+      uint64_t w = uint64_t(out_deg(h, uint32_t(u))) * out_deg(h, uint32_t(u));
+      for (uint32_t e = h.row[u]; e < h.row[u + 1]; ++e) w += out_deg(h, h.col[e]);
+      cost[u] = w;
+    }
+  });
   std::vector<std::pair<uint64_t, uint32_t>> cls[kK4LocalClasses];
   for (uint32_t u = 0; u < h.n; ++u) {
     const int k = local_class(h, u);
-    if (k < 0) continue;
-    uint64_t cost = uint64_t(out_deg(h, u)) * out_deg(h, u);
-    for (uint32_t e = h.row[u]; e < h.row[u + 1]; ++e) cost += out_deg(h, h.col[e]);
-    cls[k].emplace_back(cost, u);
+    if (k >= 0) cls[k].emplace_back(cost[u], u);
   }
   std::vector<uint32_t> roots;
   std::vector<uint32_t> rw;  // window words of each root's class

@@ -74,6 +74,17 @@ def counters(d: str, name_part: str):
     return {k: (statistics.fmean(v), len(v)) for k, v in acc.items()}
 
 
+def counters_by_kernel(d: str, name_part: str):
+    """{kernel name: {counter: (mean per dispatch, dispatches)}} for the kernels
+    whose name contains name_part (a launch of several kernels, one each)."""
+    acc = {}
+    for r in _csv(d, "counter_collection.csv"):
+        if name_part in r["Kernel_Name"]:
+            acc.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(
+                float(r["Counter_Value"]))
+    return {k: {c: (statistics.fmean(v), len(v)) for c, v in m.items()} for k, m in acc.items()}
+
+
 def kernel_stats(d: str):
     return _csv(d, "kernel_stats.csv")
 
@@ -172,19 +183,25 @@ def main():
     mine = [r for r in stats if args.kernel in r["Name"]]
     if not mine:
         raise SystemExit(f"kernel {args.kernel} not in {args.trace}")
-    k = mine[0]
-    avg_us = float(k["AverageNs"]) / 1e3
+    # a launch may be several kernels (one dispatch each): traffic is summed
+    # over them, durations are each kernel's own (they may overlap)
+    avg_us = sum(float(k["AverageNs"]) for k in mine) / 1e3
     known_kib = args.copy_mib * 1024.0
     cf = counters(args.copy_fetch, "copyBuffer")["FETCH_SIZE"][0]
     cw = counters(args.copy_write, "copyBuffer")["WRITE_SIZE"][0]
     f_fac, w_fac = known_kib / cf, known_kib / cw
-    fk, fn = counters(args.fetch, args.kernel)["FETCH_SIZE"]
-    wk, wn = counters(args.write, args.kernel)["WRITE_SIZE"]
+    fb = counters_by_kernel(args.fetch, args.kernel)
+    wb = counters_by_kernel(args.write, args.kernel)
+    fk = sum(c["FETCH_SIZE"][0] for c in fb.values())
+    wk = sum(c["WRITE_SIZE"][0] for c in wb.values())
+    fn = min(c["FETCH_SIZE"][1] for c in fb.values())
+    wn = min(c["WRITE_SIZE"][1] for c in wb.values())
     traffic = (fk * f_fac + wk * w_fac) * 1024.0
-    extra = {}
+    per_kernel = {}
     for d in args.counters:
-        for name, (v, n) in counters(d, args.kernel).items():
-            extra[name] = (v, n)
+        for kname, m in counters_by_kernel(d, args.kernel).items():
+            per_kernel.setdefault(kname, {}).update(m)
+    extra = next(iter(per_kernel.values())) if len(per_kernel) == 1 else {}
 
     with open(args.commands) as f:
         cmds = f.read().strip()
@@ -196,7 +213,10 @@ def main():
     for r in stats:
         lines.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs'])/1e3:.3f} | "
                      f"{float(r['MinNs'])/1e3:.3f} | {float(r['MaxNs'])/1e3:.3f} | {float(r['Percentage']):.2f} % |")
-    lines += ["", "## Memory traffic (per dispatch of the kernel)", "",
+    several = len(mine) > 1
+    lines += ["", "## Memory traffic (per launch: " +
+              (f"the {len(mine)} kernels matching `{args.kernel}`, one dispatch each, summed)"
+               if several else "one dispatch of the kernel)"), "",
               f"* FETCH_SIZE: {fk:,.0f} KiB (mean of {fn} dispatches) x {f_fac:.3f} = "
               f"{fk * f_fac * 1024 / 1e9:.3f} GB",
               f"* WRITE_SIZE: {wk:,.0f} KiB (mean of {wn} dispatches) x {w_fac:.3f} = "
@@ -204,8 +224,9 @@ def main():
               f"* Calibration: a copy of {args.copy_mib} MiB reads {cf:,.0f} KiB by FETCH_SIZE and "
               f"writes {cw:,.0f} KiB by WRITE_SIZE per dispatch (factors {f_fac:.3f}, {w_fac:.3f}).",
               f"* L2-to-fabric traffic per launch (reads the 256 MB last-level cache serves are "
-              f"included): {traffic / 1e9:.3f} GB; over the average duration "
-              f"{avg_us:.1f} us that is {traffic / (avg_us * 1e-6) / 1e9:.0f} GB/s "
+              f"included): {traffic / 1e9:.3f} GB; over the " +
+              ("summed average durations" if several else "average duration") +
+              f" {avg_us:.1f} us that is {traffic / (avg_us * 1e-6) / 1e9:.0f} GB/s "
               f"({traffic / (avg_us * 1e-6) / 8e12 * 100:.1f} % of 8 TB/s)."]
     if args.algorithmic_bytes:
         lines.append(f"* Algorithmic bytes per launch: {args.algorithmic_bytes / 1e9:.3f} GB "
@@ -217,6 +238,29 @@ def main():
             v, n = extra[name]
             lines.append(f"| {name} | {v:,.0f} | {n} |")
     lines += derived(extra, avg_us)
+    if several:
+        # the kernels of one launch run side by side in the trace; a counter
+        # run serialises the dispatches, so each kernel's derived figures use
+        # its own duration there
+        by_name = {}
+        if args.counters:
+            for r in _csv(args.counters[0], "kernel_trace.csv"):
+                if args.kernel in r["Kernel_Name"]:
+                    by_name.setdefault(r["Kernel_Name"], []).append(
+                        (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        by_name = {k: statistics.median(v) for k, v in by_name.items()}
+        lines += ["", "The kernels run side by side on forked streams, so the trace's durations "
+                  "overlap; the counter runs serialise the dispatches, and each kernel's section "
+                  "gives its duration there."]
+        for kname in sorted(per_kernel, key=lambda k: -by_name.get(k, 0.0)):
+            m = per_kernel[kname]
+            us = by_name.get(kname, 0.0)
+            lines += ["", f"## {kname[:100]} ({us:.1f} us alone)", "",
+                      "| counter | value | dispatches |", "|---|---|---|"]
+            for name in sorted(m):
+                v, n = m[name]
+                lines.append(f"| {name} | {v:,.0f} | {n} |")
+            lines += derived(m, us)[1:] if us else []
     src = os.path.join(ROOT, "paper_1503_02368_amd", "csrc", args.source)
     sha = kernel_sha(src)
     lines += ["", f"Kernel source hash ({args.source}, sha256 prefix): {sha}", ""]
