@@ -832,11 +832,27 @@ eh_status eh_count_rooted(eh_ctx* ctx, const eh_trie* trie, int pattern, const u
   r.erase(std::unique(r.begin(), r.end()), r.end());
   std::vector<Item> items;
   uint32_t item_dmax = 0;
+  // 4-cliques: roots of out-degree <= 512 counted over their induced
+  // out-neighbourhoods, whole roots after the S-list kernel's items
+  const bool local = pattern == EH_4CLIQUE && c->tune.k4_local && !h.symmetric;
+  std::vector<Item> lc[kK4LocalClasses];
   for (uint32_t u : r) {
+    const uint32_t du = h.row[u + 1] - h.row[u];
+    const int k = local ? k4_local_class(du) : -1;
+    if (k >= 0) {
+      lc[k].push_back(Item{u, h.row[u], du, 0});
+      continue;
+    }
     const size_t before = items.size();
     make_items_source(h, u, 0, c->tune.chunk_work, uint32_t(pattern), c->tune.use_bitsets != 0,
                       items);
-    if (items.size() > before) item_dmax = std::max(item_dmax, h.row[u + 1] - h.row[u]);
+    if (items.size() > before) item_dmax = std::max(item_dmax, du);
+  }
+  const size_t n_list = items.size();
+  uint64_t loff[kK4LocalClasses + 1] = {n_list};
+  for (uint32_t k = 0; k < kK4LocalClasses; ++k) {
+    items.insert(items.end(), lc[k].begin(), lc[k].end());
+    loff[k + 1] = items.size();
   }
   unsigned long long* acc = static_cast<unsigned long long*>(c->acc.p);
   eh_status st = launch_fill_u64(c, c->stream, acc, 1, 0);
@@ -854,12 +870,20 @@ eh_status eh_count_rooted(eh_ctx* ctx, const eh_trie* trie, int pattern, const u
     p.pattern = uint32_t(pattern);
     p.staging = EH_STAGE_SOURCE;
     p.items = buf;
-    p.n_items = items.size();
+    p.n_items = n_list;
     p.item_dmax = item_dmax;
     if (pattern == EH_4CLIQUE)
-      st = prepare_k4_lists(c, h, items.data(), items.size(), lists, p.k4s_waves, p.k4s_stride);
+      st = prepare_k4_lists(c, h, items.data(), n_list, lists, p.k4s_waves, p.k4s_stride);
     p.k4s = lists;
-    if (st == EH_OK) st = enqueue_count(c, t, &p, 0, items.size(), acc, 0, nullptr);
+    if (st == EH_OK && n_list) st = enqueue_count(c, t, &p, 0, n_list, acc, 0, nullptr);
+    for (uint32_t k = 0; st == EH_OK && k < kK4LocalClasses; ++k) {
+      LaunchArgs la = base_args(c, t);
+      la.items = static_cast<const Item*>(buf.p) + loff[k];
+      la.n_items = loff[k + 1] - loff[k];
+      la.acc = acc;
+      la.tag_base = 0;
+      st = launch_4cliques_local_items(c, c->stream, la, int(k));
+    }
   }
   if (st == EH_OK) st = read_back(c, acc, total, 1);
   (void)hipStreamSynchronize(c->stream);

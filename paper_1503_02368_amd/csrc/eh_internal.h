@@ -346,6 +346,9 @@ constexpr uint32_t k4_local_window(int k) { return k <= 1 ? kK4LocalWords / 2 : 
 // (each in k4_local_class), into a.acc[0].
 eh_status launch_4cliques_local(Ctx* c, hipStream_t s, const LaunchArgs& a,
                                const uint64_t n[kK4LocalClasses]);
+// Counts the roots of the work items a.items[0 .. n_items) (whole roots of
+// class k, any request slots as tags) into a.acc[tag - tag_base].
+eh_status launch_4cliques_local_items(Ctx* c, hipStream_t s, const LaunchArgs& a, int k);
 // Sizes and allocates the HBM S lists of a 4-clique launch over `items` when
 // a root's out-degree exceeds kK4ListMax (nothing otherwise): one list of
 // the largest such out-degree per wave, at most 4 waves per compute unit.

@@ -1094,7 +1094,11 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
 // and per row the streamed part of N+(v_i) as a segment record, so a root
 // costs one dependent load before its members and records arrive.  Blocks
 // of WPB waves take the roots, each with 3 <= d <= DMAX.
-template <int WPB, int RW, int DMAX, int U>
+// kItems (rooted requests of a server): the roots are the work items a.items
+// (root s, request slot tag), each count added to a.acc[tag - tag_base]; the
+// window, plen and the streamed sets are found from the trie on the fly
+// (elements beyond max N+(u) and words outside the window simply miss).
+template <int WPB, int RW, int DMAX, int U, bool kItems>
 __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
   constexpr uint32_t W = DMAX / 32;       // words per row
   constexpr uint32_t RS = W + 1;          // row stride: rows start in different banks
@@ -1105,31 +1109,62 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
   __shared__ uint32_t s_m[DMAX * RS];     // rows T_i
   __shared__ uint32_t s_pre[WPB][kSeg + 1];
   __shared__ uint2 s_seg[WPB][kSeg];
+  __shared__ uint32_t s_plen;
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
   const SegTab T{s_pre[wid], s_seg[wid]};
   const uint32_t* __restrict__ L = a.col;
   for (uint32_t k = tid; k < uint32_t(RW); k += NT) s_a[k] = 0;
   for (uint32_t k = tid; k < DMAX * RS; k += NT) s_m[k] = 0;
+  if (tid == 0) s_plen = 0;
   __syncthreads();
   unsigned long long acc = 0;
   // roots come by decreasing estimated cost; block b takes b, 2G-1-b, 2G+b,
   // 4G-1-b, ... (G blocks), so that every block's share costs about the same
   const uint64_t G = gridDim.x;
+  const uint64_t n_roots = kItems ? a.n_items : a.n_roots;
   for (uint64_t k = 0;; ++k) {
     const uint64_t r = k * G + ((k & 1) ? G - 1 - blockIdx.x : blockIdx.x);
-    if (r >= a.n_roots) break;
-    const uint4 rr = a.roots[r];
-    const uint32_t beg = rr.x, d = rr.y & 1023u, plen = (rr.y >> 10) & 1023u, nw = rr.y >> 20;
-    const uint32_t roff = rr.z, wb = rr.w;
-    // the first batch of segment records is loaded beside the members
+    if (r >= n_roots) break;
+    uint32_t beg, d, plen, nw, roff = 0, wb, tag = 0;
     uint2 rc0{0, 0};
-    if (tid < min(uint32_t(kSeg), d - 1)) rc0 = a.rec[roff + tid];
-    for (uint32_t k = tid; k < d; k += NT) {
-      const uint32_t x = L[beg + k];
-      s_u[k] = x;
-      if (k >= plen) atomicOr(&s_a[(x - wb) >> 5], 1u << ((x - wb) & 31));
+    if constexpr (kItems) {
+      const Item it = a.items[r];
+      tag = it.tag;
+      const uint2 ud = a.vdesc[it.s];
+      beg = ud.x;
+      d = ud.y & kMaxIndex;
+      const uint32_t lo = L[beg], hi = L[beg + d - 1];
+      // window base: a multiple of 32 with hi - wb < 32 RW, as low as possible
+      wb = hi - (lo & ~31u) < uint32_t(RW) * 32u ? (lo & ~31u)
+                                                 : ((hi + 1u - uint32_t(RW) * 32u + 31u) & ~31u);
+      nw = ((hi - wb) >> 5) + 1;
+      for (uint32_t k = tid; k < d; k += NT) {
+        const uint32_t x = L[beg + k];
+        s_u[k] = x;
+        if (x >= wb) {
+          atomicOr(&s_a[(x - wb) >> 5], 1u << ((x - wb) & 31));
+          if (k == 0 || L[beg + k - 1] < wb) s_plen = k;
+        }
+      }
+      __syncthreads();
+      plen = s_plen;
+    } else {
+      const uint4 rr = a.roots[r];
+      beg = rr.x;
+      d = rr.y & 1023u;
+      plen = (rr.y >> 10) & 1023u;
+      nw = rr.y >> 20;
+      roff = rr.z;
+      wb = rr.w;
+      // the first batch of segment records is loaded beside the members
+      if (tid < min(uint32_t(kSeg), d - 1)) rc0 = a.rec[roff + tid];
+      for (uint32_t k = tid; k < d; k += NT) {
+        const uint32_t x = L[beg + k];
+        s_u[k] = x;
+        if (k >= plen) atomicOr(&s_a[(x - wb) >> 5], 1u << ((x - wb) & 31));
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (wid == 0) {
       // s_p[w]: window members in words [0, w), lane l summing a run of words
       const uint32_t per = (nw + kWave - 1) / kWave, w0 = lane * per, w1 = min(w0 + per, nw);
@@ -1148,8 +1183,15 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
       const uint32_t nseg = min(uint32_t(kSeg), d - 1 - b0);
       Seg g{0, 0, kNoWords};
       if (lane < nseg) {
-        const uint2 rc = b0 == 0 ? rc0 : a.rec[roff + b0 + lane];
-        g = Seg{rc.x, rc.y & 0x3FFFFFu, (rc.y & kHiBit) ? int32_t((rc.y >> 22) & 0x1FFu) : kNoWords};
+        if constexpr (kItems) {
+          // a row below the window streams words only from a bitset inside it
+          const WordRule wr{a.use_bitsets != 0, wb, b0 + lane < plen ? wb : 0u};
+          g = seg_full<true>(a, s_u[b0 + lane], wr);
+        } else {
+          const uint2 rc = b0 == 0 ? rc0 : a.rec[roff + b0 + lane];
+          g = Seg{rc.x, rc.y & 0x3FFFFFu,
+                  (rc.y & kHiBit) ? int32_t((rc.y >> 22) & 0x1FFu) : kNoWords};
+        }
       }
       const uint32_t E = publish_segments(T, g, lane);
       // an element x tests bit x - wb; a bitset word (key: its index from
@@ -1275,14 +1317,22 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
         }
       }
     }
-    acc += cnt;
+    if constexpr (kItems) {
+      const unsigned long long tot = wave_sum((unsigned long long)cnt);
+      if (lane == 0 && tot) atomicAdd(&a.acc[tag - a.tag_base], tot);
+    } else {
+      acc += cnt;
+    }
     __syncthreads();
     for (uint32_t k = tid; k < d * RS; k += NT) s_m[k] = 0;
     for (uint32_t k = plen + tid; k < d; k += NT) s_a[(s_u[k] - wb) >> 5] = 0;
+    if (kItems && tid == 0) s_plen = 0;
     __syncthreads();
   }
-  const unsigned long long tot = wave_sum(acc);
-  if (lane == 0 && tot) atomicAdd(&a.acc[0], tot);
+  if constexpr (!kItems) {
+    const unsigned long long tot = wave_sum(acc);
+    if (lane == 0 && tot) atomicAdd(&a.acc[0], tot);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1523,6 +1573,23 @@ eh_status launch_lollipop(Ctx* c, hipStream_t s, const LaunchArgs& la, uint32_t 
   return hip_check(c, hipGetLastError(), "Lollipop kernel launch");
 }
 
+eh_status launch_4cliques_local_items(Ctx* c, hipStream_t s, const LaunchArgs& la, int k) {
+  if (la.n_items == 0) return EH_OK;
+  static constexpr uint32_t kPerCu[kK4LocalClasses] = {32, 28, 9, 3};
+  const DevArgs d = to_dev(la);
+  const uint32_t grid = uint32_t(std::min<uint64_t>(la.n_items, uint64_t(c->n_cu) * kPerCu[k]));
+  constexpr int RW = int(kK4LocalWords);
+  if (k == 0)
+    hipLaunchKernelGGL((k_k4_local<1, RW / 2, 64, 8, true>), dim3(grid), dim3(kWave), 0, s, d);
+  else if (k == 1)
+    hipLaunchKernelGGL((k_k4_local<1, RW / 2, 128, 8, true>), dim3(grid), dim3(kWave), 0, s, d);
+  else if (k == 2)
+    hipLaunchKernelGGL((k_k4_local<4, RW, 256, 8, true>), dim3(grid), dim3(4 * kWave), 0, s, d);
+  else
+    hipLaunchKernelGGL((k_k4_local<8, RW, 512, 8, true>), dim3(grid), dim3(8 * kWave), 0, s, d);
+  return hip_check(c, hipGetLastError(), "induced-neighbourhood 4-clique launch (items)");
+}
+
 eh_status launch_4cliques_local(Ctx* c, hipStream_t s, const LaunchArgs& la,
                                const uint64_t n[kK4LocalClasses]) {
   // blocks per CU as the LDS allows: one wave per root at out-degree <= 64
@@ -1556,13 +1623,13 @@ eh_status launch_4cliques_local(Ctx* c, hipStream_t s, const LaunchArgs& la,
                   RW == int(k4_local_window(2)) && RW == int(k4_local_window(3)),
                   "the planner's windows are the kernels'");
     if (k == 0)
-      hipLaunchKernelGGL((k_k4_local<1, RW / 2, 64, 8>), dim3(grid), dim3(kWave), 0, ks, d);
+      hipLaunchKernelGGL((k_k4_local<1, RW / 2, 64, 8, false>), dim3(grid), dim3(kWave), 0, ks, d);
     else if (k == 1)
-      hipLaunchKernelGGL((k_k4_local<1, RW / 2, 128, 8>), dim3(grid), dim3(kWave), 0, ks, d);
+      hipLaunchKernelGGL((k_k4_local<1, RW / 2, 128, 8, false>), dim3(grid), dim3(kWave), 0, ks, d);
     else if (k == 2)
-      hipLaunchKernelGGL((k_k4_local<4, RW, 256, 8>), dim3(grid), dim3(4 * kWave), 0, ks, d);
+      hipLaunchKernelGGL((k_k4_local<4, RW, 256, 8, false>), dim3(grid), dim3(4 * kWave), 0, ks, d);
     else
-      hipLaunchKernelGGL((k_k4_local<8, RW, 512, 8>), dim3(grid), dim3(8 * kWave), 0, ks, d);
+      hipLaunchKernelGGL((k_k4_local<8, RW, 512, 8, false>), dim3(grid), dim3(8 * kWave), 0, ks, d);
     eh_status st = hip_check(c, hipGetLastError(), "induced-neighbourhood 4-clique launch");
     if (st == EH_OK && k > 0) {
       st = hip_check(c, hipEventRecord(c->join[k - 1], ks), "join event");

@@ -49,7 +49,10 @@ struct Request {
   int pattern = 0;
   std::vector<uint32_t> roots;  // as submitted, until expanded
   std::vector<Item> items;  // tag filled at admission
-  uint32_t item_dmax = 0;   // max out-degree of an item's root
+  // 4-cliques: items[off[0] .. off[1]) go to the staged S-list kernel, and
+  // items[off[1+k] .. off[2+k]) are whole roots of induced-neighbourhood class k
+  uint64_t off[kK4LocalClasses + 2] = {};
+  uint32_t item_dmax = 0;   // max out-degree of an item's root (S-list items)
   uint64_t footprint = 0;   // bytes its items take in the arena
   uint64_t arena_off = 0;   // item index of its extent in the arena
   uint64_t next_item = 0;   // next item to dispatch
@@ -106,6 +109,7 @@ struct Server {
   uint32_t chunk = 4096;                       // item size target, fixed at creation
   uint64_t arena_items = 0;                    // the arena's capacity in items
   bool async_ok[5] = {false, false, false, false, false};  // by pattern
+  bool k4_local = false;   // 4-clique roots of out-degree <= 512 by induced neighbourhoods
 
   void run();
   bool step();
@@ -118,6 +122,8 @@ struct Server {
 
 namespace {
 
+// pattern: EH_TRIANGLE, EH_4CLIQUE (S-list kernel), or -1 - k for the
+// induced-neighbourhood 4-clique kernel of class k
 eh_status server_launch(Server* s, uint64_t n_items, uint64_t off, int pattern,
                         uint32_t item_dmax) {
   if (n_items == 0) return EH_OK;
@@ -153,6 +159,7 @@ eh_status server_launch(Server* s, uint64_t n_items, uint64_t off, int pattern,
   a.search_below = tu.search_below;
   a.symmetric = t.host.symmetric ? 1u : 0u;
   a.reverse = tu.reverse;
+  if (pattern < 0) return launch_4cliques_local_items(c, s->stream, a, -1 - pattern);
   if (pattern == EH_4CLIQUE) return launch_4cliques(c, s->stream, a, tu.kernel, tu.waves_per_cu);
   return launch_triangles(c, s->stream, a, tu.kernel, tu.waves_per_cu);
 }
@@ -195,7 +202,8 @@ bool Server::step() {
   std::vector<uint32_t> to_zero;
   std::vector<Request*> admitted;
   std::vector<uint4> tri, k4;  // pieces {first arena item, first step item, items, 0}
-  uint64_t n_tri = 0, n_k4 = 0;
+  std::vector<uint4> kl[kK4LocalClasses];  // the same for the induced-neighbourhood classes
+  uint64_t n_tri = 0, n_k4 = 0, n_kl[kK4LocalClasses] = {};
   uint32_t dmax_tri = 0, dmax_k4 = 0;
   // requests stay alive in `active` until this thread retires them
   std::vector<std::pair<Request*, uint64_t>> dispatched;
@@ -234,15 +242,24 @@ bool Server::step() {
         r->zeroed = true;
       }
       const uint64_t take = std::min<uint64_t>(budget, r->items.size() - r->next_item);
-      const bool is_k4 = r->pattern == EH_4CLIQUE;
-      auto& dst = is_k4 ? k4 : tri;
-      auto& dm = is_k4 ? dmax_k4 : dmax_tri;
-      uint64_t& filled = is_k4 ? n_k4 : n_tri;
-      if (take) {
-        dm = std::max(dm, r->item_dmax);
-        dst.push_back(make_uint4(uint32_t(r->arena_off + r->next_item), uint32_t(filled),
+      if (take && r->pattern != EH_4CLIQUE) {
+        dmax_tri = std::max(dmax_tri, r->item_dmax);
+        tri.push_back(make_uint4(uint32_t(r->arena_off + r->next_item), uint32_t(n_tri),
                                  uint32_t(take), 0u));
-        filled += take;
+        n_tri += take;
+      } else if (take) {
+        // the taken range, cut at the request's kernel regions
+        const uint64_t a0 = r->next_item, a1 = a0 + take;
+        for (uint32_t q = 0; q <= kK4LocalClasses; ++q) {
+          const uint64_t lo = std::max(a0, r->off[q]), hi = std::min(a1, r->off[q + 1]);
+          if (lo >= hi) continue;
+          auto& dst = q == 0 ? k4 : kl[q - 1];
+          uint64_t& filled = q == 0 ? n_k4 : n_kl[q - 1];
+          if (q == 0) dmax_k4 = std::max(dmax_k4, r->item_dmax);
+          dst.push_back(make_uint4(uint32_t(r->arena_off + lo), uint32_t(filled),
+                                   uint32_t(hi - lo), 0u));
+          filled += hi - lo;
+        }
       }
       r->next_item += take;
       budget -= take;
@@ -264,11 +281,19 @@ bool Server::step() {
   for (uint32_t slot : to_zero)
     if (st == EH_OK)
       st = launch_fill_u64(c, stream, static_cast<unsigned long long*>(acc_d.p) + slot, 1, 0);
-  for (uint4& pc : k4) pc.y += uint32_t(n_tri);  // the 4-clique items follow the triangles'
-  const size_t n_pieces = tri.size() + k4.size();
+  // step items: the triangles', the S-list 4-cliques', then each class's
+  uint64_t base[kK4LocalClasses + 2] = {0, n_tri};
+  for (uint32_t q = 0; q < kK4LocalClasses; ++q) base[q + 2] = base[q + 1] + (q ? n_kl[q - 1] : n_k4);
+  for (uint4& pc : k4) pc.y += uint32_t(base[1]);
+  for (uint32_t q = 0; q < kK4LocalClasses; ++q)
+    for (uint4& pc : kl[q]) pc.y += uint32_t(base[q + 2]);
+  size_t n_pieces = tri.size() + k4.size();
+  for (auto& v : kl) n_pieces += v.size();
   if (st == EH_OK && n_pieces) {
-    std::memcpy(pieces_h, tri.data(), tri.size() * sizeof(uint4));
-    std::memcpy(pieces_h + tri.size(), k4.data(), k4.size() * sizeof(uint4));
+    uint4* ph = pieces_h;
+    ph = std::copy(tri.begin(), tri.end(), ph);
+    ph = std::copy(k4.begin(), k4.end(), ph);
+    for (auto& v : kl) ph = std::copy(v.begin(), v.end(), ph);
     st = hip_check(c, hipMemcpyAsync(pieces_d.p, pieces_h, n_pieces * sizeof(uint4),
                                      hipMemcpyHostToDevice, stream), "upload step pieces");
     if (st == EH_OK)
@@ -276,7 +301,9 @@ bool Server::step() {
                                uint32_t(n_pieces), static_cast<Item*>(items_d.p));
   }
   if (st == EH_OK) st = server_launch(this, n_tri, 0, EH_TRIANGLE, dmax_tri);
-  if (st == EH_OK) st = server_launch(this, n_k4, n_tri, EH_4CLIQUE, dmax_k4);
+  if (st == EH_OK) st = server_launch(this, n_k4, base[1], EH_4CLIQUE, dmax_k4);
+  for (uint32_t q = 0; q < kK4LocalClasses; ++q)
+    if (st == EH_OK) st = server_launch(this, n_kl[q], base[q + 2], -1 - int(q), 0);
   if (st == EH_OK)
     st = hip_check(c, hipMemcpyAsync(acc_h, acc_d.p, o.max_active * sizeof(uint64_t),
                                      hipMemcpyDeviceToHost, stream), "read counters");
@@ -353,6 +380,8 @@ void Server::expand(Request& r, Dedup& d) const {
   }
   uint32_t* stamp = d.stamp.data();
   const uint32_t* row = h.row.data();
+  const bool local = k4_local && r.pattern == EH_4CLIQUE;
+  std::vector<Item> lc[kK4LocalClasses];  // whole roots by induced-neighbourhood class
   for (uint32_t i = 0; i < n_roots; ++i) {
     if (i + kAhead < n_roots) {
       __builtin_prefetch(stamp + us[i + kAhead], 1);
@@ -361,9 +390,20 @@ void Server::expand(Request& r, Dedup& d) const {
     const uint32_t u = us[i];
     if (stamp[u] == d.epoch) continue;
     stamp[u] = d.epoch;
+    const int k = local ? k4_local_class(row[u + 1] - row[u]) : -1;
+    if (k >= 0) {
+      lc[k].push_back(Item{u, row[u], row[u + 1] - row[u], 0});
+      continue;
+    }
     const size_t before = r.items.size();
     make_items_estimated(h, u, 0, chunk, uint32_t(r.pattern), r.items);
     if (r.items.size() > before) r.item_dmax = std::max(r.item_dmax, row[u + 1] - row[u]);
+  }
+  r.off[0] = 0;
+  r.off[1] = r.items.size();
+  for (uint32_t k = 0; k < kK4LocalClasses; ++k) {
+    r.items.insert(r.items.end(), lc[k].begin(), lc[k].end());
+    r.off[k + 2] = r.items.size();
   }
   r.stats.items = r.items.size();
   r.footprint = sizeof(Item) * r.items.size();
@@ -434,6 +474,7 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
   s.c = c;
   s.t = t;
   s.tune = c->tune;
+  s.k4_local = s.tune.k4_local && !t->host.symmetric;
   if (opts) s.o = *opts;
   if (!s.o.hbm_budget_bytes) s.o.hbm_budget_bytes = 2ull << 30;
   if (!s.o.max_active) s.o.max_active = 256;
@@ -463,9 +504,12 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
   }
   if (st == EH_OK) st = dev_alloc(c, s.arena, s.arena_items * sizeof(Item));
   if (st == EH_OK) s.free_ext.emplace(0, s.arena_items);
-  if (st == EH_OK) st = dev_alloc(c, s.pieces_d, sizeof(uint4) * s.o.max_active);
+  // a step takes one range of each active request, cut into at most one
+  // piece per kernel region
+  const size_t max_pieces = size_t(s.o.max_active) * (kK4LocalClasses + 1);
+  if (st == EH_OK) st = dev_alloc(c, s.pieces_d, sizeof(uint4) * max_pieces);
   if (st == EH_OK)
-    st = hip_check(c, hipHostMalloc((void**)&s.pieces_h, sizeof(uint4) * s.o.max_active,
+    st = hip_check(c, hipHostMalloc((void**)&s.pieces_h, sizeof(uint4) * max_pieces,
                                     hipHostMallocDefault), "pinned pieces");
   if (st == EH_OK)
     st = hip_check(c, hipHostMalloc((void**)&s.acc_h, sizeof(uint64_t) * s.o.max_active,

@@ -296,8 +296,11 @@ def test_async_and_repeat(ctx, eh):
         trie.free()
 
 
-def test_rooted(ctx, eh):
-    tune(ctx)
+@pytest.mark.parametrize("k4l", [1, 0])
+def test_rooted(ctx, eh, k4l):
+    """Rooted counts; 4-clique roots of out-degree <= 512 by induced
+    neighbourhoods (k4_local = 1) or all by the S-list kernel."""
+    tune(ctx, k4_local=k4l)
     el = inputs.rmat(12, 16, seed=12)
     g = oracle.Graph.from_edgelist(el)
     rt = g.triangles(rooted=True)["root"]
@@ -372,9 +375,13 @@ def test_batch_order_invariant(ctx, eh):
         t2.free()
 
 
-@pytest.mark.parametrize("policy", [0, 1])
-def test_server_alone_equals_mix(ctx, eh, policy):
-    tune(ctx)
+@pytest.mark.parametrize("policy,k4l", [(0, 1), (1, 1), (1, 0)])
+def test_server_alone_equals_mix(ctx, eh, policy, k4l):
+    """Each request alone = in the mix = the oracle's rooted count; 4-clique
+    requests' roots of out-degree <= 512 by induced neighbourhoods (k4_local
+    = 1: a request's items cut into the kernels' regions across steps) or
+    all by the S-list kernel."""
+    tune(ctx, k4_local=k4l)
     el = inputs.rmat(13, 16, seed=13)
     g = oracle.Graph.from_edgelist(el)
     roots_t = g.triangles(rooted=True)["root"]
