@@ -586,7 +586,8 @@ struct SegCursor {
 // is ANDed with the bitmap word it overlaps, both as popc(R[w] & mask).  A
 // composite set's members below its window are found by searching its prefix.
 // Group mode counts x when bit (x - base) K + k is set, k the segment's item.
-template <int RW, int U, bool kComposite, bool kGroup = false>
+// kElems: no segment of the batch is bitset words (every element a member).
+template <int RW, int U, bool kComposite, bool kGroup = false, bool kElems = false>
 __device__ __forceinline__ uint32_t flat_probe_bits(const DevArgs& a, const SegTab& T, uint32_t E,
                                                     const Staged& st, const uint32_t* R,
                                                     const uint32_t* Lp, uint32_t lane) {
@@ -619,6 +620,11 @@ __device__ __forceinline__ uint32_t flat_probe_bits(const DevArgs& a, const SegT
         if (ok[u] && d < st.glim) cnt += (R[pos >> 5] >> (pos & 31)) & 1u;
         continue;
       }
+      if (kElems) {
+        if (ok[u] && (d >> 5) < uint32_t(RW)) cnt += (R[d >> 5] >> (d & 31)) & 1u;
+        else if (kComposite && ok[u]) cnt += prefix_has(a, st, Lp, val[u]);
+        continue;
+      }
       const uint32_t w = bits[u] ? key[u] : (d >> 5);
       const uint32_t m = bits[u] ? val[u] : (1u << (d & 31));
       if (ok[u] && w < uint32_t(RW)) cnt += __popc(R[w] & m);
@@ -633,7 +639,7 @@ __device__ __forceinline__ uint32_t flat_probe_bits(const DevArgs& a, const SegT
 // with per = ceil(E / 64), finds the set of its first element by a binary
 // search of the length prefix and walks on from there, so a set boundary
 // costs one cursor step instead of a search per element.
-template <int RW, int U, bool kComposite, bool kGroup = false>
+template <int RW, int U, bool kComposite, bool kGroup = false, bool kElems = false>
 __device__ __forceinline__ uint32_t flat_probe_bits_blocked(const DevArgs& a, const SegTab& T,
                                                             uint32_t E, const Staged& st,
                                                             const uint32_t* R, const uint32_t* Lp,
@@ -672,6 +678,11 @@ __device__ __forceinline__ uint32_t flat_probe_bits_blocked(const DevArgs& a, co
         if (ok[u] && d < st.glim) cnt += (R[pos >> 5] >> (pos & 31)) & 1u;
         continue;
       }
+      if (kElems) {
+        if (ok[u] && (d >> 5) < uint32_t(RW)) cnt += (R[d >> 5] >> (d & 31)) & 1u;
+        else if (kComposite && ok[u]) cnt += prefix_has(a, st, Lp, val[u]);
+        continue;
+      }
       const uint32_t w = bits[u] ? key[u] : (d >> 5);
       const uint32_t m = bits[u] ? val[u] : (1u << (d & 31));
       if (ok[u] && w < uint32_t(RW)) cnt += __popc(R[w] & m);
@@ -683,17 +694,23 @@ __device__ __forceinline__ uint32_t flat_probe_bits_blocked(const DevArgs& a, co
 
 // nseg: segments in the table.  When they average fewer than search_below
 // elements, lanes take contiguous ranges (flat_probe_bits_blocked).
+// elems: no segment of the batch is bitset words (wave-uniform).
 template <int RW, int U>
 __device__ __forceinline__ uint32_t flat_probe(const DevArgs& a, const SegTab& T, uint32_t E,
                                                uint32_t nseg, const Staged& st, const uint32_t* R,
-                                               const uint32_t* Lp, uint32_t lane) {
+                                               const uint32_t* Lp, uint32_t lane,
+                                               bool elems = false) {
   const bool search = E < nseg * a.search_below;
   if (st.mode == kModeGroup)
     return search ? flat_probe_bits_blocked<RW, U, false, true>(a, T, E, st, R, Lp, lane)
                   : flat_probe_bits<RW, U, false, true>(a, T, E, st, R, Lp, lane);
-  if (st.mode == kModeBitmap)
+  if (st.mode == kModeBitmap) {
+    if (elems)
+      return search ? flat_probe_bits_blocked<RW, U, false, false, true>(a, T, E, st, R, Lp, lane)
+                    : flat_probe_bits<RW, U, false, false, true>(a, T, E, st, R, Lp, lane);
     return search ? flat_probe_bits_blocked<RW, U, false>(a, T, E, st, R, Lp, lane)
                   : flat_probe_bits<RW, U, false>(a, T, E, st, R, Lp, lane);
+  }
   if (st.mode == kModeComposite)
     return search ? flat_probe_bits_blocked<RW, U, true>(a, T, E, st, R, Lp, lane)
                   : flat_probe_bits<RW, U, true>(a, T, E, st, R, Lp, lane);
@@ -903,6 +920,8 @@ __device__ __forceinline__ void tri_staged(const DevArgs& a) {
           if (kLollipop) wt = a.vdesc[t].y & kMaxIndex;
         }
       }
+      // a batch with no bitset words takes the element-only walk
+      const bool elems = __ballot(lane < nseg && g.sm != kNoWords) == 0;
       const uint32_t E = publish_segments(T, g, lane);
       if constexpr (kLollipop) {
         // the previous batch's readers finished before publish_segments
@@ -910,7 +929,7 @@ __device__ __forceinline__ void tri_staged(const DevArgs& a) {
         wave_sync();
         cnt += flat_probe_weighted<RW, U>(a, T, s_wt[wid], E, st, R, Lp, lane, acc);
       } else {
-        cnt += flat_probe<RW, U>(a, T, E, nseg, st, R, Lp, lane);
+        cnt += flat_probe<RW, U>(a, T, E, nseg, st, R, Lp, lane, elems);
       }
     }
     if constexpr (kLollipop) acc += static_cast<unsigned long long>(cnt) * st.len;
