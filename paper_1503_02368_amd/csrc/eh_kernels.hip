@@ -711,9 +711,14 @@ __device__ __forceinline__ uint32_t flat_probe(const DevArgs& a, const SegTab& T
     return search ? flat_probe_bits_blocked<RW, U, false>(a, T, E, st, R, Lp, lane)
                   : flat_probe_bits<RW, U, false>(a, T, E, st, R, Lp, lane);
   }
-  if (st.mode == kModeComposite)
+  if (st.mode == kModeComposite) {
+    // (the eight-element instance would spill with a fourth walk variant)
+    if (U <= 4 && elems)
+      return search ? flat_probe_bits_blocked<RW, U, true, false, true>(a, T, E, st, R, Lp, lane)
+                    : flat_probe_bits<RW, U, true, false, true>(a, T, E, st, R, Lp, lane);
     return search ? flat_probe_bits_blocked<RW, U, true>(a, T, E, st, R, Lp, lane)
                   : flat_probe_bits<RW, U, true>(a, T, E, st, R, Lp, lane);
+  }
   const uint32_t* __restrict__ L = a.col;
   uint32_t cnt = 0;
   SegCursor c(T);
