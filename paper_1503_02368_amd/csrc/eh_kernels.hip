@@ -1247,7 +1247,24 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
           if (j < plen && s_u[j] == val) atomicOr(&R[j >> 5], 1u << (j & 31));
         }
       };
-      if (E < nseg * a.search_below) {
+      // a batch with no bitset words takes element-only walks
+      const bool elems = __ballot(lane < nseg && g.sm != kNoWords) == 0;
+      auto take_elem = [&](uint32_t val, uint32_t row) {
+        const uint32_t dx = val - wb;
+        uint32_t* R = s_m + row * RS;
+        if ((dx >> 5) < nw) {
+          const uint32_t aw = s_a[dx >> 5];
+          if ((aw >> (dx & 31)) & 1u) {
+            const uint32_t j = plen + s_p[dx >> 5] + __popc(aw & ((1u << (dx & 31)) - 1u));
+            atomicOr(&R[j >> 5], 1u << (j & 31));
+          }
+        } else if (plen && val < wb) {
+          const uint32_t j = lower_bound_lds(s_u, plen, val);
+          if (j < plen && s_u[j] == val) atomicOr(&R[j >> 5], 1u << (j & 31));
+        }
+      };
+      const bool blocked = E < nseg * a.search_below;
+      if (blocked) {
         // short sets: lane l walks the contiguous flat range [l per, (l+1) per)
         const uint32_t per = (E + kWave - 1) / kWave;
         const uint32_t f_beg = lane * per, f_end = min(f_beg + per, E);
@@ -1264,12 +1281,15 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
               if (f < f_end) {
                 c.seek(T, f);
                 val[q] = L[c.base + f];
-                info[q] = pack(c, f);
+                info[q] = elems ? b0 + c.j : pack(c, f);
               }
             }
 #pragma unroll
-            for (int q = 0; q < U; ++q)
-              if (info[q] != kNone) take(val[q], info[q]);
+            for (int q = 0; q < U; ++q) {
+              if (info[q] == kNone) continue;
+              if (elems) take_elem(val[q], info[q]);
+              else take(val[q], info[q]);
+            }
           }
         }
       } else {
@@ -1284,44 +1304,25 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
             if (f < E) {
               c.seek(T, f);
               val[q] = L[c.base + f];
-              info[q] = pack(c, f);
+              info[q] = elems ? b0 + c.j : pack(c, f);
             }
           }
 #pragma unroll
-          for (int q = 0; q < U; ++q)
-            if (info[q] != kNone) take(val[q], info[q]);
+          for (int q = 0; q < U; ++q) {
+            if (info[q] == kNone) continue;
+            if (elems) take_elem(val[q], info[q]);
+            else take(val[q], info[q]);
+          }
         }
       }
     }
     __syncthreads();
-    // sum over rows i and members j of T_i of |T_i & T_j| (rows i <= d-3: a
-    // pair needs two later members); T_j's bits lie above j, so only the
-    // words from j's on are ANDed
+    // sum over rows i and members j of T_i of |T_i & T_j|, one row per lane
+    // (rows i <= d-3: a pair needs two later members); T_j's bits lie above
+    // j, so only the words from j's on are ANDed
     uint32_t cnt = 0;
     const uint32_t wd = (d + 31) >> 5;  // words that can hold a member
-    if constexpr (W > 4) {
-      // W lanes per row, lane v taking word v: the members j of T_i in words
-      // up to v, each adding |T_i & T_j| within word v (nothing when T_i's
-      // word v is empty), so a long row is spread over W lanes
-      constexpr uint32_t RPW = kWave / W;
-      const uint32_t v = lane % W, sub = lane / W;
-      for (uint32_t i0 = wid * RPW; i0 + 2 < d; i0 += NT / W) {
-        const uint32_t i = i0 + sub;
-        if (i + 2 >= d || v >= wd) continue;
-        const uint32_t* Ti = s_m + i * RS;
-        const uint32_t tv = Ti[v];
-        if (!tv) continue;
-        for (uint32_t w = (i + 1) >> 5; w <= v; ++w) {
-          uint32_t bm = Ti[w];
-          while (bm) {
-            const uint32_t j = w * 32u + uint32_t(__builtin_ctz(bm));
-            bm &= bm - 1u;
-            cnt += __popc(tv & s_m[j * RS + v]);
-          }
-        }
-      }
-    }
-    for (uint32_t i = wid * kWave + lane; W <= 4 && i + 2 < d; i += NT) {
+    for (uint32_t i = wid * kWave + lane; i + 2 < d; i += NT) {
       const uint32_t* Ti = s_m + i * RS;
       if constexpr (W <= 4) {
         // short rows: T_i in registers
@@ -1337,6 +1338,17 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
             const uint32_t* Tj = s_m + j * RS;
 #pragma unroll
             for (uint32_t v = w; v < W; ++v) cnt += __popc(t[v] & Tj[v]);
+          }
+        }
+      } else {
+        // longer rows: walked word by word from LDS
+        for (uint32_t w = (i + 1) >> 5; w < wd; ++w) {
+          uint32_t bm = Ti[w];
+          while (bm) {
+            const uint32_t j = w * 32u + uint32_t(__builtin_ctz(bm));
+            bm &= bm - 1u;
+            const uint32_t* Tj = s_m + j * RS;
+            for (uint32_t v = w; v < wd; ++v) cnt += __popc(Ti[v] & Tj[v]);
           }
         }
       }
