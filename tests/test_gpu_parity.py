@@ -1165,6 +1165,39 @@ def test_graph_capture_replay(ctx, eh):
         gt.free()
 
 
+def test_graph_capture_replay_4cliques(ctx, eh):
+    """A 4-clique count whose roots run on the induced-neighbourhood kernels
+    (four launches, three on side streams forked from the captured stream and
+    joined back by events) and on the S-list kernel is captured and replayed;
+    every replay, with eager 4-clique counts on the same streams in between,
+    adds the oracle's count."""
+    import torch
+    tune(ctx, k4_local=1, staging=1, dynamic=4, grab=2)
+    el = inputs.disjoint_union(inputs.complete(600), inputs.rmat(13, 16, seed=23))
+    K = oracle.Graph.from_edgelist(el).count(4)
+    gt = ctx.build_edgelist(el)
+    try:
+        out = torch.zeros(1, dtype=torch.int64, device="cuda")
+        s = ctx.stream
+        s.wait_stream(torch.cuda.current_stream())
+        ctx.count_add_async(gt, eh.CLIQUE4, out)
+        torch.cuda.synchronize()
+        assert int(out.cpu().numpy().view(np.uint64)[0]) == K
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            ctx.count_add_async(gt, eh.CLIQUE4, out)
+        out.zero_()
+        torch.cuda.synchronize()
+        for rep in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            assert int(out.cpu().numpy().view(np.uint64)[0]) == (rep + 1) * K
+            assert ctx.count_4cliques(gt) == K
+        del g
+    finally:
+        gt.free()
+
+
 def test_randomized_parity(ctx, eh):
     """Seeded random graphs (R-MAT, G(n,p), Chung-Lu, unions, messy input)
     under seeded random settings of every tuning knob: each triangle and
