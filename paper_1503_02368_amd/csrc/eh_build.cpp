@@ -674,100 +674,6 @@ Plan* find_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging) {
   return nullptr;
 }
 
-// Roots and segment records of the induced-neighbourhood 4-clique kernel.
-// Roots are grouped by out-degree class, each class by decreasing estimated
-// cost (members streamed at the first level plus the square of the
-// out-degree for the pairs of the second).  Per root, a record
-// {position of N+(u), d | plen << 10 | nw << 20, first segment record,
-// window base wb}: the kernel's bitmap covers the nw words from wb (the top
-// window when N+(u) spans more than the class's window, else from its
-// minimum rounded down to a multiple of 32), and the plen members below wb
-// are searched.  Per row i < d-1 (v_i = member i), the part of N+(v_i) that
-// can meet N+(u) -- members up to max N+(u) -- as {start, length | word offset
-// << 22 | kHiBit}: its bitset words from wb's word on when fewer (and, for a
-// row below the window, only when the bitset starts inside it), else its
-// members.
-eh_status plan_k4_local(Ctx* c, const HostTrie& h, bool ub, Plan& plan) {
-  std::vector<uint64_t> cost(h.n, 0);
-  run_parts(weighted_parts(h.row, h.n, plan_threads(h.m)), [&](uint64_t u0, uint64_t u1, unsigned) {
-    for (uint64_t u = u0; u < u1; ++u) {
-      if (local_class(h, uint32_t(u)) < 0) continue;
-      uint64_t w = uint64_t(out_deg(h, uint32_t(u))) * out_deg(h, uint32_t(u));
-      for (uint32_t e = h.row[u]; e < h.row[u + 1]; ++e) w += out_deg(h, h.col[e]);
-      cost[u] = w;
-    }
-  });
-  std::vector<std::pair<uint64_t, uint32_t>> cls[kK4LocalClasses];
-  for (uint32_t u = 0; u < h.n; ++u) {
-    const int k = local_class(h, u);
-    if (k >= 0) cls[k].emplace_back(cost[u], u);
-  }
-  std::vector<uint32_t> roots;
-  std::vector<uint32_t> rw;  // window words of each root's class
-  for (uint32_t k = 0; k < kK4LocalClasses; ++k) {
-    std::stable_sort(cls[k].begin(), cls[k].end(),
-                     [](const auto& x, const auto& y) { return x.first > y.first; });
-    for (const auto& e : cls[k]) {
-      roots.push_back(e.second);
-      rw.push_back(k4_local_window(k));
-    }
-    plan.k4l_n[k] = cls[k].size();
-  }
-  if (roots.empty()) return EH_OK;
-  std::vector<uint64_t> roff(roots.size() + 1, 0);
-  for (size_t r = 0; r < roots.size(); ++r) roff[r + 1] = roff[r] + out_deg(h, roots[r]) - 1;
-  if (roff.back() > 0xFFFFFFFFull) {
-    c->err = "4-clique segment records beyond 2^32";
-    return EH_EOVERFLOW;
-  }
-  std::vector<uint4> rr(roots.size());
-  std::vector<uint2> rec(roff.back());
-  std::atomic<bool> long_set{false};
-  run_parts(even_parts(roots.size(), plan_threads(roff.back())),
-            [&](uint64_t r0, uint64_t r1, unsigned) {
-    for (uint64_t r = r0; r < r1; ++r) {
-      const uint32_t u = roots[r], d = out_deg(h, u), W = rw[r];
-      const uint32_t* nu = h.col.data() + h.row[u];
-      const uint32_t lo = nu[0], hi = nu[d - 1];
-      const uint32_t wb = hi - (lo & ~31u) < W * 32u ? (lo & ~31u) : ((hi + 1u - W * 32u + 31u) & ~31u);
-      const uint32_t plen = uint32_t(std::lower_bound(nu, nu + d, wb) - nu);
-      const uint32_t nw = ((hi - wb) >> 5) + 1;
-      rr[r] = make_uint4(h.row[u], d | (plen << 10) | (nw << 20), uint32_t(roff[r]), wb);
-      for (uint32_t i = 0; i + 1 < d; ++i) {
-        const uint32_t v = nu[i];
-        const uint32_t* nv = h.col.data() + h.row[v];
-        const uint32_t len = uint32_t(std::upper_bound(nv, nv + out_deg(h, v), hi) - nv);
-        uint2 g = make_uint2(h.row[v], len);
-        if (ub && len && h.bs_off[v] != kNoBitset && h.bs_base[v] >= wb) {
-          // words from the bitset's first (inside the window) to max N+(u)'s
-          const uint32_t base = h.bs_base[v];
-          const uint32_t words = std::min(h.bs_nw[v], ((hi - base) >> 5) + 1);
-          if (words < len)
-            g = make_uint2(uint32_t(h.m) + h.bs_off[v],
-                           words | (((base - wb) >> 5) << 22) | kHiBit);
-        }
-        if (!(g.y & kHiBit) && len >= (1u << 22)) long_set = true;
-        rec[roff[r] + i] = g;
-      }
-    }
-  });
-  if (long_set) {
-    c->err = "a streamed set of 2^22 or more members in a 4-clique plan";
-    return EH_EOVERFLOW;
-  }
-  eh_status st;
-  if ((st = dev_alloc(c, plan.k4l, sizeof(uint4) * rr.size())) != EH_OK ||
-      (st = hip_check(c, hipMemcpy(plan.k4l.p, rr.data(), sizeof(uint4) * rr.size(),
-                                   hipMemcpyHostToDevice), "upload 4-clique roots")) != EH_OK)
-    return st;
-  if ((st = dev_alloc(c, plan.rec, sizeof(uint2) * std::max<size_t>(rec.size(), 1))) != EH_OK)
-    return st;
-  if (!rec.empty())
-    st = hip_check(c, hipMemcpy(plan.rec.p, rec.data(), sizeof(uint2) * rec.size(),
-                                hipMemcpyHostToDevice), "upload 4-clique segment records");
-  return st;
-}
-
 eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** out) {
   const Tuning& tu = c->tune;
   const uint32_t chunk = std::max<uint32_t>(tu.chunk_work, 64);
@@ -1093,7 +999,7 @@ eh_status get_plan(Ctx* c, Trie* t, uint32_t pattern, uint32_t staging, Plan** o
       dev_free(c, plan->k4s);
       return st;
     }
-  if (plan->k4_local && (st = plan_k4_local(c, h, ub, *plan)) != EH_OK) {
+  if (plan->k4_local && (st = device_plan_k4_local(c, *t, *plan, ub)) != EH_OK) {
     free_plan(c, *plan);
     return st;
   }

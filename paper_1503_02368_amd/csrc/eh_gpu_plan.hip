@@ -720,4 +720,176 @@ eh_status device_plan_target(Ctx* c, Trie& tr, Plan& plan, uint32_t chunk, bool 
   return EH_OK;
 }
 
+namespace {
+
+// Sort key of vertex u for the induced-neighbourhood 4-clique plan: class
+// (out-degree <= 64, 128, 256, 512), then decreasing estimated cost
+// (d^2 + sum of the out-degrees of N+(u), clamped to 28 bits), then u; all
+// ones when u is not such a root.  counts[k] counts class k's roots.
+__global__ void __launch_bounds__(kB) k_k4l_keys(TrieView t, unsigned long long* __restrict__ key,
+                                                 unsigned long long* __restrict__ counts) {
+  constexpr uint64_t kCostMax = (1ull << 28) - 1;
+  for (uint64_t u = gtid(); u < t.n; u += gstride()) {
+    const uint2 ud = t.vdesc[u];
+    const uint32_t d = ud.y & kMaxIndex;
+    const int k = k4_local_class(d);
+    if (k < 0) {
+      key[u] = ~0ull;
+      continue;
+    }
+    uint64_t cost = uint64_t(d) * d;
+    for (uint32_t e = ud.x; e < ud.x + d && cost < kCostMax; ++e) cost += outdeg(t, t.col[e]);
+    cost = cost < kCostMax ? cost : kCostMax;
+    key[u] = (uint64_t(k) << 60) | ((kCostMax - cost) << 32) | u;
+    atomicAdd(&counts[k], 1ull);
+  }
+}
+
+// Rows (d - 1) of each root, in sorted order.
+__global__ void __launch_bounds__(kB) k_k4l_rows(TrieView t, const unsigned long long* __restrict__ key,
+                                                 uint64_t n_roots, uint32_t* __restrict__ rows) {
+  for (uint64_t r = gtid(); r < n_roots; r += gstride())
+    rows[r] = outdeg(t, uint32_t(key[r] & 0xFFFFFFFFull)) - 1;
+}
+
+__device__ inline uint32_t lower_bound_g(const uint32_t* a, uint32_t n, uint32_t x) {
+  uint32_t lo = 0;
+  while (n) {
+    const uint32_t h = n >> 1;
+    if (a[lo + h] < x) { lo += h + 1; n -= h + 1; } else n = h;
+  }
+  return lo;
+}
+
+// One wave per root: the root record {position of N+(u), d | plen << 10 |
+// nw << 20, first row record, window base} and, per row i < d - 1, the part
+// of N+(v_i) up to max N+(u) as elements, or as the bitset's words when fewer
+// (only from a bitset starting inside the window), {start, length | word
+// offset << 22 | kHiBit for words}.  long_set: a row of 2^22 or more members.
+__global__ void __launch_bounds__(kB) k_k4l_records(TrieView t, const unsigned long long* __restrict__ key,
+                                                    const uint32_t* __restrict__ roff, uint64_t n_roots,
+                                                    uint32_t ub, uint4* __restrict__ roots,
+                                                    uint2* __restrict__ rec,
+                                                    unsigned long long* __restrict__ long_set) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t wave = gtid() >> 6, waves = gstride() >> 6;
+  for (uint64_t r = wave; r < n_roots; r += waves) {
+    const uint32_t u = uint32_t(key[r] & 0xFFFFFFFFull);
+    const int k = int(key[r] >> 60);
+    const uint2 ud = t.vdesc[u];
+    const uint32_t d = ud.y & kMaxIndex, W = k4_local_window(k);
+    const uint32_t* nu = t.col + ud.x;
+    const uint32_t lo = nu[0], hi = nu[d - 1];
+    const uint32_t wb = hi - (lo & ~31u) < W * 32u ? (lo & ~31u) : ((hi + 1u - W * 32u + 31u) & ~31u);
+    const uint32_t plen = lower_bound_g(nu, d, wb);
+    const uint32_t nw = ((hi - wb) >> 5) + 1;
+    if (lane == 0) roots[r] = make_uint4(ud.x, d | (plen << 10) | (nw << 20), roff[r], wb);
+    for (uint32_t i = lane; i + 1 < d; i += 64) {
+      const uint32_t v = nu[i];
+      const uint2 vd = t.vdesc[v];
+      const uint32_t dv = vd.y & kMaxIndex;
+      const uint32_t* nv = t.col + vd.x;
+      // members up to hi
+      uint32_t len = lower_bound_g(nv, dv, hi);
+      if (len < dv && nv[len] == hi) ++len;
+      uint2 g = make_uint2(vd.x, len);
+      if (ub && len && (vd.y & kHiBit)) {
+        const uint4 b = t.bsdesc[v];
+        if (b.y >= wb) {
+          const uint32_t words = min(b.z, ((hi - b.y) >> 5) + 1);
+          if (words < len) g = make_uint2(b.x, words | (((b.y - wb) >> 5) << 22) | kHiBit);
+        }
+      }
+      if (!(g.y & kHiBit) && len >= (1u << 22)) atomicAdd(long_set, 1ull);
+      rec[roff[r] + i] = g;
+    }
+  }
+}
+
+}  // namespace
+
+eh_status device_plan_k4_local(Ctx* c, Trie& tr, Plan& plan, bool ub) {
+  const HostTrie& h = tr.host;
+  const uint32_t n = h.n;
+  if (n == 0) return EH_OK;
+  hipStream_t s = c->stream;
+  TrieView tv{static_cast<const uint2*>(tr.vdesc.p), static_cast<const uint32_t*>(tr.col.p),
+              h.n_bs ? static_cast<const uint4*>(tr.bsdesc.p) : nullptr, n};
+  auto chk = [&](hipError_t e, const char* what) { return hip_check(c, e, what); };
+  Scratch sc(c);
+  DevBuf key_a, key_b, small, rows, roff, tmp;
+  eh_status st;
+  if ((st = sc.get(key_a, 8ull * n)) != EH_OK || (st = sc.get(key_b, 8ull * n)) != EH_OK ||
+      (st = sc.get(small, 64)) != EH_OK)
+    return st;
+  hipLaunchKernelGGL(k_fill_u32_plan, dim3(1), dim3(kB), 0, s, ptr<uint32_t>(small), 16, 0u);
+  hipLaunchKernelGGL(k_k4l_keys, dim3(grid_of(n)), dim3(kB), 0, s, tv, ptr<unsigned long long>(key_a),
+                     ptr<unsigned long long>(small));
+  rocprim::double_buffer<unsigned long long> db(ptr<unsigned long long>(key_a),
+                                                ptr<unsigned long long>(key_b));
+  size_t tb = 0;
+  if ((st = chk(rocprim::radix_sort_keys(nullptr, tb, db, size_t(n), 0, 64, s), "sort size")) !=
+      EH_OK)
+    return st;
+  size_t ts = 0;
+  if ((st = chk(rocprim::exclusive_scan(nullptr, ts, ptr<uint32_t>(key_a), ptr<uint32_t>(key_b),
+                                        0u, size_t(n), rocprim::plus<uint32_t>(), s),
+                "scan size")) != EH_OK)
+    return st;
+  if ((st = sc.get(tmp, std::max(tb, ts))) != EH_OK) return st;
+  tb = tmp.bytes;
+  if ((st = chk(rocprim::radix_sort_keys(tmp.p, tb, db, size_t(n), 0, 64, s), "root sort")) !=
+      EH_OK)
+    return st;
+  unsigned long long counts[kK4LocalClasses + 1] = {};
+  if ((st = chk(hipMemcpyAsync(counts, small.p, sizeof(counts), hipMemcpyDeviceToHost, s),
+                "read root classes")) != EH_OK ||
+      (st = chk(hipStreamSynchronize(s), "root sync")) != EH_OK)
+    return st;
+  uint64_t n_roots = 0;
+  for (uint32_t k = 0; k < kK4LocalClasses; ++k) {
+    plan.k4l_n[k] = counts[k];
+    n_roots += counts[k];
+  }
+  if (n_roots == 0) return EH_OK;
+  const unsigned long long* sorted = db.current();
+  if ((st = sc.get(rows, 4 * n_roots)) != EH_OK || (st = sc.get(roff, 4 * n_roots)) != EH_OK)
+    return st;
+  hipLaunchKernelGGL(k_k4l_rows, dim3(grid_of(n_roots)), dim3(kB), 0, s, tv, sorted, n_roots,
+                     ptr<uint32_t>(rows));
+  ts = tmp.bytes;
+  if ((st = chk(rocprim::exclusive_scan(tmp.p, ts, ptr<uint32_t>(rows), ptr<uint32_t>(roff), 0u,
+                                        size_t(n_roots), rocprim::plus<uint32_t>(), s),
+                "row scan")) != EH_OK)
+    return st;
+  uint32_t last[2] = {0, 0};
+  if ((st = chk(hipMemcpyAsync(&last[0], ptr<uint32_t>(roff) + n_roots - 1, 4,
+                               hipMemcpyDeviceToHost, s), "read rows")) != EH_OK ||
+      (st = chk(hipMemcpyAsync(&last[1], ptr<uint32_t>(rows) + n_roots - 1, 4,
+                               hipMemcpyDeviceToHost, s), "read rows")) != EH_OK ||
+      (st = chk(hipStreamSynchronize(s), "rows sync")) != EH_OK)
+    return st;
+  const uint64_t n_rec = uint64_t(last[0]) + last[1];
+  if ((st = dev_alloc(c, plan.k4l, sizeof(uint4) * n_roots)) != EH_OK) return st;
+  if ((st = dev_alloc(c, plan.rec, sizeof(uint2) * std::max<uint64_t>(n_rec, 1))) != EH_OK)
+    return st;
+  hipLaunchKernelGGL(k_fill_u32_plan, dim3(1), dim3(kB), 0, s, ptr<uint32_t>(small), 16, 0u);
+  const uint64_t blocks = std::min<uint64_t>((n_roots + kB / 64 - 1) / (kB / 64), 1u << 16);
+  hipLaunchKernelGGL(k_k4l_records, dim3(uint32_t(blocks)), dim3(kB), 0, s, tv, sorted,
+                     ptr<uint32_t>(roff), n_roots, ub ? 1u : 0u,
+                     static_cast<uint4*>(plan.k4l.p), static_cast<uint2*>(plan.rec.p),
+                     ptr<unsigned long long>(small));
+  unsigned long long long_set = 0;
+  if ((st = chk(hipGetLastError(), "4-clique plan kernels")) != EH_OK ||
+      (st = chk(hipMemcpyAsync(&long_set, small.p, 8, hipMemcpyDeviceToHost, s),
+                "read plan flag")) != EH_OK ||
+      (st = chk(hipStreamSynchronize(s), "plan sync")) != EH_OK)
+    return st;
+  if (long_set) {
+    c->err = "a streamed set of 2^22 or more members in a 4-clique plan";
+    return EH_EOVERFLOW;
+  }
+  return EH_OK;
+}
+
 }  // namespace eh

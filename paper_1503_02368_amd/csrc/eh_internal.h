@@ -335,7 +335,7 @@ constexpr uint32_t kK4LocalMax = 512;
 constexpr uint32_t kK4LocalWords = 512;
 constexpr uint32_t kK4LocalClasses = 4;
 static_assert(Ctx::kSide + 1 >= int(kK4LocalClasses), "a side stream per further class");
-inline int k4_local_class(uint32_t d) {
+constexpr int k4_local_class(uint32_t d) {
   if (d < 3 || d > kK4LocalMax) return -1;
   return d <= 64 ? 0 : d <= 128 ? 1 : d <= 256 ? 2 : 3;
 }
@@ -349,6 +349,10 @@ eh_status launch_4cliques_local(Ctx* c, hipStream_t s, const LaunchArgs& a,
 // Counts the roots of the work items a.items[0 .. n_items) (whole roots of
 // class k, any request slots as tags) into a.acc[tag - tag_base].
 eh_status launch_4cliques_local_items(Ctx* c, hipStream_t s, const LaunchArgs& a, int k);
+// The induced-neighbourhood 4-clique plan of a pruned single-graph trie,
+// built on the GPU: plan.k4l (root records, by class and decreasing cost),
+// plan.k4l_n and plan.rec (row records).
+eh_status device_plan_k4_local(Ctx* c, Trie& tr, Plan& plan, bool ub);
 // Sizes and allocates the HBM S lists of a 4-clique launch over `items` when
 // a root's out-degree exceeds kK4ListMax (nothing otherwise): one list of
 // the largest such out-degree per wave, at most 4 waves per compute unit.
