@@ -71,6 +71,12 @@ struct Server {
   Trie* t = nullptr;
   eh_server_opts o{};
   hipStream_t stream = nullptr;
+  // the induced-neighbourhood classes of a step run beside its other launches
+  // on streams of their own (default priority), forked from and joined back
+  // into `stream` by events
+  hipStream_t side[kK4LocalClasses] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kK4LocalClasses] = {};
   Tuning tune;             // the context's tuning when the server was created
   DevBuf cursor;           // work cursors of the server's own launches
   DevBuf items_d;          // step_items Items
@@ -123,9 +129,9 @@ struct Server {
 namespace {
 
 // pattern: EH_TRIANGLE, EH_4CLIQUE (S-list kernel), or -1 - k for the
-// induced-neighbourhood 4-clique kernel of class k
+// induced-neighbourhood 4-clique kernel of class k (on ks when given)
 eh_status server_launch(Server* s, uint64_t n_items, uint64_t off, int pattern,
-                        uint32_t item_dmax) {
+                        uint32_t item_dmax, hipStream_t ks = nullptr) {
   if (n_items == 0) return EH_OK;
   Ctx* c = s->c;
   Trie& t = *s->t;
@@ -159,12 +165,25 @@ eh_status server_launch(Server* s, uint64_t n_items, uint64_t off, int pattern,
   a.search_below = tu.search_below;
   a.symmetric = t.host.symmetric ? 1u : 0u;
   a.reverse = tu.reverse;
-  if (pattern < 0) return launch_4cliques_local_items(c, s->stream, a, -1 - pattern);
+  if (pattern < 0) return launch_4cliques_local_items(c, ks ? ks : s->stream, a, -1 - pattern);
   if (pattern == EH_4CLIQUE) return launch_4cliques(c, s->stream, a, tu.kernel, tu.waves_per_cu);
   return launch_triangles(c, s->stream, a, tu.kernel, tu.waves_per_cu);
 }
 
 }  // namespace
+
+// The server's streams and events, after their work has drained.
+void destroy_streams(Server& s) {
+  for (uint32_t q = 0; q < kK4LocalClasses; ++q) {
+    if (s.side[q]) {
+      (void)hipStreamSynchronize(s.side[q]);
+      (void)hipStreamDestroy(s.side[q]);
+    }
+    if (s.join[q]) (void)hipEventDestroy(s.join[q]);
+  }
+  if (s.fork) (void)hipEventDestroy(s.fork);
+  if (s.stream) (void)hipStreamDestroy(s.stream);
+}
 
 // First fit over the free extents of the arena (in items).
 bool Server::arena_take(uint64_t n_items, uint64_t& off) {
@@ -300,10 +319,24 @@ bool Server::step() {
       st = launch_gather_items(c, stream, arena_items, static_cast<const uint4*>(pieces_d.p),
                                uint32_t(n_pieces), static_cast<Item*>(items_d.p));
   }
+  // the induced-neighbourhood classes start on their own streams once the
+  // gather is done; the triangle and S-list launches (which share the work
+  // cursors) follow one another on the server's stream
+  bool forked = false;
+  for (uint32_t q = 0; q < kK4LocalClasses && st == EH_OK; ++q) {
+    if (!n_kl[q]) continue;
+    if (!forked) {
+      st = hip_check(c, hipEventRecord(fork, stream), "fork event");
+      forked = st == EH_OK;
+    }
+    if (st == EH_OK) st = hip_check(c, hipStreamWaitEvent(side[q], fork, 0), "fork wait");
+    if (st == EH_OK) st = server_launch(this, n_kl[q], base[q + 2], -1 - int(q), 0, side[q]);
+    if (st == EH_OK) st = hip_check(c, hipEventRecord(join[q], side[q]), "join event");
+  }
   if (st == EH_OK) st = server_launch(this, n_tri, 0, EH_TRIANGLE, dmax_tri);
   if (st == EH_OK) st = server_launch(this, n_k4, base[1], EH_4CLIQUE, dmax_k4);
-  for (uint32_t q = 0; q < kK4LocalClasses; ++q)
-    if (st == EH_OK) st = server_launch(this, n_kl[q], base[q + 2], -1 - int(q), 0);
+  for (uint32_t q = 0; q < kK4LocalClasses && st == EH_OK; ++q)
+    if (n_kl[q]) st = hip_check(c, hipStreamWaitEvent(stream, join[q], 0), "join wait");
   if (st == EH_OK)
     st = hip_check(c, hipMemcpyAsync(acc_h, acc_d.p, o.max_active * sizeof(uint64_t),
                                      hipMemcpyDeviceToHost, stream), "read counters");
@@ -483,6 +516,13 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
   eh_status st = hip_check(c, hipSetDevice(c->device), "hipSetDevice");
   if (st == EH_OK)
     st = hip_check(c, hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking), "server stream");
+  for (uint32_t q = 0; q < kK4LocalClasses && st == EH_OK; ++q) {
+    st = hip_check(c, hipStreamCreateWithFlags(&s.side[q], hipStreamNonBlocking), "server stream");
+    if (st == EH_OK)
+      st = hip_check(c, hipEventCreateWithFlags(&s.join[q], hipEventDisableTiming), "join event");
+  }
+  if (st == EH_OK)
+    st = hip_check(c, hipEventCreateWithFlags(&s.fork, hipEventDisableTiming), "fork event");
   if (st == EH_OK) st = dev_alloc(c, s.items_d, sizeof(Item) * s.o.step_items);
   if (st == EH_OK) st = dev_alloc(c, s.acc_d, sizeof(uint64_t) * s.o.max_active);
   if (st == EH_OK) st = dev_alloc(c, s.cursor, sizeof(uint32_t) * kCursorWords * kMaxParts);
@@ -523,7 +563,7 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
     dev_free(c, s.pieces_d);
     if (s.pieces_h) (void)hipHostFree(s.pieces_h);
     if (s.acc_h) (void)hipHostFree(s.acc_h);
-    if (s.stream) (void)hipStreamDestroy(s.stream);
+    destroy_streams(s);
     delete x;
     return st;
   }
@@ -553,7 +593,7 @@ eh_status eh_server_create(eh_ctx* ctx, const eh_trie* resident, const eh_server
     dev_free(c, s.pieces_d);
     (void)hipHostFree(s.pieces_h);
     (void)hipHostFree(s.acc_h);
-    (void)hipStreamDestroy(s.stream);
+    destroy_streams(s);
     delete x;
     return EH_ENOMEM;
   }
@@ -704,7 +744,7 @@ eh_status eh_server_destroy(eh_server* srv) {
   dev_free(s.c, s.pieces_d);
   if (s.pieces_h) (void)hipHostFree(s.pieces_h);
   if (s.acc_h) (void)hipHostFree(s.acc_h);
-  (void)hipStreamDestroy(s.stream);
+  destroy_streams(s);
   delete srv;
   return EH_OK;
 }
