@@ -47,7 +47,7 @@ HBM_PEAK_GBS = 8000.0
 ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4  # vector lane operations per ns: CUs x SIMDs x lanes x GHz
 TUNING_FILE = os.path.join(ROOT, "paper_1503_02368_amd", "tuning.json")
 
-from paper_1503_02368_amd.profile_summary import measured_traffic  # noqa: E402
+from paper_1503_02368_amd.profile_summary import measured_traffic, valu_issue  # noqa: E402
 from paper_1503_02368_amd.workloads import WORKLOADS, make_graph  # noqa: E402
 
 
@@ -275,6 +275,9 @@ def bench_graph(name, w, args, ctx, eh, torch):
             tg = traffic / (ms / 1e3) / 1e9
             result["roofline"]["traffic_gbs"] = tg
             result["roofline"]["traffic_frac_of_peak"] = tg / HBM_PEAK_GBS
+    if "roofline" in result:
+        # the issue side of the same launch, from its committed counters
+        result["roofline"].update(valu_issue(name, ms))
     if cb is not None:
         cb.pop("count", None)
         cb.pop("bytes", None)

@@ -39,7 +39,7 @@ import time
 
 import numpy as np
 
-from paper_1503_02368_amd.profile_summary import SETS_SRC, kernel_sha, measured_traffic  # noqa: E402,F401
+from paper_1503_02368_amd.profile_summary import SETS_SRC, kernel_sha, measured_traffic, valu_issue  # noqa: E402,F401
 
 _PKG = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1503_02368_amd")
 
@@ -244,6 +244,7 @@ def _batch_roofline(ctx, eh, info, ms, name):
                               "gbs": info["b_merge"] / (ms / 1e3) / 1e9}}
     if r["traffic"]:
         r["traffic_gbs"] = r["traffic"] / (ms / 1e3) / 1e9
+    r.update(valu_issue(name, ms))
     return r
 
 

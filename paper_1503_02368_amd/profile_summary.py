@@ -41,17 +41,36 @@ def kernel_sha(src: str = KERNEL_SRC) -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(name: str, src: str = KERNEL_SRC):
-    """L2-to-fabric bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)
-    from the committed rocprofv3 counter runs, or None when the kernel source
-    (src) changed since they were taken."""
+def measured_entry(name: str, src: str = KERNEL_SRC):
+    """The committed counter summary of a workload's launch, or None when the
+    kernel source (src) changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
         d = json.load(f).get(name)
     if not d or d.get("kernel_sha") != kernel_sha(src):
         return None
-    return d.get("bytes_per_launch")
+    return d
+
+
+def measured_traffic(name: str, src: str = KERNEL_SRC):
+    """L2-to-fabric bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)
+    from the committed rocprofv3 counter runs, or None when the kernel source
+    (src) changed since they were taken."""
+    d = measured_entry(name, src)
+    return d.get("bytes_per_launch") if d else None
+
+
+def valu_issue(name: str, ms: float, src: str = KERNEL_SRC) -> dict:
+    """VALU wave64 instructions per launch (SQ_INSTS_VALU summed over the
+    launch's kernels, from the committed counter runs) and the share of the
+    chip's VALU issue cycles they fill in ms per launch: a wave64 VALU
+    instruction holds one of the 1024 SIMDs (256 CUs x 4) for 4 cycles, at
+    2.4 GHz.  Both None when the counters are stale or absent."""
+    d = measured_entry(name, src)
+    valu = d.get("valu_insts_per_launch") if d else None
+    frac = valu * 4 / (256 * 4 * 2.4e9 * ms / 1e3) if valu else None
+    return {"valu_insts_per_launch": valu, "valu_issue_frac": frac}
 
 
 def _csv(d: str, suffix: str):
@@ -271,8 +290,10 @@ def main():
     if os.path.exists(args.traffic):
         with open(args.traffic) as f:
             tj = json.load(f)
+    valu = sum(m["SQ_INSTS_VALU"][0] for m in per_kernel.values() if "SQ_INSTS_VALU" in m)
     tj[args.workload] = {"kernel": args.kernel, "kernel_sha": sha, "source": args.source,
                          "bytes_per_launch": traffic, "avg_us": avg_us,
+                         "valu_insts_per_launch": valu or None,
                          "fetch_kib": fk, "write_kib": wk, "fetch_factor": f_fac,
                          "write_factor": w_fac, "summary": os.path.relpath(args.out, ROOT)}
     with open(args.traffic, "w") as f:
