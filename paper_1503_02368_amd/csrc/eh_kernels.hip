@@ -1134,6 +1134,10 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
   __shared__ uint32_t s_pre[WPB][kSeg + 1];
   __shared__ uint2 s_seg[WPB][kSeg];
   __shared__ uint32_t s_plen;
+  // third level of rows of more than 4 words: pairs per row, scanned, and
+  // the waves' sums
+  __shared__ uint32_t s_pc[W > 4 ? DMAX : 1];
+  __shared__ uint32_t s_wt[WPB];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
   const SegTab T{s_pre[wid], s_seg[wid]};
   const uint32_t* __restrict__ L = a.col;
@@ -1180,8 +1184,8 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
       nw = rr.y >> 20;
       roff = rr.z;
       wb = rr.w;
-      // the first batch of segment records is loaded beside the members
-      if (tid < min(uint32_t(kSeg), d - 1)) rc0 = a.rec[roff + tid];
+      // the wave's first batch of segment records is loaded beside the members
+      if (wid + WPB * lane + 1 < d) rc0 = a.rec[roff + wid + WPB * lane];
       for (uint32_t k = tid; k < d; k += NT) {
         const uint32_t x = L[beg + k];
         s_u[k] = x;
@@ -1202,17 +1206,20 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
     }
     __syncthreads();
     // rows T_0 .. T_{d-2} (v_{d-1} has no later member in N+(u)), 64 rows per
-    // flat batch, batches dealt to the waves
-    for (uint32_t b0 = wid * kWave; b0 + 1 < d; b0 += NT) {
-      const uint32_t nseg = min(uint32_t(kSeg), d - 1 - b0);
+    // flat batch; wave w takes rows w, w + WPB, w + 2 WPB, ..., so that the
+    // waves' shares of a root cost about the same
+    for (uint32_t b0 = 0; b0 + wid + 1 < d; b0 += NT) {
+      const uint32_t rb = b0 + wid;  // row of the batch's segment j: rb + WPB j
+      const uint32_t nseg = min(uint32_t(kSeg), (d - 1 - rb + WPB - 1) / WPB);
       Seg g{0, 0, kNoWords};
       if (lane < nseg) {
+        const uint32_t row = rb + WPB * lane;
         if constexpr (kItems) {
           // a row below the window streams words only from a bitset inside it
-          const WordRule wr{a.use_bitsets != 0, wb, b0 + lane < plen ? wb : 0u};
-          g = seg_full<true>(a, s_u[b0 + lane], wr);
+          const WordRule wr{a.use_bitsets != 0, wb, row < plen ? wb : 0u};
+          g = seg_full<true>(a, s_u[row], wr);
         } else {
-          const uint2 rc = b0 == 0 ? rc0 : a.rec[roff + b0 + lane];
+          const uint2 rc = b0 == 0 ? rc0 : a.rec[roff + row];
           g = Seg{rc.x, rc.y & 0x3FFFFFu,
                   (rc.y & kHiBit) ? int32_t((rc.y >> 22) & 0x1FFu) : kNoWords};
         }
@@ -1226,7 +1233,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
       constexpr uint32_t kNone = 0xFFFFFFFFu;
       auto pack = [&](const SegCursor<false>& c, uint32_t f) {
         const uint32_t key = c.wbase + f;
-        return (b0 + c.j) | (c.bits ? (1u << 10) : 0u) | ((key < nw ? key : 0xFFFFu) << 16);
+        return (rb + WPB * c.j) | (c.bits ? (1u << 10) : 0u) | ((key < nw ? key : 0xFFFFu) << 16);
       };
       auto take = [&](uint32_t val, uint32_t info) {
         const bool bits = (info >> 10) & 1u;
@@ -1281,7 +1288,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
               if (f < f_end) {
                 c.seek(T, f);
                 val[q] = L[c.base + f];
-                info[q] = elems ? b0 + c.j : pack(c, f);
+                info[q] = elems ? rb + WPB * c.j : pack(c, f);
               }
             }
 #pragma unroll
@@ -1304,7 +1311,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
             if (f < E) {
               c.seek(T, f);
               val[q] = L[c.base + f];
-              info[q] = elems ? b0 + c.j : pack(c, f);
+              info[q] = elems ? rb + WPB * c.j : pack(c, f);
             }
           }
 #pragma unroll
@@ -1317,15 +1324,15 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
       }
     }
     __syncthreads();
-    // sum over rows i and members j of T_i of |T_i & T_j|, one row per lane
-    // (rows i <= d-3: a pair needs two later members); T_j's bits lie above
-    // j, so only the words from j's on are ANDed
+    // sum over rows i <= d-3 (a pair needs two later members) and members j
+    // of T_i of |T_i & T_j|; T_j's bits lie above j, so only the words from
+    // j's on are ANDed
     uint32_t cnt = 0;
     const uint32_t wd = (d + 31) >> 5;  // words that can hold a member
-    for (uint32_t i = wid * kWave + lane; i + 2 < d; i += NT) {
-      const uint32_t* Ti = s_m + i * RS;
-      if constexpr (W <= 4) {
-        // short rows: T_i in registers
+    if constexpr (W <= 4) {
+      // short rows: one row per lane, T_i in registers
+      for (uint32_t i = wid * kWave + lane; i + 2 < d; i += NT) {
+        const uint32_t* Ti = s_m + i * RS;
         uint32_t t[W];
 #pragma unroll
         for (uint32_t w = 0; w < W; ++w) t[w] = Ti[w];
@@ -1340,16 +1347,55 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
             for (uint32_t v = w; v < W; ++v) cnt += __popc(t[v] & Tj[v]);
           }
         }
-      } else {
-        // longer rows: walked word by word from LDS
-        for (uint32_t w = (i + 1) >> 5; w < wd; ++w) {
-          uint32_t bm = Ti[w];
-          while (bm) {
-            const uint32_t j = w * 32u + uint32_t(__builtin_ctz(bm));
-            bm &= bm - 1u;
-            const uint32_t* Tj = s_m + j * RS;
-            for (uint32_t v = w; v < wd; ++v) cnt += __popc(Ti[v] & Tj[v]);
+      }
+    } else {
+      // longer rows: the pairs (i, j), j in T_i, taken in row order, are
+      // dealt to the block's lanes in equal contiguous shares, so that no
+      // lane waits on a longer row; s_pc[i] = pairs in the rows below i
+      uint32_t pc = 0;
+      if (tid + 2 < d)
+        for (uint32_t w = (tid + 1) >> 5; w < wd; ++w) pc += __popc(s_m[tid * RS + w]);
+      const uint32_t incl = wave_incl_scan(pc, lane);
+      if (lane == kWave - 1) s_wt[wid] = incl;
+      __syncthreads();
+      uint32_t before = 0, total = 0;
+#pragma unroll
+      for (uint32_t k = 0; k < uint32_t(WPB); ++k) {
+        before += k < wid ? s_wt[k] : 0u;
+        total += s_wt[k];
+      }
+      if (tid + 2 < d) s_pc[tid] = before + incl - pc;
+      __syncthreads();
+      const uint32_t f0 = uint32_t(uint64_t(total) * tid / NT);
+      const uint32_t f1 = uint32_t(uint64_t(total) * (tid + 1) / NT);
+      if (f0 < f1) {
+        // the pair f0: its row (the last with s_pc[i] <= f0), word and bit
+        uint32_t i = 0;
+        for (uint32_t n = d - 2; n > 1;) {
+          const uint32_t h = n >> 1;
+          if (s_pc[i + h] <= f0) i += h;
+          n -= h;
+        }
+        const uint32_t* Ti = s_m + i * RS;
+        uint32_t k = f0 - s_pc[i], w = (i + 1) >> 5, bm = Ti[w];
+        while (k >= uint32_t(__popc(bm))) {
+          k -= uint32_t(__popc(bm));
+          bm = Ti[++w];
+        }
+        for (; k; --k) bm &= bm - 1u;
+        for (uint32_t f = f0; f < f1; ++f) {
+          while (bm == 0 && i + 2 < d) {
+            if (++w >= wd) {
+              ++i;
+              Ti += RS;
+              w = (i + 1) >> 5;
+            }
+            bm = Ti[w];
           }
+          const uint32_t j = w * 32u + uint32_t(__builtin_ctz(bm));
+          bm &= bm - 1u;
+          const uint32_t* Tj = s_m + j * RS;
+          for (uint32_t v = w; v < wd; ++v) cnt += __popc(Ti[v] & Tj[v]);
         }
       }
     }
@@ -1628,12 +1674,21 @@ eh_status launch_4cliques_local_items(Ctx* c, hipStream_t s, const LaunchArgs& l
 
 eh_status launch_4cliques_local(Ctx* c, hipStream_t s, const LaunchArgs& la,
                                const uint64_t n[kK4LocalClasses]) {
-  // blocks per CU as the LDS allows: one wave per root at out-degree <= 64
-  // and <= 128 (a 256-word window), four at <= 256 and eight at <= 512
-  static constexpr uint32_t kPerCu[kK4LocalClasses] = {32, 28, 9, 3};
+  // one wave per root at out-degree <= 64 and <= 128 (a 256-word window),
+  // four at <= 256 and eight at <= 512.  Blocks per CU: a class alone fills
+  // the CUs as the LDS allows; classes side by side take smaller grids, whose
+  // blocks the CUs hold together (R-MAT s18 4-cliques: 0.61 ms against
+  // 0.65 ms with the full grids)
+  static constexpr uint32_t kAlone[kK4LocalClasses] = {32, 28, 9, 3};
+  static constexpr uint32_t kShared[kK4LocalClasses] = {16, 16, 6, 3};
+  const int present = (n[0] != 0) + (n[1] != 0) + (n[2] != 0) + (n[3] != 0);
+  const uint32_t* kPerCu = present > 1 ? kShared : kAlone;
   // the classes run side by side: the first on s, each other on a side
-  // stream of the context forked from s, joined back into s at the end
-  bool forked = false;
+  // stream of the context forked from s before the first launch, joined
+  // back into s at the end
+  if (n[1] || n[2] || n[3])
+    if (eh_status st = hip_check(c, hipEventRecord(c->fork, s), "fork event"); st != EH_OK)
+      return st;
   uint64_t off = 0;
   for (int k = 0; k < int(kK4LocalClasses); ++k) {
     if (n[k] == 0) continue;
@@ -1643,11 +1698,6 @@ eh_status launch_4cliques_local(Ctx* c, hipStream_t s, const LaunchArgs& la,
     off += n[k];
     hipStream_t ks = s;
     if (k > 0) {
-      if (!forked) {
-        if (eh_status st = hip_check(c, hipEventRecord(c->fork, s), "fork event"); st != EH_OK)
-          return st;
-        forked = true;
-      }
       ks = c->side[k - 1];
       if (eh_status st = hip_check(c, hipStreamWaitEvent(ks, c->fork, 0), "fork wait");
           st != EH_OK)
