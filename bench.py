@@ -150,22 +150,27 @@ def bench_graph(name, w, args, ctx, eh, torch):
     s.wait_stream(torch.cuda.current_stream())
     # the process's first count also loads the planner's and kernels' code:
     # a count of a small graph with the same settings does that beforehand
-    from paper_1503_02368_amd import inputs
-    small = ctx.build_edgelist(inputs.rmat(10, 16, seed=1), layout=layout, tau=tau)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.count_add_async(small, pattern, out)
-    torch.cuda.synchronize()
-    cold_ms = (time.perf_counter() - t0) * 1e3
-    small.free()
+    cold_ms = None
+    if not args.no_code_warmup:
+        from paper_1503_02368_amd import inputs
+        small = ctx.build_edgelist(inputs.rmat(10, 16, seed=1), layout=layout, tau=tau)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.count_add_async(small, pattern, out)
+        torch.cuda.synchronize()
+        cold_ms = (time.perf_counter() - t0) * 1e3
+        small.free()
     # the first count builds and caches the work-item plan (not timed below)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.count_add_async(trie, pattern, out)
     torch.cuda.synchronize()
     first_ms = (time.perf_counter() - t0) * 1e3
-    log(f"[bench] first count (plan + count) {first_ms:.2f} ms; the process's first count, of a "
-        f"small graph, {cold_ms:.1f} ms (code loading)")
+    if cold_ms is None:
+        log(f"[bench] first count (code loading, plan + count) {first_ms:.2f} ms")
+    else:
+        log(f"[bench] first count (plan + count) {first_ms:.2f} ms; the process's first count, of "
+            f"a small graph, {cold_ms:.1f} ms (code loading)")
     for _ in range(args.warmup):
         ctx.count_add_async(trie, pattern, out)
     torch.cuda.synchronize()
@@ -197,9 +202,12 @@ def bench_graph(name, w, args, ctx, eh, torch):
         "count": count,
         "untimed": {"first_count_ms": first_ms, "process_first_count_ms": cold_ms,
                     "note": "first count = work-item planning (cached per trie, pattern and "
-                            "tuning) plus one count, wall clock, after a count of a small graph "
-                            "has loaded the code (process_first_count_ms, that small count); "
-                            f"trie build {t_build * 1e3:.0f} ms (host build and upload) also "
+                            "tuning) plus one count, wall clock, "
+                            + ("including the process's code loading (--no-code-warmup); "
+                               if cold_ms is None else
+                               "after a count of a small graph has loaded the code "
+                               "(process_first_count_ms, that small count); ")
+                            + f"trie build {t_build * 1e3:.0f} ms (host build and upload) also "
                             "untimed"},
     }
     cb = None
@@ -306,6 +314,9 @@ def main():
     ap.add_argument("--warmup-s", type=float, default=1.0, help="served: warm-up seconds per rate")
     ap.add_argument("--max-requests", type=int, default=0,
                     help="served: cap on requests per rate (0: none)")
+    ap.add_argument("--no-code-warmup", action="store_true",
+                    help="skip the small-graph count that loads the code before the first count "
+                         "(profiles: then every dispatch of the kernel is the workload's)")
     ap.add_argument("--no-per-instance", action="store_true",
                     help="batch: skip the one-launch-per-graph comparison (for profiling runs)")
     args = ap.parse_args()
