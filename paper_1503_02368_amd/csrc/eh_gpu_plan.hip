@@ -763,9 +763,10 @@ __device__ inline uint32_t lower_bound_g(const uint32_t* a, uint32_t n, uint32_t
 
 // One wave per root: the root record {position of N+(u), d | plen << 10 |
 // nw << 20, first row record, window base} and, per row i < d - 1, the part
-// of N+(v_i) up to max N+(u) as elements, or as the bitset's words when fewer
-// (only from a bitset starting inside the window), {start, length | word
-// offset << 22 | kHiBit for words}.  long_set: a row of 2^22 or more members.
+// of N+(v_i) from v_{i+1} up to max N+(u) as elements, or as the bitset's
+// words when fewer (only from a bitset starting inside the window), {start,
+// length | word offset << 22 | kHiBit for words}.  long_set: a row of 2^22 or
+// more members.
 __global__ void __launch_bounds__(kB) k_k4l_records(TrieView t, const unsigned long long* __restrict__ key,
                                                     const uint32_t* __restrict__ roff, uint64_t n_roots,
                                                     uint32_t ub, uint4* __restrict__ roots,
@@ -789,10 +790,13 @@ __global__ void __launch_bounds__(kB) k_k4l_records(TrieView t, const unsigned l
       const uint2 vd = t.vdesc[v];
       const uint32_t dv = vd.y & kMaxIndex;
       const uint32_t* nv = t.col + vd.x;
-      // members up to hi
+      // members from the next member of N+(u) up to hi: T_i only holds
+      // members after v_i, and the first of those is v_{i+1}
       uint32_t len = lower_bound_g(nv, dv, hi);
       if (len < dv && nv[len] == hi) ++len;
-      uint2 g = make_uint2(vd.x, len);
+      const uint32_t from = len ? lower_bound_g(nv, len, nu[i + 1]) : 0u;
+      len -= from;
+      uint2 g = make_uint2(vd.x + from, len);
       if (ub && len && (vd.y & kHiBit)) {
         const uint4 b = t.bsdesc[v];
         if (b.y >= wb) {
