@@ -729,19 +729,33 @@ namespace {
 __global__ void __launch_bounds__(kB) k_k4l_keys(TrieView t, unsigned long long* __restrict__ key,
                                                  unsigned long long* __restrict__ counts) {
   constexpr uint64_t kCostMax = (1ull << 28) - 1;
-  for (uint64_t u = gtid(); u < t.n; u += gstride()) {
-    const uint2 ud = t.vdesc[u];
-    const uint32_t d = ud.y & kMaxIndex;
-    const int k = k4_local_class(d);
-    if (k < 0) {
-      key[u] = ~0ull;
-      continue;
+  const uint32_t lane = threadIdx.x & 63u;
+  // every lane of a wave takes the same number of turns (the stride is a
+  // multiple of 64), so the class counts are summed per wave: one atomic per
+  // class and wave instead of one per root
+  for (uint64_t u0 = gtid() - lane; u0 < t.n; u0 += gstride()) {
+    const uint64_t u = u0 + lane;
+    int k = -1;
+    if (u < t.n) {
+      const uint2 ud = t.vdesc[u];
+      const uint32_t d = ud.y & kMaxIndex;
+      k = k4_local_class(d);
+      if (k < 0) {
+        key[u] = ~0ull;
+      } else {
+        // d <= 512 members of at most 2^31 out-degree each: no overflow
+        uint64_t cost = uint64_t(d) * d;
+        for (uint32_t e = ud.x; e < ud.x + d; ++e) cost += outdeg(t, t.col[e]);
+        cost = cost < kCostMax ? cost : kCostMax;
+        key[u] = (uint64_t(k) << 60) | ((kCostMax - cost) << 32) | u;
+      }
     }
-    uint64_t cost = uint64_t(d) * d;
-    for (uint32_t e = ud.x; e < ud.x + d && cost < kCostMax; ++e) cost += outdeg(t, t.col[e]);
-    cost = cost < kCostMax ? cost : kCostMax;
-    key[u] = (uint64_t(k) << 60) | ((kCostMax - cost) << 32) | u;
-    atomicAdd(&counts[k], 1ull);
+#pragma unroll
+    for (int q = 0; q < int(kK4LocalClasses); ++q) {
+      const uint64_t m = __ballot(k == q);
+      if (m && lane == uint32_t(__ffsll((unsigned long long)m) - 1))
+        atomicAdd(&counts[q], (unsigned long long)__popcll(m));
+    }
   }
 }
 
