@@ -178,7 +178,9 @@ __global__ void __launch_bounds__(kB) k_write_items(TrieView t,
     cut_items(t, Q, trow, uint32_t(v), chunk, tag, items + ioff[v]);
     mx = max(mx, outdeg(t, uint32_t(v)));
   }
-  if (mx) atomicMax(dmax, mx);
+  // one atomic per wave
+  for (int o = 32; o; o >>= 1) mx = max(mx, uint32_t(__shfl_xor(int(mx), o)));
+  if ((threadIdx.x & 63u) == 0 && mx) atomicMax(dmax, mx);
 }
 
 // Graph g's items start at the first item whose vertex is at or above vbase[g].
