@@ -38,6 +38,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <type_traits>
 #include <unordered_map>
 
 #include "eh_internal.h"
@@ -556,6 +557,15 @@ struct SegCursor {
       base = sg.x - start;
       wbase = kRaw ? sg.y : sg.y - start;
       bits = !kRaw && sg.y != uint32_t(kNoWords);
+    }
+  }
+  // seek for walks with no bitset words: only the element position is kept
+  __device__ __forceinline__ void seek_base(const SegTab& T, uint32_t f) {
+    while (nxt <= f) {
+      const uint32_t start = nxt;
+      ++j;
+      nxt = T.P[j + 1];
+      base = T.S[j].x - start;
     }
   }
   // Places the cursor on the segment of f by a branch-free binary search of
@@ -1271,57 +1281,72 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
         }
       };
       const bool blocked = E < nseg * a.search_below;
-      if (blocked) {
-        // short sets: lane l walks the contiguous flat range [l per, (l+1) per)
-        const uint32_t per = (E + kWave - 1) / kWave;
-        const uint32_t f_beg = lane * per, f_end = min(f_beg + per, E);
-        if (f_beg < f_end) {
-          SegCursor<false> c;
-          c.find(T, f_beg);
-          for (uint32_t f0 = f_beg; f0 < f_end; f0 += U) {
+      // the walk, instantiated for element-only batches (kE) and for batches
+      // with bitset words
+      auto walk = [&](auto kE) {
+        constexpr bool kElemsOnly = decltype(kE)::value;
+        auto seek = [&](SegCursor<false>& c, uint32_t f) {
+          if constexpr (kElemsOnly) c.seek_base(T, f);
+          else c.seek(T, f);
+        };
+        auto tag_of = [&](const SegCursor<false>& c, uint32_t f) {
+          if constexpr (kElemsOnly) return rb + WPB * c.j;
+          else return pack(c, f);
+        };
+        auto use = [&](uint32_t v, uint32_t info) {
+          if constexpr (kElemsOnly) take_elem(v, info);
+          else take(v, info);
+        };
+        if (blocked) {
+          // short sets: lane l walks the contiguous flat range [l per, (l+1) per)
+          const uint32_t per = (E + kWave - 1) / kWave;
+          const uint32_t f_beg = lane * per, f_end = min(f_beg + per, E);
+          if (f_beg < f_end) {
+            SegCursor<false> c;
+            c.find(T, f_beg);
+            for (uint32_t f0 = f_beg; f0 < f_end; f0 += U) {
+              uint32_t val[U], info[U];
+#pragma unroll
+              for (int q = 0; q < U; ++q) {
+                const uint32_t f = f0 + uint32_t(q);
+                val[q] = 0;
+                info[q] = kNone;
+                if (f < f_end) {
+                  seek(c, f);
+                  val[q] = L[c.base + f];
+                  info[q] = tag_of(c, f);
+                }
+              }
+#pragma unroll
+              for (int q = 0; q < U; ++q)
+                if (info[q] != kNone) use(val[q], info[q]);
+            }
+          }
+        } else {
+          SegCursor<false> c(T);
+          for (uint32_t f0 = 0; f0 < E; f0 += kWave * U) {
             uint32_t val[U], info[U];
 #pragma unroll
             for (int q = 0; q < U; ++q) {
-              const uint32_t f = f0 + uint32_t(q);
+              const uint32_t f = f0 + uint32_t(q) * kWave + lane;
               val[q] = 0;
               info[q] = kNone;
-              if (f < f_end) {
-                c.seek(T, f);
+              if (f < E) {
+                seek(c, f);
                 val[q] = L[c.base + f];
-                info[q] = elems ? rb + WPB * c.j : pack(c, f);
+                info[q] = tag_of(c, f);
               }
             }
 #pragma unroll
-            for (int q = 0; q < U; ++q) {
-              if (info[q] == kNone) continue;
-              if (elems) take_elem(val[q], info[q]);
-              else take(val[q], info[q]);
-            }
+            for (int q = 0; q < U; ++q)
+              if (info[q] != kNone) use(val[q], info[q]);
           }
         }
-      } else {
-        SegCursor<false> c(T);
-        for (uint32_t f0 = 0; f0 < E; f0 += kWave * U) {
-          uint32_t val[U], info[U];
-#pragma unroll
-          for (int q = 0; q < U; ++q) {
-            const uint32_t f = f0 + uint32_t(q) * kWave + lane;
-            val[q] = 0;
-            info[q] = kNone;
-            if (f < E) {
-              c.seek(T, f);
-              val[q] = L[c.base + f];
-              info[q] = elems ? rb + WPB * c.j : pack(c, f);
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < U; ++q) {
-            if (info[q] == kNone) continue;
-            if (elems) take_elem(val[q], info[q]);
-            else take(val[q], info[q]);
-          }
-        }
-      }
+      };
+      if (elems)
+        walk(std::true_type{});
+      else
+        walk(std::false_type{});
     }
     __syncthreads();
     // sum over rows i <= d-3 (a pair needs two later members) and members j
