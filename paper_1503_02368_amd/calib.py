@@ -12,7 +12,7 @@ read-only kernel reaches on this GPU, the achievable ceiling beside the
 import sys
 
 
-def probe_gbs(ctx, mib: int = 4096, reps: int = 10, blocks=(4, 8, 16)) -> dict:
+def probe_gbs(ctx, mib: int = 4096, reps: int = 10, blocks=(4, 8, 16, 32)) -> dict:
     """GB/s of the library's streaming-read kernel (eh_stream_read: 128-bit
     loads over a grid-stride loop, every byte read once) over `mib` MiB, far
     larger than the 256 MB last-level cache, timed with HIP events on the
