@@ -181,6 +181,30 @@ def test_4cliques_induced_neighbourhoods(ctx, eh, lay):
             trie.free()
 
 
+def test_4cliques_induced_window_spill(ctx, eh):
+    """Roots of out-degree 257..512 whose out-sets span more ids than the
+    eight-wave class's 16,384-id window (a near-regular graph of 20,000
+    vertices and mean degree 640: about 13.5 K such roots, a quarter of them
+    with members below the window), counted whole and rooted (the items
+    path), equal the oracle's."""
+    el = inputs.chung_lu(20000, 640, 6.0, seed=86)
+    g = oracle.Graph.from_edgelist(el)
+    root = g.cliques4_rooted_at(np.arange(el.n, dtype=np.uint32))
+    K = int(root.sum(dtype=np.uint64))
+    assert K == g.count(4)
+    trie = ctx.build_edgelist(el)
+    try:
+        assert 256 < trie.info["max_out_degree"] <= 512
+        for kw in (dict(k4_local=1, staging=1, dynamic=0), dict(k4_local=1, use_bitsets=0)):
+            tune(ctx, **kw)
+            assert ctx.count_4cliques(trie) == K, kw
+        tune(ctx, k4_local=1)
+        sample = np.random.default_rng(7).choice(el.n, 3000, replace=False).astype(np.uint32)
+        assert ctx.count_rooted(trie, eh.CLIQUE4, sample) == oracle.rooted_count(root, sample)
+    finally:
+        trie.free()
+
+
 def test_4cliques_induced_accumulate_and_noalloc(ctx, eh):
     """The accumulating and allocation-free counts run both 4-clique launches
     of a plan whose roots are split between them."""
