@@ -183,6 +183,8 @@ eh_status enqueue_count(Ctx* c, Trie& t, Plan* p, uint64_t i0, uint64_t i1,
       // single-graph plans only: the whole range of items and every root
       LaunchArgs la = a;
       la.roots = static_cast<const uint4*>(p->k4l.p);
+      la.root_cursors = reinterpret_cast<uint32_t*>(
+          static_cast<uint4*>(p->k4l.p) + (p->k4l_n[0] + p->k4l_n[1] + p->k4l_n[2] + p->k4l_n[3]));
       la.rec = static_cast<const uint2*>(p->rec.p);
       if (eh_status st = launch_4cliques_local(c, c->stream, la, p->k4l_n); st != EH_OK) return st;
     }

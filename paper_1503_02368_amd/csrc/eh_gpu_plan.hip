@@ -890,7 +890,10 @@ eh_status device_plan_k4_local(Ctx* c, Trie& tr, Plan& plan, bool ub) {
       (st = chk(hipStreamSynchronize(s), "rows sync")) != EH_OK)
     return st;
   const uint64_t n_rec = uint64_t(last[0]) + last[1];
-  if ((st = dev_alloc(c, plan.k4l, sizeof(uint4) * n_roots)) != EH_OK) return st;
+  // the root records, then one work cursor per class (kCursorWords apart)
+  if ((st = dev_alloc(c, plan.k4l, sizeof(uint4) * n_roots +
+                                       sizeof(uint32_t) * kCursorWords * kK4LocalClasses)) != EH_OK)
+    return st;
   if ((st = dev_alloc(c, plan.rec, sizeof(uint2) * std::max<uint64_t>(n_rec, 1))) != EH_OK)
     return st;
   hipLaunchKernelGGL(k_fill_u32_plan, dim3(1), dim3(kB), 0, s, ptr<uint32_t>(small), 16, 0u);

@@ -286,7 +286,8 @@ struct LaunchArgs {
   uint32_t k4s_stride = 0;             //   of out-degree > kK4ListMax, or null
   uint32_t k4s_waves = 0;
   const uint4* roots = nullptr;        // 4-cliques over induced neighbourhoods: root
-  uint64_t n_roots = 0;                //   records (segment records in rec)
+  uint64_t n_roots = 0;                //   records (segment records in rec) and the
+  uint32_t* root_cursors = nullptr;    //   classes' root cursors, kCursorWords apart
 };
 eh_status launch_fill_u64(Ctx* c, hipStream_t s, unsigned long long* p, uint64_t n,
                           unsigned long long v);

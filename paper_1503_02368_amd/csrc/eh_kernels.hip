@@ -1156,12 +1156,25 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
   if (tid == 0) s_plen = 0;
   __syncthreads();
   unsigned long long acc = 0;
-  // roots come by decreasing estimated cost; block b takes b, 2G-1-b, 2G+b,
-  // 4G-1-b, ... (G blocks), so that every block's share costs about the same
+  // roots come by decreasing estimated cost.  One-wave blocks (many roots
+  // each) deal them boustrophedon: block b takes b, 2G-1-b, 2G+b, 4G-1-b, ...
+  // (G blocks), so that every block's share costs about the same.  Blocks of
+  // several waves hold one or two roots each and start as the CUs free up
+  // beside the other classes, so they take the next root from a cursor when
+  // done with one (the costliest first)
+  constexpr bool kGrab = WPB > 1 && !kItems;
+  __shared__ uint32_t s_root;
   const uint64_t G = gridDim.x;
   const uint64_t n_roots = kItems ? a.n_items : a.n_roots;
   for (uint64_t k = 0;; ++k) {
-    const uint64_t r = k * G + ((k & 1) ? G - 1 - blockIdx.x : blockIdx.x);
+    uint64_t r;
+    if (kGrab) {
+      if (tid == 0) s_root = atomicAdd(a.cursor, 1u);
+      __syncthreads();
+      r = s_root;
+    } else {
+      r = k * G + ((k & 1) ? G - 1 - blockIdx.x : blockIdx.x);
+    }
     if (r >= n_roots) break;
     uint32_t beg, d, plen, nw, roff = 0, wb, tag = 0;
     uint2 rc0{0, 0};
@@ -1711,6 +1724,17 @@ eh_status launch_4cliques_local(Ctx* c, hipStream_t s, const LaunchArgs& la,
   // the classes run side by side: the first on s, each other on a side
   // stream of the context forked from s before the first launch, joined
   // back into s at the end
+  if (n[2] || n[3]) {
+    // the cursors of the classes of several waves per root start at zero
+    if (!la.root_cursors) {
+      c->err = "the 4-clique root classes of several waves need their cursors";
+      return EH_EINVAL;
+    }
+    if (eh_status st = launch_fill_u64(c, s, reinterpret_cast<unsigned long long*>(la.root_cursors),
+                                       uint64_t(kCursorWords) * kK4LocalClasses / 2, 0);
+        st != EH_OK)
+      return st;
+  }
   if (n[1] || n[2] || n[3])
     if (eh_status st = hip_check(c, hipEventRecord(c->fork, s), "fork event"); st != EH_OK)
       return st;
@@ -1720,6 +1744,7 @@ eh_status launch_4cliques_local(Ctx* c, hipStream_t s, const LaunchArgs& la,
     DevArgs d = to_dev(la);
     d.roots = la.roots + off;
     d.n_roots = n[k];
+    d.cursor = la.root_cursors ? la.root_cursors + uint64_t(k) * kCursorWords : nullptr;
     off += n[k];
     hipStream_t ks = s;
     if (k > 0) {
