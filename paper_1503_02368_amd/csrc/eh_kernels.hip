@@ -1156,13 +1156,13 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
   if (tid == 0) s_plen = 0;
   __syncthreads();
   unsigned long long acc = 0;
-  // roots come by decreasing estimated cost.  One-wave blocks (many roots
-  // each) deal them boustrophedon: block b takes b, 2G-1-b, 2G+b, 4G-1-b, ...
-  // (G blocks), so that every block's share costs about the same.  Blocks of
-  // several waves hold one or two roots each and start as the CUs free up
-  // beside the other classes, so they take the next root from a cursor when
-  // done with one (the costliest first)
-  constexpr bool kGrab = WPB > 1 && !kItems;
+  // roots come by decreasing estimated cost.  The class of out-degree <= 64
+  // (many roots per block) deals them boustrophedon: block b takes b, 2G-1-b,
+  // 2G+b, 4G-1-b, ... (G blocks), so that every block's share costs about the
+  // same.  The other classes' blocks hold one or two roots each and start as
+  // the CUs free up beside the other classes, so they take the next root from
+  // a cursor when done with one (the costliest first)
+  constexpr bool kGrab = DMAX > 64 && !kItems;
   __shared__ uint32_t s_root;
   const uint64_t G = gridDim.x;
   const uint64_t n_roots = kItems ? a.n_items : a.n_roots;
@@ -1724,10 +1724,10 @@ eh_status launch_4cliques_local(Ctx* c, hipStream_t s, const LaunchArgs& la,
   // the classes run side by side: the first on s, each other on a side
   // stream of the context forked from s before the first launch, joined
   // back into s at the end
-  if (n[2] || n[3]) {
-    // the cursors of the classes of several waves per root start at zero
+  if (n[1] || n[2] || n[3]) {
+    // the cursors of the classes that take roots from one start at zero
     if (!la.root_cursors) {
-      c->err = "the 4-clique root classes of several waves need their cursors";
+      c->err = "the 4-clique root classes above out-degree 64 need their cursors";
       return EH_EINVAL;
     }
     if (eh_status st = launch_fill_u64(c, s, reinterpret_cast<unsigned long long*>(la.root_cursors),
