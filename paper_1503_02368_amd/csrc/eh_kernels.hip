@@ -1135,12 +1135,14 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_staged(DevArgs a) {
 template <int WPB, int RW, int DMAX, int U, bool kItems>
 __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
   constexpr uint32_t W = DMAX / 32;       // words per row
-  constexpr uint32_t RS = W + 1;          // row stride: rows start in different banks
+  // row stride: rows start in different banks; rows of more than 4 words
+  // start on 8-byte boundaries, so that the third level reads word pairs
+  constexpr uint32_t RS = W <= 4 ? W + 1 : W + 2;
   constexpr uint32_t NT = WPB * kWave;
   __shared__ uint32_t s_a[RW];            // the window's bitmap
   __shared__ uint16_t s_p[RW];            // members in the window's words below
   __shared__ uint32_t s_u[DMAX];          // N+(u), sorted
-  __shared__ uint32_t s_m[DMAX * RS];     // rows T_i
+  __shared__ __align__(16) uint32_t s_m[DMAX * RS];  // rows T_i
   __shared__ uint32_t s_pre[WPB][kSeg + 1];
   __shared__ uint2 s_seg[WPB][kSeg];
   __shared__ uint32_t s_plen;
@@ -1432,8 +1434,14 @@ __global__ __launch_bounds__(WPB * kWave) void k_k4_local(DevArgs a) {
           }
           const uint32_t j = w * 32u + uint32_t(__builtin_ctz(bm));
           bm &= bm - 1u;
-          const uint32_t* Tj = s_m + j * RS;
-          for (uint32_t v = w; v < wd; ++v) cnt += __popc(Ti[v] & Tj[v]);
+          // word pairs from the pair holding j's word (T_j's words below
+          // j's are zero, and so are both rows' words from wd on)
+          const uint2* Ti2 = reinterpret_cast<const uint2*>(Ti);
+          const uint2* Tj2 = reinterpret_cast<const uint2*>(s_m + j * RS);
+          for (uint32_t v = w >> 1; v < (wd + 1) >> 1; ++v) {
+            const uint2 x = Ti2[v], y = Tj2[v];
+            cnt += __popc(x.x & y.x) + __popc(x.y & y.y);
+          }
         }
       }
     }
