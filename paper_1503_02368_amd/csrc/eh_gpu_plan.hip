@@ -288,35 +288,71 @@ __device__ inline void group_graph(const TrieView& t, const Item* items, const u
   *n_mem = nm;
 }
 
+// Grouping runs over chunks of at most kGroupChunk consecutive items of one
+// graph (a group never spans two chunks), so that a large graph's items are
+// grouped by many threads.  nch[g]: graph g's chunks (the entry past the last
+// graph 0, for the scan's total).
+constexpr uint32_t kGroupChunk = 256;
+
+__global__ void __launch_bounds__(kB) k_chunk_counts(const unsigned long long* __restrict__ goff,
+                                                     uint32_t n_graphs,
+                                                     unsigned long long* __restrict__ nch) {
+  for (uint64_t g = gtid(); g <= n_graphs; g += gstride())
+    nch[g] = g < n_graphs ? (goff[g + 1] - goff[g] + kGroupChunk - 1) / kGroupChunk : 0;
+}
+
+// cb[c]: the first item of chunk c (choff: the chunk scan); cb[n_chunks] = end.
+__global__ void __launch_bounds__(kB) k_chunk_bounds(const unsigned long long* __restrict__ goff,
+                                                     const unsigned long long* __restrict__ choff,
+                                                     uint32_t n_graphs,
+                                                     unsigned long long* __restrict__ cb) {
+  for (uint64_t g = gtid(); g <= n_graphs; g += gstride()) {
+    if (g == n_graphs) {
+      cb[choff[g]] = goff[g];
+      continue;
+    }
+    for (uint64_t c = choff[g]; c < choff[g + 1]; ++c)
+      cb[c] = goff[g] + (c - choff[g]) * kGroupChunk;
+  }
+}
+
+// Per graph, the first output item: the output offset of its first chunk.
+__global__ void __launch_bounds__(kB) k_graph_out(const unsigned long long* __restrict__ choff,
+                                                  const unsigned long long* __restrict__ o_off,
+                                                  uint32_t n_graphs,
+                                                  unsigned long long* __restrict__ g_out) {
+  for (uint64_t g = gtid(); g <= n_graphs; g += gstride()) g_out[g] = o_off[choff[g]];
+}
+
 __global__ void __launch_bounds__(kB) k_group_count(TrieView t, const Item* __restrict__ items,
                                                     const uint4* __restrict__ info,
-                                                    const unsigned long long* __restrict__ goff,
-                                                    uint32_t n_graphs, uint32_t group, uint32_t cap,
+                                                    const unsigned long long* __restrict__ cb,
+                                                    uint64_t n_chunks, uint32_t group, uint32_t cap,
                                                     unsigned long long* __restrict__ n_out,
                                                     unsigned long long* __restrict__ n_mem) {
-  for (uint64_t g = gtid(); g <= n_graphs; g += gstride()) {
+  for (uint64_t c = gtid(); c <= n_chunks; c += gstride()) {
     uint64_t no = 0, nm = 0;
-    if (g < n_graphs)
-      group_graph(t, items, info, goff[g], goff[g + 1], group, cap, &no, &nm, nullptr, nullptr,
+    if (c < n_chunks)
+      group_graph(t, items, info, cb[c], cb[c + 1], group, cap, &no, &nm, nullptr, nullptr,
                   nullptr, 0, nullptr);
-    n_out[g] = no;
-    n_mem[g] = nm;
+    n_out[c] = no;
+    n_mem[c] = nm;
   }
 }
 
 __global__ void __launch_bounds__(kB) k_group_write(TrieView t, const Item* __restrict__ items,
                                                     const uint4* __restrict__ info,
-                                                    const unsigned long long* __restrict__ goff,
-                                                    uint32_t n_graphs, uint32_t group, uint32_t cap,
+                                                    const unsigned long long* __restrict__ cb,
+                                                    uint64_t n_chunks, uint32_t group, uint32_t cap,
                                                     const unsigned long long* __restrict__ o_off,
                                                     const unsigned long long* __restrict__ m_off,
                                                     Item* __restrict__ out, uint4* __restrict__ sd,
                                                     uint4* __restrict__ gsub,
                                                     uint8_t* __restrict__ grouped) {
-  for (uint64_t g = gtid(); g < n_graphs; g += gstride()) {
+  for (uint64_t c = gtid(); c < n_chunks; c += gstride()) {
     uint64_t no = 0, nm = 0;
-    group_graph(t, items, info, goff[g], goff[g + 1], group, cap, &no, &nm, out + o_off[g],
-                sd + o_off[g], gsub + m_off[g], m_off[g], grouped);
+    group_graph(t, items, info, cb[c], cb[c + 1], group, cap, &no, &nm, out + o_off[c],
+                sd + o_off[c], gsub + m_off[c], m_off[c], grouped);
   }
 }
 
@@ -500,7 +536,7 @@ eh_status device_plan_target(Ctx* c, Trie& tr, Plan& plan, uint32_t chunk, bool 
   TrieView tv{static_cast<const uint2*>(tr.vdesc.p), static_cast<const uint32_t*>(tr.col.p),
               h.n_bs ? static_cast<const uint4*>(tr.bsdesc.p) : nullptr, n};
   DevBuf src, key_a, key_b, tin, trow, cnt, ioff, items, vbase, goff, small, tmp;
-  DevBuf n_out, n_mem, o_off, m_off, grouped, cost, info, qsum;
+  DevBuf n_out, n_mem, o_off, m_off, grouped, cost, info, qsum, nch, choff, cbnd, g_out, tmp_big;
   Scratch sc(c);
   eh_status st;
   auto chk = [&](hipError_t e, const char* what) { return hip_check(c, e, what); };
@@ -605,32 +641,67 @@ eh_status device_plan_target(Ctx* c, Trie& tr, Plan& plan, uint32_t chunk, bool 
   hipLaunchKernelGGL(k_fill_u8_plan, dim3(grid_of(n)), dim3(kB), 0, s, ptr<uint8_t>(grouped),
                      uint64_t(std::max<uint32_t>(n, 1)));
   if (group > 1) {
-    if ((st = sc.get(n_out, 8 * gcap)) != EH_OK || (st = sc.get(n_mem, 8 * gcap)) != EH_OK ||
-        (st = sc.get(o_off, 8 * gcap)) != EH_OK || (st = sc.get(m_off, 8 * gcap)) != EH_OK ||
+    // the graphs' item ranges cut into chunks of at most kGroupChunk items
+    if ((st = sc.get(nch, 8 * gcap)) != EH_OK || (st = sc.get(choff, 8 * gcap)) != EH_OK ||
+        (st = sc.get(g_out, 8 * gcap)) != EH_OK)
+      return st;
+    hipLaunchKernelGGL(k_chunk_counts, dim3(grid_of(gcap)), dim3(kB), 0, s,
+                       ptr<unsigned long long>(goff), G, ptr<unsigned long long>(nch));
+    tb = tmp.bytes;
+    if ((st = chk(rocprim::exclusive_scan(tmp.p, tb, ptr<unsigned long long>(nch),
+                                          ptr<unsigned long long>(choff), 0ull, size_t(gcap),
+                                          rocprim::plus<unsigned long long>(), s),
+                  "chunk scan")) != EH_OK)
+      return st;
+    unsigned long long n_chunks = 0;
+    if ((st = chk(hipMemcpyAsync(&n_chunks, ptr<unsigned long long>(choff) + G, 8,
+                                 hipMemcpyDeviceToHost, s), "read chunk count")) != EH_OK ||
+        (st = chk(hipStreamSynchronize(s), "plan sync")) != EH_OK)
+      return st;
+    const uint64_t ccap = n_chunks + 1;
+    if ((st = sc.get(cbnd, 8 * ccap)) != EH_OK || (st = sc.get(n_out, 8 * ccap)) != EH_OK ||
+        (st = sc.get(n_mem, 8 * ccap)) != EH_OK || (st = sc.get(o_off, 8 * ccap)) != EH_OK ||
+        (st = sc.get(m_off, 8 * ccap)) != EH_OK ||
         (st = sc.get(info, 16 * std::max<uint64_t>(n_items, 1))) != EH_OK)
       return st;
+    // the scans over ccap entries, with scratch of their own when the
+    // planner's is too small for them
+    DevBuf* stmp = &tmp;
+    tb = 0;
+    if ((st = chk(rocprim::exclusive_scan(nullptr, tb, ptr<unsigned long long>(n_out),
+                                          ptr<unsigned long long>(o_off), 0ull, size_t(ccap),
+                                          rocprim::plus<unsigned long long>(), s),
+                  "scan size")) != EH_OK)
+      return st;
+    if (tb > tmp.bytes) {
+      if ((st = sc.get(tmp_big, tb)) != EH_OK) return st;
+      stmp = &tmp_big;
+    }
+    hipLaunchKernelGGL(k_chunk_bounds, dim3(grid_of(gcap)), dim3(kB), 0, s,
+                       ptr<unsigned long long>(goff), ptr<unsigned long long>(choff), G,
+                       ptr<unsigned long long>(cbnd));
     if (n_items)
       hipLaunchKernelGGL(k_item_info, dim3(grid_of(n_items)), dim3(kB), 0, s, tv, ptr<Item>(items),
                          uint64_t(n_items), ptr<uint32_t>(trow), ptr<uint4>(info));
-    hipLaunchKernelGGL(k_group_count, dim3(grid_of(gcap)), dim3(kB), 0, s, tv, ptr<Item>(items),
-                       ptr<uint4>(info), ptr<unsigned long long>(goff), G, group, cap,
-                       ptr<unsigned long long>(n_out), ptr<unsigned long long>(n_mem));
-    tb = tmp.bytes;
-    if ((st = chk(rocprim::exclusive_scan(tmp.p, tb, ptr<unsigned long long>(n_out),
-                                          ptr<unsigned long long>(o_off), 0ull, size_t(gcap),
+    hipLaunchKernelGGL(k_group_count, dim3(grid_of(ccap)), dim3(kB), 0, s, tv, ptr<Item>(items),
+                       ptr<uint4>(info), ptr<unsigned long long>(cbnd), uint64_t(n_chunks), group,
+                       cap, ptr<unsigned long long>(n_out), ptr<unsigned long long>(n_mem));
+    tb = stmp->bytes;
+    if ((st = chk(rocprim::exclusive_scan(stmp->p, tb, ptr<unsigned long long>(n_out),
+                                          ptr<unsigned long long>(o_off), 0ull, size_t(ccap),
                                           rocprim::plus<unsigned long long>(), s),
                   "group scan")) != EH_OK)
       return st;
-    tb = tmp.bytes;
-    if ((st = chk(rocprim::exclusive_scan(tmp.p, tb, ptr<unsigned long long>(n_mem),
-                                          ptr<unsigned long long>(m_off), 0ull, size_t(gcap),
+    tb = stmp->bytes;
+    if ((st = chk(rocprim::exclusive_scan(stmp->p, tb, ptr<unsigned long long>(n_mem),
+                                          ptr<unsigned long long>(m_off), 0ull, size_t(ccap),
                                           rocprim::plus<unsigned long long>(), s),
                   "group scan")) != EH_OK)
       return st;
     unsigned long long tot[2] = {0, 0};
-    if ((st = chk(hipMemcpyAsync(&tot[0], ptr<unsigned long long>(o_off) + G, 8,
+    if ((st = chk(hipMemcpyAsync(&tot[0], ptr<unsigned long long>(o_off) + n_chunks, 8,
                                  hipMemcpyDeviceToHost, s), "read group count")) != EH_OK ||
-        (st = chk(hipMemcpyAsync(&tot[1], ptr<unsigned long long>(m_off) + G, 8,
+        (st = chk(hipMemcpyAsync(&tot[1], ptr<unsigned long long>(m_off) + n_chunks, 8,
                                  hipMemcpyDeviceToHost, s), "read member count")) != EH_OK ||
         (st = chk(hipStreamSynchronize(s), "plan sync")) != EH_OK)
       return st;
@@ -648,12 +719,15 @@ eh_status device_plan_target(Ctx* c, Trie& tr, Plan& plan, uint32_t chunk, bool 
       dev_free(c, gsub);
       return st;
     }
-    hipLaunchKernelGGL(k_group_write, dim3(grid_of(G)), dim3(kB), 0, s, tv, ptr<Item>(items),
-                       ptr<uint4>(info), ptr<unsigned long long>(goff), G, group, cap,
-                       ptr<unsigned long long>(o_off), ptr<unsigned long long>(m_off),
-                       ptr<Item>(out_items), ptr<uint4>(sd), ptr<uint4>(gsub),
-                       ptr<uint8_t>(grouped));
-    if ((st = chk(hipMemcpyAsync(g_off.data(), o_off.p, 8 * gcap, hipMemcpyDeviceToHost, s),
+    hipLaunchKernelGGL(k_group_write, dim3(grid_of(n_chunks)), dim3(kB), 0, s, tv,
+                       ptr<Item>(items), ptr<uint4>(info), ptr<unsigned long long>(cbnd),
+                       uint64_t(n_chunks), group, cap, ptr<unsigned long long>(o_off),
+                       ptr<unsigned long long>(m_off), ptr<Item>(out_items), ptr<uint4>(sd),
+                       ptr<uint4>(gsub), ptr<uint8_t>(grouped));
+    hipLaunchKernelGGL(k_graph_out, dim3(grid_of(gcap)), dim3(kB), 0, s,
+                       ptr<unsigned long long>(choff), ptr<unsigned long long>(o_off), G,
+                       ptr<unsigned long long>(g_out));
+    if ((st = chk(hipMemcpyAsync(g_off.data(), g_out.p, 8 * gcap, hipMemcpyDeviceToHost, s),
                   "read graph offsets")) != EH_OK) {
       dev_free(c, out_items);
       dev_free(c, sd);
